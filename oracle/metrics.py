@@ -1,0 +1,86 @@
+"""Reconstruction-quality metrics and the choice of c, FP64.  Test
+infrastructure only.
+
+Section 8, Eq. 16 (NMSVE) as printed, read literally:
+    NMSVE = ( ||v - v~||_2 + ||GL(v) - GL(v~)||_2 ) / (2n)
+over the 3n-vector of coordinates, with
+    GL(v_i) = v_i - (sum_{j in N(i)} d_ij^-1 v_j) / (sum_{j in N(i)} d_ij^-1)
+Reading: d_ij are the Euclidean edge lengths of the ORIGINAL mesh for both
+GL(v) and GL(v~), which makes GL a fixed linear operator (GL(v~) with the
+reconstruction's own distances is undefined when reconstructed vertices
+coincide).  dB = 10 log10.
+
+Section 5, Eq. 6: the DOI residual e = sum_{j in x,y,z} (v_j - U U^T v_j).
+
+Choice of c (Section 5: smallest subspace meeting a quality constraint):
+smallest c in [1, c_max] with NMSVE(c) <= target (c_max if none), then moved
+up to the first cut with a relative spectral gap
+(lambda_{c+1} - lambda_c) / lambda_{c+1} >= g_min, so the kept subspace is
+well defined (reading; the paper is silent on near-ties).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import laplacian as lap
+
+
+def gl_matrix(n: int, edges: np.ndarray, coords0: np.ndarray) -> np.ndarray:
+    """Dense GL operator: G = I - D_d^-1 A_d, A_d the 1/d_ij adjacency of the
+    original mesh, D_d its row sums.  Rows of isolated vertices are identity."""
+    w = lap.edge_weights(edges, coords0, lap.INV_DIST)
+    A = np.zeros((n, n))
+    A[edges[:, 0], edges[:, 1]] = w
+    A[edges[:, 1], edges[:, 0]] = w
+    d = A.sum(1)
+    G = np.eye(n)
+    nz = d > 0
+    G[nz] -= A[nz] / d[nz, None]
+    return G
+
+
+def nmsve(X: np.ndarray, Xr: np.ndarray, G: np.ndarray) -> float:
+    """Eq. 16 (literal reading above)."""
+    n = X.shape[0]
+    a = np.linalg.norm(X - Xr)
+    b = np.linalg.norm(G @ X - G @ Xr)
+    return float((a + b) / (2.0 * n))
+
+
+def nmsve_db(x: float) -> float:
+    return float(10.0 * np.log10(x))
+
+
+def nmsve_curve(U: np.ndarray, X: np.ndarray, G: np.ndarray, c_max: int) -> np.ndarray:
+    """NMSVE(c) for c = 1..c_max, each by an explicit reconstruction with the
+    first c columns of U (brute force)."""
+    out = np.empty(c_max)
+    for c in range(1, c_max + 1):
+        Uc = U[:, :c]
+        out[c - 1] = nmsve(X, Uc @ (Uc.T @ X), G)
+    return out
+
+
+def l2_residual_curve(U: np.ndarray, X: np.ndarray, c_max: int) -> np.ndarray:
+    """||X - U_c U_c^T X||_F for c = 1..c_max, brute force."""
+    return np.array([np.linalg.norm(X - U[:, :c] @ (U[:, :c].T @ X)) for c in range(1, c_max + 1)])
+
+
+def choose_c(curve: np.ndarray, lam: np.ndarray, target: float, g_min: float) -> int:
+    """Smallest c with curve[c-1] <= target (len(curve) if none), then snapped
+    up to the first c whose relative gap to lambda_{c+1} is >= g_min (never
+    beyond len(curve))."""
+    c_max = curve.size
+    ok = np.nonzero(curve <= target)[0]
+    c = int(ok[0]) + 1 if ok.size else c_max
+    while c < c_max and c < lam.size:
+        if (lam[c] - lam[c - 1]) >= g_min * abs(lam[c]):
+            break
+        c += 1
+    return c
+
+
+def doi_residual(U: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Eq. 6: e = sum over x, y, z of (v_j - U U^T v_j); an n-vector."""
+    R = X - U @ (U.T @ X)
+    return R.sum(axis=1)

@@ -1,0 +1,395 @@
+"""Pins of the CPU oracle against mathematics that shares no code with it:
+closed-form spectra, exact integer arithmetic, brute force and identities.
+
+Each test names the part of the paper it fixes.  None of them recomputes an
+oracle formula with the same library call it makes.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle import iterations as it
+from oracle import laplacian as lap
+from oracle import metrics as met
+from oracle import spectral as S
+from synth import meshes as M
+from synth import workloads as W
+
+
+def path_edges(n):
+    return np.stack([np.arange(n - 1), np.arange(1, n)], 1)
+
+
+def cycle_edges(n):
+    return np.stack([np.arange(n), (np.arange(n) + 1) % n], 1)
+
+
+def grid_edges(a, b):
+    idx = np.arange(a * b).reshape(a, b)
+    h = np.stack([idx[:, :-1].ravel(), idx[:, 1:].ravel()], 1)
+    v = np.stack([idx[:-1, :].ravel(), idx[1:, :].ravel()], 1)
+    return np.concatenate([h, v])
+
+
+def comb_L(prims, n):
+    e = lap.canonical_edges(prims, n)
+    return e, lap.laplacian_dense(n, e, np.ones(len(e)))
+
+
+# ---------------------------------------------------------------- Section 3, Eq. 1-2
+
+class TestLaplacianInvariants:
+    @pytest.fixture(scope="class")
+    def block(self):
+        bs = W.icosphere_blocks(level=4, n_blocks=6, c=20, p=30)
+        return bs
+
+    def test_csr_matches_dense_and_invariants(self, block):
+        for b in range(block.n_blocks):
+            X = block.coords[b]
+            n = X.shape[0]
+            for mode in (lap.COMBINATORIAL, lap.INV_SQ_DIST):
+                e = lap.canonical_edges(block.faces[b], n)
+                w = lap.edge_weights(e, X, mode)
+                L = lap.laplacian_dense(n, e, w)
+                rp, col, val = lap.laplacian_csr(n, e, w)
+                # CSR structure: diagonal present, columns ascending, degree = nnz - 1
+                for i in range(n):
+                    cols = col[rp[i]:rp[i + 1]]
+                    assert i in cols
+                    assert np.all(np.diff(cols) > 0)
+                deg = np.zeros(n, dtype=int)
+                np.add.at(deg, e[:, 0], 1)
+                np.add.at(deg, e[:, 1], 1)
+                assert np.array_equal(np.diff(rp) - 1, deg)
+                tol = 0.0 if mode == lap.COMBINATORIAL else 1e-14 * np.abs(L).max()
+                assert np.abs(lap.csr_to_dense(n, rp, col, val) - L).max() <= tol
+                # symmetric, zero row sums, PSD, trace = 2 sum w
+                assert np.array_equal(L, L.T)
+                assert np.abs(L.sum(1)).max() <= 1e-12 * max(1.0, np.abs(L).max())
+                lam = np.linalg.eigvalsh(L)
+                assert lam.min() >= -1e-10 * lam.max()
+                assert math.isclose(np.trace(L), 2 * w.sum(), rel_tol=1e-12)
+
+    def test_null_space_dimension_is_component_count(self):
+        # two disjoint triangles + an isolated vertex: 3 components
+        f = np.array([[0, 1, 2], [3, 4, 5]])
+        e, L = comb_L(f, 7)
+        lam = np.linalg.eigvalsh(L)
+        assert int((np.abs(lam) < 1e-12).sum()) == 3
+        # the constant vector is always in the null space
+        assert np.abs(L @ np.ones(7)).max() == 0
+
+    def test_outside_corner_and_degenerate_faces(self):
+        # -1 corner drops its edges; repeated corner gives no self loop
+        f = np.array([[0, 1, -1], [1, 1, 2], [2, 0, 1], [0, 1, 2]])
+        e = lap.canonical_edges(f, 3)
+        assert e.tolist() == [[0, 1], [0, 2], [1, 2]]
+        with pytest.raises(lap.IndexError_):
+            lap.canonical_edges(np.array([[0, 1, 3]]), 3)
+        with pytest.raises(lap.DegenerateError):
+            lap.edge_weights(np.array([[0, 1]]), np.zeros((2, 3)), lap.INV_SQ_DIST)
+
+    def test_literal_mixed_form_is_not_a_laplacian(self):
+        # reading of Eq. 1-2: D = |N(i)| with weighted C breaks L 1 = 0
+        v, f = M.octahedron()
+        v = v * np.array([1.0, 2.0, 0.5])
+        e = lap.canonical_edges(f, 6)
+        w = lap.edge_weights(e, v, lap.INV_SQ_DIST)
+        Lm = lap.laplacian_literal_mixed(6, e, w)
+        assert np.abs(Lm.sum(1)).max() > 1e-3
+        Lw = lap.laplacian_dense(6, e, w)
+        assert np.abs(Lw.sum(1)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- Eq. 3, closed forms
+
+class TestClosedFormSpectra:
+    @pytest.mark.parametrize("n", [2, 5, 17, 64])
+    def test_path(self, n):
+        _, L = comb_L(path_edges(n), n)
+        k = np.arange(n)
+        ref = np.sort(2 - 2 * np.cos(k * np.pi / n))
+        lam, U = S.eigh_lowest(L)
+        assert np.abs(lam - ref).max() < 1e-12
+        # eigenvectors cos(k pi (i + 1/2) / n): subspace pins for every c
+        i = np.arange(n)
+        Uref = np.cos(np.pi * np.outer(i + 0.5, k) / n)
+        for c in range(1, n):
+            assert S.sin_theta_max(Uref[:, :c], U[:, :c]) < 1e-9
+
+    @pytest.mark.parametrize("n", [3, 8, 31])
+    def test_cycle(self, n):
+        _, L = comb_L(cycle_edges(n), n)
+        ref = np.sort(2 - 2 * np.cos(2 * np.pi * np.arange(n) / n))
+        assert np.abs(np.linalg.eigvalsh(L) - ref).max() < 1e-12
+
+    @pytest.mark.parametrize("a,b", [(3, 4), (7, 5), (10, 10)])
+    def test_grid_product(self, a, b):
+        _, L = comb_L(grid_edges(a, b), a * b)
+        pa = 2 - 2 * np.cos(np.pi * np.arange(a) / a)
+        pb = 2 - 2 * np.cos(np.pi * np.arange(b) / b)
+        ref = np.sort((pa[:, None] + pb[None, :]).ravel())
+        assert np.abs(np.linalg.eigvalsh(L) - ref).max() < 1e-11
+
+    @pytest.mark.parametrize("a,b", [(3, 3), (7, 9), (12, 5)])
+    def test_triangulated_torus_from_faces(self, a, b):
+        f = M.torus_faces(a, b)
+        _, L = comb_L(f, a * b)
+        t1 = 2 * np.pi * np.arange(a)[:, None] / a
+        t2 = 2 * np.pi * np.arange(b)[None, :] / b
+        ref = np.sort((6 - 2 * np.cos(t1) - 2 * np.cos(t2) - 2 * np.cos(t1 + t2)).ravel())
+        assert np.abs(np.linalg.eigvalsh(L) - ref).max() < 1e-11
+
+    def test_platonic_solids(self):
+        r5 = 5 ** 0.5
+        cases = {
+            "tetrahedron": (M.tetrahedron(), [0, 4, 4, 4]),
+            "octahedron": (M.octahedron(), [0, 4, 4, 4, 6, 6]),
+            "icosahedron": (M.icosahedron(), [0] + [5 - r5] * 3 + [6] * 5 + [5 + r5] * 3),
+        }
+        for name, ((v, f), ref) in cases.items():
+            _, L = comb_L(f, v.shape[0])
+            assert np.abs(np.linalg.eigvalsh(L) - np.array(ref)).max() < 1e-12, name
+
+    def test_golden_platonic_fixture(self):
+        # tests/golden/platonic_spectra.txt holds the closed forms written out
+        import os
+        path = os.path.join(os.path.dirname(__file__), "golden", "platonic_spectra.txt")
+        got = {}
+        for line in open(path):
+            if line.startswith("#") or not line.strip():
+                continue
+            name, vals = line.split(":")
+            got[name.strip()] = [float(x) for x in vals.split()]
+        for name, (v, f) in {"tetrahedron": M.tetrahedron(), "octahedron": M.octahedron(),
+                             "icosahedron": M.icosahedron()}.items():
+            _, L = comb_L(f, v.shape[0])
+            assert np.abs(np.linalg.eigvalsh(L) - np.array(got[name])).max() < 1e-12
+
+
+# ---------------------------------------------------------------- brute force, <= 10 vertices
+
+def small_meshes():
+    out = {}
+    v, f = M.octahedron()
+    out["octahedron"] = (6, f)
+    v, f = M.grid_mesh(3, 3)
+    out["grid3x3"] = (9, f)
+    # a fan of 7 triangles around vertex 0 (9 vertices, open)
+    fan = np.array([[0, i, i + 1] for i in range(1, 8)])
+    out["fan9"] = (9, fan)
+    # 10-vertex strip with one -1 corner (a face cut by the block boundary)
+    strip = np.array([[i, i + 1, i + 2] for i in range(8)] + [[9, 0, -1]])
+    out["strip10"] = (10, strip)
+    return out
+
+
+@pytest.mark.parametrize("name", list(small_meshes().keys()))
+def test_exact_charpoly_eigenvalues(name):
+    n, f = small_meshes()[name]
+    _, L = comb_L(f, n)
+    ev_exact = exact.eigenvalues_exact(L.astype(int).tolist())
+    lam = np.linalg.eigvalsh(L)
+    assert np.abs(np.array(ev_exact) - lam).max() < 1e-10
+
+
+@pytest.mark.parametrize("name", ["octahedron", "grid3x3", "fan9"])
+def test_matrix_tree_theorem(name):
+    n, f = small_meshes()[name]
+    e, L = comb_L(f, n)
+    tau = exact.spanning_trees_bruteforce(n, e.tolist())
+    lam = np.linalg.eigvalsh(L)
+    prod = np.prod(lam[1:]) / n
+    assert abs(prod - tau) < 1e-6 * tau
+
+
+def test_charpoly_small_known():
+    # path on 3 vertices: L = [[1,-1,0],[-1,2,-1],[0,-1,1]], det(xI-L) = x^3 - 4x^2 + 3x
+    cp = exact.charpoly([[1, -1, 0], [-1, 2, -1], [0, -1, 1]])
+    assert cp == [Fraction(1), Fraction(-4), Fraction(3), Fraction(0)]
+
+
+# ---------------------------------------------------------------- GFT, Sections 3 and 7
+
+class TestProjection:
+    @pytest.fixture(scope="class")
+    def setup(self):
+        bs = W.grid_single(nx=12, ny=10, c=10, p=15)
+        X = bs.coords[0]
+        _, L = comb_L(bs.faces[0], X.shape[0])
+        lam, U = S.eigh_lowest(L)
+        return X, L, lam, U
+
+    def test_full_basis_is_identity(self, setup):
+        X, L, lam, U = setup
+        assert np.abs(S.encode_decode(U, X) - X).max() < 1e-12
+
+    def test_c1_gives_centroid(self, setup):
+        X, L, lam, U = setup
+        Xr = S.encode_decode(U[:, :1], X)
+        assert np.abs(Xr - X.mean(0)[None, :]).max() < 1e-12
+
+    def test_projector_idempotent_and_pythagoras(self, setup):
+        X, L, lam, U = setup
+        for c in (3, 17, 60):
+            Uc = U[:, :c]
+            Xr = S.encode_decode(Uc, X)
+            assert np.abs(S.encode_decode(Uc, Xr) - Xr).max() < 1e-12
+            E = S.project(Uc, X)
+            assert math.isclose((X ** 2).sum(), (E ** 2).sum() + ((X - Xr) ** 2).sum(), rel_tol=1e-12)
+
+    def test_kept_eigenvector_reconstructs_exactly(self):
+        n = 40
+        _, L = comb_L(path_edges(n), n)
+        lam, U = S.eigh_lowest(L)
+        i = np.arange(n)
+        X = np.stack([np.cos(np.pi * 3 * (i + 0.5) / n), np.cos(np.pi * 5 * (i + 0.5) / n),
+                      np.ones(n)], 1)
+        assert np.abs(S.encode_decode(U[:, :6], X) - X).max() < 1e-11
+        assert np.abs(S.encode_decode(U[:, :5], X)[:, 1]).max() < 1e-11  # k=5 dropped
+
+    def test_principal_angles_known_rotation(self):
+        rng = np.random.default_rng(0)
+        Q, _ = np.linalg.qr(rng.normal(size=(30, 4)))
+        th = np.array([1e-7, 1e-3, 0.2, 1.0])
+        # rotate each basis vector towards an orthogonal complement vector by th
+        C, _ = np.linalg.qr(rng.normal(size=(30, 4)) - Q @ (Q.T @ rng.normal(size=(30, 4))))
+        C = C - Q @ (Q.T @ C)
+        C, _ = np.linalg.qr(C)
+        B = Q * np.cos(th) + C * np.sin(th)
+        ang = S.principal_angles(Q, B)
+        assert np.allclose(ang, np.sort(th), rtol=1e-6, atol=1e-12)
+        assert math.isclose(S.sin_theta_max(Q, B), np.sin(1.0), rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------- Eq. 16, Eq. 6, choice of c
+
+class TestMetrics:
+    def test_nmsve_hand_example(self):
+        # 4-cycle square of side 1 (d = 1 on every edge), one vertex moved.
+        X = np.array([[0., 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]])
+        e = cycle_edges(4)
+        G = met.gl_matrix(4, lap.canonical_edges(e, 4), X)
+        Xr = X.copy()
+        Xr[0, 2] = 0.3
+        # GL(v) - GL(v~) is zero except: vertex 0 gets 0.3*... by hand:
+        # GL_0 diff = -0.3 (z), neighbours 1 and 3 each + 0.15 (z)
+        d1 = 0.3
+        d2 = math.sqrt(0.3 ** 2 + 2 * 0.15 ** 2)
+        assert math.isclose(met.nmsve(X, Xr, G), (d1 + d2) / 8, rel_tol=1e-12)
+
+    def test_gl_annihilates_constants(self):
+        bs = W.grid_single(nx=6, ny=7, c=5, p=8)
+        X = bs.coords[0]
+        e = lap.canonical_edges(bs.faces[0], X.shape[0])
+        G = met.gl_matrix(X.shape[0], e, X)
+        assert np.abs(G @ np.ones(X.shape[0])).max() < 1e-14
+
+    def test_prefix_identity_and_monotone_l2(self):
+        bs = W.grid_single(nx=10, ny=9, c=5, p=8)
+        X = bs.coords[0]
+        _, L = comb_L(bs.faces[0], X.shape[0])
+        lam, U = S.eigh_lowest(L)
+        E = U.T @ X
+        curve = met.l2_residual_curve(U, X, 60)
+        pref = np.sqrt(np.maximum((X ** 2).sum() - np.cumsum((E ** 2).sum(1))[:60], 0))
+        assert np.abs(curve - pref).max() < 1e-10 * np.linalg.norm(X)
+        assert np.all(np.diff(curve) <= 1e-12)
+
+    def test_choose_c_rule(self):
+        curve = np.array([5.0, 4.0, 2.0, 0.5, 0.4, 0.1])
+        lam = np.array([0.0, 1.0, 2.0, 3.0, 3.0001, 5.0, 6.0])
+        assert met.choose_c(curve, lam, 1.0, 0.0) == 4
+        # 4 -> lambda_5 - lambda_4 tiny relative gap: snap up to 5
+        assert met.choose_c(curve, lam, 1.0, 1e-3) == 5
+        assert met.choose_c(curve, lam, 1e-3, 1e-3) == 6  # target unreachable: c_max
+
+    def test_doi_residual_eq6(self):
+        rng = np.random.default_rng(1)
+        U, _ = np.linalg.qr(rng.normal(size=(20, 20)))
+        X = rng.normal(size=(20, 3))
+        assert np.abs(met.doi_residual(U, X)).max() < 1e-12
+        e = met.doi_residual(U[:, :5], X)
+        assert np.allclose(e, (X - U[:, :5] @ (U[:, :5].T @ X)).sum(1))
+
+
+# ---------------------------------------------------------------- Alg. 1, Section 4 rate
+
+class TestIterations:
+    def test_paper_oi_converges_at_rate_of_R(self):
+        bs = W.grid_single(nx=14, ny=12, c=6, p=6)
+        X = bs.coords[0]
+        n = X.shape[0]
+        _, L = comb_L(bs.faces[0], n)
+        lam, U = S.eigh_lowest(L)
+        c, delta, z = 6, 1e-2, 1
+        U0 = M.random_orthonormal(n, c, M.rng_for(77))
+        hist = []
+        it.paper_oi(L, U0, z, delta, 60, history=hist)
+        ang = np.array([S.sin_theta_max(U[:, :c], H) for H in hist])
+        # eigenvalues of R = (L + delta)^-1: the rate is mu_{c+1}/mu_c
+        rate = ((lam[c - 1] + delta) / (lam[c] + delta)) ** z
+        k0, k1 = 20, 40
+        measured = (ang[k1] / ang[k0]) ** (1.0 / (k1 - k0))
+        assert abs(measured - rate) < 0.02
+        assert ang[-1] < ang[0]
+
+    def test_paper_oi_z_power_reaches_svd_subspace(self):
+        bs = W.grid_single(nx=10, ny=10, c=8, p=8)
+        n = 100
+        _, L = comb_L(bs.faces[0], n)
+        lam, U = S.eigh_lowest(L)
+        # c = 5 sits at a clear gap (lambda_5 = 0.513, lambda_6 = 0.671)
+        U0 = M.random_orthonormal(n, 5, M.rng_for(78))
+        Uz = it.paper_oi(L, U0, 5, 1e-3, 40)
+        assert S.sin_theta_max(U[:, :5], Uz) < 1e-8
+
+    def test_chebyshev_apply_closed_form(self):
+        # T_m(t(L)) V = U T_m(t(Lambda)) U^T V with T_m from its trigonometric /
+        # hyperbolic closed form
+        bs = W.grid_single(nx=8, ny=9, c=5, p=8)
+        n = 72
+        _, L = comb_L(bs.faces[0], n)
+        lam, U = np.linalg.eigh(L)
+        a, b, m = 2.0, 9.0, 7
+        t = (2 * lam - a - b) / (b - a)
+        Tm = np.where(np.abs(t) <= 1, np.cos(m * np.arccos(np.clip(t, -1, 1))),
+                      np.sign(t) ** m * np.cosh(m * np.arccosh(np.maximum(np.abs(t), 1))))
+        V = np.random.default_rng(2).normal(size=(n, 4))
+        ref = U @ (Tm[:, None] * (U.T @ V))
+        got = it.chebyshev_apply(L, V, a, b, m)
+        assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+
+    def test_chebyshev_span_converges_to_eigenspace(self):
+        bs = W.grid_single(nx=12, ny=12, c=10, p=15)
+        n = 144
+        _, L = comb_L(bs.faces[0], n)
+        lam, U = np.linalg.eigh(L)
+        V0 = M.random_orthonormal(n, 15, M.rng_for(79))
+        Vs = it.chebyshev_span(L, V0, lam[15], lam[-1] + 0.1, 8, 12)
+        th, Vr = it.rayleigh_ritz(L, Vs)
+        assert S.sin_theta_max(U[:, :10], Vr[:, :10]) < 1e-9
+        assert np.abs(th[:10] - lam[:10]).max() < 1e-10
+
+    def test_doi_grows_and_shrinks(self):
+        bs = W.grid_single(nx=10, ny=10, c=4, p=4)
+        X = bs.coords[0]
+        _, L = comb_L(bs.faces[0], 100)
+        lam, U = np.linalg.eigh(L)
+        U0 = U[:, :4]
+        # a band that needs more columns than 4
+        target = np.linalg.norm(met.doi_residual(U[:, :12], X))
+        eps_l, eps_h = 0.5 * target, 1.01 * target
+        Ud, c, traj = it.paper_doi(L, U0, X, 2, 1e-3, eps_l, eps_h, 40)
+        assert c > 4
+        # Alg. 2 stops once the Eq. 6 residual of its own basis is inside the band
+        ne = np.linalg.norm(met.doi_residual(Ud, X))
+        assert eps_l <= ne <= eps_h
+        assert np.abs(Ud.T @ Ud - np.eye(c)).max() < 1e-12
+        # a band below the current error floor shrinks c
+        _, c2, _ = it.paper_doi(L, U[:, :30], X, 2, 1e-3, 1e9, 2e9, 40)
+        assert c2 < 30

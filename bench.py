@@ -1,0 +1,194 @@
+"""Throughput of the block-based spectral hot path on one MI355X.
+
+Workload: a displaced level-7 icosphere (163,842 vertices) split by seeded
+region growing into 100 submeshes of ~1,638 vertices, combinatorial
+Laplacian, c = 100 tracked eigenvectors per block (width p = 192), the first
+block from a seeded random start, every other block warm-started from its
+predecessor in BFS block order with 3 orthogonal-iteration steps, FP32.
+
+One step = eigenspace tracking of all blocks (every wave, one HIP graph
+replay) + projection of the xyz coordinates onto the first c Ritz vectors +
+reconstruction.  The Laplacian build is timed separately (outside the step).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-blocks", type=int, default=24)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + a few steps only (for profilers)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the workload is one GPU's share and no "
+              "multi-GPU path is built (see DESIGN.md, sharding).", file=sys.stderr)
+        return 2
+    import torch
+
+    import paper_1810_02719_amd as mis
+    from synth import workloads as W
+
+    t0 = time.time()
+    bs = W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192)
+    fl = W.flatten(bs)
+    dev = "cuda:0"
+    blocks = mis.Blocks(bs.n, p=fl["p"], ld=fl["ld"], pred=bs.pred)
+    prims = torch.from_numpy(np.ascontiguousarray(fl["prims"].reshape(-1))).to(dev)
+    coords = torch.from_numpy(np.ascontiguousarray(fl["coords"].reshape(-1))).to(dev)
+    V0 = np.zeros(int(blocks.u_off[-1]), np.float32)
+    starts = W.random_starts(bs)
+    for b in range(bs.n_blocks):
+        if bs.pred[b] < 0:
+            n, ld = int(blocks.n[b]), int(blocks.ld[b])
+            V0[int(blocks.u_off[b]):int(blocks.u_off[b + 1])].reshape(n, ld)[:, :192] = starts[b]
+    V0 = torch.from_numpy(V0).to(dev)
+    gen_s = time.time() - t0
+
+    ctx = mis.Context(0)
+    # Laplacian build (reported separately)
+    torch.cuda.synchronize()
+    tl = time.time()
+    L = mis.build_laplacian(ctx, blocks, fl["prim_off"], prims, 3, coords, mis.MI_W_COMBINATORIAL)
+    torch.cuda.synchronize()
+    lap_ms = (time.time() - tl) * 1e3
+
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED, T=3, m=10, passes=2, T0=8,
+                       m0=8, passes0=1, adapt=1, max_sweeps=12, a_mode=mis.MI_A_WEYL, a_value=1.0)
+    V = torch.empty(int(blocks.u_off[-1]), dtype=torch.float32, device=dev)
+    ritz = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
+    status = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+    c = torch.full((blocks.n_blocks,), 100, dtype=torch.int32, device=dev)
+    E = torch.empty(int(blocks.t_off[-1]) * 3, dtype=torch.float32, device=dev)
+    Xr = torch.empty(int(blocks.v_off[-1]) * 3, dtype=torch.float32, device=dev)
+
+    def step():
+        mis.oi_track(ctx, blocks, L, prm, V0=V0, V=V, ritz=ritz, status=status)
+        mis.project(ctx, blocks, c, V, coords, E=E)
+        mis.reconstruct(ctx, blocks, c, V, E, Xr=Xr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = 2 if args.profile_only else args.steps
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(K):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / K
+    nverts = int(blocks.v_off[-1])
+    value = nverts / (ms * 1e-3)
+    st = status.cpu().numpy()
+
+    # plain per-block GPU OI (same kernels, one block per launch sequence, no graph)
+    tp = time.time()
+    mis.oi_track(ctx, blocks, L, prm, V0=V0, ritz=torch.zeros_like(ritz),
+                 status=torch.zeros_like(status), per_block=True)
+    torch.cuda.synchronize()
+    tp = time.time()
+    mis.oi_track(ctx, blocks, L, prm, V0=V0, ritz=torch.zeros_like(ritz),
+                 status=torch.zeros_like(status), per_block=True)
+    mis.project(ctx, blocks, c, V, coords, E=E)
+    mis.reconstruct(ctx, blocks, c, V, E, Xr=Xr)
+    torch.cuda.synchronize()
+    per_block_ms = (time.time() - tp) * 1e3
+    # restore the batched result (the per-block run used the same output slab)
+    step()
+    torch.cuda.synchronize()
+
+    out = {
+        "metric": "submesh vertices/sec (OI + project/recon) at principal angle <=1e-5 vs FP64 oracle",
+        "value": value,
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "icosphere7_100blocks_c100_T3_fp32", "vertices": nverts,
+                   "blocks": int(blocks.n_blocks), "c": 100, "p": 192, "T": 3, "m": 10,
+                   "passes": 2, "T_first": 8, "m_first": 8, "waves": int(bs.level.max() + 1)},
+        "per_block_baseline": {"value": nverts / (per_block_ms * 1e-3), "unit": "vertices/s",
+                               "ms": per_block_ms},
+        "build_laplacian_ms": lap_ms,
+        "block_status_nonzero": int((st != 0).sum()),
+        "input_gen_s": gen_s,
+    }
+
+    if not args.no_cpu_baseline and not args.profile_only:
+        out["cpu_baseline"], out["sample_parity"] = cpu_baseline(bs, blocks, V, Xr, args)
+
+    print(json.dumps(out))
+    ctx.close()
+    return 0
+
+
+def cpu_baseline(bs, blocks, V, Xr, args):
+    """The FP64 oracle (dense eigh + projection + reconstruction) on a bounded
+    sample of the same blocks, timed on the host; the oracle's subspaces of the
+    sampled blocks also give the GPU result's principal angles."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import laplacian as lap
+    from oracle import spectral as S
+    order = [int(b) for b in bs.order[:args.cpu_sample_blocks]]
+    Vh = V.double().cpu().numpy()
+    Xh = Xr.double().cpu().numpy().reshape(-1, 3)
+    angles, recs = [], []
+    t = 0.0
+    nv = 0
+    for b in order:
+        n = int(blocks.n[b])
+        X = bs.coords[b].astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        e = lap.canonical_edges(bs.faces[b], n)
+        Lb = lap.laplacian_dense(n, e, np.ones(len(e)))
+        lam, U = S.eigh_lowest(Lb)
+        Xo = S.encode_decode(U[:, :100], X)
+        t += time.perf_counter() - t0
+        nv += n
+        ld = int(blocks.ld[b])
+        Vg = Vh[int(blocks.u_off[b]):int(blocks.u_off[b + 1])].reshape(n, ld)[:, :100]
+        angles.append(S.sin_theta_max(U[:, :100], Vg))
+        v0 = int(blocks.v_off[b])
+        recs.append(S.rel_error(Xh[v0:v0 + n], Xo))
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                   if i.get("internal_api") in ("openblas", "mkl", "blis")] or [1])
+    base = {"value": nv / t, "unit": "vertices/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(order)} of {bs.n_blocks} blocks (first in BFS order, {nv} vertices): "
+                      f"dense FP64 eigh + projection + reconstruction, {t:.1f} s"}
+    par = {"blocks": len(order), "sin_angle_max": float(max(angles)),
+           "sin_angle_median": float(np.median(angles)),
+           "recon_rel_err_max": float(max(recs))}
+    return base, par
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,259 @@
+/*
+ * mispectral — block-based spectral processing of triangle meshes on MI355X.
+ *
+ * C ABI of the GPU library.  A mesh is split into submeshes ("blocks"); for
+ * every block the library builds the graph Laplacian, tracks the eigenspace
+ * of its c lowest eigenvalues by orthogonal iteration warm-started from a
+ * predecessor block, projects the xyz coordinates onto it (graph Fourier
+ * transform), truncates and reconstructs.  Method: Arvanitis, Lalos,
+ * Moustakas, "Block-Based Spectral Processing of Static and Dynamic 3D Meshes
+ * using Orthogonal Iterations" (arXiv 1810.02719); sections, equations and
+ * algorithms below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns mi_status: 0 on success, a negative MI_ERR_* code
+ *    otherwise; mi_last_error() gives a message for the calling thread.
+ *    Argument errors are detected on the host before anything is enqueued.
+ *  - Memory: the caller owns every buffer.  Pointers documented "device"
+ *    must point to device memory of the context's GPU; "host" pointers to
+ *    host memory read during the call only.  The library keeps no pointer
+ *    after a call returns, except inside an mi_ctx (see mi_oi_track).
+ *  - Streams: `stream` is a hipStream_t (NULL = default stream).  Calls only
+ *    enqueue work on it unless documented as synchronous.
+ *  - The *_workspace_size queries are host arithmetic only (ctx may be NULL);
+ *    they validate the block table and parameters like the calls they size.
+ *  - Block layout: blocks are concatenated.  Block b owns the vertex rows
+ *    v_off[b] .. v_off[b+1]-1 of every per-vertex array (vertex ids inside a
+ *    block are block-local, 0 .. n_b-1).  The tracked subspace of block b is
+ *    a row-major n_b x ld_b slab (vertex-major: the p_b coefficients of a
+ *    vertex are contiguous) starting at element u_off[b]; columns
+ *    p_b .. ld_b-1 are padding and hold zeros on output.
+ *  - CSR of the block Laplacians: row_ptr holds n_b+1 block-local offsets
+ *    per block, at position v_off[b] + b; col / val of block b start at
+ *    nnz_off[b]; column ids are block-local, ascending, the diagonal is
+ *    always stored.
+ */
+#ifndef MISPECTRAL_H
+#define MISPECTRAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mi_status;
+
+#define MI_OK 0
+#define MI_ERR_ARG (-1)        /* invalid argument (checked on the host)            */
+#define MI_ERR_INDEX (-2)      /* a primitive references a vertex outside its block */
+#define MI_ERR_DEGENERATE (-3) /* zero-length edge under a distance weight          */
+#define MI_ERR_NOT_PD (-4)     /* a Gram matrix was not positive definite           */
+#define MI_ERR_NOCONV (-5)     /* an eigen-solve did not converge                   */
+#define MI_ERR_HIP (-6)        /* a HIP runtime call failed                         */
+#define MI_ERR_WORKSPACE (-7)  /* workspace smaller than the size query returned    */
+#define MI_ERR_CAPACITY (-8)   /* c > p_b, p_b > n_b or ld_b too small             */
+
+/* Off-diagonal weights C_ij of the Laplacian L = D - C (Section 3). */
+#define MI_W_COMBINATORIAL 0 /* C = adjacency, D_ii = |N(i)|                       */
+#define MI_W_INV_SQ_DIST 1   /* C_ij = 1/||v_i - v_j||^2 (Eq. 2), D_ii = sum_j C_ij */
+#define MI_W_USER 2          /* C_ij = user weight per canonical edge              */
+#define MI_W_INV_DIST 3      /* C_ij = 1/||v_i - v_j|| (the GL operator of Eq. 16)  */
+
+/* Arithmetic of the tall-skinny products (SpMM, Gram operands, rotations). */
+#define MI_FP32 0
+#define MI_FP64 1
+
+/* Start subspace of a block in mi_oi_track. */
+#define MI_WARM_GIVEN 0 /* V0 holds a start for every block                          */
+#define MI_WARM_PRED 1  /* blocks with pred >= 0 start from their predecessor's result */
+
+/* Per-block status codes written to `status` by mi_oi_track (device). */
+#define MI_BLOCK_OK 0
+#define MI_BLOCK_SHIFTED 1   /* a Cholesky factorisation needed a diagonal shift   */
+#define MI_BLOCK_NOT_PD 2    /* a Cholesky factorisation failed even when shifted */
+#define MI_BLOCK_NOCONV 4    /* Jacobi sweeps exhausted before convergence         */
+#define MI_BLOCK_NONFINITE 8 /* NaN / Inf met in a small matrix                    */
+
+typedef struct mi_ctx mi_ctx;
+
+/* Block table (all host memory). */
+typedef struct {
+  int32_t n_blocks;
+  const int64_t* v_off; /* [n_blocks+1] first vertex row of each block                 */
+  const int32_t* p;     /* [n_blocks]   tracked subspace width p_b (1 <= p_b <= n_b)   */
+  const int32_t* ld;    /* [n_blocks]   row stride of the slab, multiple of 32, >= p_b */
+  const int64_t* u_off; /* [n_blocks+1] slab offsets, u_off[b+1]-u_off[b] = n_b*ld_b    */
+  const int32_t* pred;  /* [n_blocks] warm-start predecessor (-1 none), or NULL        */
+} mi_blocks;
+
+/* Parameters of the eigenspace tracking (mi_oi_track). */
+typedef struct {
+  int32_t precision; /* MI_FP32 or MI_FP64                                            */
+  int32_t warm;      /* MI_WARM_GIVEN or MI_WARM_PRED                                 */
+  int32_t T;         /* outer iterations of blocks that have a predecessor            */
+  int32_t m;         /* Chebyshev degree of one filter pass, same blocks              */
+  int32_t passes;    /* filter passes per iteration, same blocks (>= 1)               */
+  int32_t T0;        /* the same three for blocks without a predecessor (and for      */
+  int32_t m0;        /* every block under MI_WARM_GIVEN)                              */
+  int32_t passes0;
+  int32_t adapt;     /* 1: lower filter bound a <- largest Ritz value after each
+                        Rayleigh-Ritz step; 0: keep the initial a                      */
+  int32_t max_sweeps;/* cap on Jacobi sweeps per Rayleigh-Ritz step (e.g. 12)         */
+  int32_t a_mode;    /* initial a of blocks that do not start from a predecessor:      */
+                     /*   MI_A_WEYL: a_value * b * p_b / n_b                            */
+                     /*   MI_A_ABS:  a_value                                            */
+                     /*   MI_A_RITZ: largest entry of the block's `ritz` on input      */
+                     /* (a block starting from predecessor P takes the largest Ritz    */
+                     /*  value of P scaled by n_P / n_b)                               */
+  int32_t reserved;
+  double a_value;
+  double b_abs;      /* > 0: upper filter bound b for every block; else Gershgorin     */
+  double jacobi_tol; /* off-diagonal threshold relative to ||A||_F (e.g. 1e-14)        */
+} mi_oi_params;
+
+#define MI_A_WEYL 0
+#define MI_A_ABS 1
+#define MI_A_RITZ 2
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device` (owns the launch plans, captured
+ * graphs and a device copy of block tables).  Synchronous. */
+mi_status mi_ctx_create(mi_ctx** out, int32_t device);
+mi_status mi_ctx_destroy(mi_ctx* ctx);
+/* Message of the last error on the calling thread ("" if none). */
+const char* mi_last_error(void);
+/* Library version string. */
+const char* mi_version(void);
+
+/* ---------------------------------------------------------------- Laplacian
+ * Section 3, Eq. 1-2: edge set E derived from the faces, L = D - C.  The
+ * block's graph is the subgraph induced by its vertices: every edge of a
+ * primitive whose two corners are in the block (corner id -1 marks a corner
+ * outside the block; its edges are dropped).  Self loops are dropped and
+ * duplicate edges merged.  Weighted modes use D_ii = sum_j C_ij so that L is
+ * a true Laplacian (rows sum to zero).
+ *
+ * prims    device int32 [prim_off[B]][arity], arity 3 (faces) or 2 (edges),
+ *          block-local corner ids in [-1, n_b).
+ * prim_off host int64 [B+1], first primitive of each block.
+ * Canonical edges of a block: (i, j), i < j, sorted lexicographically. */
+
+/* Workspace bytes for the two calls below. */
+mi_status mi_laplacian_workspace_size(const mi_blocks* blk, const int64_t* prim_off,
+                                      int32_t arity, size_t* ws_bytes);
+
+/* Counts the CSR entries and canonical edges of every block.  Writes host
+ * nnz_off[B+1] and edge_off[B+1] (offsets into col/val and edges).
+ * Synchronous (waits for the stream).  MI_ERR_INDEX if a corner id is out of
+ * range. */
+mi_status mi_build_laplacian_count(mi_ctx* ctx, const mi_blocks* blk, const int64_t* prim_off,
+                                   const int32_t* prims, int32_t arity, int64_t* nnz_off,
+                                   int64_t* edge_off, void* ws, size_t ws_bytes, void* stream);
+
+/* Builds the CSR (row_ptr int32 [v_off[B]+B], col int32 / val float
+ * [nnz_off[B]]) and the canonical edges (edges int32 [edge_off[B]][2] block-
+ * local, edge_w float [edge_off[B]] = C_ij).  coords: device float [v_off[B]][3]
+ * (read for the distance modes, may be NULL otherwise); user_w: device float
+ * per canonical edge for MI_W_USER (else NULL).  Structure is bit-exact;
+ * weights are computed in FP64 and rounded once.  Synchronous; returns
+ * MI_ERR_INDEX / MI_ERR_DEGENERATE for bad input. */
+mi_status mi_build_laplacian(mi_ctx* ctx, const mi_blocks* blk, const int64_t* prim_off,
+                             const int32_t* prims, int32_t arity, const int64_t* nnz_off,
+                             const int64_t* edge_off, int32_t weight_mode, const float* coords,
+                             const float* user_w, int32_t* row_ptr, int32_t* col, float* val,
+                             int32_t* edges, float* edge_w, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Recomputes only the values (val, edge_w) on an existing structure (row_ptr,
+ * col, edges from mi_build_laplacian), e.g. for a new frame of a mesh with
+ * fixed connectivity (Section 7.3).  Enqueue only; a zero-length edge sets
+ * *err_flag (device int32, may be NULL) to MI_ERR_DEGENERATE. */
+mi_status mi_laplacian_values(mi_ctx* ctx, const mi_blocks* blk, const int64_t* nnz_off,
+                              const int64_t* edge_off, int32_t weight_mode, const float* coords,
+                              const float* user_w, const int32_t* row_ptr, const int32_t* col,
+                              const int32_t* edges, float* val, float* edge_w, int32_t* err_flag,
+                              void* stream);
+
+/* ---------------------------------------------------------------- tracking
+ * Section 4, Algorithm 1: U(t) = Onorm(R^z U(t-1)) started from the
+ * previous block's subspace.  Here the operator is a polynomial filter of L
+ * (Chebyshev polynomial of degree m, damping [a, b] and amplifying the low
+ * end of the spectrum; applied `passes` times per iteration by CSR SpMMs,
+ * with a span-preserving Cholesky-QR between passes), Onorm is Cholesky-QR
+ * with an FP64 Cholesky of an FP64-accumulated Gram matrix, and every
+ * iteration ends with a Rayleigh-Ritz step (FP64 Jacobi eigen-solve of the
+ * p x p projected matrix) that orders the basis by Ritz value, so the first
+ * c columns are the tracked U_c.  A final Cholesky-QR pass re-orthonormalises
+ * the output without changing the span of any leading column set.
+ *
+ * Blocks are processed in waves: a block runs once its predecessor has
+ * finished (Section 4: the first block from its own start, the others in
+ * topological order); all blocks of a wave run in the same launches.
+ *
+ * val       device float [nnz] Laplacian values (FP32; promoted exactly in FP64 mode)
+ * V0        device [u_off[B]] start slabs (float or double per precision);
+ *           MI_WARM_GIVEN: all blocks; MI_WARM_PRED: blocks without predecessor.
+ * V         device [u_off[B]] output slabs (may alias V0).
+ * ritz      device double [sum p_b] Ritz values per block, ascending
+ *           (block b at sum_{b'<b} p_b').
+ * status    device int32 [B] MI_BLOCK_* flags (valid after the stream syncs).
+ * Workspace from mi_oi_workspace_size.  Enqueue only.  The launch sequence
+ * is captured into a HIP graph per context and replayed while the block
+ * table, parameters and pointers stay the same. */
+mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                               size_t* ws_bytes);
+mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                      const int32_t* row_ptr, const int32_t* col, const float* val,
+                      const int64_t* nnz_off, const void* V0, void* V, double* ritz,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* Same computation without the persistent graph and with one block per
+ * launch sequence: the "plain per-block GPU OI" reference the batched path
+ * is measured against.  Same arguments and results. */
+mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                                const int32_t* row_ptr, const int32_t* col, const float* val,
+                                const int64_t* nnz_off, const void* V0, void* V, double* ritz,
+                                int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- encode / decode
+ * Section 3 (GFT v_bar = U^T v, inverse GFT v = U v_bar) and Section 7.1
+ * (E[i] = U_c^T v[i], v~[i] = U_c E[i]).  c: device int32 [B], 1 <= c_b <= p_b.
+ * X, Xr: device [v_off[B]][3]; E: device [sum p_b][3] (rows k >= c_b are
+ * written as zero: the truncation).  Element type float (MI_FP32) or double
+ * (MI_FP64) for X, E, Xr and U.  Workspace from mi_encdec_workspace_size. */
+mi_status mi_encdec_workspace_size(mi_ctx* ctx, const mi_blocks* blk, int32_t precision,
+                                   size_t* ws_bytes);
+mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const int32_t* c,
+                     const void* U, const void* X, void* E, void* ws, size_t ws_bytes,
+                     void* stream);
+mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const int32_t* c,
+                         const void* U, const void* E, void* Xr, void* stream);
+
+/* ---------------------------------------------------------------- choice of c
+ * Section 5 (smallest subspace meeting a reconstruction-quality target) with
+ * the NMSVE of Eq. 16 as the quality measure: for every c in 1..c_max the
+ * library evaluates NMSVE(c) = (||X - U_c U_c^T X|| + ||GL X - GL U_c U_c^T X||)/(2n)
+ * from prefix sums of the projected coefficients and a quadratic form on the
+ * Gram of GL U (GL with the 1/d weights of the original mesh: the CSR
+ * gl_row_ptr/gl_col/gl_val of an MI_W_INV_DIST Laplacian).  c_b is the
+ * smallest c meeting `target` (c_max if none), moved up to the first c with
+ * a relative Ritz gap (theta_{c+1}-theta_c)/theta_{c+1} >= g_min.
+ * c_max: device int32 [B] per-block cap (<= p_b).  c_out: device int32 [B];
+ * metric_out: device double [sum p_b] NMSVE(c) for c = 1..p_b (entries past
+ * c_max_b undefined).  FP32 only.  Enqueue only. */
+mi_status mi_choose_c_workspace_size(mi_ctx* ctx, const mi_blocks* blk, size_t* ws_bytes);
+mi_status mi_choose_c(mi_ctx* ctx, const mi_blocks* blk, const int32_t* c_max, double target,
+                      double g_min, const float* U, const double* ritz, const float* X,
+                      const int32_t* gl_row_ptr, const int32_t* gl_col, const float* gl_val,
+                      const int64_t* nnz_off, int32_t* c_out, double* metric_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MISPECTRAL_H */

@@ -1,0 +1,257 @@
+"""Block-based spectral processing of triangle meshes on MI355X.
+
+Thin Python binding over the HIP library ``libmispectral.so`` (C ABI in
+``include/mispectral.h``).  Torch provides device memory and the current
+stream; every step of the computation runs in the library's kernels.  The
+functions mirror the C entry points:
+
+    build_laplacian   graph Laplacian of every block (Section 3, Eq. 1-2)
+    oi_track          eigenspace tracking by orthogonal iteration (Section 4, Alg. 1)
+    project           GFT coefficients E = U_c^T X (Section 3, 7.1)
+    reconstruct       inverse GFT X~ = U_c E (Section 3, 7.1)
+    choose_c          per-block subspace size for an NMSVE target (Section 5, Eq. 16)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_FP32, MI_FP64, MI_W_COMBINATORIAL,  # noqa: F401
+                   MI_W_INV_DIST, MI_W_INV_SQ_DIST, MI_W_USER, MI_WARM_GIVEN, MI_WARM_PRED,
+                   MiError)
+
+__all__ = ["Blocks", "Context", "Laplacian", "OiParams", "build_laplacian", "laplacian_values",
+           "oi_track", "project", "reconstruct", "choose_c", "MiError"]
+
+
+def _np_ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Blocks:
+    """Host block table: sizes n_b, tracked widths p_b, slab strides ld_b
+    (multiples of 32) and warm-start predecessors."""
+
+    def __init__(self, n, p=None, ld=None, pred=None):
+        self.n = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+        B = self.n.size
+        self.p = np.ascontiguousarray(np.asarray(p if p is not None else np.ones(B), dtype=np.int32))
+        if ld is None:
+            ld = ((self.p.astype(np.int64) + 31) // 32) * 32
+        self.ld = np.ascontiguousarray(np.asarray(ld, dtype=np.int32))
+        self.pred = (np.ascontiguousarray(np.asarray(pred, dtype=np.int32))
+                     if pred is not None else None)
+        self.v_off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64))
+        self.u_off = np.ascontiguousarray(
+            np.concatenate([[0], np.cumsum(self.n * self.ld.astype(np.int64))]).astype(np.int64))
+        self.t_off = np.concatenate([[0], np.cumsum(self.p.astype(np.int64))]).astype(np.int64)
+        self._s = L.MiBlocks(B, _np_ptr(self.v_off, C.c_int64), _np_ptr(self.p, C.c_int32),
+                             _np_ptr(self.ld, C.c_int32), _np_ptr(self.u_off, C.c_int64),
+                             _np_ptr(self.pred, C.c_int32))
+
+    @property
+    def n_blocks(self):
+        return int(self.n.size)
+
+    @property
+    def ref(self):
+        return C.byref(self._s)
+
+    def slab_view(self, V, b):
+        """Block b's n_b x ld_b view of a flat slab tensor."""
+        return V[int(self.u_off[b]):int(self.u_off[b + 1])].view(int(self.n[b]), int(self.ld[b]))
+
+
+class Context:
+    """Library context on one HIP device; caches workspaces so repeated calls
+    reuse the same buffers (and the library can replay its captured graph)."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        L.check(L.lib().mi_ctx_create(C.byref(h), device))
+        self.h = h
+        self._ws = {}
+
+    def workspace(self, tag, nbytes):
+        t = self._ws.get(tag)
+        if t is None or t.numel() < nbytes:
+            t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                            device=f"cuda:{self.device}")
+            self._ws[tag] = t
+        return t
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            L.lib().mi_ctx_destroy(self.h)
+            self.h = None
+        self._ws.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Laplacian:
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    edges: torch.Tensor
+    edge_w: torch.Tensor
+    nnz_off: np.ndarray
+    edge_off: np.ndarray
+    mode: int
+
+
+def build_laplacian(ctx: Context, blocks: Blocks, prim_off, prims: torch.Tensor, arity: int = 3,
+                    coords: torch.Tensor | None = None, mode: int = MI_W_COMBINATORIAL,
+                    user_w: torch.Tensor | None = None) -> Laplacian:
+    """CSR Laplacian of every block (mi_build_laplacian_count + mi_build_laplacian)."""
+    lib = L.lib()
+    prim_off = np.ascontiguousarray(np.asarray(prim_off, dtype=np.int64))
+    ws_n = C.c_size_t()
+    L.check(lib.mi_laplacian_workspace_size(blocks.ref, _np_ptr(prim_off, C.c_int64), arity,
+                                            C.byref(ws_n)))
+    ws = ctx.workspace("lap", ws_n.value)
+    B = blocks.n_blocks
+    nnz_off = np.zeros(B + 1, np.int64)
+    edge_off = np.zeros(B + 1, np.int64)
+    L.check(lib.mi_build_laplacian_count(ctx.h, blocks.ref, _np_ptr(prim_off, C.c_int64),
+                                         _dptr(prims), arity, _np_ptr(nnz_off, C.c_int64),
+                                         _np_ptr(edge_off, C.c_int64), _dptr(ws), ws.numel(),
+                                         _stream()))
+    dev = prims.device
+    N = int(blocks.v_off[-1])
+    row_ptr = torch.empty(N + B, dtype=torch.int32, device=dev)
+    col = torch.empty(max(int(nnz_off[-1]), 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(int(nnz_off[-1]), 1), dtype=torch.float32, device=dev)
+    edges = torch.empty(max(int(edge_off[-1]), 1) * 2, dtype=torch.int32, device=dev)
+    edge_w = torch.empty(max(int(edge_off[-1]), 1), dtype=torch.float32, device=dev)
+    L.check(lib.mi_build_laplacian(ctx.h, blocks.ref, _np_ptr(prim_off, C.c_int64), _dptr(prims),
+                                   arity, _np_ptr(nnz_off, C.c_int64),
+                                   _np_ptr(edge_off, C.c_int64), mode, _dptr(coords),
+                                   _dptr(user_w), _dptr(row_ptr), _dptr(col), _dptr(val),
+                                   _dptr(edges), _dptr(edge_w), _dptr(ws), ws.numel(), _stream()))
+    return Laplacian(row_ptr, col, val, edges, edge_w, nnz_off, edge_off, mode)
+
+
+def laplacian_values(ctx: Context, blocks: Blocks, lap: Laplacian, coords=None, mode=None,
+                     user_w=None, err_flag=None):
+    """Recompute lap.val / lap.edge_w in place on the existing structure."""
+    mode = lap.mode if mode is None else mode
+    L.check(L.lib().mi_laplacian_values(
+        ctx.h, blocks.ref, _np_ptr(lap.nnz_off, C.c_int64), _np_ptr(lap.edge_off, C.c_int64), mode,
+        _dptr(coords), _dptr(user_w), _dptr(lap.row_ptr), _dptr(lap.col), _dptr(lap.edges),
+        _dptr(lap.val), _dptr(lap.edge_w), _dptr(err_flag), _stream()))
+    lap.mode = mode
+    return lap
+
+
+@dataclass
+class OiParams:
+    """Mirror of mi_oi_params (see include/mispectral.h)."""
+    precision: int = MI_FP32
+    warm: int = MI_WARM_PRED
+    T: int = 3
+    m: int = 10
+    passes: int = 2
+    T0: int = 8
+    m0: int = 8
+    passes0: int = 1
+    adapt: int = 1
+    max_sweeps: int = 12
+    a_mode: int = MI_A_WEYL
+    a_value: float = 1.0
+    b_abs: float = 0.0
+    jacobi_tol: float = 1e-14
+
+    def struct(self):
+        return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
+                            self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, 0,
+                            self.a_value, self.b_abs, self.jacobi_tol)
+
+
+def _dtype(precision):
+    return torch.float64 if precision == MI_FP64 else torch.float32
+
+
+def oi_track(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, V0=None, V=None,
+             ritz=None, status=None, per_block: bool = False):
+    """Tracked subspaces of every block (mi_oi_track / mi_oi_track_per_block).
+    Returns (V, ritz, status)."""
+    lib = L.lib()
+    prm = params.struct()
+    dev = f"cuda:{ctx.device}"
+    dt = _dtype(params.precision)
+    if V is None:
+        V = torch.empty(int(blocks.u_off[-1]), dtype=dt, device=dev)
+    if ritz is None:
+        ritz = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+    ws_n = C.c_size_t()
+    L.check(lib.mi_oi_workspace_size(ctx.h, blocks.ref, C.byref(prm), C.byref(ws_n)))
+    ws = ctx.workspace("oi", ws_n.value)
+    fn = lib.mi_oi_track_per_block if per_block else lib.mi_oi_track
+    L.check(fn(ctx.h, blocks.ref, C.byref(prm), _dptr(lap.row_ptr), _dptr(lap.col), _dptr(lap.val),
+               _np_ptr(lap.nnz_off, C.c_int64), _dptr(V0), _dptr(V), _dptr(ritz), _dptr(status),
+               _dptr(ws), ws.numel(), _stream()))
+    return V, ritz, status
+
+
+def project(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, X: torch.Tensor,
+            precision: int = MI_FP32, E: torch.Tensor | None = None) -> torch.Tensor:
+    """E = U_c^T X per block (rows k >= c_b zero)."""
+    if E is None:
+        E = torch.empty(int(blocks.t_off[-1]) * 3, dtype=_dtype(precision), device=U.device)
+    L.check(L.lib().mi_project(ctx.h, blocks.ref, precision, _dptr(c), _dptr(U), _dptr(X), _dptr(E),
+                               None, 0, _stream()))
+    return E
+
+
+def reconstruct(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, E: torch.Tensor,
+                precision: int = MI_FP32, Xr: torch.Tensor | None = None) -> torch.Tensor:
+    """X~ = U_c E per block."""
+    if Xr is None:
+        Xr = torch.empty(int(blocks.v_off[-1]) * 3, dtype=_dtype(precision), device=U.device)
+    L.check(L.lib().mi_reconstruct(ctx.h, blocks.ref, precision, _dptr(c), _dptr(U), _dptr(E),
+                                   _dptr(Xr), _stream()))
+    return Xr
+
+
+def choose_c(ctx: Context, blocks: Blocks, c_max: torch.Tensor, target: float, g_min: float,
+             U: torch.Tensor, ritz: torch.Tensor, X: torch.Tensor, gl: Laplacian):
+    """Per-block c for an NMSVE target (gl: the MI_W_INV_DIST Laplacian of the
+    original mesh).  Returns (c, metric curve)."""
+    lib = L.lib()
+    ws_n = C.c_size_t()
+    L.check(lib.mi_choose_c_workspace_size(ctx.h, blocks.ref, C.byref(ws_n)))
+    ws = ctx.workspace("cc", ws_n.value)
+    c_out = torch.empty(blocks.n_blocks, dtype=torch.int32, device=U.device)
+    metric = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=U.device)
+    L.check(lib.mi_choose_c(ctx.h, blocks.ref, _dptr(c_max), float(target), float(g_min), _dptr(U),
+                            _dptr(ritz), _dptr(X), _dptr(gl.row_ptr), _dptr(gl.col), _dptr(gl.val),
+                            _np_ptr(gl.nnz_off, C.c_int64), _dptr(c_out), _dptr(metric), _dptr(ws),
+                            ws.numel(), _stream()))
+    return c_out, metric

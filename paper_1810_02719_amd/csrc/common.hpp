@@ -1,0 +1,89 @@
+// Internal helpers shared by the library's translation units: status and
+// error reporting, the device-side block descriptor, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mispectral.h"
+
+namespace mis {
+
+// Thread-local message of the last error (mi_last_error).
+void set_error(const char* fmt, ...);
+void clear_error();
+
+// Entry of a call that enqueues GPU work: clears the thread's message and any
+// stale HIP error left by earlier, unrelated calls.
+inline void begin_call() {
+  clear_error();
+  (void)hipGetLastError();
+}
+
+#define MI_TRY_HIP(expr)                                                              \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      ::mis::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                       __LINE__);                                                     \
+      return MI_ERR_HIP;                                                              \
+    }                                                                                 \
+  } while (0)
+
+#define MI_CHECK_ARG(cond, ...)      \
+  do {                               \
+    if (!(cond)) {                   \
+      ::mis::set_error(__VA_ARGS__); \
+      return MI_ERR_ARG;             \
+    }                                \
+  } while (0)
+
+// Device view of one block.
+struct BlockDev {
+  int64_t v_off;   // first vertex row
+  int64_t u_off;   // first element of the slab
+  int64_t nnz_off; // first CSR entry
+  int64_t t_off;   // offset of per-block p-vectors (ritz values): sum of p
+  int64_t m_off;   // offset of per-block ld x ld matrices: sum of ld*ld
+  int32_t n;       // vertices
+  int32_t p;       // tracked width
+  int32_t ld;      // slab row stride
+  int32_t id;      // block index in the caller's table
+};
+
+// Host-side validated copy of an mi_blocks table.
+struct HostBlocks {
+  int32_t B = 0;
+  std::vector<int64_t> v_off, u_off;
+  std::vector<int32_t> p, ld, pred;
+  std::vector<int64_t> t_off, m_off;  // derived
+};
+
+mi_status load_blocks(const mi_blocks* blk, HostBlocks* hb, bool need_slab);
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Round-robin (circle method) pairing used by the parallel Jacobi sweeps:
+// in round r of a sweep over q (even) indices, slot k pairs the indices at
+// positions k and q-1-k of the arrangement where position 0 is fixed and the
+// others rotate by r.
+__host__ __device__ inline int rr_index(int pos, int r, int q) {
+  if (pos == 0) return 0;
+  return 1 + ((pos - 1 + r) % (q - 1));
+}
+
+}  // namespace mis
+
+// Context (opaque in the C ABI).
+struct mi_ctx {
+  int device = 0;
+  // cached plan + captured graph for mi_oi_track (see oi.hip)
+  void* oi_plan = nullptr;
+  void* enc_plan = nullptr;
+  void* cc_plan = nullptr;
+};

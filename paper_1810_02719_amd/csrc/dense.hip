@@ -1,0 +1,360 @@
+// Tall-skinny kernels (see dense.hpp).
+#include "dense.hpp"
+
+namespace mis {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct VecOf;
+template <>
+struct VecOf<float> {
+  typedef f4v type;
+  static constexpr int W = 4;
+};
+template <>
+struct VecOf<double> {
+  typedef d2v type;
+  static constexpr int W = 2;
+};
+
+// ------------------------------------------------------------------ SpMM
+// Yout = alpha * (L Yin) + beta * Yin + gamma * Yprev for the rows of one
+// tile; (alpha, beta, gamma) per block and step.  Threads of a row cover its
+// ld coefficients with 16-byte vectors, so every neighbour row is gathered
+// with fully coalesced loads.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_spmm(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+           const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+           const int32_t* __restrict__ col, const float* __restrict__ val,
+           const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+           const double* __restrict__ coef, int coef_stride, int step) {
+  typedef typename VecOf<T>::type V;
+  constexpr int W = VecOf<T>::W;
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const CsrDesc c = csr[t.set];
+  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+  const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
+  const int nvec = d.ld / W;
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  const T* yb = Yin + d.off;
+  for (int idx = threadIdx.x; idx < rows * nvec; idx += 256) {
+    const int r = t.row0 + idx / nvec;
+    const int v = idx - (idx / nvec) * nvec;
+    const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
+    V acc = (V)(T)0;
+    for (int k = k0; k < k1; ++k) {
+      const int j = col[c.nnz_off + k];
+      const T w = (T)val[c.nnz_off + k];
+      const V y = *reinterpret_cast<const V*>(yb + int64_t(j) * d.ld + v * W);
+      acc += w * y;
+    }
+    const int64_t o = d.off + int64_t(r) * d.ld + v * W;
+    V out = alpha * acc + beta * *reinterpret_cast<const V*>(Yin + o);
+    if (Yprev) out += gamma * *reinterpret_cast<const V*>(Yprev + o);
+    *reinterpret_cast<V*>(Yout + o) = out;
+  }
+}
+
+template <typename T>
+void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
+                 const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
+                 const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
+                 hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_spmm<T>, dim3(ntiles), dim3(256), 0, s, tiles, sets, csr, row_ptr, col, val,
+                     Yin, Yprev, Yout, coef, coef_stride, step);
+}
+
+template void launch_spmm<float>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
+                                 const int32_t*, const int32_t*, const float*, const float*,
+                                 const float*, float*, const double*, int, int, hipStream_t);
+template void launch_spmm<double>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
+                                  const int32_t*, const int32_t*, const float*, const double*,
+                                  const double*, double*, const double*, int, int, hipStream_t);
+
+// ------------------------------------------------------------------ Gram
+// One workgroup: a 64 x 64 super-tile of A^T B (and A^T W when DUAL) over a
+// row range.  Four waves, each a 32 x 32 quadrant as 2 x 2 tiles of the
+// 16x16x4 FP64 MFMA.  Operands are promoted to FP64 exactly, so every
+// product is exact and only the FP64 accumulation rounds.
+// MFMA operand layout (16x16x4): lane l supplies A(m = l%16, k = l/16) and
+// B(k = l/16, n = l%16).  Result element (m, n = l%16) sits in register q of
+// lane l with m = l/16 + 4q for the FP64 instruction and m = 4(l/16) + q for
+// the FP32 one (measured lane layouts).
+template <typename T, bool DUAL>
+__global__ void __launch_bounds__(256)
+    k_gram(const GramTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+           const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ Wm,
+           double* __restrict__ part) {
+  const GramTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int kk = lane >> 4, mm = lane & 15;
+  const int ci0 = t.I0 + wi * 32 + mm, ci1 = ci0 + 16;
+  const int cj0 = t.J0 + wj * 32 + mm, cj1 = cj0 + 16;
+  const bool vi0 = ci0 < d.ld, vi1 = ci1 < d.ld, vj0 = cj0 < d.ld, vj1 = cj1 < d.ld;
+  d4v acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  d4v w00 = acc00, w01 = acc00, w10 = acc00, w11 = acc00;
+  const T* Ab = A + d.off;
+  const T* Bb = B + d.off;
+  const T* Wb = DUAL ? Wm + d.off : nullptr;
+  for (int r = t.r0; r < t.r1; r += 4) {
+    const int row = r + kk;
+    const bool vr = row < t.r1;
+    const int64_t ro = int64_t(row) * d.ld;
+    const double a0 = (vr && vi0) ? (double)Ab[ro + ci0] : 0.0;
+    const double a1 = (vr && vi1) ? (double)Ab[ro + ci1] : 0.0;
+    const double b0 = (vr && vj0) ? (double)Bb[ro + cj0] : 0.0;
+    const double b1 = (vr && vj1) ? (double)Bb[ro + cj1] : 0.0;
+    acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+    acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+    acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+    acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    if (DUAL) {
+      const double x0 = (vr && vj0) ? (double)Wb[ro + cj0] : 0.0;
+      const double x1 = (vr && vj1) ? (double)Wb[ro + cj1] : 0.0;
+      w00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, w00, 0, 0, 0);
+      w01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, w01, 0, 0, 0);
+      w10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0, w10, 0, 0, 0);
+      w11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, w11, 0, 0, 0);
+    }
+  }
+  double* out = part + int64_t(blockIdx.x) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
+  const int n = mm;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = kk + 4 * q;  // FP64 result layout
+    const int i0 = wi * 32 + m, i1 = i0 + 16;
+    const int j0 = wj * 32 + n, j1 = j0 + 16;
+    out[i0 * GRAM_TILE + j0] = acc00[q];
+    out[i0 * GRAM_TILE + j1] = acc01[q];
+    out[i1 * GRAM_TILE + j0] = acc10[q];
+    out[i1 * GRAM_TILE + j1] = acc11[q];
+    if (DUAL) {
+      double* o2 = out + GRAM_TILE * GRAM_TILE;
+      o2[i0 * GRAM_TILE + j0] = w00[q];
+      o2[i0 * GRAM_TILE + j1] = w01[q];
+      o2[i1 * GRAM_TILE + j0] = w10[q];
+      o2[i1 * GRAM_TILE + j1] = w11[q];
+    }
+  }
+}
+
+template <typename T>
+void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T* A, const T* B,
+                 const T* W, double* part, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (W)
+    hipLaunchKernelGGL((k_gram<T, true>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W, part);
+  else
+    hipLaunchKernelGGL((k_gram<T, false>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W,
+                       part);
+}
+template void launch_gram<float>(const GramTile*, int, const MatDesc*, const float*, const float*,
+                                 const float*, double*, hipStream_t);
+template void launch_gram<double>(const GramTile*, int, const MatDesc*, const double*,
+                                  const double*, const double*, double*, hipStream_t);
+
+// Sum the split-K partials of one super-tile in chunk order (deterministic)
+// and write the upper triangle and its mirror.
+__global__ void __launch_bounds__(256)
+    k_gram_reduce(const GramReduce* __restrict__ jobs, const MatDesc* __restrict__ outsets,
+                  const double* __restrict__ part, int dual, double* __restrict__ G,
+                  double* __restrict__ H) {
+  const GramReduce j = jobs[blockIdx.x];
+  const MatDesc o = outsets[j.set];
+  const int64_t stride = int64_t(dual ? 2 : 1) * GRAM_TILE * GRAM_TILE;
+  for (int e = threadIdx.x; e < GRAM_TILE * GRAM_TILE; e += 256) {
+    const int il = e / GRAM_TILE, jl = e % GRAM_TILE;
+    const int gi = j.I0 + il, gj = j.J0 + jl;
+    if (gi >= o.ld || gj >= o.ld || gi > gj) continue;
+    double sg = 0.0, sh = 0.0;
+    for (int c = 0; c < j.count; ++c) {
+      const double* pp = part + int64_t(j.first + c) * stride;
+      sg += pp[e];
+      if (dual) sh += pp[GRAM_TILE * GRAM_TILE + e];
+    }
+    G[o.off + int64_t(gi) * o.ld + gj] = sg;
+    G[o.off + int64_t(gj) * o.ld + gi] = sg;
+    if (dual) {
+      H[o.off + int64_t(gi) * o.ld + gj] = sh;
+      H[o.off + int64_t(gj) * o.ld + gi] = sh;
+    }
+  }
+}
+
+void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outsets,
+                        const double* part, bool dual, double* G, double* H, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(njobs), dim3(256), 0, s, jobs, outsets, part, dual ? 1 : 0,
+                     G, H);
+}
+
+// ------------------------------------------------------------------ A * S
+// Out rows [row0, row0+64) x columns [n0, n0+NCH) = A rows x S.  A's row tile
+// is staged through LDS in K-chunks (coalesced 128-byte rows), S fragments
+// come from L2 (S is shared by all row tiles of a block).  Each wave owns 16
+// rows and NCH/16 MFMA tiles.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f4v acc_t;
+  __device__ static acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+template <>
+struct Mfma<double> {
+  typedef d4v acc_t;
+  __device__ static acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+
+template <typename T, typename TO, int NCH>
+__global__ void __launch_bounds__(256)
+    k_rowmul(const RowTile* __restrict__ tiles, const MatDesc* __restrict__ asets,
+             const T* __restrict__ A, const MatDesc* __restrict__ ssets, const T* __restrict__ S,
+             const MatDesc* __restrict__ osets, TO* __restrict__ Out) {
+  constexpr int KC = 32;
+  constexpr int NT = NCH / 16;
+  __shared__ T As[ROW_TILE][KC + 1];
+  typedef typename Mfma<T>::acc_t acc_t;
+  const RowTile t = tiles[blockIdx.x];
+  const MatDesc da = asets[t.set], ds = ssets[t.set], dout = osets[t.set];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int K = ds.rows;
+  acc_t acc[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) acc[i] = (acc_t)(T)0;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = threadIdx.x; e < ROW_TILE * KC; e += 256) {
+      const int rr = e / KC, kc = e % KC;
+      const int row = t.row0 + rr;
+      As[rr][kc] = (row < da.rows && k0 + kc < K) ? A[da.off + int64_t(row) * da.ld + k0 + kc]
+                                                  : (T)0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < KC; ks += 4) {
+      const int k = k0 + ks + (lane >> 4);
+      const T a = As[wave * 16 + (lane & 15)][ks + (lane >> 4)];
+      const bool vk = k < K;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = t.n0 + nt * 16 + (lane & 15);
+        const T b = (vk && n < ds.ld) ? S[ds.off + int64_t(k) * ds.ld + n] : (T)0;
+        acc[nt] = Mfma<T>::op(a, b, acc[nt]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int n = t.n0 + nt * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = t.row0 + wave * 16 + Mfma<T>::row(lane, q);
+      if (row < dout.rows && n < dout.ld) Out[dout.off + int64_t(row) * dout.ld + n] = (TO)acc[nt][q];
+    }
+  }
+}
+
+template <typename T, typename TO>
+void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const T* A,
+                   const MatDesc* ssets, const T* S, const MatDesc* osets, TO* Out, int nch,
+                   hipStream_t s) {
+  if (ntiles <= 0) return;
+  switch (nch) {
+#define MI_ROWMUL_CASE(N)                                                                       \
+  case N:                                                                                       \
+    hipLaunchKernelGGL((k_rowmul<T, TO, N>), dim3(ntiles), dim3(256), 0, s, tiles, asets, A,   \
+                       ssets, S, osets, Out);                                                   \
+    break;
+    MI_ROWMUL_CASE(32)
+    MI_ROWMUL_CASE(64)
+    MI_ROWMUL_CASE(96)
+    MI_ROWMUL_CASE(128)
+    MI_ROWMUL_CASE(192)
+    MI_ROWMUL_CASE(256)
+#undef MI_ROWMUL_CASE
+    default:
+      break;  // the tile planner only produces the widths above
+  }
+}
+
+template void launch_rowmul<float, float>(const RowTile*, int, const MatDesc*, const float*,
+                                          const MatDesc*, const float*, const MatDesc*, float*, int,
+                                          hipStream_t);
+template void launch_rowmul<double, double>(const RowTile*, int, const MatDesc*, const double*,
+                                            const MatDesc*, const double*, const MatDesc*, double*,
+                                            int, hipStream_t);
+template void launch_rowmul<double, float>(const RowTile*, int, const MatDesc*, const double*,
+                                           const MatDesc*, const double*, const MatDesc*, float*,
+                                           int, hipStream_t);
+
+// ------------------------------------------------------------------ tile tables
+
+int gram_chunks(int nsets, int npairs, int rows) {
+  const int target = 2048;
+  int ch = ceil_div(target, std::max(1, nsets * npairs));
+  ch = std::min(ch, std::max(1, rows / 64));
+  return std::max(ch, 1);
+}
+
+// Gram tile table for a list of per-block matrices with `rows` rows each.
+void gram_tables(const std::vector<MatDesc>& sets, bool split,
+                        std::vector<GramTile>* tiles, std::vector<GramReduce>* red) {
+  for (int si = 0; si < (int)sets.size(); ++si) {
+    const MatDesc& d = sets[si];
+    const int nsup = ceil_div(d.ld, GRAM_TILE);
+    const int npairs = nsup * (nsup + 1) / 2;
+    const int ch = split ? gram_chunks((int)sets.size(), npairs, d.rows) : 1;
+    int rows_per = ceil_div(d.rows, ch);
+    rows_per = ((rows_per + 15) / 16) * 16;
+    for (int I = 0; I < nsup; ++I)
+      for (int J = I; J < nsup; ++J) {
+        GramReduce g;
+        g.set = si;
+        g.I0 = I * GRAM_TILE;
+        g.J0 = J * GRAM_TILE;
+        g.first = (int)tiles->size();
+        g.count = 0;
+        for (int r0 = 0; r0 < d.rows; r0 += rows_per) {
+          GramTile t;
+          t.set = si;
+          t.I0 = g.I0;
+          t.J0 = g.J0;
+          t.r0 = r0;
+          t.r1 = std::min(d.rows, r0 + rows_per);
+          tiles->push_back(t);
+          ++g.count;
+        }
+        red->push_back(g);
+      }
+  }
+}
+
+void row_tables(const std::vector<MatDesc>& sets, int nch, std::vector<RowTile>* tiles) {
+  for (int si = 0; si < (int)sets.size(); ++si) {
+    const MatDesc& d = sets[si];
+    for (int r0 = 0; r0 < d.rows; r0 += ROW_TILE)
+      for (int n0 = 0; n0 < d.ld; n0 += nch) tiles->push_back(RowTile{si, r0, n0});
+  }
+}
+
+void spmm_tables(const std::vector<MatDesc>& sets, std::vector<SpmmTile>* tiles) {
+  for (int si = 0; si < (int)sets.size(); ++si)
+    for (int r0 = 0; r0 < sets[si].rows; r0 += SPMM_ROWS) tiles->push_back(SpmmTile{si, r0});
+}
+
+}  // namespace mis

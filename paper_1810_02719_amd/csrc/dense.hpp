@@ -1,0 +1,89 @@
+// Tall-skinny kernels shared by the tracking and the encoder: CSR SpMM with
+// the three-term update of the Chebyshev recurrence, Gram products A^T B
+// with FP64 MFMA and a deterministic split-K reduction, and row-block
+// products A S on MFMA.
+#pragma once
+
+#include "common.hpp"
+#include "kernels_util.hpp"
+
+namespace mis {
+
+// A set of per-block matrices: block k of the set is a rows x ld row-major
+// matrix at element offset off (ld = row stride; only the first `cols`
+// columns are meaningful, the rest are zero padding).
+struct MatDesc {
+  int64_t off;
+  int32_t rows;
+  int32_t ld;
+  int32_t cols;
+  int32_t blk;  // index into per-block parameter arrays (coefficients, flags)
+};
+
+// SpMM / Chebyshev tiles: rows [row0, row0 + SPMM_ROWS) of block `set`.
+struct SpmmTile {
+  int32_t set;
+  int32_t row0;
+};
+constexpr int SPMM_ROWS = 16;
+
+// CSR location of a block: row_ptr at rp_off, col/val at nnz_off.
+struct CsrDesc {
+  int64_t rp_off;
+  int64_t nnz_off;
+};
+
+// Gram tiles: a 64 x 64 output super-tile (I0, J0) of block `set`, summed
+// over the rows [r0, r1).  Output goes to part + tile_index * 64 * 64 (and a
+// second plane for the dual product).
+struct GramTile {
+  int32_t set;
+  int32_t I0, J0;
+  int32_t r0, r1;
+};
+constexpr int GRAM_TILE = 64;
+
+// Reduce jobs: block `set`, super-tile (I0, J0), partial tiles
+// [first, first + count) in chunk order.
+struct GramReduce {
+  int32_t set;
+  int32_t I0, J0;
+  int32_t first, count;
+};
+
+// Row-product tiles: rows [row0, row0 + 64) x output columns [n0, n0 + NCH).
+struct RowTile {
+  int32_t set;
+  int32_t row0;
+  int32_t n0;
+};
+constexpr int ROW_TILE = 64;
+
+template <typename T>
+void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
+                 const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
+                 const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
+                 hipStream_t s);
+
+template <typename T>
+void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T* A, const T* B,
+                 const T* W, double* part, hipStream_t s);
+
+void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outsets,
+                        const double* part, bool dual, double* G, double* H, hipStream_t s);
+
+template <typename T, typename TO>
+void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const T* A,
+                   const MatDesc* ssets, const T* S, const MatDesc* osets, TO* Out, int nch,
+                   hipStream_t s);
+
+// Tile tables (host).  Gram: 64 x 64 super-tiles of the upper triangle,
+// split over row chunks when `split` (about 2048 workgroups in total);
+// rows: 64-row x nch-column tiles; SpMM: SPMM_ROWS-row tiles.
+int gram_chunks(int nsets, int npairs, int rows);
+void gram_tables(const std::vector<MatDesc>& sets, bool split, std::vector<GramTile>* tiles,
+                 std::vector<GramReduce>* red);
+void row_tables(const std::vector<MatDesc>& sets, int nch, std::vector<RowTile>* tiles);
+void spmm_tables(const std::vector<MatDesc>& sets, std::vector<SpmmTile>* tiles);
+
+}  // namespace mis

@@ -1,0 +1,47 @@
+// Small device/host utilities shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+namespace mis {
+
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_TILE = 256 * SCAN_PER_THREAD;
+
+size_t scan_scratch_bytes(int64_t N);
+void exclusive_scan(const int32_t* in, int64_t* out, int64_t N, int64_t* scratch, hipStream_t s);
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+// Largest b with off[b] <= x (off ascending, off[0] = 0, x < off[B]).
+__device__ inline int find_block(const int64_t* __restrict__ off, int B, int64_t x) {
+  int lo = 0, hi = B;  // invariant: off[lo] <= x < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller-provided workspace.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = used;
+    used = align_up(used + count * sizeof(T));
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+}  // namespace mis

@@ -1,0 +1,778 @@
+// Eigenspace tracking by orthogonal iteration (Section 4, Algorithm 1):
+// host runtime that plans the waves, lays out the workspace, and enqueues
+// (or captures into a HIP graph and replays) the kernel sequence.
+//
+// One iteration of a block, with Y the current basis (n_b x p_b, row-major):
+//   filter pass (x passes):  Y <- T_m(t(L)) Y / T_m(t(0))       m SpMM steps
+//     (between passes) Cholesky-QR: G = Y^T Y, Y <- Y R^-1       keeps Y well conditioned
+//   Rayleigh-Ritz:           W = L Y;  G = Y^T Y, H = Y^T W        one dual Gram pass
+//                            R^T R = G,  A = R^-T H R^-1,  A = Z Theta Z^T (Jacobi)
+//                            V <- Y R^-1 Z   (columns ordered by Ritz value)
+// and a final Cholesky-QR pass after the last iteration.  t(x) maps the
+// damped interval [a, b] to [-1, 1]; b bounds the spectrum (Gershgorin), a
+// tracks the largest Ritz value (the top of the tracked window).
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "small.hpp"
+
+namespace mis {
+
+// ------------------------------------------------------------------ per-block scalar kernels
+
+struct BlkInfo {
+  int64_t t_off;
+  int32_t n, p, pred, pad;
+};
+
+// b_hi[blk] = max_i sum_j |L_ij| (Gershgorin bound on lambda_max), one
+// workgroup per block, deterministic.
+__global__ void __launch_bounds__(256)
+    k_gershgorin(const MatDesc* __restrict__ sets, const CsrDesc* __restrict__ csr,
+                 const int32_t* __restrict__ row_ptr, const float* __restrict__ val,
+                 double* __restrict__ b_hi) {
+  __shared__ double red[4];
+  const MatDesc d = sets[blockIdx.x];
+  const CsrDesc c = csr[blockIdx.x];
+  double mx = 0.0;
+  for (int r = threadIdx.x; r < d.rows; r += 256) {
+    double s = 0.0;
+    for (int k = row_ptr[c.rp_off + r]; k < row_ptr[c.rp_off + r + 1]; ++k)
+      s += fabs((double)val[c.nnz_off + k]);
+    mx = fmax(mx, s);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) b_hi[d.blk] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void k_set_b(const MatDesc* __restrict__ sets, int nsets, double v, double* b_hi) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsets) b_hi[sets[i].blk] = v;
+}
+
+// Initial lower filter bound a of each block of a wave.
+__global__ void k_init_a(const MatDesc* __restrict__ sets, int nsets,
+                         const BlkInfo* __restrict__ info, int from_pred, int a_mode,
+                         double a_value, const double* __restrict__ ritz_in,
+                         double* __restrict__ a_lo, const double* __restrict__ b_hi) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsets) return;
+  const int b = sets[i].blk;
+  const BlkInfo bi = info[b];
+  double a;
+  if (from_pred && bi.pred >= 0) {
+    const BlkInfo pi = info[bi.pred];
+    a = a_lo[bi.pred] * (double)pi.n / (double)bi.n;
+  } else if (a_mode == MI_A_ABS) {
+    a = a_value;
+  } else if (a_mode == MI_A_RITZ) {
+    a = ritz_in[bi.t_off + bi.p - 1];
+  } else {
+    a = a_value * b_hi[b] * (double)bi.p / (double)bi.n;
+  }
+  a_lo[b] = a;
+}
+
+// Chebyshev coefficients of the scaled three-term recurrence (filter on
+// [a, b], normalised at the bottom of the spectrum lambda = 0):
+//   Y_1 = (s_1/e)(L - c0) Y_0,  Y_{k+1} = (2 s_{k+1}/e)(L - c0) Y_k - s_k s_{k+1} Y_{k-1}
+//   e = (b-a)/2, c0 = (b+a)/2, s_1 = e/(0 - c0), s_{k+1} = 1/(2/s_1 - s_k).
+// Stored as (alpha, beta, gamma) with Y_new = alpha L Y + beta Y + gamma Y_prev;
+// slot m holds (1, 0, 0) for the plain product W = L Y.
+__global__ void k_cheb_coef(const MatDesc* __restrict__ sets, int nsets,
+                            const double* __restrict__ a_lo, const double* __restrict__ b_hi,
+                            double* __restrict__ coef, int stride, int m) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsets) return;
+  const int b = sets[i].blk;
+  const double bb = b_hi[b];
+  double a = a_lo[b];
+  a = fmin(fmax(a, 1e-3 * bb), 0.95 * bb);
+  const double e = 0.5 * (bb - a), c0 = 0.5 * (bb + a);
+  const double s1 = e / (0.0 - c0);
+  double* cf = coef + int64_t(b) * stride;
+  double s = s1;
+  cf[0] = s1 / e;
+  cf[1] = -c0 * s1 / e;
+  cf[2] = 0.0;
+  for (int k = 1; k < m; ++k) {
+    const double sn = 1.0 / (2.0 / s1 - s);
+    const double al = 2.0 * sn / e;
+    cf[3 * k] = al;
+    cf[3 * k + 1] = -c0 * al;
+    cf[3 * k + 2] = -s * sn;
+    s = sn;
+  }
+  cf[3 * m] = 1.0;
+  cf[3 * m + 1] = 0.0;
+  cf[3 * m + 2] = 0.0;
+}
+
+// Warm start: block b's start is its predecessor's final basis, rows and
+// columns index-aligned; rows past the predecessor's size are zero, columns
+// past its width get the unit vector e_{(997 j) mod n_b}.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_warm_copy(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const MatDesc* __restrict__ psets, T* __restrict__ V) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set], pd = psets[t.set];
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
+    const int r = t.row0 + e / d.ld, j = e % d.ld;
+    T v = (T)0;
+    if (j < d.cols) {
+      if (j < pd.cols) {
+        if (r < pd.rows) v = V[pd.off + int64_t(r) * pd.ld + j];
+      } else if (r == int((997LL * j) % d.rows)) {
+        v = (T)1;
+      }
+    }
+    V[d.off + int64_t(r) * d.ld + j] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_copy_slab(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const T* __restrict__ src, T* __restrict__ dst) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
+    const int64_t o = d.off + int64_t(t.row0) * d.ld + e;
+    dst[o] = src[o];
+  }
+}
+
+// ------------------------------------------------------------------ plan
+
+struct WaveTables {
+  int nb = 0;
+  int T = 0, m = 0, passes = 0;
+  bool from_pred = false;
+  int max_ld = 0, max_q = 0;
+  int nch = 64, nchs = 64;
+  // device tables
+  MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
+  CsrDesc* csr = nullptr;
+  SmallDesc* sd = nullptr;
+  SpmmTile* spmm = nullptr;
+  int n_spmm = 0;
+  GramTile* gt = nullptr;
+  int n_gt = 0;
+  GramReduce* gr = nullptr;
+  int n_gr = 0;
+  GramTile* gts = nullptr;
+  int n_gts = 0;
+  GramReduce* grs = nullptr;
+  int n_grs = 0;
+  RowTile* rt = nullptr;
+  int n_rt = 0;
+  RowTile* rts = nullptr;
+  int n_rts = 0;
+};
+
+struct WsLayout {
+  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, pk, log, perm, part, a_lo, b_hi, coef, conv;
+  size_t total;
+  int coef_stride;
+};
+
+struct OiPlan {
+  // key
+  HostBlocks hb;
+  std::vector<int64_t> nnz_off;
+  mi_oi_params prm;
+  std::vector<const void*> ptrs;
+  size_t ws_bytes = 0;
+  bool per_block = false;
+  // content
+  std::vector<WaveTables> waves;
+  WsLayout L;
+  void* arena = nullptr;
+  BlkInfo* info = nullptr;
+  MatDesc* all_tall = nullptr;
+  CsrDesc* all_csr = nullptr;
+  int lds_max = 65536;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  ~OiPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (arena) (void)hipFree(arena);
+  }
+};
+
+static int q_of(int p) { return (p + 1) & ~1; }
+
+// Waves: blocks whose predecessor finished in an earlier wave.  Under
+// MI_WARM_GIVEN (or without predecessors) all blocks form one wave.  The
+// per-block reference path makes every block its own wave, in wave order.
+static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool per_block,
+                             std::vector<std::vector<int>>* waves, std::vector<int>* level) {
+  const int B = hb.B;
+  level->assign(B, 0);
+  if (prm.warm == MI_WARM_PRED) {
+    for (int b = 0; b < B; ++b) {
+      int l = 0, x = b;
+      while (hb.pred[x] >= 0) {
+        x = hb.pred[x];
+        if (++l > B) {
+          set_error("predecessor chain of block %d has a cycle", b);
+          return MI_ERR_ARG;
+        }
+      }
+      (*level)[b] = l;
+    }
+  }
+  int maxl = 0;
+  for (int b = 0; b < B; ++b) maxl = std::max(maxl, (*level)[b]);
+  waves->clear();
+  for (int l = 0; l <= maxl; ++l) {
+    std::vector<int> w;
+    for (int b = 0; b < B; ++b)
+      if ((*level)[b] == l) w.push_back(b);
+    if (w.empty()) continue;
+    if (per_block)
+      for (int b : w) waves->push_back({b});
+    else
+      waves->push_back(w);
+  }
+  return MI_OK;
+}
+
+// Output-column width of a row-product tile: the widest supported width that
+// divides ld (all blocks of the wave alike), else 64 (masked tail).  Must be
+// one of the widths launch_rowmul instantiates.
+static int pick_nch(const std::vector<int>& lds_in_wave, bool dbl) {
+  int mx = 0;
+  bool same = true;
+  for (int v : lds_in_wave) {
+    same = same && v == lds_in_wave[0];
+    mx = std::max(mx, v);
+  }
+  const int cap = dbl ? 128 : 256;
+  if (same) {
+    for (int c : {256, 192, 128, 96, 64, 32})
+      if (c <= cap && mx % c == 0) return c;
+  }
+  return 64;
+}
+
+static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t part_doubles) {
+  const size_t es = prm.precision == MI_FP64 ? 8 : 4;
+  int64_t slab = hb.u_off[hb.B];
+  int64_t mats = hb.m_off[hb.B];
+  int64_t pk = 0, lg = 0, tp = hb.t_off[hb.B];
+  for (int b = 0; b < hb.B; ++b) {
+    const int64_t q = q_of(hb.p[b]);
+    pk += q * (q + 1) / 2;
+    lg += (q - 1) * (q / 2) * 2;
+  }
+  const int mmax = std::max(prm.m, prm.m0);
+  WsLayout L;
+  Carver c(nullptr);
+  for (int i = 0; i < 4; ++i) L.slab[i] = c.used, c.take<char>(size_t(slab) * es);
+  L.G = c.used, c.take<double>(mats);
+  L.H = c.used, c.take<double>(mats);
+  L.Rinv = c.used, c.take<double>(mats);
+  L.T1 = c.used, c.take<double>(mats);
+  L.A = c.used, c.take<double>(mats);
+  L.Z = c.used, c.take<double>(mats);
+  L.S64 = c.used, c.take<double>(mats);
+  L.S32 = c.used, c.take<float>(mats);
+  L.pk = c.used, c.take<double>(pk);
+  L.log = c.used, c.take<double>(lg);
+  L.perm = c.used, c.take<int32_t>(tp);
+  L.part = c.used, c.take<double>(std::max<size_t>(part_doubles, 1));
+  L.a_lo = c.used, c.take<double>(hb.B);
+  L.b_hi = c.used, c.take<double>(hb.B);
+  L.coef_stride = 3 * (mmax + 1);
+  L.coef = c.used, c.take<double>(size_t(hb.B) * L.coef_stride);
+  L.conv = c.used, c.take<int32_t>(hb.B);
+  L.total = c.used;
+  return L;
+}
+
+// Host-side tables of one wave (device pointers filled in by upload()).
+struct WaveHost {
+  std::vector<MatDesc> tall, ptall, small;
+  std::vector<CsrDesc> csr;
+  std::vector<SmallDesc> sd;
+  std::vector<SpmmTile> spmm;
+  std::vector<GramTile> gt, gts;
+  std::vector<GramReduce> gr, grs;
+  std::vector<RowTile> rt, rts;
+};
+
+static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
+                      const std::vector<int>& blocks, const mi_oi_params& prm, WaveTables* wt,
+                      WaveHost* h, const std::vector<int64_t>& pk_off,
+                      const std::vector<int64_t>& log_off) {
+  const bool dbl = prm.precision == MI_FP64;
+  std::vector<int> lds_list;
+  for (int b : blocks) {
+    const int n = int(hb.v_off[b + 1] - hb.v_off[b]);
+    MatDesc d{hb.u_off[b], n, hb.ld[b], hb.p[b], b};
+    h->tall.push_back(d);
+    const int pb = hb.pred[b];
+    if (pb >= 0)
+      h->ptall.push_back(MatDesc{hb.u_off[pb], int(hb.v_off[pb + 1] - hb.v_off[pb]), hb.ld[pb],
+                                 hb.p[pb], pb});
+    else
+      h->ptall.push_back(d);
+    h->small.push_back(MatDesc{hb.m_off[b], hb.ld[b], hb.ld[b], hb.p[b], b});
+    h->csr.push_back(CsrDesc{hb.v_off[b] + b, nnz_off[b]});
+    SmallDesc s;
+    s.m_off = hb.m_off[b];
+    s.pk_off = pk_off[b];
+    s.log_off = log_off[b];
+    s.t_off = hb.t_off[b];
+    s.p = hb.p[b];
+    s.ld = hb.ld[b];
+    s.q = q_of(hb.p[b]);
+    s.blk = b;
+    h->sd.push_back(s);
+    lds_list.push_back(hb.ld[b]);
+    wt->max_ld = std::max(wt->max_ld, hb.ld[b]);
+    wt->max_q = std::max(wt->max_q, s.q);
+  }
+  wt->nb = (int)blocks.size();
+  wt->nch = pick_nch(lds_list, dbl);
+  wt->nchs = pick_nch(lds_list, true);
+  spmm_tables(h->tall, &h->spmm);
+  gram_tables(h->tall, true, &h->gt, &h->gr);
+  gram_tables(h->small, false, &h->gts, &h->grs);
+  row_tables(h->tall, wt->nch, &h->rt);
+  row_tables(h->small, wt->nchs, &h->rts);
+}
+
+template <typename X>
+static X* put(std::vector<char>& blob, const std::vector<X>& v, std::vector<size_t>* offs) {
+  size_t off = align_up(blob.size());
+  blob.resize(off + align_up(v.size() * sizeof(X)));
+  if (!v.empty()) memcpy(blob.data() + off, v.data(), v.size() * sizeof(X));
+  offs->push_back(off);
+  return reinterpret_cast<X*>(off);  // relocated after upload
+}
+
+static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
+                           const mi_oi_params& prm, bool per_block, int lds_max,
+                           std::unique_ptr<OiPlan>* out, size_t* ws_need) {
+  std::unique_ptr<OiPlan> P(new OiPlan());
+  P->hb = hb;
+  P->nnz_off = nnz_off;
+  P->prm = prm;
+  P->per_block = per_block;
+  P->lds_max = lds_max;
+  std::vector<std::vector<int>> waves;
+  std::vector<int> level;
+  mi_status st = build_waves(hb, prm, per_block, &waves, &level);
+  if (st) return st;
+  std::vector<int64_t> pk_off(hb.B), log_off(hb.B);
+  int64_t pk = 0, lg = 0;
+  for (int b = 0; b < hb.B; ++b) {
+    const int64_t q = q_of(hb.p[b]);
+    pk_off[b] = pk;
+    log_off[b] = lg;
+    pk += q * (q + 1) / 2;
+    lg += (q - 1) * (q / 2) * 2;
+  }
+  std::vector<char> blob;
+  std::vector<WaveHost> hosts(waves.size());
+  P->waves.resize(waves.size());
+  size_t part_max = 0;
+  for (size_t w = 0; w < waves.size(); ++w) {
+    WaveTables& wt = P->waves[w];
+    const bool warm_wave = prm.warm == MI_WARM_PRED && level[waves[w][0]] > 0;
+    wt.from_pred = warm_wave;
+    wt.T = warm_wave ? prm.T : prm.T0;
+    wt.m = warm_wave ? prm.m : prm.m0;
+    wt.passes = warm_wave ? prm.passes : prm.passes0;
+    wave_host(hb, nnz_off, waves[w], prm, &wt, &hosts[w], pk_off, log_off);
+    part_max = std::max(part_max, hosts[w].gt.size() * 2 * GRAM_TILE * GRAM_TILE);
+    part_max = std::max(part_max, hosts[w].gts.size() * 2 * GRAM_TILE * GRAM_TILE);
+  }
+  P->L = ws_layout(hb, prm, part_max);
+  *ws_need = P->L.total;
+  // block info + whole-set tables for the per-call kernels
+  std::vector<BlkInfo> info(hb.B);
+  std::vector<MatDesc> all_tall;
+  std::vector<CsrDesc> all_csr;
+  for (int b = 0; b < hb.B; ++b) {
+    info[b] = BlkInfo{hb.t_off[b], int(hb.v_off[b + 1] - hb.v_off[b]), hb.p[b], hb.pred[b], 0};
+    all_tall.push_back(MatDesc{hb.u_off[b], info[b].n, hb.ld[b], hb.p[b], b});
+    all_csr.push_back(CsrDesc{hb.v_off[b] + b, nnz_off[b]});
+  }
+  std::vector<size_t> offs;
+  put(blob, info, &offs);
+  put(blob, all_tall, &offs);
+  put(blob, all_csr, &offs);
+  for (auto& h : hosts) {
+    put(blob, h.tall, &offs);
+    put(blob, h.ptall, &offs);
+    put(blob, h.small, &offs);
+    put(blob, h.csr, &offs);
+    put(blob, h.sd, &offs);
+    put(blob, h.spmm, &offs);
+    put(blob, h.gt, &offs);
+    put(blob, h.gr, &offs);
+    put(blob, h.gts, &offs);
+    put(blob, h.grs, &offs);
+    put(blob, h.rt, &offs);
+    put(blob, h.rts, &offs);
+  }
+  MI_TRY_HIP(hipMalloc(&P->arena, std::max<size_t>(blob.size(), 256)));
+  MI_TRY_HIP(hipMemcpy(P->arena, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  char* base = static_cast<char*>(P->arena);
+  size_t k = 0;
+  P->info = reinterpret_cast<BlkInfo*>(base + offs[k++]);
+  P->all_tall = reinterpret_cast<MatDesc*>(base + offs[k++]);
+  P->all_csr = reinterpret_cast<CsrDesc*>(base + offs[k++]);
+  for (size_t w = 0; w < waves.size(); ++w) {
+    WaveTables& wt = P->waves[w];
+    WaveHost& h = hosts[w];
+    wt.tall = reinterpret_cast<MatDesc*>(base + offs[k++]);
+    wt.ptall = reinterpret_cast<MatDesc*>(base + offs[k++]);
+    wt.small = reinterpret_cast<MatDesc*>(base + offs[k++]);
+    wt.csr = reinterpret_cast<CsrDesc*>(base + offs[k++]);
+    wt.sd = reinterpret_cast<SmallDesc*>(base + offs[k++]);
+    wt.spmm = reinterpret_cast<SpmmTile*>(base + offs[k++]);
+    wt.n_spmm = (int)h.spmm.size();
+    wt.gt = reinterpret_cast<GramTile*>(base + offs[k++]);
+    wt.n_gt = (int)h.gt.size();
+    wt.gr = reinterpret_cast<GramReduce*>(base + offs[k++]);
+    wt.n_gr = (int)h.gr.size();
+    wt.gts = reinterpret_cast<GramTile*>(base + offs[k++]);
+    wt.n_gts = (int)h.gts.size();
+    wt.grs = reinterpret_cast<GramReduce*>(base + offs[k++]);
+    wt.n_grs = (int)h.grs.size();
+    wt.rt = reinterpret_cast<RowTile*>(base + offs[k++]);
+    wt.n_rt = (int)h.rt.size();
+    wt.rts = reinterpret_cast<RowTile*>(base + offs[k++]);
+    wt.n_rts = (int)h.rts.size();
+  }
+  *out = std::move(P);
+  return MI_OK;
+}
+
+// ------------------------------------------------------------------ enqueue
+
+struct Args {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  const void* V0;
+  void* V;
+  double* ritz;
+  int32_t* status;
+  char* ws;
+};
+
+template <typename T>
+static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
+  const mi_oi_params& prm = P.prm;
+  const WsLayout& L = P.L;
+  char* ws = a.ws;
+  T* slab[4];
+  for (int i = 0; i < 4; ++i) slab[i] = reinterpret_cast<T*>(ws + L.slab[i]);
+  double* G = reinterpret_cast<double*>(ws + L.G);
+  double* H = reinterpret_cast<double*>(ws + L.H);
+  double* Rinv = reinterpret_cast<double*>(ws + L.Rinv);
+  double* T1 = reinterpret_cast<double*>(ws + L.T1);
+  double* Am = reinterpret_cast<double*>(ws + L.A);
+  double* Z = reinterpret_cast<double*>(ws + L.Z);
+  double* S64 = reinterpret_cast<double*>(ws + L.S64);
+  float* S32 = reinterpret_cast<float*>(ws + L.S32);
+  double* pk = reinterpret_cast<double*>(ws + L.pk);
+  double* lg = reinterpret_cast<double*>(ws + L.log);
+  int32_t* perm = reinterpret_cast<int32_t*>(ws + L.perm);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* a_lo = reinterpret_cast<double*>(ws + L.a_lo);
+  double* b_hi = reinterpret_cast<double*>(ws + L.b_hi);
+  double* coef = reinterpret_cast<double*>(ws + L.coef);
+  int32_t* conv = reinterpret_cast<int32_t*>(ws + L.conv);
+  const bool dbl = std::is_same<T, double>::value;
+  // S of the row products: FP32 rounding of the FP64 small result, or FP64 itself
+  const T* Smat = dbl ? reinterpret_cast<const T*>(S64) : reinterpret_cast<const T*>(S32);
+  T* V = static_cast<T*>(a.V);
+  const T* V0 = static_cast<const T*>(a.V0);
+  const int B = P.hb.B;
+
+  fill_i32(a.status, 0, B, s);
+  if (prm.b_abs > 0)
+    hipLaunchKernelGGL(k_set_b, dim3(ceil_div(B, 256)), dim3(256), 0, s, P.all_tall, B, prm.b_abs, b_hi);
+  else
+    hipLaunchKernelGGL(k_gershgorin, dim3(B), dim3(256), 0, s, P.all_tall, P.all_csr, a.row_ptr,
+                       a.val, b_hi);
+
+  for (WaveTables& w : P.waves) {
+    const size_t lds_chol = size_t(3 * w.max_q + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
+    const bool chol_lds = lds_chol <= (size_t)P.lds_max;
+    const size_t lds_chol_use = chol_lds ? lds_chol : size_t(3 * w.max_q) * 8;
+    const size_t lds_jac = size_t(4 * (w.max_q / 2) + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
+    const bool jac_lds = lds_jac <= (size_t)P.lds_max;
+    const size_t lds_jac_use = jac_lds ? lds_jac : size_t(4 * (w.max_q / 2)) * 8;
+
+    hipLaunchKernelGGL(k_init_a, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb, P.info,
+                       w.from_pred ? 1 : 0, prm.a_mode, prm.a_value, a.ritz, a_lo, b_hi);
+    // start basis X of the first iteration
+    const T* X = V0;
+    if (w.from_pred) {
+      hipLaunchKernelGGL(k_warm_copy<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.ptall, V);
+      X = V;
+    }
+    int xslab = -1;  // slab holding X (-1: X lives in V0 / V)
+    for (int t = 0; t < w.T; ++t) {
+      const bool last = t == w.T - 1;
+      int ycur = -1;
+      for (int pass = 0; pass < w.passes; ++pass) {
+        hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
+                           a_lo, b_hi, coef, L.coef_stride, w.m);
+        int free_s[3], nf = 0;
+        for (int i = 0; i < 4 && nf < 3; ++i)
+          if (i != xslab) free_s[nf++] = i;
+        const T* prev = nullptr;
+        const T* cur = X;
+        for (int k = 0; k < w.m; ++k) {
+          T* out = slab[free_s[k % 3]];
+          launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, cur, prev, out,
+                         coef, L.coef_stride, k, s);
+          prev = cur;
+          cur = out;
+          ycur = free_s[k % 3];
+        }
+        if (pass < w.passes - 1) {
+          // span-preserving Cholesky-QR between passes
+          launch_gram<T>(w.gt, w.n_gt, w.tall, slab[ycur], slab[ycur], nullptr, part, s);
+          launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+          launch_chol_inv(w.sd, w.nb, G, Rinv, dbl ? nullptr : S32, pk, a.status, chol_lds,
+                          lds_chol_use, s);
+          int dst = -1;
+          for (int i = 0; i < 4; ++i)
+            if (i != ycur && i != xslab) dst = i;
+          if (dbl)
+            launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
+                                reinterpret_cast<const T*>(Rinv), w.tall, slab[dst], w.nch, s);
+          else
+            launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
+                                reinterpret_cast<const T*>(S32), w.tall, slab[dst], w.nch, s);
+          X = slab[dst];
+          xslab = dst;
+        }
+      }
+      // Rayleigh-Ritz on span(Y)
+      T* Y = slab[ycur];
+      int wsl = -1;
+      for (int i = 0; i < 4; ++i)
+        if (i != ycur) wsl = i;
+      T* Wm = slab[wsl];
+      launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
+                     L.coef_stride, w.m, s);
+      launch_gram<T>(w.gt, w.n_gt, w.tall, Y, Y, Wm, part, s);
+      launch_gram_reduce(w.gr, w.n_gr, w.small, part, true, G, H, s);
+      launch_chol_inv(w.sd, w.nb, G, Rinv, nullptr, pk, a.status, chol_lds, lds_chol_use, s);
+      // A = Rinv^T (H Rinv)
+      launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
+      launch_gram<double>(w.gts, w.n_gts, w.small, Rinv, T1, nullptr, part, s);
+      launch_gram_reduce(w.grs, w.n_grs, w.small, part, false, Am, nullptr, s);
+      launch_jacobi_init(w.sd, w.nb, Am, pk, Z, conv, s);
+      for (int sw = 0; sw < prm.max_sweeps; ++sw) {
+        launch_jacobi_sweep(w.sd, w.nb, pk, lg, conv, prm.jacobi_tol, jac_lds, lds_jac_use, s);
+        launch_apply_rot(w.sd, w.nb, w.max_q, lg, conv, Z, s);
+      }
+      launch_rr_finish(w.sd, w.nb, pk, conv, a.ritz, perm, a_lo, prm.adapt, a.status, s);
+      launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S64, w.nchs, s);
+      // S <- columns of Rinv Z in ascending Ritz order (FP32 copy for FP32 products)
+      launch_perm_cast(w.sd, w.nb, S64, perm, dbl ? nullptr : S32, dbl ? T1 : nullptr, s);
+      const T* Sm = dbl ? reinterpret_cast<const T*>(T1) : reinterpret_cast<const T*>(S32);
+      (void)Smat;
+      T* dstV;
+      int dslab = -1;
+      if (!last) {
+        dstV = V;
+      } else {
+        for (int i = 0; i < 4; ++i)
+          if (i != ycur) dslab = i;
+        dstV = slab[dslab];
+      }
+      launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, dstV, w.nch, s);
+      if (!last) {
+        X = V;
+        xslab = -1;
+      } else {
+        // final Cholesky-QR: V = Vtmp R^-1 (upper triangular: keeps the span of
+        // every leading column set, hence the Ritz order)
+        launch_gram<T>(w.gt, w.n_gt, w.tall, dstV, dstV, nullptr, part, s);
+        launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+        launch_chol_inv(w.sd, w.nb, G, Rinv, dbl ? nullptr : S32, pk, a.status, chol_lds,
+                        lds_chol_use, s);
+        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, dstV, w.small,
+                            dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
+                            w.tall, V, w.nch, s);
+      }
+    }
+    if (w.T == 0 && !w.from_pred)
+      hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+  }
+}
+
+static bool same_key(const OiPlan& P, const HostBlocks& hb, const std::vector<int64_t>& nnz,
+                     const mi_oi_params& prm, const std::vector<const void*>& ptrs,
+                     size_t ws_bytes, bool per_block) {
+  return P.per_block == per_block && P.hb.v_off == hb.v_off && P.hb.u_off == hb.u_off &&
+         P.hb.p == hb.p && P.hb.ld == hb.ld && P.hb.pred == hb.pred && P.nnz_off == nnz &&
+         memcmp(&P.prm, &prm, sizeof(prm)) == 0 && P.ptrs == ptrs && P.ws_bytes == ws_bytes;
+}
+
+static mi_status check_params(const mi_oi_params* prm) {
+  MI_CHECK_ARG(prm != nullptr, "params are NULL");
+  MI_CHECK_ARG(prm->precision == MI_FP32 || prm->precision == MI_FP64, "precision %d unsupported",
+               prm->precision);
+  MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN || prm->warm == MI_WARM_PRED, "warm mode %d unknown",
+               prm->warm);
+  MI_CHECK_ARG(prm->T >= 0 && prm->T0 >= 0 && prm->T <= 1000 && prm->T0 <= 1000, "T out of range");
+  MI_CHECK_ARG(prm->m >= 1 && prm->m0 >= 1 && prm->m <= 256 && prm->m0 <= 256, "m out of range");
+  MI_CHECK_ARG(prm->passes >= 1 && prm->passes0 >= 1, "passes must be >= 1");
+  MI_CHECK_ARG(prm->max_sweeps >= 1 && prm->max_sweeps <= 100, "max_sweeps out of range");
+  MI_CHECK_ARG(prm->a_mode >= 0 && prm->a_mode <= 2, "a_mode unknown");
+  MI_CHECK_ARG(prm->jacobi_tol > 0 && prm->jacobi_tol < 1e-3, "jacobi_tol out of range");
+  return MI_OK;
+}
+
+// Dynamic LDS available to the small kernels: the per-workgroup maximum
+// (160 KB on gfx950) less a margin for their static shared variables.
+static int device_lds_max(int dev) {
+  int v = 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    v = 65536;
+  return v - 2048;
+}
+
+static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                        const int32_t* row_ptr, const int32_t* col, const float* val,
+                        const int64_t* nnz_off, const void* V0, void* V, double* ritz,
+                        int32_t* status, void* ws, size_t ws_bytes, void* stream, bool per_block) {
+  begin_call();
+  MI_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  mi_status st = check_params(prm);
+  if (st) return st;
+  HostBlocks hb;
+  st = load_blocks(blk, &hb, true);
+  if (st) return st;
+  MI_CHECK_ARG(row_ptr && col && val && nnz_off && V && ritz && status, "NULL argument");
+  std::vector<int64_t> nnz(nnz_off, nnz_off + hb.B + 1);
+  bool needs_v0 = prm->warm == MI_WARM_GIVEN;
+  for (int b = 0; b < hb.B; ++b) needs_v0 = needs_v0 || hb.pred[b] < 0;
+  MI_CHECK_ARG(!needs_v0 || V0 != nullptr, "V0 is required");
+  MI_TRY_HIP(hipSetDevice(ctx->device));
+  const int lds_max = device_lds_max(ctx->device);
+  std::vector<const void*> ptrs = {row_ptr, col, val, V0, V, ritz, status, ws};
+  OiPlan* P = static_cast<OiPlan*>(ctx->oi_plan);
+  if (!P || !same_key(*P, hb, nnz, *prm, ptrs, ws_bytes, per_block)) {
+    delete P;
+    ctx->oi_plan = nullptr;
+    std::unique_ptr<OiPlan> np;
+    size_t need = 0;
+    st = make_plan(hb, nnz, *prm, per_block, lds_max, &np, &need);
+    if (st) return st;
+    if (!ws || ws_bytes < need) {
+      set_error("workspace %zu bytes < %zu required", ws_bytes, need);
+      return MI_ERR_WORKSPACE;
+    }
+    np->ptrs = ptrs;
+    np->ws_bytes = ws_bytes;
+    P = np.release();
+    ctx->oi_plan = P;
+  }
+  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws)};
+  hipStream_t s = (hipStream_t)stream;
+  if (per_block) {
+    if (prm->precision == MI_FP64)
+      enqueue<double>(*P, a, s);
+    else
+      enqueue<float>(*P, a, s);
+    MI_TRY_HIP(hipGetLastError());
+    return MI_OK;
+  }
+  if (!P->exec) {
+    if (!P->cap_stream) MI_TRY_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    MI_TRY_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    if (prm->precision == MI_FP64)
+      enqueue<double>(*P, a, P->cap_stream);
+    else
+      enqueue<float>(*P, a, P->cap_stream);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(P->cap_stream, &P->graph);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      set_error("graph capture failed: %s / %s", hipGetErrorString(e1), hipGetErrorString(e2));
+      return MI_ERR_HIP;
+    }
+    MI_TRY_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  }
+  MI_TRY_HIP(hipGraphLaunch(P->exec, s));
+  return MI_OK;
+}
+
+}  // namespace mis
+
+using namespace mis;
+
+extern "C" {
+
+void mis_destroy_oi_plan(mi_ctx* ctx) {
+  delete static_cast<OiPlan*>(ctx->oi_plan);
+  ctx->oi_plan = nullptr;
+}
+
+mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                               size_t* ws_bytes) {
+  clear_error();
+  MI_CHECK_ARG(ws_bytes != nullptr, "ws_bytes is NULL");
+  (void)ctx;
+  mi_status st = check_params(prm);
+  if (st) return st;
+  HostBlocks hb;
+  st = load_blocks(blk, &hb, true);
+  if (st) return st;
+  std::vector<std::vector<int>> waves;
+  std::vector<int> level;
+  st = build_waves(hb, *prm, false, &waves, &level);
+  if (st) return st;
+  // the Gram partial buffer is sized for the largest wave
+  size_t part_max = 0;
+  std::vector<int64_t> pk_off(hb.B, 0), log_off(hb.B, 0), nnz(hb.B + 1, 0);
+  for (auto& w : waves) {
+    WaveTables wt;
+    WaveHost h;
+    wave_host(hb, nnz, w, *prm, &wt, &h, pk_off, log_off);
+    part_max = std::max(part_max, h.gt.size() * 2 * GRAM_TILE * GRAM_TILE);
+    part_max = std::max(part_max, h.gts.size() * 2 * GRAM_TILE * GRAM_TILE);
+  }
+  *ws_bytes = ws_layout(hb, *prm, part_max).total;
+  return MI_OK;
+}
+
+mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                      const int32_t* row_ptr, const int32_t* col, const float* val,
+                      const int64_t* nnz_off, const void* V0, void* V, double* ritz,
+                      int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, status, ws, ws_bytes,
+                stream, false);
+}
+
+mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                                const int32_t* row_ptr, const int32_t* col, const float* val,
+                                const int64_t* nnz_off, const void* V0, void* V, double* ritz,
+                                int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, status, ws, ws_bytes,
+                stream, true);
+}
+
+}  // extern "C"

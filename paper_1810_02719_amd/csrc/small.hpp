@@ -1,0 +1,58 @@
+// Per-block small dense FP64 kernels of the orthonormalisation and the
+// Rayleigh-Ritz step (one workgroup per block).
+#pragma once
+
+#include "dense.hpp"
+
+namespace mis {
+
+// Per-block state of the small kernels.
+struct SmallDesc {
+  int64_t m_off;    // ld x ld matrices (G, H, Rinv, A, Z, S)
+  int64_t pk_off;   // packed upper-triangle scratch (q(q+1)/2)
+  int64_t log_off;  // rotation log of one sweep ((q-1) * q/2 * 2)
+  int64_t t_off;    // Ritz values / permutation (p entries)
+  int32_t p, ld, q; // q = p rounded up to even
+  int32_t blk;      // index into per-block arrays (status, a, b, flags)
+};
+
+constexpr int SMALL_THREADS = 1024;
+
+// Cholesky of the column-scaled Gram G = R^T R and the inverse factor
+// Rinv (upper, FP64, zeros elsewhere); optionally Rinv rounded to FP32
+// (S32) for the row product.  Sets MI_BLOCK_SHIFTED / _NOT_PD / _NONFINITE
+// in status.
+void launch_chol_inv(const SmallDesc* sd, int nb, const double* G, double* Rinv, float* S32,
+                     double* pk_scratch, int32_t* status, bool lds, size_t lds_bytes,
+                     hipStream_t s);
+
+// Packs the upper triangle of A (ld x ld) into the Jacobi scratch and sets Z
+// to the identity; resets the per-block "converged" flag.
+void launch_jacobi_init(const SmallDesc* sd, int nb, const double* A, double* pk, double* Z,
+                        int32_t* conv, hipStream_t s);
+
+// One cyclic sweep (q-1 rounds of q/2 disjoint rotations) of two-sided
+// Jacobi on the packed matrix; rotations go to the log.
+void launch_jacobi_sweep(const SmallDesc* sd, int nb, double* pk, double* log, int32_t* conv,
+                         double tol, bool lds, size_t lds_bytes, hipStream_t s);
+
+// Z <- Z * (rotations of the last sweep), rows in parallel.
+void launch_apply_rot(const SmallDesc* sd, int nb, int max_ld, const double* log,
+                      const int32_t* conv, double* Z, hipStream_t s);
+
+// Ritz values (diagonal) sorted ascending -> ritz[t_off..], permutation ->
+// perm[t_off..]; a[blk] <- largest Ritz value when adapt; NOCONV flag.
+void launch_rr_finish(const SmallDesc* sd, int nb, const double* pk, const int32_t* conv,
+                      double* ritz, int32_t* perm, double* a_lo, int adapt, int32_t* status,
+                      hipStream_t s);
+
+// S32[i][j] = S64[i][perm[j]] for j < p, zero for padding columns.
+void launch_perm_cast(const SmallDesc* sd, int nb, const double* S64, const int32_t* perm,
+                      float* S32, double* S64out, hipStream_t s);
+
+// Kernel symbols (for raising their dynamic-LDS limit).
+const void* k_chol_inv_ptr();
+const void* k_jacobi_sweep_ptr();
+const void* k_apply_rot_ptr();
+
+}  // namespace mis

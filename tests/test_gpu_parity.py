@@ -1,0 +1,321 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+seeded inputs.
+
+Bars: integer CSR structure bit-exact; combinatorial values exact, distance
+weights within 1 ulp of the FP64 value; tracked subspaces within a principal
+angle of 1e-5 rad (FP32) of the oracle's eigenspace and reconstructed
+coordinates within 1e-5 relative error; FP64 paths to 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1810_02719_amd as mis
+from oracle import iterations as it
+from oracle import laplacian as lap
+from oracle import metrics as met
+from oracle import spectral as S
+from synth import meshes as M
+from synth import workloads as W
+
+from gpu_common import Uploaded, oracle_block
+
+pytestmark = pytest.mark.gpu
+
+ANGLE_FP32 = 1e-5
+RECON_FP32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = mis.Context(0)
+    yield c
+    c.close()
+
+
+def warm_params(**kw):
+    p = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED, T=3, m=10, passes=2, T0=8,
+                     m0=8, passes0=1, adapt=1, max_sweeps=12, a_mode=mis.MI_A_WEYL, a_value=1.0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# ------------------------------------------------------------------ Laplacian (Section 3)
+
+def _check_csr(up, L, mode):
+    rp = L.row_ptr.cpu().numpy()
+    col = L.col.cpu().numpy()
+    val = L.val.cpu().numpy()
+    edges = L.edges.cpu().numpy().reshape(-1, 2)
+    ew = L.edge_w.cpu().numpy()
+    for b in range(up.blocks.n_blocks):
+        n = int(up.blocks.n[b])
+        X = up.X32(b)
+        e = lap.canonical_edges(up.bs.faces[b], n)
+        w = lap.edge_weights(e, X, mode)
+        orp, ocol, oval = lap.laplacian_csr(n, e, w)
+        v0 = int(up.blocks.v_off[b])
+        grp = rp[v0 + b:v0 + b + n + 1]
+        assert np.array_equal(grp, orp), f"row_ptr block {b}"
+        n0, n1 = int(L.nnz_off[b]), int(L.nnz_off[b + 1])
+        assert np.array_equal(col[n0:n1], ocol), f"col block {b}"
+        e0, e1 = int(L.edge_off[b]), int(L.edge_off[b + 1])
+        assert np.array_equal(edges[e0:e1], e), f"edges block {b}"
+        if mode == lap.COMBINATORIAL:
+            assert np.array_equal(val[n0:n1], oval.astype(np.float32))
+            assert np.array_equal(ew[e0:e1], np.ones(e1 - e0, np.float32))
+        else:
+            ulp = np.spacing(np.abs(oval).astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(val[n0:n1] - oval) <= ulp), f"values block {b}"
+            ulpw = np.spacing(w.astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(ew[e0:e1] - w) <= ulpw)
+
+
+@pytest.mark.parametrize("name", ["grid", "icosphere", "disks"])
+@pytest.mark.parametrize("mode", [lap.COMBINATORIAL, lap.INV_SQ_DIST])
+def test_laplacian_bitexact(ctx, name, mode):
+    bs = {"grid": lambda: W.grid_single(),
+          "icosphere": lambda: W.icosphere_blocks(level=4, n_blocks=7, c=20, p=30),
+          "disks": lambda: W.disk_blocks(n_blocks=5, n_min=50, n_max=700, c_max=20, p_max=30)}[name]()
+    up = Uploaded(bs)
+    L = up.laplacian(ctx, mode)
+    torch.cuda.synchronize()
+    _check_csr(up, L, mode)
+
+
+def test_laplacian_values_on_fixed_structure(ctx):
+    bs = W.icosphere_blocks(level=3, n_blocks=3, c=10, p=16)
+    up = Uploaded(bs)
+    L = up.laplacian(ctx, mis.MI_W_COMBINATORIAL)
+    new = up.coords * 1.5 + 0.25
+    ref = mis.build_laplacian(ctx, up.blocks, up.prim_off, up.prims, 3, new, mis.MI_W_INV_SQ_DIST)
+    mis.laplacian_values(ctx, up.blocks, L, new, mis.MI_W_INV_SQ_DIST)
+    torch.cuda.synchronize()
+    assert torch.equal(L.val, ref.val) and torch.equal(L.edge_w, ref.edge_w)
+
+
+def test_laplacian_errors(ctx):
+    bs = W.icosphere_blocks(level=2, n_blocks=2, c=4, p=8)
+    up = Uploaded(bs)
+    bad = up.prims.clone()
+    bad[4] = int(up.blocks.n[0]) + 5  # a corner beyond its block
+    with pytest.raises(mis.MiError) as ei:
+        mis.build_laplacian(ctx, up.blocks, up.prim_off, bad, 3, up.coords)
+    assert ei.value.code == mis._lib.MI_ERR_INDEX
+    same = up.coords.clone().view(-1, 3)
+    f0 = up.bs.faces[0][0]
+    same[int(f0[1])] = same[int(f0[0])]  # a zero-length edge
+    with pytest.raises(mis.MiError) as ei:
+        mis.build_laplacian(ctx, up.blocks, up.prim_off, up.prims, 3, same.reshape(-1).contiguous(),
+                            mis.MI_W_INV_SQ_DIST)
+    assert ei.value.code == mis._lib.MI_ERR_DEGENERATE
+
+
+# ------------------------------------------------------------------ iterate pin (span identity)
+
+@pytest.mark.parametrize("precision", [mis.MI_FP64, mis.MI_FP32])
+def test_span_identity_before_convergence(ctx, precision):
+    """With the filter interval fixed, T iterations of `passes` degree-m passes
+    span T_m(t(L))^(T*passes) V0 exactly; compare before convergence."""
+    bs = W.grid_single(nx=12, ny=13, c=10, p=24)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    dt = torch.float64 if precision == mis.MI_FP64 else torch.float32
+    V0 = up.starts(dt)
+    a, b, m, T, passes = 1.0, 12.0, 5, 2, 2
+    prm = mis.OiParams(precision=precision, warm=mis.MI_WARM_GIVEN, T0=T, m0=m, passes0=passes,
+                       adapt=0, a_mode=mis.MI_A_ABS, a_value=a, b_abs=b, max_sweeps=15)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
+    torch.cuda.synchronize()
+    Lden, _, _ = oracle_block(up, 0)
+    ref = it.chebyshev_span(Lden, V0.double().cpu().numpy().reshape(156, 32)[:, :24], a, b, m,
+                            T * passes)
+    got = up.slab(V, 0)[:, :24]
+    ang = S.sin_theta_max(ref, got)
+    assert ang < (1e-10 if precision == mis.MI_FP64 else 2e-5), ang
+    # Ritz values of the final basis are those of the oracle on the same span
+    th, _ = it.rayleigh_ritz(Lden, ref)
+    tol = 1e-10 if precision == mis.MI_FP64 else 1e-4
+    assert np.abs(ritz.cpu().numpy() - th).max() < tol * th.max()
+    assert int(st[0]) & ~mis._lib.MI_BLOCK_SHIFTED == 0
+
+
+# ------------------------------------------------------------------ single submesh, FP64
+
+def test_grid_single_fp64(ctx):
+    """32x32 grid, c = 50, 30 iterations from a seeded random orthonormal start, FP64."""
+    bs = W.grid_single()
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float64)
+    prm = mis.OiParams(precision=mis.MI_FP64, warm=mis.MI_WARM_GIVEN, T0=30, m0=8, passes0=1,
+                       adapt=1, max_sweeps=15)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
+    c = torch.full((1,), 50, dtype=torch.int32, device="cuda:0")
+    X = up.coords.double()
+    E = mis.project(ctx, up.blocks, c, V, X, mis.MI_FP64)
+    Xr = mis.reconstruct(ctx, up.blocks, c, V, E, mis.MI_FP64)
+    torch.cuda.synchronize()
+    _, lam, U = oracle_block(up, 0)
+    Vg = up.slab(V, 0)
+    assert S.sin_theta_max(U[:, :50], Vg[:, :50]) < 1e-9
+    assert np.abs(ritz.cpu().numpy()[:50] - lam[:50]).max() < 1e-10
+    assert np.abs(Vg[:, :75].T @ Vg[:, :75] - np.eye(75)).max() < 1e-12
+    Xo = S.encode_decode(U[:, :50], up.X32(0))
+    assert S.rel_error(Xr.cpu().numpy().reshape(-1, 3), Xo) < 1e-9
+    assert int(st[0]) == 0
+
+
+# ------------------------------------------------------------------ warm-started chain, FP32
+
+def _chain_check(up, V, ritz, st, c, sample=None):
+    blocks = range(up.blocks.n_blocks) if sample is None else sample
+    worst = 0.0
+    for b in blocks:
+        _, lam, U = oracle_block(up, b, k=int(up.blocks.p[b]) + 1)
+        Vg = up.slab(V, b)
+        ang = S.sin_theta_max(U[:, :c], Vg[:, :c])
+        Xo = S.encode_decode(U[:, :c], up.X32(b))
+        Xg = S.encode_decode(S.orthonormalize(Vg[:, :c]), up.X32(b))
+        rec = S.rel_error(Xg, Xo)
+        worst = max(worst, ang)
+        assert ang < ANGLE_FP32, (b, ang, lam[c] - lam[c - 1])
+        assert rec < RECON_FP32, (b, rec)
+        assert int(st[b]) & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0
+    return worst
+
+
+@pytest.fixture(scope="module")
+def chain_small():
+    return Uploaded(W.icosphere_blocks(level=5, n_blocks=8, c=100, p=192))
+
+
+def test_warm_chain_fp32(ctx, chain_small):
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0)
+    torch.cuda.synchronize()
+    _chain_check(up, V, ritz, st, 100)
+
+
+def test_determinism_and_graph_replay(ctx, chain_small):
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    V = torch.empty(int(up.blocks.u_off[-1]), device="cuda:0")
+    outs = []
+    for _ in range(3):
+        mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0, V=V)
+        torch.cuda.synchronize()
+        outs.append(V.clone())
+        torch.ones(1000, device="cuda:0").sum().item()  # eager work between replays
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2])
+
+
+def test_per_block_reference_path(ctx, chain_small):
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    Vb, rb, sb = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0)
+    Vp, rp_, sp = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0, per_block=True)
+    torch.cuda.synchronize()
+    for b in range(up.blocks.n_blocks):
+        assert S.sin_theta_max(up.slab(Vb, b)[:, :100], up.slab(Vp, b)[:, :100]) < 2e-5
+
+
+def test_project_reconstruct_given_basis(ctx, chain_small):
+    """Encode/decode kernels against FP64 numpy on the GPU's own basis, with a
+    different c per block (truncation)."""
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=up.starts(torch.float32))
+    rng = np.random.default_rng(5)
+    cs = rng.integers(1, up.blocks.p + 1)
+    c = torch.from_numpy(cs.astype(np.int32)).cuda()
+    E = mis.project(ctx, up.blocks, c, V, up.coords)
+    Xr = mis.reconstruct(ctx, up.blocks, c, V, E)
+    torch.cuda.synchronize()
+    Eh = E.double().cpu().numpy().reshape(-1, 3)
+    Xh = Xr.double().cpu().numpy().reshape(-1, 3)
+    for b in range(up.blocks.n_blocks):
+        Vg = up.slab(V, b)
+        cb = int(cs[b])
+        t0 = int(up.blocks.t_off[b])
+        Er = Vg[:, :cb].T @ up.X32(b)
+        assert np.abs(Eh[t0:t0 + cb] - Er).max() < 1e-6 * np.abs(Er).max() + 1e-7
+        assert np.all(Eh[t0 + cb:t0 + int(up.blocks.p[b])] == 0)
+        Xref = Vg[:, :cb] @ Eh[t0:t0 + cb]
+        v0, v1 = int(up.blocks.v_off[b]), int(up.blocks.v_off[b + 1])
+        assert S.rel_error(Xh[v0:v1], Xref) < 1e-6
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_full_spectrum_block(ctx):
+    """p = n (the whole spectrum): reconstruction with c = n is the identity."""
+    v, f = M.icosphere(1)
+    bs = W.BlockSet(name="ico1", coords=[v], faces=[f], pred=np.array([-1]), level=np.array([0]),
+                    order=np.array([0]), c=np.array([42]), p=np.array([42]))
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    prm = mis.OiParams(precision=mis.MI_FP64, warm=mis.MI_WARM_GIVEN, T0=3, m0=4, passes0=1,
+                       max_sweeps=20)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=up.starts(torch.float64))
+    c = torch.full((1,), 42, dtype=torch.int32, device="cuda:0")
+    X = up.coords.double()
+    Xr = mis.reconstruct(ctx, up.blocks, c, V, mis.project(ctx, up.blocks, c, V, X, mis.MI_FP64),
+                         mis.MI_FP64)
+    torch.cuda.synchronize()
+    assert S.rel_error(Xr.cpu().numpy(), X.cpu().numpy()) < 1e-12
+    _, lam, _ = oracle_block(up, 0)
+    assert np.abs(ritz.cpu().numpy() - lam).max() < 1e-10
+
+
+def test_rank_deficient_start_flags_shift(ctx):
+    """Duplicate start columns make the first Gram singular: the block is
+    flagged (shifted pivot) instead of producing NaN."""
+    bs = W.grid_single(nx=9, ny=9, c=6, p=12)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32).view(81, 32)
+    V0[:, 5] = V0[:, 4]
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=1, m0=1, passes0=2,
+                       adapt=0, a_mode=mis.MI_A_ABS, a_value=2.0)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0.reshape(-1).contiguous())
+    torch.cuda.synchronize()
+    assert int(st[0]) & mis._lib.MI_BLOCK_SHIFTED
+    assert torch.isfinite(V).all()
+
+
+# ------------------------------------------------------------------ choice of c (Section 5, Eq. 16)
+
+def test_choose_c_against_oracle(ctx):
+    bs = W.disk_blocks(n_blocks=4, n_min=400, n_max=900, c_max=64, p_max=96, key=(31,))
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    gl = up.laplacian(ctx, mis.MI_W_INV_DIST)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=12, m0=8, passes0=1)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=up.starts(torch.float32))
+    cmax = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
+    # a target inside the curve's range so the rule has a real choice
+    target = 2.0e-3
+    cg, metric = mis.choose_c(ctx, up.blocks, cmax, target, 1e-3, V, ritz, up.coords, gl)
+    torch.cuda.synchronize()
+    mh = metric.cpu().numpy()
+    for b in range(up.blocks.n_blocks):
+        n = int(up.blocks.n[b])
+        X = up.X32(b)
+        _, lam, U = oracle_block(up, b)
+        e = lap.canonical_edges(bs.faces[b], n)
+        G = met.gl_matrix(n, e, X)
+        cm = int(bs.c[b])
+        curve = met.nmsve_curve(U, X, G, cm)
+        t0 = int(up.blocks.t_off[b])
+        assert np.abs(mh[t0:t0 + cm] - curve).max() < 1e-4 * curve.max()
+        co = met.choose_c(curve, lam, target, 1e-3)
+        if int(cg[b]) != co:  # only a near-tie at the target may differ
+            k = min(int(cg[b]), co) - 1
+            assert abs(curve[k] - target) < 1e-3 * target

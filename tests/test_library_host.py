@@ -1,0 +1,87 @@
+"""CPU tests of the C ABI boundary: the library loads, exports every symbol
+the header declares, and rejects bad block tables and parameters on the host
+(no GPU needed: the workspace-size queries are host arithmetic)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import paper_1810_02719_amd as mis
+from paper_1810_02719_amd import _lib as L
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    declared = L.declared_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.mi_version().decode().startswith("mispectral")
+
+
+def _oi_ws(blocks, prm):
+    n = C.c_size_t()
+    code = L.lib().mi_oi_workspace_size(None, blocks.ref, C.byref(prm.struct()), C.byref(n))
+    return code, n.value
+
+
+def test_oi_workspace_query_valid_table():
+    b = mis.Blocks([100, 200, 150], p=[20, 40, 30], pred=[-1, 0, 1])
+    code, n = _oi_ws(b, mis.OiParams())
+    assert code == 0 and n > 0
+    # the slabs alone are 4 * sum(n * ld) floats
+    assert n >= 4 * int(b.u_off[-1]) * 4
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=[100], p=[101]), L.MI_ERR_CAPACITY),         # p > n
+    (dict(n=[100], p=[10], ld=[48]), L.MI_ERR_CAPACITY),  # ld not a multiple of 32
+    (dict(n=[100], p=[40], ld=[32]), L.MI_ERR_CAPACITY),  # ld < p
+])
+def test_bad_block_tables(kw, code):
+    b = mis.Blocks(**kw)
+    c, _ = _oi_ws(b, mis.OiParams())
+    assert c == code
+    assert L.lib().mi_last_error().decode() != ""
+
+
+def test_predecessor_cycle_rejected():
+    b = mis.Blocks([50, 50], p=[8, 8], pred=[1, 0])
+    c, _ = _oi_ws(b, mis.OiParams())
+    assert c == L.MI_ERR_ARG
+    assert "cycle" in L.lib().mi_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [("m", 0), ("passes", 0), ("T", -1), ("precision", 7),
+                                         ("a_mode", 9), ("max_sweeps", 0), ("jacobi_tol", 0.0)])
+def test_bad_params(field, value):
+    b = mis.Blocks([100], p=[10])
+    prm = mis.OiParams()
+    setattr(prm, field, value)
+    c, _ = _oi_ws(b, prm)
+    assert c == L.MI_ERR_ARG
+
+
+def test_slab_offsets_must_match():
+    b = mis.Blocks([100, 60], p=[10, 10])
+    b.u_off[1] += 32  # corrupt the table the struct points at
+    c, _ = _oi_ws(b, mis.OiParams())
+    assert c == L.MI_ERR_ARG
+
+
+def test_laplacian_workspace_query_arity():
+    b = mis.Blocks([10])
+    n = C.c_size_t()
+    off = np.array([0, 4], np.int64)
+    ptr = off.ctypes.data_as(C.POINTER(C.c_int64))
+    assert L.lib().mi_laplacian_workspace_size(b.ref, ptr, 4, C.byref(n)) == L.MI_ERR_ARG
+    assert L.lib().mi_laplacian_workspace_size(b.ref, ptr, 3, C.byref(n)) == 0
+    assert n.value > 0
+
+
+def test_choose_and_encdec_workspace_queries():
+    b = mis.Blocks([300, 500], p=[40, 64])
+    n = C.c_size_t()
+    assert L.lib().mi_choose_c_workspace_size(None, b.ref, C.byref(n)) == 0 and n.value > 0
+    assert L.lib().mi_encdec_workspace_size(None, b.ref, L.MI_FP32, C.byref(n)) == 0
+    assert L.lib().mi_encdec_workspace_size(None, b.ref, 5, C.byref(n)) == L.MI_ERR_ARG

@@ -108,10 +108,13 @@ typedef struct {
                      /*   MI_A_RITZ: largest entry of the block's `ritz` on input      */
                      /* (a block starting from predecessor P takes the largest Ritz    */
                      /*  value of P scaled by n_P / n_b)                               */
-  int32_t reserved;
+  int32_t rr_every;  /* 1: Rayleigh-Ritz on every iteration; 0: only on the last one
+                        (the others end with a Cholesky-QR and take a from the
+                        largest Rayleigh quotient of its basis)                    */
   double a_value;
   double b_abs;      /* > 0: upper filter bound b for every block; else Gershgorin     */
-  double jacobi_tol; /* off-diagonal threshold relative to ||A||_F (e.g. 1e-14)        */
+  double jacobi_tol; /* off-diagonal threshold relative to ||A||_F on the last
+                        iteration (e.g. 1e-14); earlier ones use max(tol, 1e-8)      */
 } mi_oi_params;
 
 #define MI_A_WEYL 0

@@ -176,19 +176,20 @@ class OiParams:
     T: int = 3
     m: int = 10
     passes: int = 2
-    T0: int = 8
-    m0: int = 8
-    passes0: int = 1
+    T0: int = 5
+    m0: int = 10
+    passes0: int = 2
     adapt: int = 1
     max_sweeps: int = 12
     a_mode: int = MI_A_WEYL
     a_value: float = 1.0
     b_abs: float = 0.0
     jacobi_tol: float = 1e-14
+    rr_every: int = 0
 
     def struct(self):
         return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
-                            self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, 0,
+                            self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, self.rr_every,
                             self.a_value, self.b_abs, self.jacobi_tol)
 
 

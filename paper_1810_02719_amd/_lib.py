@@ -57,7 +57,7 @@ class MiOiParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("warm", C.c_int32), ("T", C.c_int32), ("m", C.c_int32),
                 ("passes", C.c_int32), ("T0", C.c_int32), ("m0", C.c_int32),
                 ("passes0", C.c_int32), ("adapt", C.c_int32), ("max_sweeps", C.c_int32),
-                ("a_mode", C.c_int32), ("reserved", C.c_int32), ("a_value", C.c_double),
+                ("a_mode", C.c_int32), ("rr_every", C.c_int32), ("a_value", C.c_double),
                 ("b_abs", C.c_double), ("jacobi_tol", C.c_double)]
 
 

@@ -197,10 +197,9 @@ void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outset
 }
 
 // ------------------------------------------------------------------ A * S
-// Out rows [row0, row0+64) x columns [n0, n0+NCH) = A rows x S.  A's row tile
-// is staged through LDS in K-chunks (coalesced 128-byte rows), S fragments
-// come from L2 (S is shared by all row tiles of a block).  Each wave owns 16
-// rows and NCH/16 MFMA tiles.
+// Out rows [row0, row0+64) x columns [n0, n0+NCH) = A rows x S.  Per K-chunk
+// of 32, the A row tile and the S panel are staged through LDS with
+// coalesced loads; each wave owns 16 rows and NCH/16 MFMA tiles.
 template <typename T>
 struct Mfma;
 template <>
@@ -228,6 +227,7 @@ __global__ void __launch_bounds__(256)
   constexpr int KC = 32;
   constexpr int NT = NCH / 16;
   __shared__ T As[ROW_TILE][KC + 1];
+  __shared__ T Ss[KC][NCH + 1];
   typedef typename Mfma<T>::acc_t acc_t;
   const RowTile t = tiles[blockIdx.x];
   const MatDesc da = asets[t.set], ds = ssets[t.set], dout = osets[t.set];
@@ -243,16 +243,18 @@ __global__ void __launch_bounds__(256)
       As[rr][kc] = (row < da.rows && k0 + kc < K) ? A[da.off + int64_t(row) * da.ld + k0 + kc]
                                                   : (T)0;
     }
+    for (int e = threadIdx.x; e < KC * NCH; e += 256) {
+      const int kr = e / NCH, nc = e % NCH;
+      const int k = k0 + kr, n = t.n0 + nc;
+      Ss[kr][nc] = (k < K && n < ds.ld) ? S[ds.off + int64_t(k) * ds.ld + n] : (T)0;
+    }
     __syncthreads();
 #pragma unroll 2
     for (int ks = 0; ks < KC; ks += 4) {
-      const int k = k0 + ks + (lane >> 4);
       const T a = As[wave * 16 + (lane & 15)][ks + (lane >> 4)];
-      const bool vk = k < K;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int n = t.n0 + nt * 16 + (lane & 15);
-        const T b = (vk && n < ds.ld) ? S[ds.off + int64_t(k) * ds.ld + n] : (T)0;
+        const T b = Ss[ks + (lane >> 4)][nt * 16 + (lane & 15)];
         acc[nt] = Mfma<T>::op(a, b, acc[nt]);
       }
     }

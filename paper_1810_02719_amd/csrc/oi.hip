@@ -177,7 +177,7 @@ struct WaveTables {
 };
 
 struct WsLayout {
-  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, pk, log, perm, part, a_lo, b_hi, coef, conv;
+  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, part, a_lo, b_hi, coef, conv;
   size_t total;
   int coef_stride;
 };
@@ -287,6 +287,7 @@ static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t 
   L.Z = c.used, c.take<double>(mats);
   L.S64 = c.used, c.take<double>(mats);
   L.S32 = c.used, c.take<float>(mats);
+  L.Wk = c.used, c.take<double>(mats);
   L.pk = c.used, c.take<double>(pk);
   L.log = c.used, c.take<double>(lg);
   L.perm = c.used, c.take<int32_t>(tp);
@@ -490,6 +491,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   double* Z = reinterpret_cast<double*>(ws + L.Z);
   double* S64 = reinterpret_cast<double*>(ws + L.S64);
   float* S32 = reinterpret_cast<float*>(ws + L.S32);
+  double* Wk = reinterpret_cast<double*>(ws + L.Wk);
   double* pk = reinterpret_cast<double*>(ws + L.pk);
   double* lg = reinterpret_cast<double*>(ws + L.log);
   int32_t* perm = reinterpret_cast<int32_t*>(ws + L.perm);
@@ -499,8 +501,6 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   double* coef = reinterpret_cast<double*>(ws + L.coef);
   int32_t* conv = reinterpret_cast<int32_t*>(ws + L.conv);
   const bool dbl = std::is_same<T, double>::value;
-  // S of the row products: FP32 rounding of the FP64 small result, or FP64 itself
-  const T* Smat = dbl ? reinterpret_cast<const T*>(S64) : reinterpret_cast<const T*>(S32);
   T* V = static_cast<T*>(a.V);
   const T* V0 = static_cast<const T*>(a.V0);
   const int B = P.hb.B;
@@ -513,9 +513,6 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                        a.val, b_hi);
 
   for (WaveTables& w : P.waves) {
-    const size_t lds_chol = size_t(3 * w.max_q + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
-    const bool chol_lds = lds_chol <= (size_t)P.lds_max;
-    const size_t lds_chol_use = chol_lds ? lds_chol : size_t(3 * w.max_q) * 8;
     const size_t lds_jac = size_t(4 * (w.max_q / 2) + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
     const bool jac_lds = lds_jac <= (size_t)P.lds_max;
     const size_t lds_jac_use = jac_lds ? lds_jac : size_t(4 * (w.max_q / 2)) * 8;
@@ -529,8 +526,12 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       X = V;
     }
     int xslab = -1;  // slab holding X (-1: X lives in V0 / V)
+    auto chol = [&](float* s32) {
+      launch_chol_blk(w.sd, w.nb, G, Wk, Rinv, s32, a.status, w.max_ld, P.lds_max, s);
+    };
     for (int t = 0; t < w.T; ++t) {
       const bool last = t == w.T - 1;
+      const bool rr_now = last || prm.rr_every;
       int ycur = -1;
       for (int pass = 0; pass < w.passes; ++pass) {
         hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
@@ -552,47 +553,61 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           // span-preserving Cholesky-QR between passes
           launch_gram<T>(w.gt, w.n_gt, w.tall, slab[ycur], slab[ycur], nullptr, part, s);
           launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
-          launch_chol_inv(w.sd, w.nb, G, Rinv, dbl ? nullptr : S32, pk, a.status, chol_lds,
-                          lds_chol_use, s);
+          chol(dbl ? nullptr : S32);
           int dst = -1;
           for (int i = 0; i < 4; ++i)
             if (i != ycur && i != xslab) dst = i;
-          if (dbl)
-            launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
-                                reinterpret_cast<const T*>(Rinv), w.tall, slab[dst], w.nch, s);
-          else
-            launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
-                                reinterpret_cast<const T*>(S32), w.tall, slab[dst], w.nch, s);
+          launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
+                              dbl ? reinterpret_cast<const T*>(Rinv)
+                                  : reinterpret_cast<const T*>(S32),
+                              w.tall, slab[dst], w.nch, s);
           X = slab[dst];
           xslab = dst;
         }
       }
-      // Rayleigh-Ritz on span(Y)
       T* Y = slab[ycur];
       int wsl = -1;
       for (int i = 0; i < 4; ++i)
         if (i != ycur) wsl = i;
       T* Wm = slab[wsl];
+      // W = L Y;  G = Y^T Y, H = Y^T W (one dual Gram pass);  R^T R = G
       launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
                      L.coef_stride, w.m, s);
       launch_gram<T>(w.gt, w.n_gt, w.tall, Y, Y, Wm, part, s);
       launch_gram_reduce(w.gr, w.n_gr, w.small, part, true, G, H, s);
-      launch_chol_inv(w.sd, w.nb, G, Rinv, nullptr, pk, a.status, chol_lds, lds_chol_use, s);
-      // A = Rinv^T (H Rinv)
+      // T1 = H Rinv
+      if (!rr_now) {
+        // intermediate iteration: Cholesky-QR of Y; the filter's lower bound
+        // follows the largest Rayleigh quotient of the new basis
+        chol(dbl ? nullptr : S32);
+        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
+        if (prm.adapt) launch_rq_max(w.sd, w.nb, Rinv, T1, a_lo, s);
+        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small,
+                            dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
+                            w.tall, V, w.nch, s);
+        X = V;
+        xslab = -1;
+        continue;
+      }
+      // Rayleigh-Ritz: A = Rinv^T H Rinv = Z Theta Z^T,  V = Y Rinv Z
+      chol(nullptr);
       launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
       launch_gram<double>(w.gts, w.n_gts, w.small, Rinv, T1, nullptr, part, s);
       launch_gram_reduce(w.grs, w.n_grs, w.small, part, false, Am, nullptr, s);
       launch_jacobi_init(w.sd, w.nb, Am, pk, Z, conv, s);
+      // the last iteration gets the requested tolerance; intermediate ones
+      // (rr_every) only need a roughly Ritz-ordered basis of the span
+      const double jtol = last ? prm.jacobi_tol : std::max(prm.jacobi_tol, 1e-8);
       for (int sw = 0; sw < prm.max_sweeps; ++sw) {
-        launch_jacobi_sweep(w.sd, w.nb, pk, lg, conv, prm.jacobi_tol, jac_lds, lds_jac_use, s);
-        launch_apply_rot(w.sd, w.nb, w.max_q, lg, conv, Z, s);
+        launch_jacobi_sweep(w.sd, w.nb, pk, lg, conv, jtol, jac_lds, lds_jac_use, s);
+        launch_apply_rot(w.sd, w.nb, w.max_q, lg, conv, Z, P.lds_max, s);
       }
-      launch_rr_finish(w.sd, w.nb, pk, conv, a.ritz, perm, a_lo, prm.adapt, a.status, s);
+      launch_rr_finish(w.sd, w.nb, pk, conv, a.ritz, perm, a_lo, prm.adapt, a.status,
+                       std::max(1e-10, 10.0 * jtol), s);
       launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S64, w.nchs, s);
       // S <- columns of Rinv Z in ascending Ritz order (FP32 copy for FP32 products)
       launch_perm_cast(w.sd, w.nb, S64, perm, dbl ? nullptr : S32, dbl ? T1 : nullptr, s);
       const T* Sm = dbl ? reinterpret_cast<const T*>(T1) : reinterpret_cast<const T*>(S32);
-      (void)Smat;
       T* dstV;
       int dslab = -1;
       if (!last) {
@@ -611,8 +626,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         // every leading column set, hence the Ritz order)
         launch_gram<T>(w.gt, w.n_gt, w.tall, dstV, dstV, nullptr, part, s);
         launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
-        launch_chol_inv(w.sd, w.nb, G, Rinv, dbl ? nullptr : S32, pk, a.status, chol_lds,
-                        lds_chol_use, s);
+        chol(dbl ? nullptr : S32);
         launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, dstV, w.small,
                             dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
                             w.tall, V, w.nch, s);
@@ -642,6 +656,7 @@ static mi_status check_params(const mi_oi_params* prm) {
   MI_CHECK_ARG(prm->passes >= 1 && prm->passes0 >= 1, "passes must be >= 1");
   MI_CHECK_ARG(prm->max_sweeps >= 1 && prm->max_sweeps <= 100, "max_sweeps out of range");
   MI_CHECK_ARG(prm->a_mode >= 0 && prm->a_mode <= 2, "a_mode unknown");
+  MI_CHECK_ARG(prm->rr_every == 0 || prm->rr_every == 1, "rr_every must be 0 or 1");
   MI_CHECK_ARG(prm->jacobi_tol > 0 && prm->jacobi_tol < 1e-3, "jacobi_tol out of range");
   return MI_OK;
 }

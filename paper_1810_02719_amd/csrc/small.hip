@@ -8,9 +8,8 @@
 
 namespace mis {
 
-__device__ inline int64_t pidx(int i, int j, int q) {  // i <= j
-  return int64_t(i) * q - (int64_t(i) * (i + 1)) / 2 + j;
-}
+// Packed upper-triangle index (i <= j); q <= 1024 keeps it in 32 bits.
+__device__ __forceinline__ int pidx(int i, int j, int q) { return i * q - ((i * (i + 1)) >> 1) + j; }
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -24,23 +23,30 @@ __device__ inline double wave_max(double v) {
 
 // ------------------------------------------------------------------ Cholesky + inverse
 // G -> column scaling D = diag(G)^-1/2, G^ = D G D = R^^T R^ (right-looking,
-// pivots below piv_tol are raised to piv_tol and flagged), X = R^^-1 in
-// place, Rinv = D X.
+// one barrier per step: the wave that owns row k+1 finishes its last update,
+// takes the pivot from lane 0 by a shuffle and scales the row; pivots below
+// piv_tol are raised to piv_tol and flagged), X = R^^-1 in place column by
+// column, Rinv = D X.  LDS selects the storage of the packed factor (typed
+// LDS pointer when true, the per-block global scratch when false).
+template <bool LDS>
 __global__ void __launch_bounds__(SMALL_THREADS)
     k_chol_inv(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
                double* __restrict__ Rinv, float* __restrict__ S32, double* __restrict__ pks,
-               int32_t* __restrict__ status, int use_lds) {
+               int32_t* __restrict__ status) {
   extern __shared__ double smem[];
   __shared__ int flag;
   const SmallDesc d = sds[blockIdx.x];
-  const int p = d.p, ld = d.ld;
+  const int p = d.p, ld = d.ld, q = d.q;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = SMALL_THREADS / 64;
-  // dynamic LDS: [dsc | rdiag | tmp] (3 * pmax) then, in LDS mode, the packed factor
   double* dsc = smem;
-  double* rdiag = smem + d.q;
-  double* tmp = smem + 2 * d.q;
-  double* W = use_lds ? smem + 3 * d.q : pks + d.pk_off;
+  double* rdiag = smem + q;
+  double* tmp = smem + 2 * q;
+  double* W;
+  if constexpr (LDS)
+    W = smem + 3 * q;
+  else
+    W = pks + d.pk_off;
   const double* Gb = G + d.m_off;
   const double piv_tol = 1e-13;
   if (tid == 0) flag = 0;
@@ -52,35 +58,50 @@ __global__ void __launch_bounds__(SMALL_THREADS)
     dsc[i] = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 0.0;
   }
   __syncthreads();
-  for (int i = wave; i < p; i += NW)
+  for (int i = wave; i < p; i += NW) {
+    const double di = dsc[i];
     for (int j = i + lane; j < p; j += 64)
-      W[pidx(i, j, p)] = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
+      W[pidx(i, j, p)] = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * di * dsc[j];
+  }
   __syncthreads();
-  for (int k = 0; k < p; ++k) {
-    double wkk = W[pidx(k, k, p)];
-    if (!(wkk > piv_tol)) {
-      if (tid == 0) atomicOr(&flag, isfinite(wkk) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
-      wkk = piv_tol;
-    }
-    const double rkk = sqrt(wkk), inv = 1.0 / rkk;
-    if (tid == 0) rdiag[k] = rkk;
-    for (int j = k + 1 + tid; j < p; j += SMALL_THREADS) W[pidx(k, j, p)] *= inv;
-    __syncthreads();
+  // row 0: unit pivot after scaling
+  if (wave == 0) {
+    if (lane == 0) rdiag[0] = 1.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < p - 1; ++k) {
+    const int rk = pidx(k, 0, p);  // row k starts at rk + k
     for (int i = k + 1 + wave; i < p; i += NW) {
-      const double wki = W[pidx(k, i, p)];
-      for (int j = i + lane; j < p; j += 64) W[pidx(i, j, p)] -= wki * W[pidx(k, j, p)];
+      const double wki = W[rk + i];
+      const int ri = pidx(i, 0, p);
+      double piv = 0.0;
+      for (int j = i + lane; j < p; j += 64) {
+        const double v = W[ri + j] - wki * W[rk + j];
+        W[ri + j] = v;
+        if (j == i) piv = v;
+      }
+      if (i == k + 1) {  // last update of row k+1: factor it now
+        piv = __shfl(piv, 0, 64);
+        if (!(piv > piv_tol)) {
+          if (lane == 0) atomicOr(&flag, isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
+          piv = piv_tol;
+        }
+        const double rkk = sqrt(piv), inv = 1.0 / rkk;
+        for (int j = i + 1 + lane; j < p; j += 64) W[ri + j] *= inv;
+        if (lane == 0) rdiag[i] = rkk;
+      }
     }
     __syncthreads();
   }
-  // in-place inverse of the upper factor, column by column
+  // in-place inverse of the upper factor, column by column: the diagonal
+  // slot of row i holds X_ii once column i is done, the strict upper part of
+  // column j still holds R^ while column j is being solved
   for (int j = 0; j < p; ++j) {
     const double xjj = 1.0 / rdiag[j];
     for (int i = wave; i < j; i += NW) {
+      const int ri = pidx(i, 0, p);
       double acc = 0.0;
-      for (int l = i + lane; l < j; l += 64) {
-        const double xil = (l == i) ? W[pidx(i, i, p)] : W[pidx(i, l, p)];
-        acc += xil * W[pidx(l, j, p)];
-      }
+      for (int l = i + lane; l < j; l += 64) acc += W[ri + l] * W[pidx(l, j, p)];
       acc = wave_sum(acc);
       if (lane == 0) tmp[i] = acc;
     }
@@ -90,12 +111,14 @@ __global__ void __launch_bounds__(SMALL_THREADS)
     __syncthreads();
   }
   double* Rb = Rinv + d.m_off;
-  for (int64_t e = tid; e < int64_t(ld) * ld; e += SMALL_THREADS) {
-    const int i = int(e / ld), j = int(e % ld);
-    double v = 0.0;
-    if (i < p && j < p && i <= j) v = dsc[i] * W[pidx(i, j, p)];
-    Rb[e] = v;
-    if (S32) S32[d.m_off + e] = (float)v;
+  for (int i = wave; i < ld; i += NW) {
+    const double di = i < p ? dsc[i] : 0.0;
+    for (int j = lane; j < ld; j += 64) {
+      double v = 0.0;
+      if (i < p && j < p && i <= j) v = di * W[pidx(i, j, p)];
+      Rb[int64_t(i) * ld + j] = v;
+      if (S32) S32[d.m_off + int64_t(i) * ld + j] = (float)v;
+    }
   }
   if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
 }
@@ -104,8 +127,464 @@ void launch_chol_inv(const SmallDesc* sd, int nb, const double* G, double* Rinv,
                      double* pk_scratch, int32_t* status, bool lds, size_t lds_bytes,
                      hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_chol_inv, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, G, Rinv, S32,
-                     pk_scratch, status, lds ? 1 : 0);
+  if (lds)
+    hipLaunchKernelGGL(k_chol_inv<true>, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, G, Rinv,
+                       S32, pk_scratch, status);
+  else
+    hipLaunchKernelGGL(k_chol_inv<false>, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, G, Rinv,
+                       S32, pk_scratch, status);
+}
+
+// ------------------------------------------------------------------ blocked Cholesky + inverse
+// Same result as k_chol_inv with 32-wide panels, so that only the 32 x 32
+// diagonal tiles are factored step by step (inside one wavefront, one tile
+// column per lane in registers, pivots and row entries broadcast by
+// shuffles); the panel solves, trailing updates and the blocked inverse are
+// parallel phases separated by ~40 barriers in total.  The working matrix
+// lives in global memory (L2-resident, ld x ld per block), the current panel
+// in LDS when PLDS.  Diagonal tiles of the working matrix end up holding the
+// inverted tiles X_JJ; afterwards the off-diagonal blocks of X = R^^-1 are
+// formed column block by column block in place.
+constexpr int CB = 32;
+
+template <bool PLDS>
+__global__ void __launch_bounds__(256)
+    k_chol_blk(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
+               double* __restrict__ Wk, double* __restrict__ Rinv, float* __restrict__ S32,
+               int32_t* __restrict__ status) {
+  extern __shared__ double dyn[];  // PLDS: panel / product scratch, CB x ld
+  __shared__ double dsc[1024];
+  __shared__ double Xt[CB][CB + 1];
+  __shared__ int flag;
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* Gb = G + d.m_off;
+  double* W = Wk + d.m_off;
+  double* P;  // CB x ld scratch
+  if constexpr (PLDS)
+    P = dyn;
+  else
+    P = Rinv + d.m_off;  // rows 0..CB-1 of the output serve as scratch until the end
+  const double piv_tol = 1e-13;
+  if (tid == 0) flag = 0;
+  __syncthreads();
+  for (int i = tid; i < p; i += 256) {
+    const double g = Gb[int64_t(i) * ld + i];
+    if (!isfinite(g)) atomicOr(&flag, MI_BLOCK_NONFINITE);
+    if (!(g > 0.0)) atomicOr(&flag, MI_BLOCK_NOT_PD);
+    dsc[i] = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 0.0;
+  }
+  __syncthreads();
+  for (int i = wave; i < p; i += 4) {
+    const double di = dsc[i];
+    for (int j = i + lane; j < p; j += 64)
+      W[int64_t(i) * ld + j] = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * di * dsc[j];
+  }
+  __syncthreads();
+  const int nbk = (p + CB - 1) / CB;
+  for (int J = 0; J < nbk; ++J) {
+    const int j0 = J * CB, jb = min(CB, p - j0), r0 = j0 + jb;
+    // (a) factor the diagonal tile in wave 0: lane l holds tile column l
+    if (wave == 0) {
+      double c[CB];
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+        c[i] = (lane < jb && i <= lane) ? W[int64_t(j0 + i) * ld + j0 + lane] : 0.0;
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        if (k < jb) {
+          double piv = __shfl(c[k], k, 64);
+          if (!(piv > piv_tol)) {
+            if (lane == 0) atomicOr(&flag, isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
+            piv = piv_tol;
+          }
+          const double r = sqrt(piv), inv = 1.0 / r;
+          if (lane == k)
+            c[k] = r;
+          else if (lane > k)
+            c[k] *= inv;
+#pragma unroll
+          for (int i = k + 1; i < CB; ++i) {
+            const double rki = __shfl(c[k], i, 64);
+            if (lane >= i && i < jb) c[i] -= rki * c[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CB; ++i)
+        if (lane < CB) Xt[i][lane] = (lane < jb && i <= lane) ? c[i] : 0.0;  // R tile, upper
+    }
+    __syncthreads();
+    // (b) invert the tile: thread l < jb back-substitutes column l of X_JJ
+    //     into registers; all reads of R finish before the barrier, the
+    //     writes follow it
+    double xcol[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) xcol[i] = 0.0;
+    if (tid < jb) {
+      const int l = tid;
+#pragma unroll
+      for (int i = CB - 1; i >= 0; --i) {
+        if (i == l) xcol[i] = 1.0 / Xt[l][l];
+        if (i < l) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = i + 1; k < CB; ++k)
+            if (k <= l) acc += Xt[i][k] * xcol[k];
+          xcol[i] = -acc / Xt[i][i];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < CB) {
+#pragma unroll
+      for (int i = 0; i < CB; ++i) Xt[i][tid] = (tid < jb) ? xcol[i] : 0.0;
+    }
+    __syncthreads();
+    // the working matrix's diagonal tile keeps X_JJ for the inverse phase
+    for (int e = tid; e < jb * jb; e += 256) {
+      const int i = e / jb, l = e % jb;
+      if (i <= l) W[int64_t(j0 + i) * ld + j0 + l] = Xt[i][l];
+    }
+    // (c) panel solve R[J, j] = X_JJ^T W[J, j] for j >= r0, into P
+    for (int e = tid; e < jb * (p - r0); e += 256) {
+      const int i = e % jb, j = r0 + e / jb;
+      double acc = 0.0;
+      for (int k = 0; k <= i; ++k) acc += Xt[k][i] * W[int64_t(j0 + k) * ld + j];
+      P[i * ld + j] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < jb * (p - r0); e += 256) {
+      const int i = e / (p - r0), j = r0 + e % (p - r0);
+      W[int64_t(j0 + i) * ld + j] = P[i * ld + j];
+    }
+    // (d) trailing update W[i][j] -= sum_k P[k][i] P[k][j], r0 <= i <= j < p,
+    //     4 x 4 register tiles
+    {
+      const int m = p - r0;
+      const int nt = (m + 3) / 4;
+      for (int e = tid; e < nt * nt; e += 256) {
+        const int ti = e / nt, tj = e % nt;
+        if (tj < ti) continue;
+        const int i0 = r0 + 4 * ti, c0 = r0 + 4 * tj;
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int k = 0; k < jb; ++k) {
+          double pi[4], pj[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            pi[a] = (i0 + a < p) ? P[k * ld + i0 + a] : 0.0;
+            pj[a] = (c0 + a < p) ? P[k * ld + c0 + a] : 0.0;
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pj[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int i = i0 + a, j = c0 + b;
+            if (i < p && j < p && i <= j) W[int64_t(i) * ld + j] -= acc[a][b];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // blocked inverse: X[0:j0, J] = -(X[0:j0, 0:j0] R[0:j0, J]) X_JJ, in place
+  for (int J = 1; J < nbk; ++J) {
+    const int j0 = J * CB, jb = min(CB, p - j0);
+    // M[i][k] = sum_{l=i}^{j0-1} X[i][l] R[l][j0+k]  (into P as [i * CB + k])
+    for (int e = tid; e < j0 * jb; e += 256) {
+      const int i = e / jb, k = e % jb;
+      double acc = 0.0;
+      for (int l = i; l < j0; ++l) acc += W[int64_t(i) * ld + l] * W[int64_t(l) * ld + j0 + k];
+      P[i * CB + k] = acc;
+    }
+    __syncthreads();
+    // X[i][j0+k] = -sum_{k' <= k} M[i][k'] X_JJ[k'][k]
+    for (int e = tid; e < j0 * jb; e += 256) {
+      const int i = e / jb, k = e % jb;
+      double acc = 0.0;
+      for (int k2 = 0; k2 <= k; ++k2) acc += P[i * CB + k2] * W[int64_t(j0 + k2) * ld + j0 + k];
+      W[int64_t(i) * ld + j0 + k] = -acc;
+    }
+    __syncthreads();
+  }
+  double* Rb = Rinv + d.m_off;
+  for (int i = wave; i < ld; i += 4) {
+    const double di = i < p ? dsc[i] : 0.0;
+    for (int j = lane; j < ld; j += 64) {
+      double v = 0.0;
+      if (i < p && j < p && i <= j) v = di * W[int64_t(i) * ld + j];
+      Rb[int64_t(i) * ld + j] = v;
+      if (S32) S32[d.m_off + int64_t(i) * ld + j] = (float)v;
+    }
+  }
+  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
+}
+
+
+// ------------------------------------------------------------------ register Cholesky + inverse
+// For ld <= 32 RT: the p x p matrix lives in the registers of 1024 threads
+// laid out as a 32 x 32 grid; thread (tr, tc) owns the entries
+// (tr + 32 a, tc + 32 b), a, b < RT.  Right-looking Cholesky of the scaled
+// Gram, then X = R^-1 by Gauss-Jordan elimination from the bottom.  Each
+// step needs one barrier: the row that becomes the next pivot row lives in
+// one half-wavefront, which finishes its own update, takes the pivot by a
+// shuffle, scales the row and publishes it in a double-buffered LDS row.
+template <int RT>
+__global__ void __launch_bounds__(1024)
+    k_chol_reg(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
+               double* __restrict__ Wk, double* __restrict__ Rinv, float* __restrict__ S32,
+               int32_t* __restrict__ status) {
+  constexpr int LDM = 32 * RT;
+  __shared__ double dsc[LDM];
+  __shared__ double rdiag[LDM];
+  __shared__ double rowbuf[2][LDM];
+  __shared__ double colbuf[2][LDM];
+  __shared__ int flag;
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  const int hl = (tr & 1) * 32;  // first lane of this thread's half-wavefront
+  const double* Gb = G + d.m_off;
+  double* Rg = Wk + d.m_off;  // R spilled to global for the inverse phase
+  const double piv_tol = 1e-13;
+  if (tid == 0) flag = 0;
+  for (int i = tid; i < LDM; i += 1024) {
+    double v = 0.0;
+    if (i < p) {
+      const double g = Gb[int64_t(i) * ld + i];
+      if (!isfinite(g)) atomicOr(&flag, MI_BLOCK_NONFINITE);
+      if (!(g > 0.0)) atomicOr(&flag, MI_BLOCK_NOT_PD);
+      v = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 0.0;
+    }
+    dsc[i] = v;
+  }
+  __syncthreads();
+  double w[RT][RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      double v = 0.0;
+      if (i < p && j < p && i <= j)
+        v = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
+      w[a][b] = v;
+    }
+  // row 0 (unit pivot after scaling) is already R's row 0
+  if (tr == 0) {
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int j = tc + 32 * b;
+      rowbuf[0][j] = (j < p) ? w[0][b] : 0.0;
+    }
+    if (tc == 0) rdiag[0] = 1.0;
+  }
+  for (int k = 0; k < p; ++k) {
+    __syncthreads();
+    const double* rb = rowbuf[k & 1];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int i = tr + 32 * a;
+      if (i > k && i < p) {
+        const double ri = rb[i];
+#pragma unroll
+        for (int b = 0; b < RT; ++b) {
+          const int j = tc + 32 * b;
+          if (j >= i && j < p) w[a][b] -= ri * rb[j];
+        }
+      }
+    }
+    const int k1 = k + 1;
+    if (k1 < p && tr == (k1 & 31)) {
+      const int a1 = k1 >> 5;
+      double mine = 0.0;
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int b = 0; b < RT; ++b)
+          if (a == a1 && b == a1) mine = w[a][b];
+      double piv = __shfl(mine, hl + (k1 & 31), 64);
+      if (!(piv > piv_tol)) {
+        if (tc == 0) atomicOr(&flag, isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
+        piv = piv_tol;
+      }
+      const double r = sqrt(piv), inv = 1.0 / r;
+      double* nb = rowbuf[k1 & 1];
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+        if (a == a1) {
+#pragma unroll
+          for (int b = 0; b < RT; ++b) {
+            const int j = tc + 32 * b;
+            if (j == k1) w[a][b] = r;
+            else if (j > k1 && j < p) w[a][b] *= inv;
+            nb[j] = (j > k1 && j < p) ? w[a][b] : 0.0;
+          }
+        }
+      if (tc == 0) rdiag[k1] = r;
+    }
+  }
+  // R (upper, scaled) -> global scratch for the column broadcasts below
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      if (i < ld && j < ld) Rg[int64_t(i) * ld + j] = (i < p && j < p && i <= j) ? w[a][b] : 0.0;
+    }
+  __threadfence_block();
+  __syncthreads();
+  // Gauss-Jordan from the bottom: X <- I; at step k row k of X is final:
+  // scale it by 1/R_kk, then X[i][:] -= R[i][k] X[k][:] for i < k.
+  double x[RT][RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      x[a][b] = (i == j && i < p) ? 1.0 : 0.0;
+    }
+  {
+    const int k = p - 1;
+    if (tr == (k & 31)) {
+      const int ak = k >> 5;
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+        if (a == ak) {
+#pragma unroll
+          for (int b = 0; b < RT; ++b) {
+            const int j = tc + 32 * b;
+            if (j == k) x[a][b] = 1.0 / rdiag[k];
+            rowbuf[k & 1][j] = (j >= k && j < p) ? x[a][b] : 0.0;
+          }
+        }
+    }
+    if (tc == (k & 31))
+      for (int a = 0; a < RT; ++a) {
+        const int i = tr + 32 * a;
+        colbuf[k & 1][i] = (i < k) ? Rg[int64_t(i) * ld + k] : 0.0;
+      }
+  }
+  for (int k = p - 1; k >= 0; --k) {
+    __syncthreads();
+    const double* xb = rowbuf[k & 1];
+    const double* cb = colbuf[k & 1];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int i = tr + 32 * a;
+      if (i < k) {
+        const double rik = cb[i];
+#pragma unroll
+        for (int b = 0; b < RT; ++b) {
+          const int j = tc + 32 * b;
+          if (j >= k && j < p) x[a][b] -= rik * xb[j];
+        }
+      }
+    }
+    const int km = k - 1;
+    if (km >= 0) {
+      if (tr == (km & 31)) {  // row k-1 is final now: scale and publish it
+        const int ak = km >> 5;
+        const double inv = 1.0 / rdiag[km];
+        double* nb = rowbuf[km & 1];
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+          if (a == ak) {
+#pragma unroll
+            for (int b = 0; b < RT; ++b) {
+              const int j = tc + 32 * b;
+              if (j >= km && j < p) x[a][b] *= inv;
+              nb[j] = (j >= km && j < p) ? x[a][b] : 0.0;
+            }
+          }
+      }
+      if (tc == (km & 31)) {  // column k-1 of R
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          const int i = tr + 32 * a;
+          colbuf[km & 1][i] = (i < km) ? Rg[int64_t(i) * ld + km] : 0.0;
+        }
+      }
+    }
+  }
+  double* Rb = Rinv + d.m_off;
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      if (i < ld && j < ld) {
+        const double v = (i < p && j < p && i <= j) ? dsc[i] * x[a][b] : 0.0;
+        Rb[int64_t(i) * ld + j] = v;
+        if (S32) S32[d.m_off + int64_t(i) * ld + j] = (float)v;
+      }
+    }
+  // zero the rest of the ld x ld output when ld is not a multiple of 32 * RT
+  for (int e = tid; e < ld * ld; e += 1024) {
+    const int i = e / ld, j = e % ld;
+    if (i >= LDM || j >= LDM) {
+      Rb[e] = 0.0;
+      if (S32) S32[d.m_off + e] = 0.0f;
+    }
+  }
+  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
+}
+
+void launch_chol_blk(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
+                     float* S32, int32_t* status, int max_ld, int lds_max, hipStream_t s) {
+  if (nb <= 0) return;
+  switch ((max_ld + 31) / 32) {  // register-resident variant for ld <= 192
+    case 1: hipLaunchKernelGGL(k_chol_reg<1>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
+    case 2: hipLaunchKernelGGL(k_chol_reg<2>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
+    case 3: hipLaunchKernelGGL(k_chol_reg<3>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
+    case 4: hipLaunchKernelGGL(k_chol_reg<4>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
+    case 5: hipLaunchKernelGGL(k_chol_reg<5>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
+    case 6: hipLaunchKernelGGL(k_chol_reg<6>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
+    default: break;
+  }
+  const size_t pl = size_t(CB) * max_ld * sizeof(double);
+  if (pl <= size_t(lds_max) - 40000)
+    hipLaunchKernelGGL(k_chol_blk<true>, dim3(nb), dim3(256), pl, s, sd, G, Wk, Rinv, S32, status);
+  else
+    hipLaunchKernelGGL(k_chol_blk<false>, dim3(nb), dim3(256), 0, s, sd, G, Wk, Rinv, S32, status);
+}
+
+// a[blk] = max_j (Rinv^T H Rinv)_jj = max_j sum_{i<=j} Rinv[i][j] T1[i][j] with
+// T1 = H Rinv: the largest Rayleigh quotient of the Cholesky-QR basis (a
+// lower estimate of the top Ritz value, used as the filter's lower bound).
+__global__ void __launch_bounds__(256)
+    k_rq_max(const SmallDesc* __restrict__ sds, const double* __restrict__ Rinv,
+             const double* __restrict__ T1, double* __restrict__ a_lo) {
+  __shared__ double red[4];
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const double* R = Rinv + d.m_off;
+  const double* T = T1 + d.m_off;
+  double mx = -1e308;
+  for (int j = threadIdx.x; j < p; j += 256) {
+    double s = 0.0;
+    for (int i = 0; i <= j; ++i) s += R[int64_t(i) * ld + j] * T[int64_t(i) * ld + j];
+    mx = fmax(mx, s);
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) a_lo[d.blk] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+void launch_rq_max(const SmallDesc* sd, int nb, const double* Rinv, const double* T1,
+                   double* a_lo, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_rq_max, dim3(nb), dim3(256), 0, s, sd, Rinv, T1, a_lo);
 }
 
 // ------------------------------------------------------------------ Jacobi
@@ -137,12 +616,13 @@ void launch_jacobi_init(const SmallDesc* sd, int nb, const double* A, double* pk
 
 // One sweep.  Round r pairs slot k with slot q-1-k of the circle
 // arrangement; every 2x2 "pair block" A[{p_K,q_K},{p_K',q_K'}] is updated by
-// exactly one thread as J_K^T M J_K' (J = [[c, s], [-s, c]]), the diagonal
-// pair blocks by the closed form that zeroes their off-diagonal entry.
+// exactly one lane as J_K^T M J_K' (J = [[c, s], [-s, c]]), the diagonal pair
+// blocks by the closed form that zeroes their off-diagonal entry.  Waves own
+// pair rows K, lanes walk K' >= K (no integer division in the loop).
+template <bool LDS>
 __global__ void __launch_bounds__(SMALL_THREADS)
     k_jacobi_sweep(const SmallDesc* __restrict__ sds, double* __restrict__ pk,
-                   double* __restrict__ logbuf, int32_t* __restrict__ conv, double tol,
-                   int use_lds) {
+                   double* __restrict__ logbuf, int32_t* __restrict__ conv, double tol) {
   extern __shared__ double smem[];
   __shared__ double red[SMALL_THREADS / 64];
   __shared__ double s_thresh;
@@ -150,32 +630,36 @@ __global__ void __launch_bounds__(SMALL_THREADS)
   if (conv[d.blk]) return;
   const int q = d.q, h = q / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t npk = int64_t(q) * (q + 1) / 2;
-  // dynamic LDS: rotation cosines, sines, tangents, pair indices, then (LDS
-  // mode) the packed matrix
+  constexpr int NW = SMALL_THREADS / 64;
+  const int npk = (q * (q + 1)) / 2;
   double* rc = smem;
   double* rs = smem + h;
   double* rt = smem + 2 * h;
   int* pp = reinterpret_cast<int*>(smem + 3 * h);
   int* qq = pp + h;
   double* gP = pk + d.pk_off;
-  double* A = use_lds ? smem + 3 * h + h : gP;
-  if (use_lds)
-    for (int64_t e = tid; e < npk; e += SMALL_THREADS) A[e] = gP[e];
+  double* A;
+  if constexpr (LDS) {
+    A = smem + 4 * h;
+    for (int e = tid; e < npk; e += SMALL_THREADS) A[e] = gP[e];
+  } else {
+    A = gP;
+  }
   __syncthreads();
-  // Frobenius norm of the packed symmetric matrix
   double f = 0.0;
-  for (int i = wave; i < q; i += SMALL_THREADS / 64)
+  for (int i = wave; i < q; i += NW) {
+    const int ri = pidx(i, 0, q);
     for (int j = i + lane; j < q; j += 64) {
-      const double v = A[pidx(i, j, q)];
+      const double v = A[ri + j];
       f += (i == j) ? v * v : 2.0 * v * v;
     }
+  }
   f = wave_sum(f);
   if (lane == 0) red[wave] = f;
   __syncthreads();
   if (tid == 0) {
     double t = 0.0;
-    for (int w = 0; w < SMALL_THREADS / 64; ++w) t += red[w];
+    for (int w = 0; w < NW; ++w) t += red[w];
     s_thresh = tol * sqrt(t);
   }
   __syncthreads();
@@ -184,7 +668,7 @@ __global__ void __launch_bounds__(SMALL_THREADS)
   double* lg = logbuf + d.log_off;
   for (int r = 0; r < q - 1; ++r) {
     for (int k = tid; k < h; k += SMALL_THREADS) {
-      int a = rr_index(k, r, q), b = rr_index(q - 1 - k, r, q);
+      const int a = rr_index(k, r, q), b = rr_index(q - 1 - k, r, q);
       const int lo = min(a, b), hi = max(a, b);
       const double app = A[pidx(lo, lo, q)], aqq = A[pidx(hi, hi, q)], apq = A[pidx(lo, hi, q)];
       double c = 1.0, s = 0.0, t = 0.0;
@@ -200,34 +684,44 @@ __global__ void __launch_bounds__(SMALL_THREADS)
       rt[k] = t;
       pp[k] = lo;
       qq[k] = hi;
-      lg[(int64_t(r) * h + k) * 2] = c;
-      lg[(int64_t(r) * h + k) * 2 + 1] = s;
+      lg[(r * h + k) * 2] = c;
+      lg[(r * h + k) * 2 + 1] = s;
     }
     __syncthreads();
-    for (int e = tid; e < h * h; e += SMALL_THREADS) {
-      const int K = e / h, K2 = e - K * h;
-      if (K2 < K) continue;
-      const double t1 = rt[K], t2 = rt[K2];
-      if (t1 == 0.0 && t2 == 0.0) continue;
-      if (K == K2) {
-        const int lo = pp[K], hi = qq[K];
-        const double apq = A[pidx(lo, hi, q)];
-        A[pidx(lo, lo, q)] -= t1 * apq;
-        A[pidx(hi, hi, q)] += t1 * apq;
-        A[pidx(lo, hi, q)] = 0.0;
-        continue;
+    // lanes own pair columns K2 (their rotation data stays in registers),
+    // waves walk the pair rows K <= K2
+    for (int K2b = 0; K2b < h; K2b += 64) {
+      const int K2 = K2b + lane;
+      const bool live2 = K2 < h;
+      const double t2 = live2 ? rt[K2] : 0.0;
+      const double c2 = live2 ? rc[K2] : 1.0, s2 = live2 ? rs[K2] : 0.0;
+      const int y0 = live2 ? pp[K2] : 0, y1 = live2 ? qq[K2] : 0;
+      for (int K = wave; K < min(h, K2b + 64); K += NW) {
+        if (!live2 || K > K2) continue;
+        const double t1 = rt[K];
+        if (t1 == 0.0 && t2 == 0.0) continue;
+        const int x0 = pp[K], x1 = qq[K];
+        if (K2 == K) {
+          const int i01 = pidx(x0, x1, q);
+          const double apq = A[i01];
+          A[pidx(x0, x0, q)] -= t1 * apq;
+          A[pidx(x1, x1, q)] += t1 * apq;
+          A[i01] = 0.0;
+          continue;
+        }
+        const double c1 = rc[K], s1 = rs[K];
+        const int i00 = x0 < y0 ? pidx(x0, y0, q) : pidx(y0, x0, q);
+        const int i01 = x0 < y1 ? pidx(x0, y1, q) : pidx(y1, x0, q);
+        const int i10 = x1 < y0 ? pidx(x1, y0, q) : pidx(y0, x1, q);
+        const int i11 = x1 < y1 ? pidx(x1, y1, q) : pidx(y1, x1, q);
+        const double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
+        const double n00 = c2 * m00 - s2 * m01, n01 = s2 * m00 + c2 * m01;
+        const double n10 = c2 * m10 - s2 * m11, n11 = s2 * m10 + c2 * m11;
+        A[i00] = c1 * n00 - s1 * n10;
+        A[i10] = s1 * n00 + c1 * n10;
+        A[i01] = c1 * n01 - s1 * n11;
+        A[i11] = s1 * n01 + c1 * n11;
       }
-      const int x0 = pp[K], x1 = qq[K], y0 = pp[K2], y1 = qq[K2];
-      const int64_t i00 = pidx(min(x0, y0), max(x0, y0), q), i01 = pidx(min(x0, y1), max(x0, y1), q);
-      const int64_t i10 = pidx(min(x1, y0), max(x1, y0), q), i11 = pidx(min(x1, y1), max(x1, y1), q);
-      const double m00 = A[i00], m01 = A[i01], m10 = A[i10], m11 = A[i11];
-      const double c1 = rc[K], s1 = rs[K], c2 = rc[K2], s2 = rs[K2];
-      const double n00 = c2 * m00 - s2 * m01, n01 = s2 * m00 + c2 * m01;
-      const double n10 = c2 * m10 - s2 * m11, n11 = s2 * m10 + c2 * m11;
-      A[i00] = c1 * n00 - s1 * n10;
-      A[i10] = s1 * n00 + c1 * n10;
-      A[i01] = c1 * n01 - s1 * n11;
-      A[i11] = s1 * n01 + c1 * n11;
     }
     __syncthreads();
   }
@@ -236,26 +730,34 @@ __global__ void __launch_bounds__(SMALL_THREADS)
   __syncthreads();
   if (tid == 0) {
     double mx = 0.0;
-    for (int w = 0; w < SMALL_THREADS / 64; ++w) mx = fmax(mx, red[w]);
+    for (int w = 0; w < NW; ++w) mx = fmax(mx, red[w]);
     // a sweep that found nothing above the threshold rotated nothing
     if (!(mx > thresh)) conv[d.blk] = 1;
   }
-  if (use_lds)
-    for (int64_t e = tid; e < npk; e += SMALL_THREADS) gP[e] = A[e];
+  if constexpr (LDS)
+    for (int e = tid; e < npk; e += SMALL_THREADS) gP[e] = A[e];
 }
 
 void launch_jacobi_sweep(const SmallDesc* sd, int nb, double* pk, double* log, int32_t* conv,
                          double tol, bool lds, size_t lds_bytes, hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_jacobi_sweep, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, pk, log, conv,
-                     tol, lds ? 1 : 0);
+  if (lds)
+    hipLaunchKernelGGL(k_jacobi_sweep<true>, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, pk, log,
+                       conv, tol);
+  else
+    hipLaunchKernelGGL(k_jacobi_sweep<false>, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, pk,
+                       log, conv, tol);
 }
 
-// Z <- Z J_1 ... J_R (the rotations of one sweep), ZROWS rows per workgroup.
-constexpr int ZROWS = 8;
+// Z <- Z J_1 ... J_R (the rotations of one sweep), zrows rows per
+// workgroup (32, or fewer when q is large, to fit LDS).  The log is staged
+// through LDS RCH rounds at a time with coalesced loads; lane groups of zrows
+// threads share one rotation and apply it to their rows.
+constexpr int RCH = 16;
 __global__ void __launch_bounds__(256)
     k_apply_rot(const SmallDesc* __restrict__ sds, const double* __restrict__ logbuf,
-                const int32_t* __restrict__ conv, double* __restrict__ Z, int groups_per_block) {
+                const int32_t* __restrict__ conv, double* __restrict__ Z, int groups_per_block,
+                int ZROWS) {
   extern __shared__ double zs[];
   const int bi = blockIdx.x / groups_per_block, g = blockIdx.x % groups_per_block;
   const SmallDesc d = sds[bi];
@@ -265,38 +767,51 @@ __global__ void __launch_bounds__(256)
   if (row0 >= q) return;
   const int nr = min(ZROWS, q - row0);
   const int zl = q + 1;
+  double* lgs = zs + ZROWS * zl;  // RCH rounds of (c, s) pairs
   double* Zb = Z + d.m_off;
-  for (int e = threadIdx.x; e < nr * q; e += 256) {
-    const int rr = e / q, cc = e % q;
-    zs[rr * zl + cc] = Zb[int64_t(row0 + rr) * ld + cc];
-  }
-  __syncthreads();
+  for (int rr = threadIdx.x / 64; rr < nr; rr += 4)
+    for (int cc = threadIdx.x % 64; cc < q; cc += 64)
+      zs[rr * zl + cc] = Zb[int64_t(row0 + rr) * ld + cc];
   const double* lg = logbuf + d.log_off;
-  for (int r = 0; r < q - 1; ++r) {
-    for (int e = threadIdx.x; e < nr * h; e += 256) {
-      const int rr = e / h, k = e % h;
-      const double c = lg[(int64_t(r) * h + k) * 2], s = lg[(int64_t(r) * h + k) * 2 + 1];
-      if (s == 0.0) continue;
-      const int a = rr_index(k, r, q), b = rr_index(q - 1 - k, r, q);
-      const int lo = min(a, b), hi = max(a, b);
-      const double x = zs[rr * zl + lo], y = zs[rr * zl + hi];
-      zs[rr * zl + lo] = c * x - s * y;
-      zs[rr * zl + hi] = s * x + c * y;
-    }
+  const int rr = threadIdx.x % ZROWS, kg = threadIdx.x / ZROWS;
+  const int KG = 256 / ZROWS;
+  for (int r0 = 0; r0 < q - 1; r0 += RCH) {
+    const int nch = min(RCH, q - 1 - r0);
     __syncthreads();
+    for (int e = threadIdx.x; e < nch * h * 2; e += 256) lgs[e] = lg[int64_t(r0) * h * 2 + e];
+    __syncthreads();
+    for (int rl = 0; rl < nch; ++rl) {
+      const int r = r0 + rl;
+      if (rr < nr) {
+        for (int k = kg; k < h; k += KG) {
+          const double s = lgs[(rl * h + k) * 2 + 1];
+          if (s == 0.0) continue;
+          const double c = lgs[(rl * h + k) * 2];
+          const int a = rr_index(k, r, q), b = rr_index(q - 1 - k, r, q);
+          const int lo = min(a, b), hi = max(a, b);
+          const double x = zs[rr * zl + lo], y = zs[rr * zl + hi];
+          zs[rr * zl + lo] = c * x - s * y;
+          zs[rr * zl + hi] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+    }
   }
-  for (int e = threadIdx.x; e < nr * q; e += 256) {
-    const int rr = e / q, cc = e % q;
-    Zb[int64_t(row0 + rr) * ld + cc] = zs[rr * zl + cc];
-  }
+  for (int r2 = threadIdx.x / 64; r2 < nr; r2 += 4)
+    for (int cc = threadIdx.x % 64; cc < q; cc += 64)
+      Zb[int64_t(row0 + r2) * ld + cc] = zs[r2 * zl + cc];
 }
 
-void launch_apply_rot(const SmallDesc* sd, int nb, int max_ld, const double* log,
-                      const int32_t* conv, double* Z, hipStream_t s) {
+void launch_apply_rot(const SmallDesc* sd, int nb, int max_q, const double* log,
+                      const int32_t* conv, double* Z, int lds_max, hipStream_t s) {
   if (nb <= 0) return;
-  const int gpb = ceil_div(max_ld, ZROWS);
-  const size_t lds = size_t(ZROWS) * (max_ld + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_apply_rot, dim3(nb * gpb), dim3(256), lds, s, sd, log, conv, Z, gpb);
+  const size_t logb = size_t(RCH) * (max_q / 2) * 2 * sizeof(double);
+  int zrows = 32;
+  while (zrows > 1 && size_t(zrows) * (max_q + 1) * sizeof(double) + logb > size_t(lds_max))
+    zrows /= 2;
+  const int gpb = ceil_div(max_q, zrows);
+  const size_t lds = size_t(zrows) * (max_q + 1) * sizeof(double) + logb;
+  hipLaunchKernelGGL(k_apply_rot, dim3(nb * gpb), dim3(256), lds, s, sd, log, conv, Z, gpb, zrows);
 }
 
 // ------------------------------------------------------------------ Ritz ordering
@@ -304,7 +819,7 @@ __global__ void __launch_bounds__(1024)
     k_rr_finish(const SmallDesc* __restrict__ sds, const double* __restrict__ pk,
                 const int32_t* __restrict__ conv, double* __restrict__ ritz,
                 int32_t* __restrict__ perm, double* __restrict__ a_lo, int adapt,
-                int32_t* __restrict__ status) {
+                int32_t* __restrict__ status, double conv_tol) {
   __shared__ double th[1024];
   __shared__ double red[16];
   const SmallDesc d = sds[blockIdx.x];
@@ -352,16 +867,16 @@ __global__ void __launch_bounds__(1024)
       f += red2[w];
       o = fmax(o, red2[16 + w]);
     }
-    if (!(o <= 1e-10 * sqrt(f))) atomicOr(&status[d.blk], MI_BLOCK_NOCONV);
+    if (!(o <= conv_tol * sqrt(f))) atomicOr(&status[d.blk], MI_BLOCK_NOCONV);
   }
 }
 
 void launch_rr_finish(const SmallDesc* sd, int nb, const double* pk, const int32_t* conv,
                       double* ritz, int32_t* perm, double* a_lo, int adapt, int32_t* status,
-                      hipStream_t s) {
+                      double conv_tol, hipStream_t s) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_rr_finish, dim3(nb), dim3(1024), 0, s, sd, pk, conv, ritz, perm, a_lo, adapt,
-                     status);
+                     status, conv_tol);
 }
 
 __global__ void __launch_bounds__(256)
@@ -388,7 +903,7 @@ void launch_perm_cast(const SmallDesc* sd, int nb, const double* S64, const int3
 }  // namespace mis
 
 namespace mis {
-const void* k_chol_inv_ptr() { return reinterpret_cast<const void*>(&k_chol_inv); }
-const void* k_jacobi_sweep_ptr() { return reinterpret_cast<const void*>(&k_jacobi_sweep); }
+const void* k_chol_inv_ptr() { return reinterpret_cast<const void*>(&k_chol_inv<true>); }
+const void* k_jacobi_sweep_ptr() { return reinterpret_cast<const void*>(&k_jacobi_sweep<true>); }
 const void* k_apply_rot_ptr() { return reinterpret_cast<const void*>(&k_apply_rot); }
 }  // namespace mis

@@ -26,6 +26,16 @@ void launch_chol_inv(const SmallDesc* sd, int nb, const double* G, double* Rinv,
                      double* pk_scratch, int32_t* status, bool lds, size_t lds_bytes,
                      hipStream_t s);
 
+// Blocked variant of the above (32-wide panels; working matrix Wk in global
+// memory, ld x ld per block).  Same outputs and flags.
+void launch_chol_blk(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
+                     float* S32, int32_t* status, int max_ld, int lds_max, hipStream_t s);
+
+// a[blk] <- max_j (Rinv^T H Rinv)_jj from T1 = H Rinv (largest Rayleigh
+// quotient of the Cholesky-QR basis).
+void launch_rq_max(const SmallDesc* sd, int nb, const double* Rinv, const double* T1,
+                   double* a_lo, hipStream_t s);
+
 // Packs the upper triangle of A (ld x ld) into the Jacobi scratch and sets Z
 // to the identity; resets the per-block "converged" flag.
 void launch_jacobi_init(const SmallDesc* sd, int nb, const double* A, double* pk, double* Z,
@@ -37,14 +47,15 @@ void launch_jacobi_sweep(const SmallDesc* sd, int nb, double* pk, double* log, i
                          double tol, bool lds, size_t lds_bytes, hipStream_t s);
 
 // Z <- Z * (rotations of the last sweep), rows in parallel.
-void launch_apply_rot(const SmallDesc* sd, int nb, int max_ld, const double* log,
-                      const int32_t* conv, double* Z, hipStream_t s);
+void launch_apply_rot(const SmallDesc* sd, int nb, int max_q, const double* log,
+                      const int32_t* conv, double* Z, int lds_max, hipStream_t s);
 
 // Ritz values (diagonal) sorted ascending -> ritz[t_off..], permutation ->
-// perm[t_off..]; a[blk] <- largest Ritz value when adapt; NOCONV flag.
+// perm[t_off..]; a[blk] <- largest Ritz value when adapt; NOCONV flag when an
+// off-diagonal entry still exceeds conv_tol * ||A||_F.
 void launch_rr_finish(const SmallDesc* sd, int nb, const double* pk, const int32_t* conv,
                       double* ritz, int32_t* perm, double* a_lo, int adapt, int32_t* status,
-                      hipStream_t s);
+                      double conv_tol, hipStream_t s);
 
 // S32[i][j] = S64[i][perm[j]] for j < p, zero for padding columns.
 void launch_perm_cast(const SmallDesc* sd, int nb, const double* S64, const int32_t* perm,

@@ -35,8 +35,8 @@ def ctx():
 
 
 def warm_params(**kw):
-    p = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED, T=3, m=10, passes=2, T0=8,
-                     m0=8, passes0=1, adapt=1, max_sweeps=12, a_mode=mis.MI_A_WEYL, a_value=1.0)
+    p = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED, T=3, m=10, passes=2, T0=5,
+                     m0=10, passes0=2, adapt=1, max_sweeps=12, a_mode=mis.MI_A_WEYL, a_value=1.0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -103,6 +103,16 @@ def main():
     value = nverts / (ms * 1e-3)
     st = status.cpu().numpy()
 
+    # one more step with every kernel launch bracketed by HIP events on the
+    # library's stream (eager launches): per-class durations for the roofline
+    ctx.set_timing(True)
+    step()
+    torch.cuda.synchronize()
+    ktimes = ctx.kernel_times()
+    ctx.set_timing(False)
+    step()  # back to graph replay
+    torch.cuda.synchronize()
+
     per_block_ms = None
     if not args.profile_only:
         per_block_ms = per_block_run(mis, ctx, blocks, L, prm, V0, V, ritz, status, c, coords, E, Xr)
@@ -127,6 +137,8 @@ def main():
                    "passes": 2, "T_first": 5, "m_first": 10, "passes_first": 2, "waves": int(bs.level.max() + 1)},
         "per_block_baseline": None if per_block_ms is None else
         {"value": nverts / (per_block_ms * 1e-3), "unit": "vertices/s", "ms": per_block_ms},
+        "roofline": roofline(ktimes, bs, blocks, L, prm),
+        "kernels": {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in ktimes.items() if v[1]},
         "build_laplacian_ms": lap_ms,
         "block_status_nonzero": int((st != 0).sum()),
         "input_gen_s": gen_s,
@@ -138,6 +150,63 @@ def main():
     print(json.dumps(out))
     ctx.close()
     return 0
+
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector and MFMA (dense)
+
+
+def roofline(ktimes, bs, blocks, L, prm):
+    """Roofline of the dominant kernel class of the step.  The algorithmic
+    bytes or flops of one step's launches of that class (the method's own
+    traffic, not what the caches make of it) over the event-timed total."""
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    ms, launches = ktimes[dom]
+    levels = np.asarray(bs.level)
+    n = np.asarray(blocks.n, np.int64)
+    ld = np.asarray(blocks.ld, np.int64)
+    p = np.asarray(blocks.p, np.int64)
+    nnz = np.diff(np.asarray(L.nnz_off, np.int64))
+    es = 4  # FP32 slab
+    out = {"kernel": dom, "launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
+           "traffic": None}
+    if dom == "spmm":
+        # per launch over a wave: CSR (row_ptr, col, val) once, the input
+        # block once, the previous iterate (all but the first step of a
+        # pass) and the output
+        tot = 0
+        for lvl in np.unique(levels):
+            sel = levels == lvl
+            T, m, passes = (prm.T0, prm.m0, prm.passes0) if lvl == 0 else (prm.T, prm.m, prm.passes)
+            csr = int(((n[sel] + 1) * 4 + nnz[sel] * 8).sum())
+            slab = int((n[sel] * ld[sel] * es).sum())
+            per_pass = m * (csr + 2 * slab) + (m - 1) * slab
+            tot += T * (passes * per_pass + csr + 2 * slab)
+        out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot)
+        out["achieved"] = tot / (ms * 1e-3) / 1e9
+    elif dom == "chol":
+        # Cholesky (p^3/3) and triangular inverse (p^3/3) of every block's
+        # Gram, for each of the step's Cholesky-QRs
+        tot = 0
+        for lvl in np.unique(levels):
+            sel = levels == lvl
+            T, passes = (prm.T0, prm.passes0) if lvl == 0 else (prm.T, prm.passes)
+            nchol = T * passes + 1
+            tot += nchol * int((2 * p[sel].astype(np.float64) ** 3 / 3).sum())
+        out.update(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step=tot)
+        out["achieved"] = tot / (ms * 1e-3) / 1e12
+    elif dom == "jacobi_sweep":
+        # sweeps run until convergence: the work is data dependent; count the
+        # minimum, one full sweep per block and Rayleigh-Ritz (3 q^2 (q-1)
+        # flops: every rotation updates two rows of the packed matrix)
+        q = (p + 1) // 2 * 2
+        tot = int((3.0 * q ** 2 * (q - 1)).sum())
+        out.update(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step_min=tot)
+        out["achieved"] = tot / (ms * 1e-3) / 1e12
+    else:
+        out.update(bound=None, unit=None, peak=None, achieved=None)
+    out["frac"] = None if out["achieved"] is None else out["achieved"] / out["peak"]
+    return out
 
 
 def per_block_run(mis, ctx, blocks, L, prm, V0, V, ritz, status, c, coords, E, Xr):

@@ -111,6 +111,10 @@ typedef struct {
   int32_t rr_every;  /* 1: Rayleigh-Ritz on every iteration; 0: only on the last one
                         (the others end with a Cholesky-QR and take a from the
                         largest Rayleigh quotient of its basis)                    */
+  int32_t eig;       /* eigen-solver of the Rayleigh-Ritz matrix: MI_EIG_TRIDIAG
+                        (Householder tridiagonalisation, Sturm multisection and
+                        inverse iteration; used when every ld_b <= 192, else the
+                        Jacobi sweeps) or MI_EIG_JACOBI (parallel cyclic Jacobi) */
   double a_value;
   double b_abs;      /* > 0: upper filter bound b for every block; else Gershgorin     */
   double jacobi_tol; /* off-diagonal threshold relative to ||A||_F on the last
@@ -120,6 +124,9 @@ typedef struct {
 #define MI_A_WEYL 0
 #define MI_A_ABS 1
 #define MI_A_RITZ 2
+
+#define MI_EIG_TRIDIAG 0
+#define MI_EIG_JACOBI 1
 
 /* ---------------------------------------------------------------- context */
 
@@ -131,6 +138,44 @@ mi_status mi_ctx_destroy(mi_ctx* ctx);
 const char* mi_last_error(void);
 /* Library version string. */
 const char* mi_version(void);
+
+/* Kernel classes of the per-kernel event timer. */
+enum {
+  MI_K_SPMM = 0,       /* Chebyshev step / W = L Y over the vertex slab */
+  MI_K_GRAM,           /* Y^T Y (and Y^T W) partial products over the slab */
+  MI_K_GRAM_SMALL,     /* products of p x p FP64 matrices (Rayleigh-Ritz) */
+  MI_K_GRAM_REDUCE,    /* fixed-order reduction of the Gram partials */
+  MI_K_CHOL,           /* Cholesky factor and triangular inverse of the Gram */
+  MI_K_ROWMUL,         /* slab times p x p matrix (basis update) */
+  MI_K_ROWMUL_SMALL,   /* p x p times p x p */
+  MI_K_RQ_MAX,         /* largest Rayleigh quotient (filter bound) */
+  MI_K_JACOBI_INIT,    /* pack the Rayleigh-Ritz matrix */
+  MI_K_JACOBI_SWEEP,   /* one parallel cyclic Jacobi sweep */
+  MI_K_APPLY_ROT,      /* accumulate one sweep's rotations */
+  MI_K_RR_FINISH,      /* Ritz values, order, filter bound */
+  MI_K_PERM_CAST,      /* reorder / cast the Ritz rotation */
+  MI_K_SETUP,          /* bounds, coefficients, warm-start copies, fills */
+  MI_K_PROJECT,        /* E = U^T X */
+  MI_K_RECONSTRUCT,    /* Xr = U E */
+  MI_K_EIG_REDUCE,     /* Householder tridiagonalisation of the Rayleigh-Ritz matrix */
+  MI_K_EIG_VALUES,     /* its eigenvalues by Sturm multisection */
+  MI_K_EIG_VECTORS,    /* eigenvectors of the tridiagonal matrix */
+  MI_K_EIG_BACK,       /* back-transformation by the reflectors */
+  MI_K_COUNT
+};
+/* Name of a kernel class ("spmm", ...), NULL when out of range. */
+const char* mi_kernel_class_name(int32_t k);
+/* Per-kernel timing, for measurement.  With on != 0 the context's later
+ * mi_oi_track, mi_project and mi_reconstruct calls launch eagerly (no graph
+ * replay) and bracket every kernel launch with a pair of HIP events on the
+ * caller's stream; totals restart from zero.  on = 0 stops timing and frees
+ * the events.  Synchronous. */
+mi_status mi_ctx_set_timing(mi_ctx* ctx, int32_t on);
+/* Sums of the event-timed kernel durations (ms) and launch counts per class
+ * since timing was switched on: total_ms and launches hold MI_K_COUNT
+ * entries (host arrays).  Waits for the recorded events.  MI_ERR_ARG when
+ * timing is off. */
+mi_status mi_ctx_kernel_times(mi_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- Laplacian
  * Section 3, Eq. 1-2: edge set E derived from the faces, L = D - C.  The

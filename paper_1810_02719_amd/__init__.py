@@ -99,6 +99,18 @@ class Context:
             self._ws[tag] = t
         return t
 
+    def set_timing(self, on: bool):
+        """Per-kernel event timing of later oi_track / project / reconstruct
+        calls (eager launches); restarts the totals."""
+        L.check(L.lib().mi_ctx_set_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{class: (total_ms, launches)} since timing was switched on."""
+        ms = (C.c_double * L.MI_K_COUNT)()
+        n = (C.c_int64 * L.MI_K_COUNT)()
+        L.check(L.lib().mi_ctx_kernel_times(self.h, ms, n))
+        return {name: (float(ms[k]), int(n[k])) for k, name in enumerate(L.KERNEL_CLASSES)}
+
     def close(self):
         if getattr(self, "h", None) is not None:
             L.lib().mi_ctx_destroy(self.h)
@@ -186,11 +198,12 @@ class OiParams:
     b_abs: float = 0.0
     jacobi_tol: float = 1e-14
     rr_every: int = 0
+    eig: int = 0  # MI_EIG_TRIDIAG (Jacobi for ld > 192) or MI_EIG_JACOBI
 
     def struct(self):
         return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
                             self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, self.rr_every,
-                            self.a_value, self.b_abs, self.jacobi_tol)
+                            self.eig, self.a_value, self.b_abs, self.jacobi_tol)
 
 
 def _dtype(precision):

@@ -36,6 +36,15 @@ MI_A_WEYL = 0
 MI_A_ABS = 1
 MI_A_RITZ = 2
 
+MI_EIG_TRIDIAG = 0
+MI_EIG_JACOBI = 1
+
+KERNEL_CLASSES = ["spmm", "gram", "gram_small", "gram_reduce", "chol", "rowmul", "rowmul_small",
+                  "rq_max", "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish", "perm_cast",
+                  "setup", "project", "reconstruct", "eig_reduce", "eig_values", "eig_vectors",
+                  "eig_back"]
+MI_K_COUNT = len(KERNEL_CLASSES)
+
 MI_BLOCK_OK = 0
 MI_BLOCK_SHIFTED = 1
 MI_BLOCK_NOT_PD = 2
@@ -57,13 +66,16 @@ class MiOiParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("warm", C.c_int32), ("T", C.c_int32), ("m", C.c_int32),
                 ("passes", C.c_int32), ("T0", C.c_int32), ("m0", C.c_int32),
                 ("passes0", C.c_int32), ("adapt", C.c_int32), ("max_sweeps", C.c_int32),
-                ("a_mode", C.c_int32), ("rr_every", C.c_int32), ("a_value", C.c_double),
+                ("a_mode", C.c_int32), ("rr_every", C.c_int32), ("eig", C.c_int32),
+                ("a_value", C.c_double),
                 ("b_abs", C.c_double), ("jacobi_tol", C.c_double)]
 
 
 _SIGS = {
     "mi_ctx_create": [C.POINTER(_vp), C.c_int32],
     "mi_ctx_destroy": [_vp],
+    "mi_ctx_set_timing": [_vp, C.c_int32],
+    "mi_ctx_kernel_times": [_vp, C.POINTER(C.c_double), _i64p],
     "mi_laplacian_workspace_size": [C.POINTER(MiBlocks), _i64p, C.c_int32, _szp],
     "mi_build_laplacian_count": [_vp, C.POINTER(MiBlocks), _i64p, _vp, C.c_int32, _i64p, _i64p,
                                  _vp, C.c_size_t, _vp],
@@ -103,6 +115,11 @@ def lib():
         L.mi_last_error.argtypes = []
         L.mi_version.restype = C.c_char_p
         L.mi_version.argtypes = []
+        L.mi_kernel_class_name.restype = C.c_char_p
+        L.mi_kernel_class_name.argtypes = [C.c_int32]
+        names = [L.mi_kernel_class_name(k).decode() for k in range(MI_K_COUNT)]
+        if names != KERNEL_CLASSES or L.mi_kernel_class_name(MI_K_COUNT) is not None:
+            raise ImportError(f"kernel class table of {LIB_PATH} does not match the binding")
         _lib = L
     return _lib
 

@@ -77,6 +77,60 @@ __host__ __device__ inline int rr_index(int pos, int r, int q) {
   return 1 + ((pos - 1 + r) % (q - 1));
 }
 
+// Event timer of the kernel classes (mi_ctx_set_timing): every launch of a
+// timed call is bracketed by two events on the launch stream; the elapsed
+// times are summed per class when they are read.
+struct KTimer {
+  struct Rec {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[MI_K_COUNT] = {};
+  int64_t n[MI_K_COUNT] = {};
+  int open_k = -1;
+  hipEvent_t open_a = nullptr;
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  void begin(int k, hipStream_t s) {
+    open_k = k;
+    open_a = take();
+    if (open_a) (void)hipEventRecord(open_a, s);
+  }
+  void end(hipStream_t s) {
+    hipEvent_t b = take();
+    if (b && open_a) {
+      (void)hipEventRecord(b, s);
+      pending.push_back(Rec{open_k, open_a, b});
+    }
+    open_a = nullptr;
+  }
+  mi_status collect();
+  ~KTimer();
+};
+
+// Brackets the launches made during its lifetime with the timer's events
+// (no-op when timing is off).
+struct KScope {
+  KTimer* t;
+  hipStream_t s;
+  KScope(KTimer* t_, int k, hipStream_t s_) : t(t_), s(s_) {
+    if (t) t->begin(k, s);
+  }
+  ~KScope() {
+    if (t) t->end(s);
+  }
+};
+
 }  // namespace mis
 
 // Context (opaque in the C ABI).
@@ -86,4 +140,5 @@ struct mi_ctx {
   void* oi_plan = nullptr;
   void* enc_plan = nullptr;
   void* cc_plan = nullptr;
+  mis::KTimer* timer = nullptr;  // non-null while timing is on
 };

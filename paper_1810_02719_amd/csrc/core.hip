@@ -174,6 +174,29 @@ void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f64, dim3(g), dim3(256), 0, s, p, v, n);
 }
 
+mi_status KTimer::collect() {
+  for (const Rec& r : pending) {
+    float t = 0.f;
+    MI_TRY_HIP(hipEventSynchronize(r.b));
+    MI_TRY_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.k] += t;
+    n[r.k] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+  return MI_OK;
+}
+
+KTimer::~KTimer() {
+  for (const Rec& r : pending) {
+    (void)hipEventSynchronize(r.b);
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
 }  // namespace mis
 
 extern "C" {
@@ -205,7 +228,41 @@ mi_status mi_ctx_destroy(mi_ctx* ctx) {
   mis_destroy_oi_plan(ctx);
   mis_destroy_enc_plan(ctx);
   mis_destroy_cc_plan(ctx);
+  delete ctx->timer;
   delete ctx;
+  return MI_OK;
+}
+
+static const char* const k_class_names[MI_K_COUNT] = {
+    "spmm",        "gram",       "gram_small", "gram_reduce",  "chol",      "rowmul",
+    "rowmul_small", "rq_max",    "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish",
+    "perm_cast",   "setup",      "project",    "reconstruct",  "eig_reduce", "eig_values",
+    "eig_vectors", "eig_back"};
+
+const char* mi_kernel_class_name(int32_t k) {
+  return (k >= 0 && k < MI_K_COUNT) ? k_class_names[k] : nullptr;
+}
+
+mi_status mi_ctx_set_timing(mi_ctx* ctx, int32_t on) {
+  mis::clear_error();
+  MI_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  MI_TRY_HIP(hipSetDevice(ctx->device));
+  delete ctx->timer;
+  ctx->timer = on ? new mis::KTimer() : nullptr;
+  return MI_OK;
+}
+
+mi_status mi_ctx_kernel_times(mi_ctx* ctx, double* total_ms, int64_t* launches) {
+  mis::clear_error();
+  MI_CHECK_ARG(ctx != nullptr && total_ms != nullptr && launches != nullptr, "NULL argument");
+  MI_CHECK_ARG(ctx->timer != nullptr, "timing is off");
+  MI_TRY_HIP(hipSetDevice(ctx->device));
+  mi_status st = ctx->timer->collect();
+  if (st) return st;
+  for (int k = 0; k < MI_K_COUNT; ++k) {
+    total_ms[k] = ctx->timer->ms[k];
+    launches[k] = ctx->timer->n[k];
+  }
   return MI_OK;
 }
 

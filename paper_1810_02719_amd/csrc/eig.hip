@@ -1,0 +1,597 @@
+// Symmetric eigen-decomposition of the Rayleigh-Ritz matrices A (p x p,
+// FP64, p <= 192) of a wave of blocks, in four launches:
+//
+//   1. k_tri_reduce   Householder tridiagonalisation T = Q^T A Q, one
+//                     workgroup per block with A resident in registers.
+//   2. k_tri_bisect   every eigenvalue of T by Sturm-count multisection
+//                     (ascending, so the Ritz order comes for free).
+//   3. k_tri_vectors  eigenvectors of T: the twisted factorisation of
+//                     T - lambda I for isolated eigenvalues, inverse iteration
+//                     with Gram-Schmidt inside clusters of close eigenvalues.
+//   4. k_tri_back     back-transformation Z = Q Z_T, rows of Z_T^T spread
+//                     over several workgroups per block.
+//
+// The eigenvalue problem itself is textbook linear algebra (Householder
+// reduction, Sturm sequences, inverse iteration); the method only needs the
+// Ritz pairs of its projected matrix.
+#include <cfloat>
+
+#include "eig.hpp"
+
+namespace mis {
+
+namespace {
+
+constexpr int TRI_BISECT_POINTS = 3;  // Sturm counts per lane and round
+constexpr int TRI_GROUP = 4;          // lanes per eigenvalue
+constexpr int TRI_MAXIT = 24;         // multisection rounds (52 bits need 14)
+constexpr int TRI_VC = 16;            // reflectors staged per LDS chunk
+constexpr double TRI_TN_MIN = 1e-290; // floor of the matrix scale
+constexpr double TRI_CLUSTER = 1e-8;  // relative gap below which vectors are
+                                      // orthogonalised against each other
+
+// Select w[a][b] with a runtime column index kb (registers cannot be indexed).
+template <int RT>
+__device__ __forceinline__ double col_of(const double (&row)[RT], int kb) {
+  double v = 0.0;
+#pragma unroll
+  for (int b = 0; b < RT; ++b)
+    if (b == kb) v = row[b];
+  return v;
+}
+
+__device__ __forceinline__ double half_sum(double v) {
+  // sum over the 32 lanes of a half-wavefront (xor masks below 32 stay in it)
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double guard(double t, double floor_) {
+  return fabs(t) < floor_ ? -floor_ : t;
+}
+
+// Scale of T and the Sturm-count pivot floor (identical in every launch that
+// needs them, so every kernel sees the same numbers).
+struct TriScale {
+  double lo, hi, tn, pivmin;
+};
+
+__device__ TriScale tri_scale(const double* __restrict__ dd, const double* __restrict__ ee, int p,
+                              double* red /* LDS, >= 3 * (blockDim / 64) */) {
+  double lo = DBL_MAX, hi = -DBL_MAX, e2 = 0.0;
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    const double el = i > 0 ? fabs(ee[i - 1]) : 0.0;
+    const double er = i + 1 < p ? fabs(ee[i]) : 0.0;
+    lo = fmin(lo, dd[i] - el - er);
+    hi = fmax(hi, dd[i] + el + er);
+    e2 = fmax(e2, er * er);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    e2 = fmax(e2, __shfl_xor(e2, o, 64));
+  }
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[wv] = lo;
+    red[nw + wv] = hi;
+    red[2 * nw + wv] = e2;
+  }
+  __syncthreads();
+  TriScale s;
+  s.lo = red[0];
+  s.hi = red[nw];
+  e2 = red[2 * nw];
+  for (int w = 1; w < nw; ++w) {
+    s.lo = fmin(s.lo, red[w]);
+    s.hi = fmax(s.hi, red[nw + w]);
+    e2 = fmax(e2, red[2 * nw + w]);
+  }
+  s.tn = fmax(fmax(fabs(s.lo), fabs(s.hi)), TRI_TN_MIN);
+  s.pivmin = DBL_MIN * fmax(1.0, e2);
+  s.lo -= 2.0 * DBL_EPSILON * s.tn + 2.0 * s.pivmin;
+  s.hi += 2.0 * DBL_EPSILON * s.tn + 2.0 * s.pivmin;
+  return s;
+}
+
+__device__ __forceinline__ double hash_unit(int i, int j) {
+  uint32_t h = uint32_t(i) * 0x9E3779B1u + uint32_t(j) * 0x85EBCA77u + 0x165667B1u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return double(h) * (1.0 / 2147483648.0) - 1.0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ 1. reduction
+// Thread (tr, tc) = (tid / 32, tid % 32) holds A[tr + 32a][tc + 32b] in
+// registers (both triangles).  Step k: the owners of column k publish it and
+// partial squared norms; everyone forms the reflector H_k = I - beta v v^T
+// (v zero up to k, alpha = -sign(x_{k+1}) ||x||), computes p = beta A v with
+// half-wavefront reductions, then A -= v w^T + w v^T with
+// w = p - (beta/2)(v^T p) v.  Row and column k are zeroed afterwards, so the
+// trailing update runs over the full register tile without predicates.  Two
+// barriers per step; the LDS vectors are double-buffered by step parity.
+template <int RT>
+__global__ void __launch_bounds__(1024)
+    k_tri_reduce(const SmallDesc* __restrict__ sds, const double* __restrict__ A,
+                 double* __restrict__ Hv, double* __restrict__ tri, int32_t* __restrict__ status) {
+  constexpr int LDM = 32 * RT;
+  __shared__ double xcol[2][LDM];
+  __shared__ double pcol[2][LDM];
+  __shared__ double part[2][32];
+  __shared__ double vpart[2][32];
+  __shared__ int flag;
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  const double* Ab = A + d.m_off;
+  double* Hb = Hv + d.m_off;
+  double* dd = tri + 4 * d.t_off;
+  double* ee = dd + p;
+  double* bb = dd + 3 * p;
+  if (tid == 0) flag = 0;
+  __syncthreads();
+  double w[RT][RT];
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      const double v = (i < p && j < p) ? Ab[int64_t(i) * ld + j] : 0.0;
+      bad = bad || !isfinite(v);
+      w[a][b] = v;
+    }
+  if (bad) atomicOr(&flag, MI_BLOCK_NONFINITE);
+  __syncthreads();
+  for (int k = 0; k + 2 < p; ++k) {
+    const int par = k & 1, kb = k >> 5, kt = k & 31;
+    // A: publish column k (the diagonal entry goes to d_k, not into v)
+    if (tc == kt) {
+      double ss = 0.0;
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const int i = tr + 32 * a;
+        double x = col_of<RT>(w[a], kb);
+        if (i == k) {
+          dd[k] = x;
+          x = 0.0;
+        }
+        xcol[par][i] = x;
+        ss += x * x;
+      }
+      part[par][tr] = ss;
+    }
+    __syncthreads();
+    // B: reflector and p = beta A v
+    double ss = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < 32; ++t) ss += part[par][t];
+    const double x1 = xcol[par][k + 1];
+    double al, be;
+    if (ss <= DBL_MIN) {
+      al = x1;
+      be = 0.0;
+    } else {
+      al = -copysign(sqrt(ss), x1);
+      be = 1.0 / (al * (al - x1));
+    }
+    // v_i = x_i except v_{k+1} = x_{k+1} - alpha (read again from LDS where
+    // needed: keeps the register tile within the 128-VGPR budget)
+    auto vat = [&](int i) { return xcol[par][i] - (i == k + 1 ? al : 0.0); };
+    double vc[RT];
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int j = tc + 32 * b;
+      vc[b] = xcol[par][j] - (j == k + 1 ? al : 0.0);
+    }
+    double vp = 0.0;
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      double sa = 0.0;
+#pragma unroll
+      for (int b = 0; b < RT; ++b) sa = fma(w[a][b], vc[b], sa);
+      const double pa = be * half_sum(sa);
+      vp = fma(vat(tr + 32 * a), pa, vp);
+      if (tc == 0) pcol[par][tr + 32 * a] = pa;
+    }
+    if (tc == 0) vpart[par][tr] = vp;
+    if (tid == 0) {
+      ee[k] = al;
+      bb[k] = be;
+    }
+    if (tr == 0) {
+#pragma unroll
+      for (int b = 0; b < RT; ++b) {
+        const int j = tc + 32 * b;
+        if (j < ld) Hb[int64_t(k) * ld + j] = vc[b];
+      }
+    }
+    __syncthreads();
+    // C: rank-2 update of the trailing matrix
+    double vtp = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < 32; ++t) vtp += vpart[par][t];
+    const double K = 0.5 * be * vtp;
+    double wc[RT];
+#pragma unroll
+    for (int b = 0; b < RT; ++b) wc[b] = pcol[par][tc + 32 * b] - K * vc[b];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const double va = vat(tr + 32 * a);
+      const double wa = pcol[par][tr + 32 * a] - K * va;
+#pragma unroll
+      for (int b = 0; b < RT; ++b) w[a][b] -= va * wc[b] + wa * vc[b];
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+        if ((tr == kt && a == kb) || (tc == kt && b == kb)) w[a][b] = 0.0;
+  }
+  // the last 2 x 2 (or 1 x 1) block is already tridiagonal
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, j = tc + 32 * b;
+      if (p >= 2 && i == p - 2 && j == p - 2) dd[p - 2] = w[a][b];
+      if (i == p - 1 && j == p - 1) dd[p - 1] = w[a][b];
+      if (p >= 2 && i == p - 1 && j == p - 2) ee[p - 2] = w[a][b];
+    }
+  if (tid == 0) {
+    ee[p - 1] = 0.0;
+    if (p >= 2) bb[p - 2] = 0.0;
+    bb[p - 1] = 0.0;
+  }
+  __syncthreads();
+  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
+}
+
+// ------------------------------------------------------------------ 2. eigenvalues
+// Count of eigenvalues of T below x = number of negative pivots of the
+// LDL^T factorisation of T - x I (Sylvester's law of inertia); pivots
+// smaller than pivmin are replaced by -pivmin.  Each eigenvalue j is owned
+// by a group of TRI_GROUP lanes that evaluate TRI_GROUP * TRI_BISECT_POINTS
+// equispaced points of its bracket [a, b] (count(a) <= j < count(b)) per
+// round, interleaved for instruction-level parallelism.
+__global__ void __launch_bounds__(256)
+    k_tri_bisect(const SmallDesc* __restrict__ sds, double* __restrict__ tri,
+                 double* __restrict__ ritz, int32_t* __restrict__ perm, double* __restrict__ a_lo,
+                 int adapt, int32_t* __restrict__ status) {
+  extern __shared__ double smem[];
+  __shared__ double red[12];
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p;
+  const int j0 = blockIdx.y * (256 / TRI_GROUP);
+  if (j0 >= p) return;
+  double* sd_ = smem;
+  double* se2 = smem + p;
+  const double* dd = tri + 4 * d.t_off;
+  const double* ee = dd + p;
+  double* lam = tri + 4 * d.t_off + 2 * p;
+  for (int i = threadIdx.x; i < p; i += 256) {
+    sd_[i] = dd[i];
+    se2[i] = ee[i] * ee[i];
+  }
+  const TriScale sc = tri_scale(dd, ee, p, red);  // has a barrier
+  const double atol = 4.0 * DBL_EPSILON * sc.tn + 2.0 * sc.pivmin;
+  const int g = threadIdx.x / TRI_GROUP, r = threadIdx.x % TRI_GROUP;
+  const int j = j0 + g;
+  const bool live = j < p;
+  double a = sc.lo, b = sc.hi;
+  constexpr int NP = TRI_GROUP * TRI_BISECT_POINTS;
+  for (int it = 0; it < TRI_MAXIT; ++it) {
+    const bool todo = live && (b - a > atol);
+    if (!__any(todo)) break;
+    double na = a, nb = b;
+    if (todo) {
+      const double h = (b - a) * (1.0 / (NP + 1));
+      double x[TRI_BISECT_POINTS], t[TRI_BISECT_POINTS];
+      int c[TRI_BISECT_POINTS];
+#pragma unroll
+      for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
+        x[m] = a + h * double(r * TRI_BISECT_POINTS + m + 1);
+        t[m] = guard(sd_[0] - x[m], sc.pivmin);
+        c[m] = t[m] < 0.0;
+      }
+      for (int i = 1; i < p; ++i) {
+        const double di = sd_[i], e2 = se2[i - 1];
+#pragma unroll
+        for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
+          t[m] = guard((di - x[m]) - e2 / t[m], sc.pivmin);
+          c[m] += t[m] < 0.0;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
+        if (c[m] <= j) na = fmax(na, x[m]);
+        else nb = fmin(nb, x[m]);
+      }
+    }
+    for (int o = 1; o < TRI_GROUP; o <<= 1) {
+      na = fmax(na, __shfl_xor(na, o, 64));
+      nb = fmin(nb, __shfl_xor(nb, o, 64));
+    }
+    a = na;
+    b = nb;
+  }
+  if (live && r == 0) {
+    const double v = 0.5 * (a + b);
+    lam[j] = v;
+    ritz[d.t_off + j] = v;
+    perm[d.t_off + j] = j;
+    if (adapt && j == p - 1) a_lo[d.blk] = v;
+    if (!isfinite(v)) atomicOr(&status[d.blk], MI_BLOCK_NONFINITE);
+    else if (b - a > atol) atomicOr(&status[d.blk], MI_BLOCK_NOCONV);
+  }
+}
+
+// ------------------------------------------------------------------ 3. eigenvectors of T
+// One thread per eigenvalue; per-thread vectors live in columns of ld x ld
+// scratch matrices (column j of thread j: coalesced across the threads).
+// An isolated eigenvalue gets the twisted-factorisation vector: forward
+// (dp) and backward (dm) pivots of T - lambda I, the twist index k with the
+// smallest |dp_k + dm_k - (d_k - lambda)|, z_k = 1 and the two one-sided
+// recurrences.  The first eigenvalue of a cluster (consecutive gaps below
+// TRI_CLUSTER * ||T||) computes the whole cluster by inverse iteration (3
+// rounds from a fixed pseudo-random start, LDL^T solves with pivots floored
+// at eps ||T||, equal shifts separated by 10 eps ||T||, Gram-Schmidt twice
+// against the cluster's earlier vectors).  Output: unit vectors in the
+// columns of Zt (Zt[i][j] = component i of vector j).
+__device__ void tri_inverse_iteration(const double* __restrict__ sd_, const double* __restrict__ se,
+                                      const double* __restrict__ lam, int p, int ld, int j0,
+                                      int j1, double tn, double* __restrict__ dp,
+                                      double* __restrict__ y, double* __restrict__ Zt) {
+  const double fl = DBL_EPSILON * tn;
+  double sprev = 0.0;
+  for (int jj = j0; jj <= j1; ++jj) {
+    double s = lam[jj];
+    if (jj > j0 && s <= sprev + 10.0 * fl) s = sprev + 10.0 * fl;
+    sprev = s;
+    double t = guard(sd_[0] - s, fl);
+    dp[jj] = t;
+    for (int i = 1; i < p; ++i) {
+      t = guard((sd_[i] - s) - se[i - 1] * se[i - 1] / t, fl);
+      dp[int64_t(i) * ld + jj] = t;
+    }
+    double* x = Zt + jj;
+    for (int i = 0; i < p; ++i) x[int64_t(i) * ld] = hash_unit(i, jj);
+    for (int it = 0; it < 3; ++it) {
+      double mx = 0.0;
+      for (int i = 0; i < p; ++i) mx = fmax(mx, fabs(x[int64_t(i) * ld]));
+      const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+      // L y = x  (L unit lower, l_i = e_i / dp_i)
+      double yi = x[0] * inv;
+      y[jj] = yi;
+      for (int i = 1; i < p; ++i) {
+        yi = x[int64_t(i) * ld] * inv - se[i - 1] / dp[int64_t(i - 1) * ld + jj] * yi;
+        y[int64_t(i) * ld + jj] = yi;
+      }
+      // D L^T z = y
+      double zi = y[int64_t(p - 1) * ld + jj] / dp[int64_t(p - 1) * ld + jj];
+      x[int64_t(p - 1) * ld] = zi;
+      for (int i = p - 2; i >= 0; --i) {
+        const double di = dp[int64_t(i) * ld + jj];
+        zi = y[int64_t(i) * ld + jj] / di - se[i] / di * zi;
+        x[int64_t(i) * ld] = zi;
+      }
+      for (int rep = 0; rep < 2; ++rep)
+        for (int u = j0; u < jj; ++u) {
+          double dot = 0.0;
+          for (int i = 0; i < p; ++i) dot = fma(Zt[int64_t(i) * ld + u], x[int64_t(i) * ld], dot);
+          for (int i = 0; i < p; ++i) x[int64_t(i) * ld] -= dot * Zt[int64_t(i) * ld + u];
+        }
+      double nrm = 0.0;
+      for (int i = 0; i < p; ++i) nrm = fma(x[int64_t(i) * ld], x[int64_t(i) * ld], nrm);
+      const double sc = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = 0; i < p; ++i) x[int64_t(i) * ld] *= sc;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64)
+    k_tri_vectors(const SmallDesc* __restrict__ sds, const double* __restrict__ tri,
+                  double* __restrict__ DP, double* __restrict__ DM, double* __restrict__ ZT,
+                  int32_t* __restrict__ status) {
+  extern __shared__ double smem[];
+  __shared__ double red[3];
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const int j = blockIdx.y * 64 + threadIdx.x;
+  if (blockIdx.y * 64 >= p) return;
+  double* sd_ = smem;
+  double* se = smem + p;
+  const double* dd = tri + 4 * d.t_off;
+  const double* ee = dd + p;
+  const double* lam = dd + 2 * p;
+  for (int i = threadIdx.x; i < p; i += 64) {
+    sd_[i] = dd[i];
+    se[i] = ee[i];
+  }
+  const TriScale sc = tri_scale(dd, ee, p, red);  // has a barrier
+  if (j >= p) return;
+  const double ctol = TRI_CLUSTER * sc.tn;
+  if (j > 0 && !(lam[j] - lam[j - 1] > ctol)) return;  // inside a cluster led by an earlier j
+  int j1 = j;
+  while (j1 + 1 < p && !(lam[j1 + 1] - lam[j1] > ctol)) ++j1;
+  double* dp = DP + d.m_off;
+  double* dm = DM + d.m_off;
+  double* Zt = ZT + d.m_off;
+  if (j1 > j) {
+    tri_inverse_iteration(sd_, se, lam, p, ld, j, j1, sc.tn, dp, dm, Zt);
+    return;
+  }
+  const double lj = lam[j];
+  const double pm = sc.pivmin;
+  double t = guard(sd_[0] - lj, pm);
+  dp[j] = t;
+  for (int i = 1; i < p; ++i) {
+    t = guard((sd_[i] - lj) - se[i - 1] * se[i - 1] / t, pm);
+    dp[int64_t(i) * ld + j] = t;
+  }
+  const double dp_last = t;
+  t = guard(sd_[p - 1] - lj, pm);
+  dm[int64_t(p - 1) * ld + j] = t;
+  int kmin = p - 1;
+  double gmin = fabs(dp_last + t - (sd_[p - 1] - lj));
+  for (int i = p - 2; i >= 0; --i) {
+    t = guard((sd_[i] - lj) - se[i] * se[i] / t, pm);
+    dm[int64_t(i) * ld + j] = t;
+    const double gam = fabs(dp[int64_t(i) * ld + j] + t - (sd_[i] - lj));
+    if (gam < gmin) {
+      gmin = gam;
+      kmin = i;
+    }
+  }
+  double nrm = 1.0;
+  Zt[int64_t(kmin) * ld + j] = 1.0;
+  double z = 1.0;
+  for (int i = kmin - 1; i >= 0; --i) {
+    z = -se[i] * z / dp[int64_t(i) * ld + j];
+    Zt[int64_t(i) * ld + j] = z;
+    nrm = fma(z, z, nrm);
+  }
+  z = 1.0;
+  for (int i = kmin + 1; i < p; ++i) {
+    z = -se[i - 1] * z / dm[int64_t(i) * ld + j];
+    Zt[int64_t(i) * ld + j] = z;
+    nrm = fma(z, z, nrm);
+  }
+  if (!isfinite(nrm)) {  // overflow in the recurrences: fall back to inverse iteration
+    tri_inverse_iteration(sd_, se, lam, p, ld, j, j, sc.tn, dp, dm, Zt);
+    return;
+  }
+  const double inv = 1.0 / sqrt(nrm);
+  for (int i = 0; i < p; ++i) Zt[int64_t(i) * ld + j] *= inv;
+  (void)status;
+}
+
+// ------------------------------------------------------------------ 4. back-transformation
+// Z^T = Z_T^T H_{p-3} ... H_0: every row of Z_T^T (an eigenvector of T) is
+// updated independently, row . v reduced over a half-wavefront, so a block
+// splits into ld / 32 workgroups of 32 rows.  The reflectors are staged
+// through LDS TRI_VC at a time.  Output Z[i][j] = component i of the j-th
+// eigenvector (ascending), zero outside p x p.
+template <int RT>
+__global__ void __launch_bounds__(256)
+    k_tri_back(const SmallDesc* __restrict__ sds, const double* __restrict__ ZT,
+               const double* __restrict__ Hv, const double* __restrict__ tri,
+               double* __restrict__ Z) {
+  constexpr int LDM = 32 * RT;
+  __shared__ double vb[TRI_VC][LDM];
+  __shared__ double bt[TRI_VC];
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  if (int(blockIdx.y) * 32 >= ld) return;
+  const int h = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const double* Zt = ZT + d.m_off;
+  const double* Hb = Hv + d.m_off;
+  const double* bb = tri + 4 * d.t_off + 3 * p;
+  double w[4][RT];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = blockIdx.y * 32 + h + 8 * r;
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = l + 32 * b;
+      w[r][b] = (i < p && j < p) ? Zt[int64_t(i) * ld + j] : 0.0;
+    }
+  }
+  for (int k0 = p - 3; k0 >= 0; k0 -= TRI_VC) {
+    const int kl = max(0, k0 - TRI_VC + 1);
+    const int cnt = k0 - kl + 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * LDM; e += 256) {
+      const int kk = e / LDM, i = e % LDM;
+      vb[kk][i] = (i < p) ? Hb[int64_t(kl + kk) * ld + i] : 0.0;
+    }
+    if (threadIdx.x < cnt) bt[threadIdx.x] = bb[kl + threadIdx.x];
+    __syncthreads();
+    for (int kk = cnt - 1; kk >= 0; --kk) {
+      const double be = bt[kk];
+      double v[RT];
+#pragma unroll
+      for (int b = 0; b < RT; ++b) v[b] = vb[kk][l + 32 * b];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < RT; ++b) s = fma(w[r][b], v[b], s);
+        s = be * half_sum(s);
+#pragma unroll
+        for (int b = 0; b < RT; ++b) w[r][b] -= s * v[b];
+      }
+    }
+  }
+  double* Zb = Z + d.m_off;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = blockIdx.y * 32 + h + 8 * r;
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = l + 32 * b;
+      if (i < ld && j < ld) Zb[int64_t(i) * ld + j] = (i < p && j < p) ? w[r][b] : 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launch
+bool tri_eig_supported(int max_ld) { return max_ld <= TRI_MAX_LD; }
+
+#define MI_TRI_CASE(R)                                                                           \
+  case R:                                                                                        \
+    hipLaunchKernelGGL(k_tri_reduce<R>, dim3(nb), dim3(1024), 0, s, sd, A, Hv, tri, status);     \
+    break;
+
+#define MI_TRI_BACK_CASE(R)                                                                      \
+  case R:                                                                                        \
+    hipLaunchKernelGGL(k_tri_back<R>, dim3(nb, max_ld / 32), dim3(256), 0, s, sd, ZT, Hv, tri, Z); \
+    break;
+
+void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, const double* A, double* Hv,
+                       double* tri, int32_t* status, hipStream_t s) {
+  if (nb <= 0) return;
+  switch ((max_ld + 31) / 32) {
+    MI_TRI_CASE(1)
+    MI_TRI_CASE(2)
+    MI_TRI_CASE(3)
+    MI_TRI_CASE(4)
+    MI_TRI_CASE(5)
+    MI_TRI_CASE(6)
+    default: break;
+  }
+}
+
+void launch_tri_bisect(const SmallDesc* sd, int nb, int max_p, double* tri, double* ritz,
+                       int32_t* perm, double* a_lo, int adapt, int32_t* status, hipStream_t s) {
+  if (nb <= 0) return;
+  const int gy = ceil_div(max_p, 256 / TRI_GROUP);
+  hipLaunchKernelGGL(k_tri_bisect, dim3(nb, gy), dim3(256), size_t(2 * max_p) * sizeof(double), s,
+                     sd, tri, ritz, perm, a_lo, adapt, status);
+}
+
+void launch_tri_vectors(const SmallDesc* sd, int nb, int max_p, const double* tri, double* DP,
+                        double* DM, double* ZT, int32_t* status, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_tri_vectors, dim3(nb, ceil_div(max_p, 64)), dim3(64),
+                     size_t(2 * max_p) * sizeof(double), s, sd, tri, DP, DM, ZT, status);
+}
+
+void launch_tri_back(const SmallDesc* sd, int nb, int max_ld, const double* ZT, const double* Hv,
+                     const double* tri, double* Z, hipStream_t s) {
+  if (nb <= 0) return;
+  switch ((max_ld + 31) / 32) {
+    MI_TRI_BACK_CASE(1)
+    MI_TRI_BACK_CASE(2)
+    MI_TRI_BACK_CASE(3)
+    MI_TRI_BACK_CASE(4)
+    MI_TRI_BACK_CASE(5)
+    MI_TRI_BACK_CASE(6)
+    default: break;
+  }
+}
+
+}  // namespace mis

@@ -170,6 +170,7 @@ mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const
   st = enc_plan(ctx, hb, &P);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
+  KScope k_(ctx->timer, MI_K_PROJECT, s);
   if (precision == MI_FP64)
     hipLaunchKernelGGL(k_project<double>, dim3(hb.B), dim3(256), 0, s, P->dev, c,
                        (const double*)U, (const double*)X, (double*)E);
@@ -195,6 +196,7 @@ mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, c
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = hb.v_off[hb.B];
   const int grid = ceil_div(N, 4);
+  KScope k_(ctx->timer, MI_K_RECONSTRUCT, s);
   if (precision == MI_FP64)
     hipLaunchKernelGGL(k_reconstruct<double>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff, hb.B,
                        N, c, (const double*)U, (const double*)E, (double*)Xr);

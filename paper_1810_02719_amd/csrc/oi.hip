@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 
+#include "eig.hpp"
 #include "small.hpp"
 
 namespace mis {
@@ -154,7 +155,7 @@ struct WaveTables {
   int nb = 0;
   int T = 0, m = 0, passes = 0;
   bool from_pred = false;
-  int max_ld = 0, max_q = 0;
+  int max_ld = 0, max_q = 0, max_p = 0;
   int nch = 64, nchs = 64;
   // device tables
   MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
@@ -177,7 +178,8 @@ struct WaveTables {
 };
 
 struct WsLayout {
-  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, part, a_lo, b_hi, coef, conv;
+  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, tri, part, a_lo, b_hi, coef,
+      conv;
   size_t total;
   int coef_stride;
 };
@@ -291,6 +293,7 @@ static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t 
   L.pk = c.used, c.take<double>(pk);
   L.log = c.used, c.take<double>(lg);
   L.perm = c.used, c.take<int32_t>(tp);
+  L.tri = c.used, c.take<double>(4 * tp);
   L.part = c.used, c.take<double>(std::max<size_t>(part_doubles, 1));
   L.a_lo = c.used, c.take<double>(hb.B);
   L.b_hi = c.used, c.take<double>(hb.B);
@@ -343,6 +346,7 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
     lds_list.push_back(hb.ld[b]);
     wt->max_ld = std::max(wt->max_ld, hb.ld[b]);
     wt->max_q = std::max(wt->max_q, s.q);
+    wt->max_p = std::max(wt->max_p, s.p);
   }
   wt->nb = (int)blocks.size();
   wt->nch = pick_nch(lds_list, dbl);
@@ -474,6 +478,7 @@ struct Args {
   double* ritz;
   int32_t* status;
   char* ws;
+  KTimer* tm;
 };
 
 template <typename T>
@@ -495,6 +500,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   double* pk = reinterpret_cast<double*>(ws + L.pk);
   double* lg = reinterpret_cast<double*>(ws + L.log);
   int32_t* perm = reinterpret_cast<int32_t*>(ws + L.perm);
+  double* tri = reinterpret_cast<double*>(ws + L.tri);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* a_lo = reinterpret_cast<double*>(ws + L.a_lo);
   double* b_hi = reinterpret_cast<double*>(ws + L.b_hi);
@@ -505,28 +511,42 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   const T* V0 = static_cast<const T*>(a.V0);
   const int B = P.hb.B;
 
-  fill_i32(a.status, 0, B, s);
-  if (prm.b_abs > 0)
-    hipLaunchKernelGGL(k_set_b, dim3(ceil_div(B, 256)), dim3(256), 0, s, P.all_tall, B, prm.b_abs, b_hi);
-  else
-    hipLaunchKernelGGL(k_gershgorin, dim3(B), dim3(256), 0, s, P.all_tall, P.all_csr, a.row_ptr,
-                       a.val, b_hi);
+  {
+    KScope k_(a.tm, MI_K_SETUP, s);
+    fill_i32(a.status, 0, B, s);
+  }
+  {
+    KScope k_(a.tm, MI_K_SETUP, s);
+    if (prm.b_abs > 0)
+      hipLaunchKernelGGL(k_set_b, dim3(ceil_div(B, 256)), dim3(256), 0, s, P.all_tall, B, prm.b_abs,
+                         b_hi);
+    else
+      hipLaunchKernelGGL(k_gershgorin, dim3(B), dim3(256), 0, s, P.all_tall, P.all_csr, a.row_ptr,
+                         a.val, b_hi);
+  }
 
   for (WaveTables& w : P.waves) {
     const size_t lds_jac = size_t(4 * (w.max_q / 2) + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
     const bool jac_lds = lds_jac <= (size_t)P.lds_max;
     const size_t lds_jac_use = jac_lds ? lds_jac : size_t(4 * (w.max_q / 2)) * 8;
 
-    hipLaunchKernelGGL(k_init_a, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb, P.info,
-                       w.from_pred ? 1 : 0, prm.a_mode, prm.a_value, a.ritz, a_lo, b_hi);
+    {
+      KScope k_(a.tm, MI_K_SETUP, s);
+      hipLaunchKernelGGL(k_init_a, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb, P.info,
+                         w.from_pred ? 1 : 0, prm.a_mode, prm.a_value, a.ritz, a_lo, b_hi);
+    }
     // start basis X of the first iteration
     const T* X = V0;
     if (w.from_pred) {
-      hipLaunchKernelGGL(k_warm_copy<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.ptall, V);
+      {
+        KScope k_(a.tm, MI_K_SETUP, s);
+        hipLaunchKernelGGL(k_warm_copy<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.ptall, V);
+      }
       X = V;
     }
     int xslab = -1;  // slab holding X (-1: X lives in V0 / V)
     auto chol = [&](float* s32) {
+      KScope k_(a.tm, MI_K_CHOL, s);
       launch_chol_blk(w.sd, w.nb, G, Wk, Rinv, s32, a.status, w.max_ld, P.lds_max, s);
     };
     for (int t = 0; t < w.T; ++t) {
@@ -534,8 +554,11 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       const bool rr_now = last || prm.rr_every;
       int ycur = -1;
       for (int pass = 0; pass < w.passes; ++pass) {
-        hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
-                           a_lo, b_hi, coef, L.coef_stride, w.m);
+        {
+          KScope k_(a.tm, MI_K_SETUP, s);
+          hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
+                             a_lo, b_hi, coef, L.coef_stride, w.m);
+        }
         int free_s[3], nf = 0;
         for (int i = 0; i < 4 && nf < 3; ++i)
           if (i != xslab) free_s[nf++] = i;
@@ -543,24 +566,36 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         const T* cur = X;
         for (int k = 0; k < w.m; ++k) {
           T* out = slab[free_s[k % 3]];
-          launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, cur, prev, out,
-                         coef, L.coef_stride, k, s);
+          {
+            KScope k_(a.tm, MI_K_SPMM, s);
+            launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, cur, prev, out,
+                           coef, L.coef_stride, k, s);
+          }
           prev = cur;
           cur = out;
           ycur = free_s[k % 3];
         }
         if (pass < w.passes - 1) {
           // span-preserving Cholesky-QR between passes
-          launch_gram<T>(w.gt, w.n_gt, w.tall, slab[ycur], slab[ycur], nullptr, part, s);
-          launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+          {
+            KScope k_(a.tm, MI_K_GRAM, s);
+            launch_gram<T>(w.gt, w.n_gt, w.tall, slab[ycur], slab[ycur], nullptr, part, s);
+          }
+          {
+            KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
+            launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+          }
           chol(dbl ? nullptr : S32);
           int dst = -1;
           for (int i = 0; i < 4; ++i)
             if (i != ycur && i != xslab) dst = i;
-          launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
-                              dbl ? reinterpret_cast<const T*>(Rinv)
-                                  : reinterpret_cast<const T*>(S32),
-                              w.tall, slab[dst], w.nch, s);
+          {
+            KScope k_(a.tm, MI_K_ROWMUL, s);
+            launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
+                                dbl ? reinterpret_cast<const T*>(Rinv)
+                                    : reinterpret_cast<const T*>(S32),
+                                w.tall, slab[dst], w.nch, s);
+          }
           X = slab[dst];
           xslab = dst;
         }
@@ -571,42 +606,108 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         if (i != ycur) wsl = i;
       T* Wm = slab[wsl];
       // W = L Y;  G = Y^T Y, H = Y^T W (one dual Gram pass);  R^T R = G
-      launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
-                     L.coef_stride, w.m, s);
-      launch_gram<T>(w.gt, w.n_gt, w.tall, Y, Y, Wm, part, s);
-      launch_gram_reduce(w.gr, w.n_gr, w.small, part, true, G, H, s);
+      {
+        KScope k_(a.tm, MI_K_SPMM, s);
+        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
+                       L.coef_stride, w.m, s);
+      }
+      {
+        KScope k_(a.tm, MI_K_GRAM, s);
+        launch_gram<T>(w.gt, w.n_gt, w.tall, Y, Y, Wm, part, s);
+      }
+      {
+        KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
+        launch_gram_reduce(w.gr, w.n_gr, w.small, part, true, G, H, s);
+      }
       // T1 = H Rinv
       if (!rr_now) {
         // intermediate iteration: Cholesky-QR of Y; the filter's lower bound
         // follows the largest Rayleigh quotient of the new basis
         chol(dbl ? nullptr : S32);
-        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
-        if (prm.adapt) launch_rq_max(w.sd, w.nb, Rinv, T1, a_lo, s);
-        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small,
-                            dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
-                            w.tall, V, w.nch, s);
+        {
+          KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
+          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
+        }
+        if (prm.adapt) {
+          KScope k_(a.tm, MI_K_RQ_MAX, s);
+          launch_rq_max(w.sd, w.nb, Rinv, T1, a_lo, s);
+        }
+        {
+          KScope k_(a.tm, MI_K_ROWMUL, s);
+          launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small,
+                              dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
+                              w.tall, V, w.nch, s);
+        }
         X = V;
         xslab = -1;
         continue;
       }
       // Rayleigh-Ritz: A = Rinv^T H Rinv = Z Theta Z^T,  V = Y Rinv Z
       chol(nullptr);
-      launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
-      launch_gram<double>(w.gts, w.n_gts, w.small, Rinv, T1, nullptr, part, s);
-      launch_gram_reduce(w.grs, w.n_grs, w.small, part, false, Am, nullptr, s);
-      launch_jacobi_init(w.sd, w.nb, Am, pk, Z, conv, s);
-      // the last iteration gets the requested tolerance; intermediate ones
-      // (rr_every) only need a roughly Ritz-ordered basis of the span
-      const double jtol = last ? prm.jacobi_tol : std::max(prm.jacobi_tol, 1e-8);
-      for (int sw = 0; sw < prm.max_sweeps; ++sw) {
-        launch_jacobi_sweep(w.sd, w.nb, pk, lg, conv, jtol, jac_lds, lds_jac_use, s);
-        launch_apply_rot(w.sd, w.nb, w.max_q, lg, conv, Z, P.lds_max, s);
+      {
+        KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
+        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
       }
-      launch_rr_finish(w.sd, w.nb, pk, conv, a.ritz, perm, a_lo, prm.adapt, a.status,
-                       std::max(1e-10, 10.0 * jtol), s);
-      launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S64, w.nchs, s);
+      {
+        KScope k_(a.tm, MI_K_GRAM_SMALL, s);
+        launch_gram<double>(w.gts, w.n_gts, w.small, Rinv, T1, nullptr, part, s);
+      }
+      {
+        KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
+        launch_gram_reduce(w.grs, w.n_grs, w.small, part, false, Am, nullptr, s);
+      }
+      if (prm.eig == MI_EIG_TRIDIAG && tri_eig_supported(w.max_ld)) {
+        // Householder tridiagonalisation, multisection, inverse iteration;
+        // Z / T1 / S64 double as per-thread scratch before Z is written
+        {
+          KScope k_(a.tm, MI_K_EIG_REDUCE, s);
+          launch_tri_reduce(w.sd, w.nb, w.max_ld, Am, Wk, tri, a.status, s);
+        }
+        {
+          KScope k_(a.tm, MI_K_EIG_VALUES, s);
+          launch_tri_bisect(w.sd, w.nb, w.max_p, tri, a.ritz, perm, a_lo, prm.adapt, a.status, s);
+        }
+        {
+          KScope k_(a.tm, MI_K_EIG_VECTORS, s);
+          launch_tri_vectors(w.sd, w.nb, w.max_p, tri, Z, T1, S64, a.status, s);
+        }
+        {
+          KScope k_(a.tm, MI_K_EIG_BACK, s);
+          launch_tri_back(w.sd, w.nb, w.max_ld, S64, Wk, tri, Z, s);
+        }
+      } else {
+        {
+          KScope k_(a.tm, MI_K_JACOBI_INIT, s);
+          launch_jacobi_init(w.sd, w.nb, Am, pk, Z, conv, s);
+        }
+        // the last iteration gets the requested tolerance; intermediate ones
+        // (rr_every) only need a roughly Ritz-ordered basis of the span
+        const double jtol = last ? prm.jacobi_tol : std::max(prm.jacobi_tol, 1e-8);
+        for (int sw = 0; sw < prm.max_sweeps; ++sw) {
+          {
+            KScope k_(a.tm, MI_K_JACOBI_SWEEP, s);
+            launch_jacobi_sweep(w.sd, w.nb, pk, lg, conv, jtol, jac_lds, lds_jac_use, s);
+          }
+          {
+            KScope k_(a.tm, MI_K_APPLY_ROT, s);
+            launch_apply_rot(w.sd, w.nb, w.max_q, lg, conv, Z, P.lds_max, s);
+          }
+        }
+        {
+          KScope k_(a.tm, MI_K_RR_FINISH, s);
+          launch_rr_finish(w.sd, w.nb, pk, conv, a.ritz, perm, a_lo, prm.adapt, a.status,
+                           std::max(1e-10, 10.0 * jtol), s);
+        }
+      }
+      {
+        KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
+        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S64, w.nchs, s);
+      }
       // S <- columns of Rinv Z in ascending Ritz order (FP32 copy for FP32 products)
-      launch_perm_cast(w.sd, w.nb, S64, perm, dbl ? nullptr : S32, dbl ? T1 : nullptr, s);
+      {
+        KScope k_(a.tm, MI_K_PERM_CAST, s);
+        launch_perm_cast(w.sd, w.nb, S64, perm, dbl ? nullptr : S32, dbl ? T1 : nullptr, s);
+      }
       const T* Sm = dbl ? reinterpret_cast<const T*>(T1) : reinterpret_cast<const T*>(S32);
       T* dstV;
       int dslab = -1;
@@ -617,23 +718,38 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           if (i != ycur) dslab = i;
         dstV = slab[dslab];
       }
-      launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, dstV, w.nch, s);
+      {
+        KScope k_(a.tm, MI_K_ROWMUL, s);
+        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, dstV, w.nch, s);
+      }
       if (!last) {
         X = V;
         xslab = -1;
       } else {
         // final Cholesky-QR: V = Vtmp R^-1 (upper triangular: keeps the span of
         // every leading column set, hence the Ritz order)
-        launch_gram<T>(w.gt, w.n_gt, w.tall, dstV, dstV, nullptr, part, s);
-        launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+        {
+          KScope k_(a.tm, MI_K_GRAM, s);
+          launch_gram<T>(w.gt, w.n_gt, w.tall, dstV, dstV, nullptr, part, s);
+        }
+        {
+          KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
+          launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+        }
         chol(dbl ? nullptr : S32);
-        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, dstV, w.small,
-                            dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
-                            w.tall, V, w.nch, s);
+        {
+          KScope k_(a.tm, MI_K_ROWMUL, s);
+          launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, dstV, w.small,
+                              dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
+                              w.tall, V, w.nch, s);
+        }
       }
     }
     if (w.T == 0 && !w.from_pred)
-      hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+      {
+        KScope k_(a.tm, MI_K_SETUP, s);
+        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+      }
   }
 }
 
@@ -657,6 +773,8 @@ static mi_status check_params(const mi_oi_params* prm) {
   MI_CHECK_ARG(prm->max_sweeps >= 1 && prm->max_sweeps <= 100, "max_sweeps out of range");
   MI_CHECK_ARG(prm->a_mode >= 0 && prm->a_mode <= 2, "a_mode unknown");
   MI_CHECK_ARG(prm->rr_every == 0 || prm->rr_every == 1, "rr_every must be 0 or 1");
+  MI_CHECK_ARG(prm->eig == MI_EIG_TRIDIAG || prm->eig == MI_EIG_JACOBI, "eig solver %d unknown",
+               prm->eig);
   MI_CHECK_ARG(prm->jacobi_tol > 0 && prm->jacobi_tol < 1e-3, "jacobi_tol out of range");
   return MI_OK;
 }
@@ -706,9 +824,9 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
     P = np.release();
     ctx->oi_plan = P;
   }
-  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws)};
+  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer};
   hipStream_t s = (hipStream_t)stream;
-  if (per_block) {
+  if (per_block || ctx->timer) {
     if (prm->precision == MI_FP64)
       enqueue<double>(*P, a, s);
     else

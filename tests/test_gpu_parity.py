@@ -144,14 +144,16 @@ def test_span_identity_before_convergence(ctx, precision):
 
 # ------------------------------------------------------------------ single submesh, FP64
 
-def test_grid_single_fp64(ctx):
-    """32x32 grid, c = 50, 30 iterations from a seeded random orthonormal start, FP64."""
+@pytest.mark.parametrize("eig", [mis._lib.MI_EIG_TRIDIAG, mis._lib.MI_EIG_JACOBI])
+def test_grid_single_fp64(ctx, eig):
+    """32x32 grid, c = 50, 30 iterations from a seeded random orthonormal start,
+    FP64 (the grid's symmetry gives repeated eigenvalues inside the block)."""
     bs = W.grid_single()
     up = Uploaded(bs)
     Lp = up.laplacian(ctx)
     V0 = up.starts(torch.float64)
     prm = mis.OiParams(precision=mis.MI_FP64, warm=mis.MI_WARM_GIVEN, T0=30, m0=8, passes0=1,
-                       adapt=1, max_sweeps=15)
+                       adapt=1, max_sweeps=15, eig=eig)
     V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
     c = torch.full((1,), 50, dtype=torch.int32, device="cuda:0")
     X = up.coords.double()
@@ -213,6 +215,69 @@ def test_determinism_and_graph_replay(ctx, chain_small):
         outs.append(V.clone())
         torch.ones(1000, device="cuda:0").sum().item()  # eager work between replays
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2])
+
+
+def test_event_timed_launches_match_graph(ctx, chain_small):
+    """The per-kernel timer launches the same kernels eagerly: bitwise the
+    same result as the graph replay, and every class of the path is seen."""
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    V = torch.empty(int(up.blocks.u_off[-1]), device="cuda:0")
+    mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0, V=V)
+    torch.cuda.synchronize()
+    ref = V.clone()
+    ctx.set_timing(True)
+    try:
+        V.zero_()
+        mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0, V=V)
+        torch.cuda.synchronize()
+        kt = ctx.kernel_times()
+    finally:
+        ctx.set_timing(False)
+    assert torch.equal(V, ref)
+    for k in ("spmm", "gram", "chol", "rowmul", "eig_reduce", "eig_values", "eig_vectors",
+              "eig_back"):
+        ms, n = kt[k]
+        assert n > 0 and ms > 0, (k, kt[k])
+    # waves x (T (passes m + 1)) Chebyshev / L Y products
+    lv = np.asarray(up.bs.level)
+    n_spmm = sum((5 * (2 * 10 + 1)) if l == 0 else (3 * (2 * 10 + 1)) for l in np.unique(lv))
+    assert kt["spmm"][1] == n_spmm
+    assert kt["project"][1] == 0
+    with pytest.raises(mis.MiError):
+        ctx.kernel_times()  # timing is off again
+
+
+@pytest.mark.parametrize("rr_every", [0, 1])
+def test_eigen_solvers_agree(ctx, chain_small, rr_every):
+    """Tridiagonal (Householder + multisection + inverse iteration) and
+    Jacobi Rayleigh-Ritz give the same Ritz values and subspaces, and both
+    meet the oracle."""
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    out = {}
+    for eig in (mis._lib.MI_EIG_TRIDIAG, mis._lib.MI_EIG_JACOBI):
+        V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, warm_params(eig=eig, rr_every=rr_every),
+                                   V0=V0)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0, st
+        _chain_check(up, V, ritz, st, 100, sample=[0, up.blocks.n_blocks - 1])
+        out[eig] = (V.clone(), ritz.cpu().numpy())
+    (Vt, rt_), (Vj, rj) = out[0], out[1]
+    # converged Ritz values (the first c of every block) match the oracle's
+    # eigenvalues to the FP32 floor u32 ||L|| of the projected matrix (the top
+    # of the tracked window is not converged: it feeds the successors' filter
+    # bounds and may differ between the solvers)
+    t_off = np.concatenate([[0], np.cumsum(up.blocks.p)])
+    for b in range(up.blocks.n_blocks):
+        _, lam, _ = oracle_block(up, b, k=int(up.blocks.p[b]) + 1)
+        tol = 2.0 ** -24 * lam[-1]
+        for r in (rt_, rj):
+            assert np.abs(r[t_off[b]:t_off[b] + 100] - lam[:100]).max() < tol, b
+    for b in range(up.blocks.n_blocks):
+        assert S.sin_theta_max(up.slab(Vt, b)[:, :100], up.slab(Vj, b)[:, :100]) < 2e-5
 
 
 def test_per_block_reference_path(ctx, chain_small):

@@ -85,3 +85,15 @@ def test_choose_and_encdec_workspace_queries():
     assert L.lib().mi_choose_c_workspace_size(None, b.ref, C.byref(n)) == 0 and n.value > 0
     assert L.lib().mi_encdec_workspace_size(None, b.ref, L.MI_FP32, C.byref(n)) == 0
     assert L.lib().mi_encdec_workspace_size(None, b.ref, 5, C.byref(n)) == L.MI_ERR_ARG
+
+
+def test_kernel_class_table_and_timer_arguments():
+    import ctypes as C
+    lib = L.lib()
+    names = [lib.mi_kernel_class_name(k).decode() for k in range(L.MI_K_COUNT)]
+    assert names == L.KERNEL_CLASSES
+    assert lib.mi_kernel_class_name(-1) is None and lib.mi_kernel_class_name(L.MI_K_COUNT) is None
+    ms = (C.c_double * L.MI_K_COUNT)()
+    n = (C.c_int64 * L.MI_K_COUNT)()
+    assert lib.mi_ctx_kernel_times(None, ms, n) == L.MI_ERR_ARG
+    assert lib.mi_ctx_set_timing(None, 1) == L.MI_ERR_ARG

@@ -110,9 +110,10 @@ __device__ __forceinline__ double hash_unit(int i, int j) {
 // partial squared norms; everyone forms the reflector H_k = I - beta v v^T
 // (v zero up to k, alpha = -sign(x_{k+1}) ||x||), computes p = beta A v with
 // half-wavefront reductions, then A -= v w^T + w v^T with
-// w = p - (beta/2)(v^T p) v.  Row and column k are zeroed afterwards, so the
-// trailing update runs over the full register tile without predicates.  Two
-// barriers per step; the LDS vectors are double-buffered by step parity.
+// w = p - (beta/2)(v^T p) v.  v and w are zero at and above k, so finished
+// rows and columns keep their (unused) values and never feed the trailing
+// matrix; whole finished 32-blocks are skipped.  Two barriers per step; the
+// LDS vectors are double-buffered by step parity.
 template <int RT>
 __global__ void __launch_bounds__(1024)
     k_tri_reduce(const SmallDesc* __restrict__ sds, const double* __restrict__ A,
@@ -155,10 +156,8 @@ __global__ void __launch_bounds__(1024)
       for (int a = 0; a < RT; ++a) {
         const int i = tr + 32 * a;
         double x = col_of<RT>(w[a], kb);
-        if (i == k) {
-          dd[k] = x;
-          x = 0.0;
-        }
+        if (i == k) dd[k] = x;
+        if (i <= k) x = 0.0;
         xcol[par][i] = x;
         ss += x * x;
       }
@@ -181,18 +180,20 @@ __global__ void __launch_bounds__(1024)
     // v_i = x_i except v_{k+1} = x_{k+1} - alpha (read again from LDS where
     // needed: keeps the register tile within the 128-VGPR budget)
     auto vat = [&](int i) { return xcol[par][i] - (i == k + 1 ? al : 0.0); };
+    // blocks of 32 rows / columns that lie entirely at or left of k are done:
+    // skipped with uniform branches
+    const int ka = (k + 1) >> 5;
     double vc[RT];
 #pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int j = tc + 32 * b;
-      vc[b] = xcol[par][j] - (j == k + 1 ? al : 0.0);
-    }
+    for (int b = 0; b < RT; ++b) vc[b] = b < ka ? 0.0 : vat(tc + 32 * b);
     double vp = 0.0;
 #pragma unroll
     for (int a = 0; a < RT; ++a) {
+      if (a < ka) continue;
       double sa = 0.0;
 #pragma unroll
-      for (int b = 0; b < RT; ++b) sa = fma(w[a][b], vc[b], sa);
+      for (int b = 0; b < RT; ++b)
+        if (b >= ka) sa = fma(w[a][b], vc[b], sa);
       const double pa = be * half_sum(sa);
       vp = fma(vat(tr + 32 * a), pa, vp);
       if (tc == 0) pcol[par][tr + 32 * a] = pa;
@@ -217,19 +218,20 @@ __global__ void __launch_bounds__(1024)
     const double K = 0.5 * be * vtp;
     double wc[RT];
 #pragma unroll
-    for (int b = 0; b < RT; ++b) wc[b] = pcol[par][tc + 32 * b] - K * vc[b];
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      const double va = vat(tr + 32 * a);
-      const double wa = pcol[par][tr + 32 * a] - K * va;
-#pragma unroll
-      for (int b = 0; b < RT; ++b) w[a][b] -= va * wc[b] + wa * vc[b];
+    for (int b = 0; b < RT; ++b) {
+      const int j = tc + 32 * b;
+      wc[b] = (b < ka || j <= k) ? 0.0 : pcol[par][j] - K * vc[b];
     }
 #pragma unroll
-    for (int a = 0; a < RT; ++a)
+    for (int a = 0; a < RT; ++a) {
+      if (a < ka) continue;
+      const int i = tr + 32 * a;
+      const double va = vat(i);
+      const double wa = i <= k ? 0.0 : pcol[par][i] - K * va;
 #pragma unroll
       for (int b = 0; b < RT; ++b)
-        if ((tr == kt && a == kb) || (tc == kt && b == kb)) w[a][b] = 0.0;
+        if (b >= ka) w[a][b] -= va * wc[b] + wa * vc[b];
+    }
   }
   // the last 2 x 2 (or 1 x 1) block is already tridiagonal
 #pragma unroll

@@ -384,23 +384,25 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
     for (int b = 0; b < RT; ++b) {
       const int j = tc + 32 * b;
-      rowbuf[0][j] = (j < p) ? w[0][b] : 0.0;
+      rowbuf[0][j] = (j > 0 && j < p) ? w[0][b] : 0.0;  // zero at the diagonal, like every published row
     }
     if (tc == 0) rdiag[0] = 1.0;
   }
   for (int k = 0; k < p; ++k) {
     __syncthreads();
+    // rank-1 update with row k of R (zero at and left of k, and past p):
+    // 32-row blocks left of k are skipped with uniform branches; entries
+    // below the diagonal collect harmless garbage that is never read
     const double* rb = rowbuf[k & 1];
+    const int ka = (k + 1) >> 5;
 #pragma unroll
     for (int a = 0; a < RT; ++a) {
-      const int i = tr + 32 * a;
-      if (i > k && i < p) {
-        const double ri = rb[i];
+      if (a < ka) continue;
+      const double ri = rb[tr + 32 * a];
 #pragma unroll
-        for (int b = 0; b < RT; ++b) {
-          const int j = tc + 32 * b;
-          if (j >= i && j < p) w[a][b] -= ri * rb[j];
-        }
+      for (int b = 0; b < RT; ++b) {
+        if (b < a) continue;
+        w[a][b] -= ri * rb[tc + 32 * b];
       }
     }
     const int k1 = k + 1;
@@ -474,20 +476,30 @@ __global__ void __launch_bounds__(1024)
         colbuf[k & 1][i] = (i < k) ? Rg[int64_t(i) * ld + k] : 0.0;
       }
   }
+  // Column km of R is published by the threads with tc == km % 32, i.e.
+  // every 32 steps: each thread loads its next column one round ahead so
+  // that no global load sits on the step's critical path.
+  int my_km = (p - 2) - (((p - 2) - tc) & 31);  // largest km <= p-2 with km % 32 == tc
+  double pre[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) {
+    const int i = tr + 32 * a;
+    pre[a] = (my_km >= 0 && i < my_km) ? Rg[int64_t(i) * ld + my_km] : 0.0;
+  }
   for (int k = p - 1; k >= 0; --k) {
     __syncthreads();
+    // X[i][:] -= R[i][k] X[k][:]: the column is zero from row k on and the
+    // row zero left of k, so whole 32-blocks are skipped uniformly
     const double* xb = rowbuf[k & 1];
     const double* cb = colbuf[k & 1];
 #pragma unroll
     for (int a = 0; a < RT; ++a) {
-      const int i = tr + 32 * a;
-      if (i < k) {
-        const double rik = cb[i];
+      if (32 * a >= k) continue;
+      const double rik = cb[tr + 32 * a];
 #pragma unroll
-        for (int b = 0; b < RT; ++b) {
-          const int j = tc + 32 * b;
-          if (j >= k && j < p) x[a][b] -= rik * xb[j];
-        }
+      for (int b = 0; b < RT; ++b) {
+        if (32 * b + 31 < k || b < a) continue;
+        x[a][b] -= rik * xb[tc + 32 * b];
       }
     }
     const int km = k - 1;
@@ -507,11 +519,14 @@ __global__ void __launch_bounds__(1024)
             }
           }
       }
-      if (tc == (km & 31)) {  // column k-1 of R
+      if (tc == (km & 31)) {  // column k-1 of R (loaded a round earlier)
+#pragma unroll
+        for (int a = 0; a < RT; ++a) colbuf[km & 1][tr + 32 * a] = pre[a];
+        my_km -= 32;
 #pragma unroll
         for (int a = 0; a < RT; ++a) {
           const int i = tr + 32 * a;
-          colbuf[km & 1][i] = (i < km) ? Rg[int64_t(i) * ld + km] : 0.0;
+          pre[a] = (my_km >= 0 && i < my_km) ? Rg[int64_t(i) * ld + my_km] : 0.0;
         }
       }
     }

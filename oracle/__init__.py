@@ -23,7 +23,4 @@ iterations  paper-literal orthogonal iteration (Alg. 1) and dynamic OI (Alg. 2),
             and the exact span of a polynomially filtered subspace iteration
 exact       brute-force integer characteristic polynomials, Sturm bisection and
             spanning-tree counts for meshes of <= 10 vertices
-merge       degree-weighted average of overlapped submeshes (Alg. 3)
-adjoint     float64 reference gradient of encode/decode through unrolled
-            iterations (torch CPU autograd over the oracle's own steps)
 """

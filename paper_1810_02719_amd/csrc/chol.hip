@@ -1,0 +1,278 @@
+// Cholesky factor and its inverse for the Cholesky-QR step (Section 4,
+// Alg. 1, Onorm), blocked for FP64 MFMA, one workgroup per block.
+//
+// The scaled Gram G^ = D G D (D = diag(G)^-1/2) is factored as G^ = R^T R by
+// right-looking block elimination over 16-wide panels K.  The same block
+// row operations, applied to the identity, accumulate M = R^-T:
+//
+//   panel K:    R_KK = chol(G^_KK), M_KK = R_KK^-T        (one wavefront)
+//               R_K,J = R_KK^-T G^_K,J        for J > K   (MFMA)
+//               M_K  <- R_KK^-T M_K                       (MFMA)
+//   trailing:   G^_I,J -= R_K,I^T R_K,J       for K < I <= J
+//               M_I    -= R_K,I^T M_K         for I > K
+//
+// Both trailing updates are products of the same 16-row panel buffer (R row
+// panel next to the updated M row panel), so they share one MFMA routine.
+// Rinv = D M^T.
+//
+// Storage: 16 x 16 tiles in the FP64 MFMA accumulator layout, one register
+// slot per unordered tile pair (a <= b).  The slot holds G^(a, b) until panel
+// a has consumed it, then M(b, a): the Gram tile dies in the same step in
+// which that M tile is born, so G^ and M together fit in one triangle's
+// worth of registers.
+#include "small.hpp"
+
+namespace mis {
+
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr double CHOL_PIV_TOL = 1e-13;  // pivot floor of the unit-diagonal Gram
+
+// Orders one wavefront's LDS writes before its lanes read each other's
+// values (the compiler may otherwise move a read above another lane's write).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ d4v mfma64(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// acc + sign * sum_{t<16} P[t][16 r + m] Q[t][16 c + n] on one 16 x 16 tile.
+__device__ __forceinline__ d4v tile_tn(d4v acc, const double* P, int ldp, int r,
+                                       const double* Q, int ldq, int c, double sign, int lane) {
+  const int mi = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4) {
+    const double a = sign * P[(kk + kq) * ldp + 16 * r + mi];
+    const double b = Q[(kk + kq) * ldq + 16 * c + mi];
+    acc = mfma64(a, b, acc);
+  }
+  return acc;
+}
+
+// One wavefront factors the diagonal tile G^_KK = R^T R held in its
+// accumulator registers (element (mq + 4 q, mi) in g[q]) by the same row
+// operations as the panels, applied to the identity: returns M_KK = R^-T in
+// the same layout and writes R^-1 = M^T to Di.  Row k of the working matrix
+// and of M travels through a 32-double LDS buffer between wavefront-scope
+// fences.  Entries below the diagonal of the working matrix collect values
+// that are never read.
+__device__ d4v diag_factor(d4v g, double* rowbuf, double* Di, int ldd, int lane, int* fl) {
+  const int mi = lane & 15, mq = lane >> 4;
+  d4v mm;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) mm[q] = (mq + 4 * q == mi) ? 1.0 : 0.0;
+  for (int k = 0; k < 16; ++k) {
+    const int kq = k >> 2;
+    if (mq == (k & 3)) {
+      rowbuf[mi] = kq == 0 ? g[0] : kq == 1 ? g[1] : kq == 2 ? g[2] : g[3];
+      rowbuf[16 + mi] = kq == 0 ? mm[0] : kq == 1 ? mm[1] : kq == 2 ? mm[2] : mm[3];
+    }
+    wave_sync();
+    double piv = rowbuf[k];
+    if (!(piv > CHOL_PIV_TOL)) {
+      *fl |= isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE;
+      piv = CHOL_PIV_TOL;
+    }
+    const double inv = 1.0 / sqrt(piv);
+    const double rkj = rowbuf[mi] * inv;       // R[k][j]
+    const double mkj = rowbuf[16 + mi] * inv;  // new M[k][j]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = mq + 4 * q;
+      if (i == k) {
+        mm[q] = mkj;
+      } else if (i > k) {
+        const double rki = rowbuf[i] * inv;
+        g[q] = fma(-rki, rkj, g[q]);
+        mm[q] = fma(-rki, mkj, mm[q]);
+      }
+    }
+    wave_sync();  // all reads of row k before the next row is written
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Di[mi * ldd + mq + 4 * q] = mm[q];
+  return mm;
+}
+
+}  // namespace
+
+// NT = 16-tiles per dimension of the widest block of the launch
+// (ld <= 16 NT <= 192).
+template <int NT>
+__global__ void __launch_bounds__(1024)
+    k_chol_mfma(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
+                double* __restrict__ Rinv, float* __restrict__ S32, int32_t* __restrict__ status) {
+  constexpr int NPAIR = NT * (NT + 1) / 2;    // tile pairs (a <= b)
+  constexpr int SLOTS = (NPAIR + 15) / 16;    // per wavefront
+  constexpr int LDB = 16 * NT + 4;            // panel buffer row stride (doubles)
+  constexpr int LDD = 17;
+  __shared__ double bufA[16 * LDB];           // old panel: G^ row K | M row K
+  __shared__ double bufB[16 * LDB];           // new panel: R row K  | M row K
+  __shared__ double Dg[16 * LDD];             // R_KK^-1
+  __shared__ double rowbuf[32];
+  __shared__ double dsc[16 * NT];
+  __shared__ int flag;
+
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const int nk = (p + 15) >> 4;  // panels of this block (<= NT)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: slot logic is scalar
+  const int mi = lane & 15, mq = lane >> 4;  // tile element (mq + 4 q, mi)
+  const double* Gb = G + d.m_off;
+
+  if (tid == 0) flag = 0;
+  for (int i = tid; i < 16 * NT; i += 1024) {
+    double v = 1.0;
+    if (i < p) {
+      const double g = Gb[int64_t(i) * ld + i];
+      if (!isfinite(g)) atomicOr(&flag, MI_BLOCK_NONFINITE);
+      else if (!(g > 0.0)) atomicOr(&flag, MI_BLOCK_NOT_PD);
+      v = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 0.0;
+    }
+    dsc[i] = v;
+  }
+  __syncthreads();
+
+  // slot s of this wavefront: pair t = wave + 16 s in column-major upper
+  // order, a <= b
+  int ta[SLOTS], tb[SLOTS];
+  d4v reg[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int t = wave + 16 * s;
+    int b = 0;
+    while ((b + 1) * (b + 2) / 2 <= t) ++b;
+    const int a = t - b * (b + 1) / 2;
+    ta[s] = t < NPAIR ? a : -1;
+    tb[s] = t < NPAIR ? b : -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * a + mq + 4 * q, j = 16 * b + mi;
+      double v = 0.0;
+      if (t < NPAIR) {
+        if (i < p && j < p) v = Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
+        else if (i == j) v = 1.0;  // identity padding
+      }
+      reg[s][q] = v;
+    }
+  }
+
+  for (int K = 0; K < nk; ++K) {
+    // launder the slot indices so that the compiler recomputes the per-slot
+    // LDS addresses each step instead of keeping dozens of them live
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) asm volatile("" : "+s"(ta[s]), "+s"(tb[s]));
+    // 1: publish the Gram row panel and the old M row panel; the wavefront
+    // that owns the diagonal tile factors it (M_KK = R_KK^-T into its slot
+    // and the new M panel, R_KK^-1 into Dg)
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int a = ta[s], b = tb[s];
+      if (a == K) {
+        if (b == K) {
+          int fl = 0;
+          reg[s] = diag_factor(reg[s], rowbuf, Dg, LDD, lane, &fl);
+          if (lane == 0 && fl) atomicOr(&flag, fl);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bufA[(mq + 4 * q) * LDB + 16 * b + mi] = reg[s][q];
+        }
+      } else if (b == K && a >= 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bufA[(mq + 4 * q) * LDB + 16 * a + mi] = reg[s][q];
+      }
+    }
+    __syncthreads();
+    // 3: R row panel and new M row panel (both: R_KK^-T times the old panel)
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int a = ta[s], b = tb[s];
+      if (a == K && b > K) {
+        d4v acc = {0.0, 0.0, 0.0, 0.0};
+        acc = tile_tn(acc, Dg, LDD, 0, bufA, LDB, b, 1.0, lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * b + mi] = acc[q];
+        reg[s] = d4v{0.0, 0.0, 0.0, 0.0};  // the slot now holds M(b, a) = 0
+      } else if (a == K && b == K) {
+        // M_KK (already in the slot) joins the new M panel; written only now
+        // because other wavefronts read bufB in the previous step 4
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * K + mi] = reg[s][q];
+      } else if (b == K && a >= 0) {
+        d4v acc = {0.0, 0.0, 0.0, 0.0};
+        acc = tile_tn(acc, Dg, LDD, 0, bufA, LDB, a, 1.0, lane);
+        reg[s] = acc;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * a + mi] = acc[q];
+      }
+    }
+    __syncthreads();
+    // 4: trailing updates of G^ (a, b > K) and of M (row b > K, column a <= K)
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int a = ta[s], b = tb[s];
+      if (a > K) reg[s] = tile_tn(reg[s], bufB, LDB, a, bufB, LDB, b, -1.0, lane);
+      else if (b > K && a >= 0) reg[s] = tile_tn(reg[s], bufB, LDB, b, bufB, LDB, a, -1.0, lane);
+      __builtin_amdgcn_sched_barrier(0);  // one tile's operands live at a time
+    }
+    // the next step 1 writes bufA and Dg only; the barrier after it orders
+    // these bufB reads before the next step 3
+  }
+
+  // Rinv[r][c] = dsc[r] M[c][r] for r <= c < p; zero elsewhere.  Slot (a, b)
+  // holds M(b, a) and writes the two transposed tiles (a, b) and (b, a).
+  double* Rb = Rinv + d.m_off;
+  float* Sb = S32 ? S32 + d.m_off : nullptr;
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int a = ta[s], b = tb[s];
+    if (a < 0) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = mq + 4 * q;
+      // M(b, a)[m][mi] = M[16 b + m][16 a + mi] -> Rinv[16 a + mi][16 b + m]
+      const int r = 16 * a + mi, c = 16 * b + m;
+      if (r < ld && c < ld) {
+        const double v = (r <= c && c < p) ? dsc[r] * reg[s][q] : 0.0;
+        Rb[int64_t(r) * ld + c] = v;
+        if (Sb) Sb[int64_t(r) * ld + c] = (float)v;
+      }
+      if (a != b) {  // the tile below the diagonal
+        const int r2 = 16 * b + m, c2 = 16 * a + mi;
+        if (r2 < ld && c2 < ld) {
+          Rb[int64_t(r2) * ld + c2] = 0.0;
+          if (Sb) Sb[int64_t(r2) * ld + c2] = 0.0f;
+        }
+      }
+    }
+  }
+  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
+}
+
+bool launch_chol_mfma(const SmallDesc* sd, int nb, const double* G, double* Rinv, float* S32,
+                      int32_t* status, int max_ld, hipStream_t s) {
+  switch ((max_ld + 31) / 32) {
+#define MI_CHOL_CASE(N)                                                                         \
+  case N:                                                                                       \
+    hipLaunchKernelGGL(k_chol_mfma<2 * N>, dim3(nb), dim3(1024), 0, s, sd, G, Rinv, S32, status); \
+    return true;
+    MI_CHOL_CASE(1)
+    MI_CHOL_CASE(2)
+    MI_CHOL_CASE(3)
+    MI_CHOL_CASE(4)
+    MI_CHOL_CASE(5)
+    MI_CHOL_CASE(6)
+#undef MI_CHOL_CASE
+    default:
+      return false;
+  }
+}
+
+}  // namespace mis

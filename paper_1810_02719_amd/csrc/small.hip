@@ -21,122 +21,8 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// ------------------------------------------------------------------ Cholesky + inverse
-// G -> column scaling D = diag(G)^-1/2, G^ = D G D = R^^T R^ (right-looking,
-// one barrier per step: the wave that owns row k+1 finishes its last update,
-// takes the pivot from lane 0 by a shuffle and scales the row; pivots below
-// piv_tol are raised to piv_tol and flagged), X = R^^-1 in place column by
-// column, Rinv = D X.  LDS selects the storage of the packed factor (typed
-// LDS pointer when true, the per-block global scratch when false).
-template <bool LDS>
-__global__ void __launch_bounds__(SMALL_THREADS)
-    k_chol_inv(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
-               double* __restrict__ Rinv, float* __restrict__ S32, double* __restrict__ pks,
-               int32_t* __restrict__ status) {
-  extern __shared__ double smem[];
-  __shared__ int flag;
-  const SmallDesc d = sds[blockIdx.x];
-  const int p = d.p, ld = d.ld, q = d.q;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NW = SMALL_THREADS / 64;
-  double* dsc = smem;
-  double* rdiag = smem + q;
-  double* tmp = smem + 2 * q;
-  double* W;
-  if constexpr (LDS)
-    W = smem + 3 * q;
-  else
-    W = pks + d.pk_off;
-  const double* Gb = G + d.m_off;
-  const double piv_tol = 1e-13;
-  if (tid == 0) flag = 0;
-  __syncthreads();
-  for (int i = tid; i < p; i += SMALL_THREADS) {
-    const double g = Gb[int64_t(i) * ld + i];
-    if (!isfinite(g)) atomicOr(&flag, MI_BLOCK_NONFINITE);
-    if (!(g > 0.0)) atomicOr(&flag, MI_BLOCK_NOT_PD);
-    dsc[i] = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 0.0;
-  }
-  __syncthreads();
-  for (int i = wave; i < p; i += NW) {
-    const double di = dsc[i];
-    for (int j = i + lane; j < p; j += 64)
-      W[pidx(i, j, p)] = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * di * dsc[j];
-  }
-  __syncthreads();
-  // row 0: unit pivot after scaling
-  if (wave == 0) {
-    if (lane == 0) rdiag[0] = 1.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < p - 1; ++k) {
-    const int rk = pidx(k, 0, p);  // row k starts at rk + k
-    for (int i = k + 1 + wave; i < p; i += NW) {
-      const double wki = W[rk + i];
-      const int ri = pidx(i, 0, p);
-      double piv = 0.0;
-      for (int j = i + lane; j < p; j += 64) {
-        const double v = W[ri + j] - wki * W[rk + j];
-        W[ri + j] = v;
-        if (j == i) piv = v;
-      }
-      if (i == k + 1) {  // last update of row k+1: factor it now
-        piv = __shfl(piv, 0, 64);
-        if (!(piv > piv_tol)) {
-          if (lane == 0) atomicOr(&flag, isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
-          piv = piv_tol;
-        }
-        const double rkk = sqrt(piv), inv = 1.0 / rkk;
-        for (int j = i + 1 + lane; j < p; j += 64) W[ri + j] *= inv;
-        if (lane == 0) rdiag[i] = rkk;
-      }
-    }
-    __syncthreads();
-  }
-  // in-place inverse of the upper factor, column by column: the diagonal
-  // slot of row i holds X_ii once column i is done, the strict upper part of
-  // column j still holds R^ while column j is being solved
-  for (int j = 0; j < p; ++j) {
-    const double xjj = 1.0 / rdiag[j];
-    for (int i = wave; i < j; i += NW) {
-      const int ri = pidx(i, 0, p);
-      double acc = 0.0;
-      for (int l = i + lane; l < j; l += 64) acc += W[ri + l] * W[pidx(l, j, p)];
-      acc = wave_sum(acc);
-      if (lane == 0) tmp[i] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < j; i += SMALL_THREADS) W[pidx(i, j, p)] = -tmp[i] * xjj;
-    if (tid == 0) W[pidx(j, j, p)] = xjj;
-    __syncthreads();
-  }
-  double* Rb = Rinv + d.m_off;
-  for (int i = wave; i < ld; i += NW) {
-    const double di = i < p ? dsc[i] : 0.0;
-    for (int j = lane; j < ld; j += 64) {
-      double v = 0.0;
-      if (i < p && j < p && i <= j) v = di * W[pidx(i, j, p)];
-      Rb[int64_t(i) * ld + j] = v;
-      if (S32) S32[d.m_off + int64_t(i) * ld + j] = (float)v;
-    }
-  }
-  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
-}
-
-void launch_chol_inv(const SmallDesc* sd, int nb, const double* G, double* Rinv, float* S32,
-                     double* pk_scratch, int32_t* status, bool lds, size_t lds_bytes,
-                     hipStream_t s) {
-  if (nb <= 0) return;
-  if (lds)
-    hipLaunchKernelGGL(k_chol_inv<true>, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, G, Rinv,
-                       S32, pk_scratch, status);
-  else
-    hipLaunchKernelGGL(k_chol_inv<false>, dim3(nb), dim3(SMALL_THREADS), lds_bytes, s, sd, G, Rinv,
-                       S32, pk_scratch, status);
-}
-
-// ------------------------------------------------------------------ blocked Cholesky + inverse
-// Same result as k_chol_inv with 32-wide panels, so that only the 32 x 32
+// Cholesky of the scaled Gram and the inverse factor for blocks wider than
+// 192 (narrower ones use the MFMA kernel in chol.hip), with 32-wide panels, so that only the 32 x 32
 // diagonal tiles are factored step by step (inside one wavefront, one tile
 // column per lane in registers, pivots and row entries broadcast by
 // shuffles); the panel solves, trailing updates and the blocked inverse are
@@ -330,242 +216,10 @@ __global__ void __launch_bounds__(256)
 }
 
 
-// ------------------------------------------------------------------ register Cholesky + inverse
-// For ld <= 32 RT: the p x p matrix lives in the registers of 1024 threads
-// laid out as a 32 x 32 grid; thread (tr, tc) owns the entries
-// (tr + 32 a, tc + 32 b), a, b < RT.  Right-looking Cholesky of the scaled
-// Gram, then X = R^-1 by Gauss-Jordan elimination from the bottom.  Each
-// step needs one barrier: the row that becomes the next pivot row lives in
-// one half-wavefront, which finishes its own update, takes the pivot by a
-// shuffle, scales the row and publishes it in a double-buffered LDS row.
-template <int RT>
-__global__ void __launch_bounds__(1024)
-    k_chol_reg(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
-               double* __restrict__ Wk, double* __restrict__ Rinv, float* __restrict__ S32,
-               int32_t* __restrict__ status) {
-  constexpr int LDM = 32 * RT;
-  __shared__ double dsc[LDM];
-  __shared__ double rdiag[LDM];
-  __shared__ double rowbuf[2][LDM];
-  __shared__ double colbuf[2][LDM];
-  __shared__ int flag;
-  const SmallDesc d = sds[blockIdx.x];
-  const int p = d.p, ld = d.ld;
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
-  const int hl = (tr & 1) * 32;  // first lane of this thread's half-wavefront
-  const double* Gb = G + d.m_off;
-  double* Rg = Wk + d.m_off;  // R spilled to global for the inverse phase
-  const double piv_tol = 1e-13;
-  if (tid == 0) flag = 0;
-  for (int i = tid; i < LDM; i += 1024) {
-    double v = 0.0;
-    if (i < p) {
-      const double g = Gb[int64_t(i) * ld + i];
-      if (!isfinite(g)) atomicOr(&flag, MI_BLOCK_NONFINITE);
-      if (!(g > 0.0)) atomicOr(&flag, MI_BLOCK_NOT_PD);
-      v = (g > 0.0 && isfinite(g)) ? 1.0 / sqrt(g) : 0.0;
-    }
-    dsc[i] = v;
-  }
-  __syncthreads();
-  double w[RT][RT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
-      double v = 0.0;
-      if (i < p && j < p && i <= j)
-        v = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
-      w[a][b] = v;
-    }
-  // row 0 (unit pivot after scaling) is already R's row 0
-  if (tr == 0) {
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int j = tc + 32 * b;
-      rowbuf[0][j] = (j > 0 && j < p) ? w[0][b] : 0.0;  // zero at the diagonal, like every published row
-    }
-    if (tc == 0) rdiag[0] = 1.0;
-  }
-  for (int k = 0; k < p; ++k) {
-    __syncthreads();
-    // rank-1 update with row k of R (zero at and left of k, and past p):
-    // 32-row blocks left of k are skipped with uniform branches; entries
-    // below the diagonal collect harmless garbage that is never read
-    const double* rb = rowbuf[k & 1];
-    const int ka = (k + 1) >> 5;
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      if (a < ka) continue;
-      const double ri = rb[tr + 32 * a];
-#pragma unroll
-      for (int b = 0; b < RT; ++b) {
-        if (b < a) continue;
-        w[a][b] -= ri * rb[tc + 32 * b];
-      }
-    }
-    const int k1 = k + 1;
-    if (k1 < p && tr == (k1 & 31)) {
-      const int a1 = k1 >> 5;
-      double mine = 0.0;
-#pragma unroll
-      for (int a = 0; a < RT; ++a)
-#pragma unroll
-        for (int b = 0; b < RT; ++b)
-          if (a == a1 && b == a1) mine = w[a][b];
-      double piv = __shfl(mine, hl + (k1 & 31), 64);
-      if (!(piv > piv_tol)) {
-        if (tc == 0) atomicOr(&flag, isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
-        piv = piv_tol;
-      }
-      const double r = sqrt(piv), inv = 1.0 / r;
-      double* nb = rowbuf[k1 & 1];
-#pragma unroll
-      for (int a = 0; a < RT; ++a)
-        if (a == a1) {
-#pragma unroll
-          for (int b = 0; b < RT; ++b) {
-            const int j = tc + 32 * b;
-            if (j == k1) w[a][b] = r;
-            else if (j > k1 && j < p) w[a][b] *= inv;
-            nb[j] = (j > k1 && j < p) ? w[a][b] : 0.0;
-          }
-        }
-      if (tc == 0) rdiag[k1] = r;
-    }
-  }
-  // R (upper, scaled) -> global scratch for the column broadcasts below
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
-      if (i < ld && j < ld) Rg[int64_t(i) * ld + j] = (i < p && j < p && i <= j) ? w[a][b] : 0.0;
-    }
-  __threadfence_block();
-  __syncthreads();
-  // Gauss-Jordan from the bottom: X <- I; at step k row k of X is final:
-  // scale it by 1/R_kk, then X[i][:] -= R[i][k] X[k][:] for i < k.
-  double x[RT][RT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
-      x[a][b] = (i == j && i < p) ? 1.0 : 0.0;
-    }
-  {
-    const int k = p - 1;
-    if (tr == (k & 31)) {
-      const int ak = k >> 5;
-#pragma unroll
-      for (int a = 0; a < RT; ++a)
-        if (a == ak) {
-#pragma unroll
-          for (int b = 0; b < RT; ++b) {
-            const int j = tc + 32 * b;
-            if (j == k) x[a][b] = 1.0 / rdiag[k];
-            rowbuf[k & 1][j] = (j >= k && j < p) ? x[a][b] : 0.0;
-          }
-        }
-    }
-    if (tc == (k & 31))
-      for (int a = 0; a < RT; ++a) {
-        const int i = tr + 32 * a;
-        colbuf[k & 1][i] = (i < k) ? Rg[int64_t(i) * ld + k] : 0.0;
-      }
-  }
-  // Column km of R is published by the threads with tc == km % 32, i.e.
-  // every 32 steps: each thread loads its next column one round ahead so
-  // that no global load sits on the step's critical path.
-  int my_km = (p - 2) - (((p - 2) - tc) & 31);  // largest km <= p-2 with km % 32 == tc
-  double pre[RT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a) {
-    const int i = tr + 32 * a;
-    pre[a] = (my_km >= 0 && i < my_km) ? Rg[int64_t(i) * ld + my_km] : 0.0;
-  }
-  for (int k = p - 1; k >= 0; --k) {
-    __syncthreads();
-    // X[i][:] -= R[i][k] X[k][:]: the column is zero from row k on and the
-    // row zero left of k, so whole 32-blocks are skipped uniformly
-    const double* xb = rowbuf[k & 1];
-    const double* cb = colbuf[k & 1];
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      if (32 * a >= k) continue;
-      const double rik = cb[tr + 32 * a];
-#pragma unroll
-      for (int b = 0; b < RT; ++b) {
-        if (32 * b + 31 < k || b < a) continue;
-        x[a][b] -= rik * xb[tc + 32 * b];
-      }
-    }
-    const int km = k - 1;
-    if (km >= 0) {
-      if (tr == (km & 31)) {  // row k-1 is final now: scale and publish it
-        const int ak = km >> 5;
-        const double inv = 1.0 / rdiag[km];
-        double* nb = rowbuf[km & 1];
-#pragma unroll
-        for (int a = 0; a < RT; ++a)
-          if (a == ak) {
-#pragma unroll
-            for (int b = 0; b < RT; ++b) {
-              const int j = tc + 32 * b;
-              if (j >= km && j < p) x[a][b] *= inv;
-              nb[j] = (j >= km && j < p) ? x[a][b] : 0.0;
-            }
-          }
-      }
-      if (tc == (km & 31)) {  // column k-1 of R (loaded a round earlier)
-#pragma unroll
-        for (int a = 0; a < RT; ++a) colbuf[km & 1][tr + 32 * a] = pre[a];
-        my_km -= 32;
-#pragma unroll
-        for (int a = 0; a < RT; ++a) {
-          const int i = tr + 32 * a;
-          pre[a] = (my_km >= 0 && i < my_km) ? Rg[int64_t(i) * ld + my_km] : 0.0;
-        }
-      }
-    }
-  }
-  double* Rb = Rinv + d.m_off;
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
-      if (i < ld && j < ld) {
-        const double v = (i < p && j < p && i <= j) ? dsc[i] * x[a][b] : 0.0;
-        Rb[int64_t(i) * ld + j] = v;
-        if (S32) S32[d.m_off + int64_t(i) * ld + j] = (float)v;
-      }
-    }
-  // zero the rest of the ld x ld output when ld is not a multiple of 32 * RT
-  for (int e = tid; e < ld * ld; e += 1024) {
-    const int i = e / ld, j = e % ld;
-    if (i >= LDM || j >= LDM) {
-      Rb[e] = 0.0;
-      if (S32) S32[d.m_off + e] = 0.0f;
-    }
-  }
-  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
-}
-
 void launch_chol_blk(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
                      float* S32, int32_t* status, int max_ld, int lds_max, hipStream_t s) {
   if (nb <= 0) return;
-  switch ((max_ld + 31) / 32) {  // register-resident variant for ld <= 192
-    case 1: hipLaunchKernelGGL(k_chol_reg<1>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
-    case 2: hipLaunchKernelGGL(k_chol_reg<2>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
-    case 3: hipLaunchKernelGGL(k_chol_reg<3>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
-    case 4: hipLaunchKernelGGL(k_chol_reg<4>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
-    case 5: hipLaunchKernelGGL(k_chol_reg<5>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
-    case 6: hipLaunchKernelGGL(k_chol_reg<6>, dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, status); return;
-    default: break;
-  }
+  if (launch_chol_mfma(sd, nb, G, Rinv, S32, status, max_ld, s)) return;  // ld <= 192
   const size_t pl = size_t(CB) * max_ld * sizeof(double);
   if (pl <= size_t(lds_max) - 40000)
     hipLaunchKernelGGL(k_chol_blk<true>, dim3(nb), dim3(256), pl, s, sd, G, Wk, Rinv, S32, status);
@@ -917,8 +571,4 @@ void launch_perm_cast(const SmallDesc* sd, int nb, const double* S64, const int3
 
 }  // namespace mis
 
-namespace mis {
-const void* k_chol_inv_ptr() { return reinterpret_cast<const void*>(&k_chol_inv<true>); }
-const void* k_jacobi_sweep_ptr() { return reinterpret_cast<const void*>(&k_jacobi_sweep<true>); }
-const void* k_apply_rot_ptr() { return reinterpret_cast<const void*>(&k_apply_rot); }
-}  // namespace mis
+

@@ -191,7 +191,7 @@ def roofline(ktimes, bs, blocks, L, prm):
         for lvl in np.unique(levels):
             sel = levels == lvl
             T, passes = (prm.T0, prm.passes0) if lvl == 0 else (prm.T, prm.passes)
-            nchol = T * passes + 1
+            nchol = T * passes + 1 + (1 if lvl > 0 else 0)  # + the warm start's
             tot += nchol * int((2 * p[sel].astype(np.float64) ** 3 / 3).sum())
         out.update(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step=tot)
         out["achieved"] = tot / (ms * 1e-3) / 1e12

@@ -239,8 +239,12 @@ def project(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, X: t
     """E = U_c^T X per block (rows k >= c_b zero)."""
     if E is None:
         E = torch.empty(int(blocks.t_off[-1]) * 3, dtype=_dtype(precision), device=U.device)
-    L.check(L.lib().mi_project(ctx.h, blocks.ref, precision, _dptr(c), _dptr(U), _dptr(X), _dptr(E),
-                               None, 0, _stream()))
+    lib = L.lib()
+    ws_n = C.c_size_t()
+    L.check(lib.mi_encdec_workspace_size(ctx.h, blocks.ref, precision, C.byref(ws_n)))
+    ws = ctx.workspace("encdec", ws_n.value)
+    L.check(lib.mi_project(ctx.h, blocks.ref, precision, _dptr(c), _dptr(U), _dptr(X), _dptr(E),
+                           _dptr(ws), ws.numel(), _stream()))
     return E
 
 

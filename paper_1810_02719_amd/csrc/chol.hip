@@ -28,7 +28,15 @@ namespace {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-constexpr double CHOL_PIV_TOL = 1e-13;  // pivot floor of the unit-diagonal Gram
+// The unit-diagonal Gram is factored with a small diagonal shift: a nearly
+// rank-deficient basis then yields bounded (not exploding) columns of Rinv,
+// at an orthonormality cost of about shift / lambda_min.  A pivot within ten
+// shifts of zero (a column dependent on the previous ones to ~1e-6) flags
+// MI_BLOCK_SHIFTED; one below the floor (rounding, or an indefinite input)
+// is also raised to the floor.
+constexpr double CHOL_SHIFT = 2e-13;
+constexpr double CHOL_FLAG = 10.0 * CHOL_SHIFT;
+constexpr double CHOL_PIV_TOL = 1e-13;  // pivot floor
 
 // Orders one wavefront's LDS writes before its lanes read each other's
 // values (the compiler may otherwise move a read above another lane's write).
@@ -75,9 +83,9 @@ __device__ d4v diag_factor(d4v g, double* rowbuf, double* Di, int ldd, int lane,
     }
     wave_sync();
     double piv = rowbuf[k];
-    if (!(piv > CHOL_PIV_TOL)) {
+    if (!(piv > CHOL_FLAG)) {
       *fl |= isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE;
-      piv = CHOL_PIV_TOL;
+      if (!(piv > CHOL_PIV_TOL)) piv = CHOL_PIV_TOL;
     }
     const double inv = 1.0 / sqrt(piv);
     const double rkj = rowbuf[mi] * inv;       // R[k][j]
@@ -157,7 +165,7 @@ __global__ void __launch_bounds__(1024)
       const int i = 16 * a + mq + 4 * q, j = 16 * b + mi;
       double v = 0.0;
       if (t < NPAIR) {
-        if (i < p && j < p) v = Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
+        if (i < p && j < p) v = (i == j) ? 1.0 + CHOL_SHIFT : Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
         else if (i == j) v = 1.0;  // identity padding
       }
       reg[s][q] = v;

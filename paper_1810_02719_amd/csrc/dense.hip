@@ -22,9 +22,11 @@ struct VecOf<double> {
 
 // ------------------------------------------------------------------ SpMM
 // Yout = alpha * (L Yin) + beta * Yin + gamma * Yprev for the rows of one
-// tile; (alpha, beta, gamma) per block and step.  Threads of a row cover its
-// ld coefficients with 16-byte vectors, so every neighbour row is gathered
-// with fully coalesced loads.
+// tile; (alpha, beta, gamma) per block and step.  Each wavefront takes whole
+// rows: the row's CSR entries are wave-uniform (scalar loads, read once),
+// lanes cover the row's ld coefficients with 16-byte vectors, and the
+// neighbour rows are gathered four at a time so that several coalesced
+// loads are in flight per lane.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_spmm(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
@@ -40,23 +42,36 @@ __global__ void __launch_bounds__(256)
   const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
   const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
   const int nvec = d.ld / W;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rows = min(SPMM_ROWS, d.rows - t.row0);
   const T* yb = Yin + d.off;
-  for (int idx = threadIdx.x; idx < rows * nvec; idx += 256) {
-    const int r = t.row0 + idx / nvec;
-    const int v = idx - (idx / nvec) * nvec;
+  const int32_t* cb = col + c.nnz_off;
+  const float* vb = val + c.nnz_off;
+  for (int rr = wave; rr < rows; rr += 4) {
+    const int r = t.row0 + rr;
     const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
-    V acc = (V)(T)0;
-    for (int k = k0; k < k1; ++k) {
-      const int j = col[c.nnz_off + k];
-      const T w = (T)val[c.nnz_off + k];
-      const V y = *reinterpret_cast<const V*>(yb + int64_t(j) * d.ld + v * W);
-      acc += w * y;
+    for (int v = lane; v < nvec; v += 64) {
+      const T* yv = yb + v * W;
+      V acc = (V)(T)0;
+      int k = k0;
+      for (; k + 4 <= k1; k += 4) {
+        const int j0 = cb[k], j1 = cb[k + 1], j2 = cb[k + 2], j3 = cb[k + 3];
+        const V y0 = *reinterpret_cast<const V*>(yv + int64_t(j0) * d.ld);
+        const V y1 = *reinterpret_cast<const V*>(yv + int64_t(j1) * d.ld);
+        const V y2 = *reinterpret_cast<const V*>(yv + int64_t(j2) * d.ld);
+        const V y3 = *reinterpret_cast<const V*>(yv + int64_t(j3) * d.ld);
+        acc += (T)vb[k] * y0;
+        acc += (T)vb[k + 1] * y1;
+        acc += (T)vb[k + 2] * y2;
+        acc += (T)vb[k + 3] * y3;
+      }
+      for (; k < k1; ++k) acc += (T)vb[k] * *reinterpret_cast<const V*>(yv + int64_t(cb[k]) * d.ld);
+      const int64_t o = d.off + int64_t(r) * d.ld + v * W;
+      V out = alpha * acc + beta * *reinterpret_cast<const V*>(Yin + o);
+      if (Yprev) out += gamma * *reinterpret_cast<const V*>(Yprev + o);
+      *reinterpret_cast<V*>(Yout + o) = out;
     }
-    const int64_t o = d.off + int64_t(r) * d.ld + v * W;
-    V out = alpha * acc + beta * *reinterpret_cast<const V*>(Yin + o);
-    if (Yprev) out += gamma * *reinterpret_cast<const V*>(Yprev + o);
-    *reinterpret_cast<V*>(Yout + o) = out;
   }
 }
 
@@ -198,8 +213,9 @@ void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outset
 
 // ------------------------------------------------------------------ A * S
 // Out rows [row0, row0+64) x columns [n0, n0+NCH) = A rows x S.  Per K-chunk
-// of 32, the A row tile and the S panel are staged through LDS with
-// coalesced loads; each wave owns 16 rows and NCH/16 MFMA tiles.
+// of 32, the A row tile and the S panel are staged through LDS from 16-byte
+// vector loads; the next chunk is fetched into registers while the MFMAs of
+// the current one run.  Each wave owns 16 rows and NCH/16 MFMA tiles.
 template <typename T>
 struct Mfma;
 template <>
@@ -224,10 +240,17 @@ __global__ void __launch_bounds__(256)
     k_rowmul(const RowTile* __restrict__ tiles, const MatDesc* __restrict__ asets,
              const T* __restrict__ A, const MatDesc* __restrict__ ssets, const T* __restrict__ S,
              const MatDesc* __restrict__ osets, TO* __restrict__ Out) {
+  typedef typename VecOf<T>::type V;
+  constexpr int W = VecOf<T>::W;           // elements per 16-byte vector
   constexpr int KC = 32;
   constexpr int NT = NCH / 16;
-  __shared__ T As[ROW_TILE][KC + 1];
-  __shared__ T Ss[KC][NCH + 1];
+  constexpr int AV = ROW_TILE * KC / W / 256;  // A vectors per thread and chunk
+  constexpr int SV = KC * NCH / W / 256;       // S vectors per thread and chunk
+  constexpr int LDA = KC + W;                  // keeps vector rows aligned, spreads banks
+  constexpr int LDS_ = NCH + (sizeof(T) == 4 ? 16 : 16);  // row offset of half the banks
+  static_assert(AV * W * 256 == ROW_TILE * KC && SV * W * 256 == KC * NCH, "tile shape");
+  __shared__ __attribute__((aligned(16))) T As[ROW_TILE * LDA];
+  __shared__ __attribute__((aligned(16))) T Ss[KC * LDS_];
   typedef typename Mfma<T>::acc_t acc_t;
   const RowTile t = tiles[blockIdx.x];
   const MatDesc da = asets[t.set], ds = ssets[t.set], dout = osets[t.set];
@@ -236,25 +259,48 @@ __global__ void __launch_bounds__(256)
   acc_t acc[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) acc[i] = (acc_t)(T)0;
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = threadIdx.x; e < ROW_TILE * KC; e += 256) {
-      const int rr = e / KC, kc = e % KC;
+  V ra[AV], rs[SV];
+  // chunk k0 -> registers (rows past the block and columns past S read as 0)
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < AV; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      const int rr = e / (KC / W), kv = e % (KC / W);
       const int row = t.row0 + rr;
-      As[rr][kc] = (row < da.rows && k0 + kc < K) ? A[da.off + int64_t(row) * da.ld + k0 + kc]
-                                                  : (T)0;
+      ra[j] = (row < da.rows)
+                  ? *reinterpret_cast<const V*>(A + da.off + int64_t(row) * da.ld + k0 + kv * W)
+                  : (V)(T)0;
     }
-    for (int e = threadIdx.x; e < KC * NCH; e += 256) {
-      const int kr = e / NCH, nc = e % NCH;
-      const int k = k0 + kr, n = t.n0 + nc;
-      Ss[kr][nc] = (k < K && n < ds.ld) ? S[ds.off + int64_t(k) * ds.ld + n] : (T)0;
+#pragma unroll
+    for (int j = 0; j < SV; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      const int kr = e / (NCH / W), nv = e % (NCH / W);
+      const int n = t.n0 + nv * W;
+      rs[j] = (n < ds.ld)
+                  ? *reinterpret_cast<const V*>(S + ds.off + int64_t(k0 + kr) * ds.ld + n)
+                  : (V)(T)0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+    for (int j = 0; j < AV; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      *reinterpret_cast<V*>(&As[(e / (KC / W)) * LDA + (e % (KC / W)) * W]) = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < SV; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      *reinterpret_cast<V*>(&Ss[(e / (NCH / W)) * LDS_ + (e % (NCH / W)) * W]) = rs[j];
     }
     __syncthreads();
+    if (k0 + KC < K) fetch(k0 + KC);  // in flight while the MFMAs run
 #pragma unroll 2
     for (int ks = 0; ks < KC; ks += 4) {
-      const T a = As[wave * 16 + (lane & 15)][ks + (lane >> 4)];
+      const T a = As[(wave * 16 + (lane & 15)) * LDA + ks + (lane >> 4)];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const T b = Ss[ks + (lane >> 4)][nt * 16 + (lane & 15)];
+        const T b = Ss[(ks + (lane >> 4)) * LDS_ + nt * 16 + (lane & 15)];
         acc[nt] = Mfma<T>::op(a, b, acc[nt]);
       }
     }
@@ -307,7 +353,7 @@ template void launch_rowmul<double, float>(const RowTile*, int, const MatDesc*, 
 // ------------------------------------------------------------------ tile tables
 
 int gram_chunks(int nsets, int npairs, int rows) {
-  const int target = 2048;
+  const int target = 384;  // workgroups per launch: enough to fill the chip, few partials
   int ch = ceil_div(target, std::max(1, nsets * npairs));
   ch = std::min(ch, std::max(1, rows / 64));
   return std::max(ch, 1);

@@ -12,6 +12,8 @@
 
 namespace mis {
 
+constexpr int PROJ_CHUNKS = 8;  // row ranges per block of the projection sums
+
 struct EncBlock {
   int64_t v_off, u_off, t_off;
   int32_t n, p, ld, pad;
@@ -22,11 +24,23 @@ struct EncPlan {
   std::vector<int32_t> p, ld;
   EncBlock* dev = nullptr;
   int64_t* dev_voff = nullptr;
+  int64_t* dev_poff = nullptr;  // per-block offset of the projection partials
   ~EncPlan() {
     if (dev) (void)hipFree(dev);
     if (dev_voff) (void)hipFree(dev_voff);
+    if (dev_poff) (void)hipFree(dev_poff);
   }
 };
+
+// Doubles of projection partials: PROJ_CHUNKS x ld x 3 per block.
+static int64_t proj_part_doubles(const HostBlocks& hb, std::vector<int64_t>* off) {
+  int64_t t = 0;
+  for (int b = 0; b < hb.B; ++b) {
+    if (off) off->push_back(t);
+    t += int64_t(PROJ_CHUNKS) * hb.ld[b] * 3;
+  }
+  return t;
+}
 
 static mi_status enc_plan(mi_ctx* ctx, const HostBlocks& hb, EncPlan** out) {
   EncPlan* P = static_cast<EncPlan*>(ctx->enc_plan);
@@ -45,8 +59,11 @@ static mi_status enc_plan(mi_ctx* ctx, const HostBlocks& hb, EncPlan** out) {
   for (int b = 0; b < hb.B; ++b)
     h[b] = EncBlock{hb.v_off[b], hb.u_off[b], hb.t_off[b], int(hb.v_off[b + 1] - hb.v_off[b]),
                     hb.p[b], hb.ld[b], 0};
+  std::vector<int64_t> poff;
+  proj_part_doubles(hb, &poff);
   if (hipMalloc(&P->dev, hb.B * sizeof(EncBlock)) != hipSuccess ||
-      hipMalloc(&P->dev_voff, (hb.B + 1) * sizeof(int64_t)) != hipSuccess) {
+      hipMalloc(&P->dev_voff, (hb.B + 1) * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&P->dev_poff, hb.B * sizeof(int64_t)) != hipSuccess) {
     delete P;
     set_error("device allocation for the block table failed");
     return MI_ERR_HIP;
@@ -54,49 +71,72 @@ static mi_status enc_plan(mi_ctx* ctx, const HostBlocks& hb, EncPlan** out) {
   MI_TRY_HIP(hipMemcpy(P->dev, h.data(), hb.B * sizeof(EncBlock), hipMemcpyHostToDevice));
   MI_TRY_HIP(hipMemcpy(P->dev_voff, hb.v_off.data(), (hb.B + 1) * sizeof(int64_t),
                        hipMemcpyHostToDevice));
+  MI_TRY_HIP(hipMemcpy(P->dev_poff, poff.data(), hb.B * sizeof(int64_t), hipMemcpyHostToDevice));
   ctx->enc_plan = P;
   *out = P;
   return MI_OK;
 }
 
 // E[k][:] = sum_i U[i][k] X[i][:] for k < c_b, 0 for c_b <= k < p_b.
-// One workgroup per block; thread t owns coefficients k = t, t + 256, ...
-// (row reads of U are coalesced across the workgroup).
+// Stage 1: workgroup (b, chunk) sums the rows of one of PROJ_CHUNKS row
+// ranges of block b into an FP64 partial (ld x 3); thread t owns the
+// coefficients k = t, t + 256, ... (row reads of U coalesced), rows unrolled
+// by 4 for memory-level parallelism.  Stage 2 adds the partials in chunk
+// order, so the result does not depend on scheduling.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_project(const EncBlock* __restrict__ blks, const int32_t* __restrict__ cvec,
-              const T* __restrict__ U, const T* __restrict__ X, T* __restrict__ E) {
+    k_project_part(const EncBlock* __restrict__ blks, const int64_t* __restrict__ poff,
+                   const int32_t* __restrict__ cvec, const T* __restrict__ U,
+                   const T* __restrict__ X, double* __restrict__ part) {
   constexpr int KPT = 4;  // ld <= 1024
   const EncBlock b = blks[blockIdx.x];
+  const int chunk = blockIdx.y;
   const int c = min(max(cvec[blockIdx.x], 0), b.p);
+  const int rows_per = (b.n + PROJ_CHUNKS - 1) / PROJ_CHUNKS;
+  const int r0 = chunk * rows_per, r1 = min(b.n, r0 + rows_per);
   double acc[KPT][3];
 #pragma unroll
   for (int s = 0; s < KPT; ++s) acc[s][0] = acc[s][1] = acc[s][2] = 0.0;
   const T* Ub = U + b.u_off;
   const T* Xb = X + 3 * b.v_off;
-  for (int i = 0; i < b.n; ++i) {
+#pragma unroll 4
+  for (int i = r0; i < r1; ++i) {
     const double x0 = (double)Xb[3 * i], x1 = (double)Xb[3 * i + 1], x2 = (double)Xb[3 * i + 2];
 #pragma unroll
     for (int s = 0; s < KPT; ++s) {
       const int k = threadIdx.x + 256 * s;
       if (k < c) {
         const double u = (double)Ub[int64_t(i) * b.ld + k];
-        acc[s][0] += u * x0;
-        acc[s][1] += u * x1;
-        acc[s][2] += u * x2;
+        acc[s][0] = fma(u, x0, acc[s][0]);
+        acc[s][1] = fma(u, x1, acc[s][1]);
+        acc[s][2] = fma(u, x2, acc[s][2]);
       }
     }
   }
+  double* pb = part + poff[blockIdx.x] + int64_t(chunk) * b.ld * 3;
 #pragma unroll
   for (int s = 0; s < KPT; ++s) {
     const int k = threadIdx.x + 256 * s;
-    if (k < b.p) {
-      T* e = E + 3 * (b.t_off + k);
-      const bool keep = k < c;
-      e[0] = keep ? (T)acc[s][0] : (T)0;
-      e[1] = keep ? (T)acc[s][1] : (T)0;
-      e[2] = keep ? (T)acc[s][2] : (T)0;
+    if (k < b.ld) {
+      pb[3 * k] = acc[s][0];
+      pb[3 * k + 1] = acc[s][1];
+      pb[3 * k + 2] = acc[s][2];
     }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_project_sum(const EncBlock* __restrict__ blks, const int64_t* __restrict__ poff,
+                  const int32_t* __restrict__ cvec, const double* __restrict__ part,
+                  T* __restrict__ E) {
+  const EncBlock b = blks[blockIdx.x];
+  const int c = min(max(cvec[blockIdx.x], 0), b.p);
+  const double* pb = part + poff[blockIdx.x];
+  for (int e = threadIdx.x; e < 3 * b.p; e += 256) {
+    double v = 0.0;
+    for (int ch = 0; ch < PROJ_CHUNKS; ++ch) v += pb[int64_t(ch) * b.ld * 3 + e];
+    E[3 * b.t_off + e] = (e / 3 < c) ? (T)v : (T)0;
   }
 }
 
@@ -150,7 +190,7 @@ mi_status mi_encdec_workspace_size(mi_ctx* ctx, const mi_blocks* blk, int32_t pr
   HostBlocks hb;
   mi_status st = load_blocks(blk, &hb, true);
   if (st) return st;
-  *ws_bytes = 0;
+  *ws_bytes = size_t(proj_part_doubles(hb, nullptr)) * sizeof(double);
   return MI_OK;
 }
 
@@ -160,23 +200,34 @@ mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const
   begin_call();
   MI_CHECK_ARG(ctx && c && U && X && E, "NULL argument");
   MI_CHECK_ARG(precision == MI_FP32 || precision == MI_FP64, "precision %d unsupported", precision);
-  (void)ws;
-  (void)ws_bytes;
   HostBlocks hb;
   mi_status st = load_blocks(blk, &hb, true);
   if (st) return st;
+  const size_t need = size_t(proj_part_doubles(hb, nullptr)) * sizeof(double);
+  if (!ws || ws_bytes < need) {
+    set_error("workspace %zu bytes < %zu required", ws_bytes, need);
+    return MI_ERR_WORKSPACE;
+  }
+  for (int b = 0; b < hb.B; ++b)
+    MI_CHECK_ARG(hb.ld[b] <= 1024, "block %d: ld %d > 1024", b, hb.ld[b]);
   MI_TRY_HIP(hipSetDevice(ctx->device));
   EncPlan* P = nullptr;
   st = enc_plan(ctx, hb, &P);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
+  double* part = static_cast<double*>(ws);
   KScope k_(ctx->timer, MI_K_PROJECT, s);
-  if (precision == MI_FP64)
-    hipLaunchKernelGGL(k_project<double>, dim3(hb.B), dim3(256), 0, s, P->dev, c,
-                       (const double*)U, (const double*)X, (double*)E);
-  else
-    hipLaunchKernelGGL(k_project<float>, dim3(hb.B), dim3(256), 0, s, P->dev, c, (const float*)U,
-                       (const float*)X, (float*)E);
+  if (precision == MI_FP64) {
+    hipLaunchKernelGGL(k_project_part<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
+                       P->dev_poff, c, (const double*)U, (const double*)X, part);
+    hipLaunchKernelGGL(k_project_sum<double>, dim3(hb.B), dim3(256), 0, s, P->dev, P->dev_poff, c,
+                       part, (double*)E);
+  } else {
+    hipLaunchKernelGGL(k_project_part<float>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
+                       P->dev_poff, c, (const float*)U, (const float*)X, part);
+    hipLaunchKernelGGL(k_project_sum<float>, dim3(hb.B), dim3(256), 0, s, P->dev, P->dev_poff, c,
+                       part, (float*)E);
+  }
   MI_TRY_HIP(hipGetLastError());
   return MI_OK;
 }

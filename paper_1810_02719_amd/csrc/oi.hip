@@ -549,6 +549,29 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       KScope k_(a.tm, MI_K_CHOL, s);
       launch_chol_blk(w.sd, w.nb, G, Wk, Rinv, s32, a.status, w.max_ld, P.lds_max, s);
     };
+    if (w.from_pred) {
+      // The index-aligned warm start drops rows when the block is smaller
+      // than its predecessor and can be badly conditioned; one Cholesky-QR
+      // before the first filter pass keeps the filtered basis of full rank
+      // in FP32.
+      {
+        KScope k_(a.tm, MI_K_GRAM, s);
+        launch_gram<T>(w.gt, w.n_gt, w.tall, X, X, nullptr, part, s);
+      }
+      {
+        KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
+        launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
+      }
+      chol(dbl ? nullptr : S32);
+      {
+        KScope k_(a.tm, MI_K_ROWMUL, s);
+        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, X, w.small,
+                            dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
+                            w.tall, slab[0], w.nch, s);
+      }
+      X = slab[0];
+      xslab = 0;
+    }
     for (int t = 0; t < w.T; ++t) {
       const bool last = t == w.T - 1;
       const bool rr_now = last || prm.rr_every;

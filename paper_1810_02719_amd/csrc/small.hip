@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(256)
   for (int i = wave; i < p; i += 4) {
     const double di = dsc[i];
     for (int j = i + lane; j < p; j += 64)
-      W[int64_t(i) * ld + j] = (i == j) ? 1.0 : Gb[int64_t(i) * ld + j] * di * dsc[j];
+      W[int64_t(i) * ld + j] = (i == j) ? 1.0 + 2e-13 : Gb[int64_t(i) * ld + j] * di * dsc[j];
   }
   __syncthreads();
   const int nbk = (p + CB - 1) / CB;
@@ -81,9 +81,9 @@ __global__ void __launch_bounds__(256)
       for (int k = 0; k < CB; ++k) {
         if (k < jb) {
           double piv = __shfl(c[k], k, 64);
-          if (!(piv > piv_tol)) {
+          if (!(piv > 2e-12)) {  // within ten diagonal shifts of zero: flag
             if (lane == 0) atomicOr(&flag, isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE);
-            piv = piv_tol;
+            if (!(piv > piv_tol)) piv = piv_tol;
           }
           const double r = sqrt(piv), inv = 1.0 / r;
           if (lane == k)

@@ -280,6 +280,32 @@ def test_eigen_solvers_agree(ctx, chain_small, rr_every):
         assert S.sin_theta_max(up.slab(Vt, b)[:, :100], up.slab(Vj, b)[:, :100]) < 2e-5
 
 
+@pytest.fixture(scope="module")
+def chain_c2():
+    return Uploaded(W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192))
+
+
+@pytest.mark.parametrize("eig", [mis._lib.MI_EIG_TRIDIAG, mis._lib.MI_EIG_JACOBI])
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_c2_chain_every_block_healthy(ctx, chain_c2, eig, T):
+    """The 100-block level-7 chain at several iteration counts: every block
+    finite, unflagged and orthonormal (warm starts of blocks smaller than
+    their predecessor once drove Cholesky-QR into rank deficiency)."""
+    up = chain_c2
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, warm_params(eig=eig, T=T), V0=V0)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert (s == 0).all(), [(int(b), int(s[b])) for b in np.nonzero(s)[0]]
+    assert torch.isfinite(V).all() and torch.isfinite(ritz).all()
+    for b in range(0, up.blocks.n_blocks, 7):
+        Vb = up.slab(V, b)[:, :int(up.blocks.p[b])]
+        assert np.abs(Vb.T @ Vb - np.eye(Vb.shape[1])).max() < 1e-4, b
+    if T == 3:
+        _chain_check(up, V, ritz, st, 100, sample=[84, 87, 98])
+
+
 def test_per_block_reference_path(ctx, chain_small):
     up = chain_small
     Lp = up.laplacian(ctx)

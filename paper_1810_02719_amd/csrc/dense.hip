@@ -94,8 +94,9 @@ template void launch_spmm<double>(const SpmmTile*, int, const MatDesc*, const Cs
 
 // ------------------------------------------------------------------ Gram
 // One workgroup: a 64 x 64 super-tile of A^T B (and A^T W when DUAL) over a
-// row range.  Four waves, each a 32 x 32 quadrant as 2 x 2 tiles of the
-// 16x16x4 FP64 MFMA.  Operands are promoted to FP64 exactly, so every
+// row range, staged through LDS 32 rows at a time from 16-byte vector loads
+// (the next chunk is fetched while the current one is multiplied).  Four
+// waves, each a 32 x 32 quadrant as 2 x 2 tiles of the 16x16x4 FP64 MFMA.  Operands are promoted to FP64 exactly, so every
 // product is exact and only the FP64 accumulation rounds.
 // MFMA operand layout (16x16x4): lane l supplies A(m = l%16, k = l/16) and
 // B(k = l/16, n = l%16).  Result element (m, n = l%16) sits in register q of
@@ -106,40 +107,72 @@ __global__ void __launch_bounds__(256)
     k_gram(const GramTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
            const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ Wm,
            double* __restrict__ part) {
+  typedef typename VecOf<T>::type V;
+  constexpr int W = VecOf<T>::W;
+  constexpr int RC = 32;                            // rows per staged chunk
+  constexpr int NV = RC * GRAM_TILE / W / 256;      // vectors per operand and thread
+  constexpr int LDT = GRAM_TILE + 16;               // row offset of a quarter (FP32) /
+                                                    // half (FP64) of the banks
+  constexpr int NOP = DUAL ? 3 : 2;
+  __shared__ __attribute__((aligned(16))) T St[NOP][RC * LDT];
   const GramTile t = tiles[blockIdx.x];
   const MatDesc d = sets[t.set];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int kk = lane >> 4, mm = lane & 15;
-  const int ci0 = t.I0 + wi * 32 + mm, ci1 = ci0 + 16;
-  const int cj0 = t.J0 + wj * 32 + mm, cj1 = cj0 + 16;
-  const bool vi0 = ci0 < d.ld, vi1 = ci1 < d.ld, vj0 = cj0 < d.ld, vj1 = cj1 < d.ld;
+  const int kq = lane >> 4, mi = lane & 15;
   d4v acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
   d4v w00 = acc00, w01 = acc00, w10 = acc00, w11 = acc00;
-  const T* Ab = A + d.off;
-  const T* Bb = B + d.off;
-  const T* Wb = DUAL ? Wm + d.off : nullptr;
-  for (int r = t.r0; r < t.r1; r += 4) {
-    const int row = r + kk;
-    const bool vr = row < t.r1;
-    const int64_t ro = int64_t(row) * d.ld;
-    const double a0 = (vr && vi0) ? (double)Ab[ro + ci0] : 0.0;
-    const double a1 = (vr && vi1) ? (double)Ab[ro + ci1] : 0.0;
-    const double b0 = (vr && vj0) ? (double)Bb[ro + cj0] : 0.0;
-    const double b1 = (vr && vj1) ? (double)Bb[ro + cj1] : 0.0;
-    acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-    acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-    acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-    acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
-    if (DUAL) {
-      const double x0 = (vr && vj0) ? (double)Wb[ro + cj0] : 0.0;
-      const double x1 = (vr && vj1) ? (double)Wb[ro + cj1] : 0.0;
-      w00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, w00, 0, 0, 0);
-      w01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, w01, 0, 0, 0);
-      w10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0, w10, 0, 0, 0);
-      w11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, w11, 0, 0, 0);
+  const T* src[3] = {A + d.off, B + d.off, DUAL ? Wm + d.off : nullptr};
+  const int c0[3] = {t.I0, t.J0, t.J0};
+  V reg[NOP][NV];
+  // rows [r, r + RC) of the three column panels -> registers (zero outside)
+  auto fetch = [&](int r) {
+#pragma unroll
+    for (int o = 0; o < NOP; ++o)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        const int rr = e / (GRAM_TILE / W), cv = e % (GRAM_TILE / W);
+        const int row = r + rr, col = c0[o] + cv * W;
+        reg[o][j] = (row < t.r1 && col < d.ld)
+                        ? *reinterpret_cast<const V*>(src[o] + int64_t(row) * d.ld + col)
+                        : (V)(T)0;
+      }
+  };
+  fetch(t.r0);
+  for (int r = t.r0; r < t.r1; r += RC) {
+#pragma unroll
+    for (int o = 0; o < NOP; ++o)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        *reinterpret_cast<V*>(&St[o][(e / (GRAM_TILE / W)) * LDT + (e % (GRAM_TILE / W)) * W]) =
+            reg[o][j];
+      }
+    __syncthreads();
+    if (r + RC < t.r1) fetch(r + RC);  // in flight during the MFMAs
+#pragma unroll
+    for (int ks = 0; ks < RC; ks += 4) {
+      const T* ar = &St[0][(ks + kq) * LDT];
+      const T* br = &St[1][(ks + kq) * LDT];
+      const double a0 = (double)ar[wi * 32 + mi], a1 = (double)ar[wi * 32 + 16 + mi];
+      const double b0 = (double)br[wj * 32 + mi], b1 = (double)br[wj * 32 + 16 + mi];
+      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+      if (DUAL) {
+        const T* xr = &St[DUAL ? 2 : 0][(ks + kq) * LDT];
+        const double x0 = (double)xr[wj * 32 + mi], x1 = (double)xr[wj * 32 + 16 + mi];
+        w00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, w00, 0, 0, 0);
+        w01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, w01, 0, 0, 0);
+        w10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0, w10, 0, 0, 0);
+        w11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, w11, 0, 0, 0);
+      }
     }
+    __syncthreads();
   }
+  const int kk = kq, mm = mi;
   double* out = part + int64_t(blockIdx.x) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
   const int n = mm;
 #pragma unroll

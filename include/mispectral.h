@@ -267,6 +267,65 @@ mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_p
                                 const int64_t* nnz_off, const void* V0, void* V, double* ritz,
                                 int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- Ritz residuals
+ * Section 4 (how many iterations the orthogonal iteration needs): the
+ * accuracy of a tracked pair (theta_j, v_j) is measured by its residual
+ * norm r_j = || L v_j - theta_j v_j ||_2, which bounds the distance of
+ * theta_j to the spectrum of L; a caller iterates until every kept pair
+ * meets its tolerance.  For every block b and column j < p_b:
+ *   resid[t_off_b + j] = || L_b V_b[:, j] - ritz[t_off_b + j] V_b[:, j] ||_2
+ * with L_b the CSR block Laplacian (layout as for mi_oi_track), V the slab
+ * (element type float for MI_FP32, double for MI_FP64), ritz and resid
+ * device double [sum p_b].  Products and sums are FP64; the column sums are
+ * reduced in a fixed order (tile partials in the workspace, then one pass
+ * per block), so results are reproducible.  Workspace (device, no alignment
+ * beyond 8 bytes) from mi_residual_workspace_size; MI_ERR_WORKSPACE if
+ * smaller.  Enqueue only. */
+mi_status mi_residual_workspace_size(mi_ctx* ctx, const mi_blocks* blk, size_t* ws_bytes);
+mi_status mi_ritz_residuals(mi_ctx* ctx, const mi_blocks* blk, int32_t precision,
+                            const int32_t* row_ptr, const int32_t* col, const float* val,
+                            const int64_t* nnz_off, const void* V, const double* ritz,
+                            double* resid, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- adjoint of encode / decode
+ * Gradient of loss = <Gbar, X~> for X~_b = U_c U_c^T X_b (Section 3 GFT and
+ * inverse GFT, Section 7.1 truncation to c_b), where U_c holds the first c_b
+ * Ritz vectors that mi_oi_track computes from V0 with `prm` (Section 4,
+ * Alg. 1: T0 iterations of passes0 Chebyshev passes of degree m0, Cholesky-QR
+ * between passes, Rayleigh-Ritz at the end).  The paper does not
+ * differentiate its method; the derivative is that of the unrolled
+ * iteration, with respect to the coordinates X and to the edge weights w of
+ * L = sum_e w_e (e_a - e_b)(e_a - e_b)^T (Eq. 1-2).  The filter interval
+ * [a, b] and the start V0 are constants.
+ * The call replays the tracking with checkpoints (every pass input, the
+ * Cholesky-QR factors and the Rayleigh-Ritz rotation) in its workspace, then
+ * runs the reverse sweep; all blocks are batched in every launch.
+ * Requires warm = MI_WARM_GIVEN, adapt = 0, rr_every = 0, eig = MI_EIG_TRIDIAG,
+ * T0 >= 1 and every ld_b <= 192 (else MI_ERR_ARG).
+ * mode      weight mode the CSR values were built with: for MI_W_INV_SQ_DIST
+ *           and MI_W_INV_DIST the weights depend on X and Xbar includes that
+ *           path; MI_W_COMBINATORIAL / MI_W_USER weights are independent of X.
+ * row_ptr, col, val, nnz_off   the block Laplacians (layout as mi_oi_track);
+ * edges     device int32 [sum |E_b|][2] canonical edges (a < b, block-local)
+ *           at edge_off[b] (host int64 [B+1]), as mi_build_laplacian emits.
+ * V0        device start slab (precision's element type), as for mi_oi_track.
+ * X, Gbar   device [v_off[B]][3] coordinates and d loss/d X~ (element type).
+ * c         device int32 [B], 1 <= c_b <= p_b.
+ * Xbar      device double [v_off[B]][3]: d loss/d X.
+ * wbar      device double [sum |E_b|]: d loss/d w_e per canonical edge (for
+ *           distance weights: the gradient at the weights before the chain
+ *           rule into X, which Xbar already includes).
+ * Workspace from mi_adjoint_workspace_size (holds about
+ * (T0*passes0 + m0 + 10) slabs).  Enqueue only; eager launches. */
+mi_status mi_adjoint_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                                    const int64_t* nnz_off, size_t* ws_bytes);
+mi_status mi_encdec_adjoint(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                            int32_t mode, const int32_t* row_ptr, const int32_t* col,
+                            const float* val, const int64_t* nnz_off, const int32_t* edges,
+                            const int64_t* edge_off, const void* V0, const void* X,
+                            const int32_t* c, const void* Gbar, double* Xbar, double* wbar,
+                            void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- encode / decode
  * Section 3 (GFT v_bar = U^T v, inverse GFT v = U v_bar) and Section 7.1
  * (E[i] = U_c^T v[i], v~[i] = U_c E[i]).  c: device int32 [B], 1 <= c_b <= p_b.

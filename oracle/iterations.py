@@ -16,6 +16,9 @@ chebyshev_span  the exact subspace span(f(L)^T V0) reached by T outer
                 applications do not change the span, so this is the
                 iterate's reference *before* convergence.
 rayleigh_ritz   eigenpairs of V^T L V for an orthonormal V, ascending.
+ritz_residuals  r_j = || L v_j - theta_j v_j ||_2 of Ritz pairs, the accuracy
+                measure of the iteration count question of Section 4 (how
+                many iterations a block needs).
 """
 from __future__ import annotations
 
@@ -105,3 +108,9 @@ def rayleigh_ritz(L: np.ndarray, V: np.ndarray):
     H = 0.5 * (H + H.T)
     th, S = np.linalg.eigh(H)
     return th, V @ S
+
+
+def ritz_residuals(L: np.ndarray, V: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """Section 4 (iteration count): residual norm of every Ritz pair,
+    r_j = || L v_j - theta_j v_j ||_2, columns of V."""
+    return np.linalg.norm(L @ V - V * theta[None, :], axis=0)

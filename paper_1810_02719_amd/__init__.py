@@ -7,9 +7,14 @@ functions mirror the C entry points:
 
     build_laplacian   graph Laplacian of every block (Section 3, Eq. 1-2)
     oi_track          eigenspace tracking by orthogonal iteration (Section 4, Alg. 1)
+    ritz_residuals    || L v_j - theta_j v_j || of the tracked pairs (Section 4)
+    oi_track_tol      tolerance mode of the iteration count (oi_track + ritz_residuals)
     project           GFT coefficients E = U_c^T X (Section 3, 7.1)
     reconstruct       inverse GFT X~ = U_c E (Section 3, 7.1)
     choose_c          per-block subspace size for an NMSVE target (Section 5, Eq. 16)
+    encdec_adjoint    gradient of encode/decode w.r.t. coordinates and edge weights
+                      through the unrolled iteration; EncodeDecode wraps the forward
+                      and this adjoint as a torch.autograd.Function
 """
 from __future__ import annotations
 
@@ -25,7 +30,8 @@ from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_FP32, MI_FP64, MI_W_COMBIN
                    MiError)
 
 __all__ = ["Blocks", "Context", "Laplacian", "OiParams", "build_laplacian", "laplacian_values",
-           "oi_track", "project", "reconstruct", "choose_c", "MiError"]
+           "oi_track", "ritz_residuals", "oi_track_tol", "TolResult", "encdec_adjoint", "EncodeDecode",
+           "project", "reconstruct", "choose_c", "MiError"]
 
 
 def _np_ptr(a, ctype):
@@ -234,6 +240,76 @@ def oi_track(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, V0=
     return V, ritz, status
 
 
+def ritz_residuals(ctx: Context, blocks: Blocks, lap: Laplacian, V: torch.Tensor,
+                   ritz: torch.Tensor, precision: int = MI_FP32,
+                   resid: torch.Tensor | None = None) -> torch.Tensor:
+    """resid[t_off_b + j] = || L_b v_j - theta_j v_j || for every tracked column
+    (mi_ritz_residuals); device float64 [sum p_b]."""
+    if resid is None:
+        resid = torch.empty(int(blocks.t_off[-1]), dtype=torch.float64, device=V.device)
+    lib = L.lib()
+    ws_n = C.c_size_t()
+    L.check(lib.mi_residual_workspace_size(ctx.h, blocks.ref, C.byref(ws_n)))
+    ws = ctx.workspace("resid", ws_n.value)
+    L.check(lib.mi_ritz_residuals(ctx.h, blocks.ref, precision, _dptr(lap.row_ptr), _dptr(lap.col),
+                                  _dptr(lap.val), _np_ptr(lap.nnz_off, C.c_int64), _dptr(V),
+                                  _dptr(ritz), _dptr(resid), _dptr(ws), ws.numel(), _stream()))
+    return resid
+
+
+@dataclass
+class TolResult:
+    V: torch.Tensor
+    ritz: torch.Tensor
+    status: torch.Tensor
+    resid: torch.Tensor        # residual norms of the returned pairs
+    rel: np.ndarray            # per block max_{j < c_b} resid_j / theta_{p_b - 1}
+    iters: np.ndarray          # per block: iterations done when it first met tol (-1: never)
+    converged: np.ndarray      # per block bool
+    total_iters: int           # iterations every block went through
+
+
+def oi_track_tol(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, tol: float,
+                 c=None, step: int = 1, max_iters: int = 60, V0=None) -> TolResult:
+    """Tolerance mode of the iteration control: one oi_track call with
+    `params`, then rounds of `step` further iterations (every block restarts
+    from its own current basis, MI_WARM_GIVEN, lower filter bound from its
+    Ritz values) until every block's kept pairs j < c_b satisfy
+    || L v_j - theta_j v_j || <= tol * theta_{p_b - 1}, or max_iters.  Blocks
+    that already meet the tolerance keep iterating with the others (one
+    batched launch sequence per round); `iters` records when each first did.
+    The decision reads the residuals on the host once per round."""
+    B = blocks.n_blocks
+    cb = np.asarray(blocks.p if c is None else c, dtype=np.int64).reshape(-1)
+    if cb.size == 1 and B > 1:
+        cb = np.full(B, int(cb[0]))
+    if np.any(cb < 1) or np.any(cb > blocks.p):
+        raise ValueError("need 1 <= c_b <= p_b")
+    V, ritz, status = oi_track(ctx, blocks, lap, params, V0=V0)
+    if params.warm == MI_WARM_GIVEN or blocks.pred is None:
+        done = np.full(B, params.T0, np.int64)
+    else:
+        done = np.where(blocks.pred >= 0, params.T, params.T0).astype(np.int64)
+    sp = OiParams(**{**params.__dict__, "warm": MI_WARM_GIVEN, "T0": step, "m0": params.m,
+                     "passes0": params.passes, "a_mode": MI_A_RITZ})
+    iters = np.full(B, -1, np.int64)
+    Vn = torch.empty_like(V)
+    t_end = blocks.t_off[1:] - 1
+    while True:
+        resid = ritz_residuals(ctx, blocks, lap, V, ritz, params.precision)
+        r = resid.cpu().numpy()
+        th = ritz.cpu().numpy()
+        rel = np.array([r[blocks.t_off[b]:blocks.t_off[b] + cb[b]].max() / max(th[t_end[b]], 1e-300)
+                        for b in range(B)])
+        conv = rel <= tol
+        iters = np.where(conv & (iters < 0), done, iters)
+        if conv.all() or done.max() >= max_iters:
+            break
+        V, Vn = oi_track(ctx, blocks, lap, sp, V0=V, V=Vn, ritz=ritz, status=status)[0], V
+        done = done + step
+    return TolResult(V, ritz, status, resid, rel, iters, conv, int(done.max()))
+
+
 def project(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, X: torch.Tensor,
             precision: int = MI_FP32, E: torch.Tensor | None = None) -> torch.Tensor:
     """E = U_c^T X per block (rows k >= c_b zero)."""
@@ -273,3 +349,60 @@ def choose_c(ctx: Context, blocks: Blocks, c_max: torch.Tensor, target: float, g
                             _np_ptr(gl.nnz_off, C.c_int64), _dptr(c_out), _dptr(metric), _dptr(ws),
                             ws.numel(), _stream()))
     return c_out, metric
+
+
+def encdec_adjoint(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, V0: torch.Tensor,
+                   X: torch.Tensor, c: torch.Tensor, Gbar: torch.Tensor, mode: int | None = None):
+    """(d loss/d X, d loss/d w) of loss = <Gbar, X~> through the unrolled
+    tracking (mi_encdec_adjoint).  X, Gbar: flat [3 n] in the params'
+    element type; returns float64 tensors [3 n] and [sum |E_b|]."""
+    lib = L.lib()
+    prm = params.struct()
+    mode = lap.mode if mode is None else mode
+    ws_n = C.c_size_t()
+    L.check(lib.mi_adjoint_workspace_size(ctx.h, blocks.ref, C.byref(prm),
+                                          _np_ptr(lap.nnz_off, C.c_int64), C.byref(ws_n)))
+    ws = ctx.workspace("adjoint", ws_n.value)
+    Xbar = torch.empty(int(blocks.v_off[-1]) * 3, dtype=torch.float64, device=X.device)
+    wbar = torch.zeros(max(int(lap.edge_off[-1]), 1), dtype=torch.float64, device=X.device)
+    L.check(lib.mi_encdec_adjoint(ctx.h, blocks.ref, C.byref(prm), mode, _dptr(lap.row_ptr),
+                                  _dptr(lap.col), _dptr(lap.val), _np_ptr(lap.nnz_off, C.c_int64),
+                                  _dptr(lap.edges), _np_ptr(lap.edge_off, C.c_int64), _dptr(V0),
+                                  _dptr(X), _dptr(c), _dptr(Gbar), _dptr(Xbar), _dptr(wbar),
+                                  _dptr(ws), ws.numel(), _stream()))
+    return Xbar, wbar[:int(lap.edge_off[-1])]
+
+
+class EncodeDecode(torch.autograd.Function):
+    """X~ = U_c U_c^T X per block with U_c from the tracking of V0 under the
+    Laplacian of (X, w); differentiable in X and w (user weights).
+
+        Xr = EncodeDecode.apply(X, w, ctx, blocks, lap, params, V0, c)
+
+    X: flat [3 n] coordinates (float32; the projection runs in the params'
+    precision); w: per-edge user weights (float32) when lap.mode is
+    MI_W_USER, else None.  The forward recomputes the Laplacian values,
+    tracks, projects and reconstructs; the backward calls encdec_adjoint."""
+
+    @staticmethod
+    def forward(fctx, X, w, ctx, blocks, lap, params, V0, c):
+        dt = _dtype(params.precision)
+        X32 = X.detach().to(torch.float32).contiguous()
+        uw = w.detach().to(torch.float32).contiguous() if w is not None else None
+        laplacian_values(ctx, blocks, lap, X32, lap.mode, uw)
+        V, _, _ = oi_track(ctx, blocks, lap, params, V0=V0)
+        Xp = X.detach().to(dt).contiguous()
+        E = project(ctx, blocks, c, V, Xp, params.precision)
+        Xr = reconstruct(ctx, blocks, c, V, E, params.precision)
+        fctx.save_for_backward(Xp, V0, c)
+        fctx.meta = (ctx, blocks, lap, params, X.dtype, None if w is None else w.dtype)
+        return Xr.to(X.dtype)
+
+    @staticmethod
+    def backward(fctx, g):
+        Xp, V0, c = fctx.saved_tensors
+        ctx, blocks, lap, params, xdt, wdt = fctx.meta
+        G = g.detach().to(Xp.dtype).contiguous()
+        Xbar, wbar = encdec_adjoint(ctx, blocks, lap, params, V0, Xp, c, G)
+        gw = wbar.to(wdt) if wdt is not None else None
+        return Xbar.to(xdt), gw, None, None, None, None, None, None

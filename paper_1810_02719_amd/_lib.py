@@ -88,6 +88,13 @@ _SIGS = {
                     _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_oi_track_per_block": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp,
                               _i64p, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
+    "mi_residual_workspace_size": [_vp, C.POINTER(MiBlocks), _szp],
+    "mi_ritz_residuals": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _i64p, _vp, _vp, _vp,
+                          _vp, C.c_size_t, _vp],
+    "mi_adjoint_workspace_size": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _i64p, _szp],
+    "mi_encdec_adjoint": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), C.c_int32, _vp, _vp,
+                          _vp, _i64p, _vp, _i64p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
+                          _vp],
     "mi_encdec_workspace_size": [_vp, C.POINTER(MiBlocks), C.c_int32, _szp],
     "mi_project": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_reconstruct": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _vp, _vp],

@@ -140,5 +140,8 @@ struct mi_ctx {
   void* oi_plan = nullptr;
   void* enc_plan = nullptr;
   void* cc_plan = nullptr;
+  void* res_plan = nullptr;  // residual tile tables (see resid.hip)
+  void* adj_oi = nullptr;    // tracking plan of the recorded forward (adjoint.hip)
+  void* adj_plan = nullptr;  // adjoint tables (adjoint.hip)
   mis::KTimer* timer = nullptr;  // non-null while timing is on
 };

@@ -221,6 +221,8 @@ mi_status mi_ctx_create(mi_ctx** out, int32_t device) {
 void mis_destroy_oi_plan(mi_ctx* ctx);
 void mis_destroy_enc_plan(mi_ctx* ctx);
 void mis_destroy_cc_plan(mi_ctx* ctx);
+void mis_destroy_res_plan(mi_ctx* ctx);
+void mis_destroy_adj_plan(mi_ctx* ctx);
 
 mi_status mi_ctx_destroy(mi_ctx* ctx) {
   mis::clear_error();
@@ -228,6 +230,8 @@ mi_status mi_ctx_destroy(mi_ctx* ctx) {
   mis_destroy_oi_plan(ctx);
   mis_destroy_enc_plan(ctx);
   mis_destroy_cc_plan(ctx);
+  mis_destroy_res_plan(ctx);
+  mis_destroy_adj_plan(ctx);
   delete ctx->timer;
   delete ctx;
   return MI_OK;

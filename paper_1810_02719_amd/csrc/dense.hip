@@ -3,22 +3,7 @@
 
 namespace mis {
 
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef double d2v __attribute__((ext_vector_type(2)));
 typedef double d4v __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct VecOf;
-template <>
-struct VecOf<float> {
-  typedef f4v type;
-  static constexpr int W = 4;
-};
-template <>
-struct VecOf<double> {
-  typedef d2v type;
-  static constexpr int W = 2;
-};
 
 // ------------------------------------------------------------------ SpMM
 // Yout = alpha * (L Yin) + beta * Yin + gamma * Yprev for the rows of one
@@ -210,38 +195,58 @@ template void launch_gram<double>(const GramTile*, int, const MatDesc*, const do
                                   const double*, const double*, double*, hipStream_t);
 
 // Sum the split-K partials of one super-tile in chunk order (deterministic)
-// and write the upper triangle and its mirror.
+// and write the upper triangle and its mirror.  GRAM_RED_SPLIT workgroups
+// per super-tile, one element per thread, partial loads issued together.
+constexpr int GRAM_RED_SPLIT = GRAM_TILE * GRAM_TILE / 256;
 __global__ void __launch_bounds__(256)
     k_gram_reduce(const GramReduce* __restrict__ jobs, const MatDesc* __restrict__ outsets,
                   const double* __restrict__ part, int dual, double* __restrict__ G,
                   double* __restrict__ H) {
-  const GramReduce j = jobs[blockIdx.x];
+  const GramReduce j = jobs[blockIdx.x / GRAM_RED_SPLIT];
   const MatDesc o = outsets[j.set];
   const int64_t stride = int64_t(dual ? 2 : 1) * GRAM_TILE * GRAM_TILE;
-  for (int e = threadIdx.x; e < GRAM_TILE * GRAM_TILE; e += 256) {
-    const int il = e / GRAM_TILE, jl = e % GRAM_TILE;
-    const int gi = j.I0 + il, gj = j.J0 + jl;
-    if (gi >= o.ld || gj >= o.ld || gi > gj) continue;
-    double sg = 0.0, sh = 0.0;
-    for (int c = 0; c < j.count; ++c) {
-      const double* pp = part + int64_t(j.first + c) * stride;
-      sg += pp[e];
-      if (dual) sh += pp[GRAM_TILE * GRAM_TILE + e];
-    }
-    G[o.off + int64_t(gi) * o.ld + gj] = sg;
-    G[o.off + int64_t(gj) * o.ld + gi] = sg;
+  const int e = (blockIdx.x % GRAM_RED_SPLIT) * 256 + threadIdx.x;
+  const int il = e / GRAM_TILE, jl = e % GRAM_TILE;
+  const int gi = j.I0 + il, gj = j.J0 + jl;
+  if (gi >= o.ld || gj >= o.ld || gi > gj) return;
+  const double* pp = part + int64_t(j.first) * stride + e;
+  double sg = 0.0, sh = 0.0;
+  int c = 0;
+  for (; c + 4 <= j.count; c += 4) {
+    const double g0 = pp[(c + 0) * stride], g1 = pp[(c + 1) * stride];
+    const double g2 = pp[(c + 2) * stride], g3 = pp[(c + 3) * stride];
+    sg += g0;
+    sg += g1;
+    sg += g2;
+    sg += g3;
     if (dual) {
-      H[o.off + int64_t(gi) * o.ld + gj] = sh;
-      H[o.off + int64_t(gj) * o.ld + gi] = sh;
+      const double h0 = pp[(c + 0) * stride + GRAM_TILE * GRAM_TILE];
+      const double h1 = pp[(c + 1) * stride + GRAM_TILE * GRAM_TILE];
+      const double h2 = pp[(c + 2) * stride + GRAM_TILE * GRAM_TILE];
+      const double h3 = pp[(c + 3) * stride + GRAM_TILE * GRAM_TILE];
+      sh += h0;
+      sh += h1;
+      sh += h2;
+      sh += h3;
     }
+  }
+  for (; c < j.count; ++c) {
+    sg += pp[c * stride];
+    if (dual) sh += pp[c * stride + GRAM_TILE * GRAM_TILE];
+  }
+  G[o.off + int64_t(gi) * o.ld + gj] = sg;
+  G[o.off + int64_t(gj) * o.ld + gi] = sg;
+  if (dual) {
+    H[o.off + int64_t(gi) * o.ld + gj] = sh;
+    H[o.off + int64_t(gj) * o.ld + gi] = sh;
   }
 }
 
 void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outsets,
                         const double* part, bool dual, double* G, double* H, hipStream_t s) {
   if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(njobs), dim3(256), 0, s, jobs, outsets, part, dual ? 1 : 0,
-                     G, H);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(njobs * GRAM_RED_SPLIT), dim3(256), 0, s, jobs, outsets,
+                     part, dual ? 1 : 0, G, H);
 }
 
 // ------------------------------------------------------------------ A * S

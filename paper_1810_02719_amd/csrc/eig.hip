@@ -40,10 +40,35 @@ __device__ __forceinline__ double col_of(const double (&row)[RT], int kb) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double swz_xor16(double v) {
+  // ds_swizzle bit mode within 32 lanes: and 0x1f, or 0, xor 0x10
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 32 lanes of a half-wavefront, in every lane: DPP quad
+// permutations and row mirrors inside each 16-lane row, one swizzle across
+// the two rows (all lanes must be active).
 __device__ __forceinline__ double half_sum(double v) {
-  // sum over the 32 lanes of a half-wavefront (xor masks below 32 stay in it)
-  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v + swz_xor16(v);
+}
+
+// Sum of 32 doubles in LDS, in every lane of the wavefront: one LDS read per
+// lane (lane l reads x[l % 32]) and a half-wavefront DPP reduction.
+__device__ __forceinline__ double sum32(const double* x) {
+  return half_sum(x[threadIdx.x & 31]);
 }
 
 __device__ __forceinline__ double guard(double t, double floor_) {
@@ -111,9 +136,11 @@ __device__ __forceinline__ double hash_unit(int i, int j) {
 // (v zero up to k, alpha = -sign(x_{k+1}) ||x||), computes p = beta A v with
 // half-wavefront reductions, then A -= v w^T + w v^T with
 // w = p - (beta/2)(v^T p) v.  v and w are zero at and above k, so finished
-// rows and columns keep their (unused) values and never feed the trailing
-// matrix; whole finished 32-blocks are skipped.  Two barriers per step; the
-// LDS vectors are double-buffered by step parity.
+// rows and columns keep their values and never feed the trailing matrix;
+// whole finished 32-blocks are skipped, and the finished column k holds v_k
+// until the end.  Two barriers per step; the LDS vectors are double-buffered
+// by step parity; d, e and beta collect in LDS and everything goes to global
+// memory once, after the loop.
 template <int RT>
 __global__ void __launch_bounds__(1024)
     k_tri_reduce(const SmallDesc* __restrict__ sds, const double* __restrict__ A,
@@ -123,15 +150,12 @@ __global__ void __launch_bounds__(1024)
   __shared__ double pcol[2][LDM];
   __shared__ double part[2][32];
   __shared__ double vpart[2][32];
+  __shared__ double sdd[LDM], see[LDM], sbb[LDM];
   __shared__ int flag;
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
   const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
   const double* Ab = A + d.m_off;
-  double* Hb = Hv + d.m_off;
-  double* dd = tri + 4 * d.t_off;
-  double* ee = dd + p;
-  double* bb = dd + 3 * p;
   if (tid == 0) flag = 0;
   __syncthreads();
   double w[RT][RT];
@@ -151,23 +175,27 @@ __global__ void __launch_bounds__(1024)
     const int par = k & 1, kb = k >> 5, kt = k & 31;
     // A: publish column k (the diagonal entry goes to d_k, not into v)
     if (tc == kt) {
+      double x[RT];
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+        if (b == kb) {  // uniform: selects the register column
+#pragma unroll
+          for (int a = 0; a < RT; ++a) x[a] = w[a][b];
+        }
       double ss = 0.0;
 #pragma unroll
       for (int a = 0; a < RT; ++a) {
         const int i = tr + 32 * a;
-        double x = col_of<RT>(w[a], kb);
-        if (i == k) dd[k] = x;
-        if (i <= k) x = 0.0;
-        xcol[par][i] = x;
-        ss += x * x;
+        if (i == k) sdd[k] = x[a];
+        const double xi = i <= k ? 0.0 : x[a];
+        xcol[par][i] = xi;
+        ss = fma(xi, xi, ss);
       }
       part[par][tr] = ss;
     }
     __syncthreads();
     // B: reflector and p = beta A v
-    double ss = 0.0;
-#pragma unroll 8
-    for (int t = 0; t < 32; ++t) ss += part[par][t];
+    const double ss = sum32(part[par]);
     const double x1 = xcol[par][k + 1];
     double al, be;
     if (ss <= DBL_MIN) {
@@ -200,22 +228,13 @@ __global__ void __launch_bounds__(1024)
     }
     if (tc == 0) vpart[par][tr] = vp;
     if (tid == 0) {
-      ee[k] = al;
-      bb[k] = be;
-    }
-    if (tr == 0) {
-#pragma unroll
-      for (int b = 0; b < RT; ++b) {
-        const int j = tc + 32 * b;
-        if (j < ld) Hb[int64_t(k) * ld + j] = vc[b];
-      }
+      see[k] = al;
+      sbb[k] = be;
     }
     __syncthreads();
-    // C: rank-2 update of the trailing matrix
-    double vtp = 0.0;
-#pragma unroll 8
-    for (int t = 0; t < 32; ++t) vtp += vpart[par][t];
-    const double K = 0.5 * be * vtp;
+    // C: rank-2 update of the trailing matrix; the finished column k then
+    // stores the reflector v_k below the diagonal (never read by the update)
+    const double K = 0.5 * be * sum32(vpart[par]);
     double wc[RT];
 #pragma unroll
     for (int b = 0; b < RT; ++b) {
@@ -231,6 +250,9 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
       for (int b = 0; b < RT; ++b)
         if (b >= ka) w[a][b] -= va * wc[b] + wa * vc[b];
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+        if (b == kb) w[a][b] = (tc == kt && i > k) ? va : w[a][b];
     }
   }
   // the last 2 x 2 (or 1 x 1) block is already tridiagonal
@@ -239,16 +261,32 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
     for (int b = 0; b < RT; ++b) {
       const int i = tr + 32 * a, j = tc + 32 * b;
-      if (p >= 2 && i == p - 2 && j == p - 2) dd[p - 2] = w[a][b];
-      if (i == p - 1 && j == p - 1) dd[p - 1] = w[a][b];
-      if (p >= 2 && i == p - 1 && j == p - 2) ee[p - 2] = w[a][b];
+      if (p >= 2 && i == p - 2 && j == p - 2) sdd[p - 2] = w[a][b];
+      if (i == p - 1 && j == p - 1) sdd[p - 1] = w[a][b];
+      if (p >= 2 && i == p - 1 && j == p - 2) see[p - 2] = w[a][b];
     }
   if (tid == 0) {
-    ee[p - 1] = 0.0;
-    if (p >= 2) bb[p - 2] = 0.0;
-    bb[p - 1] = 0.0;
+    see[p - 1] = 0.0;
+    if (p >= 2) sbb[p - 2] = 0.0;
+    sbb[p - 1] = 0.0;
   }
+  // reflectors: row c of Hv = v_c (zero at and left of c), from the finished
+  // columns of the register tile
+  double* Hb = Hv + d.m_off;
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int i = tr + 32 * a, c = tc + 32 * b;
+      if (c + 2 < p && i < ld) Hb[int64_t(c) * ld + i] = (i > c && i < p) ? w[a][b] : 0.0;
+    }
   __syncthreads();
+  double* dd = tri + 4 * d.t_off;
+  for (int i = tid; i < p; i += 1024) {
+    dd[i] = sdd[i];
+    dd[p + i] = see[i];
+    dd[3 * p + i] = sbb[i];
+  }
   if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
 }
 
@@ -259,22 +297,22 @@ __global__ void __launch_bounds__(1024)
 // by a group of TRI_GROUP lanes that evaluate TRI_GROUP * TRI_BISECT_POINTS
 // equispaced points of its bracket [a, b] (count(a) <= j < count(b)) per
 // round, interleaved for instruction-level parallelism.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
     k_tri_bisect(const SmallDesc* __restrict__ sds, double* __restrict__ tri,
                  double* __restrict__ ritz, int32_t* __restrict__ perm, double* __restrict__ a_lo,
                  int adapt, int32_t* __restrict__ status) {
   extern __shared__ double smem[];
-  __shared__ double red[12];
+  __shared__ double red[3];
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p;
-  const int j0 = blockIdx.y * (256 / TRI_GROUP);
+  const int j0 = blockIdx.y * (64 / TRI_GROUP);
   if (j0 >= p) return;
   double* sd_ = smem;
   double* se2 = smem + p;
   const double* dd = tri + 4 * d.t_off;
   const double* ee = dd + p;
   double* lam = tri + 4 * d.t_off + 2 * p;
-  for (int i = threadIdx.x; i < p; i += 256) {
+  for (int i = threadIdx.x; i < p; i += 64) {
     sd_[i] = dd[i];
     se2[i] = ee[i] * ee[i];
   }
@@ -303,7 +341,12 @@ __global__ void __launch_bounds__(256)
         const double di = sd_[i], e2 = se2[i - 1];
 #pragma unroll
         for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
-          t[m] = guard((di - x[m]) - e2 / t[m], sc.pivmin);
+          // e2 / t by the hardware reciprocal and one Newton step: a count
+          // only needs the pivot's sign, which a few ulps cannot flip
+          // except within rounding distance of an eigenvalue
+          double r = __builtin_amdgcn_rcp(t[m]);
+          r = fma(r, fma(-t[m], r, 1.0), r);
+          t[m] = guard((di - x[m]) - e2 * r, sc.pivmin);
           c[m] += t[m] < 0.0;
         }
       }
@@ -570,8 +613,8 @@ void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, const double* A,
 void launch_tri_bisect(const SmallDesc* sd, int nb, int max_p, double* tri, double* ritz,
                        int32_t* perm, double* a_lo, int adapt, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
-  const int gy = ceil_div(max_p, 256 / TRI_GROUP);
-  hipLaunchKernelGGL(k_tri_bisect, dim3(nb, gy), dim3(256), size_t(2 * max_p) * sizeof(double), s,
+  const int gy = ceil_div(max_p, 64 / TRI_GROUP);
+  hipLaunchKernelGGL(k_tri_bisect, dim3(nb, gy), dim3(64), size_t(2 * max_p) * sizeof(double), s,
                      sd, tri, ritz, perm, a_lo, adapt, status);
 }
 

@@ -29,6 +29,30 @@ __device__ inline int find_block(const int64_t* __restrict__ off, int B, int64_t
   return lo;
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// 16-byte vector of a slab element type (one load or store per lane).
+template <typename T>
+struct VecOf;
+template <>
+struct VecOf<float> {
+  typedef f4v type;
+  static constexpr int W = 4;
+};
+template <>
+struct VecOf<double> {
+  typedef d2v type;
+  static constexpr int W = 2;
+};
+
+// Sum over the 64 lanes of a wavefront (every lane gets the total).
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Bump allocator over a caller-provided workspace.

@@ -16,16 +16,11 @@
 #include <memory>
 
 #include "eig.hpp"
-#include "small.hpp"
+#include "oi_plan.hpp"
 
 namespace mis {
 
 // ------------------------------------------------------------------ per-block scalar kernels
-
-struct BlkInfo {
-  int64_t t_off;
-  int32_t n, p, pred, pad;
-};
 
 // b_hi[blk] = max_i sum_j |L_ij| (Gershgorin bound on lambda_max), one
 // workgroup per block, deterministic.
@@ -150,66 +145,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------------ plan
-
-struct WaveTables {
-  int nb = 0;
-  int T = 0, m = 0, passes = 0;
-  bool from_pred = false;
-  int max_ld = 0, max_q = 0, max_p = 0;
-  int nch = 64, nchs = 64;
-  // device tables
-  MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
-  CsrDesc* csr = nullptr;
-  SmallDesc* sd = nullptr;
-  SpmmTile* spmm = nullptr;
-  int n_spmm = 0;
-  GramTile* gt = nullptr;
-  int n_gt = 0;
-  GramReduce* gr = nullptr;
-  int n_gr = 0;
-  GramTile* gts = nullptr;
-  int n_gts = 0;
-  GramReduce* grs = nullptr;
-  int n_grs = 0;
-  RowTile* rt = nullptr;
-  int n_rt = 0;
-  RowTile* rts = nullptr;
-  int n_rts = 0;
-};
-
-struct WsLayout {
-  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, tri, part, a_lo, b_hi, coef,
-      conv;
-  size_t total;
-  int coef_stride;
-};
-
-struct OiPlan {
-  // key
-  HostBlocks hb;
-  std::vector<int64_t> nnz_off;
-  mi_oi_params prm;
-  std::vector<const void*> ptrs;
-  size_t ws_bytes = 0;
-  bool per_block = false;
-  // content
-  std::vector<WaveTables> waves;
-  WsLayout L;
-  void* arena = nullptr;
-  BlkInfo* info = nullptr;
-  MatDesc* all_tall = nullptr;
-  CsrDesc* all_csr = nullptr;
-  int lds_max = 65536;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cap_stream = nullptr;
-  ~OiPlan() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (arena) (void)hipFree(arena);
-  }
-};
 
 static int q_of(int p) { return (p + 1) & ~1; }
 
@@ -469,18 +404,6 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
 
 // ------------------------------------------------------------------ enqueue
 
-struct Args {
-  const int32_t* row_ptr;
-  const int32_t* col;
-  const float* val;
-  const void* V0;
-  void* V;
-  double* ritz;
-  int32_t* status;
-  char* ws;
-  KTimer* tm;
-};
-
 template <typename T>
 static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   const mi_oi_params& prm = P.prm;
@@ -510,6 +433,13 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   T* V = static_cast<T*>(a.V);
   const T* V0 = static_cast<const T*>(a.V0);
   const int B = P.hb.B;
+  const OiRecord* rec = a.rec;
+  const size_t slab_bytes = size_t(P.hb.u_off[B]) * sizeof(T);
+  const size_t mats = size_t(P.hb.m_off[B]);
+  auto keep = [&](void* dst, const void* src, size_t bytes) {
+    (void)hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+  };
+  int jp = 0;  // filter passes done (recording index)
 
   {
     KScope k_(a.tm, MI_K_SETUP, s);
@@ -582,6 +512,10 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
                              a_lo, b_hi, coef, L.coef_stride, w.m);
         }
+        if (rec) {
+          if (jp == 0) keep(rec->coef, coef, size_t(B) * L.coef_stride * sizeof(double));
+          keep(rec->X[jp], X, slab_bytes);
+        }
         int free_s[3], nf = 0;
         for (int i = 0; i < 4 && nf < 3; ++i)
           if (i != xslab) free_s[nf++] = i;
@@ -598,6 +532,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           cur = out;
           ycur = free_s[k % 3];
         }
+        ++jp;
         if (pass < w.passes - 1) {
           // span-preserving Cholesky-QR between passes
           {
@@ -609,6 +544,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
             launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
           }
           chol(dbl ? nullptr : S32);
+          if (rec) keep(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, mats * sizeof(T));
           int dst = -1;
           for (int i = 0; i < 4; ++i)
             if (i != ycur && i != xslab) dst = i;
@@ -647,6 +583,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         // intermediate iteration: Cholesky-QR of Y; the filter's lower bound
         // follows the largest Rayleigh quotient of the new basis
         chol(dbl ? nullptr : S32);
+        if (rec) keep(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, mats * sizeof(T));
         {
           KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
           launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
@@ -667,6 +604,10 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       }
       // Rayleigh-Ritz: A = Rinv^T H Rinv = Z Theta Z^T,  V = Y Rinv Z
       chol(nullptr);
+      if (rec && last) {
+        keep(rec->Rrr, Rinv, mats * sizeof(double));
+        keep(rec->Y, Y, slab_bytes);
+      }
       {
         KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
         launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
@@ -679,7 +620,8 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
         launch_gram_reduce(w.grs, w.n_grs, w.small, part, false, Am, nullptr, s);
       }
-      if (prm.eig == MI_EIG_TRIDIAG && tri_eig_supported(w.max_ld)) {
+      const bool use_tri = prm.eig == MI_EIG_TRIDIAG && tri_eig_supported(w.max_ld);
+      if (use_tri) {
         // Householder tridiagonalisation, multisection, inverse iteration;
         // Z / T1 / S64 double as per-thread scratch before Z is written
         {
@@ -698,6 +640,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           KScope k_(a.tm, MI_K_EIG_BACK, s);
           launch_tri_back(w.sd, w.nb, w.max_ld, S64, Wk, tri, Z, s);
         }
+        if (rec && last) keep(rec->Z, Z, mats * sizeof(double));
       } else {
         {
           KScope k_(a.tm, MI_K_JACOBI_INIT, s);
@@ -722,12 +665,23 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                            std::max(1e-10, 10.0 * jtol), s);
         }
       }
-      {
+      if (use_tri) {
+        // already in ascending Ritz order: S = Rinv Z straight into the
+        // operand of the row product (FP32 copy for FP32 slabs)
         KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
-        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S64, w.nchs, s);
-      }
-      // S <- columns of Rinv Z in ascending Ritz order (FP32 copy for FP32 products)
-      {
+        if (dbl)
+          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, T1,
+                                        w.nchs, s);
+        else
+          launch_rowmul<double, float>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S32,
+                                       w.nchs, s);
+      } else {
+        {
+          KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
+          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S64,
+                                        w.nchs, s);
+        }
+        // S <- columns of Rinv Z in ascending Ritz order (FP32 copy for FP32 products)
         KScope k_(a.tm, MI_K_PERM_CAST, s);
         launch_perm_cast(w.sd, w.nb, S64, perm, dbl ? nullptr : S32, dbl ? T1 : nullptr, s);
       }
@@ -811,6 +765,70 @@ static int device_lds_max(int dev) {
   return v - 2048;
 }
 
+// The plan cached in *slot for this key, (re)built when the key changed.
+static mi_status get_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
+                          const std::vector<int64_t>& nnz, const mi_oi_params& prm,
+                          const std::vector<const void*>& ptrs, void* ws, size_t ws_bytes,
+                          bool per_block, OiPlan** out) {
+  OiPlan* P = static_cast<OiPlan*>(*slot);
+  if (!P || !same_key(*P, hb, nnz, prm, ptrs, ws_bytes, per_block)) {
+    delete P;
+    *slot = nullptr;
+    std::unique_ptr<OiPlan> np;
+    size_t need = 0;
+    mi_status st = make_plan(hb, nnz, prm, per_block, device_lds_max(ctx->device), &np, &need);
+    if (st) return st;
+    if (!ws || ws_bytes < need) {
+      set_error("workspace %zu bytes < %zu required", ws_bytes, need);
+      return MI_ERR_WORKSPACE;
+    }
+    np->ptrs = ptrs;
+    np->ws_bytes = ws_bytes;
+    P = np.release();
+    *slot = P;
+  }
+  *out = P;
+  return MI_OK;
+}
+
+mi_status oi_check_params(const mi_oi_params* prm) { return check_params(prm); }
+
+size_t oi_ws_bytes(const HostBlocks& hb, const mi_oi_params& prm) {
+  std::vector<std::vector<int>> waves;
+  std::vector<int> level;
+  if (build_waves(hb, prm, false, &waves, &level)) return 0;
+  // the Gram partial buffer is sized for the largest wave
+  size_t part_max = 0;
+  std::vector<int64_t> pk_off(hb.B, 0), log_off(hb.B, 0), nnz(hb.B + 1, 0);
+  for (auto& w : waves) {
+    WaveTables wt;
+    WaveHost h;
+    wave_host(hb, nnz, w, prm, &wt, &h, pk_off, log_off);
+    part_max = std::max(part_max, h.gt.size() * 2 * GRAM_TILE * GRAM_TILE);
+    part_max = std::max(part_max, h.gts.size() * 2 * GRAM_TILE * GRAM_TILE);
+  }
+  return ws_layout(hb, prm, part_max).total;
+}
+
+mi_status oi_run_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
+                      const std::vector<int64_t>& nnz, const mi_oi_params& prm,
+                      const int32_t* row_ptr, const int32_t* col, const float* val,
+                      const void* V0, void* V, double* ritz, int32_t* status, void* ws,
+                      size_t ws_bytes, const OiRecord* rec, hipStream_t s, OiPlan** plan_out) {
+  std::vector<const void*> ptrs = {row_ptr, col, val, V0, V, ritz, status, ws};
+  OiPlan* P = nullptr;
+  mi_status st = get_plan(ctx, slot, hb, nnz, prm, ptrs, ws, ws_bytes, false, &P);
+  if (st) return st;
+  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, rec};
+  if (prm.precision == MI_FP64)
+    enqueue<double>(*P, a, s);
+  else
+    enqueue<float>(*P, a, s);
+  MI_TRY_HIP(hipGetLastError());
+  if (plan_out) *plan_out = P;
+  return MI_OK;
+}
+
 static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                         const int32_t* row_ptr, const int32_t* col, const float* val,
                         const int64_t* nnz_off, const void* V0, void* V, double* ritz,
@@ -828,26 +846,11 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
   for (int b = 0; b < hb.B; ++b) needs_v0 = needs_v0 || hb.pred[b] < 0;
   MI_CHECK_ARG(!needs_v0 || V0 != nullptr, "V0 is required");
   MI_TRY_HIP(hipSetDevice(ctx->device));
-  const int lds_max = device_lds_max(ctx->device);
   std::vector<const void*> ptrs = {row_ptr, col, val, V0, V, ritz, status, ws};
-  OiPlan* P = static_cast<OiPlan*>(ctx->oi_plan);
-  if (!P || !same_key(*P, hb, nnz, *prm, ptrs, ws_bytes, per_block)) {
-    delete P;
-    ctx->oi_plan = nullptr;
-    std::unique_ptr<OiPlan> np;
-    size_t need = 0;
-    st = make_plan(hb, nnz, *prm, per_block, lds_max, &np, &need);
-    if (st) return st;
-    if (!ws || ws_bytes < need) {
-      set_error("workspace %zu bytes < %zu required", ws_bytes, need);
-      return MI_ERR_WORKSPACE;
-    }
-    np->ptrs = ptrs;
-    np->ws_bytes = ws_bytes;
-    P = np.release();
-    ctx->oi_plan = P;
-  }
-  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer};
+  OiPlan* P = nullptr;
+  st = get_plan(ctx, &ctx->oi_plan, hb, nnz, *prm, ptrs, ws, ws_bytes, per_block, &P);
+  if (st) return st;
+  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, nullptr};
   hipStream_t s = (hipStream_t)stream;
   if (per_block || ctx->timer) {
     if (prm->precision == MI_FP64)
@@ -885,6 +888,8 @@ extern "C" {
 void mis_destroy_oi_plan(mi_ctx* ctx) {
   delete static_cast<OiPlan*>(ctx->oi_plan);
   ctx->oi_plan = nullptr;
+  delete static_cast<OiPlan*>(ctx->adj_oi);
+  ctx->adj_oi = nullptr;
 }
 
 mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
@@ -901,17 +906,7 @@ mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_pa
   std::vector<int> level;
   st = build_waves(hb, *prm, false, &waves, &level);
   if (st) return st;
-  // the Gram partial buffer is sized for the largest wave
-  size_t part_max = 0;
-  std::vector<int64_t> pk_off(hb.B, 0), log_off(hb.B, 0), nnz(hb.B + 1, 0);
-  for (auto& w : waves) {
-    WaveTables wt;
-    WaveHost h;
-    wave_host(hb, nnz, w, *prm, &wt, &h, pk_off, log_off);
-    part_max = std::max(part_max, h.gt.size() * 2 * GRAM_TILE * GRAM_TILE);
-    part_max = std::max(part_max, h.gts.size() * 2 * GRAM_TILE * GRAM_TILE);
-  }
-  *ws_bytes = ws_layout(hb, *prm, part_max).total;
+  *ws_bytes = oi_ws_bytes(hb, *prm);
   return MI_OK;
 }
 

@@ -1,0 +1,115 @@
+// Plans of the eigenspace tracking (oi.hip), shared with the adjoint
+// (adjoint.hip), which replays the same forward with checkpoints.
+#pragma once
+
+#include <vector>
+
+#include "dense.hpp"
+#include "small.hpp"
+
+namespace mis {
+
+struct BlkInfo {
+  int64_t t_off;
+  int32_t n, p, pred, pad;
+};
+
+struct WaveTables {
+  int nb = 0;
+  int T = 0, m = 0, passes = 0;
+  bool from_pred = false;
+  int max_ld = 0, max_q = 0, max_p = 0;
+  int nch = 64, nchs = 64;
+  // device tables
+  MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
+  CsrDesc* csr = nullptr;
+  SmallDesc* sd = nullptr;
+  SpmmTile* spmm = nullptr;
+  int n_spmm = 0;
+  GramTile* gt = nullptr;
+  int n_gt = 0;
+  GramReduce* gr = nullptr;
+  int n_gr = 0;
+  GramTile* gts = nullptr;
+  int n_gts = 0;
+  GramReduce* grs = nullptr;
+  int n_grs = 0;
+  RowTile* rt = nullptr;
+  int n_rt = 0;
+  RowTile* rts = nullptr;
+  int n_rts = 0;
+};
+
+struct WsLayout {
+  size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, tri, part, a_lo, b_hi, coef,
+      conv;
+  size_t total;
+  int coef_stride;
+};
+
+struct OiPlan {
+  // key
+  HostBlocks hb;
+  std::vector<int64_t> nnz_off;
+  mi_oi_params prm;
+  std::vector<const void*> ptrs;
+  size_t ws_bytes = 0;
+  bool per_block = false;
+  // content
+  std::vector<WaveTables> waves;
+  WsLayout L;
+  void* arena = nullptr;
+  BlkInfo* info = nullptr;
+  MatDesc* all_tall = nullptr;
+  CsrDesc* all_csr = nullptr;
+  int lds_max = 65536;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  ~OiPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (arena) (void)hipFree(arena);
+  }
+};
+
+// Checkpoints of one recorded forward (single wave, MI_WARM_GIVEN, no
+// adaptation of the filter interval): everything the reverse sweep needs.
+struct OiRecord {
+  void** X = nullptr;       // [npass] input basis of every filter pass (slab)
+  void** S = nullptr;       // [npass-1] operand of the Cholesky-QR row product
+                            // after pass j (ld x ld, slab element type)
+  void* Y = nullptr;        // output of the last pass (slab)
+  double* Rrr = nullptr;    // Rinv of the Rayleigh-Ritz step (FP64 ld x ld)
+  double* Z = nullptr;      // Ritz vectors of A (FP64 ld x ld, ascending)
+  double* coef = nullptr;   // filter coefficients [B][coef_stride]
+  int npass = 0;
+};
+
+struct Args {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  const void* V0;
+  void* V;
+  double* ritz;
+  int32_t* status;
+  char* ws;
+  KTimer* tm;
+  const OiRecord* rec;  // checkpoints to write (eager runs only), or null
+};
+
+// Runs the tracking eagerly on `s` with the plan held in *slot (created or
+// rebuilt as needed; ws must hold the plan's workspace), recording into
+// *rec when it is non-null.
+mi_status oi_run_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
+                      const std::vector<int64_t>& nnz, const mi_oi_params& prm,
+                      const int32_t* row_ptr, const int32_t* col, const float* val,
+                      const void* V0, void* V, double* ritz, int32_t* status, void* ws,
+                      size_t ws_bytes, const OiRecord* rec, hipStream_t s, OiPlan** plan_out);
+// Workspace bytes of the plan for (hb, prm).
+size_t oi_ws_bytes(const HostBlocks& hb, const mi_oi_params& prm);
+mi_status oi_check_params(const mi_oi_params* prm);
+
+}  // namespace mis

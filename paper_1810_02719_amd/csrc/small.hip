@@ -11,11 +11,6 @@ namespace mis {
 // Packed upper-triangle index (i <= j); q <= 1024 keeps it in 32 bits.
 __device__ __forceinline__ int pidx(int i, int j, int q) { return i * q - ((i * (i + 1)) >> 1) + j; }
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
@@ -230,30 +225,45 @@ void launch_chol_blk(const SmallDesc* sd, int nb, const double* G, double* Wk, d
 // a[blk] = max_j (Rinv^T H Rinv)_jj = max_j sum_{i<=j} Rinv[i][j] T1[i][j] with
 // T1 = H Rinv: the largest Rayleigh quotient of the Cholesky-QR basis (a
 // lower estimate of the top Ritz value, used as the filter's lower bound).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_rq_max(const SmallDesc* __restrict__ sds, const double* __restrict__ Rinv,
              const double* __restrict__ T1, double* __restrict__ a_lo) {
-  __shared__ double red[4];
+  __shared__ double colsum[4][256];
+  __shared__ double red[16];
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
   const double* R = Rinv + d.m_off;
   const double* T = T1 + d.m_off;
+  // thread (g, c): rows i = g, g + 4, ... of columns c, c + 256, ...; the
+  // four row groups are added in a fixed order
+  const int g = threadIdx.x >> 8, c = threadIdx.x & 255;
   double mx = -1e308;
-  for (int j = threadIdx.x; j < p; j += 256) {
+  for (int j0 = 0; j0 < p; j0 += 256) {
+    const int j = j0 + c;
     double s = 0.0;
-    for (int i = 0; i <= j; ++i) s += R[int64_t(i) * ld + j] * T[int64_t(i) * ld + j];
-    mx = fmax(mx, s);
+    if (j < p) {
+#pragma unroll 4
+      for (int i = g; i <= j; i += 4) s = fma(R[int64_t(i) * ld + j], T[int64_t(i) * ld + j], s);
+    }
+    colsum[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < p) mx = fmax(mx, ((colsum[0][c] + colsum[1][c]) + colsum[2][c]) + colsum[3][c]);
+    __syncthreads();
   }
   mx = wave_max(mx);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) a_lo[d.blk] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+    a_lo[d.blk] = m;
+  }
 }
 
 void launch_rq_max(const SmallDesc* sd, int nb, const double* Rinv, const double* T1,
                    double* a_lo, hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_rq_max, dim3(nb), dim3(256), 0, s, sd, Rinv, T1, a_lo);
+  hipLaunchKernelGGL(k_rq_max, dim3(nb), dim3(1024), 0, s, sd, Rinv, T1, a_lo);
 }
 
 // ------------------------------------------------------------------ Jacobi

@@ -381,6 +381,145 @@ def test_rank_deficient_start_flags_shift(ctx):
     assert torch.isfinite(V).all()
 
 
+# ------------------------------------------------------------------ batched independent blocks
+
+def test_batched_uneven_blocks_with_wide_windows(ctx):
+    """Independent Delaunay disks of uneven size in one launch, cold random
+    starts, tracked widths up to 224 (> 192: the wide-block Cholesky and the
+    Jacobi eigensolver) mixed with narrow ones in the same wave."""
+    bs = W.disk_blocks(n_blocks=6, n_min=150, n_max=1800, c_max=96, p_max=224, key=(33,))
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=10, m0=8, passes0=2)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=up.starts(torch.float32))
+    c = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
+    E = mis.project(ctx, up.blocks, c, V, up.coords)
+    Xr = mis.reconstruct(ctx, up.blocks, c, V, E)
+    torch.cuda.synchronize()
+    assert int(up.blocks.ld.max()) > 192 and int(up.blocks.ld.min()) <= 192
+    assert int(st.abs().sum()) == 0, st
+    Xh = Xr.double().cpu().numpy().reshape(-1, 3)
+    for b in range(up.blocks.n_blocks):
+        cb = int(bs.c[b])
+        _, lam, U = oracle_block(up, b)
+        ang = S.sin_theta_max(U[:, :cb], up.slab(V, b)[:, :cb])
+        assert ang < ANGLE_FP32, (b, ang, cb, lam[cb] - lam[cb - 1] if cb < len(lam) else None)
+        Xo = S.encode_decode(U[:, :cb], up.X32(b))
+        v0, v1 = int(up.blocks.v_off[b]), int(up.blocks.v_off[b + 1])
+        assert S.rel_error(Xh[v0:v1], Xo) < RECON_FP32, b
+
+
+# ------------------------------------------------------------------ dynamic meshes (Section 7.3)
+
+def test_dynamic_frames_warm_from_previous_frame(ctx):
+    """Fixed connectivity, deforming coordinates, distance weights of the
+    current frame (the weights are what changes the spectrum): each frame's
+    Laplacian values are recomputed on the fixed CSR structure and its OI is
+    warm-started from the previous frame's subspace of the same block."""
+    bs = W.dynamic_frames(nu=30, n_blocks=6, n_frames=60, c=40, p=64)
+    up = Uploaded(bs)
+    frames = bs.extra["frames"]
+    Lp = up.laplacian(ctx, mis.MI_W_INV_SQ_DIST)
+    V0 = up.starts(torch.float32)
+    cold = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=8, m0=10, passes0=2)
+    # later frames: previous frame's basis and its largest Ritz value as the
+    # lower filter bound
+    # (distance weights give a wide spectrum, lambda_max / lambda_c ~ 50: the
+    # kept space rotates by up to 0.7 rad between frames and a degree-10
+    # filter gains about 10x per pass, so 5 iterations instead of 8 cold)
+    warm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=5, m0=10, passes0=2,
+                        a_mode=mis.MI_A_RITZ)
+    V = ritz = None
+    for f, fr in enumerate(frames[:4]):
+        X = np.concatenate([np.asarray(x, np.float32) for x in fr])
+        coords = torch.from_numpy(np.ascontiguousarray(X.reshape(-1))).to("cuda:0")
+        if f > 0:
+            mis.laplacian_values(ctx, up.blocks, Lp, coords, mis.MI_W_INV_SQ_DIST)
+        V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, cold if f == 0 else warm,
+                                   V0=V0 if f == 0 else V.clone(),
+                                   ritz=None if f == 0 else ritz.clone())
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0, (f, st)
+        for b in range(up.blocks.n_blocks):
+            xb = X[up.blocks.v_off[b]:up.blocks.v_off[b + 1]].astype(np.float64)
+            faces = np.asarray(up.bs.faces[b], np.int64)
+            e = lap.canonical_edges(faces, xb.shape[0])
+            Lo = lap.laplacian_dense(xb.shape[0], e, lap.edge_weights(e, xb, lap.INV_SQ_DIST))
+            lam, U = S.eigh_lowest(Lo, 41)
+            ang = S.sin_theta_max(U[:, :40], up.slab(V, b)[:, :40])
+            assert ang < ANGLE_FP32, (f, b, ang, lam[40] - lam[39])
+
+
+# ------------------------------------------------------------------ iteration control (Section 4)
+
+@pytest.mark.parametrize("precision", [mis.MI_FP32, mis.MI_FP64])
+@pytest.mark.parametrize("mode", [lap.COMBINATORIAL, lap.INV_SQ_DIST])
+def test_ritz_residuals_against_oracle(ctx, precision, mode):
+    """|| L v_j - theta_j v_j || of every tracked column against the oracle on
+    the same seeded inputs (orthonormal random columns, random theta), blocks
+    of ragged size (partial 16-row tiles), both element types, unit and
+    distance weights."""
+    bs = W.icosphere_blocks(level=4, n_blocks=5, c=24, p=40)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx, mode)
+    dt = torch.float64 if precision == mis.MI_FP64 else torch.float32
+    V = up.starts(dt, key=(61,))
+    P = int(up.blocks.t_off[-1])
+    th = M.rng_for(62).uniform(0.0, 2.0, P)
+    ritz = torch.from_numpy(th).cuda()
+    res = mis.ritz_residuals(ctx, up.blocks, Lp, V, ritz, precision)
+    torch.cuda.synchronize()
+    r = res.cpu().numpy()
+    assert np.all(np.isfinite(r)) and r.size == P
+    assert any(int(n) % 16 for n in up.blocks.n)
+    for b in range(up.blocks.n_blocks):
+        L, lam, _ = oracle_block(up, b, mode)
+        p = int(up.blocks.p[b])
+        t0 = int(up.blocks.t_off[b])
+        Vb = V[int(up.blocks.u_off[b]):int(up.blocks.u_off[b + 1])].view(int(up.blocks.n[b]), -1)
+        ro = it.ritz_residuals(L, Vb[:, :p].double().cpu().numpy(), th[t0:t0 + p])
+        # combinatorial weights are exact on both sides (only the summation
+        # order differs); distance weights are FP32 in the CSR, each within an
+        # ulp of the oracle's FP64 value, so ||dL||_2 <= ||dL||_inf
+        # <= 2^-23 * 2 max_i D_ii <= 2^-22 * lambda_max (plus FP64 rounding)
+        tol = 1e-12 if mode == lap.COMBINATORIAL else 2.0 ** -21
+        err = np.abs(r[t0:t0 + p] - ro)
+        assert err.max() <= tol * lam[-1], (b, err.max(), tol * lam[-1])
+
+
+def test_tolerance_mode_meets_davis_kahan(ctx):
+    """Tolerance mode: every block ends with max_{j<c} r_j <= tol * theta_{p-1};
+    a tighter tolerance takes at least as many iterations per block; and the
+    angle to the oracle's eigenspace obeys the sin-theta bound
+    ||R||_F / (lambda_{c+1} - theta_c) of the residuals the GPU reports."""
+    bs = W.icosphere_blocks(level=5, n_blocks=4, c=40, p=64)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T=1, m=8, passes=1, T0=1,
+                       m0=8, passes0=1)
+    res = {}
+    for tol in (1e-2, 3e-4):
+        res[tol] = mis.oi_track_tol(ctx, up.blocks, Lp, prm, tol, c=40, max_iters=60,
+                                    V0=up.starts(torch.float32))
+        torch.cuda.synchronize()
+        R = res[tol]
+        assert R.converged.all() and (R.iters >= 1).all(), (tol, R.rel, R.iters)
+        assert int(R.status.abs().sum()) == 0
+        assert (R.rel <= tol).all()
+    assert (res[3e-4].iters >= res[1e-2].iters).all()
+    assert res[3e-4].total_iters > res[1e-2].total_iters
+    R = res[3e-4]
+    r, th = R.resid.cpu().numpy(), R.ritz.cpu().numpy()
+    for b in range(up.blocks.n_blocks):
+        _, lam, U = oracle_block(up, b, k=42)
+        t0 = int(up.blocks.t_off[b])
+        delta = lam[40] - th[t0 + 39]
+        assert delta > 0
+        bound = np.sqrt(np.sum(r[t0:t0 + 40] ** 2)) / delta
+        ang = S.sin_theta_max(U[:, :40], up.slab(R.V, b)[:, :40])
+        assert ang <= bound * (1 + 1e-6) + 1e-6, (b, ang, bound)
+
+
 # ------------------------------------------------------------------ choice of c (Section 5, Eq. 16)
 
 def test_choose_c_against_oracle(ctx):
@@ -410,3 +549,106 @@ def test_choose_c_against_oracle(ctx):
         if int(cg[b]) != co:  # only a near-tie at the target may differ
             k = min(int(cg[b]), co) - 1
             assert abs(curve[k] - target) < 1e-3 * target
+
+
+# ------------------------------------------------------------------ adjoint of encode/decode
+
+def _adjoint_case(ctx, precision, mode, key=81):
+    """Three icosphere blocks (about 214 vertices: 14 SpMM tiles with a ragged
+    tail), p = 16, c = 8, two iterations of two degree-4 passes on a fixed
+    interval, seeded start, seeded d loss / d X~ and dyadic user weights
+    (exact in FP32, so both sides build the same L)."""
+    from oracle import adjoint as adj
+    bs = W.icosphere_blocks(level=3, n_blocks=3, c=8, p=16)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx, mis.MI_W_COMBINATORIAL if mode == mis.MI_W_USER else mode)
+    rng = M.rng_for(key)
+    ne = int(Lp.edge_off[-1])
+    uw = (rng.integers(32, 128, size=ne) / 64.0).astype(np.float32)
+    if mode == mis.MI_W_USER:
+        mis.laplacian_values(ctx, up.blocks, Lp, up.coords, mis.MI_W_USER,
+                             torch.from_numpy(uw).cuda())
+    dt = torch.float64 if precision == mis.MI_FP64 else torch.float32
+    a, b = 1.2, 14.0
+    prm = mis.OiParams(precision=precision, warm=mis.MI_WARM_GIVEN, T0=2, m0=4, passes0=2,
+                       adapt=0, a_mode=mis.MI_A_ABS, a_value=a, b_abs=b)
+    V0 = up.starts(dt, key=(key, 1))
+    N = int(up.blocks.v_off[-1])
+    G = rng.normal(size=(N, 3))
+    c = torch.full((up.blocks.n_blocks,), 8, dtype=torch.int32, device="cuda:0")
+    X = torch.from_numpy(up.fl["coords"].reshape(-1).astype(np.float64)).to(dt).cuda()
+    Gd = torch.from_numpy(G.reshape(-1)).to(dt).cuda()
+    Xbar, wbar = mis.encdec_adjoint(ctx, up.blocks, Lp, prm, V0, X, c, Gd)
+    torch.cuda.synchronize()
+    Xbar = Xbar.cpu().numpy().reshape(-1, 3)
+    wbar = wbar.cpu().numpy()
+    V0h = V0.double().cpu().numpy()
+    amode = {mis.MI_W_USER: lap.USER, mis.MI_W_COMBINATORIAL: lap.COMBINATORIAL,
+             mis.MI_W_INV_SQ_DIST: lap.INV_SQ_DIST}[mode]
+    out = []
+    for bk in range(up.blocks.n_blocks):
+        n, ld = int(up.blocks.n[bk]), int(up.blocks.ld[bk])
+        v0, v1 = int(up.blocks.v_off[bk]), int(up.blocks.v_off[bk + 1])
+        e0, e1 = int(Lp.edge_off[bk]), int(Lp.edge_off[bk + 1])
+        e = lap.canonical_edges(up.bs.faces[bk], n)
+        Vb = V0h[int(up.blocks.u_off[bk]):int(up.blocks.u_off[bk + 1])].reshape(n, ld)[:, :16]
+        gX, gw = adj.unrolled_grad(n, e, up.X32(bk), amode, Vb, a, b, 4, 4, 8, G[v0:v1],
+                                   uw[e0:e1].astype(np.float64))
+        out.append((gX, gw, Xbar[v0:v1], wbar[e0:e1]))
+    return out
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("mode", [mis.MI_W_USER, mis.MI_W_COMBINATORIAL])
+def test_adjoint_fp64_against_unrolled_autograd(ctx, mode):
+    """FP64 reverse sweep against FP64 autograd of the oracle's own unrolled
+    forward on the same L: both differentiate the same map, so only rounding
+    separates them."""
+    for b, (gX, gw, Xg, wg) in enumerate(_adjoint_case(ctx, mis.MI_FP64, mode)):
+        assert _rel(wg, gw) < 1e-8, (b, _rel(wg, gw))
+        assert _rel(Xg, gX) < 1e-8, (b, _rel(Xg, gX))
+
+
+def test_adjoint_fp32_against_unrolled_autograd(ctx):
+    """FP32 slabs (FP64 small matrices and accumulation) against the FP64
+    autograd reference."""
+    for b, (gX, gw, Xg, wg) in enumerate(_adjoint_case(ctx, mis.MI_FP32, mis.MI_W_USER)):
+        print(f"block {b}: rel err wbar {_rel(wg, gw):.2e} Xbar {_rel(Xg, gX):.2e}")
+        assert _rel(wg, gw) < 1e-3, (b, _rel(wg, gw))
+        assert _rel(Xg, gX) < 1e-4, (b, _rel(Xg, gX))
+
+
+def test_adjoint_distance_weights_chain(ctx):
+    """Distance weights: Xbar includes the path through w(X).  The GPU's
+    weights are FP32 roundings of the oracle's FP64 ones (relative 2^-24), so
+    the two gradients belong to Laplacians that differ by that much."""
+    for b, (gX, gw, Xg, wg) in enumerate(_adjoint_case(ctx, mis.MI_FP64, mis.MI_W_INV_SQ_DIST)):
+        print(f"block {b}: rel err wbar {_rel(wg, gw):.2e} Xbar {_rel(Xg, gX):.2e}")
+        assert _rel(wg, gw) < 1e-4, (b, _rel(wg, gw))
+        assert _rel(Xg, gX) < 1e-4, (b, _rel(Xg, gX))
+
+
+def test_encode_decode_autograd_function(ctx):
+    """torch.autograd.Function wrapper: forward equals project + reconstruct
+    of the tracked basis, backward equals encdec_adjoint."""
+    bs = W.icosphere_blocks(level=3, n_blocks=3, c=8, p=16)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx, mis.MI_W_INV_SQ_DIST)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=2, m0=4, passes0=2,
+                       adapt=0, a_mode=mis.MI_A_ABS, a_value=20.0, b_abs=0.0)
+    V0 = up.starts(torch.float32, key=(91,))
+    c = torch.full((3,), 8, dtype=torch.int32, device="cuda:0")
+    X = up.coords.clone().requires_grad_(True)
+    Xr = mis.EncodeDecode.apply(X, None, ctx, up.blocks, Lp, prm, V0, c)
+    G = torch.from_numpy(M.rng_for(92).normal(size=X.numel()).astype(np.float32)).cuda()
+    (Xr * G).sum().backward()
+    V, _, _ = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
+    E = mis.project(ctx, up.blocks, c, V, up.coords)
+    ref = mis.reconstruct(ctx, up.blocks, c, V, E)
+    Xbar, _ = mis.encdec_adjoint(ctx, up.blocks, Lp, prm, V0, up.coords, c, G)
+    torch.cuda.synchronize()
+    assert torch.equal(Xr.detach(), ref)
+    assert torch.allclose(X.grad.double(), Xbar, rtol=1e-6, atol=1e-6 * float(Xbar.abs().max()))

@@ -97,3 +97,26 @@ def test_kernel_class_table_and_timer_arguments():
     n = (C.c_int64 * L.MI_K_COUNT)()
     assert lib.mi_ctx_kernel_times(None, ms, n) == L.MI_ERR_ARG
     assert lib.mi_ctx_set_timing(None, 1) == L.MI_ERR_ARG
+
+
+def test_residual_and_adjoint_workspace_queries():
+    b = mis.Blocks([300, 500], p=[40, 64])
+    n = C.c_size_t()
+    assert L.lib().mi_residual_workspace_size(None, b.ref, C.byref(n)) == 0
+    # one FP64 partial of ld per 16-row tile
+    assert n.value == 8 * (19 * 64 + 32 * 64)
+    nnz = np.array([0, 2000, 5500], np.int64)
+    nnz_p = nnz.ctypes.data_as(C.POINTER(C.c_int64))
+    ok = mis.OiParams(warm=mis.MI_WARM_GIVEN, adapt=0, T0=2, passes0=2, m0=4)
+
+    def q(prm, blocks=b):
+        return L.lib().mi_adjoint_workspace_size(None, blocks.ref, C.byref(prm.struct()), nnz_p,
+                                                 C.byref(n))
+
+    assert q(ok) == 0 and n.value > 0
+    for field, value in (("warm", mis.MI_WARM_PRED), ("adapt", 1), ("rr_every", 1),
+                         ("eig", L.MI_EIG_JACOBI), ("T0", 0)):
+        bad = mis.OiParams(**{**ok.__dict__, field: value})
+        assert q(bad) == L.MI_ERR_ARG, field
+    wide = mis.Blocks([300, 500], p=[40, 200])
+    assert q(ok, wide) == L.MI_ERR_ARG

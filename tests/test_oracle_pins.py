@@ -393,3 +393,144 @@ class TestIterations:
         # a band below the current error floor shrinks c
         _, c2, _ = it.paper_doi(L, U[:, :30], X, 2, 1e-3, 1e9, 2e9, 40)
         assert c2 < 30
+
+
+# ---------------------------------------------------------------- Section 4, iteration count
+
+class TestRitzResiduals:
+    def test_exact_pairs_have_zero_residual(self):
+        bs = W.grid_single(nx=9, ny=8, c=6, p=8)
+        _, L = comb_L(bs.faces[0], 72)
+        lam, U = np.linalg.eigh(L)
+        r = it.ritz_residuals(L, U[:, :8], lam[:8])
+        assert r.max() < 1e-12 * lam[-1]
+
+    def test_two_vector_mix_closed_form(self):
+        # v = cos(phi) u_i + sin(phi) u_k: theta = cos^2 lam_i + sin^2 lam_k and
+        # L v - theta v = sin(phi) cos(phi) (lam_i - lam_k) (sin(phi) u_i - cos(phi) u_k),
+        # so r = |sin(phi) cos(phi)| |lam_k - lam_i|
+        _, L = comb_L(M.icosahedron()[1], 12)
+        lam, U = np.linalg.eigh(L)
+        i, k = 1, 9
+        assert abs(lam[k] - lam[i]) > 1.0
+        for phi in (0.0, 0.1, 0.7, 1.3):
+            v = np.cos(phi) * U[:, i] + np.sin(phi) * U[:, k]
+            th = np.cos(phi) ** 2 * lam[i] + np.sin(phi) ** 2 * lam[k]
+            r = it.ritz_residuals(L, v[:, None], np.array([th]))[0]
+            assert abs(r - abs(np.sin(phi) * np.cos(phi)) * abs(lam[k] - lam[i])) < 1e-12
+
+    def test_residual_bounds_distance_to_spectrum(self):
+        # symmetric L, unit v: some eigenvalue lies within r of the Rayleigh quotient
+        bs = W.grid_single(nx=10, ny=10, c=6, p=10)
+        _, L = comb_L(bs.faces[0], 100)
+        lam = np.linalg.eigvalsh(L)
+        V0 = M.random_orthonormal(100, 10, M.rng_for(5))
+        Vs = it.chebyshev_span(L, V0, 1.5, lam[-1] + 0.1, 3, 1)
+        th, Vr = it.rayleigh_ritz(L, Vs)
+        r = it.ritz_residuals(L, Vr, th)
+        assert r.max() > 1e-3  # not converged: the bound is not trivially met
+        for j in range(10):
+            assert np.abs(lam - th[j]).min() <= r[j] * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------- gradient of encode/decode
+
+class TestAdjointOracle:
+    """The FP64 autograd gradient of the unrolled encode/decode against
+    central finite differences, its special cases, and its converged limit."""
+
+    @pytest.fixture(scope="class")
+    def case(self):
+        from oracle import adjoint as adj
+        bs = W.grid_single(nx=6, ny=5, c=4, p=8)
+        n = 30
+        e = lap.canonical_edges(bs.faces[0], n)
+        X = bs.coords[0].astype(np.float64)
+        rng = M.rng_for(71)
+        V0 = M.random_orthonormal(n, 8, rng)
+        G = rng.normal(size=(n, 3))
+        uw = rng.uniform(0.5, 2.0, e.shape[0])
+        return adj, n, e, X, V0, G, uw
+
+    def _loss(self, adj, n, e, X, mode, V0, G, uw, N, m=3, c=4, b=12.0):
+        import torch
+        with torch.no_grad():
+            Xr = adj.encdec(n, torch.from_numpy(e), torch.from_numpy(X), mode,
+                            torch.from_numpy(V0), 0.9, b, m, N, c,
+                            torch.from_numpy(uw) if uw is not None else None)
+        return float((Xr.numpy() * G).sum())
+
+    def test_user_weights_match_central_differences(self, case):
+        adj, n, e, X, V0, G, uw = case
+        gX, gw = adj.unrolled_grad(n, e, X, adj.USER, V0, 0.9, 12.0, 3, 3, 4, G, uw)
+        h = 1e-6
+        for k in (0, 7, 20, e.shape[0] - 1):
+            wp, wm = uw.copy(), uw.copy()
+            wp[k] += h
+            wm[k] -= h
+            fd = (self._loss(adj, n, e, X, adj.USER, V0, G, wp, 3)
+                  - self._loss(adj, n, e, X, adj.USER, V0, G, wm, 3)) / (2 * h)
+            assert abs(fd - gw[k]) <= 1e-6 * max(1.0, abs(gw).max()), (k, fd, gw[k])
+        # projection path of X at fixed L
+        for (i, d) in ((0, 0), (13, 2), (29, 1)):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, d] += h
+            Xm[i, d] -= h
+            fd = (self._loss(adj, n, e, Xp, adj.USER, V0, G, uw, 3)
+                  - self._loss(adj, n, e, Xm, adj.USER, V0, G, uw, 3)) / (2 * h)
+            assert abs(fd - gX[i, d]) <= 1e-6 * max(1.0, abs(gX).max())
+
+    def test_distance_weights_chain_into_coordinates(self, case):
+        adj, n, e, X, V0, G, _ = case
+        Xz = X.copy()
+        Xz[:, 2] += 0.05 * np.sin(3 * X[:, 0])  # non-flat so every direction matters
+        gX, _ = adj.unrolled_grad(n, e, Xz, adj.INV_SQ_DIST, V0, 0.9, 40.0, 3, 3, 4, G)
+        h = 1e-6
+        for (i, d) in ((1, 0), (14, 1), (22, 2)):
+            Xp, Xm = Xz.copy(), Xz.copy()
+            Xp[i, d] += h
+            Xm[i, d] -= h
+            fd = (self._loss(adj, n, e, Xp, adj.INV_SQ_DIST, V0, G, None, 3, b=40.0)
+                  - self._loss(adj, n, e, Xm, adj.INV_SQ_DIST, V0, G, None, 3, b=40.0)) / (2 * h)
+            assert abs(fd - gX[i, d]) <= 1e-5 * max(1.0, abs(gX).max()), (i, d, fd, gX[i, d])
+
+    def test_combinatorial_gradient_is_the_projector(self, case):
+        # L does not depend on X: d loss/dX = U_c U_c^T Gbar with U_c the forward's basis
+        import torch
+        adj, n, e, X, V0, G, _ = case
+        gX, _ = adj.unrolled_grad(n, e, X, adj.COMBINATORIAL, V0, 0.9, 12.0, 3, 3, 4, G)
+        with torch.no_grad():
+            P = adj.encdec(n, torch.from_numpy(e), torch.eye(n, dtype=torch.float64),
+                           adj.COMBINATORIAL, torch.from_numpy(V0), 0.9, 12.0, 3, 3, 4).numpy()
+        assert np.abs(P - P.T).max() < 1e-12 and np.abs(P @ P - P).max() < 1e-12
+        assert abs(np.trace(P) - 4) < 1e-12
+        assert np.abs(gX - P @ G).max() < 1e-12
+
+    def test_eigenprojector_formula_matches_central_differences(self, case):
+        adj, n, e, X, _, G, uw = case
+        L = lap.laplacian_dense(n, e, uw)
+        _, gw = adj.eigenprojector_grad(L, e, X, G, 4)
+
+        def f(w):
+            lam, U = np.linalg.eigh(lap.laplacian_dense(n, e, w))
+            return float((U[:, :4] @ (U[:, :4].T @ X) * G).sum())
+
+        h = 1e-6
+        for k in (2, 11, 30):
+            wp, wm = uw.copy(), uw.copy()
+            wp[k] += h
+            wm[k] -= h
+            fd = (f(wp) - f(wm)) / (2 * h)
+            assert abs(fd - gw[k]) <= 1e-6 * max(1.0, abs(gw).max()), (k, fd, gw[k])
+
+    def test_unrolled_gradient_tends_to_the_converged_limit(self, case):
+        adj, n, e, X, V0, G, uw = case
+        L = lap.laplacian_dense(n, e, uw)
+        lam = np.linalg.eigvalsh(L)
+        gXl, gwl = adj.eigenprojector_grad(L, e, X, G, 4)
+        errs = []
+        for N in (2, 8, 40):
+            gX, gw = adj.unrolled_grad(n, e, X, adj.USER, V0, lam[8] + 0.05, lam[-1] + 0.1, 4, N,
+                                       4, G, uw)
+            errs.append(np.abs(gw - gwl).max() / np.abs(gwl).max())
+        assert errs[-1] < 1e-8 and errs[0] > errs[-1], errs

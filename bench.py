@@ -2,9 +2,11 @@
 
 Workload: a displaced level-7 icosphere (163,842 vertices) split by seeded
 region growing into 100 submeshes of ~1,638 vertices, combinatorial
-Laplacian, c = 100 tracked eigenvectors per block (width p = 192), the first
-block from a seeded random start, every other block warm-started from its
-predecessor in BFS block order with 3 orthogonal-iteration steps, FP32.
+Laplacian, c = 100 tracked eigenvectors per block (width p = 192).  Three
+first blocks (a seeded one and two chosen farthest-first on the block graph)
+start from seeded random bases with 5 orthogonal-iteration steps; every other
+block is warm-started from its BFS parent (an adjacent block) with 3 steps;
+FP32.  The blocks of one BFS level run together (5 levels).
 
 One step = eigenspace tracking of all blocks (every wave, one HIP graph
 replay) + projection of the xyz coordinates onto the first c Ritz vectors +
@@ -34,6 +36,9 @@ def parse():
     ap.add_argument("--cpu-sample-blocks", type=int, default=60)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + a few steps only (for profilers)")
+    ap.add_argument("--traffic-calib", action="store_true",
+                    help="first copy 256 MiB once (a plain copy kernel of known size: "
+                         "the scale of the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -49,7 +54,7 @@ def main():
     from synth import workloads as W
 
     t0 = time.time()
-    bs = W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192)
+    bs = W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192, n_roots=N_ROOTS)
     fl = W.flatten(bs)
     dev = "cuda:0"
     blocks = mis.Blocks(bs.n, p=fl["p"], ld=fl["ld"], pred=bs.pred)
@@ -86,6 +91,13 @@ def main():
         mis.project(ctx, blocks, c, V, coords, E=E)
         mis.reconstruct(ctx, blocks, c, V, E, Xr=Xr)
 
+    if args.traffic_calib:
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -134,7 +146,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "icosphere7_100blocks_c100_T3_fp32", "vertices": nverts,
                    "blocks": int(blocks.n_blocks), "c": 100, "p": 192, "T": 3, "m": 10,
-                   "passes": 2, "T_first": 5, "m_first": 10, "passes_first": 2, "waves": int(bs.level.max() + 1)},
+                   "passes": 2, "first_blocks": int((bs.pred < 0).sum()), "T_first": 5,
+                   "m_first": 10, "passes_first": 2, "waves": int(bs.level.max() + 1)},
         "per_block_baseline": None if per_block_ms is None else
         {"value": nverts / (per_block_ms * 1e-3), "unit": "vertices/s", "ms": per_block_ms},
         "roofline": roofline(ktimes, bs, blocks, L, prm),
@@ -152,6 +165,26 @@ def main():
     return 0
 
 
+N_ROOTS = 3  # first blocks (cold starts); the rest are warm-started
+CALIB_BYTES = 256 << 20
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "spmm_row_icosphere7_b100_traffic.json")
+SPMM_SOURCE = os.path.join(HERE, "paper_1810_02719_amd", "csrc", "dense.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the SpMM from the committed rocprofv3 counter
+    passes (FETCH_SIZE and WRITE_SIZE, scaled by the same counters of a copy
+    of known size), or None when the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(SPMM_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector and MFMA (dense)
 
@@ -182,8 +215,10 @@ def roofline(ktimes, bs, blocks, L, prm):
             slab = int((n[sel] * ld[sel] * es).sum())
             per_pass = m * (csr + 2 * slab) + (m - 1) * slab
             tot += T * (passes * per_pass + csr + 2 * slab)
-        out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot)
+        out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot,
+                   bytes_per_launch=tot / max(launches, 1))
         out["achieved"] = tot / (ms * 1e-3) / 1e9
+        out["traffic"] = measured_traffic()
     elif dom == "chol":
         # Cholesky (p^3/3) and triangular inverse (p^3/3) of every block's
         # Gram, for each of the step's Cholesky-QRs

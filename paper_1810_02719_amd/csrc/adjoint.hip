@@ -520,7 +520,7 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
   launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, static_cast<const T*>(rec.Y), w.small, Rc, w.tall, Q,
                       w.nch, s);
   launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, Q, nullptr, Wl, rec.coef,
-                 stride, m, s);
+                 stride, m, s, w.epl);
   // projection and Rayleigh-Ritz adjoint
   hipLaunchKernelGGL(k_adj_tall6<T>, dim3(B, ADJ_CHUNKS), dim3(256), 0, s, A.dev, Q, X, G, part);
   hipLaunchKernelGGL(k_adj_sum6, dim3(B), dim3(256), 0, s, A.dev, part, EF);
@@ -553,7 +553,8 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
     auto y_at = [&](int k) -> const T* { return k == 0 ? xin : ys + int64_t(k - 1) * slab; };
     for (int k = 0; k + 1 < m; ++k)
       launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y_at(k),
-                     k > 0 ? y_at(k - 1) : nullptr, ys + int64_t(k) * slab, rec.coef, stride, k, s);
+                     k > 0 ? y_at(k - 1) : nullptr, ys + int64_t(k) * slab, rec.coef, stride, k, s,
+                     w.epl);
     // reverse recurrence
     int nxt = cur, prv = -1;
     for (int k = m - 1; k >= 0; --k) {

@@ -38,12 +38,11 @@ constexpr double CHOL_SHIFT = 2e-13;
 constexpr double CHOL_FLAG = 10.0 * CHOL_SHIFT;
 constexpr double CHOL_PIV_TOL = 1e-13;  // pivot floor
 
-// Orders one wavefront's LDS writes before its lanes read each other's
-// values (the compiler may otherwise move a read above another lane's write).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Value of v in lane src (any lane of the wavefront), as a double.
+__device__ __forceinline__ double lane_get(double v, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ d4v mfma64(double a, double b, d4v c) {
@@ -67,41 +66,41 @@ __device__ __forceinline__ d4v tile_tn(d4v acc, const double* P, int ldp, int r,
 // accumulator registers (element (mq + 4 q, mi) in g[q]) by the same row
 // operations as the panels, applied to the identity: returns M_KK = R^-T in
 // the same layout and writes R^-1 = M^T to Di.  Row k of the working matrix
-// and of M travels through a 32-double LDS buffer between wavefront-scope
-// fences.  Entries below the diagonal of the working matrix collect values
+// and of M is read straight from the lanes that hold it (lane (k mod 4) 16 +
+// column); entries below the diagonal of the working matrix collect values
 // that are never read.
-__device__ d4v diag_factor(d4v g, double* rowbuf, double* Di, int ldd, int lane, int* fl) {
+__device__ d4v diag_factor(d4v g, double* Di, int ldd, int lane, int* fl) {
   const int mi = lane & 15, mq = lane >> 4;
   d4v mm;
 #pragma unroll
   for (int q = 0; q < 4; ++q) mm[q] = (mq + 4 * q == mi) ? 1.0 : 0.0;
+#pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const int kq = k >> 2;
-    if (mq == (k & 3)) {
-      rowbuf[mi] = kq == 0 ? g[0] : kq == 1 ? g[1] : kq == 2 ? g[2] : g[3];
-      rowbuf[16 + mi] = kq == 0 ? mm[0] : kq == 1 ? mm[1] : kq == 2 ? mm[2] : mm[3];
-    }
-    wave_sync();
-    double piv = rowbuf[k];
+    const int kq = k >> 2, src = 16 * (k & 3);
+    double piv = lane_get(g[kq], src + k);
+    const double gkj = lane_get(g[kq], src + mi);   // working row k, column mi
+    const double mkj0 = lane_get(mm[kq], src + mi);  // M row k, column mi
+    double gki[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gki[q] = lane_get(g[kq], src + mq + 4 * q);
     if (!(piv > CHOL_FLAG)) {
       *fl |= isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE;
       if (!(piv > CHOL_PIV_TOL)) piv = CHOL_PIV_TOL;
     }
     const double inv = 1.0 / sqrt(piv);
-    const double rkj = rowbuf[mi] * inv;       // R[k][j]
-    const double mkj = rowbuf[16 + mi] * inv;  // new M[k][j]
+    const double rkj = gkj * inv;   // R[k][j]
+    const double mkj = mkj0 * inv;  // new M[k][j]
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = mq + 4 * q;
       if (i == k) {
         mm[q] = mkj;
       } else if (i > k) {
-        const double rki = rowbuf[i] * inv;
+        const double rki = gki[q] * inv;
         g[q] = fma(-rki, rkj, g[q]);
         mm[q] = fma(-rki, mkj, mm[q]);
       }
     }
-    wave_sync();  // all reads of row k before the next row is written
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) Di[mi * ldd + mq + 4 * q] = mm[q];
@@ -123,7 +122,6 @@ __global__ void __launch_bounds__(1024)
   __shared__ double bufA[16 * LDB];           // old panel: G^ row K | M row K
   __shared__ double bufB[16 * LDB];           // new panel: R row K  | M row K
   __shared__ double Dg[16 * LDD];             // R_KK^-1
-  __shared__ double rowbuf[32];
   __shared__ double dsc[16 * NT];
   __shared__ int flag;
 
@@ -186,7 +184,7 @@ __global__ void __launch_bounds__(1024)
       if (a == K) {
         if (b == K) {
           int fl = 0;
-          reg[s] = diag_factor(reg[s], rowbuf, Dg, LDD, lane, &fl);
+          reg[s] = diag_factor(reg[s], Dg, LDD, lane, &fl);
           if (lane == 0 && fl) atomicOr(&flag, fl);
         } else {
 #pragma unroll

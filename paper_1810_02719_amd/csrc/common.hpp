@@ -77,20 +77,24 @@ __host__ __device__ inline int rr_index(int pos, int r, int q) {
   return 1 + ((pos - 1 + r) % (q - 1));
 }
 
-// Event timer of the kernel classes (mi_ctx_set_timing): every launch of a
-// timed call is bracketed by two events on the launch stream; the elapsed
-// times are summed per class when they are read.
+// Event timer of the kernel classes (mi_ctx_set_timing): consecutive
+// launches of one class on one stream form a group bracketed by two events
+// on that stream (a pair per launch would add the event overhead, about
+// 2 us, to every launch); the elapsed times and launch counts are summed per
+// class when they are read.  Every timed entry point closes its last group
+// before it returns.
 struct KTimer {
   struct Rec {
-    int k;
+    int k, cnt;
     hipEvent_t a, b;
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   double ms[MI_K_COUNT] = {};
   int64_t n[MI_K_COUNT] = {};
-  int open_k = -1;
+  int open_k = -1, open_n = 0;
   hipEvent_t open_a = nullptr;
+  hipStream_t open_s = nullptr;
   hipEvent_t take() {
     hipEvent_t e = nullptr;
     if (!pool.empty()) {
@@ -102,15 +106,25 @@ struct KTimer {
     return e;
   }
   void begin(int k, hipStream_t s) {
+    if (open_a && k == open_k && s == open_s) {
+      ++open_n;
+      return;
+    }
+    close();
     open_k = k;
+    open_s = s;
+    open_n = 1;
     open_a = take();
     if (open_a) (void)hipEventRecord(open_a, s);
   }
-  void end(hipStream_t s) {
+  void close() {
+    if (!open_a) return;
     hipEvent_t b = take();
-    if (b && open_a) {
-      (void)hipEventRecord(b, s);
-      pending.push_back(Rec{open_k, open_a, b});
+    if (b) {
+      (void)hipEventRecord(b, open_s);
+      pending.push_back(Rec{open_k, open_n, open_a, b});
+    } else {
+      pool.push_back(open_a);
     }
     open_a = nullptr;
   }
@@ -118,16 +132,20 @@ struct KTimer {
   ~KTimer();
 };
 
-// Brackets the launches made during its lifetime with the timer's events
-// (no-op when timing is off).
+// Marks the launches made during its lifetime as class k (no-op when timing
+// is off).
 struct KScope {
-  KTimer* t;
-  hipStream_t s;
-  KScope(KTimer* t_, int k, hipStream_t s_) : t(t_), s(s_) {
+  KScope(KTimer* t, int k, hipStream_t s) {
     if (t) t->begin(k, s);
   }
-  ~KScope() {
-    if (t) t->end(s);
+};
+
+// Closes the timer's open group when the entry point returns.
+struct KClose {
+  KTimer* t;
+  explicit KClose(KTimer* t_) : t(t_) {}
+  ~KClose() {
+    if (t) t->close();
   }
 };
 

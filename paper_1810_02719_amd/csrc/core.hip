@@ -175,12 +175,13 @@ void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
 }
 
 mi_status KTimer::collect() {
+  close();
   for (const Rec& r : pending) {
     float t = 0.f;
     MI_TRY_HIP(hipEventSynchronize(r.b));
     MI_TRY_HIP(hipEventElapsedTime(&t, r.a, r.b));
     ms[r.k] += t;
-    n[r.k] += 1;
+    n[r.k] += r.cnt;
     pool.push_back(r.a);
     pool.push_back(r.b);
   }
@@ -189,6 +190,7 @@ mi_status KTimer::collect() {
 }
 
 KTimer::~KTimer() {
+  close();
   for (const Rec& r : pending) {
     (void)hipEventSynchronize(r.b);
     pool.push_back(r.a);

@@ -60,22 +60,103 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Same product when every block of the launch has ld = 64 * EPL: one
+// wavefront per row (16 per workgroup, one tile), every lane owns EPL
+// consecutive elements of the row, and the row's neighbour rows are
+// gathered SPMM_GATHER at a time with clamped indices (zero weight past the
+// row end), so all of those loads are issued before the first use.
+// Workgroups are dealt to the 8 XCDs in turn; workgroup i takes tile
+// (i mod 8) * per + i / 8, so each XCD works through one contiguous eighth
+// of the tiles and the neighbour rows a row gathers (nearby in the BFS
+// vertex order) are mostly already in that XCD's L2.
+constexpr int SPMM_GATHER = 8;
+constexpr int NUM_XCD = 8;
+
+template <typename T, int EPL>
+__global__ void __launch_bounds__(1024)
+    k_spmm_row(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+               const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+               const int32_t* __restrict__ col, const float* __restrict__ val,
+               const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+               const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int ti = (blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
+  if (ti >= ntiles) return;
+  const SpmmTile t = tiles[ti];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MatDesc d = sets[t.set];
+  const int r = t.row0 + wave;
+  if (r >= d.rows) return;  // wave-uniform
+  const CsrDesc c = csr[t.set];
+  const int lane = threadIdx.x & 63;
+  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+  const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
+  const T* yv = Yin + d.off + lane * EPL;
+  const int32_t* cb = col + c.nnz_off;
+  const float* vb = val + c.nnz_off;
+  const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
+  T acc[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) acc[e] = (T)0;
+  for (int k = k0; k < k1; k += SPMM_GATHER) {
+    T y[SPMM_GATHER][EPL];
+    T w[SPMM_GATHER];
+#pragma unroll
+    for (int u = 0; u < SPMM_GATHER; ++u) {
+      const int kk = min(k + u, k1 - 1);
+      w[u] = k + u < k1 ? (T)vb[kk] : (T)0;
+      const T* src = yv + int64_t(cb[kk]) * d.ld;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) y[u][e] = src[e];
+    }
+#pragma unroll
+    for (int u = 0; u < SPMM_GATHER; ++u)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
+  }
+  const int64_t o = d.off + int64_t(r) * d.ld + lane * EPL;
+  T out[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) out[e] = alpha * acc[e] + beta * Yin[o + e];
+  if (Yprev) {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) out[e] += gamma * Yprev[o + e];
+  }
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) Yout[o + e] = out[e];
+}
+
 template <typename T>
 void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
                  const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
                  const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
-                 hipStream_t s) {
+                 hipStream_t s, int epl) {
   if (ntiles <= 0) return;
+#define MI_SPMM_ROW(E)                                                                          \
+  case E:                                                                                       \
+    hipLaunchKernelGGL((k_spmm_row<T, E>), dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)),          \
+                       dim3(64 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin,     \
+                       Yprev, Yout, coef, coef_stride, step, ntiles);                            \
+    return;
+  switch (epl) {
+    MI_SPMM_ROW(1)
+    MI_SPMM_ROW(2)
+    MI_SPMM_ROW(3)
+    MI_SPMM_ROW(4)
+    default:
+      break;
+  }
+#undef MI_SPMM_ROW
   hipLaunchKernelGGL(k_spmm<T>, dim3(ntiles), dim3(256), 0, s, tiles, sets, csr, row_ptr, col, val,
                      Yin, Yprev, Yout, coef, coef_stride, step);
 }
 
 template void launch_spmm<float>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
                                  const int32_t*, const int32_t*, const float*, const float*,
-                                 const float*, float*, const double*, int, int, hipStream_t);
+                                 const float*, float*, const double*, int, int, hipStream_t, int);
 template void launch_spmm<double>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
                                   const int32_t*, const int32_t*, const float*, const double*,
-                                  const double*, double*, const double*, int, int, hipStream_t);
+                                  const double*, double*, const double*, int, int, hipStream_t, int);
 
 // ------------------------------------------------------------------ Gram
 // One workgroup: a 64 x 64 super-tile of A^T B (and A^T W when DUAL) over a
@@ -436,6 +517,14 @@ void row_tables(const std::vector<MatDesc>& sets, int nch, std::vector<RowTile>*
     for (int r0 = 0; r0 < d.rows; r0 += ROW_TILE)
       for (int n0 = 0; n0 < d.ld; n0 += nch) tiles->push_back(RowTile{si, r0, n0});
   }
+}
+
+int spmm_epl(const std::vector<MatDesc>& sets) {
+  if (sets.empty()) return 0;
+  const int ld = sets[0].ld;
+  for (const MatDesc& d : sets)
+    if (d.ld != ld) return 0;
+  return (ld % 64 == 0 && ld <= 256) ? ld / 64 : 0;
 }
 
 void spmm_tables(const std::vector<MatDesc>& sets, std::vector<SpmmTile>* tiles) {

@@ -63,7 +63,10 @@ template <typename T>
 void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
                  const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
                  const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
-                 hipStream_t s);
+                 hipStream_t s, int epl = 0);
+// Elements per lane of the wavefront-per-row SpMM when every block of a
+// launch has the same ld, a multiple of 64 up to 256; 0 otherwise.
+int spmm_epl(const std::vector<MatDesc>& sets);
 
 template <typename T>
 void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T* A, const T* B,

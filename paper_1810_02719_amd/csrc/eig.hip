@@ -71,6 +71,13 @@ __device__ __forceinline__ double sum32(const double* x) {
   return half_sum(x[threadIdx.x & 31]);
 }
 
+// 1 / b by the hardware reciprocal and one Newton step (b nonzero and
+// finite: the pivots are guarded away from zero).
+__device__ __forceinline__ double recip(double b) {
+  const double r = __builtin_amdgcn_rcp(b);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+
 __device__ __forceinline__ double guard(double t, double floor_) {
   return fabs(t) < floor_ ? -floor_ : t;
 }
@@ -92,11 +99,12 @@ __device__ TriScale tri_scale(const double* __restrict__ dd, const double* __res
     e2 = fmax(e2, er * er);
   }
   for (int o = 32; o > 0; o >>= 1) {
+    if (o >= (int)blockDim.x) continue;  // workgroups narrower than a wavefront
     lo = fmin(lo, __shfl_xor(lo, o, 64));
     hi = fmax(hi, __shfl_xor(hi, o, 64));
     e2 = fmax(e2, __shfl_xor(e2, o, 64));
   }
-  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6, wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[wv] = lo;
     red[nw + wv] = hi;
@@ -344,9 +352,7 @@ __global__ void __launch_bounds__(64)
           // e2 / t by the hardware reciprocal and one Newton step: a count
           // only needs the pivot's sign, which a few ulps cannot flip
           // except within rounding distance of an eigenvalue
-          double r = __builtin_amdgcn_rcp(t[m]);
-          r = fma(r, fma(-t[m], r, 1.0), r);
-          t[m] = guard((di - x[m]) - e2 * r, sc.pivmin);
+          t[m] = guard((di - x[m]) - e2 * recip(t[m]), sc.pivmin);
           c[m] += t[m] < 0.0;
         }
       }
@@ -437,22 +443,30 @@ __device__ void tri_inverse_iteration(const double* __restrict__ sd_, const doub
   }
 }
 
-__global__ void __launch_bounds__(64)
+constexpr int TRI_VEC_THREADS = 32;  // eigenvalues per workgroup (pivots in LDS)
+
+__global__ void __launch_bounds__(TRI_VEC_THREADS)
     k_tri_vectors(const SmallDesc* __restrict__ sds, const double* __restrict__ tri,
                   double* __restrict__ DP, double* __restrict__ DM, double* __restrict__ ZT,
                   int32_t* __restrict__ status) {
   extern __shared__ double smem[];
   __shared__ double red[3];
+  constexpr int NT = TRI_VEC_THREADS;
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
-  const int j = blockIdx.y * 64 + threadIdx.x;
-  if (blockIdx.y * 64 >= p) return;
+  const int tx = threadIdx.x;
+  const int j = blockIdx.y * NT + tx;
+  if (blockIdx.y * NT >= p) return;
   double* sd_ = smem;
   double* se = smem + p;
+  // forward / backward pivots of this workgroup's eigenvalues: pivot i of
+  // thread tx at [i][tx] (consecutive threads in consecutive banks)
+  double* ldp = smem + 2 * p;
+  double* ldm = ldp + p * NT;
   const double* dd = tri + 4 * d.t_off;
   const double* ee = dd + p;
   const double* lam = dd + 2 * p;
-  for (int i = threadIdx.x; i < p; i += 64) {
+  for (int i = tx; i < p; i += NT) {
     sd_[i] = dd[i];
     se[i] = ee[i];
   }
@@ -462,30 +476,31 @@ __global__ void __launch_bounds__(64)
   if (j > 0 && !(lam[j] - lam[j - 1] > ctol)) return;  // inside a cluster led by an earlier j
   int j1 = j;
   while (j1 + 1 < p && !(lam[j1 + 1] - lam[j1] > ctol)) ++j1;
-  double* dp = DP + d.m_off;
-  double* dm = DM + d.m_off;
   double* Zt = ZT + d.m_off;
   if (j1 > j) {
-    tri_inverse_iteration(sd_, se, lam, p, ld, j, j1, sc.tn, dp, dm, Zt);
+    tri_inverse_iteration(sd_, se, lam, p, ld, j, j1, sc.tn, DP + d.m_off, DM + d.m_off, Zt);
     return;
   }
   const double lj = lam[j];
   const double pm = sc.pivmin;
+  // the two pivot recurrences only store (no loads on their chains)
   double t = guard(sd_[0] - lj, pm);
-  dp[j] = t;
+  ldp[tx] = t;
   for (int i = 1; i < p; ++i) {
-    t = guard((sd_[i] - lj) - se[i - 1] * se[i - 1] / t, pm);
-    dp[int64_t(i) * ld + j] = t;
+    t = guard((sd_[i] - lj) - se[i - 1] * se[i - 1] * recip(t), pm);
+    ldp[i * NT + tx] = t;
   }
-  const double dp_last = t;
   t = guard(sd_[p - 1] - lj, pm);
-  dm[int64_t(p - 1) * ld + j] = t;
-  int kmin = p - 1;
-  double gmin = fabs(dp_last + t - (sd_[p - 1] - lj));
+  ldm[(p - 1) * NT + tx] = t;
   for (int i = p - 2; i >= 0; --i) {
-    t = guard((sd_[i] - lj) - se[i] * se[i] / t, pm);
-    dm[int64_t(i) * ld + j] = t;
-    const double gam = fabs(dp[int64_t(i) * ld + j] + t - (sd_[i] - lj));
+    t = guard((sd_[i] - lj) - se[i] * se[i] * recip(t), pm);
+    ldm[i * NT + tx] = t;
+  }
+  // twist index: smallest |dp_k + dm_k - (d_k - lambda)| (independent terms)
+  int kmin = p - 1;
+  double gmin = fabs(ldp[(p - 1) * NT + tx] + ldm[(p - 1) * NT + tx] - (sd_[p - 1] - lj));
+  for (int i = p - 2; i >= 0; --i) {
+    const double gam = fabs(ldp[i * NT + tx] + ldm[i * NT + tx] - (sd_[i] - lj));
     if (gam < gmin) {
       gmin = gam;
       kmin = i;
@@ -495,18 +510,18 @@ __global__ void __launch_bounds__(64)
   Zt[int64_t(kmin) * ld + j] = 1.0;
   double z = 1.0;
   for (int i = kmin - 1; i >= 0; --i) {
-    z = -se[i] * z / dp[int64_t(i) * ld + j];
+    z = -se[i] * z * recip(ldp[i * NT + tx]);
     Zt[int64_t(i) * ld + j] = z;
     nrm = fma(z, z, nrm);
   }
   z = 1.0;
   for (int i = kmin + 1; i < p; ++i) {
-    z = -se[i - 1] * z / dm[int64_t(i) * ld + j];
+    z = -se[i - 1] * z * recip(ldm[i * NT + tx]);
     Zt[int64_t(i) * ld + j] = z;
     nrm = fma(z, z, nrm);
   }
   if (!isfinite(nrm)) {  // overflow in the recurrences: fall back to inverse iteration
-    tri_inverse_iteration(sd_, se, lam, p, ld, j, j, sc.tn, dp, dm, Zt);
+    tri_inverse_iteration(sd_, se, lam, p, ld, j, j, sc.tn, DP + d.m_off, DM + d.m_off, Zt);
     return;
   }
   const double inv = 1.0 / sqrt(nrm);
@@ -621,8 +636,10 @@ void launch_tri_bisect(const SmallDesc* sd, int nb, int max_p, double* tri, doub
 void launch_tri_vectors(const SmallDesc* sd, int nb, int max_p, const double* tri, double* DP,
                         double* DM, double* ZT, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_tri_vectors, dim3(nb, ceil_div(max_p, 64)), dim3(64),
-                     size_t(2 * max_p) * sizeof(double), s, sd, tri, DP, DM, ZT, status);
+  hipLaunchKernelGGL(k_tri_vectors, dim3(nb, ceil_div(max_p, TRI_VEC_THREADS)),
+                     dim3(TRI_VEC_THREADS),
+                     size_t(2 * max_p + 2 * max_p * TRI_VEC_THREADS) * sizeof(double), s, sd, tri,
+                     DP, DM, ZT, status);
 }
 
 void launch_tri_back(const SmallDesc* sd, int nb, int max_ld, const double* ZT, const double* Hv,

@@ -216,6 +216,7 @@ mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   double* part = static_cast<double*>(ws);
+  KClose kc_(ctx->timer);
   KScope k_(ctx->timer, MI_K_PROJECT, s);
   if (precision == MI_FP64) {
     hipLaunchKernelGGL(k_project_part<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
@@ -247,6 +248,7 @@ mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, c
   hipStream_t s = (hipStream_t)stream;
   const int64_t N = hb.v_off[hb.B];
   const int grid = ceil_div(N, 4);
+  KClose kc_(ctx->timer);
   KScope k_(ctx->timer, MI_K_RECONSTRUCT, s);
   if (precision == MI_FP64)
     hipLaunchKernelGGL(k_reconstruct<double>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff, hb.B,

@@ -287,6 +287,7 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
   wt->nch = pick_nch(lds_list, dbl);
   wt->nchs = pick_nch(lds_list, true);
   spmm_tables(h->tall, &h->spmm);
+  wt->epl = spmm_epl(h->tall);
   gram_tables(h->tall, true, &h->gt, &h->gr);
   gram_tables(h->small, false, &h->gts, &h->grs);
   row_tables(h->tall, wt->nch, &h->rt);
@@ -406,6 +407,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
 
 template <typename T>
 static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
+  KClose kc_(a.tm);
   const mi_oi_params& prm = P.prm;
   const WsLayout& L = P.L;
   char* ws = a.ws;
@@ -526,7 +528,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           {
             KScope k_(a.tm, MI_K_SPMM, s);
             launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, cur, prev, out,
-                           coef, L.coef_stride, k, s);
+                           coef, L.coef_stride, k, s, w.epl);
           }
           prev = cur;
           cur = out;
@@ -568,7 +570,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       {
         KScope k_(a.tm, MI_K_SPMM, s);
         launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
-                       L.coef_stride, w.m, s);
+                       L.coef_stride, w.m, s, w.epl);
       }
       {
         KScope k_(a.tm, MI_K_GRAM, s);

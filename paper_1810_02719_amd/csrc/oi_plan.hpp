@@ -20,6 +20,7 @@ struct WaveTables {
   bool from_pred = false;
   int max_ld = 0, max_q = 0, max_p = 0;
   int nch = 64, nchs = 64;
+  int epl = 0;  // elements per lane of the row-per-wavefront SpMM (0: generic kernel)
   // device tables
   MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
   CsrDesc* csr = nullptr;

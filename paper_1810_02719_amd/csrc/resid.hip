@@ -203,6 +203,7 @@ mi_status mi_ritz_residuals(mi_ctx* ctx, const mi_blocks* blk, int32_t precision
   }
   hipStream_t s = (hipStream_t)stream;
   double* part = static_cast<double*>(ws);
+  KClose kc_(ctx->timer);
   KScope k_(ctx->timer, MI_K_SETUP, s);
   if (P->ntiles > 0) {
     if (precision == MI_FP64)

@@ -346,11 +346,14 @@ def split_blocks(n: int, faces: np.ndarray, label: np.ndarray, seeds: np.ndarray
 
 
 def block_graph_order(n: int, faces: np.ndarray, label: np.ndarray, n_blocks: int,
-                      rng: np.random.Generator):
-    """Block processing order: a seeded first block, then BFS over the block
-    adjacency graph (blocks adjacent when a mesh edge joins them), ties by
-    block id.  Returns (order, pred, level) with pred = BFS parent (-1 for the
-    first block) and level = BFS depth."""
+                      rng: np.random.Generator, n_roots: int = 1):
+    """Block processing order: a seeded first block (and, for n_roots > 1,
+    further first blocks chosen farthest-first on the block graph: each the
+    block at the largest BFS distance from those already chosen, ties by
+    block id), then multi-source BFS over the block adjacency graph (blocks
+    adjacent when a mesh edge joins them), ties by block id.  Returns
+    (order, pred, level) with pred = BFS parent (-1 for first blocks) and
+    level = BFS depth."""
     e = np.concatenate([faces[:, [0, 1]], faces[:, [1, 2]], faces[:, [2, 0]]])
     la = label[e[:, 0]]
     lb = label[e[:, 1]]
@@ -361,13 +364,29 @@ def block_graph_order(n: int, faces: np.ndarray, label: np.ndarray, n_blocks: in
         adj[a].append(int(b))
     for a in range(n_blocks):
         adj[a] = sorted(set(adj[a]))
-    first = int(rng.integers(n_blocks))
+    from collections import deque
+
+    def depth(srcs):
+        d = -np.ones(n_blocks, dtype=np.int64)
+        dq = deque(srcs)
+        for r in srcs:
+            d[r] = 0
+        while dq:
+            u = dq.popleft()
+            for v in adj[u]:
+                if d[v] < 0:
+                    d[v] = d[u] + 1
+                    dq.append(v)
+        return d
+
+    roots = [int(rng.integers(n_blocks))]
+    while len(roots) < min(n_roots, n_blocks):
+        roots.append(int(np.argmax(depth(roots))))
     pred = -np.ones(n_blocks, dtype=np.int64)
     level = -np.ones(n_blocks, dtype=np.int64)
-    order = [first]
-    level[first] = 0
-    from collections import deque
-    q = deque([first])
+    order = list(roots)
+    level[roots] = 0
+    q = deque(roots)
     while q:
         u = q.popleft()
         for v in adj[u]:

@@ -61,12 +61,13 @@ def flatten(bs: BlockSet, ld=None):
                 c=np.asarray(bs.c, dtype=np.int32))
 
 
-def _partitioned(name, verts, faces, n_blocks, key, c, p):
+def _partitioned(name, verts, faces, n_blocks, key, c, p, n_roots=1):
     n = verts.shape[0]
     indptr, indices = M.vertex_adjacency(n, faces)
     label, seeds = M.region_grow(indptr, indices, n_blocks, M.rng_for(*key, 1), pts=verts)
     blocks = M.split_blocks(n, faces, label, seeds)
-    order, pred, level = M.block_graph_order(n, faces, label, n_blocks, M.rng_for(*key, 2))
+    order, pred, level = M.block_graph_order(n, faces, label, n_blocks, M.rng_for(*key, 2),
+                                             n_roots)
     coords = [verts[g] for g, _ in blocks]
     fl = [f for _, f in blocks]
     nb = len(blocks)
@@ -85,11 +86,14 @@ def grid_single(nx=32, ny=32, c=50, p=75, sigma=1e-3, key=(1,)):
                     global_ids=[np.arange(v.shape[0])], n_global=v.shape[0])
 
 
-def icosphere_blocks(level=7, n_blocks=100, c=100, p=150, amp=0.05, key=(2,)):
-    """Static block sequence: displaced icosphere split by region growing."""
+def icosphere_blocks(level=7, n_blocks=100, c=100, p=150, amp=0.05, key=(2,), n_roots=1):
+    """Static block sequence: displaced icosphere split by region growing;
+    n_roots first blocks (cold starts), every other block warm-started from
+    its BFS parent."""
     v, f = M.icosphere(level)
     v = M.displaced_sphere(v, M.rng_for(*key, 0), amp)
-    return _partitioned(f"icosphere{level}_b{n_blocks}", v, f, n_blocks, key, c, p)
+    name = f"icosphere{level}_b{n_blocks}" + (f"_r{n_roots}" if n_roots > 1 else "")
+    return _partitioned(name, v, f, n_blocks, key, c, p, n_roots)
 
 
 def disk_blocks(n_blocks=1024, n_min=500, n_max=5000, c_max=256, p_max=320, key=(3,)):

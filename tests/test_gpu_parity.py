@@ -280,9 +280,9 @@ def test_eigen_solvers_agree(ctx, chain_small, rr_every):
         assert S.sin_theta_max(up.slab(Vt, b)[:, :100], up.slab(Vj, b)[:, :100]) < 2e-5
 
 
-@pytest.fixture(scope="module")
-def chain_c2():
-    return Uploaded(W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192))
+@pytest.fixture(scope="module", params=[1, 3], ids=["roots1", "roots3"])
+def chain_c2(request):
+    return Uploaded(W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192, n_roots=request.param))
 
 
 @pytest.mark.parametrize("eig", [mis._lib.MI_EIG_TRIDIAG, mis._lib.MI_EIG_JACOBI])
@@ -303,7 +303,11 @@ def test_c2_chain_every_block_healthy(ctx, chain_c2, eig, T):
         Vb = up.slab(V, b)[:, :int(up.blocks.p[b])]
         assert np.abs(Vb.T @ Vb - np.eye(Vb.shape[1])).max() < 1e-4, b
     if T == 3:
-        _chain_check(up, V, ritz, st, 100, sample=[84, 87, 98])
+        if int((up.blocks.pred < 0).sum()) == 3:
+            # the benchmark's configuration: every block against the oracle
+            _chain_check(up, V, ritz, st, 100)
+        else:
+            _chain_check(up, V, ritz, st, 100, sample=[84, 87, 98])
 
 
 def test_per_block_reference_path(ctx, chain_small):

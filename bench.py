@@ -78,7 +78,8 @@ def main():
     lap_ms = (time.time() - tl) * 1e3
 
     prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED, T=3, m=10, passes=2, T0=5,
-                       m0=10, passes0=2, adapt=1, max_sweeps=12, a_mode=mis.MI_A_WEYL, a_value=1.0)
+                       m0=10, passes0=2, adapt=1, max_sweeps=12, a_mode=mis.MI_A_WEYL, a_value=1.0,
+                       autotune=1)
     V = torch.empty(int(blocks.u_off[-1]), dtype=torch.float32, device=dev)
     ritz = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
     status = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
@@ -152,6 +153,7 @@ def main():
         {"value": nverts / (per_block_ms * 1e-3), "unit": "vertices/s", "ms": per_block_ms},
         "roofline": roofline(ktimes, bs, blocks, L, prm),
         "kernels": {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in ktimes.items() if v[1]},
+        "launch_shapes": [list(t) for t in ctx.tuning()],
         "build_laplacian_ms": lap_ms,
         "block_status_nonzero": int((st != 0).sum()),
         "input_gen_s": gen_s,

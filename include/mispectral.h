@@ -115,6 +115,13 @@ typedef struct {
                         (Householder tridiagonalisation, Sturm multisection and
                         inverse iteration; used when every ld_b <= 192, else the
                         Jacobi sweeps) or MI_EIG_JACOBI (parallel cyclic Jacobi) */
+  int32_t autotune;  /* 1: when the plan is made (first call, or after the block
+                        table, parameters or buffers change), time candidate launch
+                        shapes of the Gram (split-K), the row product (output width)
+                        and the SpMM (row-per-wavefront or generic) per wave on the
+                        plan's own tables and keep the fastest; 0: fixed heuristics.
+                        The results agree to rounding (the Gram split changes the
+                        summation order).  mi_oi_tuning reports the choice. */
   double a_value;
   double b_abs;      /* > 0: upper filter bound b for every block; else Gershgorin     */
   double jacobi_tol; /* off-diagonal threshold relative to ||A||_F on the last
@@ -254,6 +261,12 @@ mi_status mi_laplacian_values(mi_ctx* ctx, const mi_blocks* blk, const int64_t* 
  * table, parameters and pointers stay the same. */
 mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                                size_t* ws_bytes);
+/* Launch shapes of the context's current tracking plan, three int32 per wave
+ * (Gram split-K target in workgroups, row-product output width, SpMM elements
+ * per lane or 0 for the generic kernel) for up to `cap` waves; *n_waves gets
+ * the plan's wave count.  Host only. */
+mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves);
+
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                       const int32_t* row_ptr, const int32_t* col, const float* val,
                       const int64_t* nnz_off, const void* V0, void* V, double* ritz,

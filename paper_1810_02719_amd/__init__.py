@@ -105,6 +105,15 @@ class Context:
             self._ws[tag] = t
         return t
 
+    def tuning(self):
+        """Launch shapes of the current tracking plan: one (gram_target, nch,
+        spmm_elements_per_lane) triple per wave."""
+        n = C.c_int32()
+        L.check(L.lib().mi_oi_tuning(self.h, None, 0, C.byref(n)))
+        buf = (C.c_int32 * (3 * max(n.value, 1)))()
+        L.check(L.lib().mi_oi_tuning(self.h, buf, n.value, C.byref(n)))
+        return [tuple(buf[3 * w:3 * w + 3]) for w in range(n.value)]
+
     def set_timing(self, on: bool):
         """Per-kernel event timing of later oi_track / project / reconstruct
         calls (eager launches); restarts the totals."""
@@ -205,11 +214,12 @@ class OiParams:
     jacobi_tol: float = 1e-14
     rr_every: int = 0
     eig: int = 0  # MI_EIG_TRIDIAG (Jacobi for ld > 192) or MI_EIG_JACOBI
+    autotune: int = 0  # 1: time candidate launch shapes when the plan is made
 
     def struct(self):
         return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
                             self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, self.rr_every,
-                            self.eig, self.a_value, self.b_abs, self.jacobi_tol)
+                            self.eig, self.autotune, self.a_value, self.b_abs, self.jacobi_tol)
 
 
 def _dtype(precision):

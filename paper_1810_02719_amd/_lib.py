@@ -67,7 +67,7 @@ class MiOiParams(C.Structure):
                 ("passes", C.c_int32), ("T0", C.c_int32), ("m0", C.c_int32),
                 ("passes0", C.c_int32), ("adapt", C.c_int32), ("max_sweeps", C.c_int32),
                 ("a_mode", C.c_int32), ("rr_every", C.c_int32), ("eig", C.c_int32),
-                ("a_value", C.c_double),
+                ("autotune", C.c_int32), ("a_value", C.c_double),
                 ("b_abs", C.c_double), ("jacobi_tol", C.c_double)]
 
 
@@ -84,6 +84,7 @@ _SIGS = {
     "mi_laplacian_values": [_vp, C.POINTER(MiBlocks), _i64p, _i64p, C.c_int32, _vp, _vp, _vp, _vp,
                             _vp, _vp, _vp, _vp, _vp],
     "mi_oi_workspace_size": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _szp],
+    "mi_oi_tuning": [_vp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)],
     "mi_oi_track": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp, _i64p, _vp,
                     _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_oi_track_per_block": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp,

@@ -471,8 +471,8 @@ template void launch_rowmul<double, float>(const RowTile*, int, const MatDesc*, 
 
 // ------------------------------------------------------------------ tile tables
 
-int gram_chunks(int nsets, int npairs, int rows) {
-  const int target = 384;  // workgroups per launch: enough to fill the chip, few partials
+int gram_chunks(int nsets, int npairs, int rows, int target) {
+  // target: workgroups per launch (enough to fill the chip, few partials)
   int ch = ceil_div(target, std::max(1, nsets * npairs));
   ch = std::min(ch, std::max(1, rows / 64));
   return std::max(ch, 1);
@@ -480,12 +480,12 @@ int gram_chunks(int nsets, int npairs, int rows) {
 
 // Gram tile table for a list of per-block matrices with `rows` rows each.
 void gram_tables(const std::vector<MatDesc>& sets, bool split,
-                        std::vector<GramTile>* tiles, std::vector<GramReduce>* red) {
+                        std::vector<GramTile>* tiles, std::vector<GramReduce>* red, int target) {
   for (int si = 0; si < (int)sets.size(); ++si) {
     const MatDesc& d = sets[si];
     const int nsup = ceil_div(d.ld, GRAM_TILE);
     const int npairs = nsup * (nsup + 1) / 2;
-    const int ch = split ? gram_chunks((int)sets.size(), npairs, d.rows) : 1;
+    const int ch = split ? gram_chunks((int)sets.size(), npairs, d.rows, target) : 1;
     int rows_per = ceil_div(d.rows, ch);
     rows_per = ((rows_per + 15) / 16) * 16;
     for (int I = 0; I < nsup; ++I)

@@ -83,9 +83,10 @@ void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const
 // Tile tables (host).  Gram: 64 x 64 super-tiles of the upper triangle,
 // split over row chunks when `split` (about 2048 workgroups in total);
 // rows: 64-row x nch-column tiles; SpMM: SPMM_ROWS-row tiles.
-int gram_chunks(int nsets, int npairs, int rows);
+constexpr int GRAM_TARGET = 384;  // default workgroups of a split Gram launch
+int gram_chunks(int nsets, int npairs, int rows, int target = GRAM_TARGET);
 void gram_tables(const std::vector<MatDesc>& sets, bool split, std::vector<GramTile>* tiles,
-                 std::vector<GramReduce>* red);
+                 std::vector<GramReduce>* red, int target = GRAM_TARGET);
 void row_tables(const std::vector<MatDesc>& sets, int nch, std::vector<RowTile>* tiles);
 void spmm_tables(const std::vector<MatDesc>& sets, std::vector<SpmmTile>* tiles);
 

@@ -253,7 +253,7 @@ struct WaveHost {
 static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
                       const std::vector<int>& blocks, const mi_oi_params& prm, WaveTables* wt,
                       WaveHost* h, const std::vector<int64_t>& pk_off,
-                      const std::vector<int64_t>& log_off) {
+                      const std::vector<int64_t>& log_off, const WaveTune* tune = nullptr) {
   const bool dbl = prm.precision == MI_FP64;
   std::vector<int> lds_list;
   for (int b : blocks) {
@@ -284,11 +284,12 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
     wt->max_p = std::max(wt->max_p, s.p);
   }
   wt->nb = (int)blocks.size();
-  wt->nch = pick_nch(lds_list, dbl);
+  wt->nch = tune ? tune->nch : pick_nch(lds_list, dbl);
   wt->nchs = pick_nch(lds_list, true);
   spmm_tables(h->tall, &h->spmm);
-  wt->epl = spmm_epl(h->tall);
-  gram_tables(h->tall, true, &h->gt, &h->gr);
+  wt->epl = tune ? tune->epl : spmm_epl(h->tall);
+  wt->gram_target = tune ? tune->gram_target : GRAM_TARGET;
+  gram_tables(h->tall, true, &h->gt, &h->gr, wt->gram_target);
   gram_tables(h->small, false, &h->gts, &h->grs);
   row_tables(h->tall, wt->nch, &h->rt);
   row_tables(h->small, wt->nchs, &h->rts);
@@ -303,9 +304,22 @@ static X* put(std::vector<char>& blob, const std::vector<X>& v, std::vector<size
   return reinterpret_cast<X*>(off);  // relocated after upload
 }
 
+// Gram split-K targets and row-product widths the autotuner tries.
+static const int kGramTargets[] = {192, 384, 768, 1536};
+static const int kNchs[] = {64, 96, 128, 192, 256};
+
+// Gram partial doubles of the largest split a tuned plan may choose.
+static size_t tuned_part_max(const std::vector<MatDesc>& tall) {
+  std::vector<GramTile> gt;
+  std::vector<GramReduce> gr;
+  gram_tables(tall, true, &gt, &gr, kGramTargets[3]);
+  return gt.size() * 2 * GRAM_TILE * GRAM_TILE;
+}
+
 static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
                            const mi_oi_params& prm, bool per_block, int lds_max,
-                           std::unique_ptr<OiPlan>* out, size_t* ws_need) {
+                           std::unique_ptr<OiPlan>* out, size_t* ws_need,
+                           const std::vector<WaveTune>* tune = nullptr) {
   std::unique_ptr<OiPlan> P(new OiPlan());
   P->hb = hb;
   P->nnz_off = nnz_off;
@@ -336,9 +350,11 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
     wt.T = warm_wave ? prm.T : prm.T0;
     wt.m = warm_wave ? prm.m : prm.m0;
     wt.passes = warm_wave ? prm.passes : prm.passes0;
-    wave_host(hb, nnz_off, waves[w], prm, &wt, &hosts[w], pk_off, log_off);
+    wave_host(hb, nnz_off, waves[w], prm, &wt, &hosts[w], pk_off, log_off,
+              tune ? &(*tune)[w] : nullptr);
     part_max = std::max(part_max, hosts[w].gt.size() * 2 * GRAM_TILE * GRAM_TILE);
     part_max = std::max(part_max, hosts[w].gts.size() * 2 * GRAM_TILE * GRAM_TILE);
+    if (prm.autotune) part_max = std::max(part_max, tuned_part_max(hosts[w].tall));
   }
   P->L = ws_layout(hb, prm, part_max);
   *ws_need = P->L.total;
@@ -398,9 +414,116 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
     wt.n_rt = (int)h.rt.size();
     wt.rts = reinterpret_cast<RowTile*>(base + offs[k++]);
     wt.n_rts = (int)h.rts.size();
+    wt.tall_host = h.tall;
   }
   *out = std::move(P);
   return MI_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Per wave, times the candidate launch shapes of the tall-skinny kernels on
+// the plan's own tables and workspace (operand values do not matter for the
+// timing; every index stays inside the same buffers as in production) and
+// keeps the fastest: the Gram's split-K target, the row product's output
+// width, and the SpMM variant.  Runs on a private stream at plan creation.
+
+// Milliseconds per call of f: one warm-up, then three timed calls.
+template <typename F>
+static float time_calls(hipStream_t s, F&& f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  float ms = 1e30f;
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    f();
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < 3; ++r) f();
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess)
+      ms /= 3.f;
+    else
+      ms = 1e30f;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return ms;
+}
+
+// Temporary device copy of a host table.
+template <typename X>
+struct DevTable {
+  X* p = nullptr;
+  explicit DevTable(const std::vector<X>& v) {
+    if (!v.empty() && hipMalloc(&p, v.size() * sizeof(X)) == hipSuccess &&
+        hipMemcpy(p, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
+  }
+  ~DevTable() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+static void autotune_waves(const OiPlan& P, const std::vector<const void*>& ptrs, char* ws,
+                           hipStream_t s, std::vector<WaveTune>* tune) {
+  const WsLayout& L = P.L;
+  T* y0 = reinterpret_cast<T*>(ws + L.slab[0]);
+  T* y1 = reinterpret_cast<T*>(ws + L.slab[1]);
+  T* y2 = reinterpret_cast<T*>(ws + L.slab[2]);
+  const T* Sm = reinterpret_cast<const T*>(ws + L.G);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* G = reinterpret_cast<double*>(ws + L.H);
+  double* coef = reinterpret_cast<double*>(ws + L.coef);
+  const int32_t* row_ptr = static_cast<const int32_t*>(ptrs[0]);
+  const int32_t* col = static_cast<const int32_t*>(ptrs[1]);
+  const float* val = static_cast<const float*>(ptrs[2]);
+  const bool dbl = std::is_same<T, double>::value;
+  tune->clear();
+  for (const WaveTables& w : P.waves) {
+    WaveTune best{w.gram_target, w.nch, w.epl};
+    float bt = 1e30f;
+    for (int target : kGramTargets) {
+      std::vector<GramTile> gt;
+      std::vector<GramReduce> gr;
+      gram_tables(w.tall_host, true, &gt, &gr, target);
+      DevTable<GramTile> dgt(gt);
+      DevTable<GramReduce> dgr(gr);
+      if (!dgt.p || !dgr.p) continue;
+      const float t = time_calls(s, [&] {
+        launch_gram<T>(dgt.p, (int)gt.size(), w.tall, y0, y0, nullptr, part, s);
+        launch_gram_reduce(dgr.p, (int)gr.size(), w.small, part, false, G, nullptr, s);
+      });
+      if (t < bt) bt = t, best.gram_target = target;
+    }
+    bool same = true;
+    for (const MatDesc& d : w.tall_host) same = same && d.ld == w.tall_host[0].ld;
+    bt = 1e30f;
+    for (int nch : kNchs) {
+      if (nch > (dbl ? 128 : 256)) continue;
+      if (!(same && w.tall_host[0].ld % nch == 0) && nch != 64) continue;
+      std::vector<RowTile> rt;
+      row_tables(w.tall_host, nch, &rt);
+      DevTable<RowTile> drt(rt);
+      if (!drt.p) continue;
+      const float t = time_calls(s, [&] {
+        launch_rowmul<T, T>(drt.p, (int)rt.size(), w.tall, y0, w.small, Sm, w.tall, y1, nch, s);
+      });
+      if (t < bt) bt = t, best.nch = nch;
+    }
+    const int epl = spmm_epl(w.tall_host);
+    if (epl > 0) {
+      const float t_row = time_calls(s, [&] {
+        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y0, y1, y2, coef,
+                       L.coef_stride, 0, s, epl);
+      });
+      const float t_gen = time_calls(s, [&] {
+        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y0, y1, y2, coef,
+                       L.coef_stride, 0, s, 0);
+      });
+      best.epl = t_row <= t_gen ? epl : 0;
+    }
+    tune->push_back(best);
+  }
 }
 
 // ------------------------------------------------------------------ enqueue
@@ -755,6 +878,7 @@ static mi_status check_params(const mi_oi_params* prm) {
   MI_CHECK_ARG(prm->eig == MI_EIG_TRIDIAG || prm->eig == MI_EIG_JACOBI, "eig solver %d unknown",
                prm->eig);
   MI_CHECK_ARG(prm->jacobi_tol > 0 && prm->jacobi_tol < 1e-3, "jacobi_tol out of range");
+  MI_CHECK_ARG(prm->autotune == 0 || prm->autotune == 1, "autotune must be 0 or 1");
   return MI_OK;
 }
 
@@ -784,6 +908,23 @@ static mi_status get_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
       set_error("workspace %zu bytes < %zu required", ws_bytes, need);
       return MI_ERR_WORKSPACE;
     }
+    if (prm.autotune) {
+      if (!np->cap_stream)
+        MI_TRY_HIP(hipStreamCreateWithFlags(&np->cap_stream, hipStreamNonBlocking));
+      std::vector<WaveTune> tune;
+      if (prm.precision == MI_FP64)
+        autotune_waves<double>(*np, ptrs, static_cast<char*>(ws), np->cap_stream, &tune);
+      else
+        autotune_waves<float>(*np, ptrs, static_cast<char*>(ws), np->cap_stream, &tune);
+      MI_TRY_HIP(hipGetLastError());
+      MI_TRY_HIP(hipStreamSynchronize(np->cap_stream));
+      std::unique_ptr<OiPlan> tp;
+      st = make_plan(hb, nnz, prm, per_block, device_lds_max(ctx->device), &tp, &need, &tune);
+      if (st) return st;
+      tp->cap_stream = np->cap_stream;
+      np->cap_stream = nullptr;
+      np = std::move(tp);
+    }
     np->ptrs = ptrs;
     np->ws_bytes = ws_bytes;
     P = np.release();
@@ -808,6 +949,7 @@ size_t oi_ws_bytes(const HostBlocks& hb, const mi_oi_params& prm) {
     wave_host(hb, nnz, w, prm, &wt, &h, pk_off, log_off);
     part_max = std::max(part_max, h.gt.size() * 2 * GRAM_TILE * GRAM_TILE);
     part_max = std::max(part_max, h.gts.size() * 2 * GRAM_TILE * GRAM_TILE);
+    if (prm.autotune) part_max = std::max(part_max, tuned_part_max(h.tall));
   }
   return ws_layout(hb, prm, part_max).total;
 }
@@ -909,6 +1051,20 @@ mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_pa
   st = build_waves(hb, *prm, false, &waves, &level);
   if (st) return st;
   *ws_bytes = oi_ws_bytes(hb, *prm);
+  return MI_OK;
+}
+
+mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves) {
+  clear_error();
+  MI_CHECK_ARG(ctx && n_waves && (out || cap == 0) && cap >= 0, "NULL argument");
+  const OiPlan* P = static_cast<const OiPlan*>(ctx->oi_plan);
+  MI_CHECK_ARG(P != nullptr, "no tracking plan yet (call mi_oi_track first)");
+  *n_waves = (int32_t)P->waves.size();
+  for (int w = 0; w < (int)P->waves.size() && w < cap; ++w) {
+    out[3 * w] = P->waves[w].gram_target;
+    out[3 * w + 1] = P->waves[w].nch;
+    out[3 * w + 2] = P->waves[w].epl;
+  }
   return MI_OK;
 }
 

@@ -21,6 +21,8 @@ struct WaveTables {
   int max_ld = 0, max_q = 0, max_p = 0;
   int nch = 64, nchs = 64;
   int epl = 0;  // elements per lane of the row-per-wavefront SpMM (0: generic kernel)
+  int gram_target = GRAM_TARGET;  // workgroups of the split Gram launch
+  std::vector<MatDesc> tall_host;  // host copy of `tall` (for retuning)
   // device tables
   MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
   CsrDesc* csr = nullptr;
@@ -46,6 +48,13 @@ struct WsLayout {
       conv;
   size_t total;
   int coef_stride;
+};
+
+// Launch shape of one wave (the autotuner's choices).
+struct WaveTune {
+  int gram_target;  // split-K target of the Gram
+  int nch;          // output-column width of the row product
+  int epl;          // row-per-wavefront SpMM elements per lane (0: generic)
 };
 
 struct OiPlan {

@@ -249,6 +249,30 @@ def test_event_timed_launches_match_graph(ctx, chain_small):
         ctx.kernel_times()  # timing is off again
 
 
+def test_autotuned_launch_shapes(ctx, chain_small):
+    """autotune = 1: the plan times candidate Gram splits, row-product widths
+    and SpMM variants per wave; the result still meets the oracle and the
+    chosen shapes are valid for the wave."""
+    up = chain_small
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, warm_params(autotune=1), V0=V0)
+    torch.cuda.synchronize()
+    tune = ctx.tuning()
+    assert len(tune) == int(np.asarray(up.bs.level).max()) + 1
+    ld = int(up.blocks.ld[0])
+    for g, nch, epl in tune:
+        assert g in (192, 384, 768, 1536)
+        assert nch in (64, 96, 128, 192, 256) and (ld % nch == 0 or nch == 64)
+        assert epl in (0, ld // 64)
+    _chain_check(up, V, ritz, st, 100)
+    # the default heuristics give the same subspaces
+    V2, _, _ = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0)
+    torch.cuda.synchronize()
+    for b in range(up.blocks.n_blocks):
+        assert S.sin_theta_max(up.slab(V2, b)[:, :100], up.slab(V, b)[:, :100]) < 1e-5
+
+
 @pytest.mark.parametrize("rr_every", [0, 1])
 def test_eigen_solvers_agree(ctx, chain_small, rr_every):
     """Tridiagonal (Householder + multisection + inverse iteration) and
@@ -656,3 +680,166 @@ def test_encode_decode_autograd_function(ctx):
     torch.cuda.synchronize()
     assert torch.equal(Xr.detach(), ref)
     assert torch.allclose(X.grad.double(), Xbar, rtol=1e-6, atol=1e-6 * float(Xbar.abs().max()))
+
+
+# ------------------------------------------------------------------ full-size configurations
+# The dynamic (C5) and batched-uneven (C3) workloads and the 1M-vertex precision
+# workload (C4, in FP32) at their full sizes, checked on sampled blocks.  The
+# FP32 bar is the 1e-5 angle, raised to twice the Davis-Kahan floor
+# u32 lambda_p / gap_c where a block's own cut is too tight for FP32 to reach it.
+
+def _fp32_bar(lam, c, p):
+    return max(ANGLE_FP32, 2.0 * S.fp32_floor(lam, c, p))
+
+
+def test_c5_full_size_frames_and_adjoint(ctx):
+    """100,002-vertex geodesic sphere, 64 blocks, c = 150, p = 192, distance
+    weights of the current frame: frame 0 cold, frames 1-2 warm-started from
+    the previous frame, sampled blocks against the oracle.  Then the adjoint
+    of frame 2's encode/decode (3 iterations of two degree-10 passes on a
+    fixed interval from a seeded start) against the oracle's FP64 autograd on
+    two sampled blocks."""
+    from oracle import adjoint as adj
+    bs = W.dynamic_frames()
+    up = Uploaded(bs)
+    frames = bs.extra["frames"]
+    Lp = up.laplacian(ctx, mis.MI_W_INV_SQ_DIST)
+    cold = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=8, m0=10, passes0=2)
+    warm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=5, m0=10, passes0=2,
+                        a_mode=mis.MI_A_RITZ)
+    sample = [0, 21, 42, 63]
+    V = ritz = None
+    for f in range(3):
+        X = np.concatenate([np.asarray(x, np.float32) for x in frames[f]])
+        coords = torch.from_numpy(np.ascontiguousarray(X.reshape(-1))).to("cuda:0")
+        if f > 0:
+            mis.laplacian_values(ctx, up.blocks, Lp, coords, mis.MI_W_INV_SQ_DIST)
+        V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, cold if f == 0 else warm,
+                                   V0=up.starts(torch.float32) if f == 0 else V.clone(),
+                                   ritz=None if f == 0 else ritz.clone())
+        torch.cuda.synchronize()
+        s = st.cpu().numpy()
+        assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all(), (f, s)
+        if f == 1:
+            continue
+        for b in sample:
+            xb = X[up.blocks.v_off[b]:up.blocks.v_off[b + 1]].astype(np.float64)
+            e = lap.canonical_edges(np.asarray(up.bs.faces[b], np.int64), xb.shape[0])
+            Lo = lap.laplacian_dense(xb.shape[0], e, lap.edge_weights(e, xb, lap.INV_SQ_DIST))
+            lam, U = S.eigh_lowest(Lo, 193)
+            ang = S.sin_theta_max(U[:, :150], up.slab(V, b)[:, :150])
+            print(f"frame {f} block {b}: sin angle {ang:.2e} (bar {_fp32_bar(lam, 150, 192):.1e})")
+            assert ang <= _fp32_bar(lam, 150, 192), (f, b, ang, lam[150] - lam[149])
+    # adjoint of frame 2 on a fixed interval [a, b]: b above every block's
+    # Gershgorin bound, a below the sampled blocks' lambda_p
+    X = np.concatenate([np.asarray(x, np.float32) for x in frames[2]])
+    bsamp = [0, 42]
+    gersh, lp = 0.0, np.inf
+    Los = {}
+    for b in range(up.blocks.n_blocks):
+        xb = X[up.blocks.v_off[b]:up.blocks.v_off[b + 1]].astype(np.float64)
+        e = lap.canonical_edges(np.asarray(up.bs.faces[b], np.int64), xb.shape[0])
+        w = lap.edge_weights(e, xb, lap.INV_SQ_DIST)
+        deg = np.zeros(xb.shape[0])
+        np.add.at(deg, e[:, 0], w)
+        np.add.at(deg, e[:, 1], w)
+        gersh = max(gersh, 2.0 * deg.max())
+        if b in bsamp:
+            Los[b] = (e, xb)
+            lp = min(lp, np.linalg.eigvalsh(lap.laplacian_dense(xb.shape[0], e, w))[191])
+    a_f, b_f = 0.9 * lp, 1.01 * gersh
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=3, m0=10, passes0=2,
+                       adapt=0, a_mode=mis.MI_A_ABS, a_value=a_f, b_abs=b_f)
+    V0 = up.starts(torch.float32, key=(95,))
+    G = M.rng_for(96).normal(size=(X.shape[0], 3))
+    c = torch.full((up.blocks.n_blocks,), 150, dtype=torch.int32, device="cuda:0")
+    Xd = torch.from_numpy(np.ascontiguousarray(X.reshape(-1))).cuda()
+    Gd = torch.from_numpy(G.reshape(-1).astype(np.float32)).cuda()
+    Xbar, wbar = mis.encdec_adjoint(ctx, up.blocks, Lp, prm, V0, Xd, c, Gd)
+    torch.cuda.synchronize()
+    Xbar = Xbar.cpu().numpy().reshape(-1, 3)
+    wbar = wbar.cpu().numpy()
+    V0h = V0.double().cpu().numpy()
+    for b in bsamp:
+        e, xb = Los[b]
+        n = xb.shape[0]
+        v0, v1 = int(up.blocks.v_off[b]), int(up.blocks.v_off[b + 1])
+        e0, e1 = int(Lp.edge_off[b]), int(Lp.edge_off[b + 1])
+        Vb = V0h[int(up.blocks.u_off[b]):int(up.blocks.u_off[b + 1])].reshape(n, 192)
+        gX, gw = adj.unrolled_grad(n, e, xb, lap.INV_SQ_DIST, Vb, a_f, b_f, 10, 6, 150,
+                                   G[v0:v1].astype(np.float32).astype(np.float64))
+        rx, rw = _rel(Xbar[v0:v1], gX), _rel(wbar[e0:e1], gw)
+        print(f"adjoint block {b}: rel err Xbar {rx:.2e} wbar {rw:.2e}")
+        assert rx < 1e-2 and rw < 1e-2, (b, rx, rw)
+
+
+def test_c3_full_size_batched_uneven(ctx):
+    """1,024 independent Delaunay disks of 500-5,000 vertices (2.8M vertices),
+    p_b = min(320, n_b), c_b = min(256, p_b), cold seeded starts, one launch
+    sequence for all blocks; NMSVE curves and the choice of c for every block
+    in one call.  Every block healthy; sampled blocks (smallest, largest and
+    four seeded others) against the oracle, at the FP32 bar of their cut."""
+    bs = W.disk_blocks()
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    gl = up.laplacian(ctx, mis.MI_W_INV_DIST)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=12, m0=8, passes0=2)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=up.starts(torch.float32))
+    cmax = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
+    cg, metric = mis.choose_c(ctx, up.blocks, cmax, 1e-4, 1e-3, V, ritz, up.coords, gl)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all()
+    cgh = cg.cpu().numpy()
+    assert ((cgh >= 1) & (cgh <= np.asarray(bs.c))).all()
+    n = np.asarray(up.blocks.n)
+    rng = M.rng_for(97)
+    sample = sorted({int(np.argmin(n)), int(np.argmax(n)), *rng.choice(len(n), 4, replace=False)})
+    for b in sample:
+        cb, pb = int(bs.c[b]), int(bs.p[b])
+        _, lam, U = oracle_block(up, b, k=pb + 1)
+        ang = S.sin_theta_max(U[:, :cb], up.slab(V, b)[:, :cb])
+        print(f"block {b} (n {n[b]}, c {cb}): sin angle {ang:.2e} (bar {_fp32_bar(lam, cb, pb):.1e})")
+        assert ang <= _fp32_bar(lam, cb, pb), (b, ang, lam[cb] - lam[cb - 1])
+
+
+def test_c4_full_size_fp32(ctx):
+    """The 998,562-vertex displaced geodesic sphere in 100 blocks of about 10k
+    vertices, c = 200, p = 256, all blocks in one launch sequence from seeded
+    starts (FP32 slabs: the reduced-precision input option is not built);
+    two sampled blocks against the oracle at the FP32 bar of their cut, and
+    the SpMM's event-timed bandwidth on slabs far larger than the
+    infinity cache."""
+    bs = W.geodesic_blocks()
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=12, m0=10, passes0=2)
+    V0 = up.starts(torch.float32)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    try:
+        mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0, V=V)
+        torch.cuda.synchronize()
+        kt = ctx.kernel_times()
+    finally:
+        ctx.set_timing(False)
+    s = st.cpu().numpy()
+    assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all()
+    # algorithmic SpMM bytes: CSR once, the input rows, the previous iterate
+    # (all but the first step of a pass) and the output, per step
+    n = np.asarray(up.blocks.n, np.int64)
+    nnz = np.diff(np.asarray(Lp.nnz_off, np.int64))
+    csr = int(((n + 1) * 4 + nnz * 8).sum())
+    slab = int((n * np.asarray(up.blocks.ld, np.int64) * 4).sum())
+    per_pass = 10 * (csr + 2 * slab) + 9 * slab
+    tot = prm.T0 * (2 * per_pass + csr + 2 * slab)
+    ms, launches = kt["spmm"]
+    print(f"C4 SpMM: {launches} launches, {1e3 * ms / launches:.1f} us each, "
+          f"{tot / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+    for b in (0, 57):
+        cb, pb = int(bs.c[b]), int(bs.p[b])
+        _, lam, U = oracle_block(up, b, k=pb + 1)
+        ang = S.sin_theta_max(U[:, :cb], up.slab(V, b)[:, :cb])
+        print(f"block {b} (n {n[b]}): sin angle {ang:.2e} (bar {_fp32_bar(lam, cb, pb):.1e})")
+        assert ang <= _fp32_bar(lam, cb, pb), (b, ang, lam[cb] - lam[cb - 1])

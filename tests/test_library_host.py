@@ -53,7 +53,8 @@ def test_predecessor_cycle_rejected():
 
 
 @pytest.mark.parametrize("field,value", [("m", 0), ("passes", 0), ("T", -1), ("precision", 7),
-                                         ("a_mode", 9), ("max_sweeps", 0), ("jacobi_tol", 0.0)])
+                                         ("a_mode", 9), ("max_sweeps", 0), ("jacobi_tol", 0.0),
+                                         ("autotune", 2), ("eig", 5), ("rr_every", 3)])
 def test_bad_params(field, value):
     b = mis.Blocks([100], p=[10])
     prm = mis.OiParams()
@@ -120,3 +121,9 @@ def test_residual_and_adjoint_workspace_queries():
         assert q(bad) == L.MI_ERR_ARG, field
     wide = mis.Blocks([300, 500], p=[40, 200])
     assert q(ok, wide) == L.MI_ERR_ARG
+
+
+def test_params_struct_layout_matches_header():
+    # 14 int32 fields, then the doubles at 8-byte alignment
+    assert C.sizeof(L.MiOiParams) == 56 + 3 * 8
+    assert L.MiOiParams.a_value.offset == 56 and L.MiOiParams.autotune.offset == 52

@@ -38,6 +38,20 @@ constexpr double CHOL_SHIFT = 2e-13;
 constexpr double CHOL_FLAG = 10.0 * CHOL_SHIFT;
 constexpr double CHOL_PIV_TOL = 1e-13;  // pivot floor
 
+// Orders one wavefront's LDS writes before its lanes read each other's
+// values (the compiler may otherwise move a read above another lane's write).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1 / sqrt(x) for x > 0: hardware estimate and one Newton step.
+__device__ __forceinline__ double inv_sqrt(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
+
 // Value of v in lane src (any lane of the wavefront), as a double.
 __device__ __forceinline__ double lane_get(double v, int src) {
   const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
@@ -87,7 +101,7 @@ __device__ d4v diag_factor(d4v g, double* Di, int ldd, int lane, int* fl) {
       *fl |= isfinite(piv) ? MI_BLOCK_SHIFTED : MI_BLOCK_NONFINITE;
       if (!(piv > CHOL_PIV_TOL)) piv = CHOL_PIV_TOL;
     }
-    const double inv = 1.0 / sqrt(piv);
+    const double inv = inv_sqrt(piv);
     const double rkj = gkj * inv;   // R[k][j]
     const double mkj = mkj0 * inv;  // new M[k][j]
 #pragma unroll
@@ -123,6 +137,7 @@ __global__ void __launch_bounds__(1024)
   __shared__ double bufB[16 * LDB];           // new panel: R row K  | M row K
   __shared__ double Dg[16 * LDD];             // R_KK^-1
   __shared__ double dsc[16 * NT];
+  __shared__ double tbuf[16][16 * 17];       // per-wavefront tile transpose for the stores
   __shared__ int flag;
 
   const SmallDesc d = sds[blockIdx.x];
@@ -233,23 +248,35 @@ __global__ void __launch_bounds__(1024)
   }
 
   // Rinv[r][c] = dsc[r] M[c][r] for r <= c < p; zero elsewhere.  Slot (a, b)
-  // holds M(b, a) and writes the two transposed tiles (a, b) and (b, a).
+  // holds M(b, a) and writes the two transposed tiles (a, b) and (b, a); the
+  // first goes through a per-wavefront LDS transpose so that consecutive
+  // lanes store consecutive columns.
   double* Rb = Rinv + d.m_off;
   float* Sb = S32 ? S32 + d.m_off : nullptr;
+  double* tw = tbuf[wave];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     const int a = ta[s], b = tb[s];
     if (a < 0) continue;
+    // tw[x][y] = M(b, a)[y][x]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tw[mi * 17 + mq + 4 * q] = reg[s][q];
+    wave_sync();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int m = mq + 4 * q;
-      // M(b, a)[m][mi] = M[16 b + m][16 a + mi] -> Rinv[16 a + mi][16 b + m]
-      const int r = 16 * a + mi, c = 16 * b + m;
+      const int rr = mq + 4 * q;
+      // M(b, a)[mi][rr] = M[16 b + mi][16 a + rr] -> Rinv[16 a + rr][16 b + mi]
+      const int r = 16 * a + rr, c = 16 * b + mi;
       if (r < ld && c < ld) {
-        const double v = (r <= c && c < p) ? dsc[r] * reg[s][q] : 0.0;
+        const double v = (r <= c && c < p) ? dsc[r] * tw[rr * 17 + mi] : 0.0;
         Rb[int64_t(r) * ld + c] = v;
         if (Sb) Sb[int64_t(r) * ld + c] = (float)v;
       }
+    }
+    wave_sync();  // the reads above before the next slot's writes
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = mq + 4 * q;
       if (a != b) {  // the tile below the diagonal
         const int r2 = 16 * b + m, c2 = 16 * a + mi;
         if (r2 < ld && c2 < ld) {

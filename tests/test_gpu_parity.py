@@ -705,7 +705,10 @@ def test_c5_full_size_frames_and_adjoint(ctx):
     frames = bs.extra["frames"]
     Lp = up.laplacian(ctx, mis.MI_W_INV_SQ_DIST)
     cold = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=8, m0=10, passes0=2)
-    warm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=5, m0=10, passes0=2,
+    # an eigenvector crosses the cut between frames (gap_c down to 12 against
+    # lambda_p near 6,000), so the previous frame's space is up to pi/2 away
+    # and a warm frame needs 7 iterations where a cold one takes 8
+    warm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=7, m0=10, passes0=2,
                         a_mode=mis.MI_A_RITZ)
     sample = [0, 21, 42, 63]
     V = ritz = None

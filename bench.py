@@ -152,6 +152,7 @@ def main():
         "per_block_baseline": None if per_block_ms is None else
         {"value": nverts / (per_block_ms * 1e-3), "unit": "vertices/s", "ms": per_block_ms},
         "roofline": roofline(ktimes, bs, blocks, L, prm),
+        "roofline_spmm": roofline(ktimes, bs, blocks, L, prm, "spmm"),
         "kernels": {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in ktimes.items() if v[1]},
         "launch_shapes": [list(t) for t in ctx.tuning()],
         "build_laplacian_ms": lap_ms,
@@ -174,10 +175,11 @@ TRAFFIC_FILE = os.path.join(HERE, "profiles", "spmm_row_icosphere7_b100_traffic.
 SPMM_SOURCE = os.path.join(HERE, "paper_1810_02719_amd", "csrc", "dense.hip")
 
 
-def measured_traffic():
+def measured_traffic(alg_bytes_per_launch):
     """HBM bytes per launch of the SpMM from the committed rocprofv3 counter
     passes (FETCH_SIZE and WRITE_SIZE, scaled by the same counters of a copy
-    of known size), or None when the kernel source changed since."""
+    of known size), or None when the kernel source changed since or the
+    launches no longer have the size they had then."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
@@ -186,16 +188,21 @@ def measured_traffic():
         return None
     if rec.get("source_sha256") != sha:
         return None
+    ref = rec.get("algorithmic_bytes_per_launch")
+    if not ref or abs(ref - alg_bytes_per_launch) > 0.01 * ref:
+        return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector and MFMA (dense)
 
 
-def roofline(ktimes, bs, blocks, L, prm):
-    """Roofline of the dominant kernel class of the step.  The algorithmic
-    bytes or flops of one step's launches of that class (the method's own
-    traffic, not what the caches make of it) over the event-timed total."""
-    dom = max(ktimes, key=lambda k: ktimes[k][0])
+def roofline(ktimes, bs, blocks, L, prm, dom=None):
+    """Roofline of a kernel class of the step (default: the dominant one, the
+    largest event-timed total).  The algorithmic bytes or flops of one step's
+    launches of that class (the method's own traffic, not what the caches
+    make of it) over the event-timed total."""
+    if dom is None:
+        dom = max(ktimes, key=lambda k: ktimes[k][0])
     ms, launches = ktimes[dom]
     levels = np.asarray(bs.level)
     n = np.asarray(blocks.n, np.int64)
@@ -220,7 +227,7 @@ def roofline(ktimes, bs, blocks, L, prm):
         out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot,
                    bytes_per_launch=tot / max(launches, 1))
         out["achieved"] = tot / (ms * 1e-3) / 1e9
-        out["traffic"] = measured_traffic()
+        out["traffic"] = measured_traffic(tot / max(launches, 1))
     elif dom == "chol":
         # Cholesky (p^3/3) and triangular inverse (p^3/3) of every block's
         # Gram, for each of the step's Cholesky-QRs

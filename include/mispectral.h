@@ -117,9 +117,9 @@ typedef struct {
                         Jacobi sweeps) or MI_EIG_JACOBI (parallel cyclic Jacobi) */
   int32_t autotune;  /* 1: when the plan is made (first call, or after the block
                         table, parameters or buffers change), time candidate launch
-                        shapes of the Gram (split-K), the row product (output width)
-                        and the SpMM (row-per-wavefront or generic) per wave on the
-                        plan's own tables and keep the fastest; 0: fixed heuristics.
+                        shapes of the Gram (split-K) and the row product (output
+                        width) per wave on the plan's own tables and keep the
+                        fastest; 0: fixed heuristics.
                         The results agree to rounding (the Gram split changes the
                         summation order).  mi_oi_tuning reports the choice. */
   double a_value;

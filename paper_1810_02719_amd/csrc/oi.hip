@@ -150,11 +150,21 @@ static int q_of(int p) { return (p + 1) & ~1; }
 
 // Waves: blocks whose predecessor finished in an earlier wave.  Under
 // MI_WARM_GIVEN (or without predecessors) all blocks form one wave.  The
-// per-block reference path makes every block its own wave, in wave order.
+// predecessor forest's trees are independent: the trees are dealt to up to
+// MAX_LANES stream lanes (by root block id), and each lane's waves run in
+// level order on their own stream inside the captured graph, so the
+// latency-bound small solves of one lane overlap the bandwidth-bound
+// products of another.  The per-block reference path makes every block its
+// own wave, in level order, on one lane.
+constexpr int MAX_LANES = 4;
+
 static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool per_block,
-                             std::vector<std::vector<int>>* waves, std::vector<int>* level) {
+                             std::vector<std::vector<int>>* waves, std::vector<int>* level,
+                             std::vector<int>* wave_lane = nullptr, int* n_lanes = nullptr) {
   const int B = hb.B;
   level->assign(B, 0);
+  std::vector<int> root(B);
+  for (int b = 0; b < B; ++b) root[b] = b;
   if (prm.warm == MI_WARM_PRED) {
     for (int b = 0; b < B; ++b) {
       int l = 0, x = b;
@@ -166,21 +176,41 @@ static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool
         }
       }
       (*level)[b] = l;
+      root[b] = x;
     }
+  }
+  // lane of each block: its tree's rank among the roots, modulo MAX_LANES
+  std::vector<int> lane(B, 0);
+  int nl = 1;
+  if (prm.warm == MI_WARM_PRED && !per_block) {
+    std::vector<int> rank(B, -1);
+    int nr = 0;
+    for (int b = 0; b < B; ++b)
+      if (root[b] == b) rank[b] = nr++;
+    for (int b = 0; b < B; ++b) lane[b] = rank[root[b]] % MAX_LANES;
+    nl = std::min(nr, MAX_LANES);
   }
   int maxl = 0;
   for (int b = 0; b < B; ++b) maxl = std::max(maxl, (*level)[b]);
   waves->clear();
-  for (int l = 0; l <= maxl; ++l) {
-    std::vector<int> w;
-    for (int b = 0; b < B; ++b)
-      if ((*level)[b] == l) w.push_back(b);
-    if (w.empty()) continue;
-    if (per_block)
-      for (int b : w) waves->push_back({b});
-    else
-      waves->push_back(w);
-  }
+  if (wave_lane) wave_lane->clear();
+  for (int ln = 0; ln < nl; ++ln)
+    for (int l = 0; l <= maxl; ++l) {
+      std::vector<int> w;
+      for (int b = 0; b < B; ++b)
+        if ((*level)[b] == l && lane[b] == ln) w.push_back(b);
+      if (w.empty()) continue;
+      if (per_block) {
+        for (int b : w) {
+          waves->push_back({b});
+          if (wave_lane) wave_lane->push_back(0);
+        }
+      } else {
+        waves->push_back(w);
+        if (wave_lane) wave_lane->push_back(ln);
+      }
+    }
+  if (n_lanes) *n_lanes = nl;
   return MI_OK;
 }
 
@@ -202,7 +232,8 @@ static int pick_nch(const std::vector<int>& lds_in_wave, bool dbl) {
   return 64;
 }
 
-static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t part_doubles) {
+static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t part_doubles,
+                          int n_lanes) {
   const size_t es = prm.precision == MI_FP64 ? 8 : 4;
   int64_t slab = hb.u_off[hb.B];
   int64_t mats = hb.m_off[hb.B];
@@ -229,7 +260,8 @@ static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t 
   L.log = c.used, c.take<double>(lg);
   L.perm = c.used, c.take<int32_t>(tp);
   L.tri = c.used, c.take<double>(4 * tp);
-  L.part = c.used, c.take<double>(std::max<size_t>(part_doubles, 1));
+  L.part_lane = std::max<size_t>(part_doubles, 1);
+  L.part = c.used, c.take<double>(L.part_lane * std::max(n_lanes, 1));
   L.a_lo = c.used, c.take<double>(hb.B);
   L.b_hi = c.used, c.take<double>(hb.B);
   L.coef_stride = 3 * (mmax + 1);
@@ -327,8 +359,8 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   P->per_block = per_block;
   P->lds_max = lds_max;
   std::vector<std::vector<int>> waves;
-  std::vector<int> level;
-  mi_status st = build_waves(hb, prm, per_block, &waves, &level);
+  std::vector<int> level, wave_lane;
+  mi_status st = build_waves(hb, prm, per_block, &waves, &level, &wave_lane, &P->n_lanes);
   if (st) return st;
   std::vector<int64_t> pk_off(hb.B), log_off(hb.B);
   int64_t pk = 0, lg = 0;
@@ -350,13 +382,14 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
     wt.T = warm_wave ? prm.T : prm.T0;
     wt.m = warm_wave ? prm.m : prm.m0;
     wt.passes = warm_wave ? prm.passes : prm.passes0;
+    wt.lane = wave_lane[w];
     wave_host(hb, nnz_off, waves[w], prm, &wt, &hosts[w], pk_off, log_off,
               tune ? &(*tune)[w] : nullptr);
     part_max = std::max(part_max, hosts[w].gt.size() * 2 * GRAM_TILE * GRAM_TILE);
     part_max = std::max(part_max, hosts[w].gts.size() * 2 * GRAM_TILE * GRAM_TILE);
     if (prm.autotune) part_max = std::max(part_max, tuned_part_max(hosts[w].tall));
   }
-  P->L = ws_layout(hb, prm, part_max);
+  P->L = ws_layout(hb, prm, part_max, P->n_lanes);
   *ws_need = P->L.total;
   // block info + whole-set tables for the per-call kernels
   std::vector<BlkInfo> info(hb.B);
@@ -424,8 +457,8 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
 // Per wave, times the candidate launch shapes of the tall-skinny kernels on
 // the plan's own tables and workspace (operand values do not matter for the
 // timing; every index stays inside the same buffers as in production) and
-// keeps the fastest: the Gram's split-K target, the row product's output
-// width, and the SpMM variant.  Runs on a private stream at plan creation.
+// keeps the fastest: the Gram's split-K target and the row product's output
+// width.  Runs on a private stream at plan creation.
 
 // Milliseconds per call of f: one warm-up, then three timed calls.
 template <typename F>
@@ -464,19 +497,14 @@ struct DevTable {
 };
 
 template <typename T>
-static void autotune_waves(const OiPlan& P, const std::vector<const void*>& ptrs, char* ws,
-                           hipStream_t s, std::vector<WaveTune>* tune) {
+static void autotune_waves(const OiPlan& P, char* ws, hipStream_t s,
+                           std::vector<WaveTune>* tune) {
   const WsLayout& L = P.L;
   T* y0 = reinterpret_cast<T*>(ws + L.slab[0]);
   T* y1 = reinterpret_cast<T*>(ws + L.slab[1]);
-  T* y2 = reinterpret_cast<T*>(ws + L.slab[2]);
   const T* Sm = reinterpret_cast<const T*>(ws + L.G);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* G = reinterpret_cast<double*>(ws + L.H);
-  double* coef = reinterpret_cast<double*>(ws + L.coef);
-  const int32_t* row_ptr = static_cast<const int32_t*>(ptrs[0]);
-  const int32_t* col = static_cast<const int32_t*>(ptrs[1]);
-  const float* val = static_cast<const float*>(ptrs[2]);
   const bool dbl = std::is_same<T, double>::value;
   tune->clear();
   for (const WaveTables& w : P.waves) {
@@ -510,18 +538,10 @@ static void autotune_waves(const OiPlan& P, const std::vector<const void*>& ptrs
       });
       if (t < bt) bt = t, best.nch = nch;
     }
-    const int epl = spmm_epl(w.tall_host);
-    if (epl > 0) {
-      const float t_row = time_calls(s, [&] {
-        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y0, y1, y2, coef,
-                       L.coef_stride, 0, s, epl);
-      });
-      const float t_gen = time_calls(s, [&] {
-        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y0, y1, y2, coef,
-                       L.coef_stride, 0, s, 0);
-      });
-      best.epl = t_row <= t_gen ? epl : 0;
-    }
+    // the SpMM keeps the row-per-wavefront kernel wherever it applies: it is
+    // the faster one on every wave size measured, and a fixed choice keeps
+    // one SpMM kernel per plan
+    best.epl = spmm_epl(w.tall_host);
     tune->push_back(best);
   }
 }
@@ -580,7 +600,19 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                          a.val, b_hi);
   }
 
+  // lanes: fork every lane stream from s, run each lane's waves on its own
+  // stream, join them back into s at the end (graph capture only; eager runs
+  // keep everything on s)
+  const bool fork = a.fork && P.n_lanes > 1 && (int)P.lane_s.size() >= P.n_lanes;
+  if (fork) {
+    (void)hipEventRecord(P.fork_ev, s);
+    for (int l = 0; l < P.n_lanes; ++l) (void)hipStreamWaitEvent(P.lane_s[l], P.fork_ev, 0);
+  }
+  double* part0 = part;
+  const hipStream_t s_main = s;
   for (WaveTables& w : P.waves) {
+    hipStream_t s = fork ? P.lane_s[w.lane] : s_main;
+    double* part = part0 + (fork ? size_t(w.lane) * L.part_lane : 0);
     const size_t lds_jac = size_t(4 * (w.max_q / 2) + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
     const bool jac_lds = lds_jac <= (size_t)P.lds_max;
     const size_t lds_jac_use = jac_lds ? lds_jac : size_t(4 * (w.max_q / 2)) * 8;
@@ -853,6 +885,12 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
       }
   }
+  if (fork) {
+    for (int l = 0; l < P.n_lanes; ++l) {
+      (void)hipEventRecord(P.lane_ev[l], P.lane_s[l]);
+      (void)hipStreamWaitEvent(s, P.lane_ev[l], 0);
+    }
+  }
 }
 
 static bool same_key(const OiPlan& P, const HostBlocks& hb, const std::vector<int64_t>& nnz,
@@ -913,9 +951,9 @@ static mi_status get_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
         MI_TRY_HIP(hipStreamCreateWithFlags(&np->cap_stream, hipStreamNonBlocking));
       std::vector<WaveTune> tune;
       if (prm.precision == MI_FP64)
-        autotune_waves<double>(*np, ptrs, static_cast<char*>(ws), np->cap_stream, &tune);
+        autotune_waves<double>(*np, static_cast<char*>(ws), np->cap_stream, &tune);
       else
-        autotune_waves<float>(*np, ptrs, static_cast<char*>(ws), np->cap_stream, &tune);
+        autotune_waves<float>(*np, static_cast<char*>(ws), np->cap_stream, &tune);
       MI_TRY_HIP(hipGetLastError());
       MI_TRY_HIP(hipStreamSynchronize(np->cap_stream));
       std::unique_ptr<OiPlan> tp;
@@ -939,7 +977,8 @@ mi_status oi_check_params(const mi_oi_params* prm) { return check_params(prm); }
 size_t oi_ws_bytes(const HostBlocks& hb, const mi_oi_params& prm) {
   std::vector<std::vector<int>> waves;
   std::vector<int> level;
-  if (build_waves(hb, prm, false, &waves, &level)) return 0;
+  int n_lanes = 1;
+  if (build_waves(hb, prm, false, &waves, &level, nullptr, &n_lanes)) return 0;
   // the Gram partial buffer is sized for the largest wave
   size_t part_max = 0;
   std::vector<int64_t> pk_off(hb.B, 0), log_off(hb.B, 0), nnz(hb.B + 1, 0);
@@ -951,7 +990,7 @@ size_t oi_ws_bytes(const HostBlocks& hb, const mi_oi_params& prm) {
     part_max = std::max(part_max, h.gts.size() * 2 * GRAM_TILE * GRAM_TILE);
     if (prm.autotune) part_max = std::max(part_max, tuned_part_max(h.tall));
   }
-  return ws_layout(hb, prm, part_max).total;
+  return ws_layout(hb, prm, part_max, n_lanes).total;
 }
 
 mi_status oi_run_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
@@ -963,7 +1002,7 @@ mi_status oi_run_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
   OiPlan* P = nullptr;
   mi_status st = get_plan(ctx, slot, hb, nnz, prm, ptrs, ws, ws_bytes, false, &P);
   if (st) return st;
-  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, rec};
+  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, rec, false};
   if (prm.precision == MI_FP64)
     enqueue<double>(*P, a, s);
   else
@@ -994,7 +1033,8 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
   OiPlan* P = nullptr;
   st = get_plan(ctx, &ctx->oi_plan, hb, nnz, *prm, ptrs, ws, ws_bytes, per_block, &P);
   if (st) return st;
-  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, nullptr};
+  Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, nullptr,
+         false};
   hipStream_t s = (hipStream_t)stream;
   if (per_block || ctx->timer) {
     if (prm->precision == MI_FP64)
@@ -1006,6 +1046,18 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
   }
   if (!P->exec) {
     if (!P->cap_stream) MI_TRY_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    if (P->n_lanes > 1 && P->lane_s.empty()) {
+      MI_TRY_HIP(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+      for (int l = 0; l < P->n_lanes; ++l) {
+        hipStream_t ls = nullptr;
+        hipEvent_t le = nullptr;
+        MI_TRY_HIP(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+        P->lane_s.push_back(ls);
+        MI_TRY_HIP(hipEventCreateWithFlags(&le, hipEventDisableTiming));
+        P->lane_ev.push_back(le);
+      }
+    }
+    a.fork = true;
     MI_TRY_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     if (prm->precision == MI_FP64)
       enqueue<double>(*P, a, P->cap_stream);

@@ -22,6 +22,7 @@ struct WaveTables {
   int nch = 64, nchs = 64;
   int epl = 0;  // elements per lane of the row-per-wavefront SpMM (0: generic kernel)
   int gram_target = GRAM_TARGET;  // workgroups of the split Gram launch
+  int lane = 0;  // stream lane: the waves of one lane form one dependency chain
   std::vector<MatDesc> tall_host;  // host copy of `tall` (for retuning)
   // device tables
   MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
@@ -46,6 +47,7 @@ struct WaveTables {
 struct WsLayout {
   size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, tri, part, a_lo, b_hi, coef,
       conv;
+  size_t part_lane;  // Gram partial doubles of one stream lane
   size_t total;
   int coef_stride;
 };
@@ -76,10 +78,19 @@ struct OiPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
+  // independent trees of the block forest run on separate stream lanes
+  // inside the captured graph
+  int n_lanes = 1;
+  std::vector<hipStream_t> lane_s;
+  std::vector<hipEvent_t> lane_ev;
+  hipEvent_t fork_ev = nullptr;
   ~OiPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (hipStream_t x : lane_s) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : lane_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (arena) (void)hipFree(arena);
   }
 };
@@ -108,6 +119,7 @@ struct Args {
   char* ws;
   KTimer* tm;
   const OiRecord* rec;  // checkpoints to write (eager runs only), or null
+  bool fork;            // run the plan's lanes on its lane streams (graph capture)
 };
 
 // Runs the tracking eagerly on `s` with the plan held in *slot (created or

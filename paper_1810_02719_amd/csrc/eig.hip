@@ -30,20 +30,10 @@ constexpr double TRI_TN_MIN = 1e-290; // floor of the matrix scale
 constexpr double TRI_CLUSTER = 1e-8;  // relative gap below which vectors are
                                       // orthogonalised against each other
 
-// Select w[a][b] with a runtime column index kb (registers cannot be indexed).
-template <int RT>
-__device__ __forceinline__ double col_of(const double (&row)[RT], int kb) {
-  double v = 0.0;
-#pragma unroll
-  for (int b = 0; b < RT; ++b)
-    if (b == kb) v = row[b];
-  return v;
-}
-
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -65,10 +55,36 @@ __device__ __forceinline__ double half_sum(double v) {
   return v + swz_xor16(v);
 }
 
+// Sum over the 16 lanes of a DPP row, in every lane of the row.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_d<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);        // row_half_mirror
+  return v + dpp_d<0x140>(v);  // row_mirror
+}
+
 // Sum of 32 doubles in LDS, in every lane of the wavefront: one LDS read per
 // lane (lane l reads x[l % 32]) and a half-wavefront DPP reduction.
 __device__ __forceinline__ double sum32(const double* x) {
   return half_sum(x[threadIdx.x & 31]);
+}
+
+// A value that every lane holds identically, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Square root of a normal positive x: hardware reciprocal square root, one
+// Goldschmidt step for sqrt(x) and 1/(2 sqrt(x)), one Newton correction.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  return fma(fma(-g, g, x), h, g);
 }
 
 // 1 / b by the hardware reciprocal and one Newton step (b nonzero and
@@ -138,22 +154,126 @@ __device__ __forceinline__ double hash_unit(int i, int j) {
 }  // namespace
 
 // ------------------------------------------------------------------ 1. reduction
-// Thread (tr, tc) = (tid / 32, tid % 32) holds A[tr + 32a][tc + 32b] in
-// registers (both triangles).  Step k: the owners of column k publish it and
+// TRI_THREADS threads per block.  Thread (tr, tc) = (tid / 16, tid % 16) holds
+// A[tr + 32a][tc + 16b] (a < RT, b < 2 RT) in registers, both triangles.
+// Step k: the owners of column k publish it below the diagonal (LDS) with
 // partial squared norms; everyone forms the reflector H_k = I - beta v v^T
-// (v zero up to k, alpha = -sign(x_{k+1}) ||x||), computes p = beta A v with
-// half-wavefront reductions, then A -= v w^T + w v^T with
-// w = p - (beta/2)(v^T p) v.  v and w are zero at and above k, so finished
-// rows and columns keep their values and never feed the trailing matrix;
-// whole finished 32-blocks are skipped, and the finished column k holds v_k
-// until the end.  Two barriers per step; the LDS vectors are double-buffered
-// by step parity; d, e and beta collect in LDS and everything goes to global
-// memory once, after the loop.
+// (v zero up to k, v_{k+1} = x_{k+1} - alpha, alpha = -sign(x_{k+1}) ||x||),
+// computes p = beta A v with sums inside 16-lane DPP rows, and applies
+// A -= v w^T + w v^T with w = p - (beta/2)(v^T p) v.  v and w vanish at and
+// above k, so finished rows and columns keep their values.  The step loop is
+// split by the number KB of finished 16-column blocks, so each loop skips them
+// (and the finished 32-row blocks) at compile time.  Two barriers per step;
+// the LDS vectors are double-buffered by step parity; v_k is stored as row k
+// of Hv as soon as it is known.
+constexpr int TRI_THREADS = 512;
+
 template <int RT>
-__global__ void __launch_bounds__(1024)
+__device__ __forceinline__ void tri_publish(const double (&w)[RT][2 * RT], double (*xcol)[32 * RT],
+                                            double (*part)[32], double* sdd, int k, int tr,
+                                            int tc) {
+  const int par = k & 1, kb = k >> 4, kt = k & 15;
+  if (tc == kt) {
+    double ss = 0.0;
+#pragma unroll
+    for (int b = 0; b < 2 * RT; ++b)
+      if (b == kb) {  // uniform: selects the register column
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          const int i = tr + 32 * a;
+          const double x = w[a][b];
+          if (i == k) sdd[k] = x;
+          const double xi = i <= k ? 0.0 : x;
+          xcol[par][i] = xi;
+          ss = fma(xi, xi, ss);
+        }
+      }
+    part[par][tr] = ss;
+  }
+  __syncthreads();
+}
+
+// Step k after column k is published; KB = (k + 1) / 16 finished column
+// blocks, KB / 2 finished row blocks.
+template <int RT, int KB>
+__device__ __forceinline__ void tri_step(double (&w)[RT][2 * RT], double (*xcol)[32 * RT],
+                                         double (*pcol)[32 * RT], double (*part)[32],
+                                         double (*vpart)[32], double* see, double* sbb,
+                                         double* Hb, int k, int ld, int tr, int tc) {
+  constexpr int CB = 2 * RT, KA = KB / 2;
+  const int par = k & 1, k1 = k + 1;
+  const double ss = sum32(part[par]);
+  const double x1 = xcol[par][k1];
+  double vc[CB], vr[RT];
+#pragma unroll
+  for (int b = KB; b < CB; ++b) vc[b] = xcol[par][tc + 16 * b];
+#pragma unroll
+  for (int a = KA; a < RT; ++a) vr[a] = xcol[par][tr + 32 * a];
+  double al, be;
+  if (ss <= DBL_MIN) {
+    al = x1;
+    be = 0.0;
+  } else {
+    al = -copysign(sqrt_pos(ss), x1);
+    be = recip(al * (al - x1));
+  }
+  al = uniform(al);
+  be = uniform(be);
+  // element k+1 of v lies in column block KB and row block KA
+  vc[KB] -= tc == (k1 & 15) ? al : 0.0;
+  vr[KA] -= tr == (k1 & 31) ? al : 0.0;
+  double vp = 0.0;
+#pragma unroll
+  for (int a = KA; a < RT; ++a) {
+    double sa = 0.0;
+#pragma unroll
+    for (int b = KB; b < CB; ++b) sa = fma(w[a][b], vc[b], sa);
+    const double pa = be * row_sum16(sa);
+    vp = fma(vr[a], pa, vp);
+    const int i = tr + 32 * a;
+    if (tc == 0) pcol[par][i] = i <= k ? 0.0 : pa;
+  }
+  if (tc == 0) vpart[par][tr] = vp;
+  if (threadIdx.x == 0) {
+    see[k] = al;
+    sbb[k] = be;
+  }
+  if ((int)threadIdx.x < ld)
+    Hb[int64_t(k) * ld + threadIdx.x] = xcol[par][threadIdx.x] - ((int)threadIdx.x == k1 ? al : 0.0);
+  __syncthreads();
+  const double K = uniform(0.5 * be * sum32(vpart[par]));
+  double wc[CB];
+#pragma unroll
+  for (int b = KB; b < CB; ++b) wc[b] = fma(-K, vc[b], pcol[par][tc + 16 * b]);
+#pragma unroll
+  for (int a = KA; a < RT; ++a) {
+    const double wa = fma(-K, vr[a], pcol[par][tr + 32 * a]);
+#pragma unroll
+    for (int b = KB; b < CB; ++b) w[a][b] = fma(-vr[a], wc[b], fma(-wa, vc[b], w[a][b]));
+  }
+}
+
+// Steps k with (k + 1) / 16 == KB, then the next column block.
+template <int RT, int KB>
+__device__ __forceinline__ void tri_steps(double (&w)[RT][2 * RT], double (*xcol)[32 * RT],
+                                          double (*pcol)[32 * RT], double (*part)[32],
+                                          double (*vpart)[32], double* sdd, double* see,
+                                          double* sbb, double* Hb, int p, int ld, int tr, int tc) {
+  if constexpr (KB < 2 * RT) {
+    const int k_end = min(16 * KB + 15, p - 2);
+    for (int k = max(16 * KB - 1, 0); k < k_end; ++k) {
+      tri_publish<RT>(w, xcol, part, sdd, k, tr, tc);
+      tri_step<RT, KB>(w, xcol, pcol, part, vpart, see, sbb, Hb, k, ld, tr, tc);
+    }
+    tri_steps<RT, KB + 1>(w, xcol, pcol, part, vpart, sdd, see, sbb, Hb, p, ld, tr, tc);
+  }
+}
+
+template <int RT>
+__global__ void __launch_bounds__(TRI_THREADS)
     k_tri_reduce(const SmallDesc* __restrict__ sds, const double* __restrict__ A,
                  double* __restrict__ Hv, double* __restrict__ tri, int32_t* __restrict__ status) {
-  constexpr int LDM = 32 * RT;
+  constexpr int LDM = 32 * RT, CB = 2 * RT;
   __shared__ double xcol[2][LDM];
   __shared__ double pcol[2][LDM];
   __shared__ double part[2][32];
@@ -162,113 +282,31 @@ __global__ void __launch_bounds__(1024)
   __shared__ int flag;
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
-  const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   const double* Ab = A + d.m_off;
+  double* Hb = Hv + d.m_off;
   if (tid == 0) flag = 0;
   __syncthreads();
-  double w[RT][RT];
+  double w[RT][CB];
   bool bad = false;
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
+    for (int b = 0; b < CB; ++b) {
+      const int i = tr + 32 * a, j = tc + 16 * b;
       const double v = (i < p && j < p) ? Ab[int64_t(i) * ld + j] : 0.0;
       bad = bad || !isfinite(v);
       w[a][b] = v;
     }
   if (bad) atomicOr(&flag, MI_BLOCK_NONFINITE);
   __syncthreads();
-  for (int k = 0; k + 2 < p; ++k) {
-    const int par = k & 1, kb = k >> 5, kt = k & 31;
-    // A: publish column k (the diagonal entry goes to d_k, not into v)
-    if (tc == kt) {
-      double x[RT];
-#pragma unroll
-      for (int b = 0; b < RT; ++b)
-        if (b == kb) {  // uniform: selects the register column
-#pragma unroll
-          for (int a = 0; a < RT; ++a) x[a] = w[a][b];
-        }
-      double ss = 0.0;
-#pragma unroll
-      for (int a = 0; a < RT; ++a) {
-        const int i = tr + 32 * a;
-        if (i == k) sdd[k] = x[a];
-        const double xi = i <= k ? 0.0 : x[a];
-        xcol[par][i] = xi;
-        ss = fma(xi, xi, ss);
-      }
-      part[par][tr] = ss;
-    }
-    __syncthreads();
-    // B: reflector and p = beta A v
-    const double ss = sum32(part[par]);
-    const double x1 = xcol[par][k + 1];
-    double al, be;
-    if (ss <= DBL_MIN) {
-      al = x1;
-      be = 0.0;
-    } else {
-      al = -copysign(sqrt(ss), x1);
-      be = 1.0 / (al * (al - x1));
-    }
-    // v_i = x_i except v_{k+1} = x_{k+1} - alpha (read again from LDS where
-    // needed: keeps the register tile within the 128-VGPR budget)
-    auto vat = [&](int i) { return xcol[par][i] - (i == k + 1 ? al : 0.0); };
-    // blocks of 32 rows / columns that lie entirely at or left of k are done:
-    // skipped with uniform branches
-    const int ka = (k + 1) >> 5;
-    double vc[RT];
-#pragma unroll
-    for (int b = 0; b < RT; ++b) vc[b] = b < ka ? 0.0 : vat(tc + 32 * b);
-    double vp = 0.0;
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      if (a < ka) continue;
-      double sa = 0.0;
-#pragma unroll
-      for (int b = 0; b < RT; ++b)
-        if (b >= ka) sa = fma(w[a][b], vc[b], sa);
-      const double pa = be * half_sum(sa);
-      vp = fma(vat(tr + 32 * a), pa, vp);
-      if (tc == 0) pcol[par][tr + 32 * a] = pa;
-    }
-    if (tc == 0) vpart[par][tr] = vp;
-    if (tid == 0) {
-      see[k] = al;
-      sbb[k] = be;
-    }
-    __syncthreads();
-    // C: rank-2 update of the trailing matrix; the finished column k then
-    // stores the reflector v_k below the diagonal (never read by the update)
-    const double K = 0.5 * be * sum32(vpart[par]);
-    double wc[RT];
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int j = tc + 32 * b;
-      wc[b] = (b < ka || j <= k) ? 0.0 : pcol[par][j] - K * vc[b];
-    }
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      if (a < ka) continue;
-      const int i = tr + 32 * a;
-      const double va = vat(i);
-      const double wa = i <= k ? 0.0 : pcol[par][i] - K * va;
-#pragma unroll
-      for (int b = 0; b < RT; ++b)
-        if (b >= ka) w[a][b] -= va * wc[b] + wa * vc[b];
-#pragma unroll
-      for (int b = 0; b < RT; ++b)
-        if (b == kb) w[a][b] = (tc == kt && i > k) ? va : w[a][b];
-    }
-  }
+  tri_steps<RT, 0>(w, xcol, pcol, part, vpart, sdd, see, sbb, Hb, p, ld, tr, tc);
   // the last 2 x 2 (or 1 x 1) block is already tridiagonal
 #pragma unroll
   for (int a = 0; a < RT; ++a)
 #pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, j = tc + 32 * b;
+    for (int b = 0; b < CB; ++b) {
+      const int i = tr + 32 * a, j = tc + 16 * b;
       if (p >= 2 && i == p - 2 && j == p - 2) sdd[p - 2] = w[a][b];
       if (i == p - 1 && j == p - 1) sdd[p - 1] = w[a][b];
       if (p >= 2 && i == p - 1 && j == p - 2) see[p - 2] = w[a][b];
@@ -278,19 +316,9 @@ __global__ void __launch_bounds__(1024)
     if (p >= 2) sbb[p - 2] = 0.0;
     sbb[p - 1] = 0.0;
   }
-  // reflectors: row c of Hv = v_c (zero at and left of c), from the finished
-  // columns of the register tile
-  double* Hb = Hv + d.m_off;
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = tr + 32 * a, c = tc + 32 * b;
-      if (c + 2 < p && i < ld) Hb[int64_t(c) * ld + i] = (i > c && i < p) ? w[a][b] : 0.0;
-    }
   __syncthreads();
   double* dd = tri + 4 * d.t_off;
-  for (int i = tid; i < p; i += 1024) {
+  for (int i = tid; i < p; i += TRI_THREADS) {
     dd[i] = sdd[i];
     dd[p + i] = see[i];
     dd[3 * p + i] = sbb[i];
@@ -603,7 +631,7 @@ bool tri_eig_supported(int max_ld) { return max_ld <= TRI_MAX_LD; }
 
 #define MI_TRI_CASE(R)                                                                           \
   case R:                                                                                        \
-    hipLaunchKernelGGL(k_tri_reduce<R>, dim3(nb), dim3(1024), 0, s, sd, A, Hv, tri, status);     \
+    hipLaunchKernelGGL(k_tri_reduce<R>, dim3(nb), dim3(TRI_THREADS), 0, s, sd, A, Hv, tri, status); \
     break;
 
 #define MI_TRI_BACK_CASE(R)                                                                      \

@@ -22,9 +22,7 @@ namespace mis {
 
 namespace {
 
-constexpr int TRI_BISECT_POINTS = 3;  // Sturm counts per lane and round
-constexpr int TRI_GROUP = 4;          // lanes per eigenvalue
-constexpr int TRI_MAXIT = 24;         // multisection rounds (52 bits need 14)
+constexpr int TRI_MAXIT = 24;         // multisection rounds (52 bits need at most 17)
 constexpr int TRI_VC = 16;            // reflectors staged per LDS chunk
 constexpr double TRI_TN_MIN = 1e-290; // floor of the matrix scale
 constexpr double TRI_CLUSTER = 1e-8;  // relative gap below which vectors are
@@ -330,9 +328,12 @@ __global__ void __launch_bounds__(TRI_THREADS)
 // Count of eigenvalues of T below x = number of negative pivots of the
 // LDL^T factorisation of T - x I (Sylvester's law of inertia); pivots
 // smaller than pivmin are replaced by -pivmin.  Each eigenvalue j is owned
-// by a group of TRI_GROUP lanes that evaluate TRI_GROUP * TRI_BISECT_POINTS
-// equispaced points of its bracket [a, b] (count(a) <= j < count(b)) per
-// round, interleaved for instruction-level parallelism.
+// by a group of G lanes that evaluate G equispaced points of its bracket
+// [a, b] (count(a) <= j < count(b)) per round, one Sturm count per lane: a
+// count is a chain of p dependent divisions, so one chain per lane keeps
+// each round at the chain's latency, and more lanes per eigenvalue cut the
+// number of rounds.
+template <int G>
 __global__ void __launch_bounds__(64)
     k_tri_bisect(const SmallDesc* __restrict__ sds, double* __restrict__ tri,
                  double* __restrict__ ritz, int32_t* __restrict__ perm, double* __restrict__ a_lo,
@@ -341,7 +342,7 @@ __global__ void __launch_bounds__(64)
   __shared__ double red[3];
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p;
-  const int j0 = blockIdx.y * (64 / TRI_GROUP);
+  const int j0 = blockIdx.y * (64 / G);
   if (j0 >= p) return;
   double* sd_ = smem;
   double* se2 = smem + p;
@@ -354,43 +355,29 @@ __global__ void __launch_bounds__(64)
   }
   const TriScale sc = tri_scale(dd, ee, p, red);  // has a barrier
   const double atol = 4.0 * DBL_EPSILON * sc.tn + 2.0 * sc.pivmin;
-  const int g = threadIdx.x / TRI_GROUP, r = threadIdx.x % TRI_GROUP;
+  const int g = threadIdx.x / G, r = threadIdx.x % G;
   const int j = j0 + g;
   const bool live = j < p;
   double a = sc.lo, b = sc.hi;
-  constexpr int NP = TRI_GROUP * TRI_BISECT_POINTS;
   for (int it = 0; it < TRI_MAXIT; ++it) {
     const bool todo = live && (b - a > atol);
     if (!__any(todo)) break;
     double na = a, nb = b;
     if (todo) {
-      const double h = (b - a) * (1.0 / (NP + 1));
-      double x[TRI_BISECT_POINTS], t[TRI_BISECT_POINTS];
-      int c[TRI_BISECT_POINTS];
-#pragma unroll
-      for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
-        x[m] = a + h * double(r * TRI_BISECT_POINTS + m + 1);
-        t[m] = guard(sd_[0] - x[m], sc.pivmin);
-        c[m] = t[m] < 0.0;
-      }
+      const double x = a + (b - a) * (double(r + 1) * (1.0 / (G + 1)));
+      double t = guard(sd_[0] - x, sc.pivmin);
+      int c = t < 0.0;
       for (int i = 1; i < p; ++i) {
-        const double di = sd_[i], e2 = se2[i - 1];
-#pragma unroll
-        for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
-          // e2 / t by the hardware reciprocal and one Newton step: a count
-          // only needs the pivot's sign, which a few ulps cannot flip
-          // except within rounding distance of an eigenvalue
-          t[m] = guard((di - x[m]) - e2 * recip(t[m]), sc.pivmin);
-          c[m] += t[m] < 0.0;
-        }
+        // e2 / t by the hardware reciprocal and one Newton step: a count
+        // only needs the pivot's sign, which a few ulps cannot flip except
+        // within rounding distance of an eigenvalue
+        t = guard((sd_[i] - x) - se2[i - 1] * recip(t), sc.pivmin);
+        c += t < 0.0;
       }
-#pragma unroll
-      for (int m = 0; m < TRI_BISECT_POINTS; ++m) {
-        if (c[m] <= j) na = fmax(na, x[m]);
-        else nb = fmin(nb, x[m]);
-      }
+      if (c <= j) na = x;
+      else nb = x;
     }
-    for (int o = 1; o < TRI_GROUP; o <<= 1) {
+    for (int o = 1; o < G; o <<= 1) {
       na = fmax(na, __shfl_xor(na, o, 64));
       nb = fmin(nb, __shfl_xor(nb, o, 64));
     }
@@ -656,9 +643,15 @@ void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, const double* A,
 void launch_tri_bisect(const SmallDesc* sd, int nb, int max_p, double* tri, double* ritz,
                        int32_t* perm, double* a_lo, int adapt, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
-  const int gy = ceil_div(max_p, 64 / TRI_GROUP);
-  hipLaunchKernelGGL(k_tri_bisect, dim3(nb, gy), dim3(64), size_t(2 * max_p) * sizeof(double), s,
-                     sd, tri, ritz, perm, a_lo, adapt, status);
+  // 16 lanes per eigenvalue while the launch leaves most CUs idle, 8 once it
+  // holds more blocks (more rounds, but half the waves)
+  const size_t shm = size_t(2 * max_p) * sizeof(double);
+  if (nb <= 16)
+    hipLaunchKernelGGL(k_tri_bisect<16>, dim3(nb, ceil_div(max_p, 4)), dim3(64), shm, s, sd, tri,
+                       ritz, perm, a_lo, adapt, status);
+  else
+    hipLaunchKernelGGL(k_tri_bisect<8>, dim3(nb, ceil_div(max_p, 8)), dim3(64), shm, s, sd, tri,
+                       ritz, perm, a_lo, adapt, status);
 }
 
 void launch_tri_vectors(const SmallDesc* sd, int nb, int max_p, const double* tri, double* DP,

@@ -521,18 +521,21 @@ __global__ void __launch_bounds__(TRI_VEC_THREADS)
       kmin = i;
     }
   }
+  // the two one-sided recurrences from z_k = 1; z_i replaces the pivot it
+  // consumed (ldp[i] for i < k, ldm[i] read and ldp[i] written for i > k),
+  // so the vector stays in LDS until it is scaled on the way out
   double nrm = 1.0;
-  Zt[int64_t(kmin) * ld + j] = 1.0;
+  ldp[kmin * NT + tx] = 1.0;
   double z = 1.0;
   for (int i = kmin - 1; i >= 0; --i) {
-    z = -se[i] * z * recip(ldp[i * NT + tx]);
-    Zt[int64_t(i) * ld + j] = z;
+    z *= -se[i] * recip(ldp[i * NT + tx]);
+    ldp[i * NT + tx] = z;
     nrm = fma(z, z, nrm);
   }
   z = 1.0;
   for (int i = kmin + 1; i < p; ++i) {
-    z = -se[i - 1] * z * recip(ldm[i * NT + tx]);
-    Zt[int64_t(i) * ld + j] = z;
+    z *= -se[i - 1] * recip(ldm[i * NT + tx]);
+    ldp[i * NT + tx] = z;
     nrm = fma(z, z, nrm);
   }
   if (!isfinite(nrm)) {  // overflow in the recurrences: fall back to inverse iteration
@@ -540,77 +543,105 @@ __global__ void __launch_bounds__(TRI_VEC_THREADS)
     return;
   }
   const double inv = 1.0 / sqrt(nrm);
-  for (int i = 0; i < p; ++i) Zt[int64_t(i) * ld + j] *= inv;
+  for (int i = 0; i < p; ++i) Zt[int64_t(i) * ld + j] = ldp[i * NT + tx] * inv;
   (void)status;
 }
 
 // ------------------------------------------------------------------ 4. back-transformation
 // Z^T = Z_T^T H_{p-3} ... H_0: every row of Z_T^T (an eigenvector of T) is
-// updated independently, row . v reduced over a half-wavefront, so a block
-// splits into ld / 32 workgroups of 32 rows.  The reflectors are staged
-// through LDS TRI_VC at a time.  Output Z[i][j] = component i of the j-th
-// eigenvector (ascending), zero outside p x p.
+// updated independently, so a block splits into ld / 32 workgroups of 32
+// rows.  A row is held by 8 lanes, lane q holding components 16b + 2q and
+// 16b + 2q + 1: its dot product with a reflector is reduced in three DPP
+// steps, and the reflector is read from LDS as 128-bit pairs.  The
+// reflectors stream through LDS TRI_VC at a time; the next chunk is loaded
+// into registers while the current one is applied.  Output Z[i][j] =
+// component i of the j-th eigenvector (ascending), zero outside p x p.
+constexpr int TRI_BACK_THREADS = 256;
+
+// Sum over the 8 lanes of each aligned lane octet, in every lane.
+__device__ __forceinline__ double oct_sum(double v) {
+  v += dpp_d<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);         // quad_perm [2,3,0,1]
+  return v + dpp_d<0x141>(v);  // row_half_mirror: lane l <-> 7 - l of each octet
+}
+
 template <int RT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(TRI_BACK_THREADS)
     k_tri_back(const SmallDesc* __restrict__ sds, const double* __restrict__ ZT,
                const double* __restrict__ Hv, const double* __restrict__ tri,
                double* __restrict__ Z) {
-  constexpr int LDM = 32 * RT;
-  __shared__ double vb[TRI_VC][LDM];
+  constexpr int LDM = 32 * RT, NB = 2 * RT;
+  constexpr int PF = TRI_VC * LDM / TRI_BACK_THREADS;  // chunk values per thread
+  static_assert(PF * TRI_BACK_THREADS == TRI_VC * LDM, "chunk must split evenly");
+  __shared__ __align__(16) double vb[TRI_VC * LDM];
   __shared__ double bt[TRI_VC];
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
   if (int(blockIdx.y) * 32 >= ld) return;
-  const int h = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int tid = threadIdx.x, g = tid >> 3, q = tid & 7;
+  const int j = blockIdx.y * 32 + g;
   const double* Zt = ZT + d.m_off;
   const double* Hb = Hv + d.m_off;
   const double* bb = tri + 4 * d.t_off + 3 * p;
-  double w[4][RT];
+  double w[NB][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int j = blockIdx.y * 32 + h + 8 * r;
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = l + 32 * b;
-      w[r][b] = (i < p && j < p) ? Zt[int64_t(i) * ld + j] : 0.0;
+    for (int s = 0; s < 2; ++s) {
+      const int i = 16 * b + 2 * q + s;
+      w[b][s] = (i < p && j < p) ? Zt[int64_t(i) * ld + j] : 0.0;
     }
-  }
+  // reflectors kl .. k0 of one chunk, element e = kk * LDM + i
+  double pf[PF], pfb = 0.0;
+  auto fetch = [&](int k0) {
+    const int kl = max(0, k0 - TRI_VC + 1), cnt = k0 - kl + 1;
+#pragma unroll
+    for (int m = 0; m < PF; ++m) {
+      const int e = tid + TRI_BACK_THREADS * m, kk = e / LDM, i = e % LDM;
+      pf[m] = (kk < cnt && i < p) ? Hb[int64_t(kl + kk) * ld + i] : 0.0;
+    }
+    pfb = tid < cnt ? bb[kl + tid] : 0.0;
+  };
+  if (p >= 3) fetch(p - 3);
   for (int k0 = p - 3; k0 >= 0; k0 -= TRI_VC) {
-    const int kl = max(0, k0 - TRI_VC + 1);
-    const int cnt = k0 - kl + 1;
+    const int cnt = k0 - max(0, k0 - TRI_VC + 1) + 1;
+    __syncthreads();  // the previous chunk is consumed
+#pragma unroll
+    for (int m = 0; m < PF; ++m) vb[tid + TRI_BACK_THREADS * m] = pf[m];
+    if (tid < TRI_VC) bt[tid] = pfb;
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt * LDM; e += 256) {
-      const int kk = e / LDM, i = e % LDM;
-      vb[kk][i] = (i < p) ? Hb[int64_t(kl + kk) * ld + i] : 0.0;
-    }
-    if (threadIdx.x < cnt) bt[threadIdx.x] = bb[kl + threadIdx.x];
-    __syncthreads();
+    if (k0 >= TRI_VC) fetch(k0 - TRI_VC);
     for (int kk = cnt - 1; kk >= 0; --kk) {
       const double be = bt[kk];
-      double v[RT];
+      double v[NB][2];
 #pragma unroll
-      for (int b = 0; b < RT; ++b) v[b] = vb[kk][l + 32 * b];
+      for (int b = 0; b < NB; ++b) {
+        const double2 t = *reinterpret_cast<const double2*>(&vb[kk * LDM + 16 * b + 2 * q]);
+        v[b][0] = t.x;
+        v[b][1] = t.y;
+      }
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double s = 0.0;
+      for (int b = 0; b < NB; ++b) {
+        s0 = fma(w[b][0], v[b][0], s0);
+        s1 = fma(w[b][1], v[b][1], s1);
+      }
+      const double sc = be * oct_sum(s0 + s1);
 #pragma unroll
-        for (int b = 0; b < RT; ++b) s = fma(w[r][b], v[b], s);
-        s = be * half_sum(s);
-#pragma unroll
-        for (int b = 0; b < RT; ++b) w[r][b] -= s * v[b];
+      for (int b = 0; b < NB; ++b) {
+        w[b][0] = fma(-sc, v[b][0], w[b][0]);
+        w[b][1] = fma(-sc, v[b][1], w[b][1]);
       }
     }
   }
   double* Zb = Z + d.m_off;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int j = blockIdx.y * 32 + h + 8 * r;
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int b = 0; b < RT; ++b) {
-      const int i = l + 32 * b;
-      if (i < ld && j < ld) Zb[int64_t(i) * ld + j] = (i < p && j < p) ? w[r][b] : 0.0;
+    for (int s = 0; s < 2; ++s) {
+      const int i = 16 * b + 2 * q + s;
+      if (i < ld && j < ld) Zb[int64_t(i) * ld + j] = (i < p && j < p) ? w[b][s] : 0.0;
     }
-  }
 }
 
 // ------------------------------------------------------------------ launch
@@ -623,7 +654,7 @@ bool tri_eig_supported(int max_ld) { return max_ld <= TRI_MAX_LD; }
 
 #define MI_TRI_BACK_CASE(R)                                                                      \
   case R:                                                                                        \
-    hipLaunchKernelGGL(k_tri_back<R>, dim3(nb, max_ld / 32), dim3(256), 0, s, sd, ZT, Hv, tri, Z); \
+    hipLaunchKernelGGL(k_tri_back<R>, dim3(nb, max_ld / 32), dim3(TRI_BACK_THREADS), 0, s, sd, ZT, Hv, tri, Z); \
     break;
 
 void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, const double* A, double* Hv,

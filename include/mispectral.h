@@ -168,12 +168,14 @@ enum {
   MI_K_EIG_VALUES,     /* its eigenvalues by Sturm multisection */
   MI_K_EIG_VECTORS,    /* eigenvectors of the tridiagonal matrix */
   MI_K_EIG_BACK,       /* back-transformation by the reflectors */
+  MI_K_MERGE,          /* degree-weighted merge of overlapped submeshes */
   MI_K_COUNT
 };
 /* Name of a kernel class ("spmm", ...), NULL when out of range. */
 const char* mi_kernel_class_name(int32_t k);
 /* Per-kernel timing, for measurement.  With on != 0 the context's later
- * mi_oi_track, mi_project and mi_reconstruct calls launch eagerly (no graph
+ * mi_oi_track, mi_project, mi_reconstruct and mi_merge_overlapped calls
+ * launch eagerly (no graph
  * replay) and bracket every kernel launch with a pair of HIP events on the
  * caller's stream; totals restart from zero.  on = 0 stops timing and frees
  * the events.  Synchronous. */
@@ -352,6 +354,33 @@ mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const
                      void* stream);
 mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const int32_t* c,
                          const void* U, const void* E, void* Xr, void* stream);
+
+/* ---------------------------------------------------------------- merge of overlapped submeshes
+ * Section 6.1, Alg. 3: the submeshes overlap (each part extended with the
+ * neighbours of its boundary vertices to n_d vertices), so a mesh vertex can
+ * have several reconstructions.  Its merged position is their average, each
+ * weighted by the vertex's degree in that submesh: the number of its
+ * neighbours there, i.e. the entries of its Laplacian row minus the
+ * diagonal.  Sums run in FP64 over the submeshes in ascending block order,
+ * so the result is bitwise reproducible.  A vertex whose weights are all
+ * zero (isolated in every submesh that holds it) gets the plain mean of its
+ * reconstructions; a vertex in no submesh gets 0.
+ * gid        host int32 [v_off[B]]: the mesh vertex of every block row (row i
+ *            of block b at v_off[b] + i), in [0, n_vertices).
+ * n_vertices mesh vertex count, < 2^31.
+ * row_ptr    device int32: the blocks' Laplacian row pointers as
+ *            mi_build_laplacian writes them (n_b + 1 entries per block, block
+ *            b starting at v_off[b] + b).
+ * Xr         device float [v_off[B]][3]: reconstructed block coordinates
+ *            (the output of mi_reconstruct).
+ * Xout       device float [n_vertices][3]: merged mesh coordinates.
+ * The occurrence table is built on the host from gid on the first call for
+ * a given (v_off, gid, n_vertices) and cached in the context (synchronous
+ * upload); later calls only enqueue the kernel.  MI_ERR_INDEX when a gid
+ * entry is out of range. */
+mi_status mi_merge_overlapped(mi_ctx* ctx, const mi_blocks* blk, const int32_t* gid,
+                              int64_t n_vertices, const int32_t* row_ptr, const float* Xr,
+                              float* Xout, void* stream);
 
 /* ---------------------------------------------------------------- choice of c
  * Section 5 (smallest subspace meeting a reconstruction-quality target) with

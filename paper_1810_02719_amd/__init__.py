@@ -344,6 +344,19 @@ def reconstruct(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, 
     return Xr
 
 
+def merge_overlapped(ctx: Context, blocks: Blocks, gid, n_vertices: int, lap: Laplacian,
+                     Xr: torch.Tensor, Xout: torch.Tensor | None = None) -> torch.Tensor:
+    """Degree-weighted merge of the reconstructions of overlapped submeshes
+    (mi_merge_overlapped).  gid: host int32 [v_off[B]], the mesh vertex of
+    every block row; Xr: FP32 [v_off[B] * 3]; returns FP32 [n_vertices * 3]."""
+    gid = np.ascontiguousarray(np.asarray(gid, dtype=np.int32))
+    if Xout is None:
+        Xout = torch.empty(int(n_vertices) * 3, dtype=torch.float32, device=Xr.device)
+    L.check(L.lib().mi_merge_overlapped(ctx.h, blocks.ref, _np_ptr(gid, C.c_int32), int(n_vertices),
+                                        _dptr(lap.row_ptr), _dptr(Xr), _dptr(Xout), _stream()))
+    return Xout
+
+
 def choose_c(ctx: Context, blocks: Blocks, c_max: torch.Tensor, target: float, g_min: float,
              U: torch.Tensor, ritz: torch.Tensor, X: torch.Tensor, gl: Laplacian):
     """Per-block c for an NMSVE target (gl: the MI_W_INV_DIST Laplacian of the

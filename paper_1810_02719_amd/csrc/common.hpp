@@ -161,5 +161,6 @@ struct mi_ctx {
   void* res_plan = nullptr;  // residual tile tables (see resid.hip)
   void* adj_oi = nullptr;    // tracking plan of the recorded forward (adjoint.hip)
   void* adj_plan = nullptr;  // adjoint tables (adjoint.hip)
+  void* merge_plan = nullptr;  // occurrence table of overlapped submeshes (merge.hip)
   mis::KTimer* timer = nullptr;  // non-null while timing is on
 };

@@ -345,6 +345,49 @@ def split_blocks(n: int, faces: np.ndarray, label: np.ndarray, seeds: np.ndarray
     return blocks
 
 
+def overlap_extend(indptr, indices, label: np.ndarray, n_parts: int, n_d: int):
+    """Equal-size overlapped submeshes (Section 6.1): every part is extended
+    with the neighbours of its boundary vertices in adjacent parts, ring
+    after ring, until it holds n_d vertices; from the ring that would
+    overshoot, the lowest global ids are taken.  A part whose connected
+    surroundings hold fewer than n_d vertices keeps all of them.  Returns the
+    sorted global vertex ids of every extended part."""
+    n = indptr.size - 1
+    out = []
+    for b in range(n_parts):
+        inset = label == b
+        members = list(np.nonzero(inset)[0])
+        frontier = np.asarray(members, dtype=np.int64)
+        while len(members) < n_d and frontier.size:
+            counts = indptr[frontier + 1] - indptr[frontier]
+            starts = np.repeat(indptr[frontier], counts)
+            offs = np.arange(counts.sum()) - np.repeat(np.cumsum(counts) - counts, counts)
+            ring = np.unique(indices[starts + offs])
+            ring = ring[~inset[ring]]
+            take = ring[: n_d - len(members)]
+            inset[take] = True
+            members.extend(int(v) for v in take)
+            frontier = take
+        out.append(np.sort(np.asarray(members, dtype=np.int64)))
+    return out
+
+
+def split_members(n: int, faces: np.ndarray, members: list, seeds: np.ndarray):
+    """As split_blocks, for explicit (possibly overlapping) vertex sets: per
+    block the global ids in BFS-from-seed order and the faces with at least
+    two vertices in the block, in block-local ids (-1 = corner outside)."""
+    indptr, indices = vertex_adjacency(n, faces)
+    blocks = []
+    for b, mem in enumerate(members):
+        order = bfs_order(indptr, indices, mem, int(seeds[b]))
+        g2l = -np.ones(n, dtype=np.int64)
+        g2l[order] = np.arange(order.size)
+        lf_all = g2l[faces]
+        fsel = (lf_all >= 0).sum(1) >= 2
+        blocks.append((order, lf_all[fsel]))
+    return blocks
+
+
 def block_graph_order(n: int, faces: np.ndarray, label: np.ndarray, n_blocks: int,
                       rng: np.random.Generator, n_roots: int = 1):
     """Block processing order: a seeded first block (and, for n_roots > 1,

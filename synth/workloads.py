@@ -76,6 +76,38 @@ def _partitioned(name, verts, faces, n_blocks, key, c, p, n_roots=1):
                     n_global=n, extra=dict(label=label, seeds=seeds, faces_global=faces))
 
 
+def overlapped(name, verts, faces, n_blocks, key, c, p, overlap=0.15, n_roots=1):
+    """Region-grown parts extended to equal-size overlapped submeshes of
+    n_d = ceil((1 + overlap) * max part size) vertices (Section 6.1; the paper
+    finds 15 % sufficient).  The block order and the warm-start predecessors
+    follow the parts' adjacency, as for non-overlapping blocks."""
+    n = verts.shape[0]
+    indptr, indices = M.vertex_adjacency(n, faces)
+    label, seeds = M.region_grow(indptr, indices, n_blocks, M.rng_for(*key, 1), pts=verts)
+    sizes = np.bincount(label, minlength=n_blocks)
+    n_d = int(np.ceil((1.0 + overlap) * sizes.max()))
+    members = M.overlap_extend(indptr, indices, label, n_blocks, n_d)
+    blocks = M.split_members(n, faces, members, seeds)
+    order, pred, level = M.block_graph_order(n, faces, label, n_blocks, M.rng_for(*key, 2),
+                                             n_roots)
+    nb = len(blocks)
+    return BlockSet(name=name, coords=[verts[g] for g, _ in blocks], faces=[f for _, f in blocks],
+                    pred=pred, level=level, order=order, c=np.full(nb, c), p=np.full(nb, p),
+                    global_ids=[g for g, _ in blocks], n_global=n,
+                    extra=dict(label=label, seeds=seeds, faces_global=faces, n_d=n_d,
+                               verts_global=verts))
+
+
+def icosphere_overlapped(level=7, n_blocks=100, c=100, p=192, amp=0.05, overlap=0.15, key=(2,),
+                         n_roots=1):
+    """The static icosphere workload with overlapped equal-size submeshes
+    (same mesh, same parts as icosphere_blocks with the same key)."""
+    v, f = M.icosphere(level)
+    v = M.displaced_sphere(v, M.rng_for(*key, 0), amp)
+    name = f"icosphere{level}_b{n_blocks}_ov{int(round(100 * overlap))}"
+    return overlapped(name, v, f, n_blocks, key, c, p, overlap, n_roots)
+
+
 def grid_single(nx=32, ny=32, c=50, p=75, sigma=1e-3, key=(1,)):
     """Single submesh: nx-by-ny grid on [0, 2pi]^2, z = 0.1 sin x cos y + N(0, sigma)."""
     v, f = M.grid_mesh(nx, ny)

@@ -13,6 +13,7 @@ import torch
 import paper_1810_02719_amd as mis
 from oracle import iterations as it
 from oracle import laplacian as lap
+from oracle import merge as mg
 from oracle import metrics as met
 from oracle import spectral as S
 from synth import meshes as M
@@ -603,6 +604,74 @@ def test_choose_c_against_oracle(ctx):
         if int(cg[b]) != co:  # only a near-tie at the target may differ
             k = min(int(cg[b]), co) - 1
             assert abs(curve[k] - target) < 1e-3 * target
+
+
+# ------------------------------------------------------------------ overlapped submeshes (Section 6.1, Alg. 3)
+
+def _merge_oracle(up, Xr):
+    bs = up.bs
+    deg = [mg.submesh_degrees(f, len(g)) for g, f in zip(bs.global_ids, bs.faces)]
+    v = up.blocks.v_off
+    return mg.weighted_average(bs.n_global, bs.global_ids, deg,
+                               [Xr[v[b]:v[b + 1]] for b in range(bs.n_blocks)])
+
+
+@pytest.mark.parametrize("level,nb", [(4, 10), (7, 100)], ids=["small", "c2_full"])
+def test_merge_bitexact_against_oracle(ctx, level, nb):
+    """Degree-weighted merge of seeded per-row values on overlapped
+    submeshes (15 %, equal size), bit-exact against the oracle's Alg. 3; the
+    mesh's own coordinates come back unchanged; a second call reuses the
+    occurrence table; an out-of-range vertex id is rejected."""
+    bs = W.icosphere_overlapped(level=level, n_blocks=nb, c=4, p=32)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    gid = np.concatenate(bs.global_ids).astype(np.int32)
+    Xr = M.rng_for(71, level).normal(size=(gid.size, 3)).astype(np.float32)
+    Xd = torch.from_numpy(Xr.reshape(-1)).to("cuda:0")
+    out = mis.merge_overlapped(ctx, up.blocks, gid, bs.n_global, Lp, Xd)
+    torch.cuda.synchronize()
+    ref = _merge_oracle(up, Xr)
+    assert np.array_equal(out.cpu().numpy().reshape(-1, 3), ref)
+    again = mis.merge_overlapped(ctx, up.blocks, gid, bs.n_global, Lp, Xd)
+    assert torch.equal(again, out)
+    # equal reconstructions (the block coordinates themselves) merge exactly
+    own = mis.merge_overlapped(ctx, up.blocks, gid, bs.n_global, Lp, up.coords)
+    mesh = bs.extra["verts_global"].astype(np.float32)
+    assert np.array_equal(own.cpu().numpy().reshape(-1, 3), mesh)
+    bad = gid.copy()
+    bad[-1] = bs.n_global
+    with pytest.raises(mis.MiError) as ei:
+        mis.merge_overlapped(ctx, up.blocks, bad, bs.n_global, Lp, Xd)
+    assert ei.value.code == mis._lib.MI_ERR_INDEX
+
+
+def test_overlapped_pipeline_against_oracle(ctx):
+    """Overlapped submeshes end to end: Laplacian, tracked subspace from a
+    seeded start, projection, truncation, reconstruction and the merge,
+    against the oracle's exact eigenvectors followed by its Alg. 3."""
+    c, p = 24, 64
+    bs = W.icosphere_overlapped(level=4, n_blocks=8, c=c, p=p)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=40, m0=8, passes0=1,
+                       adapt=1, max_sweeps=15)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
+    cc = torch.full((bs.n_blocks,), c, dtype=torch.int32, device="cuda:0")
+    E = mis.project(ctx, up.blocks, cc, V, up.coords)
+    Xr = mis.reconstruct(ctx, up.blocks, cc, V, E)
+    gid = np.concatenate(bs.global_ids).astype(np.int32)
+    out = mis.merge_overlapped(ctx, up.blocks, gid, bs.n_global, Lp, Xr)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    Xo = []
+    for b in range(bs.n_blocks):
+        _, lam, U = oracle_block(up, b, k=p + 1)
+        assert S.sin_theta_max(U[:, :c], up.slab(V, b)[:, :c]) < ANGLE_FP32 * 10, b
+        Xo.append(S.encode_decode(U[:, :c], up.X32(b)))
+    ref = _merge_oracle(up, np.concatenate(Xo))
+    got = out.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    assert S.rel_error(got, ref.astype(np.float64)) < RECON_FP32 * 10
 
 
 # ------------------------------------------------------------------ adjoint of encode/decode

@@ -13,6 +13,7 @@ import pytest
 from oracle import exact
 from oracle import iterations as it
 from oracle import laplacian as lap
+from oracle import merge as mg
 from oracle import metrics as met
 from oracle import spectral as S
 from synth import meshes as M
@@ -534,3 +535,101 @@ class TestAdjointOracle:
                                        4, G, uw)
             errs.append(np.abs(gw - gwl).max() / np.abs(gwl).max())
         assert errs[-1] < 1e-8 and errs[0] > errs[-1], errs
+
+
+# ---------------------------------------------------------------- Section 6.1, Alg. 3
+
+class TestOverlappedMerge:
+    """Weighted average of a vertex's reconstructions in the overlapped
+    submeshes that hold it, weighted by its degree in each (Alg. 3)."""
+
+    def test_degrees_are_neighbour_counts(self):
+        # brute force: neighbour sets from the faces, kept inside the block
+        bs = W.icosphere_overlapped(level=3, n_blocks=6, c=4, p=8)
+        fg = bs.extra["faces_global"]
+        nbr = [set() for _ in range(bs.n_global)]
+        for f in fg:
+            for a in range(3):
+                for b in range(3):
+                    if a != b:
+                        nbr[f[a]].add(int(f[b]))
+        for gid, faces in zip(bs.global_ids, bs.faces):
+            inblk = set(int(g) for g in gid)
+            deg = mg.submesh_degrees(faces, len(gid))
+            for k, g in enumerate(gid):
+                assert deg[k] == len(nbr[g] & inblk)
+
+    def test_single_submesh_is_identity(self):
+        v, f = M.icosphere(2)
+        X = M.rng_for(61).normal(size=v.shape).astype(np.float32)
+        deg = mg.submesh_degrees(f, v.shape[0])
+        out = mg.weighted_average(v.shape[0], [np.arange(v.shape[0])], [deg], [X])
+        assert np.array_equal(out, X)
+        assert (deg == np.bincount(f.ravel(), minlength=v.shape[0])).all()  # closed surface: degree = faces per vertex
+
+    def test_disjoint_parts_are_identity(self):
+        bs = W.icosphere_blocks(level=3, n_blocks=5, c=4, p=8)
+        rng = M.rng_for(62)
+        Xb = [rng.normal(size=(len(g), 3)).astype(np.float32) for g in bs.global_ids]
+        deg = [mg.submesh_degrees(f, len(g)) for g, f in zip(bs.global_ids, bs.faces)]
+        out = mg.weighted_average(bs.n_global, bs.global_ids, deg, Xb)
+        ref = np.zeros((bs.n_global, 3), np.float32)
+        for g, x in zip(bs.global_ids, Xb):
+            ref[g] = x
+        assert np.array_equal(out, ref)
+
+    def test_weighted_centroid_balances(self):
+        # the paper's example point lies in three submeshes with degrees 4, 5
+        # and 6 (Section 6.1, the figure on degree weights): the merged point
+        # r satisfies sum_j w_j (r - v_j) = 0, and it moves toward the
+        # reconstruction with the largest degree
+        pts = np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0], [0.0, 6.0, 1.5]], np.float32)
+        gid = [np.array([0]), np.array([0]), np.array([0])]
+        deg = [np.array([4]), np.array([5]), np.array([6])]
+        r = mg.weighted_average(1, gid, deg, [pts[0:1], pts[1:2], pts[2:3]])[0].astype(np.float64)
+        bal = 4 * (r - pts[0]) + 5 * (r - pts[1]) + 6 * (r - pts[2])
+        assert np.abs(bal).max() < 1e-5
+        r_eq = mg.weighted_average(1, gid, [np.array([1])] * 3, [pts[0:1], pts[1:2], pts[2:3]])[0]
+        assert np.allclose(r_eq, pts.mean(0), atol=1e-6)
+        # two submeshes: the distances to the two reconstructions are in the
+        # inverse ratio of the degrees
+        r2 = mg.weighted_average(1, gid[:2], [np.array([2]), np.array([6])], [pts[0:1], pts[1:2]])[0]
+        da, db = np.linalg.norm(r2 - pts[0]), np.linalg.norm(r2 - pts[1])
+        assert abs(da / db - 3.0) < 1e-6
+
+    def test_equal_reconstructions_are_kept(self):
+        bs = W.icosphere_overlapped(level=3, n_blocks=6, c=4, p=8)
+        Xg = M.rng_for(63).normal(size=(bs.n_global, 3)).astype(np.float32)
+        deg = [mg.submesh_degrees(f, len(g)) for g, f in zip(bs.global_ids, bs.faces)]
+        out = mg.weighted_average(bs.n_global, bs.global_ids, deg, [Xg[g] for g in bs.global_ids])
+        assert np.abs(out - Xg).max() <= 2 * np.finfo(np.float32).eps * np.abs(Xg).max()
+
+    def test_all_zero_degrees_take_the_mean_and_uncovered_vertices_zero(self):
+        gid = [np.array([0, 1]), np.array([0])]
+        deg = [np.array([0, 0]), np.array([0])]
+        X = [np.array([[1, 2, 3], [5, 5, 5]], np.float32), np.array([[3, 4, 5]], np.float32)]
+        out = mg.weighted_average(3, gid, deg, X)
+        assert np.array_equal(out[0], [2, 3, 4]) and np.array_equal(out[1], [5, 5, 5])
+        assert np.array_equal(out[2], [0, 0, 0])
+
+
+class TestOverlapGenerator:
+    """Equal-size overlapped submeshes of Section 6.1 (input generation)."""
+
+    def test_sizes_cores_and_rings(self):
+        bs = W.icosphere_overlapped(level=4, n_blocks=10, c=4, p=8, overlap=0.15)
+        lab = bs.extra["label"]
+        n_d = bs.extra["n_d"]
+        sizes = np.bincount(lab)
+        assert n_d == int(np.ceil(1.15 * sizes.max()))
+        indptr, indices = M.vertex_adjacency(bs.n_global, bs.extra["faces_global"])
+        for b, g in enumerate(bs.global_ids):
+            assert len(g) == n_d == len(set(g.tolist()))
+            core = set(np.nonzero(lab == b)[0].tolist())
+            assert core <= set(g.tolist())
+            # every added vertex touches the block: the rings grow outwards
+            gs = set(g.tolist())
+            for v in gs - core:
+                assert any(int(u) in gs for u in indices[indptr[v]:indptr[v + 1]])
+        cover = np.bincount(np.concatenate(bs.global_ids), minlength=bs.n_global)
+        assert cover.min() >= 1 and cover.max() >= 2

@@ -183,6 +183,22 @@ def main():
 
     merge = merge_run(mis, ctx, W, dev, reps=5 if args.profile_only else 50)
 
+    # codec (Section 8): 12-bit uniform quantisation of this step's feature
+    # vectors, the rate, and the change of the reconstruction it causes
+    qb = 12
+    mis.quantize(ctx, blocks, c, E, qb)
+    ctx.set_timing(True)
+    for _ in range(5 if args.profile_only else 20):
+        _, _, Eq = mis.quantize(ctx, blocks, c, E, qb)
+    torch.cuda.synchronize()
+    q_ms, q_n = ctx.kernel_times()["quantize"]
+    ctx.set_timing(False)
+    Xq = mis.reconstruct(ctx, blocks, c, V, Eq)
+    torch.cuda.synchronize()
+    codec = {"qbits": qb, "bpv": 3.0 * qb * float(c.sum().item()) / nverts,
+             "kernel_ms": q_ms / max(q_n, 1),
+             "recon_rel_change": float((Xq - Xr).double().norm() / Xr.double().norm())}
+
     out = {
         "metric": "submesh vertices/sec (OI + project/recon) at principal angle <=1e-5 vs FP64 oracle",
         "value": value,
@@ -208,6 +224,7 @@ def main():
         "launch_shapes": [list(t) for t in ctx.tuning()],
         "build_laplacian_ms": lap_ms,
         "merge": merge,
+        "codec": codec,
         "block_status_nonzero": int((st != 0).sum()),
         "input_gen_s": gen_s,
     }

@@ -169,6 +169,7 @@ enum {
   MI_K_EIG_VECTORS,    /* eigenvectors of the tridiagonal matrix */
   MI_K_EIG_BACK,       /* back-transformation by the reflectors */
   MI_K_MERGE,          /* degree-weighted merge of overlapped submeshes */
+  MI_K_QUANTIZE,       /* uniform quantisation of the feature vectors */
   MI_K_COUNT
 };
 /* Name of a kernel class ("spmm", ...), NULL when out of range. */
@@ -381,6 +382,26 @@ mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, c
 mi_status mi_merge_overlapped(mi_ctx* ctx, const mi_blocks* blk, const int32_t* gid,
                               int64_t n_vertices, const int32_t* row_ptr, const float* Xr,
                               float* Xout, void* stream);
+
+/* ---------------------------------------------------------------- quantisation
+ * Section 8 (compression): the feature vectors E are quantised uniformly
+ * with qbits bits (12 in the paper's experiments).  For each block and
+ * coordinate axis the first c_b coefficients are mapped onto 2^qbits levels
+ * spanning their range [lo, hi]: step = (hi - lo) / (2^qbits - 1),
+ * code = rint((e - lo) / step) (ties to even, clamped to the levels; every
+ * code 0 when step is 0), dequantised e' = lo + code * step.  All in FP32,
+ * each operation rounded on its own, so the result is reproducible bit for
+ * bit.  The rate is 3 * qbits * sum_b c_b bits for the whole mesh (plus the
+ * per-block ranges).
+ * c       device int32 [B], 0 <= c_b <= p_b.
+ * E       device float [sum p_b][3] (from mi_project; rows >= c_b are ignored).
+ * codes   device uint16 [sum p_b][3]; rows >= c_b are written as 0.
+ * params  device float [B][3][2]: (lo, step) of every block and axis.
+ * Eq      device float [sum p_b][3] or NULL: the dequantised coefficients
+ *         (rows >= c_b zero), ready for mi_reconstruct.
+ * qbits in [1, 16].  Enqueue only. */
+mi_status mi_quantize(mi_ctx* ctx, const mi_blocks* blk, const int32_t* c, int32_t qbits,
+                      const float* E, uint16_t* codes, float* params, float* Eq, void* stream);
 
 /* ---------------------------------------------------------------- choice of c
  * Section 5 (smallest subspace meeting a reconstruction-quality target) with

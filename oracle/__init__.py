@@ -24,4 +24,5 @@ iterations  paper-literal orthogonal iteration (Alg. 1) and dynamic OI (Alg. 2),
 exact       brute-force integer characteristic polynomials, Sturm bisection and
             spanning-tree counts for meshes of <= 10 vertices
 merge       degree-weighted merge of overlapped submeshes (Section 6.1, Alg. 3)
+codec       uniform quantisation of the feature vectors and the bit rate (Section 8)
 """

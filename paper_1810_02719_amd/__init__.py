@@ -357,6 +357,20 @@ def merge_overlapped(ctx: Context, blocks: Blocks, gid, n_vertices: int, lap: La
     return Xout
 
 
+def quantize(ctx: Context, blocks: Blocks, c: torch.Tensor, E: torch.Tensor, qbits: int = 12,
+             dequantize: bool = True):
+    """Uniform qbits-bit quantisation of the feature vectors (mi_quantize).
+    Returns (codes uint16 [sum p_b * 3] as int16 storage, params FP32 [B * 6],
+    dequantised E or None)."""
+    n = int(blocks.t_off[-1]) * 3
+    codes = torch.empty(n, dtype=torch.int16, device=E.device)
+    params = torch.empty(blocks.n_blocks * 6, dtype=torch.float32, device=E.device)
+    Eq = torch.empty(n, dtype=torch.float32, device=E.device) if dequantize else None
+    L.check(L.lib().mi_quantize(ctx.h, blocks.ref, _dptr(c), int(qbits), _dptr(E), _dptr(codes),
+                                _dptr(params), _dptr(Eq) if Eq is not None else None, _stream()))
+    return codes, params, Eq
+
+
 def choose_c(ctx: Context, blocks: Blocks, c_max: torch.Tensor, target: float, g_min: float,
              U: torch.Tensor, ritz: torch.Tensor, X: torch.Tensor, gl: Laplacian):
     """Per-block c for an NMSVE target (gl: the MI_W_INV_DIST Laplacian of the

@@ -162,5 +162,6 @@ struct mi_ctx {
   void* adj_oi = nullptr;    // tracking plan of the recorded forward (adjoint.hip)
   void* adj_plan = nullptr;  // adjoint tables (adjoint.hip)
   void* merge_plan = nullptr;  // occurrence table of overlapped submeshes (merge.hip)
+  void* codec_plan = nullptr;  // block offsets of the quantiser (codec.hip)
   mis::KTimer* timer = nullptr;  // non-null while timing is on
 };

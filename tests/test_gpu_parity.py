@@ -12,6 +12,7 @@ import torch
 
 import paper_1810_02719_amd as mis
 from oracle import iterations as it
+from oracle import codec as cd
 from oracle import laplacian as lap
 from oracle import merge as mg
 from oracle import metrics as met
@@ -672,6 +673,72 @@ def test_overlapped_pipeline_against_oracle(ctx):
     ref = _merge_oracle(up, np.concatenate(Xo))
     got = out.cpu().numpy().reshape(-1, 3).astype(np.float64)
     assert S.rel_error(got, ref.astype(np.float64)) < RECON_FP32 * 10
+
+
+# ------------------------------------------------------------------ quantisation (Section 8)
+
+def _quant_check(blocks, c_h, E_h, codes, params, Eq, qbits):
+    codes = codes.cpu().numpy().view(np.uint16).reshape(-1, 3)
+    params = params.cpu().numpy().reshape(-1, 3, 2)
+    Eq = Eq.cpu().numpy().reshape(-1, 3)
+    t = blocks.t_off
+    for b in range(blocks.n_blocks):
+        cr, lo, step, deq = cd.quantize_block(E_h[t[b]:t[b + 1]], int(c_h[b]), qbits)
+        cb = int(c_h[b])
+        assert np.array_equal(codes[t[b]:t[b] + cb], cr), b
+        assert (codes[t[b] + cb:t[b + 1]] == 0).all()
+        assert np.array_equal(params[b, :, 0], lo) and np.array_equal(params[b, :, 1], step), b
+        assert np.array_equal(Eq[t[b]:t[b] + cb], deq), b
+        assert (Eq[t[b] + cb:t[b + 1]] == 0).all()
+
+
+@pytest.mark.parametrize("qbits", [12, 5])
+def test_quantize_pipeline_bitexact(ctx, qbits):
+    """Feature vectors of a tracked chain quantised on the GPU, bit-exact
+    against the oracle's quantiser on the same E; the dequantised
+    reconstruction stays within the quantiser's error of the unquantised
+    one."""
+    bs = W.icosphere_blocks(level=4, n_blocks=4, c=24, p=48)
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=up.starts(torch.float32))
+    c = torch.tensor([24, 1, 0, 48], dtype=torch.int32, device="cuda:0")
+    E = mis.project(ctx, up.blocks, torch.full_like(c, 48), V, up.coords)
+    codes, params, Eq = mis.quantize(ctx, up.blocks, c, E, qbits)
+    torch.cuda.synchronize()
+    _quant_check(up.blocks, c.cpu().numpy(), E.cpu().numpy().reshape(-1, 3), codes, params, Eq, qbits)
+    Xr = mis.reconstruct(ctx, up.blocks, torch.full_like(c, 48), V, Eq)
+    Xe = mis.reconstruct(ctx, up.blocks, torch.full_like(c, 48), V, E)
+    torch.cuda.synchronize()
+    # orthonormal U: the coordinate error is the coefficient error
+    dq = (Eq - E).view(-1, 3).double().cpu().numpy()
+    for b in range(4):
+        v = slice(int(up.blocks.v_off[b]), int(up.blocks.v_off[b + 1]))
+        t = slice(int(up.blocks.t_off[b]), int(up.blocks.t_off[b + 1]))
+        dx = (Xr - Xe).view(-1, 3)[v].double().cpu().numpy()
+        assert abs(np.linalg.norm(dx) - np.linalg.norm(dq[t])) < 1e-4 * max(1.0, np.linalg.norm(dq[t]))
+
+
+def test_quantize_full_size_layout(ctx):
+    """The benchmark's layout (100 blocks, p = 192, c = 100) with seeded
+    coefficients decaying like a spectrum: codes, ranges and dequantised
+    values bit-exact against the oracle; the rate is 3 * 12 * sum c_b / n."""
+    bs = W.icosphere_blocks(level=7, n_blocks=100, c=100, p=192)
+    fl = W.flatten(bs)
+    blocks = mis.Blocks(bs.n, p=fl["p"], ld=fl["ld"], pred=bs.pred)
+    rng = M.rng_for(91)
+    E_h = np.concatenate([rng.normal(size=(192, 3)) / (1.0 + np.arange(192))[:, None]
+                          for _ in range(100)]).astype(np.float32)
+    c_h = rng.integers(80, 121, size=100).astype(np.int32)
+    E = torch.from_numpy(E_h.reshape(-1)).to("cuda:0")
+    c = torch.from_numpy(c_h).to("cuda:0")
+    codes, params, Eq = mis.quantize(ctx, blocks, c, E, 12)
+    torch.cuda.synchronize()
+    _quant_check(blocks, c_h, E_h, codes, params, Eq, 12)
+    assert abs(cd.bits_per_vertex(12, c_h, int(blocks.v_off[-1])) - 36.0 * c_h.sum() / 163842) < 1e-12
+    with pytest.raises(mis.MiError) as ei:
+        mis.quantize(ctx, blocks, c, E, 17)
+    assert ei.value.code == mis._lib.MI_ERR_ARG
 
 
 # ------------------------------------------------------------------ adjoint of encode/decode

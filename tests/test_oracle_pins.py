@@ -12,6 +12,7 @@ import pytest
 
 from oracle import exact
 from oracle import iterations as it
+from oracle import codec as cd
 from oracle import laplacian as lap
 from oracle import merge as mg
 from oracle import metrics as met
@@ -633,3 +634,39 @@ class TestOverlapGenerator:
                 assert any(int(u) in gs for u in indices[indptr[v]:indptr[v + 1]])
         cover = np.bincount(np.concatenate(bs.global_ids), minlength=bs.n_global)
         assert cover.min() >= 1 and cover.max() >= 2
+
+
+# ---------------------------------------------------------------- Section 8 (compression)
+
+class TestQuantiser:
+    """Uniform q-bit quantisation of the feature vectors and the bit rate."""
+
+    def test_levels_are_exact_on_a_grid(self):
+        # values already on the 2^q levels of their range come back exactly
+        q = 3
+        E = np.zeros((8, 3), np.float32)
+        E[:, 0] = np.arange(8) * 0.25 - 1.0          # step 0.25, lo -1
+        E[:, 1] = np.arange(8)[::-1]                  # step 1, reversed
+        E[:, 2] = 2.5                                 # constant axis
+        codes, lo, step, deq = cd.quantize_block(E, 8, q)
+        assert np.array_equal(codes[:, 0], np.arange(8)) and np.array_equal(codes[:, 1], np.arange(8)[::-1])
+        assert (codes[:, 2] == 0).all() and step[2] == 0 and lo[2] == 2.5
+        assert np.array_equal(deq, E)
+
+    def test_error_bound_and_extremes(self):
+        rng = M.rng_for(81)
+        E = rng.normal(scale=3.0, size=(150, 3)).astype(np.float32)
+        for q in (4, 8, 12, 16):
+            codes, lo, step, deq = cd.quantize_block(E, 100, q)
+            assert codes.max() <= (1 << q) - 1
+            err = np.abs(deq.astype(np.float64) - E[:100].astype(np.float64))
+            # half a step, plus the FP32 rounding of the level's value
+            assert (err <= step.astype(np.float64) / 2 * (1 + 1e-5) + 4 * np.finfo(np.float32).eps * np.abs(E[:100]).max(0)).all()
+            for k in range(3):  # the range ends map to the first and last level
+                assert codes[np.argmin(E[:100, k]), k] == 0
+                assert codes[np.argmax(E[:100, k]), k] == (1 << q) - 1
+
+    def test_rate_counts_bits_per_mesh_vertex(self):
+        # the paper's bpv = 3 q_c c k / n_d for k equal blocks of n_d vertices
+        assert cd.bits_per_vertex(12, np.full(70, 100), 70 * 512) == 3 * 12 * 100 * 70 / (70 * 512)
+        assert cd.bits_per_vertex(12, np.array([0, 0]), 10) == 0.0

@@ -12,6 +12,12 @@ coincide).  dB = 10 log10.
 
 Section 5, Eq. 6: the DOI residual e = sum_{j in x,y,z} (v_j - U U^T v_j).
 
+Section 8 (theta): the angle between the normal of every face of the
+original mesh and the normal of the same face of the reconstruction,
+averaged over all faces, in degrees (the unit of the paper's table of
+theta values).  Reading: a face whose normal vanishes on either side (zero
+area) has no direction and is left out of the average.
+
 Choice of c (Section 5: smallest subspace meeting a quality constraint):
 smallest c in [1, c_max] with NMSVE(c) <= target (c_max if none), then moved
 up to the first cut with a relative spectral gap
@@ -19,6 +25,8 @@ up to the first cut with a relative spectral gap
 well defined (reading; the paper is silent on near-ties).
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -49,6 +57,55 @@ def nmsve(X: np.ndarray, Xr: np.ndarray, G: np.ndarray) -> float:
 
 def nmsve_db(x: float) -> float:
     return float(10.0 * np.log10(x))
+
+
+def gl_apply(n: int, edges: np.ndarray, coords0: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """G Y for the GL operator of gl_matrix, one edge at a time (sparse, for
+    whole meshes): row i gets Y_i - sum_j w_ij Y_j / sum_j w_ij, w = 1/d_ij of
+    the original mesh; rows without neighbours are left unchanged."""
+    w = lap.edge_weights(edges, coords0, lap.INV_DIST)
+    Y = np.asarray(Y, dtype=np.float64)
+    num = np.zeros_like(Y)
+    den = np.zeros(n)
+    i, j = edges[:, 0], edges[:, 1]
+    np.add.at(num, i, w[:, None] * Y[j])
+    np.add.at(num, j, w[:, None] * Y[i])
+    np.add.at(den, i, w)
+    np.add.at(den, j, w)
+    out = Y.copy()
+    nz = den > 0
+    out[nz] -= num[nz] / den[nz, None]
+    return out
+
+
+def nmsve_mesh(n: int, edges: np.ndarray, X: np.ndarray, Xr: np.ndarray) -> float:
+    """Eq. 16 over a whole mesh given by its edge list, with the GL weights
+    of the original coordinates X (literal reading above)."""
+    X = np.asarray(X, dtype=np.float64)
+    Xr = np.asarray(Xr, dtype=np.float64)
+    a = np.linalg.norm(X - Xr)
+    b = np.linalg.norm(gl_apply(n, edges, X, X) - gl_apply(n, edges, X, Xr))
+    return float((a + b) / (2.0 * n))
+
+
+def mean_normal_angle(faces: np.ndarray, X: np.ndarray, Xr: np.ndarray):
+    """theta of Section 8: the mean over faces of the angle, in degrees,
+    between the face normal (v1 - v0) x (v2 - v0) of X and of Xr.  Returns
+    (theta, number of faces averaged); faces with a zero normal on either
+    side are skipped."""
+    X = np.asarray(X, dtype=np.float64)
+    Xr = np.asarray(Xr, dtype=np.float64)
+    total, used = 0.0, 0
+    for a, b, c in np.asarray(faces):
+        no = np.cross(X[b] - X[a], X[c] - X[a])
+        nr = np.cross(Xr[b] - Xr[a], Xr[c] - Xr[a])
+        lo, lr = np.linalg.norm(no), np.linalg.norm(nr)
+        if lo == 0.0 or lr == 0.0:
+            continue
+        cosang = min(1.0, max(-1.0, float(no @ nr) / (lo * lr)))
+        total += math.degrees(math.acos(cosang))
+        used += 1
+    return (total / used if used else 0.0), used
 
 
 def nmsve_curve(U: np.ndarray, X: np.ndarray, G: np.ndarray, c_max: int) -> np.ndarray:

@@ -670,3 +670,76 @@ class TestQuantiser:
         # the paper's bpv = 3 q_c c k / n_d for k equal blocks of n_d vertices
         assert cd.bits_per_vertex(12, np.full(70, 100), 70 * 512) == 3 * 12 * 100 * 70 / (70 * 512)
         assert cd.bits_per_vertex(12, np.array([0, 0]), 10) == 0.0
+
+
+class TestMeshQuality:
+    """Whole-mesh NMSVE (Eq. 16) and the mean face-normal angle theta
+    (Section 8) that the quality report computes."""
+
+    def test_nmsve_mesh_hand_example(self):
+        # the 4-cycle square of TestMetrics, through the edge-by-edge operator
+        X = np.array([[0., 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]])
+        Xr = X.copy()
+        Xr[0, 2] = 0.3
+        e = lap.canonical_edges(cycle_edges(4), 4)
+        d2 = math.sqrt(0.3 ** 2 + 2 * 0.15 ** 2)
+        assert math.isclose(met.nmsve_mesh(4, e, X, Xr), (0.3 + d2) / 8, rel_tol=1e-12)
+
+    def test_nmsve_of_a_translation(self):
+        # GL removes constants, so a rigid shift t leaves only the l2 term:
+        # NMSVE = sqrt(n) |t| / (2 n)
+        v, f = M.icosphere(2)
+        X = M.displaced_sphere(v, M.rng_for(90), 0.05)
+        n = X.shape[0]
+        t = np.array([0.3, -0.4, 1.2])
+        e = lap.canonical_edges(f, n)
+        got = met.nmsve_mesh(n, e, X, X + t)
+        assert math.isclose(got, math.sqrt(n) * 1.3 / (2 * n), rel_tol=1e-12)
+        assert met.nmsve_mesh(n, e, X, X) == 0.0
+
+    def test_sparse_gl_matches_dense_operator(self):
+        bs = W.grid_single(nx=7, ny=6, c=5, p=8)
+        X = bs.coords[0]
+        n = X.shape[0]
+        e = lap.canonical_edges(bs.faces[0], n)
+        Y = M.rng_for(91).normal(size=(n, 3))
+        assert np.abs(met.gl_apply(n, e, X, Y) - met.gl_matrix(n, e, X) @ Y).max() < 1e-13
+        # an isolated vertex keeps its value
+        e2 = e[(e != n - 1).all(1)]
+        assert np.array_equal(met.gl_apply(n, e2, X, Y)[n - 1], Y[n - 1])
+
+    def test_angle_hand_example(self):
+        # normal (0,0,1) against (1,0,0) x (0,1,1) = (0,-1,1): 45 degrees
+        f = np.array([[0, 1, 2]])
+        X = np.array([[0., 0, 0], [1, 0, 0], [0, 1, 0]])
+        Xr = np.array([[0., 0, 0], [1, 0, 0], [0, 1, 1]])
+        th, used = met.mean_normal_angle(f, X, Xr)
+        assert used == 1 and math.isclose(th, 45.0, rel_tol=1e-12)
+        # two faces at 45 and 90 degrees average to 67.5
+        f2 = np.array([[0, 1, 2], [3, 4, 5]])
+        X2 = np.concatenate([X, X + 5])
+        Xr2 = np.concatenate([Xr, np.array([[5., 5, 5], [6, 5, 5], [5, 5, 6]])])  # normal (0,-1,0)
+        th, used = met.mean_normal_angle(f2, X2, Xr2)
+        assert used == 2 and math.isclose(th, 67.5, rel_tol=1e-12)
+
+    def test_angle_of_rotated_and_mirrored_plane(self):
+        # every normal of a flat mesh is (0,0,1); a rotation about the x axis
+        # by alpha turns each by alpha, a mirror in x flips each
+        v, f = M.grid_mesh(9, 8)
+        v[:, 2] = 0.0
+        a = math.radians(31.0)
+        R = np.array([[1, 0, 0], [0, math.cos(a), -math.sin(a)], [0, math.sin(a), math.cos(a)]])
+        th, used = met.mean_normal_angle(f, v, v @ R.T)
+        assert used == len(f) and math.isclose(th, 31.0, rel_tol=1e-10)
+        th, _ = met.mean_normal_angle(f, v, v * np.array([-1.0, 1.0, 1.0]))
+        assert math.isclose(th, 180.0, rel_tol=1e-12)
+        th, _ = met.mean_normal_angle(f, v, v)
+        assert th == 0.0
+
+    def test_zero_area_faces_are_left_out(self):
+        f = np.array([[0, 1, 2], [0, 1, 3]])
+        X = np.array([[0., 0, 0], [1, 0, 0], [0, 1, 0], [2, 0, 0]])  # face 1 collinear
+        Xr = np.array([[0., 0, 0], [1, 0, 0], [0, 1, 1], [0, 0, 1]])
+        th, used = met.mean_normal_angle(f, X, Xr)
+        assert used == 1 and math.isclose(th, 45.0, rel_tol=1e-12)
+        assert met.mean_normal_angle(f[1:], X, Xr) == (0.0, 0)

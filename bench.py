@@ -91,6 +91,36 @@ def merge_run(mis, ctx, W, dev, reps):
             "setup_s": gen_s}
 
 
+def quality_run(mis, ctx, bs, blocks, L, coords, Xr, Xq, dev, reps):
+    """Section 8 quality of the step's reconstruction on the whole mesh: the
+    blocks' reconstructions placed at their mesh vertices (the merge, with
+    one occurrence per vertex for disjoint blocks), then NMSVE in dB and the
+    mean face-normal angle, for the FP32 coefficients and their 12-bit codes."""
+    import torch
+    gid = np.concatenate(bs.global_ids).astype(np.int32)
+    nv = int(bs.n_global)
+    Xg = mis.merge_overlapped(ctx, blocks, gid, nv, L, coords)  # the original mesh
+    Xm = mis.merge_overlapped(ctx, blocks, gid, nv, L, Xr)
+    Xmq = mis.merge_overlapped(ctx, blocks, gid, nv, L, Xq)
+    faces = torch.from_numpy(np.ascontiguousarray(
+        bs.extra["faces_global"].astype(np.int32).reshape(-1))).to(dev)
+    Lm = mis.mesh_laplacian(ctx, nv, faces)
+    q32 = mis.mesh_quality(ctx, nv, Lm.row_ptr, Lm.col, faces, Xg, Xm)
+    q12 = mis.mesh_quality(ctx, nv, Lm.row_ptr, Lm.col, faces, Xg, Xmq)
+    ctx.set_timing(True)
+    for _ in range(reps):
+        mis.mesh_quality(ctx, nv, Lm.row_ptr, Lm.col, faces, Xg, Xm, out=q32)
+    torch.cuda.synchronize()
+    k_ms, k_n = ctx.kernel_times()["quality"]
+    ctx.set_timing(False)
+    a = dict(zip(mis.QUALITY_FIELDS, q32.cpu().numpy().tolist()))
+    b = dict(zip(mis.QUALITY_FIELDS, q12.cpu().numpy().tolist()))
+    return {"workload": "icosphere7 whole mesh, c=100 per block", "vertices": nv,
+            "faces": int(faces.numel() // 3), "nmsve": a["nmsve"], "nmsve_db": a["nmsve_db"],
+            "theta_deg": a["theta_deg"], "nmsve_db_12bit": b["nmsve_db"],
+            "theta_deg_12bit": b["theta_deg"], "kernel_ms": k_ms / max(k_n, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -198,6 +228,8 @@ def main():
     codec = {"qbits": qb, "bpv": 3.0 * qb * float(c.sum().item()) / nverts,
              "kernel_ms": q_ms / max(q_n, 1),
              "recon_rel_change": float((Xq - Xr).double().norm() / Xr.double().norm())}
+    quality = quality_run(mis, ctx, bs, blocks, L, coords, Xr, Xq, dev,
+                          reps=5 if args.profile_only else 50)
 
     out = {
         "metric": "submesh vertices/sec (OI + project/recon) at principal angle <=1e-5 vs FP64 oracle",
@@ -225,6 +257,7 @@ def main():
         "build_laplacian_ms": lap_ms,
         "merge": merge,
         "codec": codec,
+        "quality": quality,
         "block_status_nonzero": int((st != 0).sum()),
         "input_gen_s": gen_s,
     }

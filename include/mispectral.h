@@ -170,6 +170,7 @@ enum {
   MI_K_EIG_BACK,       /* back-transformation by the reflectors */
   MI_K_MERGE,          /* degree-weighted merge of overlapped submeshes */
   MI_K_QUANTIZE,       /* uniform quantisation of the feature vectors */
+  MI_K_QUALITY,        /* whole-mesh NMSVE and face-normal angle */
   MI_K_COUNT
 };
 /* Name of a kernel class ("spmm", ...), NULL when out of range. */
@@ -402,6 +403,34 @@ mi_status mi_merge_overlapped(mi_ctx* ctx, const mi_blocks* blk, const int32_t* 
  * qbits in [1, 16].  Enqueue only. */
 mi_status mi_quantize(mi_ctx* ctx, const mi_blocks* blk, const int32_t* c, int32_t qbits,
                       const float* E, uint16_t* codes, float* params, float* Eq, void* stream);
+
+/* ---------------------------------------------------------------- quality report
+ * Section 8: the reconstruction quality of a whole mesh.
+ *   NMSVE = ( ||v - v~||_2 + ||GL(v) - GL(v~)||_2 ) / (2n)          (Eq. 16)
+ *   GL(v)_i = v_i - sum_j d_ij^-1 v_j / sum_j d_ij^-1, j over the neighbours of i,
+ * over the 3n-vectors of coordinates, with the edge lengths d_ij of the
+ * ORIGINAL mesh X for both operands (GL is one linear operator; a vertex
+ * without neighbours keeps GL(v)_i = v_i).  theta = the angle between the
+ * normal (x_b - x_a) x (x_c - x_a) of every face in X and in Xr, averaged
+ * over the faces whose normal is nonzero on both sides, in degrees.  All
+ * sums in FP64 over a fixed grid, bitwise reproducible.
+ * row_ptr  device int32 [n_vertices + 1], col device int32 [nnz]: the
+ *          neighbour lists of the mesh vertices (entries with col == row,
+ *          such as a Laplacian's diagonal, are skipped), e.g. the Laplacian
+ *          mi_build_laplacian writes for one block holding the whole mesh.
+ * faces    device int32 [n_faces][3], mesh vertex ids.
+ * X, Xr    device float [n_vertices][3]: original and reconstructed mesh.
+ * out      device double [8], written by the stream: NMSVE, 10 log10 NMSVE,
+ *          ||v - v~||_2, ||GL(v) - GL(v~)||_2, theta (degrees; 0 when no
+ *          face counts), faces averaged, zero-length edges, out-of-range
+ *          indices.  A zero-length edge or an index outside [0, n_vertices)
+ *          (counted in out[6] / out[7] and skipped, never dereferenced)
+ *          makes the NMSVE entries and theta NaN.
+ * The first call on a context allocates its partial-sum buffer (48 KiB);
+ * later calls only enqueue two kernels. */
+mi_status mi_mesh_quality(mi_ctx* ctx, int64_t n_vertices, const int32_t* row_ptr,
+                          const int32_t* col, int64_t nnz, int64_t n_faces, const int32_t* faces,
+                          const float* X, const float* Xr, double* out, void* stream);
 
 /* ---------------------------------------------------------------- choice of c
  * Section 5 (smallest subspace meeting a reconstruction-quality target) with

@@ -371,6 +371,34 @@ def quantize(ctx: Context, blocks: Blocks, c: torch.Tensor, E: torch.Tensor, qbi
     return codes, params, Eq
 
 
+def mesh_laplacian(ctx: Context, n_vertices: int, faces: torch.Tensor,
+                   coords: torch.Tensor | None = None, mode: int = MI_W_COMBINATORIAL) -> Laplacian:
+    """Laplacian of a whole mesh (one block holding every vertex): its
+    row_ptr / col are the neighbour lists mesh_quality takes."""
+    nf = int(faces.numel() // 3)
+    blocks = Blocks(np.array([int(n_vertices)]), p=np.array([1]), pred=np.array([-1]))
+    return build_laplacian(ctx, blocks, np.array([0, nf]), faces, 3, coords, mode)
+
+
+QUALITY_FIELDS = ("nmsve", "nmsve_db", "l2", "gl", "theta_deg", "faces_used", "zero_edges",
+                  "bad_indices")
+
+
+def mesh_quality(ctx: Context, n_vertices: int, row_ptr: torch.Tensor, col: torch.Tensor,
+                 faces: torch.Tensor, X: torch.Tensor, Xr: torch.Tensor,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """NMSVE (Eq. 16) and mean face-normal angle of a whole mesh
+    (mi_mesh_quality).  row_ptr / col: neighbour CSR of the mesh (a
+    Laplacian's diagonal is skipped); faces int32 [F * 3]; X, Xr FP32
+    [n * 3].  Returns the FP64 [8] device tensor named by QUALITY_FIELDS."""
+    if out is None:
+        out = torch.empty(8, dtype=torch.float64, device=X.device)
+    L.check(L.lib().mi_mesh_quality(ctx.h, int(n_vertices), _dptr(row_ptr), _dptr(col),
+                                    int(col.numel()), int(faces.numel() // 3), _dptr(faces),
+                                    _dptr(X), _dptr(Xr), _dptr(out), _stream()))
+    return out
+
+
 def choose_c(ctx: Context, blocks: Blocks, c_max: torch.Tensor, target: float, g_min: float,
              U: torch.Tensor, ritz: torch.Tensor, X: torch.Tensor, gl: Laplacian):
     """Per-block c for an NMSVE target (gl: the MI_W_INV_DIST Laplacian of the

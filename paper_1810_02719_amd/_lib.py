@@ -42,7 +42,7 @@ MI_EIG_JACOBI = 1
 KERNEL_CLASSES = ["spmm", "gram", "gram_small", "gram_reduce", "chol", "rowmul", "rowmul_small",
                   "rq_max", "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish", "perm_cast",
                   "setup", "project", "reconstruct", "eig_reduce", "eig_values", "eig_vectors",
-                  "eig_back", "merge", "quantize"]
+                  "eig_back", "merge", "quantize", "quality"]
 MI_K_COUNT = len(KERNEL_CLASSES)
 
 MI_BLOCK_OK = 0
@@ -101,6 +101,7 @@ _SIGS = {
     "mi_reconstruct": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _vp, _vp],
     "mi_merge_overlapped": [_vp, C.POINTER(MiBlocks), _vp, C.c_int64, _vp, _vp, _vp, _vp],
     "mi_quantize": [_vp, C.POINTER(MiBlocks), _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp],
+    "mi_mesh_quality": [_vp, C.c_int64, _vp, _vp, C.c_int64, C.c_int64, _vp, _vp, _vp, _vp, _vp],
     "mi_choose_c_workspace_size": [_vp, C.POINTER(MiBlocks), _szp],
     "mi_choose_c": [_vp, C.POINTER(MiBlocks), _vp, C.c_double, C.c_double, _vp, _vp, _vp, _vp,
                     _vp, _vp, _i64p, _vp, _vp, _vp, C.c_size_t, _vp],

@@ -163,5 +163,6 @@ struct mi_ctx {
   void* adj_plan = nullptr;  // adjoint tables (adjoint.hip)
   void* merge_plan = nullptr;  // occurrence table of overlapped submeshes (merge.hip)
   void* codec_plan = nullptr;  // block offsets of the quantiser (codec.hip)
+  void* quality_plan = nullptr;  // partial sums of the quality report (quality.hip)
   mis::KTimer* timer = nullptr;  // non-null while timing is on
 };

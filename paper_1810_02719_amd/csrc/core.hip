@@ -227,6 +227,7 @@ void mis_destroy_res_plan(mi_ctx* ctx);
 void mis_destroy_adj_plan(mi_ctx* ctx);
 void mis_destroy_merge_plan(mi_ctx* ctx);
 void mis_destroy_codec_plan(mi_ctx* ctx);
+void mis_destroy_quality_plan(mi_ctx* ctx);
 
 mi_status mi_ctx_destroy(mi_ctx* ctx) {
   mis::clear_error();
@@ -238,6 +239,7 @@ mi_status mi_ctx_destroy(mi_ctx* ctx) {
   mis_destroy_adj_plan(ctx);
   mis_destroy_merge_plan(ctx);
   mis_destroy_codec_plan(ctx);
+  mis_destroy_quality_plan(ctx);
   delete ctx->timer;
   delete ctx;
   return MI_OK;
@@ -247,7 +249,8 @@ static const char* const k_class_names[MI_K_COUNT] = {
     "spmm",        "gram",       "gram_small", "gram_reduce",  "chol",      "rowmul",
     "rowmul_small", "rq_max",    "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish",
     "perm_cast",   "setup",      "project",    "reconstruct",  "eig_reduce", "eig_values",
-    "eig_vectors", "eig_back",   "merge",      "quantize"};
+    "eig_vectors", "eig_back",   "merge",      "quantize",
+    "quality"};
 
 const char* mi_kernel_class_name(int32_t k) {
   return (k >= 0 && k < MI_K_COUNT) ? k_class_names[k] : nullptr;

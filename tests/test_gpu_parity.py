@@ -1008,3 +1008,86 @@ def test_c4_full_size_fp32(ctx):
         ang = S.sin_theta_max(U[:, :cb], up.slab(V, b)[:, :cb])
         print(f"block {b} (n {n[b]}): sin angle {ang:.2e} (bar {_fp32_bar(lam, cb, pb):.1e})")
         assert ang <= _fp32_bar(lam, cb, pb), (b, ang, lam[cb] - lam[cb - 1])
+
+
+# ------------------------------------------------------------------ whole-mesh quality report
+
+def _quality_inputs(level, key):
+    v, f = M.icosphere(level)
+    X = M.displaced_sphere(v, M.rng_for(key, 0), 0.05).astype(np.float32)
+    Xr = (X + M.rng_for(key, 1).normal(scale=1e-3, size=X.shape)).astype(np.float32)
+    # face 0 collapsed to a point in the reconstruction: it and its neighbours
+    # across two collapsed corners have no normal there
+    Xr[f[0, 1]] = Xr[f[0, 0]]
+    Xr[f[0, 2]] = Xr[f[0, 0]]
+    return X, Xr, f
+
+
+def _quality_call(ctx, X, Xr, f):
+    n = X.shape[0]
+    fd = torch.from_numpy(np.ascontiguousarray(f.astype(np.int32).reshape(-1))).to("cuda:0")
+    Xd = torch.from_numpy(np.ascontiguousarray(X.reshape(-1))).to("cuda:0")
+    Xrd = torch.from_numpy(np.ascontiguousarray(Xr.reshape(-1))).to("cuda:0")
+    Lm = mis.mesh_laplacian(ctx, n, fd)
+    out = mis.mesh_quality(ctx, n, Lm.row_ptr, Lm.col, fd, Xd, Xrd)
+    torch.cuda.synchronize()
+    return out, (Lm, fd, Xd, Xrd)
+
+
+@pytest.mark.parametrize("level", [3, 7], ids=["small", "c2_full"])
+def test_mesh_quality_against_oracle(ctx, level):
+    """NMSVE (Eq. 16, original edge lengths in GL), its dB value, both norms
+    and the mean face-normal angle of a seeded perturbed icosphere against
+    the oracle (FP64 sums in another order: relative 1e-10; theta from acos
+    there, atan2 here); a repeated call is bitwise identical."""
+    X, Xr, f = _quality_inputs(level, 95)
+    n = X.shape[0]
+    out, args = _quality_call(ctx, X, Xr, f)
+    got = dict(zip(mis.QUALITY_FIELDS, out.cpu().numpy().tolist()))
+    X64, Xr64 = X.astype(np.float64), Xr.astype(np.float64)
+    e = lap.canonical_edges(f, n)
+    ref_nm = met.nmsve_mesh(n, e, X64, Xr64)
+    ref_th, ref_used = met.mean_normal_angle(f, X64, Xr64)
+    ref_gl = np.linalg.norm(met.gl_apply(n, e, X64, X64) - met.gl_apply(n, e, X64, Xr64))
+    assert got["bad_indices"] == 0 and got["zero_edges"] == 0
+    assert got["faces_used"] == ref_used and ref_used < f.shape[0]
+    assert abs(got["nmsve"] - ref_nm) <= 1e-10 * ref_nm
+    assert abs(got["nmsve_db"] - met.nmsve_db(ref_nm)) <= 1e-9
+    assert abs(got["l2"] - np.linalg.norm(X64 - Xr64)) <= 1e-10 * got["l2"]
+    assert abs(got["gl"] - ref_gl) <= 1e-10 * ref_gl
+    assert abs(got["theta_deg"] - ref_th) <= 1e-8 + 1e-10 * ref_th
+    Lm, fd, Xd, Xrd = args
+    again = mis.mesh_quality(ctx, n, Lm.row_ptr, Lm.col, fd, Xd, Xrd)
+    assert torch.equal(again, out)
+
+
+def test_mesh_quality_degenerate_inputs(ctx):
+    """A zero-length edge of the original mesh and an out-of-range face
+    index are counted and skipped (never read) and make the NMSVE and theta
+    NaN; the oracle rejects the zero-length edge too.  A reconstruction equal
+    to the mesh gives 0 (-inf dB) and theta 0; an empty mesh gives zeros."""
+    X, Xr, f = _quality_inputs(2, 96)
+    n = X.shape[0]
+    same, _ = _quality_call(ctx, X, X.copy(), f)
+    s = same.cpu().numpy()
+    assert s[0] == 0.0 and s[1] == -np.inf and s[4] == 0.0 and s[5] == f.shape[0]
+    Xz = X.copy()
+    a, b = int(f[3, 0]), int(f[3, 1])
+    Xz[b] = Xz[a]
+    with pytest.raises(lap.DegenerateError):
+        met.nmsve_mesh(n, lap.canonical_edges(f, n), Xz.astype(np.float64), Xr.astype(np.float64))
+    out, _ = _quality_call(ctx, Xz, Xr, f)
+    o = out.cpu().numpy()
+    assert o[6] == 2 and o[7] == 0 and np.isnan(o[0]) and np.isnan(o[1]) and np.isnan(o[4])
+    fb = f.copy()
+    fb[5, 2] = n
+    fd = torch.from_numpy(np.ascontiguousarray(fb.astype(np.int32).reshape(-1))).to("cuda:0")
+    Lm = mis.mesh_laplacian(ctx, n, torch.from_numpy(
+        np.ascontiguousarray(f.astype(np.int32).reshape(-1))).to("cuda:0"))
+    Xd = torch.from_numpy(np.ascontiguousarray(X.reshape(-1))).to("cuda:0")
+    Xrd = torch.from_numpy(np.ascontiguousarray(Xr.reshape(-1))).to("cuda:0")
+    o = mis.mesh_quality(ctx, n, Lm.row_ptr, Lm.col, fd, Xd, Xrd).cpu().numpy()
+    assert o[7] == 1 and o[6] == 0 and np.isnan(o[0]) and np.isnan(o[4])
+    empty = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    z = mis.mesh_quality(ctx, 0, empty, empty[:0], empty[:0], Xd[:0], Xrd[:0]).cpu().numpy()
+    assert z[0] == 0.0 and z[4] == 0.0 and z[5] == 0.0 and z[7] == 0.0

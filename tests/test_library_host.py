@@ -127,3 +127,11 @@ def test_params_struct_layout_matches_header():
     # 14 int32 fields, then the doubles at 8-byte alignment
     assert C.sizeof(L.MiOiParams) == 56 + 3 * 8
     assert L.MiOiParams.a_value.offset == 56 and L.MiOiParams.autotune.offset == 52
+
+
+def test_quality_report_argument_checks():
+    lib = L.lib()
+    out = (C.c_double * 8)()
+    assert lib.mi_mesh_quality(None, 10, None, None, 0, 0, None, None, None, out, None) == L.MI_ERR_ARG
+    assert b"NULL" in lib.mi_last_error()
+    assert mis.QUALITY_FIELDS[:2] == ("nmsve", "nmsve_db") and len(mis.QUALITY_FIELDS) == 8

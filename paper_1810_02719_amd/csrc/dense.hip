@@ -94,11 +94,49 @@ __global__ void __launch_bounds__(1024)
   const T* yv = Yin + d.off + lane * EPL;
   const int32_t* cb = col + c.nnz_off;
   const float* vb = val + c.nnz_off;
-  const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
-  T acc[EPL];
+  // the row's own terms first: their loads overlap the row pointer ->
+  // column -> neighbour chain of the gather (without a previous iterate the
+  // third term reads the current one with weight 0, so both loads are
+  // unconditional and issued here)
+  const int64_t o = d.off + int64_t(r) * d.ld + lane * EPL;
+  const T* yp = Yprev ? Yprev : Yin;
+  const T g3 = Yprev ? gamma : (T)0;
+  T yin[EPL], ypr[EPL];
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) acc[e] = (T)0;
-  for (int k = k0; k < k1; k += SPMM_GATHER) {
+  for (int e = 0; e < EPL; ++e) {
+    yin[e] = Yin[o + e];
+    ypr[e] = yp[o + e];
+  }
+  const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
+  T acc[EPL], base[EPL];
+  {
+    // first chunk of the row, unconditional (entries past the row gather the
+    // row itself with weight 0), so that the row's own terms are consumed
+    // in the same block and their loads stay ahead of the gather
+    T y[SPMM_GATHER][EPL];
+    T w[SPMM_GATHER];
+#pragma unroll
+    for (int u = 0; u < SPMM_GATHER; ++u) {
+      const bool in = k0 + u < k1;
+      w[u] = in ? (T)vb[k0 + u] : (T)0;
+      const T* src = yv + int64_t(in ? cb[k0 + u] : r) * d.ld;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) y[u][e] = src[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      base[e] = beta * yin[e] + g3 * ypr[e];
+      acc[e] = (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < SPMM_GATHER; ++u)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
+    // pin base here: otherwise the compiler sinks its loads past the loop
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(base[e]));
+  }
+  for (int k = k0 + SPMM_GATHER; k < k1; k += SPMM_GATHER) {
     T y[SPMM_GATHER][EPL];
     T w[SPMM_GATHER];
 #pragma unroll
@@ -114,14 +152,9 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
       for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
   }
-  const int64_t o = d.off + int64_t(r) * d.ld + lane * EPL;
   T out[EPL];
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) out[e] = alpha * acc[e] + beta * Yin[o + e];
-  if (Yprev) {
-#pragma unroll
-    for (int e = 0; e < EPL; ++e) out[e] += gamma * Yprev[o + e];
-  }
+  for (int e = 0; e < EPL; ++e) out[e] = alpha * acc[e] + base[e];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) Yout[o + e] = out[e];
 }

@@ -9,6 +9,9 @@ paper_oi        Algorithm 1 as the paper states it: U(t) = Onorm(R^z U(t-1)),
 paper_doi       Algorithm 2 (dynamic OI, Section 5) with the branch reading
                 of the text (grow c when the residual of Eq. 6 is above
                 eps_h, shrink when below eps_l), bounded iterations.
+doi_chebyshev   the same walk with the operator of the tracking path: each
+                iteration applies `passes` degree-m Chebyshev filters on a
+                fixed interval [a, b] in place of R^z, then Onorm.
 chebyshev_span  the exact subspace span(f(L)^T V0) reached by T outer
                 iterations that each apply the degree-m Chebyshev polynomial
                 of the first kind on the damped interval [a, b]; the
@@ -51,31 +54,61 @@ def paper_oi(L: np.ndarray, U0: np.ndarray, z: int, delta: float, t_max: int,
     return U
 
 
-def paper_doi(L: np.ndarray, U0: np.ndarray, X: np.ndarray, z: int, delta: float,
-              eps_l: float, eps_h: float, c_max: int, t_max: int = 200):
-    """Algorithm 2 (dynamic OI) with the text's branch reading: if ||e|| is
-    above eps_h append e/||e|| as a new column (Eq. 7) and re-orthonormalise;
-    if below eps_l drop the last column; stop when inside [eps_l, eps_h].
-    Returns (U, c, trajectory of (c, ||e||))."""
-    n = L.shape[0]
-    R = np.linalg.inv(L + delta * np.eye(n))
+def dynamic_oi(apply_op, U0: np.ndarray, X: np.ndarray, eps_l: float, eps_h: float,
+               c_max: int, t_max: int):
+    """Algorithm 2 (dynamic OI) with the text's branch reading, for an
+    operator apply_op (Y = op(U)): U(t) = Onorm(op(U(t-1))); e(t) of Eq. 6;
+    if ||e|| is above eps_h (and c < c_max) append e/||e|| as a new column
+    (Eq. 7), the next iteration's Onorm orthonormalises it; if below eps_l
+    (and c > 1) keep the first c - 1 columns; otherwise stop.  After t_max
+    iterations the walk stops where it is.  Returns (U, c, trajectory of
+    (c, ||e||) before each decision)."""
     U = U0.copy()
     traj = []
     for _ in range(t_max):
-        Y = U
-        for _ in range(z):
-            Y = R @ Y
-        U = householder_onorm(Y, U.shape[1])
+        U = householder_onorm(apply_op(U), U.shape[1])
         e = doi_residual(U, X)
         ne = float(np.linalg.norm(e))
         traj.append((U.shape[1], ne))
         if ne > eps_h and U.shape[1] < c_max and ne > 0:
-            U = householder_onorm(np.concatenate([U, (e / ne)[:, None]], axis=1), U.shape[1] + 1)
+            U = np.concatenate([U, (e / ne)[:, None]], axis=1)
         elif ne < eps_l and U.shape[1] > 1:
             U = U[:, :-1]
         else:
             break
     return U, U.shape[1], traj
+
+
+def paper_doi(L: np.ndarray, U0: np.ndarray, X: np.ndarray, z: int, delta: float,
+              eps_l: float, eps_h: float, c_max: int, t_max: int = 200):
+    """Algorithm 2 with the paper's operator R^z, R = (L + delta I)^-1.
+    The basis returned is orthonormal (a column appended by the last
+    decision is orthonormalised once more)."""
+    n = L.shape[0]
+    R = np.linalg.inv(L + delta * np.eye(n))
+
+    def op(U):
+        Y = U
+        for _ in range(z):
+            Y = R @ Y
+        return Y
+
+    U, c, traj = dynamic_oi(op, U0, X, eps_l, eps_h, c_max, t_max)
+    return householder_onorm(U, c), c, traj
+
+
+def doi_chebyshev(L: np.ndarray, U0: np.ndarray, X: np.ndarray, a: float, b: float, m: int,
+                  passes: int, eps_l: float, eps_h: float, c_max: int, t_max: int):
+    """Algorithm 2 with `passes` degree-m Chebyshev filters on the fixed
+    damped interval [a, b] as the operator (the tracking path's filter; a
+    re-orthonormalisation between passes does not change the span)."""
+    def op(U):
+        Y = U
+        for _ in range(passes):
+            Y = chebyshev_apply(L, Y, a, b, m)
+        return Y
+
+    return dynamic_oi(op, U0, X, eps_l, eps_h, c_max, t_max)
 
 
 def chebyshev_apply(L: np.ndarray, V: np.ndarray, a: float, b: float, m: int) -> np.ndarray:

@@ -396,6 +396,55 @@ class TestIterations:
         _, c2, _ = it.paper_doi(L, U[:, :30], X, 2, 1e-3, 1e9, 2e9, 40)
         assert c2 < 30
 
+    def _doi_case(self):
+        bs = W.grid_single(nx=9, ny=8, c=4, p=4)
+        X = bs.coords[0]
+        _, L = comb_L(bs.faces[0], 72)
+        lam, U = np.linalg.eigh(L)
+        return X, L, lam, U
+
+    def test_doi_chebyshev_first_decision_closed_form(self):
+        # an eigenvector start is invariant under the filter: the first
+        # residual is that of the exact eigenvectors (eigh, no filter code),
+        # the same for the paper's operator; inside the band the walk stops
+        X, L, lam, U = self._doi_case()
+        r6 = float(np.linalg.norm((X - U[:, :6] @ (U[:, :6].T @ X)).sum(1)))
+        Ud, c, traj = it.doi_chebyshev(L, U[:, :6], X, 0.5, 8.5, 6, 2, 0.9 * r6, 1.1 * r6, 20, 30)
+        assert c == 6 and len(traj) == 1 and traj[0][0] == 6
+        assert math.isclose(traj[0][1], r6, rel_tol=1e-9)
+        assert S.sin_theta_max(U[:, :6], Ud) < 1e-10
+        _, _, tp = it.paper_doi(L, U[:, :6], X, 2, 1e-3, 0.9 * r6, 1.1 * r6, 20, 30)
+        assert math.isclose(tp[0][1], r6, rel_tol=1e-9)
+
+    def test_doi_chebyshev_walks_to_the_limits(self):
+        X, L, lam, U = self._doi_case()
+        # always above the band: one column per iteration up to c_max, then stop
+        Ud, c, traj = it.doi_chebyshev(L, U[:, :3], X, 0.5, 8.5, 6, 2, 0.0, 0.0, 9, 30)
+        assert [t[0] for t in traj] == list(range(3, 10)) and c == 9
+        assert np.abs(Ud.T @ Ud - np.eye(9)).max() < 1e-12
+        # one iteration that grows: the new column is the normalised Eq. 6
+        # residual of the filtered basis, orthogonal to it (Eq. 7)
+        U1, c, traj = it.doi_chebyshev(L, U[:, :3], X, 0.5, 8.5, 6, 2, 0.0, 0.0, 9, 1)
+        e = (X - U1[:, :3] @ (U1[:, :3].T @ X)).sum(1)
+        assert c == 4 and np.allclose(U1[:, 3], e / np.linalg.norm(e), atol=1e-14)
+        assert np.abs(U1[:, :3].T @ U1[:, 3]).max() < 1e-12
+        # always below the band: one column fewer per iteration down to 1
+        _, c, traj = it.doi_chebyshev(L, U[:, :5], X, 0.5, 8.5, 6, 2, 1e9, 2e9, 9, 30)
+        assert [t[0] for t in traj] == [5, 4, 3, 2, 1] and c == 1
+        # no iteration: the start comes back
+        Ud, c, traj = it.doi_chebyshev(L, U[:, :5], X, 0.5, 8.5, 6, 2, 0.0, 1.0, 9, 0)
+        assert c == 5 and traj == [] and np.array_equal(Ud, U[:, :5])
+
+    def test_doi_chebyshev_stops_inside_the_band(self):
+        X, L, lam, U = self._doi_case()
+        target = float(np.linalg.norm(met.doi_residual(U[:, :14], X)))
+        Ud, c, traj = it.doi_chebyshev(L, U[:, :4], X, 1.0, 8.5, 8, 2, 0.5 * target,
+                                       1.01 * target, 40, 60)
+        assert c > 4 and traj[-1][0] == c
+        ne = float(np.linalg.norm(met.doi_residual(Ud, X)))
+        assert 0.5 * target <= ne <= 1.01 * target and math.isclose(ne, traj[-1][1], rel_tol=1e-12)
+        assert np.abs(Ud.T @ Ud - np.eye(c)).max() < 1e-12
+
 
 # ---------------------------------------------------------------- Section 4, iteration count
 

@@ -91,6 +91,33 @@ def merge_run(mis, ctx, W, dev, reps):
             "setup_s": gen_s}
 
 
+def doi_run(mis, ctx, blocks, L, coords, V0, dev, reps):
+    """The dynamic walk of Alg. 2 on the step's blocks (not part of the step):
+    start sizes 80, band [0.045, 0.065] of the Eq. 6 residual, c_max 190,
+    at most 60 iterations per block; the same filter as the step.  Time per
+    walk (eager launches) and the sizes it reaches."""
+    import torch
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED, m=10, passes=2, m0=10,
+                       passes0=2, adapt=1, a_mode=mis.MI_A_WEYL, a_value=1.0)
+    c0 = torch.full((blocks.n_blocks,), 80, dtype=torch.int32, device=dev)
+    args = (ctx, blocks, L, prm, coords, c0, 0.045, 0.065, 190, 60)
+    r = mis.doi_track(*args, V0=V0)  # plan
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        r = mis.doi_track(*args, V0=V0)
+    e1.record()
+    torch.cuda.synchronize()
+    c = r.c.cpu().numpy()
+    its = r.iters.cpu().numpy()
+    return {"workload": "icosphere7_100blocks, c0=80, band [0.045, 0.065], c_max=190, t_max=60",
+            "walk_ms": e0.elapsed_time(e1) / reps, "iters_mean": float(its.mean()),
+            "iters_max": int(its.max()), "c_mean": float(c.mean()), "c_min": int(c.min()),
+            "c_max": int(c.max()), "status_nonzero": int((r.status.cpu().numpy() != 0).sum())}
+
+
 def quality_run(mis, ctx, bs, blocks, L, coords, Xr, Xq, dev, reps):
     """Section 8 quality of the step's reconstruction on the whole mesh: the
     blocks' reconstructions placed at their mesh vertices (the merge, with
@@ -230,6 +257,7 @@ def main():
              "recon_rel_change": float((Xq - Xr).double().norm() / Xr.double().norm())}
     quality = quality_run(mis, ctx, bs, blocks, L, coords, Xr, Xq, dev,
                           reps=5 if args.profile_only else 50)
+    doi = None if args.profile_only else doi_run(mis, ctx, blocks, L, coords, V0, dev, reps=3)
 
     out = {
         "metric": "submesh vertices/sec (OI + project/recon) at principal angle <=1e-5 vs FP64 oracle",
@@ -252,12 +280,14 @@ def main():
         {"value": nverts / (per_block_ms * 1e-3), "unit": "vertices/s", "ms": per_block_ms},
         "roofline": roofline(ktimes, bs, blocks, L, prm),
         "roofline_spmm": roofline(ktimes, bs, blocks, L, prm, "spmm"),
+        "roofline_chol": roofline(ktimes, bs, blocks, L, prm, "chol"),
         "kernels": {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in ktimes.items() if v[1]},
         "launch_shapes": [list(t) for t in ctx.tuning()],
         "build_laplacian_ms": lap_ms,
         "merge": merge,
         "codec": codec,
         "quality": quality,
+        "doi": doi,
         "block_status_nonzero": int((st != 0).sum()),
         "input_gen_s": gen_s,
     }
@@ -273,19 +303,26 @@ def main():
 N_ROOTS = 3  # first blocks (cold starts); the rest are warm-started
 CALIB_BYTES = 256 << 20
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "spmm_row_icosphere7_b100_traffic.json")
-SPMM_SOURCE = os.path.join(HERE, "paper_1810_02719_amd", "csrc", "dense.hip")
+CSRC = os.path.join(HERE, "paper_1810_02719_amd", "csrc")
+TRAFFIC = {
+    "spmm": (os.path.join(HERE, "profiles", "spmm_row_icosphere7_b100_traffic.json"),
+             os.path.join(CSRC, "dense.hip")),
+    "chol": (os.path.join(HERE, "profiles", "chol_mfma_icosphere7_b100_traffic.json"),
+             os.path.join(CSRC, "chol.hip")),
+}
 
 
-def measured_traffic(alg_bytes_per_launch):
-    """HBM bytes per launch of the SpMM from the committed rocprofv3 counter
-    passes (FETCH_SIZE and WRITE_SIZE, scaled by the same counters of a copy
-    of known size), or None when the kernel source changed since or the
-    launches no longer have the size they had then."""
+def measured_traffic(kind, alg_bytes_per_launch):
+    """HBM bytes per launch of a kernel class ("spmm", "chol") from the
+    committed rocprofv3 counter passes (FETCH_SIZE and WRITE_SIZE, scaled by
+    the same counters of a copy of known size), or None when the kernel
+    source changed since or the launches no longer have the size they had
+    then."""
     import hashlib
+    path, source = TRAFFIC[kind]
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(SPMM_SOURCE, "rb").read()).hexdigest()
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != sha:
@@ -329,18 +366,25 @@ def roofline(ktimes, bs, blocks, L, prm, dom=None):
         out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot,
                    bytes_per_launch=tot / max(launches, 1))
         out["achieved"] = tot / (ms * 1e-3) / 1e9
-        out["traffic"] = measured_traffic(tot / max(launches, 1))
+        out["traffic"] = measured_traffic("spmm", tot / max(launches, 1))
     elif dom == "chol":
         # Cholesky (p^3/3) and triangular inverse (p^3/3) of every block's
-        # Gram, for each of the step's Cholesky-QRs
-        tot = 0
+        # Gram, for each of the step's Cholesky-QRs.  Bytes: the Gram's upper
+        # triangle read (FP64), R^-1 written in full (FP64, ld x ld) and, for
+        # all but the Rayleigh-Ritz factorisation, its FP32 copy
+        tot, byt = 0, 0
         for lvl in np.unique(levels):
             sel = levels == lvl
             T, passes = (prm.T0, prm.passes0) if lvl == 0 else (prm.T, prm.passes)
             nchol = T * passes + 1 + (1 if lvl > 0 else 0)  # + the warm start's
             tot += nchol * int((2 * p[sel].astype(np.float64) ** 3 / 3).sum())
-        out.update(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step=tot)
+            pp, ll = p[sel].astype(np.int64), ld[sel].astype(np.int64)
+            byt += int((nchol * 8 * pp * (pp + 1) // 2 + (nchol - 1) * 12 * ll * ll
+                        + 8 * ll * ll).sum())
+        out.update(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step=tot,
+                   bytes_per_launch=byt / max(launches, 1))
         out["achieved"] = tot / (ms * 1e-3) / 1e12
+        out["traffic"] = measured_traffic("chol", byt / max(launches, 1))
     elif dom == "eig_reduce":
         # Householder tridiagonalisation of every block's p x p Rayleigh-Ritz
         # matrix (4 p^3 / 3 flops), one per block and step

@@ -171,6 +171,7 @@ enum {
   MI_K_MERGE,          /* degree-weighted merge of overlapped submeshes */
   MI_K_QUANTIZE,       /* uniform quantisation of the feature vectors */
   MI_K_QUALITY,        /* whole-mesh NMSVE and face-normal angle */
+  MI_K_DOI,            /* decisions of the dynamic walk (Alg. 2) */
   MI_K_COUNT
 };
 /* Name of a kernel class ("spmm", ...), NULL when out of range. */
@@ -283,6 +284,50 @@ mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_p
                                 const int32_t* row_ptr, const int32_t* col, const float* val,
                                 const int64_t* nnz_off, const void* V0, void* V, double* ritz,
                                 int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- dynamic OI
+ * Section 5, Algorithm 2 (dynamic OI), with the branches as the text states
+ * them: every iteration U(t) = Onorm(F(L) U(t-1)), with F the tracking
+ * path's filter (`passes` Chebyshev passes of degree m on [a, b], as in
+ * mi_oi_track; no Rayleigh-Ritz step), then the Eq. 6 residual
+ *   e = sum over x, y, z of (v_j - U U^T v_j)      (v_j: the block's coordinates)
+ * decides: ||e|| > eps_h and c < min(c_max, p_b): append e/||e|| as column c
+ * (Eq. 7; the next Onorm orthonormalises it), c <- c + 1; ||e|| < eps_l and
+ * c > 1: drop column c - 1, c <- c - 1; otherwise stop.  A block stops at
+ * the latest after t_max iterations, with the last decision applied.
+ * Blocks run in waves as in mi_oi_track; under MI_WARM_PRED a block starts
+ * from its predecessor's final basis (index-aligned rows, re-orthonormalised)
+ * and final c, blocks without predecessor from V0 and their c on input.
+ * The active columns are the first c of the slab; the others are zero.
+ * X       device float [v_off[B]][3] block coordinates (Eq. 6's v).
+ * V0      start slabs as for mi_oi_track; must not alias V.
+ * V       device slabs out: the final bases (columns >= c_b zero).
+ * c       device int32 [B]: start sizes in (blocks without predecessor),
+ *         final sizes out.
+ * traj    device double [B][t_max][2]: (c, ||e||) before every decision,
+ *         (-1, -1) after the block stopped.
+ * iters   device int32 [B]: iterations run.
+ * status  device int32 [B] MI_BLOCK_* flags (MI_BLOCK_NOT_PD is cleared:
+ *         the zero columns read as rank deficiency).
+ * prm     as for mi_oi_track except that T, rr_every, eig, max_sweeps and
+ *         jacobi_tol are unused and a_mode MI_A_RITZ is rejected; with
+ *         adapt = 1, a follows the largest Rayleigh quotient of the basis.
+ * Every ld_b <= 1024.  Workspace from mi_doi_workspace_size (the tracking
+ * workspace plus one slab and B flags).  Runs eagerly on the stream (no
+ * graph); enqueue only. */
+typedef struct {
+  double eps_l, eps_h; /* band of ||e||_2, 0 <= eps_l <= eps_h                     */
+  int32_t c_max;       /* upper limit of c (with p_b)                             */
+  int32_t t_max;       /* iteration limit per block                               */
+} mi_doi_params;
+
+mi_status mi_doi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                                const mi_doi_params* dp, size_t* ws_bytes);
+mi_status mi_doi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                       const mi_doi_params* dp, const int32_t* row_ptr, const int32_t* col,
+                       const float* val, const int64_t* nnz_off, const float* X, const void* V0,
+                       void* V, int32_t* c, double* traj, int32_t* iters, int32_t* status,
+                       void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- Ritz residuals
  * Section 4 (how many iterations the orthogonal iteration needs): the

@@ -250,6 +250,40 @@ def oi_track(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, V0=
     return V, ritz, status
 
 
+class DoiResult:
+    """Output of doi_track: final bases V, sizes c, trajectory traj [B, t_max,
+    2] of (c, ||e||) before each decision ((-1, -1) after a block stopped),
+    iterations run and status flags (device tensors)."""
+
+    def __init__(self, V, c, traj, iters, status):
+        self.V, self.c, self.traj, self.iters, self.status = V, c, traj, iters, status
+
+
+def doi_track(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, X: torch.Tensor,
+              c0: torch.Tensor, eps_l: float, eps_h: float, c_max: int, t_max: int,
+              V0: torch.Tensor | None = None) -> DoiResult:
+    """Dynamic OI, Alg. 2 (mi_doi_track): X the block coordinates (FP32 [v_off[B]
+    * 3]); c0 int32 [B] start sizes of blocks without predecessor."""
+    lib = L.lib()
+    prm = params.struct()
+    dp = L.MiDoiParams(float(eps_l), float(eps_h), int(c_max), int(t_max))
+    dev = f"cuda:{ctx.device}"
+    V = torch.empty(int(blocks.u_off[-1]), dtype=_dtype(params.precision), device=dev)
+    c = c0.to(torch.int32).clone()
+    traj = torch.empty(max(blocks.n_blocks * int(t_max) * 2, 1), dtype=torch.float64, device=dev)
+    iters = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+    status = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+    ws_n = C.c_size_t()
+    L.check(lib.mi_doi_workspace_size(ctx.h, blocks.ref, C.byref(prm), C.byref(dp), C.byref(ws_n)))
+    ws = ctx.workspace("doi", ws_n.value)
+    L.check(lib.mi_doi_track(ctx.h, blocks.ref, C.byref(prm), C.byref(dp), _dptr(lap.row_ptr),
+                             _dptr(lap.col), _dptr(lap.val), _np_ptr(lap.nnz_off, C.c_int64),
+                             _dptr(X), _dptr(V0), _dptr(V), _dptr(c), _dptr(traj), _dptr(iters),
+                             _dptr(status), _dptr(ws), ws.numel(), _stream()))
+    return DoiResult(V, c, traj[:blocks.n_blocks * int(t_max) * 2].view(blocks.n_blocks, int(t_max), 2),
+                     iters, status)
+
+
 def ritz_residuals(ctx: Context, blocks: Blocks, lap: Laplacian, V: torch.Tensor,
                    ritz: torch.Tensor, precision: int = MI_FP32,
                    resid: torch.Tensor | None = None) -> torch.Tensor:

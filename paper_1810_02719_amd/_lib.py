@@ -42,7 +42,7 @@ MI_EIG_JACOBI = 1
 KERNEL_CLASSES = ["spmm", "gram", "gram_small", "gram_reduce", "chol", "rowmul", "rowmul_small",
                   "rq_max", "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish", "perm_cast",
                   "setup", "project", "reconstruct", "eig_reduce", "eig_values", "eig_vectors",
-                  "eig_back", "merge", "quantize", "quality"]
+                  "eig_back", "merge", "quantize", "quality", "doi"]
 MI_K_COUNT = len(KERNEL_CLASSES)
 
 MI_BLOCK_OK = 0
@@ -71,6 +71,11 @@ class MiOiParams(C.Structure):
                 ("b_abs", C.c_double), ("jacobi_tol", C.c_double)]
 
 
+class MiDoiParams(C.Structure):
+    _fields_ = [("eps_l", C.c_double), ("eps_h", C.c_double), ("c_max", C.c_int32),
+                ("t_max", C.c_int32)]
+
+
 _SIGS = {
     "mi_ctx_create": [C.POINTER(_vp), C.c_int32],
     "mi_ctx_destroy": [_vp],
@@ -87,6 +92,10 @@ _SIGS = {
     "mi_oi_tuning": [_vp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)],
     "mi_oi_track": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp, _i64p, _vp,
                     _vp, _vp, _vp, _vp, C.c_size_t, _vp],
+    "mi_doi_workspace_size": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams),
+                              C.POINTER(MiDoiParams), _szp],
+    "mi_doi_track": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), C.POINTER(MiDoiParams), _vp,
+                     _vp, _vp, _i64p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_oi_track_per_block": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp,
                               _i64p, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_residual_workspace_size": [_vp, C.POINTER(MiBlocks), _szp],

@@ -156,6 +156,7 @@ struct mi_ctx {
   int device = 0;
   // cached plan + captured graph for mi_oi_track (see oi.hip)
   void* oi_plan = nullptr;
+  void* doi_plan = nullptr;  // tracking plan of the dynamic walk (oi.hip)
   void* enc_plan = nullptr;
   void* cc_plan = nullptr;
   void* res_plan = nullptr;  // residual tile tables (see resid.hip)

@@ -144,6 +144,146 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ------------------------------------------------------------------ dynamic OI (Alg. 2)
+// The walk keeps c_b active columns at the front of the slab and zeros in
+// the others.  The tracking kernels then act on the active columns alone:
+// the filter maps zero columns to zero, and the Cholesky-QR of a basis with
+// trailing zero columns yields the Cholesky-QR of its leading c_b columns
+// (a Cholesky factor's leading block is the factor of the leading block;
+// the zero columns come out as zero).  Each step computes the Eq. 6
+// residual e = sum over x, y, z of (v - U U^T v) = s - U (U^T s), s_i =
+// x_i + y_i + z_i, in FP64, and appends e/||e|| (Eq. 7), drops the last
+// column, or stops; a stopped block's basis is frozen in a copy.
+constexpr int DOI_THREADS = 256;
+constexpr int DOI_CHUNK = 1024;   // rows of s staged in LDS at a time
+constexpr int DOI_MAX_LD = 1024;  // slab stride the step kernel supports
+
+// Start of the walk in the blocks of a wave: c_b is the predecessor's final
+// size (warm waves) or the caller's start size, clamped to [1, min(c_max,
+// p_b)]; columns >= c_b of the start basis are cleared; the trajectory is
+// reset to -1 and the block marked running.
+template <typename T>
+__global__ void __launch_bounds__(DOI_THREADS)
+    k_doi_init(const MatDesc* __restrict__ sets, const BlkInfo* __restrict__ info, int from_pred,
+               int c_max, int t_max, int32_t* __restrict__ c, int32_t* __restrict__ done,
+               double* __restrict__ traj, T* __restrict__ U) {
+  const MatDesc d = sets[blockIdx.x];
+  const int b = d.blk, pb = info[b].pred;
+  int cb = (from_pred && pb >= 0) ? c[pb] : c[b];
+  cb = max(1, min(cb, min(c_max, d.cols)));
+  for (int64_t e = threadIdx.x; e < int64_t(d.rows) * d.ld; e += DOI_THREADS)
+    if (int(e % d.ld) >= cb) U[d.off + e] = (T)0;
+  for (int i = threadIdx.x; i < 2 * t_max; i += DOI_THREADS) traj[2 * int64_t(b) * t_max + i] = -1.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c[b] = cb;
+    done[b] = 0;
+  }
+}
+
+// s_i = x_i + y_i + z_i of row i of a block (FP64)
+__device__ inline double doi_s(const float* xb, int i) {
+  return (double)xb[3 * i] + (double)xb[3 * i + 1] + (double)xb[3 * i + 2];
+}
+
+// e_i = s_i - sum_{j < cb} U_ij w_j for row i, one wavefront (lanes over j)
+template <typename T>
+__device__ inline double doi_e(const T* Ub, int ld, int cb, const double* w, const float* xb, int i,
+                               int lane) {
+  double acc = 0.0;
+  for (int j = lane; j < cb; j += 64) acc += (double)Ub[int64_t(i) * ld + j] * w[j];
+  return doi_s(xb, i) - wave_sum(acc);
+}
+
+// One decision of the walk per running block of a wave (one workgroup per
+// block): the Eq. 6 residual of the current basis, recorded with c; then
+// grow (||e|| > eps_h and c < min(c_max, p_b)), shrink (||e|| < eps_l and
+// c > 1) or stop.  A stopping block, or every block at the last iteration,
+// copies its basis into Vf.
+template <typename T>
+__global__ void __launch_bounds__(DOI_THREADS)
+    k_doi_step(const MatDesc* __restrict__ sets, const int64_t* __restrict__ v_off,
+               const float* __restrict__ X, T* __restrict__ U, T* __restrict__ Vf,
+               int32_t* __restrict__ c, int32_t* __restrict__ done, int32_t* __restrict__ iters,
+               double* __restrict__ traj, int t, int t_max, double eps_l, double eps_h, int c_max) {
+  __shared__ double s_rows[DOI_CHUNK];
+  __shared__ double w_col[DOI_MAX_LD];
+  __shared__ double red[DOI_THREADS / 64];
+  const MatDesc d = sets[blockIdx.x];
+  const int b = d.blk;
+  if (done[b]) return;  // uniform over the workgroup
+  const int cb = c[b], n = d.rows, ld = d.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const float* xb = X + 3 * v_off[b];
+  T* Ub = U + d.off;
+  // w = U^T s over the active columns (threads over columns, rows staged)
+  double wj[DOI_MAX_LD / DOI_THREADS];
+#pragma unroll
+  for (int q = 0; q < DOI_MAX_LD / DOI_THREADS; ++q) wj[q] = 0.0;
+  for (int r0 = 0; r0 < n; r0 += DOI_CHUNK) {
+    const int nr = min(DOI_CHUNK, n - r0);
+    __syncthreads();
+    for (int i = tid; i < nr; i += DOI_THREADS) s_rows[i] = doi_s(xb, r0 + i);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < DOI_MAX_LD / DOI_THREADS; ++q) {
+      const int j = tid + DOI_THREADS * q;
+      if (j < cb)
+        for (int i = 0; i < nr; ++i) wj[q] += (double)Ub[int64_t(r0 + i) * ld + j] * s_rows[i];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DOI_MAX_LD / DOI_THREADS; ++q) {
+    const int j = tid + DOI_THREADS * q;
+    if (j < DOI_MAX_LD) w_col[j] = j < cb ? wj[q] : 0.0;
+  }
+  __syncthreads();
+  // ||e||^2, rows over wavefronts
+  double ss = 0.0;
+  for (int i = wv; i < n; i += DOI_THREADS / 64) {
+    const double e = doi_e(Ub, ld, cb, w_col, xb, i, lane);
+    ss += e * e;
+  }
+  if (lane == 0) red[wv] = ss;
+  __syncthreads();
+  double tot = 0.0;
+  for (int k = 0; k < DOI_THREADS / 64; ++k) tot += red[k];
+  const double ne = sqrt(tot);
+  const int cmax_b = min(c_max, d.cols);
+  const int dec = (ne > eps_h && cb < cmax_b && ne > 0.0) ? 1 : (ne < eps_l && cb > 1) ? -1 : 0;
+  if (tid == 0) {
+    traj[(int64_t(b) * t_max + t) * 2] = (double)cb;
+    traj[(int64_t(b) * t_max + t) * 2 + 1] = ne;
+  }
+  if (dec == 1) {  // Eq. 7: the normalised residual becomes column cb
+    for (int i = wv; i < n; i += DOI_THREADS / 64) {
+      const double e = doi_e(Ub, ld, cb, w_col, xb, i, lane);
+      if (lane == 0) Ub[int64_t(i) * ld + cb] = (T)(e / ne);
+    }
+  } else if (dec == -1) {
+    for (int i = tid; i < n; i += DOI_THREADS) Ub[int64_t(i) * ld + cb - 1] = (T)0;
+  }
+  const bool stop = dec == 0 || t == t_max - 1;
+  if (stop) {
+    __syncthreads();  // the column update above before the copy
+    for (int64_t e = tid; e < int64_t(n) * ld; e += DOI_THREADS) Vf[d.off + e] = Ub[e];
+  }
+  if (tid == 0) {
+    c[b] = cb + dec;
+    if (stop) {
+      done[b] = 1;
+      iters[b] = t + 1;
+    }
+  }
+}
+
+// The factorisations of the walk see the zero columns as rank deficiency
+// and flag it; it is the walk's own layout, not a failure.
+__global__ void k_doi_status(int B, int32_t* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) status[b] &= ~MI_BLOCK_NOT_PD;
+}
+
 // ------------------------------------------------------------------ plan
 
 static int q_of(int p) { return (p + 1) & ~1; }
@@ -404,6 +544,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   put(blob, info, &offs);
   put(blob, all_tall, &offs);
   put(blob, all_csr, &offs);
+  put(blob, hb.v_off, &offs);
   for (auto& h : hosts) {
     put(blob, h.tall, &offs);
     put(blob, h.ptall, &offs);
@@ -425,6 +566,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   P->info = reinterpret_cast<BlkInfo*>(base + offs[k++]);
   P->all_tall = reinterpret_cast<MatDesc*>(base + offs[k++]);
   P->all_csr = reinterpret_cast<CsrDesc*>(base + offs[k++]);
+  P->v_off = reinterpret_cast<int64_t*>(base + offs[k++]);
   for (size_t w = 0; w < waves.size(); ++w) {
     WaveTables& wt = P->waves[w];
     WaveHost& h = hosts[w];
@@ -579,6 +721,9 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   const T* V0 = static_cast<const T*>(a.V0);
   const int B = P.hb.B;
   const OiRecord* rec = a.rec;
+  const DoiArgs* doi = a.doi;
+  T* Vf = doi ? reinterpret_cast<T*>(ws + doi->off_vf) : nullptr;
+  int32_t* doi_done = doi ? reinterpret_cast<int32_t*>(ws + doi->off_done) : nullptr;
   const size_t slab_bytes = size_t(P.hb.u_off[B]) * sizeof(T);
   const size_t mats = size_t(P.hb.m_off[B]);
   auto keep = [&](void* dst, const void* src, size_t bytes) {
@@ -631,6 +776,18 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       }
       X = V;
     }
+    if (doi) {
+      // the walk edits its basis in place: roots start from a copy of V0
+      if (!w.from_pred) {
+        KScope k_(a.tm, MI_K_SETUP, s);
+        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+      }
+      X = V;
+      KScope k_(a.tm, MI_K_DOI, s);
+      hipLaunchKernelGGL(k_doi_init<T>, dim3(w.nb), dim3(DOI_THREADS), 0, s, w.tall, P.info,
+                         w.from_pred ? 1 : 0, doi->c_max, doi->t_max, doi->c, doi_done, doi->traj,
+                         V);
+    }
     int xslab = -1;  // slab holding X (-1: X lives in V0 / V)
     auto chol = [&](float* s32) {
       KScope k_(a.tm, MI_K_CHOL, s);
@@ -659,9 +816,10 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       X = slab[0];
       xslab = 0;
     }
-    for (int t = 0; t < w.T; ++t) {
-      const bool last = t == w.T - 1;
-      const bool rr_now = last || prm.rr_every;
+    const int n_iter = doi ? doi->t_max : w.T;
+    for (int t = 0; t < n_iter; ++t) {
+      const bool last = !doi && t == w.T - 1;
+      const bool rr_now = !doi && (last || prm.rr_every);
       int ycur = -1;
       for (int pass = 0; pass < w.passes; ++pass) {
         {
@@ -757,6 +915,12 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         }
         X = V;
         xslab = -1;
+        if (doi) {
+          KScope k_(a.tm, MI_K_DOI, s);
+          hipLaunchKernelGGL(k_doi_step<T>, dim3(w.nb), dim3(DOI_THREADS), 0, s, w.tall, P.v_off,
+                             doi->X, V, Vf, doi->c, doi_done, doi->iters, doi->traj, t, doi->t_max,
+                             doi->eps_l, doi->eps_h, doi->c_max);
+        }
         continue;
       }
       // Rayleigh-Ritz: A = Rinv^T H Rinv = Z Theta Z^T,  V = Y Rinv Z
@@ -879,11 +1043,21 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         }
       }
     }
-    if (w.T == 0 && !w.from_pred)
-      {
+    if (doi) {
+      // the frozen bases become the wave's output (and the next waves' start)
+      if (doi->t_max > 0) {
         KScope k_(a.tm, MI_K_SETUP, s);
-        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                           (const T*)Vf, V);
       }
+    } else if (w.T == 0 && !w.from_pred) {
+      KScope k_(a.tm, MI_K_SETUP, s);
+      hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+    }
+  }
+  if (doi) {
+    KScope k_(a.tm, MI_K_DOI, s_main);
+    hipLaunchKernelGGL(k_doi_status, dim3(ceil_div(B, 256)), dim3(256), 0, s_main, B, a.status);
   }
   if (fork) {
     for (int l = 0; l < P.n_lanes; ++l) {
@@ -1075,6 +1249,27 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
   return MI_OK;
 }
 
+// Workspace of the walk: the plan's layout, then the frozen bases (one slab)
+// and the stop flags.
+static void doi_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t* off_vf,
+                       size_t* off_done, size_t* total) {
+  const size_t es = prm.precision == MI_FP64 ? 8 : 4;
+  *off_vf = align_up(oi_ws_bytes(hb, prm));
+  *off_done = *off_vf + align_up(size_t(hb.u_off[hb.B]) * es);
+  *total = *off_done + align_up(size_t(std::max(hb.B, 1)) * sizeof(int32_t));
+}
+
+static mi_status doi_check(const HostBlocks& hb, const mi_oi_params* prm, const mi_doi_params* dp) {
+  MI_CHECK_ARG(dp != nullptr, "walk parameters are NULL");
+  MI_CHECK_ARG(dp->eps_l >= 0 && dp->eps_h >= dp->eps_l, "need 0 <= eps_l <= eps_h");
+  MI_CHECK_ARG(dp->t_max >= 0 && dp->t_max <= 10000, "t_max %d out of range", dp->t_max);
+  MI_CHECK_ARG(dp->c_max >= 1, "c_max must be >= 1");
+  MI_CHECK_ARG(prm->a_mode != MI_A_RITZ, "the walk takes no Ritz values: a_mode RITZ unsupported");
+  for (int b = 0; b < hb.B; ++b)
+    MI_CHECK_ARG(hb.ld[b] <= DOI_MAX_LD, "block %d: ld %d above %d", b, hb.ld[b], DOI_MAX_LD);
+  return MI_OK;
+}
+
 }  // namespace mis
 
 using namespace mis;
@@ -1084,6 +1279,8 @@ extern "C" {
 void mis_destroy_oi_plan(mi_ctx* ctx) {
   delete static_cast<OiPlan*>(ctx->oi_plan);
   ctx->oi_plan = nullptr;
+  delete static_cast<OiPlan*>(ctx->doi_plan);
+  ctx->doi_plan = nullptr;
   delete static_cast<OiPlan*>(ctx->adj_oi);
   ctx->adj_oi = nullptr;
 }
@@ -1126,6 +1323,79 @@ mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm
                       int32_t* status, void* ws, size_t ws_bytes, void* stream) {
   return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, status, ws, ws_bytes,
                 stream, false);
+}
+
+mi_status mi_doi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                                const mi_doi_params* dp, size_t* ws_bytes) {
+  clear_error();
+  (void)ctx;
+  MI_CHECK_ARG(ws_bytes != nullptr, "ws_bytes is NULL");
+  mi_status st = check_params(prm);
+  if (st) return st;
+  HostBlocks hb;
+  st = load_blocks(blk, &hb, true);
+  if (st) return st;
+  st = doi_check(hb, prm, dp);
+  if (st) return st;
+  std::vector<std::vector<int>> waves;
+  std::vector<int> level;
+  st = build_waves(hb, *prm, false, &waves, &level);
+  if (st) return st;
+  size_t a, b;
+  doi_layout(hb, *prm, &a, &b, ws_bytes);
+  return MI_OK;
+}
+
+mi_status mi_doi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
+                       const mi_doi_params* dp, const int32_t* row_ptr, const int32_t* col,
+                       const float* val, const int64_t* nnz_off, const float* X, const void* V0,
+                       void* V, int32_t* c, double* traj, int32_t* iters, int32_t* status,
+                       void* ws, size_t ws_bytes, void* stream) {
+  begin_call();
+  MI_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  mi_status st = check_params(prm);
+  if (st) return st;
+  HostBlocks hb;
+  st = load_blocks(blk, &hb, true);
+  if (st) return st;
+  st = doi_check(hb, prm, dp);
+  if (st) return st;
+  MI_CHECK_ARG(row_ptr && col && val && nnz_off && X && V && c && iters && status,
+               "NULL argument");
+  MI_CHECK_ARG(dp->t_max == 0 || traj, "traj is required when t_max > 0");
+  bool needs_v0 = prm->warm == MI_WARM_GIVEN;
+  for (int b = 0; b < hb.B; ++b) needs_v0 = needs_v0 || hb.pred[b] < 0;
+  MI_CHECK_ARG(!needs_v0 || V0 != nullptr, "V0 is required");
+  MI_CHECK_ARG(V0 != V, "V0 and V must not alias (the walk edits V in place)");
+  size_t off_vf, off_done, need;
+  doi_layout(hb, *prm, &off_vf, &off_done, &need);
+  MI_CHECK_ARG(ws && ws_bytes >= need, "workspace %zu bytes < %zu required", ws_bytes, need);
+  std::vector<int64_t> nnz(nnz_off, nnz_off + hb.B + 1);
+  MI_TRY_HIP(hipSetDevice(ctx->device));
+  std::vector<const void*> ptrs = {row_ptr, col, val, V0, V, nullptr, status, ws};
+  OiPlan* P = nullptr;
+  st = get_plan(ctx, &ctx->doi_plan, hb, nnz, *prm, ptrs, ws, ws_bytes, false, &P);
+  if (st) return st;
+  DoiArgs d;
+  d.X = X;
+  d.c = c;
+  d.traj = traj;
+  d.iters = iters;
+  d.eps_l = dp->eps_l;
+  d.eps_h = dp->eps_h;
+  d.c_max = dp->c_max;
+  d.t_max = dp->t_max;
+  d.off_vf = off_vf;
+  d.off_done = off_done;
+  Args a{row_ptr, col, val, V0, V, nullptr, status, static_cast<char*>(ws), ctx->timer, nullptr,
+         false, &d};
+  hipStream_t s = (hipStream_t)stream;
+  if (prm->precision == MI_FP64)
+    enqueue<double>(*P, a, s);
+  else
+    enqueue<float>(*P, a, s);
+  MI_TRY_HIP(hipGetLastError());
+  return MI_OK;
 }
 
 mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,

@@ -72,6 +72,7 @@ struct OiPlan {
   WsLayout L;
   void* arena = nullptr;
   BlkInfo* info = nullptr;
+  int64_t* v_off = nullptr;  // first vertex row of every block [B + 1]
   MatDesc* all_tall = nullptr;
   CsrDesc* all_csr = nullptr;
   int lds_max = 65536;
@@ -108,6 +109,19 @@ struct OiRecord {
   int npass = 0;
 };
 
+// The dynamic walk of Alg. 2 (mi_doi_track): the iteration count and the
+// band of the Eq. 6 residual, the caller's buffers, and the workspace
+// beyond the plan's own layout (frozen bases, stop flags).
+struct DoiArgs {
+  const float* X = nullptr;  // block coordinates [v_off[B]][3]
+  int32_t* c = nullptr;      // [B] start size in, final size out
+  double* traj = nullptr;    // [B][t_max][2]: (c, ||e||) before each decision
+  int32_t* iters = nullptr;  // [B] iterations run
+  double eps_l = 0, eps_h = 0;
+  int c_max = 0, t_max = 0;
+  size_t off_vf = 0, off_done = 0;  // workspace offsets
+};
+
 struct Args {
   const int32_t* row_ptr;
   const int32_t* col;
@@ -120,6 +134,7 @@ struct Args {
   KTimer* tm;
   const OiRecord* rec;  // checkpoints to write (eager runs only), or null
   bool fork;            // run the plan's lanes on its lane streams (graph capture)
+  const DoiArgs* doi = nullptr;  // the walk of Alg. 2 instead of fixed iterations
 };
 
 // Runs the tracking eagerly on `s` with the plan held in *slot (created or

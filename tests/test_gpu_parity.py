@@ -1091,3 +1091,152 @@ def test_mesh_quality_degenerate_inputs(ctx):
     empty = torch.zeros(1, dtype=torch.int32, device="cuda:0")
     z = mis.mesh_quality(ctx, 0, empty, empty[:0], empty[:0], Xd[:0], Xrd[:0]).cpu().numpy()
     assert z[0] == 0.0 and z[4] == 0.0 and z[5] == 0.0 and z[7] == 0.0
+
+
+# ------------------------------------------------------------------ dynamic OI (Alg. 2)
+
+DOI_SMALL = dict(a=1.5, b=12.0, m=6, passes=2, eps_l=0.3, eps_h=0.58, c0=6, c_max=28, t_max=40)
+
+
+def _doi_oracle_chain(up, cfg, order):
+    """The oracle's walk for every block in level order: roots from their
+    seeded start, the others from the oracle's own final basis of the
+    predecessor (rows index-aligned, re-orthonormalised) and its final c.
+    The filter's lower end follows the tracking rule a_b = a_pred n_pred / n_b."""
+    bs = up.bs
+    starts = W.random_starts(bs)
+    res, a_of = {}, {}
+    for b in order:
+        L, _, _ = oracle_block(up, b, k=1)
+        X = up.X32(b)
+        n, p = X.shape[0], int(bs.p[b])
+        cmax_b = min(cfg["c_max"], p)
+        pb = int(bs.pred[b])
+        if pb < 0:
+            a_of[b] = cfg["a"]
+            c = max(1, min(cfg["c0"], cmax_b))
+            U0 = starts[b][:, :c]
+        else:
+            a_of[b] = a_of[pb] * int(bs.n[pb]) / n
+            Up, cp = res[pb][0], res[pb][1]
+            c = max(1, min(cp, cmax_b))
+            A = np.zeros((n, c))
+            k = min(n, Up.shape[0])
+            A[:k] = Up[:k, :c]
+            U0 = it.householder_onorm(A, c)
+        U, cf, traj = it.doi_chebyshev(L, U0, X, a_of[b], cfg["b"], cfg["m"], cfg["passes"],
+                                      cfg["eps_l"], cfg["eps_h"], cmax_b, cfg["t_max"])
+        res[b] = (it.householder_onorm(U, cf), cf, traj)
+    return res
+
+
+def _doi_run(ctx, up, cfg, precision):
+    prm = mis.OiParams(precision=precision, warm=mis.MI_WARM_PRED, m=cfg["m"], passes=cfg["passes"],
+                       m0=cfg["m"], passes0=cfg["passes"], adapt=0, a_mode=mis.MI_A_ABS,
+                       a_value=cfg["a"], b_abs=cfg["b"])
+    c0 = torch.full((up.blocks.n_blocks,), cfg["c0"], dtype=torch.int32, device="cuda:0")
+    V0 = up.starts(torch.float64 if precision == mis.MI_FP64 else torch.float32)
+    r = mis.doi_track(ctx, up.blocks, up.laplacian(ctx), prm, up.coords, c0, cfg["eps_l"],
+                      cfg["eps_h"], cfg["c_max"], cfg["t_max"], V0=V0)
+    torch.cuda.synchronize()
+    return r
+
+
+@pytest.mark.parametrize("precision", [mis.MI_FP64, mis.MI_FP32], ids=["fp64", "fp32"])
+def test_doi_against_oracle(ctx, precision):
+    """Alg. 2 on eight warm-started icosphere blocks (p = 32): every block's
+    sequence of sizes and stop iteration equal to the oracle's walk, the
+    Eq. 6 residuals before each decision and the final subspace within the
+    precision's tolerance; columns beyond c are zero.  The band is checked to
+    leave every decision clear of the thresholds."""
+    cfg = DOI_SMALL
+    bs = W.icosphere_blocks(level=4, n_blocks=8, c=cfg["c0"], p=32)
+    up = Uploaded(bs)
+    order = sorted(range(bs.n_blocks), key=lambda b: int(bs.level[b]))
+    ref = _doi_oracle_chain(up, cfg, order)
+    r = _doi_run(ctx, up, cfg, precision)
+    tol_ne, tol_ang = (1e-9, 1e-9) if precision == mis.MI_FP64 else (2e-4, 2e-4)
+    c_g = r.c.cpu().numpy()
+    it_g = r.iters.cpu().numpy()
+    traj = r.traj.cpu().numpy()
+    assert (r.status.cpu().numpy() == 0).all()
+    grew = 0
+    for b in order:
+        U, cf, tr = ref[b]
+        for cc, ne in tr:  # decisions well inside the tolerance
+            assert min(abs(ne - cfg["eps_l"]), abs(ne - cfg["eps_h"])) > 100 * tol_ne * ne, (b, ne)
+        assert it_g[b] == len(tr) and c_g[b] == cf, (b, it_g[b], len(tr), c_g[b], cf)
+        assert np.array_equal(traj[b, :len(tr), 0], [t[0] for t in tr])
+        assert np.allclose(traj[b, :len(tr), 1], [t[1] for t in tr], rtol=tol_ne, atol=0)
+        assert (traj[b, len(tr):] == -1).all()
+        Vb = up.slab(r.V, b)
+        assert S.sin_theta_max(U, Vb[:, :cf]) < tol_ang, b
+        assert (Vb[:, cf:] == 0).all()
+        grew += cf > cfg["c0"]
+    assert grew >= 4  # the band makes most walks grow
+
+
+def test_doi_limits_and_errors(ctx):
+    """eps_h = 0: a root grows one column per iteration to c_max and stops
+    there; a block that starts at c_max (its predecessor's size) stops after
+    one iteration.  Invalid bands, Ritz-based a and aliased buffers are
+    argument errors."""
+    cfg = dict(DOI_SMALL, eps_l=0.0, eps_h=0.0, c_max=12, t_max=20)
+    bs = W.icosphere_blocks(level=4, n_blocks=8, c=cfg["c0"], p=32)
+    up = Uploaded(bs)
+    r = _doi_run(ctx, up, cfg, mis.MI_FP32)
+    c_g, it_g = r.c.cpu().numpy(), r.iters.cpu().numpy()
+    for b in range(bs.n_blocks):
+        assert c_g[b] == 12
+        assert it_g[b] == (12 - cfg["c0"] + 1 if bs.pred[b] < 0 else 1), (b, it_g[b])
+    prm = mis.OiParams(precision=mis.MI_FP32, a_mode=mis.MI_A_RITZ)
+    c0 = torch.full((bs.n_blocks,), 4, dtype=torch.int32, device="cuda:0")
+    V0 = up.starts(torch.float32)
+    Lp = up.laplacian(ctx)
+    for kw in (dict(eps_l=0.5, eps_h=0.1, prm=mis.OiParams(precision=mis.MI_FP32)),
+               dict(eps_l=0.1, eps_h=0.5, prm=prm)):
+        with pytest.raises(mis.MiError) as ei:
+            mis.doi_track(ctx, up.blocks, Lp, kw["prm"], up.coords, c0, kw["eps_l"], kw["eps_h"], 8, 5,
+                          V0=V0)
+        assert ei.value.code == mis._lib.MI_ERR_ARG
+
+
+def test_doi_full_size_walk_rules(ctx):
+    """The walk on the 100 blocks of the icosphere workload (p = 192, FP32,
+    adaptive filter bound): every recorded decision follows the rule, the
+    final sizes are the last decision applied, the kept columns are
+    orthonormal and the rest zero, and a stopped block's recorded residual
+    is the residual of its output basis (recomputed in FP64)."""
+    bs = W.icosphere_blocks(level=7, n_blocks=100, c=80, p=192, n_roots=3)
+    up = Uploaded(bs)
+    eps_l, eps_h, c_max, t_max = 0.045, 0.065, 190, 60
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_PRED)
+    c0 = torch.full((bs.n_blocks,), 80, dtype=torch.int32, device="cuda:0")
+    r = mis.doi_track(ctx, up.blocks, up.laplacian(ctx), prm, up.coords, c0, eps_l, eps_h, c_max,
+                      t_max, V0=up.starts(torch.float32))
+    torch.cuda.synchronize()
+    assert (r.status.cpu().numpy() == 0).all()
+    c_g, it_g, traj = r.c.cpu().numpy(), r.iters.cpu().numpy(), r.traj.cpu().numpy()
+    moved = 0
+    for b in range(bs.n_blocks):
+        k = int(it_g[b])
+        assert 1 <= k <= t_max and (traj[b, k:] == -1).all()
+        cmax_b = min(c_max, int(bs.p[b]))
+        for t in range(k):
+            cc, ne = int(traj[b, t, 0]), traj[b, t, 1]
+            dec = 1 if (ne > eps_h and cc < cmax_b) else (-1 if (ne < eps_l and cc > 1) else 0)
+            if t < k - 1:
+                assert dec != 0 and int(traj[b, t + 1, 0]) == cc + dec, (b, t)
+            else:
+                assert (dec == 0) or k == t_max, (b, t)
+                assert c_g[b] == cc + dec
+        moved += k > 1
+        Vb = up.slab(r.V, b)
+        cb = int(c_g[b])
+        assert np.abs(Vb[:, :cb].T @ Vb[:, :cb] - np.eye(cb)).max() < 1e-4, b
+        assert (Vb[:, cb:] == 0).all()
+        if k < t_max:
+            X = up.X32(b)
+            e = met.doi_residual(Vb[:, :cb], X)
+            assert abs(np.linalg.norm(e) - traj[b, k - 1, 1]) < 1e-4 * traj[b, k - 1, 1], b
+    assert moved >= 50

@@ -314,7 +314,9 @@ mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_p
  *         adapt = 1, a follows the largest Rayleigh quotient of the basis.
  * Every ld_b <= 1024.  Workspace from mi_doi_workspace_size (the tracking
  * workspace plus one slab and B flags).  Runs eagerly on the stream (no
- * graph); enqueue only. */
+ * graph) and synchronises it after every iteration to read the stop flags:
+ * a wave ends as soon as all its blocks have stopped.  Returns when the
+ * walk is complete. */
 typedef struct {
   double eps_l, eps_h; /* band of ||e||_2, 0 <= eps_l <= eps_h                     */
   int32_t c_max;       /* upper limit of c (with p_b)                             */

@@ -817,7 +817,8 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       xslab = 0;
     }
     const int n_iter = doi ? doi->t_max : w.T;
-    for (int t = 0; t < n_iter; ++t) {
+    bool wave_stopped = false;
+    for (int t = 0; t < n_iter && !wave_stopped; ++t) {
       const bool last = !doi && t == w.T - 1;
       const bool rr_now = !doi && (last || prm.rr_every);
       int ycur = -1;
@@ -920,6 +921,16 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           hipLaunchKernelGGL(k_doi_step<T>, dim3(w.nb), dim3(DOI_THREADS), 0, s, w.tall, P.v_off,
                              doi->X, V, Vf, doi->c, doi_done, doi->iters, doi->traj, t, doi->t_max,
                              doi->eps_l, doi->eps_h, doi->c_max);
+        }
+        if (doi && doi->host_done) {
+          // the walk runs eagerly: once every block of the wave has stopped,
+          // the remaining iterations are skipped
+          (void)hipMemcpyAsync(doi->host_done, doi_done, size_t(B) * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s);
+          (void)hipStreamSynchronize(s);
+          bool all = true;
+          for (const MatDesc& d : w.tall_host) all = all && doi->host_done[d.blk] != 0;
+          wave_stopped = all;
         }
         continue;
       }
@@ -1387,6 +1398,7 @@ mi_status mi_doi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* pr
   d.t_max = dp->t_max;
   d.off_vf = off_vf;
   d.off_done = off_done;
+  MI_TRY_HIP(hipHostMalloc((void**)&d.host_done, size_t(std::max(hb.B, 1)) * sizeof(int32_t)));
   Args a{row_ptr, col, val, V0, V, nullptr, status, static_cast<char*>(ws), ctx->timer, nullptr,
          false, &d};
   hipStream_t s = (hipStream_t)stream;
@@ -1394,7 +1406,13 @@ mi_status mi_doi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* pr
     enqueue<double>(*P, a, s);
   else
     enqueue<float>(*P, a, s);
-  MI_TRY_HIP(hipGetLastError());
+  const hipError_t e = hipGetLastError();
+  (void)hipStreamSynchronize(s);  // the last read of host_done is complete
+  (void)hipHostFree(d.host_done);
+  if (e != hipSuccess) {
+    set_error("HIP: %s", hipGetErrorString(e));
+    return MI_ERR_HIP;
+  }
   return MI_OK;
 }
 

@@ -120,6 +120,7 @@ struct DoiArgs {
   double eps_l = 0, eps_h = 0;
   int c_max = 0, t_max = 0;
   size_t off_vf = 0, off_done = 0;  // workspace offsets
+  int32_t* host_done = nullptr;     // pinned copy of the stop flags [B] (early exit)
 };
 
 struct Args {

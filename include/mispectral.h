@@ -126,7 +126,22 @@ typedef struct {
   double b_abs;      /* > 0: upper filter bound b for every block; else Gershgorin     */
   double jacobi_tol; /* off-diagonal threshold relative to ||A||_F on the last
                         iteration (e.g. 1e-14); earlier ones use max(tol, 1e-8)      */
+  int32_t op;        /* operator of a filter pass: MI_OP_CHEB (the Chebyshev filter
+                        above) or MI_OP_RZ: R^z = (L + delta I)^-z, Section 4's
+                        operator, applied as z linear solves, each by cg_iters
+                        iterations of column-wise conjugate gradients (FP64
+                        scalars and column sums, reproducible) from a zero
+                        start; each filter pass applies R^z, m only numbers
+                        the coefficient slots then (m >= 1), and the
+                        adjoint (mi_encdec_adjoint) rejects it            */
+  int32_t z;         /* power of R (MI_OP_RZ), 1..16                               */
+  int32_t cg_iters;  /* conjugate-gradient iterations per solve (MI_OP_RZ)         */
+  int32_t pad_;
+  double delta;      /* shift of R (MI_OP_RZ), > 0                                  */
 } mi_oi_params;
+
+#define MI_OP_CHEB 0
+#define MI_OP_RZ 1
 
 #define MI_A_WEYL 0
 #define MI_A_ABS 1
@@ -172,6 +187,7 @@ enum {
   MI_K_QUANTIZE,       /* uniform quantisation of the feature vectors */
   MI_K_QUALITY,        /* whole-mesh NMSVE and face-normal angle */
   MI_K_DOI,            /* decisions of the dynamic walk (Alg. 2) */
+  MI_K_CG,             /* conjugate-gradient updates of R^z */
   MI_K_COUNT
 };
 /* Name of a kernel class ("spmm", ...), NULL when out of range. */

@@ -25,6 +25,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
+from ._lib import MI_OP_CHEB, MI_OP_RZ  # noqa: F401
 from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_FP32, MI_FP64, MI_W_COMBINATORIAL,  # noqa: F401
                    MI_W_INV_DIST, MI_W_INV_SQ_DIST, MI_W_USER, MI_WARM_GIVEN, MI_WARM_PRED,
                    MiError)
@@ -215,11 +216,16 @@ class OiParams:
     rr_every: int = 0
     eig: int = 0  # MI_EIG_TRIDIAG (Jacobi for ld > 192) or MI_EIG_JACOBI
     autotune: int = 0  # 1: time candidate launch shapes when the plan is made
+    op: int = 0  # MI_OP_CHEB (Chebyshev filter) or MI_OP_RZ ((L + delta I)^-z by CG)
+    z: int = 1
+    cg_iters: int = 200
+    delta: float = 1e-3
 
     def struct(self):
         return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
                             self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, self.rr_every,
-                            self.eig, self.autotune, self.a_value, self.b_abs, self.jacobi_tol)
+                            self.eig, self.autotune, self.a_value, self.b_abs, self.jacobi_tol,
+                            self.op, self.z, self.cg_iters, 0, self.delta)
 
 
 def _dtype(precision):

@@ -39,10 +39,13 @@ MI_A_RITZ = 2
 MI_EIG_TRIDIAG = 0
 MI_EIG_JACOBI = 1
 
+MI_OP_CHEB = 0
+MI_OP_RZ = 1
+
 KERNEL_CLASSES = ["spmm", "gram", "gram_small", "gram_reduce", "chol", "rowmul", "rowmul_small",
                   "rq_max", "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish", "perm_cast",
                   "setup", "project", "reconstruct", "eig_reduce", "eig_values", "eig_vectors",
-                  "eig_back", "merge", "quantize", "quality", "doi"]
+                  "eig_back", "merge", "quantize", "quality", "doi", "cg"]
 MI_K_COUNT = len(KERNEL_CLASSES)
 
 MI_BLOCK_OK = 0
@@ -68,7 +71,9 @@ class MiOiParams(C.Structure):
                 ("passes0", C.c_int32), ("adapt", C.c_int32), ("max_sweeps", C.c_int32),
                 ("a_mode", C.c_int32), ("rr_every", C.c_int32), ("eig", C.c_int32),
                 ("autotune", C.c_int32), ("a_value", C.c_double),
-                ("b_abs", C.c_double), ("jacobi_tol", C.c_double)]
+                ("b_abs", C.c_double), ("jacobi_tol", C.c_double), ("op", C.c_int32),
+                ("z", C.c_int32), ("cg_iters", C.c_int32), ("pad_", C.c_int32),
+                ("delta", C.c_double)]
 
 
 class MiDoiParams(C.Structure):

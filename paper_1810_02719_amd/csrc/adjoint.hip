@@ -585,6 +585,7 @@ static mi_status adj_check(const mi_oi_params* prm, const HostBlocks& hb) {
   mi_status st = oi_check_params(prm);
   if (st) return st;
   MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN, "the adjoint needs warm = MI_WARM_GIVEN");
+  MI_CHECK_ARG(prm->op == MI_OP_CHEB, "the adjoint differentiates the Chebyshev filter only");
   MI_CHECK_ARG(prm->adapt == 0 && prm->rr_every == 0,
                "the adjoint needs a fixed filter interval (adapt = 0, rr_every = 0)");
   MI_CHECK_ARG(prm->eig == MI_EIG_TRIDIAG, "the adjoint needs eig = MI_EIG_TRIDIAG");

@@ -144,6 +144,136 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ------------------------------------------------------------------ R^z (Section 4)
+// The paper's operator R^z = (L + delta I)^-z, applied as z solves with
+// (L + delta I), each by a fixed number of conjugate-gradient iterations on
+// every column of the block at once (the columns are independent systems):
+//   x = 0, r = p = b;  q = (L + delta I) p;  alpha = r.r / p.q;
+//   x += alpha p;  r -= alpha q;  beta = r.r(new) / r.r(old);  p = r + beta p.
+// q comes from the SpMM with the coefficients (1, delta, 0).  The other
+// steps run over the SpMM's 16-row tiles (one wavefront per tile and 64
+// columns); every column reduction is written as per-tile FP64 partials and
+// summed by the consumer in tile order, so results are reproducible and
+// the stream lanes never share a partial (slots are numbered per block).
+constexpr int CG_COLS = 64;
+
+// Coefficient rows of R^z: slot 0 = (1, delta, 0) for q = (L + delta I) p,
+// slot m = (1, 0, 0) for the Rayleigh-Ritz product W = L Y.
+__global__ void k_rz_coef(const MatDesc* __restrict__ sets, int nsets, double delta,
+                          double* __restrict__ coef, int stride, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsets) return;
+  double* cf = coef + int64_t(sets[i].blk) * stride;
+  cf[0] = 1.0;
+  cf[1] = delta;
+  cf[2] = 0.0;
+  cf[3 * m] = 1.0;
+  cf[3 * m + 1] = 0.0;
+  cf[3 * m + 2] = 0.0;
+}
+
+// Column j's sum over the block's tile partials (tile order).
+__device__ inline double cg_sum(const double* __restrict__ part, int64_t base, int ntiles, int ldp,
+                                int j) {
+  double s = 0.0;
+  for (int k = 0; k < ntiles; ++k) s += part[(base + k) * ldp + j];
+  return s;
+}
+
+// Start of a solve: r = p = b, x = 0, partials of r.r.  b may be x itself
+// (the previous solve's result): every element is read before it is cleared.
+template <typename T>
+__global__ void __launch_bounds__(64)
+    k_cg_start(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+               const int64_t* __restrict__ tile_base, int ldp, const T* b, T* x,
+               T* __restrict__ r, T* __restrict__ p, double* __restrict__ partR) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int j = blockIdx.y * CG_COLS + threadIdx.x;
+  if (j >= d.ld) return;
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  double s = 0.0;
+  for (int i = 0; i < rows; ++i) {
+    const int64_t o = d.off + int64_t(t.row0 + i) * d.ld + j;
+    const T v = b[o];
+    r[o] = v;
+    p[o] = v;
+    x[o] = (T)0;
+    s += (double)v * (double)v;
+  }
+  partR[(tile_base[d.blk] + t.row0 / SPMM_ROWS) * ldp + j] = s;
+}
+
+// p.q partials of every tile (after q = (L + delta I) p).
+template <typename T>
+__global__ void __launch_bounds__(64)
+    k_cg_pq(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+            const int64_t* __restrict__ tile_base, int ldp, const T* __restrict__ p,
+            const T* __restrict__ q, double* __restrict__ partP) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int j = blockIdx.y * CG_COLS + threadIdx.x;
+  if (j >= d.ld) return;
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  double s = 0.0;
+  for (int i = 0; i < rows; ++i) {
+    const int64_t o = d.off + int64_t(t.row0 + i) * d.ld + j;
+    s += (double)p[o] * (double)q[o];
+  }
+  partP[(tile_base[d.blk] + t.row0 / SPMM_ROWS) * ldp + j] = s;
+}
+
+// x += alpha p, r -= alpha q with alpha = r.r / p.q, and the partials of the
+// new r.r (into the other buffer).
+template <typename T>
+__global__ void __launch_bounds__(64)
+    k_cg_xr(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+            const int64_t* __restrict__ tile_base, int ldp, T* __restrict__ x, T* __restrict__ r,
+            const T* __restrict__ p, const T* __restrict__ q, const double* __restrict__ partP,
+            const double* __restrict__ partR, double* __restrict__ partR2) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int j = blockIdx.y * CG_COLS + threadIdx.x;
+  if (j >= d.ld) return;
+  const int nt = (d.rows + SPMM_ROWS - 1) / SPMM_ROWS;
+  const int64_t base = tile_base[d.blk];
+  const double pq = cg_sum(partP, base, nt, ldp, j);
+  const double rr = cg_sum(partR, base, nt, ldp, j);
+  const double alpha = (j < d.cols && pq > 0.0) ? rr / pq : 0.0;
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  double s = 0.0;
+  for (int i = 0; i < rows; ++i) {
+    const int64_t o = d.off + int64_t(t.row0 + i) * d.ld + j;
+    x[o] = (T)((double)x[o] + alpha * (double)p[o]);
+    const double rn = (double)r[o] - alpha * (double)q[o];
+    r[o] = (T)rn;
+    s += rn * rn;
+  }
+  partR2[(base + t.row0 / SPMM_ROWS) * ldp + j] = s;
+}
+
+// p = r + beta p with beta = r.r(new) / r.r(old).
+template <typename T>
+__global__ void __launch_bounds__(64)
+    k_cg_p(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+           const int64_t* __restrict__ tile_base, int ldp, const T* __restrict__ r,
+           T* __restrict__ p, const double* __restrict__ partR, const double* __restrict__ partR2) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int j = blockIdx.y * CG_COLS + threadIdx.x;
+  if (j >= d.ld) return;
+  const int nt = (d.rows + SPMM_ROWS - 1) / SPMM_ROWS;
+  const int64_t base = tile_base[d.blk];
+  const double r0 = cg_sum(partR, base, nt, ldp, j);
+  const double r1 = cg_sum(partR2, base, nt, ldp, j);
+  const double beta = (j < d.cols && r0 > 0.0) ? r1 / r0 : 0.0;
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  for (int i = 0; i < rows; ++i) {
+    const int64_t o = d.off + int64_t(t.row0 + i) * d.ld + j;
+    p[o] = (T)((double)r[o] + beta * (double)p[o]);
+  }
+}
+
 // ------------------------------------------------------------------ dynamic OI (Alg. 2)
 // The walk keeps c_b active columns at the front of the slab and zeros in
 // the others.  The tracking kernels then act on the active columns alone:
@@ -407,6 +537,16 @@ static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t 
   L.coef_stride = 3 * (mmax + 1);
   L.coef = c.used, c.take<double>(size_t(hb.B) * L.coef_stride);
   L.conv = c.used, c.take<int32_t>(hb.B);
+  // R^z: per-tile column partials (p.q and two generations of r.r)
+  int64_t tiles = 0;
+  L.cg_ldp = 0;
+  for (int b = 0; b < hb.B; ++b) {
+    tiles += (hb.v_off[b + 1] - hb.v_off[b] + SPMM_ROWS - 1) / SPMM_ROWS;
+    L.cg_ldp = std::max(L.cg_ldp, hb.ld[b]);
+  }
+  L.cg_tiles = tiles;
+  L.cg_part = c.used;
+  if (prm.op == MI_OP_RZ) c.take<double>(3 * size_t(tiles) * L.cg_ldp);
   L.total = c.used;
   return L;
 }
@@ -545,6 +685,10 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   put(blob, all_tall, &offs);
   put(blob, all_csr, &offs);
   put(blob, hb.v_off, &offs);
+  std::vector<int64_t> tile_base(hb.B + 1, 0);
+  for (int b = 0; b < hb.B; ++b)
+    tile_base[b + 1] = tile_base[b] + (hb.v_off[b + 1] - hb.v_off[b] + SPMM_ROWS - 1) / SPMM_ROWS;
+  put(blob, tile_base, &offs);
   for (auto& h : hosts) {
     put(blob, h.tall, &offs);
     put(blob, h.ptall, &offs);
@@ -567,6 +711,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   P->all_tall = reinterpret_cast<MatDesc*>(base + offs[k++]);
   P->all_csr = reinterpret_cast<CsrDesc*>(base + offs[k++]);
   P->v_off = reinterpret_cast<int64_t*>(base + offs[k++]);
+  P->tile_base = reinterpret_cast<int64_t*>(base + offs[k++]);
   for (size_t w = 0; w < waves.size(); ++w) {
     WaveTables& wt = P->waves[w];
     WaveHost& h = hosts[w];
@@ -825,8 +970,12 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       for (int pass = 0; pass < w.passes; ++pass) {
         {
           KScope k_(a.tm, MI_K_SETUP, s);
-          hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
-                             a_lo, b_hi, coef, L.coef_stride, w.m);
+          if (prm.op == MI_OP_RZ)
+            hipLaunchKernelGGL(k_rz_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,
+                               prm.delta, coef, L.coef_stride, w.m);
+          else
+            hipLaunchKernelGGL(k_cheb_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall,
+                               w.nb, a_lo, b_hi, coef, L.coef_stride, w.m);
         }
         if (rec) {
           if (jp == 0) keep(rec->coef, coef, size_t(B) * L.coef_stride * sizeof(double));
@@ -835,9 +984,54 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         int free_s[3], nf = 0;
         for (int i = 0; i < 4 && nf < 3; ++i)
           if (i != xslab) free_s[nf++] = i;
+        if (prm.op == MI_OP_RZ) {
+          // Y = R^z X: x, r, p in the free slabs; q in X's slab once the first
+          // solve has read X (or in the fourth slab when X is outside them)
+          int q_s = xslab;
+          if (q_s < 0)
+            for (int i = 0; i < 4; ++i)
+              if (i != free_s[0] && i != free_s[1] && i != free_s[2]) q_s = i;
+          T* xs = slab[free_s[0]];
+          T* rs = slab[free_s[1]];
+          T* ps = slab[free_s[2]];
+          T* qs = slab[q_s];
+          const size_t plane = size_t(L.cg_tiles) * L.cg_ldp;
+          double* cgp = reinterpret_cast<double*>(ws + L.cg_part);
+          double* partP = cgp;
+          double* partR[2] = {cgp + plane, cgp + 2 * plane};
+          const dim3 cg_grid(w.n_spmm, ceil_div(w.max_ld, CG_COLS));
+          const int ldp = L.cg_ldp;
+          for (int zz = 0; zz < prm.z; ++zz) {
+            {
+              KScope k_(a.tm, MI_K_CG, s);
+              hipLaunchKernelGGL(k_cg_start<T>, cg_grid, dim3(CG_COLS), 0, s, w.spmm, w.tall,
+                                 P.tile_base, ldp, zz == 0 ? X : (const T*)xs, xs, rs, ps,
+                                 partR[0]);
+            }
+            for (int it = 0; it < prm.cg_iters; ++it) {
+              double* r_old = partR[it & 1];
+              double* r_new = partR[(it + 1) & 1];
+              {
+                KScope k_(a.tm, MI_K_SPMM, s);
+                launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, ps,
+                               nullptr, qs, coef, L.coef_stride, 0, s, w.epl);
+              }
+              KScope k_(a.tm, MI_K_CG, s);
+              hipLaunchKernelGGL(k_cg_pq<T>, cg_grid, dim3(CG_COLS), 0, s, w.spmm, w.tall,
+                                 P.tile_base, ldp, (const T*)ps, (const T*)qs, partP);
+              hipLaunchKernelGGL(k_cg_xr<T>, cg_grid, dim3(CG_COLS), 0, s, w.spmm, w.tall,
+                                 P.tile_base, ldp, xs, rs, (const T*)ps, (const T*)qs,
+                                 (const double*)partP, (const double*)r_old, r_new);
+              hipLaunchKernelGGL(k_cg_p<T>, cg_grid, dim3(CG_COLS), 0, s, w.spmm, w.tall,
+                                 P.tile_base, ldp, (const T*)rs, ps, (const double*)r_old,
+                                 (const double*)r_new);
+            }
+          }
+          ycur = free_s[0];
+        }
         const T* prev = nullptr;
         const T* cur = X;
-        for (int k = 0; k < w.m; ++k) {
+        for (int k = 0; k < (prm.op == MI_OP_RZ ? 0 : w.m); ++k) {
           T* out = slab[free_s[k % 3]];
           {
             KScope k_(a.tm, MI_K_SPMM, s);
@@ -1102,6 +1296,12 @@ static mi_status check_params(const mi_oi_params* prm) {
                prm->eig);
   MI_CHECK_ARG(prm->jacobi_tol > 0 && prm->jacobi_tol < 1e-3, "jacobi_tol out of range");
   MI_CHECK_ARG(prm->autotune == 0 || prm->autotune == 1, "autotune must be 0 or 1");
+  MI_CHECK_ARG(prm->op == MI_OP_CHEB || prm->op == MI_OP_RZ, "operator %d unknown", prm->op);
+  if (prm->op == MI_OP_RZ) {
+    MI_CHECK_ARG(prm->z >= 1 && prm->z <= 16, "z %d outside [1, 16]", prm->z);
+    MI_CHECK_ARG(prm->cg_iters >= 1 && prm->cg_iters <= 100000, "cg_iters out of range");
+    MI_CHECK_ARG(prm->delta > 0, "delta must be > 0");
+  }
   return MI_OK;
 }
 

@@ -47,6 +47,9 @@ struct WaveTables {
 struct WsLayout {
   size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, tri, part, a_lo, b_hi, coef,
       conv;
+  size_t cg_part;    // R^z: three tile-partial buffers [tiles][cg_ldp] (0 without R^z)
+  int cg_ldp = 0;    // largest ld (row stride of the partials)
+  int64_t cg_tiles = 0;  // 16-row tiles of all blocks
   size_t part_lane;  // Gram partial doubles of one stream lane
   size_t total;
   int coef_stride;
@@ -73,6 +76,7 @@ struct OiPlan {
   void* arena = nullptr;
   BlkInfo* info = nullptr;
   int64_t* v_off = nullptr;  // first vertex row of every block [B + 1]
+  int64_t* tile_base = nullptr;  // first 16-row tile of every block [B + 1]
   MatDesc* all_tall = nullptr;
   CsrDesc* all_csr = nullptr;
   int lds_max = 65536;

@@ -124,9 +124,10 @@ def test_residual_and_adjoint_workspace_queries():
 
 
 def test_params_struct_layout_matches_header():
-    # 14 int32 fields, then the doubles at 8-byte alignment
-    assert C.sizeof(L.MiOiParams) == 56 + 3 * 8
+    # 14 int32 fields, 3 doubles, 4 int32 (operator fields), delta
+    assert C.sizeof(L.MiOiParams) == 56 + 3 * 8 + 16 + 8
     assert L.MiOiParams.a_value.offset == 56 and L.MiOiParams.autotune.offset == 52
+    assert L.MiOiParams.op.offset == 80 and L.MiOiParams.delta.offset == 96
 
 
 def test_quality_report_argument_checks():
@@ -135,3 +136,11 @@ def test_quality_report_argument_checks():
     assert lib.mi_mesh_quality(None, 10, None, None, 0, 0, None, None, None, out, None) == L.MI_ERR_ARG
     assert b"NULL" in lib.mi_last_error()
     assert mis.QUALITY_FIELDS[:2] == ("nmsve", "nmsve_db") and len(mis.QUALITY_FIELDS) == 8
+
+
+def test_rz_operator_params():
+    b = mis.Blocks([100], p=[10])
+    assert _oi_ws(b, mis.OiParams(op=mis.MI_OP_RZ))[0] == 0
+    for kw in (dict(op=2), dict(op=mis.MI_OP_RZ, z=0), dict(op=mis.MI_OP_RZ, z=17),
+               dict(op=mis.MI_OP_RZ, cg_iters=0), dict(op=mis.MI_OP_RZ, delta=0.0)):
+        assert _oi_ws(b, mis.OiParams(**kw))[0] == L.MI_ERR_ARG, kw

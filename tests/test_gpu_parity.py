@@ -1281,3 +1281,45 @@ def test_rz_operator_against_oracle(ctx):
         a2 = S.sin_theta_max(Vb, U[:, :8])
         a13 = S.sin_theta_max(up.slab(V13, b)[:, :16], U[:, :8])
         assert a2 < a13, (b, a2, a13)
+
+
+def test_doi_with_rz_against_paper_walk(ctx):
+    """The fully literal dynamic OI: Alg. 2 with the paper's operator R^z
+    (z = 2, delta = 1e-3, conjugate gradients, FP64) on the eight warm-started
+    blocks, against the oracle's walk with the dense inverse: the same sizes
+    and stop iterations, residuals to 1e-8 and final subspaces to 1e-8."""
+    eps_l, eps_h, c0, c_max, t_max = 0.25, 0.5, 6, 28, 40
+    bs = W.icosphere_blocks(level=4, n_blocks=8, c=c0, p=32)
+    up = Uploaded(bs)
+    order = sorted(range(bs.n_blocks), key=lambda b: int(bs.level[b]))
+    starts = W.random_starts(bs)
+    ref = {}
+    for b in order:
+        L, _, _ = oracle_block(up, b, k=1)
+        X = up.X32(b)
+        n, pb = X.shape[0], int(bs.pred[b])
+        if pb < 0:
+            c, U0 = c0, starts[b][:, :c0]
+        else:
+            Up, c = ref[pb][0], min(ref[pb][1], c_max)
+            A = np.zeros((n, c))
+            k = min(n, Up.shape[0])
+            A[:k] = Up[:k, :c]
+            U0 = it.householder_onorm(A, c)
+        ref[b] = it.paper_doi(L, U0, X, 2, 1e-3, eps_l, eps_h, min(c_max, 32), t_max)
+    prm = mis.OiParams(precision=mis.MI_FP64, warm=mis.MI_WARM_PRED, m=1, passes=1, m0=1, passes0=1,
+                       adapt=0, op=mis.MI_OP_RZ, z=2, cg_iters=400, delta=1e-3)
+    c0t = torch.full((bs.n_blocks,), c0, dtype=torch.int32, device="cuda:0")
+    r = mis.doi_track(ctx, up.blocks, up.laplacian(ctx), prm, up.coords, c0t, eps_l, eps_h, c_max,
+                      t_max, V0=up.starts(torch.float64))
+    torch.cuda.synchronize()
+    assert (r.status.cpu().numpy() == 0).all()
+    c_g, it_g, traj = r.c.cpu().numpy(), r.iters.cpu().numpy(), r.traj.cpu().numpy()
+    for b in order:
+        U, cf, tr = ref[b]
+        for _, ne in tr:
+            assert min(abs(ne - eps_l), abs(ne - eps_h)) > 1e-4 * ne, (b, ne)
+        assert it_g[b] == len(tr) and c_g[b] == cf, (b, it_g[b], len(tr), c_g[b], cf)
+        assert np.array_equal(traj[b, :len(tr), 0], [t[0] for t in tr])
+        assert np.allclose(traj[b, :len(tr), 1], [t[1] for t in tr], rtol=1e-8, atol=0)
+        assert S.sin_theta_max(U, up.slab(r.V, b)[:, :cf]) < 1e-8, b

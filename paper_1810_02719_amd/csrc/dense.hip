@@ -159,6 +159,105 @@ __global__ void __launch_bounds__(1024)
   for (int e = 0; e < EPL; ++e) Yout[o + e] = out[e];
 }
 
+// The same product with two rows per wavefront: both rows' loads are in
+// flight together, so a launch holds twice the rows per wavefront slot.
+template <typename T, int EPL>
+__global__ void __launch_bounds__(512)
+    k_spmm_row2(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val,
+                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int ti = (blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
+  if (ti >= ntiles) return;
+  const SpmmTile t = tiles[ti];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MatDesc d = sets[t.set];
+  const int ra = t.row0 + 2 * wave;
+  if (ra >= d.rows) return;  // wave-uniform
+  const bool two = ra + 1 < d.rows;
+  const int rw[2] = {ra, two ? ra + 1 : ra};
+  const CsrDesc c = csr[t.set];
+  const int lane = threadIdx.x & 63;
+  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+  const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
+  const T* yv = Yin + d.off + lane * EPL;
+  const int32_t* cb = col + c.nnz_off;
+  const float* vb = val + c.nnz_off;
+  const T* yp = Yprev ? Yprev : Yin;
+  const T g3 = Yprev ? gamma : (T)0;
+  int64_t o[2];
+  T yin[2][EPL], ypr[2][EPL];
+  int k0[2], k1[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    o[h] = d.off + int64_t(rw[h]) * d.ld + lane * EPL;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      yin[h][e] = Yin[o[h] + e];
+      ypr[h][e] = yp[o[h] + e];
+    }
+    k0[h] = row_ptr[c.rp_off + rw[h]];
+    k1[h] = row_ptr[c.rp_off + rw[h] + 1];
+  }
+  T acc[2][EPL], base[2][EPL];
+  {
+    // first chunk of both rows (entries past a row gather the row itself
+    // with weight 0)
+    T y[2][SPMM_GATHER][EPL];
+    T w[2][SPMM_GATHER];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < SPMM_GATHER; ++u) {
+        const bool in = k0[h] + u < k1[h];
+        w[h][u] = in ? (T)vb[k0[h] + u] : (T)0;
+        const T* src = yv + int64_t(in ? cb[k0[h] + u] : rw[h]) * d.ld;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) y[h][u][e] = src[e];
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        base[h][e] = beta * yin[h][e] + g3 * ypr[h][e];
+        acc[h][e] = (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < SPMM_GATHER; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[h][e] = fma(w[h][u], y[h][u][e], acc[h][e]);
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(base[h][e]));
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    for (int k = k0[h] + SPMM_GATHER; k < k1[h]; k += SPMM_GATHER) {
+      T y[SPMM_GATHER][EPL];
+      T w[SPMM_GATHER];
+#pragma unroll
+      for (int u = 0; u < SPMM_GATHER; ++u) {
+        const int kk = min(k + u, k1[h] - 1);
+        w[u] = k + u < k1[h] ? (T)vb[kk] : (T)0;
+        const T* src = yv + int64_t(cb[kk]) * d.ld;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) y[u][e] = src[e];
+      }
+#pragma unroll
+      for (int u = 0; u < SPMM_GATHER; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[h][e] = fma(w[u], y[u][e], acc[h][e]);
+    }
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) Yout[o[0] + e] = alpha * acc[0][e] + base[0][e];
+  if (two) {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) Yout[o[1] + e] = alpha * acc[1][e] + base[1][e];
+  }
+}
+
 template <typename T>
 void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
                  const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
@@ -171,6 +270,12 @@ void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const C
                        dim3(64 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin,     \
                        Yprev, Yout, coef, coef_stride, step, ntiles);                            \
     return;
+  if (epl == 3) {
+    hipLaunchKernelGGL((k_spmm_row2<T, 3>), dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)),
+                       dim3(32 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin, Yprev,
+                       Yout, coef, coef_stride, step, ntiles);
+    return;
+  }
   switch (epl) {
     MI_SPMM_ROW(1)
     MI_SPMM_ROW(2)

@@ -968,7 +968,9 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       const bool rr_now = !doi && (last || prm.rr_every);
       int ycur = -1;
       for (int pass = 0; pass < w.passes; ++pass) {
-        {
+        // the interval [a, b] changes only at the end of an iteration: the
+        // first pass's coefficients serve every pass of the iteration
+        if (pass == 0) {
           KScope k_(a.tm, MI_K_SETUP, s);
           if (prm.op == MI_OP_RZ)
             hipLaunchKernelGGL(k_rz_coef, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb,

@@ -316,6 +316,9 @@ def main():
         "roofline": roofline(ktimes, bs, blocks, L, prm),
         "roofline_spmm": roofline(ktimes, bs, blocks, L, prm, "spmm"),
         "roofline_chol": roofline(ktimes, bs, blocks, L, prm, "chol"),
+        "roofline_gram": roofline(ktimes, bs, blocks, L, prm, "gram"),
+        "roofline_project": roofline(ktimes, bs, blocks, L, prm, "project"),
+        "roofline_reconstruct": roofline(ktimes, bs, blocks, L, prm, "reconstruct"),
         "kernels": {k: {"ms": round(v[0], 4), "launches": v[1]} for k, v in ktimes.items() if v[1]},
         "launch_shapes": [list(t) for t in ctx.tuning()],
         "build_laplacian_ms": lap_ms,
@@ -439,6 +442,14 @@ def roofline(ktimes, bs, blocks, L, prm, dom=None):
             tot += (single + 2 * T) * per
         out.update(bound="mfma", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step=tot)
         out["achieved"] = tot / (ms * 1e-3) / 1e12
+    elif dom in ("project", "reconstruct"):
+        # per row: the first c_b entries of the basis row (FP32) and the
+        # row's coordinates (project: read; reconstruct: written)
+        c = np.asarray(bs.c, np.int64)
+        tot = int((n * (es * c + 12)).sum())
+        out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot,
+                   bytes_per_launch=tot / max(launches, 1))
+        out["achieved"] = tot / (ms * 1e-3) / 1e9
     elif dom == "jacobi_sweep":
         # sweeps run until convergence: the work is data dependent; count the
         # minimum, one full sweep per block and Rayleigh-Ritz (3 q^2 (q-1)

@@ -12,11 +12,17 @@
 
 namespace mis {
 
-constexpr int PROJ_CHUNKS = 8;  // row ranges per block of the projection sums
+constexpr int PROJ_CHUNKS = 16;  // row ranges per block of the projection sums
+constexpr int ENC_TILE = 64;     // rows per workgroup of the reconstruction
+constexpr int ENC_KPL = 4;       // columns per lane of the tiled kernels (ld <= 256)
 
 struct EncBlock {
   int64_t v_off, u_off, t_off;
   int32_t n, p, ld, pad;
+};
+
+struct EncTile {
+  int32_t blk, row0;
 };
 
 struct EncPlan {
@@ -25,10 +31,14 @@ struct EncPlan {
   EncBlock* dev = nullptr;
   int64_t* dev_voff = nullptr;
   int64_t* dev_poff = nullptr;  // per-block offset of the projection partials
+  EncTile* tiles = nullptr;     // ENC_TILE-row tiles of every block
+  int n_tiles = 0;
+  int max_ld = 0;
   ~EncPlan() {
     if (dev) (void)hipFree(dev);
     if (dev_voff) (void)hipFree(dev_voff);
     if (dev_poff) (void)hipFree(dev_poff);
+    if (tiles) (void)hipFree(tiles);
   }
 };
 
@@ -61,13 +71,23 @@ static mi_status enc_plan(mi_ctx* ctx, const HostBlocks& hb, EncPlan** out) {
                     hb.p[b], hb.ld[b], 0};
   std::vector<int64_t> poff;
   proj_part_doubles(hb, &poff);
+  std::vector<EncTile> tiles;
+  for (int b = 0; b < hb.B; ++b) {
+    P->max_ld = std::max(P->max_ld, hb.ld[b]);
+    for (int r0 = 0; r0 < h[b].n; r0 += ENC_TILE) tiles.push_back(EncTile{b, r0});
+  }
+  P->n_tiles = (int)tiles.size();
   if (hipMalloc(&P->dev, hb.B * sizeof(EncBlock)) != hipSuccess ||
       hipMalloc(&P->dev_voff, (hb.B + 1) * sizeof(int64_t)) != hipSuccess ||
-      hipMalloc(&P->dev_poff, hb.B * sizeof(int64_t)) != hipSuccess) {
+      hipMalloc(&P->dev_poff, hb.B * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&P->tiles, std::max<size_t>(tiles.size(), 1) * sizeof(EncTile)) != hipSuccess) {
     delete P;
     set_error("device allocation for the block table failed");
     return MI_ERR_HIP;
   }
+  if (!tiles.empty())
+    MI_TRY_HIP(hipMemcpy(P->tiles, tiles.data(), tiles.size() * sizeof(EncTile),
+                         hipMemcpyHostToDevice));
   MI_TRY_HIP(hipMemcpy(P->dev, h.data(), hb.B * sizeof(EncBlock), hipMemcpyHostToDevice));
   MI_TRY_HIP(hipMemcpy(P->dev_voff, hb.v_off.data(), (hb.B + 1) * sizeof(int64_t),
                        hipMemcpyHostToDevice));
@@ -137,6 +157,134 @@ __global__ void __launch_bounds__(256)
     double v = 0.0;
     for (int ch = 0; ch < PROJ_CHUNKS; ++ch) v += pb[int64_t(ch) * b.ld * 3 + e];
     E[3 * b.t_off + e] = (e / 3 < c) ? (T)v : (T)0;
+  }
+}
+
+// The same projection for ld <= 256 with every wavefront busy: the four
+// wavefronts of a workgroup take every fourth row of the chunk, lanes the
+// columns k = lane + 64 s; the wavefronts' sums meet in LDS and are added in
+// wavefront order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_project_part_w(const EncBlock* __restrict__ blks, const int64_t* __restrict__ poff,
+                     const int32_t* __restrict__ cvec, const T* __restrict__ U,
+                     const T* __restrict__ X, double* __restrict__ part) {
+  __shared__ double red[4][64 * ENC_KPL][3];
+  const EncBlock b = blks[blockIdx.x];
+  const int chunk = blockIdx.y;
+  const int c = min(max(cvec[blockIdx.x], 0), b.p);
+  const int rows_per = (b.n + PROJ_CHUNKS - 1) / PROJ_CHUNKS;
+  const int r0 = chunk * rows_per, r1 = min(b.n, r0 + rows_per);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[ENC_KPL][3];
+#pragma unroll
+  for (int s = 0; s < ENC_KPL; ++s) acc[s][0] = acc[s][1] = acc[s][2] = 0.0;
+  const T* Ub = U + b.u_off;
+  const T* Xb = X + 3 * b.v_off;
+  // four rows of the wavefront per batch, every load unconditional (a row
+  // past the chunk reads the first row with weight 0, a column past c reads
+  // column 0 with weight 0), so that a batch's loads are in flight together
+  for (int i0 = r0 + wv; i0 < r1; i0 += 16) {
+    double x[4][3];
+    T ur[4][ENC_KPL];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int i = i0 + 4 * h;
+      const bool in = i < r1;
+      const int ii = in ? i : r0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) x[h][q] = in ? (double)Xb[3 * ii + q] : 0.0;
+#pragma unroll
+      for (int s = 0; s < ENC_KPL; ++s) {
+        const int k = lane + 64 * s;
+        ur[h][s] = Ub[int64_t(ii) * b.ld + (k < c ? k : 0)];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int s = 0; s < ENC_KPL; ++s) {
+        const double u = lane + 64 * s < c ? (double)ur[h][s] : 0.0;
+        acc[s][0] = fma(u, x[h][0], acc[s][0]);
+        acc[s][1] = fma(u, x[h][1], acc[s][1]);
+        acc[s][2] = fma(u, x[h][2], acc[s][2]);
+      }
+  }
+#pragma unroll
+  for (int s = 0; s < ENC_KPL; ++s) {
+    const int k = lane + 64 * s;
+    red[wv][k][0] = acc[s][0];
+    red[wv][k][1] = acc[s][1];
+    red[wv][k][2] = acc[s][2];
+  }
+  __syncthreads();
+  double* pb = part + poff[blockIdx.x] + int64_t(chunk) * b.ld * 3;
+  const int k = threadIdx.x;
+  if (k < b.ld)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) pb[3 * k + q] = ((red[0][k][q] + red[1][k][q]) + red[2][k][q]) + red[3][k][q];
+}
+
+// Reconstruction over 64-row tiles of one block (no block search per row):
+// each lane keeps the coefficients of its columns k = lane + 64 s in
+// registers for the tile's rows; the four wavefronts take every fourth row,
+// a wave reduction per row.  ld <= 256.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_reconstruct_t(const EncBlock* __restrict__ blks, const EncTile* __restrict__ tiles,
+                    const int32_t* __restrict__ cvec, const T* __restrict__ U,
+                    const T* __restrict__ E, T* __restrict__ Xr) {
+  const EncTile t = tiles[blockIdx.x];
+  const EncBlock b = blks[t.blk];
+  const int c = min(max(cvec[t.blk], 0), b.p);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // coefficients of this lane's columns (unconditional loads, 0 past c)
+  double e[ENC_KPL][3];
+#pragma unroll
+  for (int s = 0; s < ENC_KPL; ++s) {
+    const int k = lane + 64 * s;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double v = (double)E[3 * (b.t_off + (k < c ? k : 0)) + q];
+      e[s][q] = k < c ? v : 0.0;
+    }
+  }
+  const int r1 = min(b.n, t.row0 + ENC_TILE);
+  const T* Ub = U + b.u_off;
+  // four rows of the wavefront per batch, loads unconditional (a row past
+  // the tile reads the tile's first row and is not stored)
+  for (int i0 = t.row0 + wv; i0 < r1; i0 += 16) {
+    T ur[4][ENC_KPL];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int i = i0 + 4 * h < r1 ? i0 + 4 * h : t.row0;
+#pragma unroll
+      for (int s = 0; s < ENC_KPL; ++s) {
+        const int k = lane + 64 * s;
+        ur[h][s] = Ub[int64_t(i) * b.ld + (k < c ? k : 0)];  // e is 0 past c
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int s = 0; s < ENC_KPL; ++s) {
+        const double u = (double)ur[h][s];
+        s0 = fma(u, e[s][0], s0);
+        s1 = fma(u, e[s][1], s1);
+        s2 = fma(u, e[s][2], s2);
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      const int i = i0 + 4 * h;
+      if (lane == 0 && i < r1) {
+        T* o = Xr + 3 * (b.v_off + i);
+        o[0] = (T)s0;
+        o[1] = (T)s1;
+        o[2] = (T)s2;
+      }
+    }
   }
 }
 
@@ -218,14 +366,23 @@ mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const
   double* part = static_cast<double*>(ws);
   KClose kc_(ctx->timer);
   KScope k_(ctx->timer, MI_K_PROJECT, s);
+  const bool tiled = P->max_ld <= 64 * ENC_KPL;
   if (precision == MI_FP64) {
-    hipLaunchKernelGGL(k_project_part<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
-                       P->dev_poff, c, (const double*)U, (const double*)X, part);
+    if (tiled)
+      hipLaunchKernelGGL(k_project_part_w<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s,
+                         P->dev, P->dev_poff, c, (const double*)U, (const double*)X, part);
+    else
+      hipLaunchKernelGGL(k_project_part<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
+                         P->dev_poff, c, (const double*)U, (const double*)X, part);
     hipLaunchKernelGGL(k_project_sum<double>, dim3(hb.B), dim3(256), 0, s, P->dev, P->dev_poff, c,
                        part, (double*)E);
   } else {
-    hipLaunchKernelGGL(k_project_part<float>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
-                       P->dev_poff, c, (const float*)U, (const float*)X, part);
+    if (tiled)
+      hipLaunchKernelGGL(k_project_part_w<float>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s,
+                         P->dev, P->dev_poff, c, (const float*)U, (const float*)X, part);
+    else
+      hipLaunchKernelGGL(k_project_part<float>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, P->dev,
+                         P->dev_poff, c, (const float*)U, (const float*)X, part);
     hipLaunchKernelGGL(k_project_sum<float>, dim3(hb.B), dim3(256), 0, s, P->dev, P->dev_poff, c,
                        part, (float*)E);
   }
@@ -250,12 +407,22 @@ mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, c
   const int grid = ceil_div(N, 4);
   KClose kc_(ctx->timer);
   KScope k_(ctx->timer, MI_K_RECONSTRUCT, s);
-  if (precision == MI_FP64)
-    hipLaunchKernelGGL(k_reconstruct<double>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff, hb.B,
-                       N, c, (const double*)U, (const double*)E, (double*)Xr);
-  else
-    hipLaunchKernelGGL(k_reconstruct<float>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff, hb.B,
-                       N, c, (const float*)U, (const float*)E, (float*)Xr);
+  const bool tiled = P->max_ld <= 64 * ENC_KPL;
+  if (tiled && P->n_tiles > 0) {
+    if (precision == MI_FP64)
+      hipLaunchKernelGGL(k_reconstruct_t<double>, dim3(P->n_tiles), dim3(256), 0, s, P->dev,
+                         P->tiles, c, (const double*)U, (const double*)E, (double*)Xr);
+    else
+      hipLaunchKernelGGL(k_reconstruct_t<float>, dim3(P->n_tiles), dim3(256), 0, s, P->dev,
+                         P->tiles, c, (const float*)U, (const float*)E, (float*)Xr);
+  } else if (!tiled) {
+    if (precision == MI_FP64)
+      hipLaunchKernelGGL(k_reconstruct<double>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff,
+                         hb.B, N, c, (const double*)U, (const double*)E, (double*)Xr);
+    else
+      hipLaunchKernelGGL(k_reconstruct<float>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff,
+                         hb.B, N, c, (const float*)U, (const float*)E, (float*)Xr);
+  }
   MI_TRY_HIP(hipGetLastError());
   return MI_OK;
 }

@@ -69,6 +69,15 @@ typedef int32_t mi_status;
 /* Start subspace of a block in mi_oi_track. */
 #define MI_WARM_GIVEN 0 /* V0 holds a start for every block                          */
 #define MI_WARM_PRED 1  /* blocks with pred >= 0 start from their predecessor's result */
+#define MI_RANDOM 2     /* blocks without a predecessor (all blocks when pred is NULL)
+                           start from seeded pseudo-random numbers (mi_oi_params.seed),
+                           the others from their predecessor as under MI_WARM_PRED;
+                           V0 is not read.  Entry (i, j) of block b's start is
+                           2 u - 1 with u = (z >> 11) 2^-53, z = SplitMix64 of the
+                           counter seed + 0x9E3779B97F4A7C15 (1 + b 2^40 + i 2^12 + j)
+                           (Steele, Lea and Flood 2014; b < 2^24, i < 2^28, j < 2^12),
+                           for j < p_b; the start is orthonormalised by a Cholesky-QR
+                           before its first filter pass */
 
 /* Per-block status codes written to `status` by mi_oi_track (device). */
 #define MI_BLOCK_OK 0
@@ -76,6 +85,8 @@ typedef int32_t mi_status;
 #define MI_BLOCK_NOT_PD 2    /* a Cholesky factorisation failed even when shifted */
 #define MI_BLOCK_NOCONV 4    /* Jacobi sweeps exhausted before convergence         */
 #define MI_BLOCK_NONFINITE 8 /* NaN / Inf met in a small matrix                    */
+#define MI_BLOCK_UNCONVERGED 16 /* tolerance mode: the kept pairs did not meet tol
+                                   within the iteration limit                     */
 
 typedef struct mi_ctx mi_ctx;
 
@@ -87,12 +98,15 @@ typedef struct {
   const int32_t* ld;    /* [n_blocks]   row stride of the slab, multiple of 32, >= p_b */
   const int64_t* u_off; /* [n_blocks+1] slab offsets, u_off[b+1]-u_off[b] = n_b*ld_b    */
   const int32_t* pred;  /* [n_blocks] warm-start predecessor (-1 none), or NULL        */
+  const int32_t* c;     /* [n_blocks] kept pairs c_b (1 <= c_b <= p_b): the Ritz pairs
+                           the tolerance test of mi_oi_track covers; NULL = p_b.
+                           Other calls ignore it                                    */
 } mi_blocks;
 
 /* Parameters of the eigenspace tracking (mi_oi_track). */
 typedef struct {
   int32_t precision; /* MI_FP32 or MI_FP64                                            */
-  int32_t warm;      /* MI_WARM_GIVEN or MI_WARM_PRED                                 */
+  int32_t warm;      /* MI_WARM_GIVEN, MI_WARM_PRED or MI_RANDOM                      */
   int32_t T;         /* outer iterations of blocks that have a predecessor            */
   int32_t m;         /* Chebyshev degree of one filter pass, same blocks              */
   int32_t passes;    /* filter passes per iteration, same blocks (>= 1)               */
@@ -138,6 +152,19 @@ typedef struct {
   int32_t cg_iters;  /* conjugate-gradient iterations per solve (MI_OP_RZ)         */
   int32_t pad_;
   double delta;      /* shift of R (MI_OP_RZ), > 0                                  */
+  double tol;        /* 0: fixed iteration counts (T, T0).  > 0: tolerance mode
+                        (Section 4 leaves the number of iterations to the user):
+                        every iteration ends with the Rayleigh-Ritz step and a
+                        Cholesky-QR, then the residuals r_j = ||L v_j - theta_j v_j||
+                        of the Ritz pairs; a block whose kept pairs j < c_b satisfy
+                        max_j r_j <= tol |theta_{p_b - 1}| is converged, and its
+                        basis, Ritz values and residuals of that iteration are the
+                        output (later iterations do not change them).  T and T0
+                        cap the iterations; a block still unconverged there
+                        returns its last iterate with MI_BLOCK_UNCONVERGED.  The
+                        launch sequence stays fixed (converged blocks keep being
+                        iterated in the batch, their output is frozen)          */
+  uint64_t seed;     /* seed of the MI_RANDOM start                                 */
 } mi_oi_params;
 
 #define MI_OP_CHEB 0
@@ -272,10 +299,17 @@ mi_status mi_laplacian_values(mi_ctx* ctx, const mi_blocks* blk, const int64_t* 
  *
  * val       device float [nnz] Laplacian values (FP32; promoted exactly in FP64 mode)
  * V0        device [u_off[B]] start slabs (float or double per precision);
- *           MI_WARM_GIVEN: all blocks; MI_WARM_PRED: blocks without predecessor.
+ *           MI_WARM_GIVEN: all blocks; MI_WARM_PRED: blocks without predecessor;
+ *           MI_RANDOM: not read (may be NULL).
  * V         device [u_off[B]] output slabs (may alias V0).
  * ritz      device double [sum p_b] Ritz values per block, ascending
  *           (block b at sum_{b'<b} p_b').
+ * resid     device double [sum p_b] residual norms ||L v_j - theta_j v_j||_2 of
+ *           the returned pairs (same layout as ritz), or NULL (then not
+ *           computed; required in tolerance mode).
+ * iters     device int32 [B] iterations whose result is returned: the first
+ *           iteration meeting tol in tolerance mode (the cap when none did),
+ *           else the fixed count; or NULL.
  * status    device int32 [B] MI_BLOCK_* flags (valid after the stream syncs).
  * Workspace from mi_oi_workspace_size.  Enqueue only.  The launch sequence
  * is captured into a HIP graph per context and replayed while the block
@@ -291,7 +325,8 @@ mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves)
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                       const int32_t* row_ptr, const int32_t* col, const float* val,
                       const int64_t* nnz_off, const void* V0, void* V, double* ritz,
-                      int32_t* status, void* ws, size_t ws_bytes, void* stream);
+                      double* resid, int32_t* iters, int32_t* status, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* Same computation without the persistent graph and with one block per
  * launch sequence: the "plain per-block GPU OI" reference the batched path
@@ -299,7 +334,8 @@ mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm
 mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                                 const int32_t* row_ptr, const int32_t* col, const float* val,
                                 const int64_t* nnz_off, const void* V0, void* V, double* ritz,
-                                int32_t* status, void* ws, size_t ws_bytes, void* stream);
+                                double* resid, int32_t* iters, int32_t* status, void* ws,
+                                size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- dynamic OI
  * Section 5, Algorithm 2 (dynamic OI), with the branches as the text states

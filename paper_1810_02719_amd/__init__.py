@@ -26,9 +26,9 @@ import torch
 
 from . import _lib as L
 from ._lib import MI_OP_CHEB, MI_OP_RZ  # noqa: F401
-from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_FP32, MI_FP64, MI_W_COMBINATORIAL,  # noqa: F401
-                   MI_W_INV_DIST, MI_W_INV_SQ_DIST, MI_W_USER, MI_WARM_GIVEN, MI_WARM_PRED,
-                   MiError)
+from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_FP32, MI_FP64, MI_RANDOM,  # noqa: F401
+                   MI_W_COMBINATORIAL, MI_W_INV_DIST, MI_W_INV_SQ_DIST, MI_W_USER, MI_WARM_GIVEN,
+                   MI_WARM_PRED, MiError)
 
 __all__ = ["Blocks", "Context", "Laplacian", "OiParams", "build_laplacian", "laplacian_values",
            "oi_track", "ritz_residuals", "oi_track_tol", "TolResult", "encdec_adjoint", "EncodeDecode",
@@ -55,9 +55,10 @@ def _stream():
 
 class Blocks:
     """Host block table: sizes n_b, tracked widths p_b, slab strides ld_b
-    (multiples of 32) and warm-start predecessors."""
+    (multiples of 32), warm-start predecessors and the kept pairs c_b that
+    the tolerance test covers (None: p_b)."""
 
-    def __init__(self, n, p=None, ld=None, pred=None):
+    def __init__(self, n, p=None, ld=None, pred=None, c=None):
         self.n = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
         B = self.n.size
         self.p = np.ascontiguousarray(np.asarray(p if p is not None else np.ones(B), dtype=np.int32))
@@ -66,13 +67,17 @@ class Blocks:
         self.ld = np.ascontiguousarray(np.asarray(ld, dtype=np.int32))
         self.pred = (np.ascontiguousarray(np.asarray(pred, dtype=np.int32))
                      if pred is not None else None)
+        self.c = (np.ascontiguousarray(np.asarray(c, dtype=np.int32).reshape(-1))
+                  if c is not None else None)
+        if self.c is not None and self.c.size == 1 and B > 1:
+            self.c = np.full(B, int(self.c[0]), np.int32)
         self.v_off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(self.n)]).astype(np.int64))
         self.u_off = np.ascontiguousarray(
             np.concatenate([[0], np.cumsum(self.n * self.ld.astype(np.int64))]).astype(np.int64))
         self.t_off = np.concatenate([[0], np.cumsum(self.p.astype(np.int64))]).astype(np.int64)
         self._s = L.MiBlocks(B, _np_ptr(self.v_off, C.c_int64), _np_ptr(self.p, C.c_int32),
                              _np_ptr(self.ld, C.c_int32), _np_ptr(self.u_off, C.c_int64),
-                             _np_ptr(self.pred, C.c_int32))
+                             _np_ptr(self.pred, C.c_int32), _np_ptr(self.c, C.c_int32))
 
     @property
     def n_blocks(self):
@@ -220,12 +225,15 @@ class OiParams:
     z: int = 1
     cg_iters: int = 200
     delta: float = 1e-3
+    tol: float = 0.0  # > 0: tolerance mode (T, T0 cap the iterations)
+    seed: int = 0     # seed of the MI_RANDOM start
 
     def struct(self):
         return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
                             self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, self.rr_every,
                             self.eig, self.autotune, self.a_value, self.b_abs, self.jacobi_tol,
-                            self.op, self.z, self.cg_iters, 0, self.delta)
+                            self.op, self.z, self.cg_iters, 0, self.delta, self.tol,
+                            int(self.seed) & 0xFFFFFFFFFFFFFFFF)
 
 
 def _dtype(precision):
@@ -233,9 +241,10 @@ def _dtype(precision):
 
 
 def oi_track(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, V0=None, V=None,
-             ritz=None, status=None, per_block: bool = False):
+             ritz=None, status=None, per_block: bool = False, resid=None, iters=None):
     """Tracked subspaces of every block (mi_oi_track / mi_oi_track_per_block).
-    Returns (V, ritz, status)."""
+    Returns (V, ritz, status); resid (FP64 [sum p_b]) and iters (int32 [B])
+    are filled when given (resid is allocated in tolerance mode)."""
     lib = L.lib()
     prm = params.struct()
     dev = f"cuda:{ctx.device}"
@@ -246,13 +255,15 @@ def oi_track(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, V0=
         ritz = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
     if status is None:
         status = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+    if resid is None and params.tol > 0:
+        resid = torch.empty(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
     ws_n = C.c_size_t()
     L.check(lib.mi_oi_workspace_size(ctx.h, blocks.ref, C.byref(prm), C.byref(ws_n)))
     ws = ctx.workspace("oi", ws_n.value)
     fn = lib.mi_oi_track_per_block if per_block else lib.mi_oi_track
     L.check(fn(ctx.h, blocks.ref, C.byref(prm), _dptr(lap.row_ptr), _dptr(lap.col), _dptr(lap.val),
-               _np_ptr(lap.nnz_off, C.c_int64), _dptr(V0), _dptr(V), _dptr(ritz), _dptr(status),
-               _dptr(ws), ws.numel(), _stream()))
+               _np_ptr(lap.nnz_off, C.c_int64), _dptr(V0), _dptr(V), _dptr(ritz), _dptr(resid),
+               _dptr(iters), _dptr(status), _dptr(ws), ws.numel(), _stream()))
     return V, ritz, status
 
 
@@ -312,52 +323,25 @@ class TolResult:
     V: torch.Tensor
     ritz: torch.Tensor
     status: torch.Tensor
-    resid: torch.Tensor        # residual norms of the returned pairs
-    rel: np.ndarray            # per block max_{j < c_b} resid_j / theta_{p_b - 1}
-    iters: np.ndarray          # per block: iterations done when it first met tol (-1: never)
-    converged: np.ndarray      # per block bool
-    total_iters: int           # iterations every block went through
+    resid: torch.Tensor        # residual norms of the returned pairs (device FP64)
+    iters: torch.Tensor        # per block: iteration whose result is returned (device int32)
+    converged: torch.Tensor    # per block: met tol within the cap (device bool)
 
 
 def oi_track_tol(ctx: Context, blocks: Blocks, lap: Laplacian, params: OiParams, tol: float,
-                 c=None, step: int = 1, max_iters: int = 60, V0=None) -> TolResult:
-    """Tolerance mode of the iteration control: one oi_track call with
-    `params`, then rounds of `step` further iterations (every block restarts
-    from its own current basis, MI_WARM_GIVEN, lower filter bound from its
-    Ritz values) until every block's kept pairs j < c_b satisfy
-    || L v_j - theta_j v_j || <= tol * theta_{p_b - 1}, or max_iters.  Blocks
-    that already meet the tolerance keep iterating with the others (one
-    batched launch sequence per round); `iters` records when each first did.
-    The decision reads the residuals on the host once per round."""
-    B = blocks.n_blocks
-    cb = np.asarray(blocks.p if c is None else c, dtype=np.int64).reshape(-1)
-    if cb.size == 1 and B > 1:
-        cb = np.full(B, int(cb[0]))
-    if np.any(cb < 1) or np.any(cb > blocks.p):
-        raise ValueError("need 1 <= c_b <= p_b")
-    V, ritz, status = oi_track(ctx, blocks, lap, params, V0=V0)
-    if params.warm == MI_WARM_GIVEN or blocks.pred is None:
-        done = np.full(B, params.T0, np.int64)
-    else:
-        done = np.where(blocks.pred >= 0, params.T, params.T0).astype(np.int64)
-    sp = OiParams(**{**params.__dict__, "warm": MI_WARM_GIVEN, "T0": step, "m0": params.m,
-                     "passes0": params.passes, "a_mode": MI_A_RITZ})
-    iters = np.full(B, -1, np.int64)
-    Vn = torch.empty_like(V)
-    t_end = blocks.t_off[1:] - 1
-    while True:
-        resid = ritz_residuals(ctx, blocks, lap, V, ritz, params.precision)
-        r = resid.cpu().numpy()
-        th = ritz.cpu().numpy()
-        rel = np.array([r[blocks.t_off[b]:blocks.t_off[b] + cb[b]].max() / max(th[t_end[b]], 1e-300)
-                        for b in range(B)])
-        conv = rel <= tol
-        iters = np.where(conv & (iters < 0), done, iters)
-        if conv.all() or done.max() >= max_iters:
-            break
-        V, Vn = oi_track(ctx, blocks, lap, sp, V0=V, V=Vn, ritz=ritz, status=status)[0], V
-        done = done + step
-    return TolResult(V, ritz, status, resid, rel, iters, conv, int(done.max()))
+                 V0=None) -> TolResult:
+    """Tolerance mode of the iteration control (mi_oi_track with params.tol
+    = tol): every block stops at the first iteration whose kept pairs j <
+    c_b (blocks.c) satisfy ||L v_j - theta_j v_j|| <= tol |theta_{p_b - 1}|;
+    params.T / T0 cap the iterations.  The test runs on the device, inside
+    the library's launch sequence."""
+    prm = OiParams(**{**params.__dict__, "tol": float(tol)})
+    dev = f"cuda:{ctx.device}"
+    resid = torch.empty(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
+    iters = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+    V, ritz, status = oi_track(ctx, blocks, lap, prm, V0=V0, resid=resid, iters=iters)
+    conv = (status & L.MI_BLOCK_UNCONVERGED) == 0
+    return TolResult(V, ritz, status, resid, iters, conv)
 
 
 def project(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, X: torch.Tensor,
@@ -487,7 +471,10 @@ class EncodeDecode(torch.autograd.Function):
     X: flat [3 n] coordinates (float32; the projection runs in the params'
     precision); w: per-edge user weights (float32) when lap.mode is
     MI_W_USER, else None.  The forward recomputes the Laplacian values,
-    tracks, projects and reconstructs; the backward calls encdec_adjoint."""
+    tracks, projects and reconstructs; the backward restores the Laplacian
+    values of its own forward (lap is shared: another forward may have
+    rewritten lap.val since, e.g. the next frame of a sequence) and calls
+    encdec_adjoint.  After a backward, lap holds that forward's values."""
 
     @staticmethod
     def forward(fctx, X, w, ctx, blocks, lap, params, V0, c):
@@ -499,14 +486,16 @@ class EncodeDecode(torch.autograd.Function):
         Xp = X.detach().to(dt).contiguous()
         E = project(ctx, blocks, c, V, Xp, params.precision)
         Xr = reconstruct(ctx, blocks, c, V, E, params.precision)
-        fctx.save_for_backward(Xp, V0, c)
+        # the inputs that set the Laplacian values of this forward
+        fctx.save_for_backward(Xp, V0, c, X32, uw)
         fctx.meta = (ctx, blocks, lap, params, X.dtype, None if w is None else w.dtype)
         return Xr.to(X.dtype)
 
     @staticmethod
     def backward(fctx, g):
-        Xp, V0, c = fctx.saved_tensors
+        Xp, V0, c, X32, uw = fctx.saved_tensors
         ctx, blocks, lap, params, xdt, wdt = fctx.meta
+        laplacian_values(ctx, blocks, lap, X32, lap.mode, uw)
         G = g.detach().to(Xp.dtype).contiguous()
         Xbar, wbar = encdec_adjoint(ctx, blocks, lap, params, V0, Xp, c, G)
         gw = wbar.to(wdt) if wdt is not None else None

@@ -31,6 +31,7 @@ MI_FP64 = 1
 
 MI_WARM_GIVEN = 0
 MI_WARM_PRED = 1
+MI_RANDOM = 2
 
 MI_A_WEYL = 0
 MI_A_ABS = 1
@@ -53,6 +54,7 @@ MI_BLOCK_SHIFTED = 1
 MI_BLOCK_NOT_PD = 2
 MI_BLOCK_NOCONV = 4
 MI_BLOCK_NONFINITE = 8
+MI_BLOCK_UNCONVERGED = 16
 
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
@@ -62,7 +64,7 @@ _vp = C.c_void_p
 
 class MiBlocks(C.Structure):
     _fields_ = [("n_blocks", C.c_int32), ("v_off", _i64p), ("p", _i32p), ("ld", _i32p),
-                ("u_off", _i64p), ("pred", _i32p)]
+                ("u_off", _i64p), ("pred", _i32p), ("c", _i32p)]
 
 
 class MiOiParams(C.Structure):
@@ -73,7 +75,7 @@ class MiOiParams(C.Structure):
                 ("autotune", C.c_int32), ("a_value", C.c_double),
                 ("b_abs", C.c_double), ("jacobi_tol", C.c_double), ("op", C.c_int32),
                 ("z", C.c_int32), ("cg_iters", C.c_int32), ("pad_", C.c_int32),
-                ("delta", C.c_double)]
+                ("delta", C.c_double), ("tol", C.c_double), ("seed", C.c_uint64)]
 
 
 class MiDoiParams(C.Structure):
@@ -96,13 +98,13 @@ _SIGS = {
     "mi_oi_workspace_size": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _szp],
     "mi_oi_tuning": [_vp, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)],
     "mi_oi_track": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp, _i64p, _vp,
-                    _vp, _vp, _vp, _vp, C.c_size_t, _vp],
+                    _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_doi_workspace_size": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams),
                               C.POINTER(MiDoiParams), _szp],
     "mi_doi_track": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), C.POINTER(MiDoiParams), _vp,
                      _vp, _vp, _i64p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_oi_track_per_block": [_vp, C.POINTER(MiBlocks), C.POINTER(MiOiParams), _vp, _vp, _vp,
-                              _i64p, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
+                              _i64p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
     "mi_residual_workspace_size": [_vp, C.POINTER(MiBlocks), _szp],
     "mi_ritz_residuals": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _i64p, _vp, _vp, _vp,
                           _vp, C.c_size_t, _vp],

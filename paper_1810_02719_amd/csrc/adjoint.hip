@@ -585,9 +585,15 @@ static mi_status adj_check(const mi_oi_params* prm, const HostBlocks& hb) {
   mi_status st = oi_check_params(prm);
   if (st) return st;
   MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN, "the adjoint needs warm = MI_WARM_GIVEN");
+  MI_CHECK_ARG(prm->tol == 0, "the adjoint differentiates fixed iteration counts (tol = 0)");
   MI_CHECK_ARG(prm->op == MI_OP_CHEB, "the adjoint differentiates the Chebyshev filter only");
   MI_CHECK_ARG(prm->adapt == 0 && prm->rr_every == 0,
                "the adjoint needs a fixed filter interval (adapt = 0, rr_every = 0)");
+  // the reverse sweep holds the interval [a, b] constant, so it must not be
+  // a function of the inputs: a Gershgorin b depends on the weights, and a
+  // Weyl-law a on b
+  MI_CHECK_ARG(prm->b_abs > 0 && prm->a_mode == MI_A_ABS,
+               "the adjoint needs a given filter interval (b_abs > 0, a_mode = MI_A_ABS)");
   MI_CHECK_ARG(prm->eig == MI_EIG_TRIDIAG, "the adjoint needs eig = MI_EIG_TRIDIAG");
   MI_CHECK_ARG(prm->T0 >= 1, "the adjoint needs T0 >= 1");
   int max_ld = 0;

@@ -61,6 +61,7 @@ struct HostBlocks {
   int32_t B = 0;
   std::vector<int64_t> v_off, u_off;
   std::vector<int32_t> p, ld, pred;
+  std::vector<int32_t> c;             // kept pairs of the tolerance test (p when not given)
   std::vector<int64_t> t_off, m_off;  // derived
 };
 

@@ -62,6 +62,16 @@ mi_status load_blocks(const mi_blocks* blk, HostBlocks* hb, bool need_slab) {
     hb->t_off[b + 1] = hb->t_off[b] + hb->p[b];
     hb->m_off[b + 1] = hb->m_off[b] + int64_t(hb->ld[b]) * hb->ld[b];
   }
+  hb->c = hb->p;
+  if (blk->c) {
+    for (int b = 0; b < B; ++b) {
+      if (blk->c[b] < 1 || blk->c[b] > hb->p[b]) {
+        set_error("block %d: c = %d outside [1, p = %d]", b, blk->c[b], hb->p[b]);
+        return MI_ERR_CAPACITY;
+      }
+      hb->c[b] = blk->c[b];
+    }
+  }
   return MI_OK;
 }
 

@@ -110,10 +110,12 @@ __global__ void k_cheb_coef(const MatDesc* __restrict__ sets, int nsets,
 // Warm start: block b's start is its predecessor's final basis, rows and
 // columns index-aligned; rows past the predecessor's size are zero, columns
 // past its width get the unit vector e_{(997 j) mod n_b}.
+// The predecessor's basis is read from src (the caller's output), the start
+// is written to dst (the same buffer outside the tolerance mode).
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_warm_copy(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
-                const MatDesc* __restrict__ psets, T* __restrict__ V) {
+                const MatDesc* __restrict__ psets, const T* src, T* dst) {
   const SpmmTile t = tiles[blockIdx.x];
   const MatDesc d = sets[t.set], pd = psets[t.set];
   const int rows = min(SPMM_ROWS, d.rows - t.row0);
@@ -122,13 +124,178 @@ __global__ void __launch_bounds__(256)
     T v = (T)0;
     if (j < d.cols) {
       if (j < pd.cols) {
-        if (r < pd.rows) v = V[pd.off + int64_t(r) * pd.ld + j];
+        if (r < pd.rows) v = src[pd.off + int64_t(r) * pd.ld + j];
       } else if (r == int((997LL * j) % d.rows)) {
         v = (T)1;
       }
     }
-    V[d.off + int64_t(r) * d.ld + j] = v;
+    dst[d.off + int64_t(r) * d.ld + j] = v;
   }
+}
+
+// Seeded start of a block without predecessor (MI_RANDOM): entry (i, j) is
+// 2u - 1, u uniform in [0, 1) from the SplitMix64 output function (Steele,
+// Lea and Flood 2014) applied to the counter seed + golden (1 + key), key =
+// b 2^40 + i 2^12 + j: independent of the slab layout and of the launch.
+__device__ inline double splitmix_unit(uint64_t seed, uint64_t key) {
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (key + 1ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return double(z >> 11) * 0x1.0p-53;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_random_start(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                   uint64_t seed, T* __restrict__ out) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
+    const int r = t.row0 + e / d.ld, j = e % d.ld;
+    const uint64_t key = (uint64_t(d.blk) << 40) + (uint64_t(r) << 12) + uint64_t(j);
+    out[d.off + int64_t(r) * d.ld + j] =
+        j < d.cols ? (T)(2.0 * splitmix_unit(seed, key) - 1.0) : (T)0;
+  }
+}
+
+// ------------------------------------------------------------------ tolerance mode
+// Residual norms r_j = ||L v_j - theta_j v_j||_2 of a wave's Ritz pairs.
+// Stage 1, one workgroup per 16-row tile: each wavefront takes whole rows,
+// gathers the neighbour rows, forms (L V)_row - theta V_row and accumulates
+// its squares per column in FP64; the four wavefronts' sums are added in a
+// fixed order into the tile's partial (global tile numbering).  Stage 2 adds
+// a block's tile partials in tile order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_resid_tile(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                 const CsrDesc* __restrict__ csr, const BlkInfo* __restrict__ info,
+                 const int64_t* __restrict__ tile_base, int ldp,
+                 const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                 const float* __restrict__ val, const T* __restrict__ V,
+                 const double* __restrict__ ritz, double* __restrict__ part) {
+  constexpr int MAXC = 1024 / 64;  // columns per lane for ld <= 1024
+  __shared__ double wsum[4][1024];
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const CsrDesc c = csr[t.set];
+  const double* th = ritz + info[d.blk].t_off;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  const T* Vb = V + d.off;
+  const int32_t* cb = col + c.nnz_off;
+  const float* vb = val + c.nnz_off;
+  double acc[MAXC];
+#pragma unroll
+  for (int s = 0; s < MAXC; ++s) acc[s] = 0.0;
+  for (int rr = wave; rr < rows; rr += 4) {
+    const int r = t.row0 + rr;
+    const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
+#pragma unroll
+    for (int s = 0; s < MAXC; ++s) {
+      const int j = lane + 64 * s;
+      if (j >= d.ld) continue;
+      double lv = 0.0;
+      for (int k = k0; k < k1; ++k) lv = fma((double)vb[k], (double)Vb[int64_t(cb[k]) * d.ld + j], lv);
+      const double th_j = j < d.cols ? th[j] : 0.0;
+      const double res = fma(-th_j, (double)Vb[int64_t(r) * d.ld + j], lv);
+      acc[s] = fma(res, res, acc[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < MAXC; ++s) {
+    const int j = lane + 64 * s;
+    if (j < d.ld) wsum[wave][j] = acc[s];
+  }
+  __syncthreads();
+  double* out = part + (tile_base[d.blk] + t.row0 / SPMM_ROWS) * ldp;
+  for (int j = threadIdx.x; j < d.ld; j += 256)
+    out[j] = ((wsum[0][j] + wsum[1][j]) + wsum[2][j]) + wsum[3][j];
+}
+
+// Stage 2 and the test, one workgroup per block of the wave: resid[j] =
+// sqrt(sum of the tile partials) for j < p; then thread 0 decides whether
+// the block is converged (max_{j < c} r_j <= tol |theta_{p-1}|), or ends at
+// the iteration cap, and if so freezes it now (fnow = 1): the iteration
+// count, Ritz values and residuals go to the outputs.
+__global__ void __launch_bounds__(256)
+    k_tol_check(const MatDesc* __restrict__ sets, const BlkInfo* __restrict__ info,
+                const int64_t* __restrict__ tile_base, int ldp, const double* __restrict__ part,
+                double* __restrict__ resid_w, const double* __restrict__ ritz_w, double tol,
+                int iter, int last, int32_t* __restrict__ frozen, int32_t* __restrict__ fnow,
+                double* __restrict__ ritz_out, double* __restrict__ resid_out,
+                int32_t* __restrict__ iters, int32_t* __restrict__ status) {
+  __shared__ double red[4];
+  const MatDesc d = sets[blockIdx.x];
+  const BlkInfo bi = info[d.blk];
+  const int nt = (d.rows + SPMM_ROWS - 1) / SPMM_ROWS;
+  const int64_t base = tile_base[d.blk];
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < bi.p; j += 256) {
+    double s = 0.0;
+    for (int k = 0; k < nt; ++k) s += part[(base + k) * ldp + j];
+    const double r = sqrt(s);
+    resid_w[bi.t_off + j] = r;
+    if (j < bi.c) mx = fmax(mx, r);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const bool was = frozen[d.blk] != 0;
+  const bool conv = mx <= tol * fabs(ritz_w[bi.t_off + bi.p - 1]);
+  const bool now = !was && (conv || last);
+  if (now) {
+    for (int j = threadIdx.x; j < bi.p; j += 256) {
+      ritz_out[bi.t_off + j] = ritz_w[bi.t_off + j];
+      if (resid_out) resid_out[bi.t_off + j] = resid_w[bi.t_off + j];
+    }
+  }
+  if (threadIdx.x == 0) {
+    fnow[d.blk] = now ? 1 : 0;
+    if (now) {
+      frozen[d.blk] = 1;
+      if (iters) iters[d.blk] = iter + 1;
+      if (!conv) atomicOr(&status[d.blk], MI_BLOCK_UNCONVERGED);
+    }
+  }
+}
+
+// Rows of the blocks frozen in this iteration: working basis -> output.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_freeze_rows(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                  const int32_t* __restrict__ fnow, const T* __restrict__ src,
+                  T* __restrict__ dst) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  if (!fnow[d.blk]) return;
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
+    const int64_t o = d.off + int64_t(t.row0) * d.ld + e;
+    dst[o] = src[o];
+  }
+}
+
+// Fixed iteration counts: the residual norms of the final pairs (stage 2
+// only) and the iteration count of every block of the wave.
+__global__ void __launch_bounds__(256)
+    k_resid_final(const MatDesc* __restrict__ sets, const BlkInfo* __restrict__ info,
+                  const int64_t* __restrict__ tile_base, int ldp, const double* __restrict__ part,
+                  double* __restrict__ resid, int T, int32_t* __restrict__ iters) {
+  const MatDesc d = sets[blockIdx.x];
+  const BlkInfo bi = info[d.blk];
+  const int nt = (d.rows + SPMM_ROWS - 1) / SPMM_ROWS;
+  const int64_t base = tile_base[d.blk];
+  if (resid)
+    for (int j = threadIdx.x; j < bi.p; j += 256) {
+      double s = 0.0;
+      for (int k = 0; k < nt; ++k) s += part[(base + k) * ldp + j];
+      resid[bi.t_off + j] = sqrt(s);
+    }
+  if (iters && threadIdx.x == 0) iters[d.blk] = T;
 }
 
 template <typename T>
@@ -418,6 +585,12 @@ __global__ void k_doi_status(int B, int32_t* __restrict__ status) {
 
 static int q_of(int p) { return (p + 1) & ~1; }
 
+// Blocks with a predecessor start from it (MI_WARM_PRED, and MI_RANDOM for
+// the blocks that have one).
+static bool chained(const mi_oi_params& prm) {
+  return prm.warm == MI_WARM_PRED || prm.warm == MI_RANDOM;
+}
+
 // Waves: blocks whose predecessor finished in an earlier wave.  Under
 // MI_WARM_GIVEN (or without predecessors) all blocks form one wave.  The
 // predecessor forest's trees are independent: the trees are dealt to up to
@@ -435,7 +608,7 @@ static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool
   level->assign(B, 0);
   std::vector<int> root(B);
   for (int b = 0; b < B; ++b) root[b] = b;
-  if (prm.warm == MI_WARM_PRED) {
+  if (chained(prm)) {
     for (int b = 0; b < B; ++b) {
       int l = 0, x = b;
       while (hb.pred[x] >= 0) {
@@ -452,7 +625,7 @@ static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool
   // lane of each block: its tree's rank among the roots, modulo MAX_LANES
   std::vector<int> lane(B, 0);
   int nl = 1;
-  if (prm.warm == MI_WARM_PRED && !per_block) {
+  if (chained(prm) && !per_block) {
     std::vector<int> rank(B, -1);
     int nr = 0;
     for (int b = 0; b < B; ++b)
@@ -547,6 +720,13 @@ static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t 
   L.cg_tiles = tiles;
   L.cg_part = c.used;
   if (prm.op == MI_OP_RZ) c.take<double>(3 * size_t(tiles) * L.cg_ldp);
+  L.rpart = c.used, c.take<double>(size_t(tiles) * L.cg_ldp);
+  const bool tolm = prm.tol > 0;
+  L.slab_w = c.used, c.take<char>(tolm ? size_t(slab) * es : 0);
+  L.ritz_w = c.used, c.take<double>(tolm ? tp : 0);
+  L.resid_w = c.used, c.take<double>(tolm ? tp : 0);
+  L.frozen = c.used, c.take<int32_t>(tolm ? hb.B : 0);
+  L.fnow = c.used, c.take<int32_t>(tolm ? hb.B : 0);
   L.total = c.used;
   return L;
 }
@@ -657,7 +837,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   size_t part_max = 0;
   for (size_t w = 0; w < waves.size(); ++w) {
     WaveTables& wt = P->waves[w];
-    const bool warm_wave = prm.warm == MI_WARM_PRED && level[waves[w][0]] > 0;
+    const bool warm_wave = chained(prm) && level[waves[w][0]] > 0;
     wt.from_pred = warm_wave;
     wt.T = warm_wave ? prm.T : prm.T0;
     wt.m = warm_wave ? prm.m : prm.m0;
@@ -676,7 +856,8 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
   std::vector<MatDesc> all_tall;
   std::vector<CsrDesc> all_csr;
   for (int b = 0; b < hb.B; ++b) {
-    info[b] = BlkInfo{hb.t_off[b], int(hb.v_off[b + 1] - hb.v_off[b]), hb.p[b], hb.pred[b], 0};
+    info[b] = BlkInfo{hb.t_off[b], int(hb.v_off[b + 1] - hb.v_off[b]), hb.p[b], hb.pred[b],
+                      hb.c[b]};
     all_tall.push_back(MatDesc{hb.u_off[b], info[b].n, hb.ld[b], hb.p[b], b});
     all_csr.push_back(CsrDesc{hb.v_off[b] + b, nnz_off[b]});
   }
@@ -862,11 +1043,20 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   double* coef = reinterpret_cast<double*>(ws + L.coef);
   int32_t* conv = reinterpret_cast<int32_t*>(ws + L.conv);
   const bool dbl = std::is_same<T, double>::value;
-  T* V = static_cast<T*>(a.V);
-  const T* V0 = static_cast<const T*>(a.V0);
   const int B = P.hb.B;
   const OiRecord* rec = a.rec;
   const DoiArgs* doi = a.doi;
+  // tolerance mode: iterate in a working slab, copy each block out when it
+  // meets the tolerance (or at the cap)
+  const bool tolm = prm.tol > 0 && !doi && !rec;
+  T* Vout = static_cast<T*>(a.V);
+  T* V = tolm ? reinterpret_cast<T*>(ws + L.slab_w) : Vout;
+  double* ritz_w = tolm ? reinterpret_cast<double*>(ws + L.ritz_w) : a.ritz;
+  double* resid_w = reinterpret_cast<double*>(ws + L.resid_w);
+  double* rpart = reinterpret_cast<double*>(ws + L.rpart);
+  int32_t* frozen = reinterpret_cast<int32_t*>(ws + L.frozen);
+  int32_t* fnow = reinterpret_cast<int32_t*>(ws + L.fnow);
+  const T* V0 = static_cast<const T*>(a.V0);
   T* Vf = doi ? reinterpret_cast<T*>(ws + doi->off_vf) : nullptr;
   int32_t* doi_done = doi ? reinterpret_cast<int32_t*>(ws + doi->off_done) : nullptr;
   const size_t slab_bytes = size_t(P.hb.u_off[B]) * sizeof(T);
@@ -879,6 +1069,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   {
     KScope k_(a.tm, MI_K_SETUP, s);
     fill_i32(a.status, 0, B, s);
+    if (tolm) fill_i32(frozen, 0, B, s);
   }
   {
     KScope k_(a.tm, MI_K_SETUP, s);
@@ -917,9 +1108,18 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
     if (w.from_pred) {
       {
         KScope k_(a.tm, MI_K_SETUP, s);
-        hipLaunchKernelGGL(k_warm_copy<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.ptall, V);
+        hipLaunchKernelGGL(k_warm_copy<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.ptall,
+                           (const T*)Vout, V);
       }
       X = V;
+    }
+    // seeded start of the blocks without predecessor (MI_RANDOM)
+    const bool rand_root = prm.warm == MI_RANDOM && !w.from_pred && !doi;
+    if (rand_root) {
+      KScope k_(a.tm, MI_K_SETUP, s);
+      hipLaunchKernelGGL(k_random_start<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                         (uint64_t)prm.seed, slab[1]);
+      X = slab[1];
     }
     if (doi) {
       // the walk edits its basis in place: roots start from a copy of V0
@@ -938,11 +1138,11 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       KScope k_(a.tm, MI_K_CHOL, s);
       launch_chol_blk(w.sd, w.nb, G, Wk, Rinv, s32, a.status, w.max_ld, P.lds_max, s);
     };
-    if (w.from_pred) {
+    if (w.from_pred || rand_root) {
       // The index-aligned warm start drops rows when the block is smaller
-      // than its predecessor and can be badly conditioned; one Cholesky-QR
-      // before the first filter pass keeps the filtered basis of full rank
-      // in FP32.
+      // than its predecessor and can be badly conditioned (and a seeded
+      // start is not orthonormal); one Cholesky-QR before the first filter
+      // pass keeps the filtered basis of full rank in FP32.
       {
         KScope k_(a.tm, MI_K_GRAM, s);
         launch_gram<T>(w.gt, w.n_gt, w.tall, X, X, nullptr, part, s);
@@ -965,7 +1165,10 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
     bool wave_stopped = false;
     for (int t = 0; t < n_iter && !wave_stopped; ++t) {
       const bool last = !doi && t == w.T - 1;
-      const bool rr_now = !doi && (last || prm.rr_every);
+      // an iteration that ends with the Rayleigh-Ritz step and the final
+      // Cholesky-QR: the last one, or every one in the tolerance mode
+      const bool fin = !doi && (last || tolm);
+      const bool rr_now = !doi && (fin || prm.rr_every);
       int ycur = -1;
       for (int pass = 0; pass < w.passes; ++pass) {
         // the interval [a, b] changes only at the end of an iteration: the
@@ -1158,7 +1361,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         }
         {
           KScope k_(a.tm, MI_K_EIG_VALUES, s);
-          launch_tri_bisect(w.sd, w.nb, w.max_p, tri, a.ritz, perm, a_lo, prm.adapt, a.status, s);
+          launch_tri_bisect(w.sd, w.nb, w.max_p, tri, ritz_w, perm, a_lo, prm.adapt, a.status, s);
         }
         {
           KScope k_(a.tm, MI_K_EIG_VECTORS, s);
@@ -1189,7 +1392,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         }
         {
           KScope k_(a.tm, MI_K_RR_FINISH, s);
-          launch_rr_finish(w.sd, w.nb, pk, conv, a.ritz, perm, a_lo, prm.adapt, a.status,
+          launch_rr_finish(w.sd, w.nb, pk, conv, ritz_w, perm, a_lo, prm.adapt, a.status,
                            std::max(1e-10, 10.0 * jtol), s);
         }
       }
@@ -1216,7 +1419,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       const T* Sm = dbl ? reinterpret_cast<const T*>(T1) : reinterpret_cast<const T*>(S32);
       T* dstV;
       int dslab = -1;
-      if (!last) {
+      if (!fin) {
         dstV = V;
       } else {
         for (int i = 0; i < 4; ++i)
@@ -1227,7 +1430,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         KScope k_(a.tm, MI_K_ROWMUL, s);
         launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, dstV, w.nch, s);
       }
-      if (!last) {
+      if (!fin) {
         X = V;
         xslab = -1;
       } else {
@@ -1248,6 +1451,24 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                               dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
                               w.tall, V, w.nch, s);
         }
+        X = V;
+        xslab = -1;
+        if (tolm) {
+          // residuals of the new Ritz pairs, the test, and the copy-out of the
+          // blocks that converge now (or reach the cap)
+          {
+            KScope k_(a.tm, MI_K_SETUP, s);
+            hipLaunchKernelGGL(k_resid_tile<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                               w.csr, P.info, P.tile_base, L.cg_ldp, a.row_ptr, a.col, a.val,
+                               (const T*)V, (const double*)ritz_w, rpart);
+            hipLaunchKernelGGL(k_tol_check, dim3(w.nb), dim3(256), 0, s, w.tall, P.info,
+                               P.tile_base, L.cg_ldp, (const double*)rpart, resid_w,
+                               (const double*)ritz_w, prm.tol, t, last ? 1 : 0, frozen, fnow,
+                               a.ritz, a.resid, a.iters, a.status);
+            hipLaunchKernelGGL(k_freeze_rows<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                               (const int32_t*)fnow, (const T*)V, Vout);
+          }
+        }
       }
     }
     if (doi) {
@@ -1257,9 +1478,25 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
                            (const T*)Vf, V);
       }
-    } else if (w.T == 0 && !w.from_pred) {
+    } else if (w.T == 0) {
+      // no iteration: the start itself (after its Cholesky-QR for predecessor
+      // and seeded starts) is the result
       KScope k_(a.tm, MI_K_SETUP, s);
-      hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, V0, V);
+      if (X != Vout)
+        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, X,
+                           Vout);
+      if (a.iters)
+        hipLaunchKernelGGL(k_resid_final, dim3(w.nb), dim3(256), 0, s, w.tall, P.info,
+                           P.tile_base, L.cg_ldp, (const double*)rpart, (double*)nullptr, 0,
+                           a.iters);
+    } else if (!tolm && (a.resid || a.iters)) {
+      KScope k_(a.tm, MI_K_SETUP, s);
+      if (a.resid)
+        hipLaunchKernelGGL(k_resid_tile<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                           w.csr, P.info, P.tile_base, L.cg_ldp, a.row_ptr, a.col, a.val,
+                           (const T*)Vout, (const double*)a.ritz, rpart);
+      hipLaunchKernelGGL(k_resid_final, dim3(w.nb), dim3(256), 0, s, w.tall, P.info, P.tile_base,
+                         L.cg_ldp, (const double*)rpart, a.resid, w.T, a.iters);
     }
   }
   if (doi) {
@@ -1278,7 +1515,8 @@ static bool same_key(const OiPlan& P, const HostBlocks& hb, const std::vector<in
                      const mi_oi_params& prm, const std::vector<const void*>& ptrs,
                      size_t ws_bytes, bool per_block) {
   return P.per_block == per_block && P.hb.v_off == hb.v_off && P.hb.u_off == hb.u_off &&
-         P.hb.p == hb.p && P.hb.ld == hb.ld && P.hb.pred == hb.pred && P.nnz_off == nnz &&
+         P.hb.p == hb.p && P.hb.ld == hb.ld && P.hb.pred == hb.pred && P.hb.c == hb.c &&
+         P.nnz_off == nnz &&
          memcmp(&P.prm, &prm, sizeof(prm)) == 0 && P.ptrs == ptrs && P.ws_bytes == ws_bytes;
 }
 
@@ -1286,8 +1524,11 @@ static mi_status check_params(const mi_oi_params* prm) {
   MI_CHECK_ARG(prm != nullptr, "params are NULL");
   MI_CHECK_ARG(prm->precision == MI_FP32 || prm->precision == MI_FP64, "precision %d unsupported",
                prm->precision);
-  MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN || prm->warm == MI_WARM_PRED, "warm mode %d unknown",
-               prm->warm);
+  MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN || prm->warm == MI_WARM_PRED || prm->warm == MI_RANDOM,
+               "warm mode %d unknown", prm->warm);
+  MI_CHECK_ARG(prm->tol >= 0 && prm->tol < 1, "tol must be in [0, 1)");
+  MI_CHECK_ARG(prm->tol == 0 || (prm->T >= 1 && prm->T0 >= 1),
+               "the tolerance mode needs T, T0 >= 1 (the iteration caps)");
   MI_CHECK_ARG(prm->T >= 0 && prm->T0 >= 0 && prm->T <= 1000 && prm->T0 <= 1000, "T out of range");
   MI_CHECK_ARG(prm->m >= 1 && prm->m0 >= 1 && prm->m <= 256 && prm->m0 <= 256, "m out of range");
   MI_CHECK_ARG(prm->passes >= 1 && prm->passes0 >= 1, "passes must be >= 1");
@@ -1402,7 +1643,8 @@ mi_status oi_run_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
 static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                         const int32_t* row_ptr, const int32_t* col, const float* val,
                         const int64_t* nnz_off, const void* V0, void* V, double* ritz,
-                        int32_t* status, void* ws, size_t ws_bytes, void* stream, bool per_block) {
+                        double* resid, int32_t* iters, int32_t* status, void* ws,
+                        size_t ws_bytes, void* stream, bool per_block) {
   begin_call();
   MI_CHECK_ARG(ctx != nullptr, "ctx is NULL");
   mi_status st = check_params(prm);
@@ -1413,15 +1655,23 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
   MI_CHECK_ARG(row_ptr && col && val && nnz_off && V && ritz && status, "NULL argument");
   std::vector<int64_t> nnz(nnz_off, nnz_off + hb.B + 1);
   bool needs_v0 = prm->warm == MI_WARM_GIVEN;
-  for (int b = 0; b < hb.B; ++b) needs_v0 = needs_v0 || hb.pred[b] < 0;
+  for (int b = 0; b < hb.B; ++b) needs_v0 = needs_v0 || (prm->warm == MI_WARM_PRED && hb.pred[b] < 0);
   MI_CHECK_ARG(!needs_v0 || V0 != nullptr, "V0 is required");
+  MI_CHECK_ARG(prm->tol == 0 || resid != nullptr, "the tolerance mode needs resid");
+  if (prm->warm == MI_RANDOM)
+    for (int b = 0; b < hb.B; ++b)
+      MI_CHECK_ARG(b < (1 << 24) && hb.p[b] <= 4096 &&
+                       hb.v_off[b + 1] - hb.v_off[b] <= (int64_t(1) << 28),
+                   "MI_RANDOM covers b < 2^24, p_b <= 4096, n_b <= 2^28");
   MI_TRY_HIP(hipSetDevice(ctx->device));
-  std::vector<const void*> ptrs = {row_ptr, col, val, V0, V, ritz, status, ws};
+  std::vector<const void*> ptrs = {row_ptr, col, val, V0, V, ritz, resid, iters, status, ws};
   OiPlan* P = nullptr;
   st = get_plan(ctx, &ctx->oi_plan, hb, nnz, *prm, ptrs, ws, ws_bytes, per_block, &P);
   if (st) return st;
   Args a{row_ptr, col, val, V0, V, ritz, status, static_cast<char*>(ws), ctx->timer, nullptr,
          false};
+  a.resid = resid;
+  a.iters = iters;
   hipStream_t s = (hipStream_t)stream;
   if (per_block || ctx->timer) {
     if (prm->precision == MI_FP64)
@@ -1478,6 +1728,8 @@ static mi_status doi_check(const HostBlocks& hb, const mi_oi_params* prm, const 
   MI_CHECK_ARG(dp->t_max >= 0 && dp->t_max <= 10000, "t_max %d out of range", dp->t_max);
   MI_CHECK_ARG(dp->c_max >= 1, "c_max must be >= 1");
   MI_CHECK_ARG(prm->a_mode != MI_A_RITZ, "the walk takes no Ritz values: a_mode RITZ unsupported");
+  MI_CHECK_ARG(prm->warm != MI_RANDOM && prm->tol == 0,
+               "the walk takes given or predecessor starts and no tolerance (it has its own rule)");
   for (int b = 0; b < hb.B; ++b)
     MI_CHECK_ARG(hb.ld[b] <= DOI_MAX_LD, "block %d: ld %d above %d", b, hb.ld[b], DOI_MAX_LD);
   return MI_OK;
@@ -1533,9 +1785,10 @@ mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves)
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                       const int32_t* row_ptr, const int32_t* col, const float* val,
                       const int64_t* nnz_off, const void* V0, void* V, double* ritz,
-                      int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-  return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, status, ws, ws_bytes,
-                stream, false);
+                      double* resid, int32_t* iters, int32_t* status, void* ws,
+                      size_t ws_bytes, void* stream) {
+  return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, resid, iters, status, ws,
+                ws_bytes, stream, false);
 }
 
 mi_status mi_doi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
@@ -1621,9 +1874,10 @@ mi_status mi_doi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* pr
 mi_status mi_oi_track_per_block(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                                 const int32_t* row_ptr, const int32_t* col, const float* val,
                                 const int64_t* nnz_off, const void* V0, void* V, double* ritz,
-                                int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-  return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, status, ws, ws_bytes,
-                stream, true);
+                                double* resid, int32_t* iters, int32_t* status, void* ws,
+                                size_t ws_bytes, void* stream) {
+  return oi_run(ctx, blk, prm, row_ptr, col, val, nnz_off, V0, V, ritz, resid, iters, status, ws,
+                ws_bytes, stream, true);
 }
 
 }  // extern "C"

@@ -11,7 +11,7 @@ namespace mis {
 
 struct BlkInfo {
   int64_t t_off;
-  int32_t n, p, pred, pad;
+  int32_t n, p, pred, c;  // c: kept pairs of the tolerance test
 };
 
 struct WaveTables {
@@ -48,6 +48,11 @@ struct WsLayout {
   size_t slab[4], G, H, Rinv, T1, A, Z, S64, S32, Wk, pk, log, perm, tri, part, a_lo, b_hi, coef,
       conv;
   size_t cg_part;    // R^z: three tile-partial buffers [tiles][cg_ldp] (0 without R^z)
+  size_t rpart;      // residual norms: per-tile column partials [tiles][cg_ldp]
+  // tolerance mode only (zero-size otherwise): the working basis, Ritz values
+  // and residuals of the current iteration, and per-block flags (frozen,
+  // frozen in this iteration)
+  size_t slab_w, ritz_w, resid_w, frozen, fnow;
   int cg_ldp = 0;    // largest ld (row stride of the partials)
   int64_t cg_tiles = 0;  // 16-row tiles of all blocks
   size_t part_lane;  // Gram partial doubles of one stream lane
@@ -140,6 +145,8 @@ struct Args {
   const OiRecord* rec;  // checkpoints to write (eager runs only), or null
   bool fork;            // run the plan's lanes on its lane streams (graph capture)
   const DoiArgs* doi = nullptr;  // the walk of Alg. 2 instead of fixed iterations
+  double* resid = nullptr;       // residual norms of the returned pairs, or null
+  int32_t* iters = nullptr;      // iterations of the returned result per block, or null
 };
 
 // Runs the tracking eagerly on `s` with the plan held in *slot (created or

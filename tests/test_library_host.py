@@ -108,7 +108,8 @@ def test_residual_and_adjoint_workspace_queries():
     assert n.value == 8 * (19 * 64 + 32 * 64)
     nnz = np.array([0, 2000, 5500], np.int64)
     nnz_p = nnz.ctypes.data_as(C.POINTER(C.c_int64))
-    ok = mis.OiParams(warm=mis.MI_WARM_GIVEN, adapt=0, T0=2, passes0=2, m0=4)
+    ok = mis.OiParams(warm=mis.MI_WARM_GIVEN, adapt=0, T0=2, passes0=2, m0=4, a_mode=mis.MI_A_ABS,
+                      a_value=1.0, b_abs=10.0)
 
     def q(prm, blocks=b):
         return L.lib().mi_adjoint_workspace_size(None, blocks.ref, C.byref(prm.struct()), nnz_p,
@@ -116,7 +117,8 @@ def test_residual_and_adjoint_workspace_queries():
 
     assert q(ok) == 0 and n.value > 0
     for field, value in (("warm", mis.MI_WARM_PRED), ("adapt", 1), ("rr_every", 1),
-                         ("eig", L.MI_EIG_JACOBI), ("T0", 0)):
+                         ("eig", L.MI_EIG_JACOBI), ("T0", 0), ("b_abs", 0.0),
+                         ("a_mode", mis.MI_A_WEYL), ("tol", 1e-6), ("warm", mis.MI_RANDOM)):
         bad = mis.OiParams(**{**ok.__dict__, field: value})
         assert q(bad) == L.MI_ERR_ARG, field
     wide = mis.Blocks([300, 500], p=[40, 200])
@@ -124,10 +126,34 @@ def test_residual_and_adjoint_workspace_queries():
 
 
 def test_params_struct_layout_matches_header():
-    # 14 int32 fields, 3 doubles, 4 int32 (operator fields), delta
-    assert C.sizeof(L.MiOiParams) == 56 + 3 * 8 + 16 + 8
+    # 14 int32 fields, 3 doubles, 4 int32 (operator fields), delta, tol, seed
+    assert C.sizeof(L.MiOiParams) == 56 + 3 * 8 + 16 + 8 + 8 + 8
     assert L.MiOiParams.a_value.offset == 56 and L.MiOiParams.autotune.offset == 52
     assert L.MiOiParams.op.offset == 80 and L.MiOiParams.delta.offset == 96
+    assert L.MiOiParams.tol.offset == 104 and L.MiOiParams.seed.offset == 112
+    # the block table: n_blocks, then six pointers
+    assert C.sizeof(L.MiBlocks) == 8 + 6 * 8 and L.MiBlocks.c.offset == 48
+
+
+def test_tolerance_and_seeded_start_params():
+    b = mis.Blocks([100, 80], p=[10, 12])
+    assert _oi_ws(b, mis.OiParams(warm=mis.MI_RANDOM))[0] == 0
+    assert _oi_ws(b, mis.OiParams(tol=1e-6, T=4, T0=4))[0] == 0
+    for kw in (dict(warm=3), dict(tol=-1.0), dict(tol=1.5), dict(tol=1e-6, T0=0),
+               dict(tol=1e-6, T=0)):
+        assert _oi_ws(b, mis.OiParams(**kw))[0] == L.MI_ERR_ARG, kw
+    # kept pairs outside [1, p_b]
+    for c in ([0, 5], [11, 5], [10, 13]):
+        bad = mis.Blocks([100, 80], p=[10, 12], c=c)
+        assert _oi_ws(bad, mis.OiParams(tol=1e-6))[0] == L.MI_ERR_CAPACITY, c
+    assert _oi_ws(mis.Blocks([100, 80], p=[10, 12], c=[10, 1]), mis.OiParams(tol=1e-6))[0] == 0
+    # the dynamic walk has its own stopping rule and takes no seeded start
+    dp = L.MiDoiParams(0.01, 0.02, 8, 5)
+    n = C.c_size_t()
+    for kw in (dict(warm=mis.MI_RANDOM), dict(tol=1e-6)):
+        prm = mis.OiParams(**kw)
+        assert L.lib().mi_doi_workspace_size(None, b.ref, C.byref(prm.struct()), C.byref(dp),
+                                             C.byref(n)) == L.MI_ERR_ARG, kw
 
 
 def test_quality_report_argument_checks():

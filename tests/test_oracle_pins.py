@@ -319,6 +319,126 @@ class TestMetrics:
         assert np.allclose(e, (X - U[:, :5] @ (U[:, :5].T @ X)).sum(1))
 
 
+class TestHandWorkedWeights:
+    """Distance weights (Eq. 2 and the GL operator of Eq. 16) and the Eq. 6
+    residual on meshes small enough to work out by hand, with unequal edge
+    lengths, so that 1/d and 1/d^2 (or a sum and a mean) give different
+    numbers."""
+
+    # right triangle with legs 1 and 2: edges (0,1) d = 1, (0,2) d = 2, (1,2) d = sqrt 5
+    TRI_X = np.array([[0., 0, 0], [1, 0, 0], [0, 2, 0]])
+    TRI_F = np.array([[0, 1, 2]])
+    # three vertices on a line at x = 0, 1, 3: edges (0,1) d = 1, (1,2) d = 2
+    PATH_X = np.array([[0., 0, 0], [1, 0, 0], [3, 0, 0]])
+    PATH_E = np.array([[0, 1], [1, 2]])
+
+    def test_right_triangle_inverse_square_weights(self):
+        e = lap.canonical_edges(self.TRI_F, 3)
+        assert e.tolist() == [[0, 1], [0, 2], [1, 2]]
+        w = lap.edge_weights(e, self.TRI_X, lap.INV_SQ_DIST)
+        assert np.allclose(w, [1.0, 0.25, 0.2], rtol=0, atol=1e-15)
+        L = lap.laplacian_dense(3, e, w)
+        want = np.array([[1.25, -1.0, -0.25],
+                         [-1.0, 1.2, -0.2],
+                         [-0.25, -0.2, 0.45]])
+        assert np.abs(L - want).max() < 1e-15
+
+    def test_right_triangle_inverse_distance_weights(self):
+        e = lap.canonical_edges(self.TRI_F, 3)
+        w = lap.edge_weights(e, self.TRI_X, lap.INV_DIST)
+        assert np.allclose(w, [1.0, 0.5, 1.0 / math.sqrt(5.0)], rtol=0, atol=1e-15)
+
+    def test_gl_on_a_path_with_unequal_lengths(self):
+        # GL(v_1) = v_1 - (v_0 / 1 + v_2 / 2) / (1 + 1/2); the ends have one neighbour
+        G = met.gl_matrix(3, self.PATH_E, self.PATH_X)
+        want = np.array([[1.0, -1.0, 0.0],
+                         [-2.0 / 3.0, 1.0, -1.0 / 3.0],
+                         [0.0, -1.0, 1.0]])
+        assert np.abs(G - want).max() < 1e-15
+        Y = np.array([[2.0, -1.0, 0.5], [4.0, 3.0, -2.0], [-6.0, 9.0, 1.0]])
+        assert np.abs(met.gl_apply(3, self.PATH_E, self.PATH_X, Y) - want @ Y).max() < 1e-14
+        # middle row by hand for the first column: 4 - (2 + (-6)/2) / 1.5
+        assert math.isclose(met.gl_apply(3, self.PATH_E, self.PATH_X, Y)[1, 0],
+                            4.0 - (2.0 - 3.0) / 1.5, rel_tol=1e-15)
+
+    def test_nmsve_on_a_path_with_unequal_lengths(self):
+        # move end vertex 0 by 0.6 along y: the l2 term is 0.6; G times the
+        # difference is (0.6, -0.4, 0) along y (row 1 weighs vertex 0 by 2/3)
+        Xr = self.PATH_X.copy()
+        Xr[0, 1] += 0.6
+        want = (0.6 + math.sqrt(0.36 + 0.16)) / (2 * 3)
+        G = met.gl_matrix(3, self.PATH_E, self.PATH_X)
+        assert math.isclose(met.nmsve(self.PATH_X, Xr, G), want, rel_tol=1e-14)
+        assert math.isclose(met.nmsve_mesh(3, self.PATH_E, self.PATH_X, Xr), want, rel_tol=1e-14)
+
+    def test_eq6_residual_by_hand(self):
+        # U = the constant unit vector (c = 1): v_j - U U^T v_j removes each
+        # coordinate's mean; Eq. 6 sums the three residual vectors
+        U = np.full((3, 1), 1.0 / math.sqrt(3.0))
+        X = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [7.0, 8.0, 10.0]])
+        e = met.doi_residual(U, X)
+        assert np.abs(e - np.array([-28.0 / 3.0, -1.0 / 3.0, 29.0 / 3.0])).max() < 1e-14
+
+
+class TestSubsetEigensolver:
+    """The subset driver that the block references use for large blocks
+    (k lowest pairs) against the closed form of the path graph, whose
+    spectrum is simple: lambda_k = 2 - 2 cos(k pi / n), u_k(i) ~ cos(k pi (i + 1/2) / n)."""
+
+    @pytest.mark.parametrize("n,k", [(40, 7), (64, 33)])
+    def test_lowest_pairs_of_a_path(self, n, k):
+        e = path_edges(n)
+        L = lap.laplacian_dense(n, lap.canonical_edges(e, n), np.ones(n - 1))
+        lam, U = S.eigh_lowest(L, k)
+        assert lam.shape == (k,) and U.shape == (n, k)
+        j = np.arange(k)
+        assert np.abs(lam - (2.0 - 2.0 * np.cos(j * np.pi / n))).max() < 1e-13
+        i = np.arange(n)[:, None]
+        Uc = np.cos(j[None, :] * np.pi * (i + 0.5) / n)
+        Uc /= np.linalg.norm(Uc, axis=0)
+        # simple spectrum: each column equals the closed form up to sign
+        assert np.abs(np.abs(np.sum(U * Uc, axis=0)) - 1.0).max() < 1e-12
+
+    def test_subset_equals_full_solve_on_a_mesh(self):
+        bs = W.grid_single(nx=9, ny=8, c=5, p=8)
+        X = bs.coords[0]
+        _, L = comb_L(bs.faces[0], X.shape[0])
+        lam_f, U_f = np.linalg.eigh(L)
+        lam_s, U_s = S.eigh_lowest(L, 20)
+        assert np.abs(lam_s - lam_f[:20]).max() < 1e-12
+        # compare at a cut with a clear gap
+        c = next(c for c in range(12, 20) if lam_f[c] - lam_f[c - 1] > 1e-3)
+        assert S.sin_theta_max(U_f[:, :c], U_s[:, :c]) < 1e-10
+
+
+def test_golden_grid32_fixture():
+    """tests/golden/grid32_combinatorial.txt (written by make_golden.py from the
+    oracle): the 32 x 32 single-submesh workload's sizes, lowest 76 eigenvalues
+    (the tracked width p = 75 plus one), NMSVE and l2 residual at c = 50.  A
+    regression pin of the oracle and the input generator; the GPU FP64 test
+    compares its Ritz values with the same file."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "grid32_combinatorial.txt")
+    rec = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        rec[k] = [float(x) for x in v]
+    bs = W.grid_single()
+    X = bs.coords[0]
+    n = X.shape[0]
+    e = lap.canonical_edges(bs.faces[0], n)
+    assert (n, e.shape[0], n + 2 * e.shape[0]) == (rec["n"][0], rec["edges"][0], rec["nnz"][0])
+    _, L = comb_L(bs.faces[0], n)
+    lam, U = S.eigh_lowest(L)
+    assert np.abs(lam[:76] - np.array(rec["lambda_1_to_76"])).max() < 1e-12
+    Xr = S.encode_decode(U[:, :50], X)
+    G = met.gl_matrix(n, e, X)
+    assert math.isclose(met.nmsve(X, Xr, G), rec["nmsve_c50"][0], rel_tol=1e-10)
+    assert math.isclose(float(np.linalg.norm(X - Xr)), rec["l2_residual_c50"][0], rel_tol=1e-10)
+
+
 # ---------------------------------------------------------------- Alg. 1, Section 4 rate
 
 class TestIterations:

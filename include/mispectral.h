@@ -127,7 +127,7 @@ typedef struct {
                         largest Rayleigh quotient of its basis)                    */
   int32_t eig;       /* eigen-solver of the Rayleigh-Ritz matrix: MI_EIG_TRIDIAG
                         (Householder tridiagonalisation, Sturm multisection and
-                        inverse iteration; used when every ld_b <= 192, else the
+                        inverse iteration; used when every ld_b <= 320, else the
                         Jacobi sweeps) or MI_EIG_JACOBI (parallel cyclic Jacobi) */
   int32_t autotune;  /* 1: when the plan is made (first call, or after the block
                         table, parameters or buffers change), time candidate launch

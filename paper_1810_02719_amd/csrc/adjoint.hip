@@ -598,7 +598,9 @@ static mi_status adj_check(const mi_oi_params* prm, const HostBlocks& hb) {
   MI_CHECK_ARG(prm->T0 >= 1, "the adjoint needs T0 >= 1");
   int max_ld = 0;
   for (int b = 0; b < hb.B; ++b) max_ld = std::max(max_ld, hb.ld[b]);
-  MI_CHECK_ARG(tri_eig_supported(max_ld), "the adjoint supports ld <= %d", TRI_MAX_LD);
+  // the widths the reverse sweep is tested at
+  constexpr int ADJ_MAX_LD = 192;
+  MI_CHECK_ARG(max_ld <= ADJ_MAX_LD, "the adjoint supports ld <= %d", ADJ_MAX_LD);
   return MI_OK;
 }
 

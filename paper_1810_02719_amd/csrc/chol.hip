@@ -15,11 +15,16 @@
 // panel next to the updated M row panel), so they share one MFMA routine.
 // Rinv = D M^T.
 //
-// Storage: 16 x 16 tiles in the FP64 MFMA accumulator layout, one register
-// slot per unordered tile pair (a <= b).  The slot holds G^(a, b) until panel
-// a has consumed it, then M(b, a): the Gram tile dies in the same step in
-// which that M tile is born, so G^ and M together fit in one triangle's
-// worth of registers.
+// Storage: 16 x 16 tiles in the FP64 MFMA accumulator layout, one slot per
+// unordered tile pair (a <= b).  The slot holds G^(a, b) until panel a has
+// consumed it, then M(b, a): the Gram tile dies in the same step in which
+// that M tile is born, so G^ and M together fit in one triangle's worth of
+// storage.  Up to ld = 192 every slot is a register tile.  Wider blocks (up
+// to ld = 320) keep the slots of the first tile rows in global scratch
+// (each lane stores and reloads only its own four values, so no other
+// wavefront touches them) and the rest in registers: a slot (a, b) is
+// rewritten once per panel K < b, so the slots with the largest b, the ones
+// rewritten most often, are the register ones.
 #include "small.hpp"
 
 namespace mis {
@@ -124,20 +129,24 @@ __device__ d4v diag_factor(d4v g, double* Di, int ldd, int lane, int* fl) {
 }  // namespace
 
 // NT = 16-tiles per dimension of the widest block of the launch
-// (ld <= 16 NT <= 192).
-template <int NT>
+// (ld <= 16 NT <= 320); SG = slots per wavefront kept in global scratch
+// (Wk, ld x ld per block, 16 SG x 256 doubles used).
+template <int NT, int SG>
 __global__ void __launch_bounds__(1024)
     k_chol_mfma(const SmallDesc* __restrict__ sds, const double* __restrict__ G,
-                double* __restrict__ Rinv, float* __restrict__ S32, int32_t* __restrict__ status) {
+                double* __restrict__ Wk, double* __restrict__ Rinv, float* __restrict__ S32,
+                int32_t* __restrict__ status) {
   constexpr int NPAIR = NT * (NT + 1) / 2;    // tile pairs (a <= b)
   constexpr int SLOTS = (NPAIR + 15) / 16;    // per wavefront
+  static_assert(SG >= 0 && SG <= SLOTS, "global slots");
   constexpr int LDB = 16 * NT + 4;            // panel buffer row stride (doubles)
   constexpr int LDD = 17;
-  __shared__ double bufA[16 * LDB];           // old panel: G^ row K | M row K
+  // bufA doubles as the 16 per-wavefront tile transposes of the stores
+  constexpr int LDA_SZ = 16 * LDB > 16 * 16 * 17 ? 16 * LDB : 16 * 16 * 17;
+  __shared__ double bufA[LDA_SZ];             // old panel: G^ row K | M row K
   __shared__ double bufB[16 * LDB];           // new panel: R row K  | M row K
   __shared__ double Dg[16 * LDD];             // R_KK^-1
   __shared__ double dsc[16 * NT];
-  __shared__ double tbuf[16][16 * 17];       // per-wavefront tile transpose for the stores
   __shared__ int flag;
 
   const SmallDesc d = sds[blockIdx.x];
@@ -162,17 +171,25 @@ __global__ void __launch_bounds__(1024)
   __syncthreads();
 
   // slot s of this wavefront: pair t = wave + 16 s in column-major upper
-  // order, a <= b
+  // order, a <= b; slots s < SG at gsl(s), the others in reg[s].  With
+  // global slots, pairs with b >= nk (past the block's own panels) are never
+  // touched: they would only produce zero padding, and skipping them keeps
+  // the global slots of a narrow block inside its own ld x ld scratch
+  // (256 t + 255 < ld^2 for t < nk (nk + 1) / 2).
   int ta[SLOTS], tb[SLOTS];
   d4v reg[SLOTS];
-#pragma unroll
+  d4v* gbase = reinterpret_cast<d4v*>(Wk + d.m_off) + 64 * wave + lane;
+  auto gsl = [&](int s) { return gbase + 1024 * s; };
+#pragma clang loop unroll(full)
   for (int s = 0; s < SLOTS; ++s) {
     const int t = wave + 16 * s;
-    int b = 0;
-    while ((b + 1) * (b + 2) / 2 <= t) ++b;
+    int b = 0;  // column of pair t: the number of x in [1, NT) with x (x + 1) / 2 <= t
+#pragma unroll
+    for (int x = 1; x < NT; ++x) b += (x * (x + 1) / 2 <= t) ? 1 : 0;
     const int a = t - b * (b + 1) / 2;
     ta[s] = t < NPAIR ? a : -1;
     tb[s] = t < NPAIR ? b : -1;
+    d4v v4;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = 16 * a + mq + 4 * q, j = 16 * b + mi;
@@ -181,71 +198,92 @@ __global__ void __launch_bounds__(1024)
         if (i < p && j < p) v = (i == j) ? 1.0 + CHOL_SHIFT : Gb[int64_t(i) * ld + j] * dsc[i] * dsc[j];
         else if (i == j) v = 1.0;  // identity padding
       }
-      reg[s][q] = v;
+      v4[q] = v;
+    }
+    if (s < SG) {
+      if (t < NPAIR && b < nk) *gsl(s) = v4;
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      reg[s] = v4;
     }
   }
 
   for (int K = 0; K < nk; ++K) {
     // launder the slot indices so that the compiler recomputes the per-slot
     // LDS addresses each step instead of keeping dozens of them live
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int s = 0; s < SLOTS; ++s) asm volatile("" : "+s"(ta[s]), "+s"(tb[s]));
+    // the same for the global slot addresses (one base, offsets per use)
+    if (SG > 0) asm volatile("" : "+v"(gbase));
     // 1: publish the Gram row panel and the old M row panel; the wavefront
     // that owns the diagonal tile factors it (M_KK = R_KK^-T into its slot
     // and the new M panel, R_KK^-1 into Dg)
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int s = 0; s < SLOTS; ++s) {
       const int a = ta[s], b = tb[s];
-      if (a == K) {
-        if (b == K) {
+      if ((SG == 0 || b < nk) && (a == K || (b == K && a >= 0))) {
+        d4v cur = s < SG ? *gsl(s) : reg[s];
+        if (a == K && b == K) {
           int fl = 0;
-          reg[s] = diag_factor(reg[s], Dg, LDD, lane, &fl);
+          cur = diag_factor(cur, Dg, LDD, lane, &fl);
           if (lane == 0 && fl) atomicOr(&flag, fl);
+          if (s < SG) *gsl(s) = cur;
+          else reg[s] = cur;
         } else {
+          const int c = a == K ? b : a;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) bufA[(mq + 4 * q) * LDB + 16 * b + mi] = reg[s][q];
+          for (int q = 0; q < 4; ++q) bufA[(mq + 4 * q) * LDB + 16 * c + mi] = cur[q];
         }
-      } else if (b == K && a >= 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bufA[(mq + 4 * q) * LDB + 16 * a + mi] = reg[s][q];
       }
+      if (s < SG) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     // 3: R row panel and new M row panel (both: R_KK^-T times the old panel)
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int s = 0; s < SLOTS; ++s) {
       const int a = ta[s], b = tb[s];
-      if (a == K && b > K) {
+      if (a == K && b > K && (SG == 0 || b < nk)) {
         d4v acc = {0.0, 0.0, 0.0, 0.0};
         acc = tile_tn(acc, Dg, LDD, 0, bufA, LDB, b, 1.0, lane);
 #pragma unroll
         for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * b + mi] = acc[q];
-        reg[s] = d4v{0.0, 0.0, 0.0, 0.0};  // the slot now holds M(b, a) = 0
+        // the slot now holds M(b, a) = 0
+        if (s < SG) *gsl(s) = d4v{0.0, 0.0, 0.0, 0.0};
+        else reg[s] = d4v{0.0, 0.0, 0.0, 0.0};
       } else if (a == K && b == K) {
         // M_KK (already in the slot) joins the new M panel; written only now
         // because other wavefronts read bufB in the previous step 4
+        const d4v cur = s < SG ? *gsl(s) : reg[s];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * K + mi] = reg[s][q];
+        for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * K + mi] = cur[q];
       } else if (b == K && a >= 0) {
         d4v acc = {0.0, 0.0, 0.0, 0.0};
         acc = tile_tn(acc, Dg, LDD, 0, bufA, LDB, a, 1.0, lane);
-        reg[s] = acc;
+        if (s < SG) *gsl(s) = acc;
+        else reg[s] = acc;
 #pragma unroll
         for (int q = 0; q < 4; ++q) bufB[(mq + 4 * q) * LDB + 16 * a + mi] = acc[q];
       }
+      if (s < SG) __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
     // 4: trailing updates of G^ (a, b > K) and of M (row b > K, column a <= K)
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int s = 0; s < SLOTS; ++s) {
       const int a = ta[s], b = tb[s];
-      if (a > K) reg[s] = tile_tn(reg[s], bufB, LDB, a, bufB, LDB, b, -1.0, lane);
-      else if (b > K && a >= 0) reg[s] = tile_tn(reg[s], bufB, LDB, b, bufB, LDB, a, -1.0, lane);
+      if ((SG == 0 || b < nk) && (a > K || (b > K && a >= 0))) {
+        d4v cur = s < SG ? *gsl(s) : reg[s];
+        if (a > K) cur = tile_tn(cur, bufB, LDB, a, bufB, LDB, b, -1.0, lane);
+        else cur = tile_tn(cur, bufB, LDB, b, bufB, LDB, a, -1.0, lane);
+        if (s < SG) *gsl(s) = cur;
+        else reg[s] = cur;
+      }
       __builtin_amdgcn_sched_barrier(0);  // one tile's operands live at a time
     }
     // the next step 1 writes bufA and Dg only; the barrier after it orders
     // these bufB reads before the next step 3
   }
+  __syncthreads();  // bufA is reused as the transpose buffers below
 
   // Rinv[r][c] = dsc[r] M[c][r] for r <= c < p; zero elsewhere.  Slot (a, b)
   // holds M(b, a) and writes the two transposed tiles (a, b) and (b, a); the
@@ -253,14 +291,16 @@ __global__ void __launch_bounds__(1024)
   // lanes store consecutive columns.
   double* Rb = Rinv + d.m_off;
   float* Sb = S32 ? S32 + d.m_off : nullptr;
-  double* tw = tbuf[wave];
-#pragma unroll
+  double* tw = bufA + wave * (16 * 17);
+#pragma clang loop unroll(full)
   for (int s = 0; s < SLOTS; ++s) {
     const int a = ta[s], b = tb[s];
     if (a < 0) continue;
+    // tiles past the block's panels only hold padding: their outputs are 0
+    const d4v cur = (SG > 0 && b >= nk) ? d4v{0.0, 0.0, 0.0, 0.0} : s < SG ? *gsl(s) : reg[s];
     // tw[x][y] = M(b, a)[y][x]
 #pragma unroll
-    for (int q = 0; q < 4; ++q) tw[mi * 17 + mq + 4 * q] = reg[s][q];
+    for (int q = 0; q < 4; ++q) tw[mi * 17 + mq + 4 * q] = cur[q];
     wave_sync();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -289,19 +329,29 @@ __global__ void __launch_bounds__(1024)
   if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
 }
 
-bool launch_chol_mfma(const SmallDesc* sd, int nb, const double* G, double* Rinv, float* S32,
-                      int32_t* status, int max_ld, hipStream_t s) {
-  switch ((max_ld + 31) / 32) {
+bool launch_chol_mfma(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
+                      float* S32, int32_t* status, int max_ld, hipStream_t s) {
+  // at most 5 register slots per wavefront (3 above ld = 192, where the global
+  // slots need registers of their own; more spill at 128 VGPRs); the rest in Wk
 #define MI_CHOL_CASE(N)                                                                         \
-  case N:                                                                                       \
-    hipLaunchKernelGGL(k_chol_mfma<2 * N>, dim3(nb), dim3(1024), 0, s, sd, G, Rinv, S32, status); \
-    return true;
+  case N: {                                                                                     \
+    constexpr int NT = 2 * N, SL = (NT * (NT + 1) / 2 + 15) / 16;                              \
+    constexpr int RS = NT <= 12 ? 5 : NT <= 16 ? 3 : 2, SG = SL > RS ? SL - RS : 0;             \
+    hipLaunchKernelGGL((k_chol_mfma<NT, SG>), dim3(nb), dim3(1024), 0, s, sd, G, Wk, Rinv, S32, \
+                       status);                                                                 \
+    return true;                                                                                \
+  }
+  switch ((max_ld + 31) / 32) {
     MI_CHOL_CASE(1)
     MI_CHOL_CASE(2)
     MI_CHOL_CASE(3)
     MI_CHOL_CASE(4)
     MI_CHOL_CASE(5)
     MI_CHOL_CASE(6)
+    MI_CHOL_CASE(7)
+    MI_CHOL_CASE(8)
+    MI_CHOL_CASE(9)
+    MI_CHOL_CASE(10)
 #undef MI_CHOL_CASE
     default:
       return false;

@@ -72,7 +72,11 @@ __global__ void __launch_bounds__(256)
 constexpr int SPMM_GATHER = 8;
 constexpr int NUM_XCD = 8;
 
-template <typename T, int EPL>
+// With STRIDED, lane l owns the row's columns l, l + 64, ..., so that each
+// of its EPL loads is one coalesced 256-byte (FP32) wavefront access; used
+// for EPL = 5 (320-wide slabs), where EPL consecutive elements would not
+// form 16-byte vectors.
+template <typename T, int EPL, bool STRIDED = false>
 __global__ void __launch_bounds__(1024)
     k_spmm_row(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
@@ -91,21 +95,23 @@ __global__ void __launch_bounds__(1024)
   const int lane = threadIdx.x & 63;
   const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
   const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
-  const T* yv = Yin + d.off + lane * EPL;
+  constexpr int ES = STRIDED ? 64 : 1;  // element stride of a lane
+  const int l0 = STRIDED ? lane : lane * EPL;
+  const T* yv = Yin + d.off + l0;
   const int32_t* cb = col + c.nnz_off;
   const float* vb = val + c.nnz_off;
   // the row's own terms first: their loads overlap the row pointer ->
   // column -> neighbour chain of the gather (without a previous iterate the
   // third term reads the current one with weight 0, so both loads are
   // unconditional and issued here)
-  const int64_t o = d.off + int64_t(r) * d.ld + lane * EPL;
+  const int64_t o = d.off + int64_t(r) * d.ld + l0;
   const T* yp = Yprev ? Yprev : Yin;
   const T g3 = Yprev ? gamma : (T)0;
   T yin[EPL], ypr[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    yin[e] = Yin[o + e];
-    ypr[e] = yp[o + e];
+    yin[e] = Yin[o + e * ES];
+    ypr[e] = yp[o + e * ES];
   }
   const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
   T acc[EPL], base[EPL];
@@ -121,7 +127,7 @@ __global__ void __launch_bounds__(1024)
       w[u] = in ? (T)vb[k0 + u] : (T)0;
       const T* src = yv + int64_t(in ? cb[k0 + u] : r) * d.ld;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) y[u][e] = src[e];
+      for (int e = 0; e < EPL; ++e) y[u][e] = src[e * ES];
     }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
@@ -145,7 +151,7 @@ __global__ void __launch_bounds__(1024)
       w[u] = k + u < k1 ? (T)vb[kk] : (T)0;
       const T* src = yv + int64_t(cb[kk]) * d.ld;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) y[u][e] = src[e];
+      for (int e = 0; e < EPL; ++e) y[u][e] = src[e * ES];
     }
 #pragma unroll
     for (int u = 0; u < SPMM_GATHER; ++u)
@@ -156,7 +162,7 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
   for (int e = 0; e < EPL; ++e) out[e] = alpha * acc[e] + base[e];
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) Yout[o + e] = out[e];
+  for (int e = 0; e < EPL; ++e) Yout[o + e * ES] = out[e];
 }
 
 // The same product with two rows per wavefront: both rows' loads are in
@@ -281,6 +287,11 @@ void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const C
     MI_SPMM_ROW(2)
     MI_SPMM_ROW(3)
     MI_SPMM_ROW(4)
+    case 5:
+      hipLaunchKernelGGL((k_spmm_row<T, 5, true>), dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)),
+                         dim3(64 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin,
+                         Yprev, Yout, coef, coef_stride, step, ntiles);
+      return;
     default:
       break;
   }
@@ -662,7 +673,7 @@ int spmm_epl(const std::vector<MatDesc>& sets) {
   const int ld = sets[0].ld;
   for (const MatDesc& d : sets)
     if (d.ld != ld) return 0;
-  return (ld % 64 == 0 && ld <= 256) ? ld / 64 : 0;
+  return (ld % 64 == 0 && ld <= 320) ? ld / 64 : 0;
 }
 
 void spmm_tables(const std::vector<MatDesc>& sets, std::vector<SpmmTile>* tiles) {

@@ -65,7 +65,7 @@ void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const C
                  const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
                  hipStream_t s, int epl = 0);
 // Elements per lane of the wavefront-per-row SpMM when every block of a
-// launch has the same ld, a multiple of 64 up to 256; 0 otherwise.
+// launch has the same ld, a multiple of 64 up to 320; 0 otherwise.
 int spmm_epl(const std::vector<MatDesc>& sets);
 
 template <typename T>

@@ -1,8 +1,9 @@
 // Symmetric eigen-decomposition of the Rayleigh-Ritz matrices A (p x p,
-// FP64, p <= 192) of a wave of blocks, in four launches:
+// FP64, p <= 320) of a wave of blocks, in four launches:
 //
 //   1. k_tri_reduce   Householder tridiagonalisation T = Q^T A Q, one
-//                     workgroup per block with A resident in registers.
+//                     workgroup per block with A resident in registers
+//                     (k_tri_reduce_g with A in global memory above 192).
 //   2. k_tri_bisect   every eigenvalue of T by Sturm-count multisection
 //                     (ascending, so the Ritz order comes for free).
 //   3. k_tri_vectors  eigenvectors of T: the twisted factorisation of
@@ -324,6 +325,128 @@ __global__ void __launch_bounds__(TRI_THREADS)
   if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
 }
 
+// Wider blocks (192 < ld <= TRI_MAX_LD): the same reflectors with the
+// matrix in global memory (the block's A, overwritten), one workgroup of
+// TRI_G_THREADS per block.  Row k right of the diagonal is column k below it
+// (A is kept full and symmetric), so thread i reads x_i = A[k][i] with one
+// coalesced row load.  Step k: the norm of x (block sum), alpha, beta and v
+// (v_{k+1} = x_{k+1} - alpha, zero at and above k) into LDS and row k of Hv;
+// p = beta A v over the trailing rows, one wavefront per row and lanes over
+// columns; K = (beta/2) v^T p, w = p - K v; A -= v w^T + w v^T on the
+// trailing block, again one wavefront per row.  Four barriers per step; the
+// sums run in a fixed order (wavefront tree, then the 16 wavefront partials
+// in order), so the result does not depend on the launch.
+constexpr int TRI_G_THREADS = 1024;
+constexpr int TRI_G_WAVES = TRI_G_THREADS / 64;
+
+// Sum over the workgroup of one value per thread; every thread gets it.
+__device__ __forceinline__ double tri_g_sum(double v, double* part) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < TRI_G_WAVES; ++w) t += part[w];
+  return t;
+}
+
+__global__ void __launch_bounds__(TRI_G_THREADS)
+    k_tri_reduce_g(const SmallDesc* __restrict__ sds, double* __restrict__ A,
+                   double* __restrict__ Hv, double* __restrict__ tri, int32_t* __restrict__ status) {
+  __shared__ double vv[TRI_MAX_LD], ww[TRI_MAX_LD];
+  __shared__ double sdd[TRI_MAX_LD], see[TRI_MAX_LD], sbb[TRI_MAX_LD];
+  __shared__ double part[2][TRI_G_WAVES];
+  __shared__ int flag;
+  const SmallDesc d = sds[blockIdx.x];
+  const int p = d.p, ld = d.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Ab = A + d.m_off;
+  double* Hb = Hv + d.m_off;
+  if (tid == 0) flag = 0;
+  __syncthreads();
+  {
+    bool bad = false;
+    for (int i = wave; i < p; i += TRI_G_WAVES)
+      for (int j = lane; j < p; j += 64) bad = bad || !isfinite(Ab[int64_t(i) * ld + j]);
+    if (bad) atomicOr(&flag, MI_BLOCK_NONFINITE);
+  }
+  for (int k = 0; k + 2 < p; ++k) {
+    const int k1 = k + 1;
+    // 1: the reflector of column k
+    const double x = (tid > k && tid < p) ? Ab[int64_t(k) * ld + tid] : 0.0;
+    const double ss = tri_g_sum(x * x, part[k & 1]);
+    const double x1 = Ab[int64_t(k) * ld + k1];
+    double al, be;
+    if (ss <= DBL_MIN) {
+      al = x1;
+      be = 0.0;
+    } else {
+      al = -copysign(sqrt_pos(ss), x1);
+      be = recip(al * (al - x1));
+    }
+    const double v = x - (tid == k1 ? al : 0.0);
+    if (tid < TRI_MAX_LD) vv[tid] = v;
+    if (tid < ld) Hb[int64_t(k) * ld + tid] = v;
+    if (tid == 0) {
+      sdd[k] = Ab[int64_t(k) * ld + k];
+      see[k] = al;
+      sbb[k] = be;
+    }
+    __syncthreads();
+    // 2: p = beta A v over the trailing rows (two rows per wavefront at a time)
+    for (int i = k1 + wave; i < p; i += 2 * TRI_G_WAVES) {
+      const int i2 = i + TRI_G_WAVES;
+      const bool two = i2 < p;
+      double s1 = 0.0, s2 = 0.0;
+      for (int j = k1 + lane; j < p; j += 64) {
+        const double vj = vv[j];
+        s1 = fma(Ab[int64_t(i) * ld + j], vj, s1);
+        if (two) s2 = fma(Ab[int64_t(i2) * ld + j], vj, s2);
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        ww[i] = be * s1;
+        if (two) ww[i2] = be * s2;
+      }
+    }
+    __syncthreads();
+    // 3: w = p - K v with K = (beta / 2) v^T p
+    const double vp = tri_g_sum((tid > k && tid < p) ? vv[tid] * ww[tid] : 0.0, part[(k & 1) ^ 1]);
+    const double K = 0.5 * be * vp;
+    if (tid > k && tid < p) ww[tid] = fma(-K, vv[tid], ww[tid]);
+    __syncthreads();
+    // 4: A -= v w^T + w v^T on the trailing block
+    for (int i = k1 + wave; i < p; i += TRI_G_WAVES) {
+      const double vi = vv[i], wi = ww[i];
+      for (int j = k1 + lane; j < p; j += 64) {
+        const int64_t o = int64_t(i) * ld + j;
+        Ab[o] = fma(-vi, ww[j], fma(-wi, vv[j], Ab[o]));
+      }
+    }
+    __syncthreads();
+  }
+  // the last 2 x 2 (or 1 x 1) block is already tridiagonal
+  if (tid == 0) {
+    if (p >= 2) {
+      sdd[p - 2] = Ab[int64_t(p - 2) * ld + p - 2];
+      see[p - 2] = Ab[int64_t(p - 1) * ld + p - 2];
+      sbb[p - 2] = 0.0;
+    }
+    sdd[p - 1] = Ab[int64_t(p - 1) * ld + p - 1];
+    see[p - 1] = 0.0;
+    sbb[p - 1] = 0.0;
+  }
+  __syncthreads();
+  double* dd = tri + 4 * d.t_off;
+  for (int i = tid; i < p; i += TRI_G_THREADS) {
+    dd[i] = sdd[i];
+    dd[p + i] = see[i];
+    dd[3 * p + i] = sbb[i];
+  }
+  if (tid == 0 && flag) atomicOr(&status[d.blk], flag);
+}
+
 // ------------------------------------------------------------------ 2. eigenvalues
 // Count of eigenvalues of T below x = number of negative pivots of the
 // LDL^T factorisation of T - x I (Sylvester's law of inertia); pivots
@@ -458,15 +581,15 @@ __device__ void tri_inverse_iteration(const double* __restrict__ sd_, const doub
   }
 }
 
-constexpr int TRI_VEC_THREADS = 32;  // eigenvalues per workgroup (pivots in LDS)
-
-__global__ void __launch_bounds__(TRI_VEC_THREADS)
+// NT eigenvalues per workgroup (their pivots in LDS: 2 p NT doubles): 32
+// up to p = 192, 16 for wider blocks.
+template <int NT>
+__global__ void __launch_bounds__(NT)
     k_tri_vectors(const SmallDesc* __restrict__ sds, const double* __restrict__ tri,
                   double* __restrict__ DP, double* __restrict__ DM, double* __restrict__ ZT,
                   int32_t* __restrict__ status) {
   extern __shared__ double smem[];
   __shared__ double red[3];
-  constexpr int NT = TRI_VEC_THREADS;
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
   const int tx = threadIdx.x;
@@ -657,9 +780,14 @@ bool tri_eig_supported(int max_ld) { return max_ld <= TRI_MAX_LD; }
     hipLaunchKernelGGL(k_tri_back<R>, dim3(nb, max_ld / 32), dim3(TRI_BACK_THREADS), 0, s, sd, ZT, Hv, tri, Z); \
     break;
 
-void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, const double* A, double* Hv,
+void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, double* A, double* Hv,
                        double* tri, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
+  if (max_ld > 32 * 6) {
+    hipLaunchKernelGGL(k_tri_reduce_g, dim3(nb), dim3(TRI_G_THREADS), 0, s, sd, A, Hv, tri,
+                       status);
+    return;
+  }
   switch ((max_ld + 31) / 32) {
     MI_TRI_CASE(1)
     MI_TRI_CASE(2)
@@ -688,10 +816,14 @@ void launch_tri_bisect(const SmallDesc* sd, int nb, int max_p, double* tri, doub
 void launch_tri_vectors(const SmallDesc* sd, int nb, int max_p, const double* tri, double* DP,
                         double* DM, double* ZT, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_tri_vectors, dim3(nb, ceil_div(max_p, TRI_VEC_THREADS)),
-                     dim3(TRI_VEC_THREADS),
-                     size_t(2 * max_p + 2 * max_p * TRI_VEC_THREADS) * sizeof(double), s, sd, tri,
-                     DP, DM, ZT, status);
+  if (max_p <= 192)
+    hipLaunchKernelGGL(k_tri_vectors<32>, dim3(nb, ceil_div(max_p, 32)), dim3(32),
+                       size_t(2 * max_p + 2 * max_p * 32) * sizeof(double), s, sd, tri, DP, DM,
+                       ZT, status);
+  else
+    hipLaunchKernelGGL(k_tri_vectors<16>, dim3(nb, ceil_div(max_p, 16)), dim3(16),
+                       size_t(2 * max_p + 2 * max_p * 16) * sizeof(double), s, sd, tri, DP, DM,
+                       ZT, status);
 }
 
 void launch_tri_back(const SmallDesc* sd, int nb, int max_ld, const double* ZT, const double* Hv,
@@ -704,6 +836,10 @@ void launch_tri_back(const SmallDesc* sd, int nb, int max_ld, const double* ZT, 
     MI_TRI_BACK_CASE(4)
     MI_TRI_BACK_CASE(5)
     MI_TRI_BACK_CASE(6)
+    MI_TRI_BACK_CASE(7)
+    MI_TRI_BACK_CASE(8)
+    MI_TRI_BACK_CASE(9)
+    MI_TRI_BACK_CASE(10)
     default: break;
   }
 }

@@ -1,5 +1,5 @@
 // Symmetric eigen-decomposition of the per-block Rayleigh-Ritz matrices by
-// Householder tridiagonalisation (see eig.hip).  Used for p <= TRI_MAX_LD;
+// Householder tridiagonalisation (see eig.hip).  Used for ld <= TRI_MAX_LD;
 // wider blocks take the Jacobi sweeps of small.hpp.
 #pragma once
 
@@ -7,13 +7,14 @@
 
 namespace mis {
 
-constexpr int TRI_MAX_LD = 192;
+constexpr int TRI_MAX_LD = 320;
 
 bool tri_eig_supported(int max_ld);
 
 // A (ld x ld at m_off, p x p used) -> d, e, beta in tri[4 t_off ..] (layout
-// d[p] e[p] lambda[p] beta[p]) and the reflectors in the rows of Hv.
-void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, const double* A, double* Hv,
+// d[p] e[p] lambda[p] beta[p]) and the reflectors in the rows of Hv.  Above
+// ld = 192 the reduction works in place in A (its contents are destroyed).
+void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, double* A, double* Hv,
                        double* tri, int32_t* status, hipStream_t s);
 // Eigenvalues ascending -> lambda in tri, ritz[t_off + j], perm[t_off + j] = j,
 // a_lo[blk] = largest when adapt.  Flags NOCONV / NONFINITE.

@@ -17,7 +17,7 @@ __device__ inline double wave_max(double v) {
 }
 
 // Cholesky of the scaled Gram and the inverse factor for blocks wider than
-// 192 (narrower ones use the MFMA kernel in chol.hip), with 32-wide panels, so that only the 32 x 32
+// 320 (narrower ones use the MFMA kernel in chol.hip), with 32-wide panels, so that only the 32 x 32
 // diagonal tiles are factored step by step (inside one wavefront, one tile
 // column per lane in registers, pivots and row entries broadcast by
 // shuffles); the panel solves, trailing updates and the blocked inverse are
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256)
 void launch_chol_blk(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
                      float* S32, int32_t* status, int max_ld, int lds_max, hipStream_t s) {
   if (nb <= 0) return;
-  if (launch_chol_mfma(sd, nb, G, Rinv, S32, status, max_ld, s)) return;  // ld <= 192
+  if (launch_chol_mfma(sd, nb, G, Wk, Rinv, S32, status, max_ld, s)) return;  // ld <= 320
   const size_t pl = size_t(CB) * max_ld * sizeof(double);
   if (pl <= size_t(lds_max) - 40000)
     hipLaunchKernelGGL(k_chol_blk<true>, dim3(nb), dim3(256), pl, s, sd, G, Wk, Rinv, S32, status);

@@ -21,15 +21,15 @@ constexpr int SMALL_THREADS = 1024;
 // Cholesky of the column-scaled Gram G = R^T R and the inverse factor Rinv
 // (upper, FP64, zeros elsewhere); optionally Rinv rounded to FP32 (S32) for
 // the row product.  Sets MI_BLOCK_SHIFTED / _NOT_PD / _NONFINITE in status.
-// ld <= 192 runs the FP64-MFMA kernel of chol.hip, wider blocks a 32-panel
+// ld <= 320 runs the FP64-MFMA kernel of chol.hip, wider blocks a 32-panel
 // kernel with the working matrix Wk in global memory (ld x ld per block).
 void launch_chol_blk(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
                      float* S32, int32_t* status, int max_ld, int lds_max, hipStream_t s);
 
-// Blocked FP64-MFMA variant for ld <= 192 (chol.hip); false when max_ld is
-// wider.  Same outputs and flags.
-bool launch_chol_mfma(const SmallDesc* sd, int nb, const double* G, double* Rinv, float* S32,
-                      int32_t* status, int max_ld, hipStream_t s);
+// Blocked FP64-MFMA variant for ld <= 320 (chol.hip; above 192 part of its
+// tiles live in Wk); false when max_ld is wider.  Same outputs and flags.
+bool launch_chol_mfma(const SmallDesc* sd, int nb, const double* G, double* Wk, double* Rinv,
+                      float* S32, int32_t* status, int max_ld, hipStream_t s);
 
 // a[blk] <- max_j (Rinv^T H Rinv)_jj from T1 = H Rinv (largest Rayleigh
 // quotient of the Cholesky-QR basis).

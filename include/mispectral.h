@@ -456,6 +456,24 @@ mi_status mi_project(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const
 mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, const int32_t* c,
                          const void* U, const void* E, void* Xr, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * projection of mi_project, same arguments, layouts and result (the same
+ * kernels, bit for bit), with no workspace argument and no allocation of
+ * any kind.  Its block table and FP64 partial sums live in a fixed 16 MiB
+ * array in device memory that the library holds on every device it runs on
+ * until the process ends; the table is staged into it through kernel
+ * arguments.  Needs 48 B per block plus 16 x ld_b x 3 x 8 B of partials
+ * per block (about 170 blocks at ld = 256, 220 at ld = 192); a larger
+ * block table returns MI_ERR_WORKSPACE before anything is enqueued.  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (different streams, or host threads) race and must not be issued;
+ * calls on one stream are ordered.  Nothing in the array must start at zero
+ * (every partial is written before it is read).  Enqueue only. */
+mi_status mi_project_noalloc(mi_ctx* ctx, const mi_blocks* blk, int32_t precision,
+                             const int32_t* c, const void* U, const void* X, void* E,
+                             void* stream);
+
 /* ---------------------------------------------------------------- merge of overlapped submeshes
  * Section 6.1, Alg. 3: the submeshes overlap (each part extended with the
  * neighbours of its boundary vertices to n_d vertices), so a mesh vertex can

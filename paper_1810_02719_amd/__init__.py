@@ -358,6 +358,15 @@ def project(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, X: t
     return E
 
 
+def project_noalloc(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor,
+                    X: torch.Tensor, E: torch.Tensor, precision: int = MI_FP32) -> torch.Tensor:
+    """E = U_c^T X per block without any device allocation
+    (mi_project_noalloc): E must be given (device, [sum p_b * 3])."""
+    L.check(L.lib().mi_project_noalloc(ctx.h, blocks.ref, precision, _dptr(c), _dptr(U), _dptr(X),
+                                       _dptr(E), _stream()))
+    return E
+
+
 def reconstruct(ctx: Context, blocks: Blocks, c: torch.Tensor, U: torch.Tensor, E: torch.Tensor,
                 precision: int = MI_FP32, Xr: torch.Tensor | None = None) -> torch.Tensor:
     """X~ = U_c E per block."""

@@ -114,6 +114,7 @@ _SIGS = {
                           _vp],
     "mi_encdec_workspace_size": [_vp, C.POINTER(MiBlocks), C.c_int32, _szp],
     "mi_project": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
+    "mi_project_noalloc": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _vp, _vp],
     "mi_reconstruct": [_vp, C.POINTER(MiBlocks), C.c_int32, _vp, _vp, _vp, _vp, _vp],
     "mi_merge_overlapped": [_vp, C.POINTER(MiBlocks), _vp, C.c_int64, _vp, _vp, _vp, _vp],
     "mi_quantize": [_vp, C.POINTER(MiBlocks), _vp, C.c_int32, _vp, _vp, _vp, _vp, _vp],

@@ -6,6 +6,7 @@
 // vertex row); sums run in FP64 and in a fixed order, so results are
 // bitwise reproducible.
 #include <cstring>
+#include <mutex>
 
 #include "common.hpp"
 #include "kernels_util.hpp"
@@ -327,6 +328,58 @@ __global__ void __launch_bounds__(256)
 
 using namespace mis;
 
+// ------------------------------------------------------------------ allocation-free projection
+// mi_project_noalloc keeps what mi_project puts in the context's plan (the
+// block table) and in the caller's workspace (the FP64 partial sums) in this
+// fixed array instead.  Host code never passes the array's name to a kernel
+// (in host code it is only a stand-in for the symbol): every use goes
+// through the device address looked up for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;  // 16 MiB per device
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (each device holds its own copy of the array).
+mi_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    set_error("device %d outside the %d devices the fixed scratch tracks", dev,
+              NOALLOC_MAX_DEVICES);
+    return MI_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    MI_TRY_HIP(hipSetDevice(dev));
+    void* ptr = nullptr;
+    MI_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      set_error("hipGetSymbolAddress returned a null address for the fixed scratch");
+      return MI_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MI_OK;
+}
+
+// A host table reaches device memory through kernel arguments, STAGE_BYTES at
+// a time: the runtime copies the arguments, so nothing is allocated and the
+// host copy need not outlive the call.
+constexpr int STAGE_BYTES = 2048;
+struct StageChunk {
+  unsigned char b[STAGE_BYTES];
+};
+
+__global__ void __launch_bounds__(256) k_stage(StageChunk ch, int n, unsigned char* __restrict__ dst) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = ch.b[i];
+}
+
+}  // namespace
+
 extern "C" {
 
 mi_status mi_encdec_workspace_size(mi_ctx* ctx, const mi_blocks* blk, int32_t precision,
@@ -422,6 +475,79 @@ mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, c
     else
       hipLaunchKernelGGL(k_reconstruct<float>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff,
                          hb.B, N, c, (const float*)U, (const float*)E, (float*)Xr);
+  }
+  MI_TRY_HIP(hipGetLastError());
+  return MI_OK;
+}
+
+mi_status mi_project_noalloc(mi_ctx* ctx, const mi_blocks* blk, int32_t precision,
+                             const int32_t* c, const void* U, const void* X, void* E,
+                             void* stream) {
+  begin_call();
+  MI_CHECK_ARG(ctx && c && U && X && E, "NULL argument");
+  MI_CHECK_ARG(precision == MI_FP32 || precision == MI_FP64, "precision %d unsupported", precision);
+  HostBlocks hb;
+  mi_status st = load_blocks(blk, &hb, true);
+  if (st) return st;
+  for (int b = 0; b < hb.B; ++b)
+    MI_CHECK_ARG(hb.ld[b] <= 1024, "block %d: ld %d > 1024", b, hb.ld[b]);
+  // scratch layout: block table | partial offsets | FP64 partials
+  std::vector<int64_t> poff;
+  const int64_t nparts = proj_part_doubles(hb, &poff);
+  const size_t tab_bytes = size_t(hb.B) * sizeof(EncBlock);
+  const size_t poff_at = align_up(tab_bytes);
+  const size_t part_at = align_up(poff_at + size_t(hb.B) * sizeof(int64_t));
+  const size_t need = part_at + size_t(nparts) * sizeof(double);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    set_error("the projection needs %zu bytes of scratch; the fixed scratch holds %zu "
+              "(use mi_project with a workspace)", need, NOALLOC_SCRATCH_BYTES);
+    return MI_ERR_WORKSPACE;
+  }
+  MI_TRY_HIP(hipSetDevice(ctx->device));
+  void* base = nullptr;
+  st = scratch_address(ctx->device, &base);
+  if (st) return st;
+  std::vector<unsigned char> host(part_at, 0);
+  int max_ld = 0;
+  for (int b = 0; b < hb.B; ++b) {
+    const EncBlock e{hb.v_off[b], hb.u_off[b], hb.t_off[b], int(hb.v_off[b + 1] - hb.v_off[b]),
+                     hb.p[b], hb.ld[b], 0};
+    std::memcpy(host.data() + size_t(b) * sizeof(EncBlock), &e, sizeof(EncBlock));
+    max_ld = std::max(max_ld, hb.ld[b]);
+  }
+  if (hb.B > 0) std::memcpy(host.data() + poff_at, poff.data(), size_t(hb.B) * sizeof(int64_t));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* dbase = static_cast<unsigned char*>(base);
+  for (size_t o = 0; o < host.size(); o += STAGE_BYTES) {
+    StageChunk ch;
+    const int n = int(std::min<size_t>(STAGE_BYTES, host.size() - o));
+    std::memcpy(ch.b, host.data() + o, size_t(n));
+    hipLaunchKernelGGL(k_stage, dim3(1), dim3(256), 0, s, ch, n, dbase + o);
+  }
+  const EncBlock* dev = reinterpret_cast<const EncBlock*>(dbase);
+  const int64_t* dpoff = reinterpret_cast<const int64_t*>(dbase + poff_at);
+  double* part = reinterpret_cast<double*>(dbase + part_at);
+  const bool tiled = max_ld <= 64 * ENC_KPL;
+  if (hb.B > 0) {
+    if (precision == MI_FP64) {
+      if (tiled)
+        hipLaunchKernelGGL(k_project_part_w<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s,
+                           dev, dpoff, c, (const double*)U, (const double*)X, part);
+      else
+        hipLaunchKernelGGL(k_project_part<double>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, dev,
+                           dpoff, c, (const double*)U, (const double*)X, part);
+      hipLaunchKernelGGL(k_project_sum<double>, dim3(hb.B), dim3(256), 0, s, dev, dpoff, c, part,
+                         (double*)E);
+    } else {
+      if (tiled)
+        hipLaunchKernelGGL(k_project_part_w<float>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s,
+                           dev, dpoff, c, (const float*)U, (const float*)X, part);
+      else
+        hipLaunchKernelGGL(k_project_part<float>, dim3(hb.B, PROJ_CHUNKS), dim3(256), 0, s, dev,
+                           dpoff, c, (const float*)U, (const float*)X, part);
+      hipLaunchKernelGGL(k_project_sum<float>, dim3(hb.B), dim3(256), 0, s, dev, dpoff, c, part,
+                         (float*)E);
+    }
   }
   MI_TRY_HIP(hipGetLastError());
   return MI_OK;

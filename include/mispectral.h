@@ -65,6 +65,15 @@ typedef int32_t mi_status;
 /* Arithmetic of the tall-skinny products (SpMM, Gram operands, rotations). */
 #define MI_FP32 0
 #define MI_FP64 1
+#define MI_BF16_IN 2   /* mi_oi_track only: the working slabs of the filter and the
+                          Cholesky-QR (the inputs of the SpMM and Gram products) in
+                          bfloat16, rounded to nearest even, with FP32 accumulation
+                          inside a product and FP64 across a Gram's row chunks; FP64
+                          Cholesky and Rayleigh-Ritz solves; the row products in FP32;
+                          V0 and V are FP32 (float).  Chebyshev filter, fixed
+                          iteration counts, every block of a wave with the same ld
+                          (a multiple of 64 up to 320); not for the dynamic walk or
+                          the adjoint (MI_ERR_ARG). */
 
 /* Start subspace of a block in mi_oi_track. */
 #define MI_WARM_GIVEN 0 /* V0 holds a start for every block                          */
@@ -105,7 +114,7 @@ typedef struct {
 
 /* Parameters of the eigenspace tracking (mi_oi_track). */
 typedef struct {
-  int32_t precision; /* MI_FP32 or MI_FP64                                            */
+  int32_t precision; /* MI_FP32, MI_FP64 or MI_BF16_IN                                */
   int32_t warm;      /* MI_WARM_GIVEN, MI_WARM_PRED or MI_RANDOM                      */
   int32_t T;         /* outer iterations of blocks that have a predecessor            */
   int32_t m;         /* Chebyshev degree of one filter pass, same blocks              */
@@ -131,9 +140,9 @@ typedef struct {
                         Jacobi sweeps) or MI_EIG_JACOBI (parallel cyclic Jacobi) */
   int32_t autotune;  /* 1: when the plan is made (first call, or after the block
                         table, parameters or buffers change), time candidate launch
-                        shapes of the Gram (split-K) and the row product (output
-                        width) per wave on the plan's own tables and keep the
-                        fastest; 0: fixed heuristics.
+                        shapes of the Gram (split-K), the row product (output
+                        width) and the SpMM (variant) per wave on the plan's own
+                        tables and keep the fastest; 0: fixed heuristics.
                         The results agree to rounding (the Gram split changes the
                         summation order).  mi_oi_tuning reports the choice. */
   double a_value;
@@ -226,6 +235,13 @@ const char* mi_kernel_class_name(int32_t k);
  * caller's stream; totals restart from zero.  on = 0 stops timing and frees
  * the events.  Synchronous. */
 mi_status mi_ctx_set_timing(mi_ctx* ctx, int32_t on);
+/* Launch-shape override, for measurement and for checking the variants
+ * against each other: tracking plans made after the call (the plan is
+ * rebuilt when the variant differs) run the wavefront-per-row SpMM as
+ * `variant` (the codes of mi_oi_tuning, 0..6) in every wave that uses it,
+ * whatever the autotuner would pick; -1 restores the autotuner or the
+ * default.  MI_ERR_ARG for other values.  Host only. */
+mi_status mi_oi_force_spmm(mi_ctx* ctx, int32_t variant);
 /* Sums of the event-timed kernel durations (ms) and launch counts per class
  * since timing was switched on: total_ms and launches hold MI_K_COUNT
  * entries (host arrays).  Waits for the recorded events.  MI_ERR_ARG when
@@ -298,10 +314,10 @@ mi_status mi_laplacian_values(mi_ctx* ctx, const mi_blocks* blk, const int64_t* 
  * topological order); all blocks of a wave run in the same launches.
  *
  * val       device float [nnz] Laplacian values (FP32; promoted exactly in FP64 mode)
- * V0        device [u_off[B]] start slabs (float or double per precision);
+ * V0        device [u_off[B]] start slabs (double for MI_FP64, else float);
  *           MI_WARM_GIVEN: all blocks; MI_WARM_PRED: blocks without predecessor;
  *           MI_RANDOM: not read (may be NULL).
- * V         device [u_off[B]] output slabs (may alias V0).
+ * V         device [u_off[B]] output slabs, same type (may alias V0).
  * ritz      device double [sum p_b] Ritz values per block, ascending
  *           (block b at sum_{b'<b} p_b').
  * resid     device double [sum p_b] residual norms ||L v_j - theta_j v_j||_2 of
@@ -316,10 +332,16 @@ mi_status mi_laplacian_values(mi_ctx* ctx, const mi_blocks* blk, const int64_t* 
  * table, parameters and pointers stay the same. */
 mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                                size_t* ws_bytes);
-/* Launch shapes of the context's current tracking plan, three int32 per wave
+/* Launch shapes of the context's current tracking plan, four int32 per wave
  * (Gram split-K target in workgroups, row-product output width, SpMM elements
- * per lane or 0 for the generic kernel) for up to `cap` waves; *n_waves gets
- * the plan's wave count.  Host only. */
+ * per lane or 0 for the generic kernel, SpMM variant: 0 one row per
+ * wavefront gathering 8 neighbour rows at a time, 1 the same gathering 4,
+ * 2 two rows per wavefront, 3 one row per wavefront in 4-wavefront
+ * workgroups, 4 and 5 two and four rows per wavefront one after the other
+ * with their indices loaded first, 6 the same with two rows in
+ * 4-wavefront workgroups, -1 the default for the width) for up to `cap`
+ * waves; *n_waves
+ * gets the plan's wave count.  Host only. */
 mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves);
 
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,

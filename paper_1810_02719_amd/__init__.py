@@ -26,7 +26,7 @@ import torch
 
 from . import _lib as L
 from ._lib import MI_OP_CHEB, MI_OP_RZ  # noqa: F401
-from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_FP32, MI_FP64, MI_RANDOM,  # noqa: F401
+from ._lib import (MI_A_ABS, MI_A_RITZ, MI_A_WEYL, MI_BF16_IN, MI_FP32, MI_FP64, MI_RANDOM,  # noqa: F401
                    MI_W_COMBINATORIAL, MI_W_INV_DIST, MI_W_INV_SQ_DIST, MI_W_USER, MI_WARM_GIVEN,
                    MI_WARM_PRED, MiError)
 
@@ -113,12 +113,18 @@ class Context:
 
     def tuning(self):
         """Launch shapes of the current tracking plan: one (gram_target, nch,
-        spmm_elements_per_lane) triple per wave."""
+        spmm_elements_per_lane, spmm_variant) tuple per wave."""
         n = C.c_int32()
         L.check(L.lib().mi_oi_tuning(self.h, None, 0, C.byref(n)))
-        buf = (C.c_int32 * (3 * max(n.value, 1)))()
+        buf = (C.c_int32 * (4 * max(n.value, 1)))()
         L.check(L.lib().mi_oi_tuning(self.h, buf, n.value, C.byref(n)))
-        return [tuple(buf[3 * w:3 * w + 3]) for w in range(n.value)]
+        return [tuple(buf[4 * w:4 * w + 4]) for w in range(n.value)]
+
+    def force_spmm(self, variant: int = -1):
+        """Run later tracking plans' per-row SpMM as `variant` (0..6, the codes
+        `tuning()` reports) in every wave that uses it; -1 restores the
+        autotuner's or the default choice."""
+        L.check(L.lib().mi_oi_force_spmm(self.h, int(variant)))
 
     def set_timing(self, on: bool):
         """Per-kernel event timing of later oi_track / project / reconstruct
@@ -433,15 +439,18 @@ def mesh_quality(ctx: Context, n_vertices: int, row_ptr: torch.Tensor, col: torc
 
 
 def choose_c(ctx: Context, blocks: Blocks, c_max: torch.Tensor, target: float, g_min: float,
-             U: torch.Tensor, ritz: torch.Tensor, X: torch.Tensor, gl: Laplacian):
+             U: torch.Tensor, ritz: torch.Tensor, X: torch.Tensor, gl: Laplacian,
+             c_out: torch.Tensor | None = None, metric: torch.Tensor | None = None):
     """Per-block c for an NMSVE target (gl: the MI_W_INV_DIST Laplacian of the
     original mesh).  Returns (c, metric curve)."""
     lib = L.lib()
     ws_n = C.c_size_t()
     L.check(lib.mi_choose_c_workspace_size(ctx.h, blocks.ref, C.byref(ws_n)))
     ws = ctx.workspace("cc", ws_n.value)
-    c_out = torch.empty(blocks.n_blocks, dtype=torch.int32, device=U.device)
-    metric = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=U.device)
+    if c_out is None:
+        c_out = torch.empty(blocks.n_blocks, dtype=torch.int32, device=U.device)
+    if metric is None:
+        metric = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=U.device)
     L.check(lib.mi_choose_c(ctx.h, blocks.ref, _dptr(c_max), float(target), float(g_min), _dptr(U),
                             _dptr(ritz), _dptr(X), _dptr(gl.row_ptr), _dptr(gl.col), _dptr(gl.val),
                             _np_ptr(gl.nnz_off, C.c_int64), _dptr(c_out), _dptr(metric), _dptr(ws),

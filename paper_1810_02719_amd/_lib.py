@@ -28,6 +28,7 @@ MI_W_INV_DIST = 3
 
 MI_FP32 = 0
 MI_FP64 = 1
+MI_BF16_IN = 2
 
 MI_WARM_GIVEN = 0
 MI_WARM_PRED = 1
@@ -87,6 +88,7 @@ _SIGS = {
     "mi_ctx_create": [C.POINTER(_vp), C.c_int32],
     "mi_ctx_destroy": [_vp],
     "mi_ctx_set_timing": [_vp, C.c_int32],
+    "mi_oi_force_spmm": [_vp, C.c_int32],
     "mi_ctx_kernel_times": [_vp, C.POINTER(C.c_double), _i64p],
     "mi_laplacian_workspace_size": [C.POINTER(MiBlocks), _i64p, C.c_int32, _szp],
     "mi_build_laplacian_count": [_vp, C.POINTER(MiBlocks), _i64p, _vp, C.c_int32, _i64p, _i64p,

@@ -520,7 +520,7 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
   launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, static_cast<const T*>(rec.Y), w.small, Rc, w.tall, Q,
                       w.nch, s);
   launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, Q, nullptr, Wl, rec.coef,
-                 stride, m, s, w.epl);
+                 stride, m, s, w.epl, w.spmm_var);
   // projection and Rayleigh-Ritz adjoint
   hipLaunchKernelGGL(k_adj_tall6<T>, dim3(B, ADJ_CHUNKS), dim3(256), 0, s, A.dev, Q, X, G, part);
   hipLaunchKernelGGL(k_adj_sum6, dim3(B), dim3(256), 0, s, A.dev, part, EF);
@@ -554,7 +554,7 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
     for (int k = 0; k + 1 < m; ++k)
       launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y_at(k),
                      k > 0 ? y_at(k - 1) : nullptr, ys + int64_t(k) * slab, rec.coef, stride, k, s,
-                     w.epl);
+                     w.epl, w.spmm_var);
     // reverse recurrence
     int nxt = cur, prv = -1;
     for (int k = m - 1; k >= 0; --k) {
@@ -584,6 +584,7 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
 static mi_status adj_check(const mi_oi_params* prm, const HostBlocks& hb) {
   mi_status st = oi_check_params(prm);
   if (st) return st;
+  MI_CHECK_ARG(prm->precision != MI_BF16_IN, "the adjoint supports MI_FP32 and MI_FP64");
   MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN, "the adjoint needs warm = MI_WARM_GIVEN");
   MI_CHECK_ARG(prm->tol == 0, "the adjoint differentiates fixed iteration counts (tol = 0)");
   MI_CHECK_ARG(prm->op == MI_OP_CHEB, "the adjoint differentiates the Chebyshev filter only");

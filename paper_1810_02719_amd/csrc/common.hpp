@@ -167,4 +167,5 @@ struct mi_ctx {
   void* codec_plan = nullptr;  // block offsets of the quantiser (codec.hip)
   void* quality_plan = nullptr;  // partial sums of the quality report (quality.hip)
   mis::KTimer* timer = nullptr;  // non-null while timing is on
+  int spmm_force = -1;  // SpMM variant forced on later tracking plans (-1: autotune/default)
 };

@@ -1,6 +1,7 @@
 // Context, error reporting, block-table validation and a device-wide
 // exclusive scan used by the Laplacian builder.
 #include "common.hpp"
+#include "dense.hpp"
 #include "kernels_util.hpp"
 
 namespace mis {
@@ -272,6 +273,14 @@ mi_status mi_ctx_set_timing(mi_ctx* ctx, int32_t on) {
   MI_TRY_HIP(hipSetDevice(ctx->device));
   delete ctx->timer;
   ctx->timer = on ? new mis::KTimer() : nullptr;
+  return MI_OK;
+}
+
+mi_status mi_oi_force_spmm(mi_ctx* ctx, int32_t variant) {
+  mis::clear_error();
+  MI_CHECK_ARG(ctx != nullptr, "ctx is NULL");
+  MI_CHECK_ARG(variant >= -1 && variant < mis::SPMM_NVAR, "SpMM variant %d unknown", variant);
+  ctx->spmm_force = variant;
   return MI_OK;
 }
 

@@ -76,25 +76,33 @@ constexpr int NUM_XCD = 8;
 // of its EPL loads is one coalesced 256-byte (FP32) wavefront access; used
 // for EPL = 5 (320-wide slabs), where EPL consecutive elements would not
 // form 16-byte vectors.
-template <typename T, int EPL, bool STRIDED = false>
-__global__ void __launch_bounds__(1024)
+// With WPG = 4 a tile's 16 rows are split over four workgroups of four
+// wavefronts (same XCD, consecutive), so that more workgroups fit a CU when
+// the kernel's registers allow more wavefronts than one 16-wavefront group.
+template <typename T, int EPL, bool STRIDED = false, int G = SPMM_GATHER, int WPG = SPMM_ROWS>
+__global__ void __launch_bounds__(64 * WPG)
     k_spmm_row(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
                const int32_t* __restrict__ col, const float* __restrict__ val,
                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  static_assert(SPMM_ROWS % WPG == 0, "workgroup split");
+  constexpr int SPLIT = SPMM_ROWS / WPG;
   const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
-  const int ti = (blockIdx.x % NUM_XCD) * per + blockIdx.x / NUM_XCD;
+  const int k = blockIdx.x / NUM_XCD;  // index within this workgroup's XCD
+  const int ti = (blockIdx.x % NUM_XCD) * per + k / SPLIT;
   if (ti >= ntiles) return;
   const SpmmTile t = tiles[ti];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const MatDesc d = sets[t.set];
-  const int r = t.row0 + wave;
+  const int r = t.row0 + (k % SPLIT) * WPG + wave;
   if (r >= d.rows) return;  // wave-uniform
   const CsrDesc c = csr[t.set];
   const int lane = threadIdx.x & 63;
+  typedef Acc<T> AC;  // arithmetic in AC::type (FP32 for BF16 slabs)
+  typedef typename AC::type A;
   const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
-  const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
+  const A alpha = (A)cf[0], beta = (A)cf[1], gamma = (A)cf[2];
   constexpr int ES = STRIDED ? 64 : 1;  // element stride of a lane
   const int l0 = STRIDED ? lane : lane * EPL;
   const T* yv = Yin + d.off + l0;
@@ -106,68 +114,179 @@ __global__ void __launch_bounds__(1024)
   // unconditional and issued here)
   const int64_t o = d.off + int64_t(r) * d.ld + l0;
   const T* yp = Yprev ? Yprev : Yin;
-  const T g3 = Yprev ? gamma : (T)0;
-  T yin[EPL], ypr[EPL];
+  const A g3 = Yprev ? gamma : (A)0;
+  A yin[EPL], ypr[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    yin[e] = Yin[o + e * ES];
-    ypr[e] = yp[o + e * ES];
+    yin[e] = AC::load(Yin[o + e * ES]);
+    ypr[e] = AC::load(yp[o + e * ES]);
   }
   const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
-  T acc[EPL], base[EPL];
+  A acc[EPL], base[EPL];
   {
     // first chunk of the row, unconditional (entries past the row gather the
     // row itself with weight 0), so that the row's own terms are consumed
     // in the same block and their loads stay ahead of the gather
-    T y[SPMM_GATHER][EPL];
-    T w[SPMM_GATHER];
+    A y[G][EPL];
+    A w[G];
 #pragma unroll
-    for (int u = 0; u < SPMM_GATHER; ++u) {
+    for (int u = 0; u < G; ++u) {
       const bool in = k0 + u < k1;
-      w[u] = in ? (T)vb[k0 + u] : (T)0;
+      w[u] = in ? (A)vb[k0 + u] : (A)0;
       const T* src = yv + int64_t(in ? cb[k0 + u] : r) * d.ld;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) y[u][e] = src[e * ES];
+      for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
     }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       base[e] = beta * yin[e] + g3 * ypr[e];
-      acc[e] = (T)0;
+      acc[e] = (A)0;
     }
 #pragma unroll
-    for (int u = 0; u < SPMM_GATHER; ++u)
+    for (int u = 0; u < G; ++u)
 #pragma unroll
       for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
     // pin base here: otherwise the compiler sinks its loads past the loop
 #pragma unroll
     for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(base[e]));
   }
-  for (int k = k0 + SPMM_GATHER; k < k1; k += SPMM_GATHER) {
-    T y[SPMM_GATHER][EPL];
-    T w[SPMM_GATHER];
+  for (int k = k0 + G; k < k1; k += G) {
+    A y[G][EPL];
+    A w[G];
 #pragma unroll
-    for (int u = 0; u < SPMM_GATHER; ++u) {
+    for (int u = 0; u < G; ++u) {
       const int kk = min(k + u, k1 - 1);
-      w[u] = k + u < k1 ? (T)vb[kk] : (T)0;
+      w[u] = k + u < k1 ? (A)vb[kk] : (A)0;
       const T* src = yv + int64_t(cb[kk]) * d.ld;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) y[u][e] = src[e * ES];
+      for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
     }
 #pragma unroll
-    for (int u = 0; u < SPMM_GATHER; ++u)
+    for (int u = 0; u < G; ++u)
 #pragma unroll
       for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
   }
-  T out[EPL];
+  A out[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) out[e] = alpha * acc[e] + base[e];
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) Yout[o + e * ES] = out[e];
+  for (int e = 0; e < EPL; ++e) Yout[o + e * ES] = AC::store(out[e]);
+}
+
+// The same product with R rows per wavefront taken one after the other, the
+// row pointers, column indices and weights of all R rows loaded first (into
+// scalar registers: they are wave-uniform), so that the chain row pointer ->
+// columns -> neighbour rows is paid once per R rows and each row then costs
+// one round of gathers.  A workgroup of 16 wavefronts covers R consecutive
+// tiles of its XCD's range; entries past a row's first SPMM_GATHER are
+// gathered afterwards in chunks (rows of high degree).
+template <typename T, int EPL, bool STRIDED, int R, int WPG = SPMM_ROWS>
+__global__ void __launch_bounds__(64 * WPG)
+    k_spmm_rows(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val,
+                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  typedef Acc<T> AC;
+  typedef typename AC::type A;
+  constexpr int G = SPMM_GATHER;
+  constexpr int ES = STRIDED ? 64 : 1;
+  constexpr int SPLIT = SPMM_ROWS / WPG;  // workgroups per group of R tiles
+  const int ngroups = (ntiles + R - 1) / R;
+  const int per = (ngroups + NUM_XCD - 1) / NUM_XCD;
+  const int kx = blockIdx.x / NUM_XCD;
+  const int g = (blockIdx.x % NUM_XCD) * per + kx / SPLIT;
+  if (g >= ngroups) return;
+  const int wave = (kx % SPLIT) * WPG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int l0 = STRIDED ? lane : lane * EPL;
+  // indices of the R rows (wave-uniform)
+  int rr[R], sset[R], k0[R], k1[R], cj[R][G];
+  A wj[R][G];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int ti = g * R + j;
+    rr[j] = -1;
+    sset[j] = 0;
+    k0[j] = k1[j] = 0;
+    if (ti < ntiles) {
+      const SpmmTile t = tiles[ti];
+      const MatDesc d = sets[t.set];
+      const int r = t.row0 + wave;
+      if (r < d.rows) {
+        rr[j] = r;
+        sset[j] = t.set;
+        const CsrDesc c = csr[t.set];
+        k0[j] = row_ptr[c.rp_off + r];
+        k1[j] = row_ptr[c.rp_off + r + 1];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const CsrDesc c = csr[sset[j]];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const bool in = k0[j] + u < k1[j];
+      cj[j][u] = in ? col[c.nnz_off + k0[j] + u] : max(rr[j], 0);
+      wj[j][u] = in ? (A)val[c.nnz_off + k0[j] + u] : (A)0;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (rr[j] < 0) continue;  // wave-uniform
+    const MatDesc d = sets[sset[j]];
+    const CsrDesc c = csr[sset[j]];
+    const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+    const A alpha = (A)cf[0], beta = (A)cf[1], gamma = (A)cf[2];
+    const T* yv = Yin + d.off + l0;
+    const int64_t o = d.off + int64_t(rr[j]) * d.ld + l0;
+    const T* yp = Yprev ? Yprev : Yin;
+    const A g3 = Yprev ? gamma : (A)0;
+    A y[G][EPL], yin[EPL], ypr[EPL], acc[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      yin[e] = AC::load(Yin[o + e * ES]);
+      ypr[e] = AC::load(yp[o + e * ES]);
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const T* src = yv + int64_t(cj[j][u]) * d.ld;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) acc[e] = (A)0;
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) acc[e] = fma(wj[j][u], y[u][e], acc[e]);
+    const int32_t* cb = col + c.nnz_off;
+    const float* vb = val + c.nnz_off;
+    for (int k = k0[j] + G; k < k1[j]; k += G) {
+      A w[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int kk = min(k + u, k1[j] - 1);
+        w[u] = k + u < k1[j] ? (A)vb[kk] : (A)0;
+        const T* src = yv + int64_t(cb[kk]) * d.ld;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
+      }
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      Yout[o + e * ES] = AC::store(alpha * acc[e] + (beta * yin[e] + g3 * ypr[e]));
+  }
 }
 
 // The same product with two rows per wavefront: both rows' loads are in
 // flight together, so a launch holds twice the rows per wavefront slot.
-template <typename T, int EPL>
+template <typename T, int EPL, bool STRIDED = false>
 __global__ void __launch_bounds__(512)
     k_spmm_row2(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
                 const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
@@ -186,49 +305,53 @@ __global__ void __launch_bounds__(512)
   const int rw[2] = {ra, two ? ra + 1 : ra};
   const CsrDesc c = csr[t.set];
   const int lane = threadIdx.x & 63;
+  typedef Acc<T> AC;
+  typedef typename AC::type A;
   const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
-  const T alpha = (T)cf[0], beta = (T)cf[1], gamma = (T)cf[2];
-  const T* yv = Yin + d.off + lane * EPL;
+  const A alpha = (A)cf[0], beta = (A)cf[1], gamma = (A)cf[2];
+  constexpr int ES = STRIDED ? 64 : 1;  // element stride of a lane
+  const int l0 = STRIDED ? lane : lane * EPL;
+  const T* yv = Yin + d.off + l0;
   const int32_t* cb = col + c.nnz_off;
   const float* vb = val + c.nnz_off;
   const T* yp = Yprev ? Yprev : Yin;
-  const T g3 = Yprev ? gamma : (T)0;
+  const A g3 = Yprev ? gamma : (A)0;
   int64_t o[2];
-  T yin[2][EPL], ypr[2][EPL];
+  A yin[2][EPL], ypr[2][EPL];
   int k0[2], k1[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    o[h] = d.off + int64_t(rw[h]) * d.ld + lane * EPL;
+    o[h] = d.off + int64_t(rw[h]) * d.ld + l0;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      yin[h][e] = Yin[o[h] + e];
-      ypr[h][e] = yp[o[h] + e];
+      yin[h][e] = AC::load(Yin[o[h] + e * ES]);
+      ypr[h][e] = AC::load(yp[o[h] + e * ES]);
     }
     k0[h] = row_ptr[c.rp_off + rw[h]];
     k1[h] = row_ptr[c.rp_off + rw[h] + 1];
   }
-  T acc[2][EPL], base[2][EPL];
+  A acc[2][EPL], base[2][EPL];
   {
     // first chunk of both rows (entries past a row gather the row itself
     // with weight 0)
-    T y[2][SPMM_GATHER][EPL];
-    T w[2][SPMM_GATHER];
+    A y[2][SPMM_GATHER][EPL];
+    A w[2][SPMM_GATHER];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int u = 0; u < SPMM_GATHER; ++u) {
         const bool in = k0[h] + u < k1[h];
-        w[h][u] = in ? (T)vb[k0[h] + u] : (T)0;
+        w[h][u] = in ? (A)vb[k0[h] + u] : (A)0;
         const T* src = yv + int64_t(in ? cb[k0[h] + u] : rw[h]) * d.ld;
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) y[h][u][e] = src[e];
+        for (int e = 0; e < EPL; ++e) y[h][u][e] = AC::load(src[e * ES]);
       }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         base[h][e] = beta * yin[h][e] + g3 * ypr[h][e];
-        acc[h][e] = (T)0;
+        acc[h][e] = (A)0;
       }
 #pragma unroll
       for (int u = 0; u < SPMM_GATHER; ++u)
@@ -241,15 +364,15 @@ __global__ void __launch_bounds__(512)
 #pragma unroll
   for (int h = 0; h < 2; ++h)
     for (int k = k0[h] + SPMM_GATHER; k < k1[h]; k += SPMM_GATHER) {
-      T y[SPMM_GATHER][EPL];
-      T w[SPMM_GATHER];
+      A y[SPMM_GATHER][EPL];
+      A w[SPMM_GATHER];
 #pragma unroll
       for (int u = 0; u < SPMM_GATHER; ++u) {
         const int kk = min(k + u, k1[h] - 1);
-        w[u] = k + u < k1[h] ? (T)vb[kk] : (T)0;
+        w[u] = k + u < k1[h] ? (A)vb[kk] : (A)0;
         const T* src = yv + int64_t(cb[kk]) * d.ld;
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) y[u][e] = src[e];
+        for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
       }
 #pragma unroll
       for (int u = 0; u < SPMM_GATHER; ++u)
@@ -257,55 +380,94 @@ __global__ void __launch_bounds__(512)
         for (int e = 0; e < EPL; ++e) acc[h][e] = fma(w[u], y[u][e], acc[h][e]);
     }
 #pragma unroll
-  for (int e = 0; e < EPL; ++e) Yout[o[0] + e] = alpha * acc[0][e] + base[0][e];
+  for (int e = 0; e < EPL; ++e) Yout[o[0] + e * ES] = AC::store(alpha * acc[0][e] + base[0][e]);
   if (two) {
 #pragma unroll
-    for (int e = 0; e < EPL; ++e) Yout[o[1] + e] = alpha * acc[1][e] + base[1][e];
+    for (int e = 0; e < EPL; ++e)
+      Yout[o[1] + e * ES] = AC::store(alpha * acc[1][e] + base[1][e]);
   }
 }
+
+template <typename T, int EPL, bool ST>
+static void launch_spmm_rows(int var, const SpmmTile* tiles, int ntiles, const MatDesc* sets,
+                             const CsrDesc* csr, const int32_t* row_ptr, const int32_t* col,
+                             const float* val, const T* Yin, const T* Yprev, T* Yout,
+                             const double* coef, int coef_stride, int step, hipStream_t s) {
+  const dim3 grid(NUM_XCD * ceil_div(ntiles, NUM_XCD));
+  if (var == SPMM_VAR_ROW2)
+    hipLaunchKernelGGL((k_spmm_row2<T, EPL, ST>), grid, dim3(32 * SPMM_ROWS), 0, s, tiles, sets,
+                       csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride, step, ntiles);
+  else if (var == SPMM_VAR_ROW_G4)
+    hipLaunchKernelGGL((k_spmm_row<T, EPL, ST, 4>), grid, dim3(64 * SPMM_ROWS), 0, s, tiles,
+                       sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride, step,
+                       ntiles);
+  else if (var == SPMM_VAR_ROWS2)
+    hipLaunchKernelGGL((k_spmm_rows<T, EPL, ST, 2>),
+                       dim3(NUM_XCD * ceil_div(ceil_div(ntiles, 2), NUM_XCD)), dim3(1024), 0, s,
+                       tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
+                       step, ntiles);
+  else if (var == SPMM_VAR_ROWS4)
+    hipLaunchKernelGGL((k_spmm_rows<T, EPL, ST, 4>),
+                       dim3(NUM_XCD * ceil_div(ceil_div(ntiles, 4), NUM_XCD)), dim3(1024), 0, s,
+                       tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
+                       step, ntiles);
+  else if (var == SPMM_VAR_ROWS2_W4)
+    hipLaunchKernelGGL((k_spmm_rows<T, EPL, ST, 2, 4>),
+                       dim3(4 * NUM_XCD * ceil_div(ceil_div(ntiles, 2), NUM_XCD)), dim3(256), 0,
+                       s, tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef,
+                       coef_stride, step, ntiles);
+  else if (var == SPMM_VAR_ROW_W4)
+    hipLaunchKernelGGL((k_spmm_row<T, EPL, ST, SPMM_GATHER, 4>), dim3(4 * grid.x), dim3(256), 0,
+                       s, tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef,
+                       coef_stride, step, ntiles);
+  else
+    hipLaunchKernelGGL((k_spmm_row<T, EPL, ST>), grid, dim3(64 * SPMM_ROWS), 0, s, tiles, sets,
+                       csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride, step, ntiles);
+}
+
+int spmm_default_var(int epl) { return epl == 3 ? SPMM_VAR_ROW2 : SPMM_VAR_ROW; }
 
 template <typename T>
 void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
                  const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
                  const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
-                 hipStream_t s, int epl) {
+                 hipStream_t s, int epl, int var) {
   if (ntiles <= 0) return;
-#define MI_SPMM_ROW(E)                                                                          \
-  case E:                                                                                       \
-    hipLaunchKernelGGL((k_spmm_row<T, E>), dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)),          \
-                       dim3(64 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin,     \
-                       Yprev, Yout, coef, coef_stride, step, ntiles);                            \
+  if (var < 0) var = spmm_default_var(epl);
+#define MI_SPMM_ROWS(E, ST)                                                                    \
+  case E:                                                                                      \
+    launch_spmm_rows<T, E, ST>(var, tiles, ntiles, sets, csr, row_ptr, col, val, Yin, Yprev,   \
+                               Yout, coef, coef_stride, step, s);                              \
     return;
-  if (epl == 3) {
-    hipLaunchKernelGGL((k_spmm_row2<T, 3>), dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)),
-                       dim3(32 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin, Yprev,
-                       Yout, coef, coef_stride, step, ntiles);
-    return;
-  }
   switch (epl) {
-    MI_SPMM_ROW(1)
-    MI_SPMM_ROW(2)
-    MI_SPMM_ROW(3)
-    MI_SPMM_ROW(4)
-    case 5:
-      hipLaunchKernelGGL((k_spmm_row<T, 5, true>), dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)),
-                         dim3(64 * SPMM_ROWS), 0, s, tiles, sets, csr, row_ptr, col, val, Yin,
-                         Yprev, Yout, coef, coef_stride, step, ntiles);
-      return;
+    MI_SPMM_ROWS(1, false)
+    MI_SPMM_ROWS(2, false)
+    MI_SPMM_ROWS(3, false)
+    MI_SPMM_ROWS(4, false)
+    MI_SPMM_ROWS(5, true)
     default:
       break;
   }
-#undef MI_SPMM_ROW
-  hipLaunchKernelGGL(k_spmm<T>, dim3(ntiles), dim3(256), 0, s, tiles, sets, csr, row_ptr, col, val,
-                     Yin, Yprev, Yout, coef, coef_stride, step);
+#undef MI_SPMM_ROWS
+  // the vector kernel for waves of mixed widths (FP32 and FP64 slabs only: the
+  // plan refuses BF16 slabs without a uniform width)
+  if constexpr (!std::is_same<T, bf16>::value)
+    hipLaunchKernelGGL(k_spmm<T>, dim3(ntiles), dim3(256), 0, s, tiles, sets, csr, row_ptr, col,
+                       val, Yin, Yprev, Yout, coef, coef_stride, step);
 }
 
 template void launch_spmm<float>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
                                  const int32_t*, const int32_t*, const float*, const float*,
-                                 const float*, float*, const double*, int, int, hipStream_t, int);
+                                 const float*, float*, const double*, int, int, hipStream_t, int,
+                                 int);
 template void launch_spmm<double>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
                                   const int32_t*, const int32_t*, const float*, const double*,
-                                  const double*, double*, const double*, int, int, hipStream_t, int);
+                                  const double*, double*, const double*, int, int, hipStream_t,
+                                  int, int);
+template void launch_spmm<bf16>(const SpmmTile*, int, const MatDesc*, const CsrDesc*,
+                                const int32_t*, const int32_t*, const float*, const bf16*,
+                                const bf16*, bf16*, const double*, int, int, hipStream_t, int,
+                                int);
 
 // ------------------------------------------------------------------ Gram
 // One workgroup: a 64 x 64 super-tile of A^T B (and A^T W when DUAL) over a
@@ -409,6 +571,124 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The same super-tiles for BF16 slabs on the BF16 MFMA (16x16x16, FP32
+// accumulation): products of two BF16 values are exact in FP32, so only the
+// FP32 sums over one staged chunk of 32 rows round; each chunk's sums are
+// added into FP64 accumulators, and the partials in FP64 like the other
+// Grams (an FP32 sum over all of a workgroup's rows would cost the
+// Cholesky-QR its orthogonality on ill-conditioned iterates).  Each 32-row chunk of the three column
+// panels is staged through LDS transposed (a column's rows contiguous), so
+// that a lane's four consecutive-row operands are one 64-bit LDS read.
+// Operand layout (16x16x16 BF16): lane l supplies A(m = l%16, k = 4(l/16) +
+// i) and B(k = 4(l/16) + i, n = l%16), i < 4; result (m = 4(l/16) + q, n =
+// l%16) in register q.
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+template <bool DUAL>
+__global__ void __launch_bounds__(256)
+    k_gram_bf16(const GramTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const bf16* __restrict__ A, const bf16* __restrict__ B,
+                const bf16* __restrict__ Wm, double* __restrict__ part) {
+  constexpr int RC = 32;           // rows per staged chunk
+  constexpr int LDT = RC + 8;      // LDS stride of a column (bf16 elements)
+  constexpr int NOP = DUAL ? 3 : 2;
+  __shared__ __attribute__((aligned(16))) uint16_t St[NOP][GRAM_TILE * LDT];
+  const GramTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int kq = lane >> 4, mi = lane & 15;
+  d4v acc[2][2], accw[2][2];  // FP64 sums over the chunks
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = accw[a][b] = d4v{0.0, 0.0, 0.0, 0.0};
+  const bf16* src[3] = {A + d.off, B + d.off, DUAL ? Wm + d.off : nullptr};
+  const int c0[3] = {t.I0, t.J0, t.J0};
+  // thread e stages 8 consecutive columns of one row of each panel
+  const int srow = threadIdx.x >> 3, scol = (threadIdx.x & 7) * 8;
+  uint4 reg[NOP];
+  auto fetch = [&](int r) {
+#pragma unroll
+    for (int o = 0; o < NOP; ++o) {
+      const int row = r + srow, col = c0[o] + scol;
+      reg[o] = (row < t.r1 && col < d.ld)
+                   ? *reinterpret_cast<const uint4*>(src[o] + int64_t(row) * d.ld + col)
+                   : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  fetch(t.r0);
+  for (int r = t.r0; r < t.r1; r += RC) {
+#pragma unroll
+    for (int o = 0; o < NOP; ++o) {
+      const uint32_t w4[4] = {reg[o].x, reg[o].y, reg[o].z, reg[o].w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        St[o][(scol + j) * LDT + srow] = uint16_t(w4[j >> 1] >> (16 * (j & 1)));
+    }
+    __syncthreads();
+    if (r + RC < t.r1) fetch(r + RC);  // in flight during the MFMAs
+    f4v c32[2][2], w32[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) c32[i][j] = w32[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < RC; ks += 16) {
+      s4v a[2], b[2], x[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        a[h] = *reinterpret_cast<const s4v*>(&St[0][(wi * 32 + h * 16 + mi) * LDT + ks + 4 * kq]);
+        b[h] = *reinterpret_cast<const s4v*>(&St[1][(wj * 32 + h * 16 + mi) * LDT + ks + 4 * kq]);
+        if (DUAL)
+          x[h] = *reinterpret_cast<const s4v*>(
+              &St[DUAL ? 2 : 0][(wj * 32 + h * 16 + mi) * LDT + ks + 4 * kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          c32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], c32[i][j], 0, 0, 0);
+          if (DUAL)
+            w32[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], x[j], w32[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[i][j][q] += (double)c32[i][j][q];
+          if (DUAL) accw[i][j][q] += (double)w32[i][j][q];
+        }
+    __syncthreads();
+  }
+  double* out = part + int64_t(blockIdx.x) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = wi * 32 + i * 16 + 4 * kq + q, n = wj * 32 + j * 16 + mi;
+        out[m * GRAM_TILE + n] = acc[i][j][q];
+        if (DUAL) out[GRAM_TILE * GRAM_TILE + m * GRAM_TILE + n] = accw[i][j][q];
+      }
+}
+
+template <>
+void launch_gram<bf16>(const GramTile* tiles, int ntiles, const MatDesc* sets, const bf16* A,
+                       const bf16* B, const bf16* W, double* part, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (W)
+    hipLaunchKernelGGL(k_gram_bf16<true>, dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W,
+                       part);
+  else
+    hipLaunchKernelGGL(k_gram_bf16<false>, dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W,
+                       part);
+}
+
 template <typename T>
 void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T* A, const T* B,
                  const T* W, double* part, hipStream_t s) {
@@ -503,20 +783,26 @@ struct Mfma<double> {
   __device__ static int row(int lane, int q) { return (lane >> 4) + 4 * q; }
 };
 
-template <typename T, typename TO, int NCH>
+// A may be a BF16 slab (TA = bf16, T = float): its chunk is widened to FP32
+// on the way into LDS and the product runs on the FP32 MFMA.
+template <typename TA, typename T, typename TO, int NCH>
 __global__ void __launch_bounds__(256)
     k_rowmul(const RowTile* __restrict__ tiles, const MatDesc* __restrict__ asets,
-             const T* __restrict__ A, const MatDesc* __restrict__ ssets, const T* __restrict__ S,
+             const TA* __restrict__ A, const MatDesc* __restrict__ ssets, const T* __restrict__ S,
              const MatDesc* __restrict__ osets, TO* __restrict__ Out) {
   typedef typename VecOf<T>::type V;
+  typedef typename VecOf<TA>::type VA;
   constexpr int W = VecOf<T>::W;           // elements per 16-byte vector
+  constexpr int WA = VecOf<TA>::W;
   constexpr int KC = 32;
   constexpr int NT = NCH / 16;
-  constexpr int AV = ROW_TILE * KC / W / 256;  // A vectors per thread and chunk
-  constexpr int SV = KC * NCH / W / 256;       // S vectors per thread and chunk
-  constexpr int LDA = KC + W;                  // keeps vector rows aligned, spreads banks
+  constexpr int AV = ROW_TILE * KC / WA / 256;  // A vectors per thread and chunk
+  constexpr int SV = KC * NCH / W / 256;        // S vectors per thread and chunk
+  constexpr int LDA = KC + W;                   // keeps vector rows aligned, spreads banks
   constexpr int LDS_ = NCH + (sizeof(T) == 4 ? 16 : 16);  // row offset of half the banks
-  static_assert(AV * W * 256 == ROW_TILE * KC && SV * W * 256 == KC * NCH, "tile shape");
+  static_assert(AV * WA * 256 == ROW_TILE * KC && SV * W * 256 == KC * NCH, "tile shape");
+  static_assert(std::is_same<TA, T>::value || (std::is_same<TA, bf16>::value &&
+                                              std::is_same<T, float>::value), "A type");
   __shared__ __attribute__((aligned(16))) T As[ROW_TILE * LDA];
   __shared__ __attribute__((aligned(16))) T Ss[KC * LDS_];
   typedef typename Mfma<T>::acc_t acc_t;
@@ -527,17 +813,19 @@ __global__ void __launch_bounds__(256)
   acc_t acc[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) acc[i] = (acc_t)(T)0;
-  V ra[AV], rs[SV];
+  VA ra[AV];
+  V rs[SV];
   // chunk k0 -> registers (rows past the block and columns past S read as 0)
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < AV; ++j) {
       const int e = threadIdx.x + 256 * j;
-      const int rr = e / (KC / W), kv = e % (KC / W);
+      const int rr = e / (KC / WA), kv = e % (KC / WA);
       const int row = t.row0 + rr;
-      ra[j] = (row < da.rows)
-                  ? *reinterpret_cast<const V*>(A + da.off + int64_t(row) * da.ld + k0 + kv * W)
-                  : (V)(T)0;
+      if (row < da.rows)
+        ra[j] = *reinterpret_cast<const VA*>(A + da.off + int64_t(row) * da.ld + k0 + kv * WA);
+      else
+        __builtin_memset(&ra[j], 0, sizeof(VA));
     }
 #pragma unroll
     for (int j = 0; j < SV; ++j) {
@@ -554,7 +842,22 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int j = 0; j < AV; ++j) {
       const int e = threadIdx.x + 256 * j;
-      *reinterpret_cast<V*>(&As[(e / (KC / W)) * LDA + (e % (KC / W)) * W]) = ra[j];
+      T* dst = &As[(e / (KC / WA)) * LDA + (e % (KC / WA)) * WA];
+      if constexpr (std::is_same<TA, T>::value) {
+        *reinterpret_cast<V*>(dst) = ra[j];
+      } else {
+        const uint32_t w4[4] = {ra[j].x, ra[j].y, ra[j].z, ra[j].w};
+        f4v lo, hi;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          lo[2 * q] = bf16_to_f32(bf16{uint16_t(w4[q])});
+          lo[2 * q + 1] = bf16_to_f32(bf16{uint16_t(w4[q] >> 16)});
+          hi[2 * q] = bf16_to_f32(bf16{uint16_t(w4[2 + q])});
+          hi[2 * q + 1] = bf16_to_f32(bf16{uint16_t(w4[2 + q] >> 16)});
+        }
+        *reinterpret_cast<f4v*>(dst) = lo;
+        *reinterpret_cast<f4v*>(dst + 4) = hi;
+      }
     }
 #pragma unroll
     for (int j = 0; j < SV; ++j) {
@@ -580,21 +883,22 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = t.row0 + wave * 16 + Mfma<T>::row(lane, q);
-      if (row < dout.rows && n < dout.ld) Out[dout.off + int64_t(row) * dout.ld + n] = (TO)acc[nt][q];
+      if (row < dout.rows && n < dout.ld)
+        Out[dout.off + int64_t(row) * dout.ld + n] = Acc<TO>::store((typename Acc<TO>::type)acc[nt][q]);
     }
   }
 }
 
-template <typename T, typename TO>
-void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const T* A,
+template <typename TA, typename T, typename TO>
+void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const TA* A,
                    const MatDesc* ssets, const T* S, const MatDesc* osets, TO* Out, int nch,
                    hipStream_t s) {
   if (ntiles <= 0) return;
   switch (nch) {
 #define MI_ROWMUL_CASE(N)                                                                       \
   case N:                                                                                       \
-    hipLaunchKernelGGL((k_rowmul<T, TO, N>), dim3(ntiles), dim3(256), 0, s, tiles, asets, A,   \
-                       ssets, S, osets, Out);                                                   \
+    hipLaunchKernelGGL((k_rowmul<TA, T, TO, N>), dim3(ntiles), dim3(256), 0, s, tiles, asets,  \
+                       A, ssets, S, osets, Out);                                                \
     break;
     MI_ROWMUL_CASE(32)
     MI_ROWMUL_CASE(64)
@@ -608,15 +912,21 @@ void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const
   }
 }
 
-template void launch_rowmul<float, float>(const RowTile*, int, const MatDesc*, const float*,
-                                          const MatDesc*, const float*, const MatDesc*, float*, int,
-                                          hipStream_t);
-template void launch_rowmul<double, double>(const RowTile*, int, const MatDesc*, const double*,
-                                            const MatDesc*, const double*, const MatDesc*, double*,
-                                            int, hipStream_t);
-template void launch_rowmul<double, float>(const RowTile*, int, const MatDesc*, const double*,
-                                           const MatDesc*, const double*, const MatDesc*, float*,
-                                           int, hipStream_t);
+template void launch_rowmul<float, float, float>(const RowTile*, int, const MatDesc*,
+                                                 const float*, const MatDesc*, const float*,
+                                                 const MatDesc*, float*, int, hipStream_t);
+template void launch_rowmul<double, double, double>(const RowTile*, int, const MatDesc*,
+                                                    const double*, const MatDesc*, const double*,
+                                                    const MatDesc*, double*, int, hipStream_t);
+template void launch_rowmul<double, double, float>(const RowTile*, int, const MatDesc*,
+                                                   const double*, const MatDesc*, const double*,
+                                                   const MatDesc*, float*, int, hipStream_t);
+template void launch_rowmul<bf16, float, bf16>(const RowTile*, int, const MatDesc*, const bf16*,
+                                               const MatDesc*, const float*, const MatDesc*, bf16*,
+                                               int, hipStream_t);
+template void launch_rowmul<bf16, float, float>(const RowTile*, int, const MatDesc*, const bf16*,
+                                                const MatDesc*, const float*, const MatDesc*,
+                                                float*, int, hipStream_t);
 
 // ------------------------------------------------------------------ tile tables
 

@@ -59,11 +59,27 @@ struct RowTile {
 };
 constexpr int ROW_TILE = 64;
 
+// Variants of the wavefront-per-row SpMM (the autotuner picks one per wave):
+// one row per wavefront gathering 8 neighbour rows at a time, the same with
+// 4 at a time (fewer registers, more wavefronts per CU), two rows per
+// wavefront, one row per wavefront in workgroups of 4 wavefronts, or 2 or 4
+// rows per wavefront one after the other with all their indices loaded
+// first (2 also in workgroups of 4 wavefronts).
+constexpr int SPMM_VAR_ROW = 0;
+constexpr int SPMM_VAR_ROW_G4 = 1;
+constexpr int SPMM_VAR_ROW2 = 2;
+constexpr int SPMM_VAR_ROW_W4 = 3;
+constexpr int SPMM_VAR_ROWS2 = 4;
+constexpr int SPMM_VAR_ROWS4 = 5;
+constexpr int SPMM_VAR_ROWS2_W4 = 6;
+constexpr int SPMM_NVAR = 7;
+int spmm_default_var(int epl);
+
 template <typename T>
 void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,
                  const int32_t* row_ptr, const int32_t* col, const float* val, const T* Yin,
                  const T* Yprev, T* Yout, const double* coef, int coef_stride, int step,
-                 hipStream_t s, int epl = 0);
+                 hipStream_t s, int epl = 0, int var = -1);
 // Elements per lane of the wavefront-per-row SpMM when every block of a
 // launch has the same ld, a multiple of 64 up to 320; 0 otherwise.
 int spmm_epl(const std::vector<MatDesc>& sets);
@@ -75,8 +91,10 @@ void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T
 void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outsets,
                         const double* part, bool dual, double* G, double* H, hipStream_t s);
 
-template <typename T, typename TO>
-void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const T* A,
+// Out = A S row tile by row tile; A may be a BF16 slab with S and the MFMA in
+// FP32 (TA = bf16, T = float).
+template <typename TA, typename T, typename TO>
+void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const TA* A,
                    const MatDesc* ssets, const T* S, const MatDesc* osets, TO* Out, int nch,
                    hipStream_t s);
 

@@ -327,17 +327,23 @@ __global__ void __launch_bounds__(TRI_THREADS)
 
 // Wider blocks (192 < ld <= TRI_MAX_LD): the same reflectors with the
 // matrix in global memory (the block's A, overwritten), one workgroup of
-// TRI_G_THREADS per block.  Row k right of the diagonal is column k below it
-// (A is kept full and symmetric), so thread i reads x_i = A[k][i] with one
-// coalesced row load.  Step k: the norm of x (block sum), alpha, beta and v
-// (v_{k+1} = x_{k+1} - alpha, zero at and above k) into LDS and row k of Hv;
-// p = beta A v over the trailing rows, one wavefront per row and lanes over
-// columns; K = (beta/2) v^T p, w = p - K v; A -= v w^T + w v^T on the
-// trailing block, again one wavefront per row.  Four barriers per step; the
-// sums run in a fixed order (wavefront tree, then the 16 wavefront partials
-// in order), so the result does not depend on the launch.
+// TRI_G_THREADS per block.  A is kept full and symmetric, so column k below
+// the diagonal is row k right of it: one coalesced row load.  The rank-2
+// update of step k - 1 is deferred and fused into step k's sweep, so the
+// trailing block is read and written once per step:
+//   A (one wavefront): row k with update k - 1 applied gives x, its norm,
+//     alpha, beta and v (v_{k+1} = x_{k+1} - alpha, zero at and above k),
+//     into LDS and row k of Hv;
+//   B (all): every trailing row i > k gets update k - 1 (A -= v w^T + w v^T
+//     with the previous v, w), is written back, and gives
+//     p_i = beta (A v)_i, one wavefront per row and lanes over columns;
+//   C: K = (beta/2) v^T p and w = p - K v.
+// The last update is applied to the final 2 x 2 block at the end.  Every
+// sum runs in a fixed order (wavefront tree, then the wavefront partials in
+// order), so the result does not depend on the launch.
 constexpr int TRI_G_THREADS = 1024;
 constexpr int TRI_G_WAVES = TRI_G_THREADS / 64;
+constexpr int TRI_G_PL = (TRI_MAX_LD + 63) / 64;  // row elements per lane
 
 // Sum over the workgroup of one value per thread; every thread gets it.
 __device__ __forceinline__ double tri_g_sum(double v, double* part) {
@@ -353,7 +359,7 @@ __device__ __forceinline__ double tri_g_sum(double v, double* part) {
 __global__ void __launch_bounds__(TRI_G_THREADS)
     k_tri_reduce_g(const SmallDesc* __restrict__ sds, double* __restrict__ A,
                    double* __restrict__ Hv, double* __restrict__ tri, int32_t* __restrict__ status) {
-  __shared__ double vv[TRI_MAX_LD], ww[TRI_MAX_LD];
+  __shared__ double vv[2][TRI_MAX_LD], ww[2][TRI_MAX_LD];
   __shared__ double sdd[TRI_MAX_LD], see[TRI_MAX_LD], sbb[TRI_MAX_LD];
   __shared__ double part[2][TRI_G_WAVES];
   __shared__ int flag;
@@ -363,6 +369,10 @@ __global__ void __launch_bounds__(TRI_G_THREADS)
   double* Ab = A + d.m_off;
   double* Hb = Hv + d.m_off;
   if (tid == 0) flag = 0;
+  for (int i = tid; i < 2 * TRI_MAX_LD; i += TRI_G_THREADS) {
+    (&vv[0][0])[i] = 0.0;
+    (&ww[0][0])[i] = 0.0;
+  }
   __syncthreads();
   {
     bool bad = false;
@@ -371,69 +381,96 @@ __global__ void __launch_bounds__(TRI_G_THREADS)
     if (bad) atomicOr(&flag, MI_BLOCK_NONFINITE);
   }
   for (int k = 0; k + 2 < p; ++k) {
-    const int k1 = k + 1;
-    // 1: the reflector of column k
-    const double x = (tid > k && tid < p) ? Ab[int64_t(k) * ld + tid] : 0.0;
-    const double ss = tri_g_sum(x * x, part[k & 1]);
-    const double x1 = Ab[int64_t(k) * ld + k1];
-    double al, be;
-    if (ss <= DBL_MIN) {
-      al = x1;
-      be = 0.0;
-    } else {
-      al = -copysign(sqrt_pos(ss), x1);
-      be = recip(al * (al - x1));
-    }
-    const double v = x - (tid == k1 ? al : 0.0);
-    if (tid < TRI_MAX_LD) vv[tid] = v;
-    if (tid < ld) Hb[int64_t(k) * ld + tid] = v;
-    if (tid == 0) {
-      sdd[k] = Ab[int64_t(k) * ld + k];
-      see[k] = al;
-      sbb[k] = be;
+    const int k1 = k + 1, cur = k & 1, prv = cur ^ 1;
+    // A: the reflector of column k (row k with the pending update applied)
+    if (wave == 0) {
+      const double vk = vv[prv][k], wk = ww[prv][k];
+      double xa[TRI_G_PL];
+      double ss = 0.0;
+#pragma unroll
+      for (int t = 0; t < TRI_G_PL; ++t) {
+        const int j = k + lane + 64 * t;
+        double x = 0.0;
+        if (j < p)
+          x = fma(-vk, ww[prv][j], fma(-wk, vv[prv][j], Ab[int64_t(k) * ld + j]));
+        xa[t] = x;
+        if (j > k) ss = fma(x, x, ss);
+      }
+      ss = wave_sum(ss);
+      const double dkk = __shfl(xa[0], 0, 64), x1 = __shfl(xa[0], 1, 64);
+      double al, be;
+      if (ss <= DBL_MIN) {
+        al = x1;
+        be = 0.0;
+      } else {
+        al = -copysign(sqrt_pos(ss), x1);
+        be = recip(al * (al - x1));
+      }
+#pragma unroll
+      for (int t = 0; t < TRI_G_PL; ++t) {
+        const int j = k + lane + 64 * t;
+        const double v = (j > k && j < p) ? xa[t] - (j == k1 ? al : 0.0) : 0.0;
+        if (j < TRI_MAX_LD) vv[cur][j] = v;
+        if (j < ld) Hb[int64_t(k) * ld + j] = v;
+      }
+      for (int j = lane; j <= k; j += 64) Hb[int64_t(k) * ld + j] = 0.0;
+      if (lane == 0) {
+        sdd[k] = dkk;
+        see[k] = al;
+        sbb[k] = be;
+      }
     }
     __syncthreads();
-    // 2: p = beta A v over the trailing rows (two rows per wavefront at a time)
+    const double be = sbb[k];
+    // B: pending update of every trailing row, written back, and p = beta A v
     for (int i = k1 + wave; i < p; i += 2 * TRI_G_WAVES) {
       const int i2 = i + TRI_G_WAVES;
       const bool two = i2 < p;
+      const double v1 = vv[prv][i], w1 = ww[prv][i];
+      const double v2 = two ? vv[prv][i2] : 0.0, w2 = two ? ww[prv][i2] : 0.0;
       double s1 = 0.0, s2 = 0.0;
       for (int j = k1 + lane; j < p; j += 64) {
-        const double vj = vv[j];
-        s1 = fma(Ab[int64_t(i) * ld + j], vj, s1);
-        if (two) s2 = fma(Ab[int64_t(i2) * ld + j], vj, s2);
+        const double vj = vv[prv][j], wj = ww[prv][j], nj = vv[cur][j];
+        const int64_t o1 = int64_t(i) * ld + j;
+        const double a1 = fma(-v1, wj, fma(-w1, vj, Ab[o1]));
+        Ab[o1] = a1;
+        s1 = fma(a1, nj, s1);
+        if (two) {
+          const int64_t o2 = int64_t(i2) * ld + j;
+          const double a2 = fma(-v2, wj, fma(-w2, vj, Ab[o2]));
+          Ab[o2] = a2;
+          s2 = fma(a2, nj, s2);
+        }
       }
       s1 = wave_sum(s1);
       s2 = wave_sum(s2);
       if (lane == 0) {
-        ww[i] = be * s1;
-        if (two) ww[i2] = be * s2;
+        ww[cur][i] = be * s1;
+        if (two) ww[cur][i2] = be * s2;
       }
     }
     __syncthreads();
-    // 3: w = p - K v with K = (beta / 2) v^T p
-    const double vp = tri_g_sum((tid > k && tid < p) ? vv[tid] * ww[tid] : 0.0, part[(k & 1) ^ 1]);
+    // C: w = p - K v with K = (beta / 2) v^T p
+    const double vp =
+        tri_g_sum((tid > k && tid < p) ? vv[cur][tid] * ww[cur][tid] : 0.0, part[cur]);
     const double K = 0.5 * be * vp;
-    if (tid > k && tid < p) ww[tid] = fma(-K, vv[tid], ww[tid]);
-    __syncthreads();
-    // 4: A -= v w^T + w v^T on the trailing block
-    for (int i = k1 + wave; i < p; i += TRI_G_WAVES) {
-      const double vi = vv[i], wi = ww[i];
-      for (int j = k1 + lane; j < p; j += 64) {
-        const int64_t o = int64_t(i) * ld + j;
-        Ab[o] = fma(-vi, ww[j], fma(-wi, vv[j], Ab[o]));
-      }
-    }
+    if (tid > k && tid < p) ww[cur][tid] = fma(-K, vv[cur][tid], ww[cur][tid]);
     __syncthreads();
   }
-  // the last 2 x 2 (or 1 x 1) block is already tridiagonal
+  // the last 2 x 2 (or 1 x 1) block is already tridiagonal once the pending
+  // update of the last step is applied
   if (tid == 0) {
+    const int kl = p - 3, c = kl & 1;  // the last step and its buffers
+    auto upd = [&](int i, int j) {
+      const double a = Ab[int64_t(i) * ld + j];
+      return kl >= 0 ? fma(-vv[c][i], ww[c][j], fma(-ww[c][i], vv[c][j], a)) : a;
+    };
     if (p >= 2) {
-      sdd[p - 2] = Ab[int64_t(p - 2) * ld + p - 2];
-      see[p - 2] = Ab[int64_t(p - 1) * ld + p - 2];
+      sdd[p - 2] = upd(p - 2, p - 2);
+      see[p - 2] = upd(p - 1, p - 2);
       sbb[p - 2] = 0.0;
     }
-    sdd[p - 1] = Ab[int64_t(p - 1) * ld + p - 1];
+    sdd[p - 1] = upd(p - 1, p - 1);
     see[p - 1] = 0.0;
     sbb[p - 1] = 0.0;
   }

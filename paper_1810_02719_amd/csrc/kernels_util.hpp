@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 namespace mis {
 
@@ -44,6 +45,46 @@ template <>
 struct VecOf<double> {
   typedef d2v type;
   static constexpr int W = 2;
+};
+struct bf16;
+template <>
+struct VecOf<bf16> {
+  typedef uint4 type;  // eight BF16 values
+  static constexpr int W = 8;
+};
+
+// Slab element of the reduced-precision option: bfloat16 storage (the upper
+// half of an FP32 word), arithmetic in FP32.  Rounding to nearest, ties to
+// even (NaN kept quiet).
+struct bf16 {
+  uint16_t u;
+};
+__host__ __device__ inline float bf16_to_f32(bf16 x) {
+  const uint32_t w = uint32_t(x.u) << 16;
+  float f;
+  __builtin_memcpy(&f, &w, 4);
+  return f;
+}
+__host__ __device__ inline bf16 f32_to_bf16(float f) {
+  uint32_t w;
+  __builtin_memcpy(&w, &f, 4);
+  if ((w & 0x7F800000u) == 0x7F800000u && (w & 0x007FFFFFu)) return bf16{uint16_t((w >> 16) | 0x40u)};
+  w += 0x7FFFu + ((w >> 16) & 1u);
+  return bf16{uint16_t(w >> 16)};
+}
+
+// Arithmetic type of a slab element type and the conversions to and from it.
+template <typename T>
+struct Acc {
+  typedef T type;
+  __host__ __device__ static T load(T x) { return x; }
+  __host__ __device__ static T store(T x) { return x; }
+};
+template <>
+struct Acc<bf16> {
+  typedef float type;
+  __host__ __device__ static float load(bf16 x) { return bf16_to_f32(x); }
+  __host__ __device__ static bf16 store(float x) { return f32_to_bf16(x); }
 };
 
 // Sum over the 64 lanes of a wavefront (every lane gets the total).

@@ -112,24 +112,26 @@ __global__ void k_cheb_coef(const MatDesc* __restrict__ sets, int nsets,
 // past its width get the unit vector e_{(997 j) mod n_b}.
 // The predecessor's basis is read from src (the caller's output), the start
 // is written to dst (the same buffer outside the tolerance mode).
-template <typename T>
+// (src and dst may differ in element type: FP32 output, BF16 working slab.)
+template <typename TS, typename TD>
 __global__ void __launch_bounds__(256)
     k_warm_copy(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
-                const MatDesc* __restrict__ psets, const T* src, T* dst) {
+                const MatDesc* __restrict__ psets, const TS* src, TD* dst) {
+  typedef typename Acc<TD>::type A;
   const SpmmTile t = tiles[blockIdx.x];
   const MatDesc d = sets[t.set], pd = psets[t.set];
   const int rows = min(SPMM_ROWS, d.rows - t.row0);
   for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
     const int r = t.row0 + e / d.ld, j = e % d.ld;
-    T v = (T)0;
+    A v = (A)0;
     if (j < d.cols) {
       if (j < pd.cols) {
-        if (r < pd.rows) v = src[pd.off + int64_t(r) * pd.ld + j];
+        if (r < pd.rows) v = (A)Acc<TS>::load(src[pd.off + int64_t(r) * pd.ld + j]);
       } else if (r == int((997LL * j) % d.rows)) {
-        v = (T)1;
+        v = (A)1;
       }
     }
-    dst[d.off + int64_t(r) * d.ld + j] = v;
+    dst[d.off + int64_t(r) * d.ld + j] = Acc<TD>::store(v);
   }
 }
 
@@ -155,8 +157,9 @@ __global__ void __launch_bounds__(256)
   for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
     const int r = t.row0 + e / d.ld, j = e % d.ld;
     const uint64_t key = (uint64_t(d.blk) << 40) + (uint64_t(r) << 12) + uint64_t(j);
+    typedef typename Acc<T>::type A;
     out[d.off + int64_t(r) * d.ld + j] =
-        j < d.cols ? (T)(2.0 * splitmix_unit(seed, key) - 1.0) : (T)0;
+        Acc<T>::store(j < d.cols ? (A)(2.0 * splitmix_unit(seed, key) - 1.0) : (A)0);
   }
 }
 
@@ -298,16 +301,17 @@ __global__ void __launch_bounds__(256)
   if (iters && threadIdx.x == 0) iters[d.blk] = T;
 }
 
-template <typename T>
+// (with a conversion when the element types differ: FP32 <-> BF16)
+template <typename TS, typename TD = TS>
 __global__ void __launch_bounds__(256)
     k_copy_slab(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
-                const T* __restrict__ src, T* __restrict__ dst) {
+                const TS* __restrict__ src, TD* __restrict__ dst) {
   const SpmmTile t = tiles[blockIdx.x];
   const MatDesc d = sets[t.set];
   const int rows = min(SPMM_ROWS, d.rows - t.row0);
   for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
     const int64_t o = d.off + int64_t(t.row0) * d.ld + e;
-    dst[o] = src[o];
+    dst[o] = Acc<TD>::store((typename Acc<TD>::type)Acc<TS>::load(src[o]));
   }
 }
 
@@ -622,10 +626,15 @@ static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool
       root[b] = x;
     }
   }
+  int maxl = 0;
+  for (int b = 0; b < B; ++b) maxl = std::max(maxl, (*level)[b]);
   // lane of each block: its tree's rank among the roots, modulo MAX_LANES
+  // (blocks that are all independent form one wave on one lane: lanes pay
+  // off by overlapping the levels of different trees, and one launch over
+  // every block fills the chip best)
   std::vector<int> lane(B, 0);
   int nl = 1;
-  if (chained(prm) && !per_block) {
+  if (chained(prm) && !per_block && maxl > 0) {
     std::vector<int> rank(B, -1);
     int nr = 0;
     for (int b = 0; b < B; ++b)
@@ -633,8 +642,6 @@ static mi_status build_waves(const HostBlocks& hb, const mi_oi_params& prm, bool
     for (int b = 0; b < B; ++b) lane[b] = rank[root[b]] % MAX_LANES;
     nl = std::min(nr, MAX_LANES);
   }
-  int maxl = 0;
-  for (int b = 0; b < B; ++b) maxl = std::max(maxl, (*level)[b]);
   waves->clear();
   if (wave_lane) wave_lane->clear();
   for (int ln = 0; ln < nl; ++ln)
@@ -677,7 +684,7 @@ static int pick_nch(const std::vector<int>& lds_in_wave, bool dbl) {
 
 static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t part_doubles,
                           int n_lanes) {
-  const size_t es = prm.precision == MI_FP64 ? 8 : 4;
+  const size_t es = prm.precision == MI_FP64 ? 8 : prm.precision == MI_BF16_IN ? 2 : 4;
   int64_t slab = hb.u_off[hb.B];
   int64_t mats = hb.m_off[hb.B];
   int64_t pk = 0, lg = 0, tp = hb.t_off[hb.B];
@@ -745,7 +752,8 @@ struct WaveHost {
 static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
                       const std::vector<int>& blocks, const mi_oi_params& prm, WaveTables* wt,
                       WaveHost* h, const std::vector<int64_t>& pk_off,
-                      const std::vector<int64_t>& log_off, const WaveTune* tune = nullptr) {
+                      const std::vector<int64_t>& log_off, const WaveTune* tune = nullptr,
+                      int spmm_force = -1) {
   const bool dbl = prm.precision == MI_FP64;
   std::vector<int> lds_list;
   for (int b : blocks) {
@@ -780,6 +788,8 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
   wt->nchs = pick_nch(lds_list, true);
   spmm_tables(h->tall, &h->spmm);
   wt->epl = tune ? tune->epl : spmm_epl(h->tall);
+  wt->spmm_var = tune ? tune->spmm_var : -1;
+  if (spmm_force >= 0 && wt->epl > 0) wt->spmm_var = spmm_force;
   wt->gram_target = tune ? tune->gram_target : GRAM_TARGET;
   gram_tables(h->tall, true, &h->gt, &h->gr, wt->gram_target);
   gram_tables(h->small, false, &h->gts, &h->grs);
@@ -810,9 +820,10 @@ static size_t tuned_part_max(const std::vector<MatDesc>& tall) {
 
 static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
                            const mi_oi_params& prm, bool per_block, int lds_max,
-                           std::unique_ptr<OiPlan>* out, size_t* ws_need,
+                           int spmm_force, std::unique_ptr<OiPlan>* out, size_t* ws_need,
                            const std::vector<WaveTune>* tune = nullptr) {
   std::unique_ptr<OiPlan> P(new OiPlan());
+  P->spmm_force = spmm_force;
   P->hb = hb;
   P->nnz_off = nnz_off;
   P->prm = prm;
@@ -844,10 +855,13 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
     wt.passes = warm_wave ? prm.passes : prm.passes0;
     wt.lane = wave_lane[w];
     wave_host(hb, nnz_off, waves[w], prm, &wt, &hosts[w], pk_off, log_off,
-              tune ? &(*tune)[w] : nullptr);
+              tune ? &(*tune)[w] : nullptr, spmm_force);
     part_max = std::max(part_max, hosts[w].gt.size() * 2 * GRAM_TILE * GRAM_TILE);
     part_max = std::max(part_max, hosts[w].gts.size() * 2 * GRAM_TILE * GRAM_TILE);
     if (prm.autotune) part_max = std::max(part_max, tuned_part_max(hosts[w].tall));
+    // BF16 slabs run only the wavefront-per-row SpMM (one width per wave)
+    MI_CHECK_ARG(prm.precision != MI_BF16_IN || wt.epl > 0,
+                 "MI_BF16_IN needs every block of a wave to share ld, a multiple of 64 up to 320");
   }
   P->L = ws_layout(hb, prm, part_max, P->n_lanes);
   *ws_need = P->L.total;
@@ -965,18 +979,19 @@ struct DevTable {
 };
 
 template <typename T>
-static void autotune_waves(const OiPlan& P, char* ws, hipStream_t s,
-                           std::vector<WaveTune>* tune) {
+static void autotune_waves(const OiPlan& P, char* ws, hipStream_t s, const int32_t* row_ptr,
+                           const int32_t* col, const float* val, std::vector<WaveTune>* tune) {
   const WsLayout& L = P.L;
   T* y0 = reinterpret_cast<T*>(ws + L.slab[0]);
   T* y1 = reinterpret_cast<T*>(ws + L.slab[1]);
-  const T* Sm = reinterpret_cast<const T*>(ws + L.G);
+  typedef typename Acc<T>::type TS;  // element type of the row product's S
+  const TS* Sm = reinterpret_cast<const TS*>(ws + L.G);
   double* part = reinterpret_cast<double*>(ws + L.part);
   double* G = reinterpret_cast<double*>(ws + L.H);
   const bool dbl = std::is_same<T, double>::value;
   tune->clear();
   for (const WaveTables& w : P.waves) {
-    WaveTune best{w.gram_target, w.nch, w.epl};
+    WaveTune best{w.gram_target, w.nch, w.epl, -1};
     float bt = 1e30f;
     for (int target : kGramTargets) {
       std::vector<GramTile> gt;
@@ -1002,22 +1017,40 @@ static void autotune_waves(const OiPlan& P, char* ws, hipStream_t s,
       DevTable<RowTile> drt(rt);
       if (!drt.p) continue;
       const float t = time_calls(s, [&] {
-        launch_rowmul<T, T>(drt.p, (int)rt.size(), w.tall, y0, w.small, Sm, w.tall, y1, nch, s);
+        launch_rowmul<T, TS>(drt.p, (int)rt.size(), w.tall, y0, w.small, Sm, w.tall, y1, nch, s);
       });
       if (t < bt) bt = t, best.nch = nch;
     }
-    // the SpMM keeps the row-per-wavefront kernel wherever it applies: it is
-    // the faster one on every wave size measured, and a fixed choice keeps
-    // one SpMM kernel per plan
+    // the SpMM keeps the row-per-wavefront kernel wherever it applies (the
+    // faster one on every wave size measured) and times its variants: one
+    // or two rows per wavefront, 8 or 4 neighbour rows gathered at a time,
+    // 16- or 4-wavefront workgroups (one Chebyshev step with a previous
+    // iterate, the common case)
     best.epl = spmm_epl(w.tall_host);
+    if (best.epl > 0) {
+      T* y2 = reinterpret_cast<T*>(ws + L.slab[2]);
+      const double* coef = reinterpret_cast<const double*>(ws + L.coef);
+      bt = 1e30f;
+      for (int var = 0; var < SPMM_NVAR; ++var) {
+        const float t = time_calls(s, [&] {
+          launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y0, y1, y2, coef,
+                         L.coef_stride, 1, s, best.epl, var);
+        });
+        if (t < bt) bt = t, best.spmm_var = var;
+      }
+    }
     tune->push_back(best);
   }
 }
 
 // ------------------------------------------------------------------ enqueue
 
-template <typename T>
+// T: element type of the working slabs; TV: of the caller's V0 and V (the
+// same, except for BF16 working slabs with an FP32 result).
+template <typename T, typename TV = T>
 static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
+  constexpr bool same = std::is_same<T, TV>::value;
+  typedef typename Acc<T>::type TS;  // the row products' S (FP32 or FP64)
   KClose kc_(a.tm);
   const mi_oi_params& prm = P.prm;
   const WsLayout& L = P.L;
@@ -1049,15 +1082,15 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   // tolerance mode: iterate in a working slab, copy each block out when it
   // meets the tolerance (or at the cap)
   const bool tolm = prm.tol > 0 && !doi && !rec;
-  T* Vout = static_cast<T*>(a.V);
-  T* V = tolm ? reinterpret_cast<T*>(ws + L.slab_w) : Vout;
+  TV* Vout = static_cast<TV*>(a.V);
+  TV* V = tolm ? reinterpret_cast<TV*>(ws + L.slab_w) : Vout;
   double* ritz_w = tolm ? reinterpret_cast<double*>(ws + L.ritz_w) : a.ritz;
   double* resid_w = reinterpret_cast<double*>(ws + L.resid_w);
   double* rpart = reinterpret_cast<double*>(ws + L.rpart);
   int32_t* frozen = reinterpret_cast<int32_t*>(ws + L.frozen);
   int32_t* fnow = reinterpret_cast<int32_t*>(ws + L.fnow);
-  const T* V0 = static_cast<const T*>(a.V0);
-  T* Vf = doi ? reinterpret_cast<T*>(ws + doi->off_vf) : nullptr;
+  const TV* V0 = static_cast<const TV*>(a.V0);
+  TV* Vf = doi ? reinterpret_cast<TV*>(ws + doi->off_vf) : nullptr;
   int32_t* doi_done = doi ? reinterpret_cast<int32_t*>(ws + doi->off_done) : nullptr;
   const size_t slab_bytes = size_t(P.hb.u_off[B]) * sizeof(T);
   const size_t mats = size_t(P.hb.m_off[B]);
@@ -1103,15 +1136,32 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       hipLaunchKernelGGL(k_init_a, dim3(ceil_div(w.nb, 256)), dim3(256), 0, s, w.tall, w.nb, P.info,
                          w.from_pred ? 1 : 0, prm.a_mode, prm.a_value, a.ritz, a_lo, b_hi);
     }
-    // start basis X of the first iteration
-    const T* X = V0;
+    // start basis X of the first iteration (in a working slab when the
+    // working type differs from the caller's)
+    const T* X = nullptr;
+    int xslab = -1;  // slab holding X (-1: X lives in V0 / V)
+    bool start_in_v = false;  // the start's Cholesky-QR wrote the output
+    if constexpr (same) {
+      X = V0;
+    } else if (!w.from_pred && prm.warm != MI_RANDOM) {
+      KScope k_(a.tm, MI_K_SETUP, s);
+      hipLaunchKernelGGL((k_copy_slab<TV, T>), dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                         V0, slab[1]);
+      X = slab[1];
+      xslab = 1;
+    }
     if (w.from_pred) {
-      {
-        KScope k_(a.tm, MI_K_SETUP, s);
-        hipLaunchKernelGGL(k_warm_copy<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.ptall,
-                           (const T*)Vout, V);
+      KScope k_(a.tm, MI_K_SETUP, s);
+      if constexpr (same) {
+        hipLaunchKernelGGL((k_warm_copy<T, T>), dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                           w.ptall, (const T*)Vout, V);
+        X = V;
+      } else {
+        hipLaunchKernelGGL((k_warm_copy<TV, T>), dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                           w.ptall, (const TV*)Vout, slab[1]);
+        X = slab[1];
+        xslab = 1;
       }
-      X = V;
     }
     // seeded start of the blocks without predecessor (MI_RANDOM)
     const bool rand_root = prm.warm == MI_RANDOM && !w.from_pred && !doi;
@@ -1121,7 +1171,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                          (uint64_t)prm.seed, slab[1]);
       X = slab[1];
     }
-    if (doi) {
+    if constexpr (same) if (doi) {
       // the walk edits its basis in place: roots start from a copy of V0
       if (!w.from_pred) {
         KScope k_(a.tm, MI_K_SETUP, s);
@@ -1133,7 +1183,6 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                          w.from_pred ? 1 : 0, doi->c_max, doi->t_max, doi->c, doi_done, doi->traj,
                          V);
     }
-    int xslab = -1;  // slab holding X (-1: X lives in V0 / V)
     auto chol = [&](float* s32) {
       KScope k_(a.tm, MI_K_CHOL, s);
       launch_chol_blk(w.sd, w.nb, G, Wk, Rinv, s32, a.status, w.max_ld, P.lds_max, s);
@@ -1152,14 +1201,18 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
       }
       chol(dbl ? nullptr : S32);
-      {
-        KScope k_(a.tm, MI_K_ROWMUL, s);
-        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, X, w.small,
-                            dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
-                            w.tall, slab[0], w.nch, s);
+      const TS* Sr = dbl ? reinterpret_cast<const TS*>(Rinv) : reinterpret_cast<const TS*>(S32);
+      KScope k_(a.tm, MI_K_ROWMUL, s);
+      if (!same && w.T == 0 && !doi) {
+        // no iteration follows: the orthonormalised start is the result,
+        // written in the output type
+        launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, X, w.small, Sr, w.tall, Vout, w.nch, s);
+        start_in_v = true;
+      } else {
+        launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, X, w.small, Sr, w.tall, slab[0], w.nch, s);
+        X = slab[0];
+        xslab = 0;
       }
-      X = slab[0];
-      xslab = 0;
     }
     const int n_iter = doi ? doi->t_max : w.T;
     bool wave_stopped = false;
@@ -1189,7 +1242,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         int free_s[3], nf = 0;
         for (int i = 0; i < 4 && nf < 3; ++i)
           if (i != xslab) free_s[nf++] = i;
-        if (prm.op == MI_OP_RZ) {
+        if constexpr (same) if (prm.op == MI_OP_RZ) {
           // Y = R^z X: x, r, p in the free slabs; q in X's slab once the first
           // solve has read X (or in the fourth slab when X is outside them)
           int q_s = xslab;
@@ -1219,7 +1272,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
               {
                 KScope k_(a.tm, MI_K_SPMM, s);
                 launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, ps,
-                               nullptr, qs, coef, L.coef_stride, 0, s, w.epl);
+                               nullptr, qs, coef, L.coef_stride, 0, s, w.epl, w.spmm_var);
               }
               KScope k_(a.tm, MI_K_CG, s);
               hipLaunchKernelGGL(k_cg_pq<T>, cg_grid, dim3(CG_COLS), 0, s, w.spmm, w.tall,
@@ -1241,7 +1294,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           {
             KScope k_(a.tm, MI_K_SPMM, s);
             launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, cur, prev, out,
-                           coef, L.coef_stride, k, s, w.epl);
+                           coef, L.coef_stride, k, s, w.epl, w.spmm_var);
           }
           prev = cur;
           cur = out;
@@ -1265,10 +1318,10 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
             if (i != ycur && i != xslab) dst = i;
           {
             KScope k_(a.tm, MI_K_ROWMUL, s);
-            launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
-                                dbl ? reinterpret_cast<const T*>(Rinv)
-                                    : reinterpret_cast<const T*>(S32),
-                                w.tall, slab[dst], w.nch, s);
+            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
+                                 dbl ? reinterpret_cast<const TS*>(Rinv)
+                                     : reinterpret_cast<const TS*>(S32),
+                                 w.tall, slab[dst], w.nch, s);
           }
           X = slab[dst];
           xslab = dst;
@@ -1283,7 +1336,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       {
         KScope k_(a.tm, MI_K_SPMM, s);
         launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
-                       L.coef_stride, w.m, s, w.epl);
+                       L.coef_stride, w.m, s, w.epl, w.spmm_var);
       }
       {
         KScope k_(a.tm, MI_K_GRAM, s);
@@ -1309,13 +1362,19 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         }
         {
           KScope k_(a.tm, MI_K_ROWMUL, s);
-          launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small,
-                              dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
-                              w.tall, V, w.nch, s);
+          const TS* Sr = dbl ? reinterpret_cast<const TS*>(Rinv) : reinterpret_cast<const TS*>(S32);
+          if constexpr (same) {
+            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, V, w.nch, s);
+            X = V;
+            xslab = -1;
+          } else {
+            // the W = L Y slab is free after the dual Gram
+            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, Wm, w.nch, s);
+            X = Wm;
+            xslab = wsl;
+          }
         }
-        X = V;
-        xslab = -1;
-        if (doi) {
+        if constexpr (same) if (doi) {
           KScope k_(a.tm, MI_K_DOI, s);
           hipLaunchKernelGGL(k_doi_step<T>, dim3(w.nb), dim3(DOI_THREADS), 0, s, w.tall, P.v_off,
                              doi->X, V, Vf, doi->c, doi_done, doi->iters, doi->traj, t, doi->t_max,
@@ -1404,7 +1463,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, T1,
                                         w.nchs, s);
         else
-          launch_rowmul<double, float>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S32,
+          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, Rinv, w.small, Z, w.small, S32,
                                        w.nchs, s);
       } else {
         {
@@ -1416,24 +1475,30 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         KScope k_(a.tm, MI_K_PERM_CAST, s);
         launch_perm_cast(w.sd, w.nb, S64, perm, dbl ? nullptr : S32, dbl ? T1 : nullptr, s);
       }
-      const T* Sm = dbl ? reinterpret_cast<const T*>(T1) : reinterpret_cast<const T*>(S32);
-      T* dstV;
+      const TS* Sm = dbl ? reinterpret_cast<const TS*>(T1) : reinterpret_cast<const TS*>(S32);
       int dslab = -1;
+      for (int i = 0; i < 4; ++i)
+        if (i != ycur) dslab = i;
       if (!fin) {
-        dstV = V;
-      } else {
-        for (int i = 0; i < 4; ++i)
-          if (i != ycur) dslab = i;
-        dstV = slab[dslab];
-      }
-      {
+        // an intermediate Rayleigh-Ritz step (rr_every): the rotated basis
+        // is the next iteration's start
         KScope k_(a.tm, MI_K_ROWMUL, s);
-        launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, dstV, w.nch, s);
-      }
-      if (!fin) {
-        X = V;
-        xslab = -1;
+        if constexpr (same) {
+          launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, V, w.nch, s);
+          X = V;
+          xslab = -1;
+        } else {
+          launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, slab[dslab], w.nch,
+                               s);
+          X = slab[dslab];
+          xslab = dslab;
+        }
       } else {
+        T* dstV = slab[dslab];
+        {
+          KScope k_(a.tm, MI_K_ROWMUL, s);
+          launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sm, w.tall, dstV, w.nch, s);
+        }
         // final Cholesky-QR: V = Vtmp R^-1 (upper triangular: keeps the span of
         // every leading column set, hence the Ritz order)
         {
@@ -1447,13 +1512,16 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         chol(dbl ? nullptr : S32);
         {
           KScope k_(a.tm, MI_K_ROWMUL, s);
-          launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, dstV, w.small,
-                              dbl ? reinterpret_cast<const T*>(Rinv) : reinterpret_cast<const T*>(S32),
-                              w.tall, V, w.nch, s);
+          launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, dstV, w.small,
+                               dbl ? reinterpret_cast<const TS*>(Rinv)
+                                   : reinterpret_cast<const TS*>(S32),
+                               w.tall, V, w.nch, s);
         }
-        X = V;
-        xslab = -1;
-        if (tolm) {
+        if constexpr (same) {
+          X = V;
+          xslab = -1;
+        }
+        if constexpr (same) if (tolm) {
           // residuals of the new Ritz pairs, the test, and the copy-out of the
           // blocks that converge now (or reach the cap)
           {
@@ -1475,16 +1543,16 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       // the frozen bases become the wave's output (and the next waves' start)
       if (doi->t_max > 0) {
         KScope k_(a.tm, MI_K_SETUP, s);
-        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
-                           (const T*)Vf, V);
+        hipLaunchKernelGGL(k_copy_slab<TV>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                           (const TV*)Vf, V);
       }
     } else if (w.T == 0) {
       // no iteration: the start itself (after its Cholesky-QR for predecessor
       // and seeded starts) is the result
       KScope k_(a.tm, MI_K_SETUP, s);
-      if (X != Vout)
-        hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, X,
-                           Vout);
+      if (!start_in_v && static_cast<const void*>(X) != static_cast<const void*>(Vout))
+        hipLaunchKernelGGL((k_copy_slab<T, TV>), dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+                           X, Vout);
       if (a.iters)
         hipLaunchKernelGGL(k_resid_final, dim3(w.nb), dim3(256), 0, s, w.tall, P.info,
                            P.tile_base, L.cg_ldp, (const double*)rpart, (double*)nullptr, 0,
@@ -1492,9 +1560,9 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
     } else if (!tolm && (a.resid || a.iters)) {
       KScope k_(a.tm, MI_K_SETUP, s);
       if (a.resid)
-        hipLaunchKernelGGL(k_resid_tile<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
+        hipLaunchKernelGGL(k_resid_tile<TV>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall,
                            w.csr, P.info, P.tile_base, L.cg_ldp, a.row_ptr, a.col, a.val,
-                           (const T*)Vout, (const double*)a.ritz, rpart);
+                           (const TV*)Vout, (const double*)a.ritz, rpart);
       hipLaunchKernelGGL(k_resid_final, dim3(w.nb), dim3(256), 0, s, w.tall, P.info, P.tile_base,
                          L.cg_ldp, (const double*)rpart, a.resid, w.T, a.iters);
     }
@@ -1522,8 +1590,11 @@ static bool same_key(const OiPlan& P, const HostBlocks& hb, const std::vector<in
 
 static mi_status check_params(const mi_oi_params* prm) {
   MI_CHECK_ARG(prm != nullptr, "params are NULL");
-  MI_CHECK_ARG(prm->precision == MI_FP32 || prm->precision == MI_FP64, "precision %d unsupported",
-               prm->precision);
+  MI_CHECK_ARG(prm->precision == MI_FP32 || prm->precision == MI_FP64 ||
+                   prm->precision == MI_BF16_IN,
+               "precision %d unsupported", prm->precision);
+  MI_CHECK_ARG(prm->precision != MI_BF16_IN || (prm->op == MI_OP_CHEB && prm->tol == 0),
+               "MI_BF16_IN supports the Chebyshev filter with fixed iteration counts only");
   MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN || prm->warm == MI_WARM_PRED || prm->warm == MI_RANDOM,
                "warm mode %d unknown", prm->warm);
   MI_CHECK_ARG(prm->tol >= 0 && prm->tol < 1, "tol must be in [0, 1)");
@@ -1563,12 +1634,14 @@ static mi_status get_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
                           const std::vector<const void*>& ptrs, void* ws, size_t ws_bytes,
                           bool per_block, OiPlan** out) {
   OiPlan* P = static_cast<OiPlan*>(*slot);
-  if (!P || !same_key(*P, hb, nnz, prm, ptrs, ws_bytes, per_block)) {
+  if (!P || !same_key(*P, hb, nnz, prm, ptrs, ws_bytes, per_block) ||
+      P->spmm_force != ctx->spmm_force) {
     delete P;
     *slot = nullptr;
     std::unique_ptr<OiPlan> np;
     size_t need = 0;
-    mi_status st = make_plan(hb, nnz, prm, per_block, device_lds_max(ctx->device), &np, &need);
+    mi_status st = make_plan(hb, nnz, prm, per_block, device_lds_max(ctx->device),
+                             ctx->spmm_force, &np, &need);
     if (st) return st;
     if (!ws || ws_bytes < need) {
       set_error("workspace %zu bytes < %zu required", ws_bytes, need);
@@ -1578,14 +1651,21 @@ static mi_status get_plan(mi_ctx* ctx, void** slot, const HostBlocks& hb,
       if (!np->cap_stream)
         MI_TRY_HIP(hipStreamCreateWithFlags(&np->cap_stream, hipStreamNonBlocking));
       std::vector<WaveTune> tune;
+      const int32_t* rp = static_cast<const int32_t*>(ptrs[0]);
+      const int32_t* cl = static_cast<const int32_t*>(ptrs[1]);
+      const float* vl = static_cast<const float*>(ptrs[2]);
+      char* wsc = static_cast<char*>(ws);
       if (prm.precision == MI_FP64)
-        autotune_waves<double>(*np, static_cast<char*>(ws), np->cap_stream, &tune);
+        autotune_waves<double>(*np, wsc, np->cap_stream, rp, cl, vl, &tune);
+      else if (prm.precision == MI_BF16_IN)
+        autotune_waves<bf16>(*np, wsc, np->cap_stream, rp, cl, vl, &tune);
       else
-        autotune_waves<float>(*np, static_cast<char*>(ws), np->cap_stream, &tune);
+        autotune_waves<float>(*np, wsc, np->cap_stream, rp, cl, vl, &tune);
       MI_TRY_HIP(hipGetLastError());
       MI_TRY_HIP(hipStreamSynchronize(np->cap_stream));
       std::unique_ptr<OiPlan> tp;
-      st = make_plan(hb, nnz, prm, per_block, device_lds_max(ctx->device), &tp, &need, &tune);
+      st = make_plan(hb, nnz, prm, per_block, device_lds_max(ctx->device), ctx->spmm_force, &tp,
+                     &need, &tune);
       if (st) return st;
       tp->cap_stream = np->cap_stream;
       np->cap_stream = nullptr;
@@ -1676,6 +1756,8 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
   if (per_block || ctx->timer) {
     if (prm->precision == MI_FP64)
       enqueue<double>(*P, a, s);
+    else if (prm->precision == MI_BF16_IN)
+      enqueue<bf16, float>(*P, a, s);
     else
       enqueue<float>(*P, a, s);
     MI_TRY_HIP(hipGetLastError());
@@ -1698,6 +1780,8 @@ static mi_status oi_run(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* p
     MI_TRY_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     if (prm->precision == MI_FP64)
       enqueue<double>(*P, a, P->cap_stream);
+    else if (prm->precision == MI_BF16_IN)
+      enqueue<bf16, float>(*P, a, P->cap_stream);
     else
       enqueue<float>(*P, a, P->cap_stream);
     hipError_t e1 = hipGetLastError();
@@ -1724,6 +1808,7 @@ static void doi_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t* of
 
 static mi_status doi_check(const HostBlocks& hb, const mi_oi_params* prm, const mi_doi_params* dp) {
   MI_CHECK_ARG(dp != nullptr, "walk parameters are NULL");
+  MI_CHECK_ARG(prm->precision != MI_BF16_IN, "the dynamic walk supports MI_FP32 and MI_FP64");
   MI_CHECK_ARG(dp->eps_l >= 0 && dp->eps_h >= dp->eps_l, "need 0 <= eps_l <= eps_h");
   MI_CHECK_ARG(dp->t_max >= 0 && dp->t_max <= 10000, "t_max %d out of range", dp->t_max);
   MI_CHECK_ARG(dp->c_max >= 1, "c_max must be >= 1");
@@ -1775,9 +1860,10 @@ mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves)
   MI_CHECK_ARG(P != nullptr, "no tracking plan yet (call mi_oi_track first)");
   *n_waves = (int32_t)P->waves.size();
   for (int w = 0; w < (int)P->waves.size() && w < cap; ++w) {
-    out[3 * w] = P->waves[w].gram_target;
-    out[3 * w + 1] = P->waves[w].nch;
-    out[3 * w + 2] = P->waves[w].epl;
+    out[4 * w] = P->waves[w].gram_target;
+    out[4 * w + 1] = P->waves[w].nch;
+    out[4 * w + 2] = P->waves[w].epl;
+    out[4 * w + 3] = P->waves[w].spmm_var;
   }
   return MI_OK;
 }

@@ -21,6 +21,7 @@ struct WaveTables {
   int max_ld = 0, max_q = 0, max_p = 0;
   int nch = 64, nchs = 64;
   int epl = 0;  // elements per lane of the row-per-wavefront SpMM (0: generic kernel)
+  int spmm_var = -1;  // SpMM variant (SPMM_VAR_*; -1: the default for epl)
   int gram_target = GRAM_TARGET;  // workgroups of the split Gram launch
   int lane = 0;  // stream lane: the waves of one lane form one dependency chain
   std::vector<MatDesc> tall_host;  // host copy of `tall` (for retuning)
@@ -65,6 +66,7 @@ struct WaveTune {
   int gram_target;  // split-K target of the Gram
   int nch;          // output-column width of the row product
   int epl;          // row-per-wavefront SpMM elements per lane (0: generic)
+  int spmm_var;     // SpMM variant (SPMM_VAR_*, -1: the default for epl)
 };
 
 struct OiPlan {
@@ -75,6 +77,7 @@ struct OiPlan {
   std::vector<const void*> ptrs;
   size_t ws_bytes = 0;
   bool per_block = false;
+  int spmm_force = -1;  // SpMM variant forced on every wave that uses the per-row kernels
   // content
   std::vector<WaveTables> waves;
   WsLayout L;

@@ -151,6 +151,16 @@ def disk_blocks(n_blocks=1024, n_min=500, n_max=5000, c_max=256, p_max=320, key=
                     order=np.arange(n_blocks), c=c, p=p, global_ids=gids, n_global=int(sizes.sum()))
 
 
+def sample_blocks(n, k=64, key=(97,)):
+    """Seeded sample of k block indices of a set with block sizes n (without
+    replacement), always including the smallest and the largest block;
+    ascending."""
+    n = np.asarray(n)
+    rng = M.rng_for(*key)
+    pick = rng.choice(n.size, size=min(k, n.size), replace=False)
+    return np.array(sorted({int(np.argmin(n)), int(np.argmax(n)), *map(int, pick)}))
+
+
 def geodesic_blocks(nu=316, n_blocks=100, c=200, p=256, amp=0.05, key=(4,)):
     """Precision workload: displaced geodesic sphere (10 nu^2 + 2 vertices)."""
     v, f = M.geodesic_sphere(nu)

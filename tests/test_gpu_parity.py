@@ -6,6 +6,8 @@ weights within 1 ulp of the FP64 value; tracked subspaces within a principal
 angle of 1e-5 rad (FP32) of the oracle's eigenspace and reconstructed
 coordinates within 1e-5 relative error; FP64 paths to 1e-9.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -174,15 +176,22 @@ def test_grid_single_fp64(ctx, eig):
 
 # ------------------------------------------------------------------ warm-started chain, FP32
 
-def _chain_check(up, V, ritz, st, c, sample=None):
+def _chain_check(up, V, ritz, st, c, sample=None, Xr=None):
+    """Subspaces at c against the oracle; the reconstruction is the GPU's own
+    (mi_project + mi_reconstruct output Xr) when given, else the GPU basis
+    applied on the host."""
     blocks = range(up.blocks.n_blocks) if sample is None else sample
     worst = 0.0
+    Xh = None if Xr is None else Xr.double().cpu().numpy().reshape(-1, 3)
     for b in blocks:
         _, lam, U = oracle_block(up, b, k=int(up.blocks.p[b]) + 1)
         Vg = up.slab(V, b)
         ang = S.sin_theta_max(U[:, :c], Vg[:, :c])
         Xo = S.encode_decode(U[:, :c], up.X32(b))
-        Xg = S.encode_decode(S.orthonormalize(Vg[:, :c]), up.X32(b))
+        if Xh is None:
+            Xg = S.encode_decode(S.orthonormalize(Vg[:, :c]), up.X32(b))
+        else:
+            Xg = Xh[int(up.blocks.v_off[b]):int(up.blocks.v_off[b + 1])]
         rec = S.rel_error(Xg, Xo)
         worst = max(worst, ang)
         assert ang < ANGLE_FP32, (b, ang, lam[c] - lam[c - 1])
@@ -263,16 +272,59 @@ def test_autotuned_launch_shapes(ctx, chain_small):
     tune = ctx.tuning()
     assert len(tune) == int(np.asarray(up.bs.level).max()) + 1
     ld = int(up.blocks.ld[0])
-    for g, nch, epl in tune:
+    for g, nch, epl, var in tune:
         assert g in (192, 384, 768, 1536)
         assert nch in (64, 96, 128, 192, 256) and (ld % nch == 0 or nch == 64)
         assert epl in (0, ld // 64)
+        assert var in (tuple(range(7)) if epl else (-1,))
     _chain_check(up, V, ritz, st, 100)
     # the default heuristics give the same subspaces
     V2, _, _ = mis.oi_track(ctx, up.blocks, Lp, warm_params(), V0=V0)
     torch.cuda.synchronize()
     for b in range(up.blocks.n_blocks):
         assert S.sin_theta_max(up.slab(V2, b)[:, :100], up.slab(V, b)[:, :100]) < 1e-5
+
+
+@pytest.mark.parametrize("width", [64, 128, 192, 256, 320])
+def test_spmm_variants_agree(ctx, width):
+    """Every launch shape of the wavefront-per-row SpMM (forced on the plan in
+    turn) gives the same tracked subspaces and Ritz values on a wave of
+    independent disks of one tracked width, and each meets the oracle."""
+    bs = W.disk_blocks(n_blocks=3, n_min=max(width + 40, 300), n_max=2400, c_max=width - 32,
+                       p_max=width, key=(36, width))
+    bs.p = np.full(3, width)
+    bs.c = bs.p - 32
+    up = Uploaded(bs)
+    assert (np.asarray(up.blocks.ld) == width).all()
+    Lp = up.laplacian(ctx)
+    V0 = up.starts(torch.float32)
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=6, m0=10, passes0=2)
+    out = []
+    try:
+        for var in range(7):
+            ctx.force_spmm(var)
+            V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
+            torch.cuda.synchronize()
+            assert [t[3] for t in ctx.tuning()] == [var], ctx.tuning()
+            assert int(st.abs().sum()) == 0, (var, st)
+            out.append((V.clone(), ritz.cpu().numpy()))
+    finally:
+        ctx.force_spmm(-1)
+    V_ref, r_ref = out[0]
+    for b in range(up.blocks.n_blocks):
+        cb = int(bs.c[b])
+        _, lam, U = oracle_block(up, b, k=width + 1)
+        t0 = int(up.blocks.t_off[b])
+        for var, (V, r) in enumerate(out):
+            Vb = up.slab(V, b)[:, :cb]
+            ang = S.sin_theta_max(U[:, :cb], Vb)
+            dv = S.sin_theta_max(up.slab(V_ref, b)[:, :cb], Vb)
+            dr = np.abs(r[t0:t0 + cb] - r_ref[t0:t0 + cb]).max()
+            print(f"width {width} block {b} variant {var}: sin {ang:.2e}, vs variant 0 {dv:.1e}, "
+                  f"ritz {dr:.1e}, bit-equal {bool(torch.equal(V, V_ref))}")
+            assert ang < ANGLE_FP32, (var, b, ang)
+            assert dv < 1e-5, (var, b, dv)
+            assert dr <= 4 * np.finfo(np.float32).eps * lam[cb - 1] + 1e-12, (var, b, dr)
 
 
 @pytest.mark.parametrize("rr_every", [0, 1])
@@ -330,8 +382,13 @@ def test_c2_chain_every_block_healthy(ctx, chain_c2, eig, T):
         assert np.abs(Vb.T @ Vb - np.eye(Vb.shape[1])).max() < 1e-4, b
     if T == 3:
         if int((up.blocks.pred < 0).sum()) == 3:
-            # the benchmark's configuration: every block against the oracle
-            _chain_check(up, V, ritz, st, 100)
+            # the benchmark's configuration: every block against the oracle,
+            # with the library's projection and reconstruction at its layout
+            c = torch.full((up.blocks.n_blocks,), 100, dtype=torch.int32, device="cuda:0")
+            E = mis.project(ctx, up.blocks, c, V, up.coords)
+            Xr = mis.reconstruct(ctx, up.blocks, c, V, E)
+            torch.cuda.synchronize()
+            _chain_check(up, V, ritz, st, 100, Xr=Xr)
         else:
             _chain_check(up, V, ritz, st, 100, sample=[84, 87, 98])
 
@@ -712,6 +769,70 @@ def test_seeded_random_start(ctx, precision):
         assert S.sin_theta_max(ref, up.slab(V2, b)[:, :p]) > 0.1
 
 
+def _bf16_round(x):
+    """Nearest bfloat16 (ties to even) of float32 values, as float64."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_seeded_start_orthonormalised(ctx):
+    """MI_BF16_IN with no iteration: the seeded start is rounded to BF16 in a
+    working slab, its Gram taken on the BF16 MFMA and its Cholesky-QR written
+    in FP32 from the BF16 slab, so the result must be orthonormal to FP32
+    rounding (a wrong Gram would leave it far from orthonormal) and span
+    exactly the BF16-rounded SplitMix64 matrix."""
+    bs = W.disk_blocks(n_blocks=3, n_min=300, n_max=700, c_max=48, p_max=64, key=(36,))
+    up = Uploaded(bs)
+    blocks = mis.Blocks(bs.n, p=up.fl["p"], ld=up.fl["ld"])
+    Lp = up.laplacian(ctx)
+    seed = 1810027193
+    prm = mis.OiParams(precision=mis.MI_BF16_IN, warm=mis.MI_RANDOM, T=0, T0=0, seed=seed)
+    V, _, st = mis.oi_track(ctx, blocks, Lp, prm)
+    torch.cuda.synchronize()
+    assert V.dtype == torch.float32 and int(st.abs().sum()) == 0
+    for b in range(blocks.n_blocks):
+        n, p = int(blocks.n[b]), int(blocks.p[b])
+        Vb = up.slab(V, b)
+        ref = _bf16_round(_splitmix_start(seed, b, n, p).astype(np.float32))
+        assert np.abs(Vb[:, :p].T @ Vb[:, :p] - np.eye(p)).max() < 2e-5, b
+        assert S.sin_theta_max(ref, Vb[:, :p]) < 1e-5, b
+
+
+@pytest.mark.parametrize("warm", [mis.MI_WARM_GIVEN, mis.MI_RANDOM], ids=["given", "random"])
+def test_bf16_small_disks_against_oracle(ctx, warm):
+    """BF16 working slabs on uneven disks of one width (p = 128): every block
+    finite and unflagged, the FP32 output orthonormal, and its subspace and
+    reconstruction against the FP64 oracle at the BF16 scale.  The bar,
+    5e-2 for the angle and 2e-2 for the reconstruction, is a few times what
+    BF16 rounding of the iterates (u = 2^-8) gives at the cuts of these
+    blocks, 5e-3 to 3e-2; a wrong kernel gives O(1)."""
+    bs = W.disk_blocks(n_blocks=6, n_min=300, n_max=2000, c_max=96, p_max=128, key=(35,))
+    up = Uploaded(bs)
+    blocks = mis.Blocks(bs.n, p=up.fl["p"], ld=up.fl["ld"])
+    Lp = up.laplacian(ctx)
+    prm = mis.OiParams(precision=mis.MI_BF16_IN, warm=warm, seed=11, T0=10, m0=8, passes0=2)
+    V, ritz, st = mis.oi_track(ctx, blocks, Lp, prm,
+                               V0=up.starts(torch.float32) if warm == mis.MI_WARM_GIVEN else None)
+    c = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
+    E = mis.project(ctx, blocks, c, V, up.coords)
+    Xr = mis.reconstruct(ctx, blocks, c, V, E)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0, st
+    Xh = Xr.double().cpu().numpy().reshape(-1, 3)
+    for b in range(blocks.n_blocks):
+        cb = int(bs.c[b])
+        _, lam, U = oracle_block(up, b, k=int(bs.p[b]) + 1)
+        Vb = up.slab(V, b)[:, :cb]
+        ang = S.sin_theta_max(U[:, :cb], Vb)
+        v0, v1 = int(blocks.v_off[b]), int(blocks.v_off[b + 1])
+        rec = S.rel_error(Xh[v0:v1], S.encode_decode(U[:, :cb], up.X32(b)))
+        print(f"block {b} (n {blocks.n[b]}, gap {lam[cb] - lam[cb - 1]:.1e}): sin {ang:.2e}, "
+              f"recon {rec:.2e}")
+        assert np.abs(Vb.T @ Vb - np.eye(cb)).max() < 2e-5, b
+        assert ang < 5e-2 and rec < 2e-2, (b, ang, rec)
+
+
 def test_seeded_start_tolerance_against_oracle(ctx):
     """Independent uneven disks from seeded random starts in tolerance mode
     (the batched-uneven workload's configuration at a small size): every
@@ -1087,11 +1208,14 @@ def _fp32_bar(lam, c, p):
 
 def test_c5_full_size_frames_and_adjoint(ctx):
     """100,002-vertex geodesic sphere, 64 blocks, c = 150, p = 192, distance
-    weights of the current frame: frame 0 cold, frames 1-2 warm-started from
-    the previous frame, sampled blocks against the oracle.  Then the adjoint
-    of frame 2's encode/decode (3 iterations of two degree-10 passes on a
-    fixed interval from a seeded start) against the oracle's FP64 autograd on
-    two sampled blocks."""
+    weights of the current frame: frame 0 cold, frames 1-59 each warm-started
+    from the previous frame; at frames 0, 1, 30 and 59 a seeded sample of 16
+    blocks against the oracle at sin 1e-5 (the blocks whose Davis-Kahan
+    floor estimate u32 lambda_p / gap_c exceeds 1e-5 are listed).  Then the
+    adjoint of frame 2's
+    encode/decode (3 iterations of two degree-10 passes on a fixed interval
+    from a seeded start) against the oracle's FP64 autograd on two sampled
+    blocks, to 1e-3 relative."""
     from oracle import adjoint as adj
     bs = W.dynamic_frames()
     up = Uploaded(bs)
@@ -1103,9 +1227,11 @@ def test_c5_full_size_frames_and_adjoint(ctx):
     # and a warm frame needs 7 iterations where a cold one takes 8
     warm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=7, m0=10, passes0=2,
                         a_mode=mis.MI_A_RITZ)
-    sample = [0, 21, 42, 63]
+    sample = [int(b) for b in W.sample_blocks(np.asarray(up.blocks.n), k=16, key=(98,))]
+    assert len(sample) >= 16
     V = ritz = None
-    for f in range(3):
+    tight = []
+    for f in range(len(frames)):
         X = np.concatenate([np.asarray(x, np.float32) for x in frames[f]])
         coords = torch.from_numpy(np.ascontiguousarray(X.reshape(-1))).to("cuda:0")
         if f > 0:
@@ -1116,7 +1242,7 @@ def test_c5_full_size_frames_and_adjoint(ctx):
         torch.cuda.synchronize()
         s = st.cpu().numpy()
         assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all(), (f, s)
-        if f == 1:
+        if f not in (0, 1, 30, 59):
             continue
         for b in sample:
             xb = X[up.blocks.v_off[b]:up.blocks.v_off[b + 1]].astype(np.float64)
@@ -1124,11 +1250,17 @@ def test_c5_full_size_frames_and_adjoint(ctx):
             Lo = lap.laplacian_dense(xb.shape[0], e, lap.edge_weights(e, xb, lap.INV_SQ_DIST))
             lam, U = S.eigh_lowest(Lo, 193)
             ang = S.sin_theta_max(U[:, :150], up.slab(V, b)[:, :150])
-            print(f"frame {f} block {b}: sin angle {ang:.2e} (bar {_fp32_bar(lam, 150, 192):.1e})")
-            assert ang <= _fp32_bar(lam, 150, 192), (f, b, ang, lam[150] - lam[149])
+            floor = S.fp32_floor(lam, 150, 192)
+            if floor > ANGLE_FP32:
+                tight.append((f, b, float(lam[150] - lam[149]), floor))
+            print(f"frame {f} block {b}: sin angle {ang:.2e} (FP32 floor estimate {floor:.1e})")
+            assert ang <= ANGLE_FP32, (f, b, ang, lam[150] - lam[149])
+    print(f"cuts whose FP32 floor estimate exceeds 1e-5 (frame, block, gap, floor): {tight}")
     # adjoint of frame 2 on a fixed interval [a, b]: b above every block's
     # Gershgorin bound, a below the sampled blocks' lambda_p
     X = np.concatenate([np.asarray(x, np.float32) for x in frames[2]])
+    mis.laplacian_values(ctx, up.blocks, Lp, torch.from_numpy(np.ascontiguousarray(
+        X.reshape(-1))).to("cuda:0"), mis.MI_W_INV_SQ_DIST)
     bsamp = [0, 42]
     gersh, lp = 0.0, np.inf
     Los = {}
@@ -1166,79 +1298,155 @@ def test_c5_full_size_frames_and_adjoint(ctx):
                                    G[v0:v1].astype(np.float32).astype(np.float64))
         rx, rw = _rel(Xbar[v0:v1], gX), _rel(wbar[e0:e1], gw)
         print(f"adjoint block {b}: rel err Xbar {rx:.2e} wbar {rw:.2e}")
-        assert rx < 1e-2 and rw < 1e-2, (b, rx, rw)
+        assert rx < 1e-3 and rw < 1e-3, (b, rx, rw)
+
+
+def _c3_target():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_calibrated_target.txt")) as f:
+        for line in f:
+            if line.startswith("target "):
+                return float(line.split()[1])
+    raise AssertionError("no target in c3_calibrated_target.txt")
 
 
 def test_c3_full_size_batched_uneven(ctx):
     """1,024 independent Delaunay disks of 500-5,000 vertices (2.8M vertices),
-    p_b = min(320, n_b), c_b = min(256, p_b), cold seeded starts, one launch
-    sequence for all blocks; NMSVE curves and the choice of c for every block
-    in one call.  Every block healthy; sampled blocks (smallest, largest and
-    four seeded others) against the oracle, at the FP32 bar of their cut."""
+    p_b = min(320, n_b), c_max = 256, in the benchmark's launch configuration
+    (seeded MI_RANDOM starts, T = 6 iterations of two degree-12 passes, one
+    wave, autotuned shapes).  On the seeded 64-block sample plus the smallest
+    and largest disk: the kept space at c_max within sin 1e-5 of the
+    oracle's (a block whose cut is a near-tie, relative gap below 1e-3, is
+    listed and checked at the end of its cluster instead); the GPU's NMSVE
+    curve (Eq. 16) against the oracle's explicit reconstructions; and the
+    choice of c at the literal target 1e-4 (no block reaches it: c = 256)
+    and at the calibrated target, equal to the oracle's brute-force choice
+    up to a curve value at the target within rounding, with the kept space
+    at the chosen c within 1e-5."""
     bs = W.disk_blocks()
     up = Uploaded(bs)
+    blocks = mis.Blocks(bs.n, p=up.fl["p"], ld=up.fl["ld"])
     Lp = up.laplacian(ctx)
     gl = up.laplacian(ctx, mis.MI_W_INV_DIST)
-    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=12, m0=8, passes0=2)
-    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=up.starts(torch.float32))
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_RANDOM, seed=181002719, T0=6, m0=12,
+                       passes0=2, adapt=1, a_mode=mis.MI_A_WEYL, a_value=1.0, autotune=1)
+    V, ritz, st = mis.oi_track(ctx, blocks, Lp, prm)
     cmax = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
-    cg, metric = mis.choose_c(ctx, up.blocks, cmax, 1e-4, 1e-3, V, ritz, up.coords, gl)
+    target = _c3_target()
+    c_lit, _ = mis.choose_c(ctx, blocks, cmax, 1e-4, 1e-3, V, ritz, up.coords, gl)
+    c_cal, metric = mis.choose_c(ctx, blocks, cmax, target, 1e-3, V, ritz, up.coords, gl)
     torch.cuda.synchronize()
     s = st.cpu().numpy()
-    assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all()
-    cgh = cg.cpu().numpy()
-    assert ((cgh >= 1) & (cgh <= np.asarray(bs.c))).all()
-    n = np.asarray(up.blocks.n)
-    rng = M.rng_for(97)
-    sample = sorted({int(np.argmin(n)), int(np.argmax(n)), *rng.choice(len(n), 4, replace=False)})
-    for b in sample:
-        cb, pb = int(bs.c[b]), int(bs.p[b])
-        _, lam, U = oracle_block(up, b, k=pb + 1)
-        ang = S.sin_theta_max(U[:, :cb], up.slab(V, b)[:, :cb])
-        print(f"block {b} (n {n[b]}, c {cb}): sin angle {ang:.2e} (bar {_fp32_bar(lam, cb, pb):.1e})")
-        assert ang <= _fp32_bar(lam, cb, pb), (b, ang, lam[cb] - lam[cb - 1])
+    assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE
+                 | mis._lib.MI_BLOCK_NOCONV) == 0).all()
+    c_lit, c_cal, mh = c_lit.cpu().numpy(), c_cal.cpu().numpy(), metric.cpu().numpy()
+    assert ((c_cal >= 1) & (c_cal <= np.asarray(bs.c))).all()
+    n = np.asarray(blocks.n)
+    ties, worst = [], 0.0
+    for b in W.sample_blocks(n):
+        b = int(b)
+        cm, pb = int(bs.c[b]), int(bs.p[b])
+        X = up.X32(b)
+        e = lap.canonical_edges(np.asarray(bs.faces[b], np.int64), int(n[b]))
+        # not the cached oracle_block: 66 dense 5,000 x 5,000 Laplacians
+        lam, U = S.eigh_lowest(lap.laplacian_dense(int(n[b]), e, np.ones(len(e))), pb + 1)
+        Vb = up.slab(V, b)
+        cut = cm
+        if (lam[cm] - lam[cm - 1]) < 1e-3 * lam[cm]:  # near-tie at the cut
+            while cut < pb - 1 and (lam[cut] - lam[cut - 1]) < 1e-3 * lam[cut]:
+                cut += 1
+            ties.append((b, cm, cut, float(lam[cm] - lam[cm - 1])))
+        ang = S.sin_theta_max(U[:, :cut], Vb[:, :cut])
+        worst = max(worst, ang)
+        curve = met.nmsve_curve_sparse(U, X, e, X, cm)
+        t0 = int(blocks.t_off[b])
+        assert np.abs(mh[t0:t0 + cm] - curve).max() < 1e-4 * curve.max(), b
+        assert int(c_lit[b]) == met.choose_c(curve, lam, 1e-4, 1e-3) == cm, b
+        co = met.choose_c(curve, lam, target, 1e-3)
+        cg = int(c_cal[b])
+        if cg != co:  # only a curve value at the target within rounding may differ
+            k = min(cg, co) - 1
+            assert abs(curve[k] - target) < 1e-4 * target, (b, cg, co, curve[k], target)
+        ang_c = S.sin_theta_max(U[:, :cg], Vb[:, :cg])
+        print(f"block {b} (n {n[b]}): sin angle {ang:.2e} at c {cut}, {ang_c:.2e} at the "
+              f"chosen c {cg} (oracle {co})")
+        assert ang <= ANGLE_FP32, (b, ang, cut)
+        assert ang_c <= ANGLE_FP32, (b, ang_c, cg)
+    print(f"worst sin angle {worst:.2e}; near-ties at c_max (block, c, cluster end, gap): {ties}")
 
 
-def test_c4_full_size_fp32(ctx):
+def test_c4_full_size_fp32_and_bf16(ctx):
     """The 998,562-vertex displaced geodesic sphere in 100 blocks of about 10k
-    vertices, c = 200, p = 256, all blocks in one launch sequence from seeded
-    starts (FP32 slabs: the reduced-precision input option is not built);
-    two sampled blocks against the oracle at the FP32 bar of their cut, and
-    the SpMM's event-timed bandwidth on slabs far larger than the
-    infinity cache."""
+    vertices, c = 200, p = 256, all blocks in one wave from seeded starts,
+    once with FP32 slabs and once with BF16 working slabs (MI_BF16_IN).  On
+    8 seeded blocks (with the smallest and largest) against the FP64 oracle:
+    FP32 within sin 1e-5 (a cut too tight for FP32 is listed and held to
+    twice its floor); BF16 reported per block (angle, reconstruction error,
+    ||E - E_oracle|| / ||E_oracle||) and held to the BF16 scale (angle 5e-2,
+    reconstruction and coefficients 2e-2).  The SpMM's event-timed
+    bandwidth on slabs far larger than the infinity cache, for both."""
     bs = W.geodesic_blocks()
     up = Uploaded(bs)
+    blocks = mis.Blocks(bs.n, p=up.fl["p"], ld=up.fl["ld"])  # independent: one wave
     Lp = up.laplacian(ctx)
-    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=12, m0=10, passes0=2)
-    V0 = up.starts(torch.float32)
-    V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    try:
-        mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0, V=V)
-        torch.cuda.synchronize()
-        kt = ctx.kernel_times()
-    finally:
-        ctx.set_timing(False)
-    s = st.cpu().numpy()
-    assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all()
-    # algorithmic SpMM bytes: CSR once, the input rows, the previous iterate
-    # (all but the first step of a pass) and the output, per step
-    n = np.asarray(up.blocks.n, np.int64)
+    n = np.asarray(blocks.n, np.int64)
     nnz = np.diff(np.asarray(Lp.nnz_off, np.int64))
     csr = int(((n + 1) * 4 + nnz * 8).sum())
-    slab = int((n * np.asarray(up.blocks.ld, np.int64) * 4).sum())
-    per_pass = 10 * (csr + 2 * slab) + 9 * slab
-    tot = prm.T0 * (2 * per_pass + csr + 2 * slab)
-    ms, launches = kt["spmm"]
-    print(f"C4 SpMM: {launches} launches, {1e3 * ms / launches:.1f} us each, "
-          f"{tot / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
-    for b in (0, 57):
+    c = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
+    res = {}
+    for prec, es in ((mis.MI_FP32, 4), (mis.MI_BF16_IN, 2)):
+        prm = mis.OiParams(precision=prec, warm=mis.MI_RANDOM, seed=181002719, T0=12, m0=10,
+                           passes0=2)
+        V, ritz, st = mis.oi_track(ctx, blocks, Lp, prm)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        try:
+            mis.oi_track(ctx, blocks, Lp, prm, V=V)
+            torch.cuda.synchronize()
+            kt = ctx.kernel_times()
+        finally:
+            ctx.set_timing(False)
+        s = st.cpu().numpy()
+        assert (s & (mis._lib.MI_BLOCK_NOT_PD | mis._lib.MI_BLOCK_NONFINITE) == 0).all()
+        E = mis.project(ctx, blocks, c, V, up.coords)
+        torch.cuda.synchronize()
+        # algorithmic SpMM bytes: CSR once, the input rows, the previous
+        # iterate (all but the first step of a pass) and the output, per step
+        slab = int((n * np.asarray(blocks.ld, np.int64) * es).sum())
+        per_pass = 10 * (csr + 2 * slab) + 9 * slab
+        tot = prm.T0 * (2 * per_pass + csr + 2 * slab)
+        ms, launches = kt["spmm"]
+        print(f"precision {prec}: SpMM {launches} launches, {1e3 * ms / launches:.1f} us each, "
+              f"{tot / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic")
+        res[prec] = (V, E.cpu().numpy().reshape(-1, 3))
+    for b in W.sample_blocks(n, k=6, key=(99,)):
+        b = int(b)
         cb, pb = int(bs.c[b]), int(bs.p[b])
-        _, lam, U = oracle_block(up, b, k=pb + 1)
-        ang = S.sin_theta_max(U[:, :cb], up.slab(V, b)[:, :cb])
-        print(f"block {b} (n {n[b]}): sin angle {ang:.2e} (bar {_fp32_bar(lam, cb, pb):.1e})")
-        assert ang <= _fp32_bar(lam, cb, pb), (b, ang, lam[cb] - lam[cb - 1])
+        X = up.X32(b)
+        e = lap.canonical_edges(np.asarray(bs.faces[b], np.int64), int(n[b]))
+        lam, U = S.eigh_lowest(lap.laplacian_dense(int(n[b]), e, np.ones(len(e))), pb + 1)
+        Eo = U[:, :cb].T @ X
+        Xo = U[:, :cb] @ Eo
+        t0 = int(blocks.t_off[b])
+        bar32 = ANGLE_FP32
+        if 2.0 * S.fp32_floor(lam, cb, pb) > ANGLE_FP32:
+            bar32 = 2.0 * S.fp32_floor(lam, cb, pb)
+        out = []
+        for prec, (V, Eh) in res.items():
+            Vb = up.slab(V, b)[:, :cb]
+            ang = S.sin_theta_max(U[:, :cb], Vb)
+            Eg = Eh[t0:t0 + cb]
+            # coefficients depend on the basis signs and rotations inside
+            # clusters: compare U_c E (the reconstruction) and the
+            # basis-independent ||E|| per axis
+            rec = S.rel_error(Vb @ Eg, Xo)
+            dE = float(np.abs(np.linalg.norm(Eg, axis=0) - np.linalg.norm(Eo, axis=0)).max()
+                       / np.linalg.norm(Eo, axis=0).max())
+            out.append((prec, ang, rec, dE))
+        print(f"block {b} (n {n[b]}, gap {lam[cb] - lam[cb - 1]:.1e}): " +
+              "; ".join(f"prec {p}: sin {a:.2e} recon {r:.2e} dE {d:.2e}" for p, a, r, d in out))
+        (_, a32, r32, _), (_, a16, r16, d16) = out
+        assert a32 <= bar32 and r32 < RECON_FP32, (b, a32, r32)
+        assert a16 < 5e-2 and r16 < 2e-2 and d16 < 2e-2, (b, a16, r16, d16)
 
 
 # ------------------------------------------------------------------ whole-mesh quality report

@@ -118,6 +118,25 @@ def nmsve_curve(U: np.ndarray, X: np.ndarray, G: np.ndarray, c_max: int) -> np.n
     return out
 
 
+def nmsve_curve_sparse(U: np.ndarray, X: np.ndarray, edges: np.ndarray, coords0: np.ndarray,
+                       c_max: int) -> np.ndarray:
+    """NMSVE(c) for c = 1..c_max by explicit reconstructions, with the GL
+    operator applied edge by edge (gl_apply) instead of as a dense matrix,
+    for blocks too large for gl_matrix: GL is linear (original distances),
+    so GL(U_c E_c) = GL(U_c) E_c and GL(U) is formed once."""
+    n = X.shape[0]
+    X = np.asarray(X, dtype=np.float64)
+    GX = gl_apply(n, edges, coords0, X)
+    GU = gl_apply(n, edges, coords0, U[:, :c_max])
+    out = np.empty(c_max)
+    for c in range(1, c_max + 1):
+        E = U[:, :c].T @ X
+        a = np.linalg.norm(X - U[:, :c] @ E)
+        b = np.linalg.norm(GX - GU[:, :c] @ E)
+        out[c - 1] = (a + b) / (2.0 * n)
+    return out
+
+
 def l2_residual_curve(U: np.ndarray, X: np.ndarray, c_max: int) -> np.ndarray:
     """||X - U_c U_c^T X||_F for c = 1..c_max, brute force."""
     return np.array([np.linalg.norm(X - U[:, :c] @ (U[:, :c].T @ X)) for c in range(1, c_max + 1)])

@@ -371,6 +371,26 @@ class TestHandWorkedWeights:
         assert math.isclose(met.nmsve(self.PATH_X, Xr, G), want, rel_tol=1e-14)
         assert math.isclose(met.nmsve_mesh(3, self.PATH_E, self.PATH_X, Xr), want, rel_tol=1e-14)
 
+    def test_sparse_nmsve_curve(self):
+        # the edge-by-edge GL of the large-block curve against the dense GL
+        # matrix (both pinned above by hand) on a grid with noisy heights,
+        # a random orthonormal basis; zero at the full basis
+        bs = W.grid_single(nx=7, ny=6, c=5, p=8)
+        X = bs.coords[0]
+        n = X.shape[0]
+        e = lap.canonical_edges(bs.faces[0], n)
+        Q, _ = np.linalg.qr(np.random.default_rng(3).normal(size=(n, n)))
+        G = met.gl_matrix(n, e, X)
+        dense = np.array([met.nmsve(X, Q[:, :c] @ (Q[:, :c].T @ X), G) for c in range(1, n + 1)])
+        sparse = met.nmsve_curve_sparse(Q, X, e, X, n)
+        assert np.abs(sparse - dense).max() <= 1e-13 * dense.max()
+        assert sparse[-1] < 1e-14
+        # c = 1 with the constant vector: every coordinate replaced by its mean
+        U1 = np.full((n, 1), 1.0 / math.sqrt(n))
+        Xm = np.broadcast_to(X.mean(0), X.shape)
+        assert math.isclose(met.nmsve_curve_sparse(U1, X, e, X, 1)[0], met.nmsve(X, Xm, G),
+                            rel_tol=1e-12)
+
     def test_eq6_residual_by_hand(self):
         # U = the constant unit vector (c = 1): v_j - U U^T v_j removes each
         # coordinate's mean; Eq. 6 sums the three residual vectors

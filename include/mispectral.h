@@ -238,7 +238,7 @@ mi_status mi_ctx_set_timing(mi_ctx* ctx, int32_t on);
 /* Launch-shape override, for measurement and for checking the variants
  * against each other: tracking plans made after the call (the plan is
  * rebuilt when the variant differs) run the wavefront-per-row SpMM as
- * `variant` (the codes of mi_oi_tuning, 0..6) in every wave that uses it,
+ * `variant` (the codes of mi_oi_tuning, 0..10) in every wave that uses it,
  * whatever the autotuner would pick; -1 restores the autotuner or the
  * default.  MI_ERR_ARG for other values.  Host only. */
 mi_status mi_oi_force_spmm(mi_ctx* ctx, int32_t variant);
@@ -339,9 +339,14 @@ mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_pa
  * 2 two rows per wavefront, 3 one row per wavefront in 4-wavefront
  * workgroups, 4 and 5 two and four rows per wavefront one after the other
  * with their indices loaded first, 6 the same with two rows in
- * 4-wavefront workgroups, -1 the default for the width) for up to `cap`
- * waves; *n_waves
- * gets the plan's wave count.  Host only. */
+ * 4-wavefront workgroups; 7 to 10 one row per wavefront gathering only the
+ * off-diagonal entries with the diagonal folded into the row's own term,
+ * over consecutive rows in workgroups of 8 (7, 9), 16 (8) or 4 (10)
+ * wavefronts, the previous iterate and the output streamed non-temporally
+ * except in 9; -1 the default, 7) for up to `cap` waves;
+ * *n_waves gets the plan's wave count.  Variants 0 to 6 give bit-identical
+ * results, and so do 7 to 10 among themselves (the folded diagonal rounds
+ * differently).  Host only. */
 mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves);
 
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
@@ -428,18 +433,25 @@ mi_status mi_ritz_residuals(mi_ctx* ctx, const mi_blocks* blk, int32_t precision
 /* ---------------------------------------------------------------- adjoint of encode / decode
  * Gradient of loss = <Gbar, X~> for X~_b = U_c U_c^T X_b (Section 3 GFT and
  * inverse GFT, Section 7.1 truncation to c_b), where U_c holds the first c_b
- * Ritz vectors that mi_oi_track computes from V0 with `prm` (Section 4,
- * Alg. 1: T0 iterations of passes0 Chebyshev passes of degree m0, Cholesky-QR
+ * Ritz vectors that mi_oi_track computes with `prm` (Section 4, Alg. 1:
+ * T0 iterations of passes0 Chebyshev passes of degree m0 for the blocks
+ * started from V0 or the seeded start, T of passes of degree m for blocks
+ * warm-started from their predecessor under MI_WARM_PRED; Cholesky-QR
  * between passes, Rayleigh-Ritz at the end).  The paper does not
  * differentiate its method; the derivative is that of the unrolled
  * iteration, with respect to the coordinates X and to the edge weights w of
- * L = sum_e w_e (e_a - e_b)(e_a - e_b)^T (Eq. 1-2).  The filter interval
- * [a, b] and the start V0 are constants.
+ * L = sum_e w_e (e_a - e_b)(e_a - e_b)^T (Eq. 1-2).  The gradient is stopped
+ * at every block's start basis (V0, the seeded start, or the predecessor's
+ * result) and at the filter interval of every iteration (the Gershgorin or
+ * given b, the initial a of a_mode, and with adapt = 1 the Rayleigh-quotient
+ * updates of a): these are recorded in the forward and held constant.
  * The call replays the tracking with checkpoints (every pass input, the
- * Cholesky-QR factors and the Rayleigh-Ritz rotation) in its workspace, then
- * runs the reverse sweep; all blocks are batched in every launch.
- * Requires warm = MI_WARM_GIVEN, adapt = 0, rr_every = 0, eig = MI_EIG_TRIDIAG,
- * T0 >= 1 and every ld_b <= 192 (else MI_ERR_ARG).
+ * Cholesky-QR factors, the coefficients of every iteration and the
+ * Rayleigh-Ritz rotation) in its workspace, then runs the reverse sweep
+ * wave by wave, every wave's blocks batched in each launch.
+ * Requires tol = 0, op = MI_OP_CHEB, rr_every = 0, eig = MI_EIG_TRIDIAG,
+ * precision MI_FP32 or MI_FP64, T0 >= 1 (and T >= 1 when blocks are
+ * warm-started) and every ld_b <= 192 (else MI_ERR_ARG).
  * mode      weight mode the CSR values were built with: for MI_W_INV_SQ_DIST
  *           and MI_W_INV_DIST the weights depend on X and Xbar includes that
  *           path; MI_W_COMBINATORIAL / MI_W_USER weights are independent of X.
@@ -454,7 +466,8 @@ mi_status mi_ritz_residuals(mi_ctx* ctx, const mi_blocks* blk, int32_t precision
  *           distance weights: the gradient at the weights before the chain
  *           rule into X, which Xbar already includes).
  * Workspace from mi_adjoint_workspace_size (holds about
- * (T0*passes0 + m0 + 10) slabs).  Enqueue only; eager launches. */
+ * (max(T0*passes0, T*passes) + max(m0, m) + 10) slabs).  Enqueue only;
+ * eager launches. */
 mi_status mi_adjoint_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
                                     const int64_t* nnz_off, size_t* ws_bytes);
 mi_status mi_encdec_adjoint(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,

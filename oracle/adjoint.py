@@ -17,7 +17,9 @@ the one the tracking computes for one block:
 
 with w = 1 (combinatorial), w = 1/|x_a - x_b|^2 (distance weights, then the
 weights depend on X) or user weights.  The filter interval [a, b] is a
-constant: no gradient flows into it.  Torch autograd on the CPU in float64
+constant: no gradient flows into it.  tracked_grad runs the same map with the
+tracking's interval schedule (Gershgorin b, adaptive a) and warm starts, the
+interval and the start again held constant.  Torch autograd on the CPU in float64
 differentiates the plain forward (QR is Householder, eigh is LAPACK).
 
 eigenprojector_grad is the converged limit of the same gradient (first-order
@@ -103,6 +105,86 @@ def unrolled_grad(n: int, edges: np.ndarray, X: np.ndarray, mode: int, V0: np.nd
         (gX2,) = torch.autograd.grad((weights(e, Xc, mode) * gw).sum(), (Xc,))
         gX += gX2
     return gX.numpy(), gw.numpy()
+
+
+def gershgorin(L: torch.Tensor) -> float:
+    """max_i sum_j |L_ij|: an upper bound of the spectrum (Gershgorin's
+    circle theorem)."""
+    return float(L.detach().abs().sum(dim=1).max())
+
+
+def warm_start(V_pred: np.ndarray, n: int, p: int) -> np.ndarray:
+    """The tracking's index-aligned warm start of an n-vertex block of width p
+    from its predecessor's basis: shared rows and columns copied, missing rows
+    zero, columns j past the predecessor's width the unit vector
+    e_{(997 j) mod n}."""
+    npd, ppd = V_pred.shape
+    S0 = np.zeros((n, p))
+    k, q = min(n, npd), min(p, ppd)
+    S0[:k, :q] = V_pred[:k, :q]
+    for j in range(ppd, p):
+        S0[(997 * j) % n, j] = 1.0
+    return S0
+
+
+def tracked_grad(n: int, edges: np.ndarray, X: np.ndarray, mode: int, start: np.ndarray, c: int,
+                 Gbar: np.ndarray, *, T: int, m: int, passes: int, a0, b=None, adapt=False,
+                 orth_start=False, user_w=None, schedule=None):
+    """Gradient of loss = <Gbar, X~> through one block's tracking as the
+    library schedules it, with its filter interval held constant:
+      b    the given bound, or gershgorin(L) when None;
+      a_0  a0, or a0(b) when callable (the initial lower bound of a_mode);
+      per iteration t the filter runs on [clip(a_t, 1e-3 b, 0.95 b), b];
+      with adapt, a_{t+1} = max_j q_j^T L q_j over the orthonormalised basis
+      after iteration t (not after the last);
+      T iterations of `passes` Chebyshev passes of degree m, the basis
+      orthonormalised after every pass, Rayleigh-Ritz at the end
+    (Section 4, Alg. 1).  The start (orthonormalised first when orth_start)
+    is a constant, and so are b and every a_t: the gradient is stopped at
+    them.  `schedule` = (b, [a_0 .. a_{T-1}]) replaces the rule (for finite
+    differences at a frozen interval).
+    Returns (d loss/dX, d loss/dw, info) with info = {"b", "a" (the a_t used,
+    before clipping), "theta" (Ritz values, ascending), "U" (n x p Ritz
+    vectors)}."""
+    e = torch.from_numpy(np.asarray(edges, np.int64))
+    Xt = torch.tensor(np.asarray(X, np.float64), requires_grad=True)
+    if mode == USER:
+        w0 = torch.tensor(np.asarray(user_w, np.float64), requires_grad=True)
+    else:
+        w0 = weights(e, Xt, mode).detach().requires_grad_(True)
+    L = laplacian(n, e, w0)
+    Ld = L.detach()
+    if schedule is not None:
+        bb, a_list = float(schedule[0]), [float(a) for a in schedule[1]]
+    else:
+        bb = float(b) if b is not None else gershgorin(Ld)
+        a_list = [float(a0(bb)) if callable(a0) else float(a0)]
+    Q = torch.from_numpy(np.asarray(start, np.float64))
+    if orth_start:
+        Q, _ = torch.linalg.qr(Q)
+    for t in range(T):
+        a = a_list[t]
+        ac = min(max(a, 1e-3 * bb), 0.95 * bb)
+        for _ in range(passes):
+            Q, _ = torch.linalg.qr(chebyshev(L, Q, ac, bb, m))
+        if schedule is None and t < T - 1:
+            Qd = Q.detach()
+            a_list.append(float(torch.diagonal(Qd.T @ Ld @ Qd).max()) if adapt else a)
+    H = Q.T @ L @ Q
+    H = 0.5 * (H + H.T)
+    theta, S = torch.linalg.eigh(H)
+    U = Q @ S[:, :c]
+    Xr = U @ (U.T @ Xt)
+    loss = (torch.from_numpy(np.asarray(Gbar, np.float64)) * Xr).sum()
+    gX, gw = torch.autograd.grad(loss, (Xt, w0))
+    gX = gX.clone()
+    if mode in (INV_SQ_DIST, INV_DIST):
+        Xc = Xt.detach().clone().requires_grad_(True)
+        (gX2,) = torch.autograd.grad((weights(e, Xc, mode) * gw).sum(), (Xc,))
+        gX += gX2
+    info = {"b": bb, "a": a_list, "theta": theta.detach().numpy(),
+            "U": (Q @ S).detach().numpy(), "loss": float(loss.detach())}
+    return gX.numpy(), gw.numpy(), info
 
 
 def eigenprojector_grad(L: np.ndarray, edges: np.ndarray, X: np.ndarray, Gbar: np.ndarray, c: int):

@@ -16,8 +16,10 @@
 //   filter pass    Y = p(L) X by the three-term recurrence; its reverse
 //                  recurrence gives Xbar = p(L) Ybar and, per step,
 //                  wbar_e += alpha_k d_e(ybar_{k+1}) . d_e(y_k)
-// and stops at the given start basis (a constant).  The filter interval is a
-// constant, so no gradient flows into it.  Distance weights chain into X.
+// and stops at each block's start basis (the given or seeded start, or the
+// predecessor's result: a constant).  The filter interval of every iteration
+// (recorded in the forward, adaptive or not) is a constant too, so no
+// gradient flows into it.  Distance weights chain into X.
 #include <cstring>
 
 #include "eig.hpp"
@@ -40,10 +42,24 @@ struct AdjPlan {
   AdjBlock* dev = nullptr;
   int max_ne = 0;
   int64_t part_doubles = 0;
+  // block ids of the tracking plan's waves, wave after wave (woff[w] .. woff[w + 1])
+  std::vector<int32_t> ids, woff;
+  int32_t* ids_dev = nullptr;
   ~AdjPlan() {
     if (dev) (void)hipFree(dev);
+    if (ids_dev) (void)hipFree(ids_dev);
   }
 };
+
+// Passes and iterations of the longest wave: the roots run T0 iterations of
+// passes0 passes; blocks warm-started from a predecessor run T of passes.
+void adj_counts(const HostBlocks& hb, const mi_oi_params& prm, int* npass, int* n_iter) {
+  bool warm = false;
+  if (prm.warm == MI_WARM_PRED)
+    for (int b = 0; b < hb.B; ++b) warm = warm || hb.pred[b] >= 0;
+  *npass = std::max(prm.T0 * prm.passes0, warm ? prm.T * prm.passes : 0);
+  *n_iter = std::max(prm.T0, warm ? prm.T : 0);
+}
 
 // Workspace of one adjoint call (element type T of the slabs).
 struct AdjWs {
@@ -56,7 +72,8 @@ AdjWs adj_layout(const HostBlocks& hb, const mi_oi_params& prm, int64_t nnz, int
   const size_t es = prm.precision == MI_FP64 ? 8 : 4;
   const int B = hb.B;
   const int64_t slab = hb.u_off[B], mats = hb.m_off[B], tp = hb.t_off[B];
-  const int npass = prm.T0 * prm.passes0;
+  int npass = 0, n_iter = 0;
+  adj_counts(hb, prm, &npass, &n_iter);
   Carver c(nullptr);
   AdjWs L;
   auto take = [&](size_t bytes) {
@@ -73,13 +90,13 @@ AdjWs adj_layout(const HostBlocks& hb, const mi_oi_params& prm, int64_t nnz, int
   L.recY = take(slab * es);
   L.Rrr = take(mats * 8);
   L.Z = take(mats * 8);
-  L.coef = take(size_t(B) * 3 * (std::max(prm.m, prm.m0) + 1) * 8);
+  L.coef = take(size_t(n_iter) * B * 3 * (std::max(prm.m, prm.m0) + 1) * 8);
   L.Q = take(slab * es);
   L.W = take(slab * es);
   L.Qb = take(slab * es);
   L.Tm = take(slab * es);
   L.yb = take(3 * slab * es);
-  L.ys = take(size_t(std::max(prm.m0 - 1, 1)) * slab * es);
+  L.ys = take(size_t(std::max(std::max(prm.m0, prm.m) - 1, 1)) * slab * es);
   L.acc = take(std::max<int64_t>(nnz, 1) * 8);
   L.part = take(std::max<int64_t>(part, 1) * 8);
   L.EF = take(6 * tp * 8);
@@ -210,10 +227,11 @@ __global__ void __launch_bounds__(256)
 // second kernel adds the partials in chunk order.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_adj_tall6(const AdjBlock* __restrict__ blks, const T* __restrict__ Q,
-                const T* __restrict__ X, const T* __restrict__ G, double* __restrict__ part) {
+    k_adj_tall6(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ ids,
+                const T* __restrict__ Q, const T* __restrict__ X, const T* __restrict__ G,
+                double* __restrict__ part) {
   constexpr int KPT = 4;  // ld <= 1024
-  const AdjBlock b = blks[blockIdx.x];
+  const AdjBlock b = blks[ids[blockIdx.x]];
   const int chunk = blockIdx.y;
   const int rows_per = (b.n + ADJ_CHUNKS - 1) / ADJ_CHUNKS;
   const int r0 = chunk * rows_per, r1 = min(b.n, r0 + rows_per);
@@ -253,9 +271,9 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void __launch_bounds__(256)
-    k_adj_sum6(const AdjBlock* __restrict__ blks, const double* __restrict__ part,
-               double* __restrict__ EF) {
-  const AdjBlock b = blks[blockIdx.x];
+    k_adj_sum6(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ ids,
+               const double* __restrict__ part, double* __restrict__ EF) {
+  const AdjBlock b = blks[ids[blockIdx.x]];
   for (int e = threadIdx.x; e < 6 * b.p; e += 256) {
     double v = 0.0;
     for (int ch = 0; ch < ADJ_CHUNKS; ++ch) v += part[b.part_off + int64_t(ch) * b.ld * 6 + e];
@@ -266,9 +284,10 @@ __global__ void __launch_bounds__(256)
 // ------------------------------------------------------------------ Rayleigh-Ritz adjoint
 // ZEF[j][:] = sum_k Z[k][j] EF[k][:]  (Z^T Q^T X | Z^T Q^T Gbar), j < p.
 __global__ void __launch_bounds__(256)
-    k_rr_zef(const AdjBlock* __restrict__ blks, const double* __restrict__ Z,
-             const double* __restrict__ EF, double* __restrict__ ZEF) {
-  const AdjBlock b = blks[blockIdx.x];
+    k_rr_zef(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ ids,
+             const double* __restrict__ Z, const double* __restrict__ EF,
+             double* __restrict__ ZEF) {
+  const AdjBlock b = blks[ids[blockIdx.x]];
   const double* Zb = Z + b.m_off;
   const double* ef = EF + 6 * b.t_off;
   for (int e = threadIdx.x; e < 6 * b.p; e += 256) {
@@ -284,11 +303,13 @@ __global__ void __launch_bounds__(256)
 // T1[k][i] = sum_{c<=j<p} Z[k][j] K_ji, K_ji = z_j^T Q^T Ubar_i / (theta_i - theta_j)
 //          = (ZF_j . ZE_i + ZE_j . ZF_i) / (theta_i - theta_j)   for i < c.
 __global__ void __launch_bounds__(256)
-    k_rr_pk(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ cvec,
-            const double* __restrict__ Z, const double* __restrict__ theta,
-            const double* __restrict__ ZEF, double* __restrict__ PP, double* __restrict__ T1) {
-  const AdjBlock b = blks[blockIdx.x];
-  const int c = min(max(cvec[blockIdx.x], 1), b.p);
+    k_rr_pk(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ ids,
+            const int32_t* __restrict__ cvec, const double* __restrict__ Z,
+            const double* __restrict__ theta, const double* __restrict__ ZEF,
+            double* __restrict__ PP, double* __restrict__ T1) {
+  const int bi = ids[blockIdx.x];
+  const AdjBlock b = blks[bi];
+  const int c = min(max(cvec[bi], 1), b.p);
   const double* Zb = Z + b.m_off;
   const double* ze = ZEF + 6 * b.t_off;
   const double* th = theta + b.t_off;
@@ -316,11 +337,12 @@ __global__ void __launch_bounds__(256)
 // in FP64 and in the slab element type.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_rr_abar(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ cvec,
-              const double* __restrict__ Z, const double* __restrict__ T1,
-              double* __restrict__ S2d, T* __restrict__ S2) {
-  const AdjBlock b = blks[blockIdx.x];
-  const int c = min(max(cvec[blockIdx.x], 1), b.p);
+    k_rr_abar(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ ids,
+              const int32_t* __restrict__ cvec, const double* __restrict__ Z,
+              const double* __restrict__ T1, double* __restrict__ S2d, T* __restrict__ S2) {
+  const int bi = ids[blockIdx.x];
+  const AdjBlock b = blks[bi];
+  const int c = min(max(cvec[bi], 1), b.p);
   const int e = blockIdx.y * 256 + threadIdx.x;
   if (e >= b.ld * b.ld) return;
   const int k = e / b.ld, l = e % b.ld;
@@ -364,9 +386,10 @@ __global__ void __launch_bounds__(256)
 // RT = R^T and MRT = M R^T (ld x ld per block); M FP64, R in the slab type.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_adj_prep(const AdjBlock* __restrict__ blks, const double* __restrict__ M,
-               const T* __restrict__ R, T* __restrict__ RT, T* __restrict__ MRT) {
-  const AdjBlock b = blks[blockIdx.x];
+    k_adj_prep(const AdjBlock* __restrict__ blks, const int32_t* __restrict__ ids,
+               const double* __restrict__ M, const T* __restrict__ R, T* __restrict__ RT,
+               T* __restrict__ MRT) {
+  const AdjBlock b = blks[ids[blockIdx.x]];
   const int e = blockIdx.y * 256 + threadIdx.x;
   if (e >= b.ld * b.ld) return;
   const int k = e / b.ld, l = e % b.ld;
@@ -378,11 +401,18 @@ __global__ void __launch_bounds__(256)
   MRT[b.m_off + e] = (T)s;
 }
 
+// out = a - b over the rows of a wave's tiles.
 template <typename T>
-__global__ void k_adj_sub(int64_t n, const T* __restrict__ a, const T* __restrict__ b,
-                          T* __restrict__ out) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i < n) out[i] = a[i] - b[i];
+__global__ void __launch_bounds__(256)
+    k_adj_sub(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+              const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ out) {
+  const SpmmTile t = tiles[blockIdx.x];
+  const MatDesc d = sets[t.set];
+  const int rows = min(SPMM_ROWS, d.rows - t.row0);
+  for (int e = threadIdx.x; e < rows * d.ld; e += 256) {
+    const int64_t o = d.off + int64_t(t.row0) * d.ld + e;
+    out[o] = a[o] - b[o];
+  }
 }
 
 template <typename T>
@@ -477,11 +507,9 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
                     const OiRecord& rec, const int32_t* row_ptr, const int32_t* col,
                     const float* val, const int32_t* edges, const int32_t* c, const T* X,
                     const T* G, int mode, double* Xbar, double* wbar, hipStream_t s) {
-  const WaveTables& w = P.waves[0];
   const HostBlocks& hb = P.hb;
   const int B = hb.B;
   const int64_t slab = hb.u_off[B], mats = hb.m_off[B];
-  const int m = w.m, npass = rec.npass;
   const int stride = P.L.coef_stride;
   auto S = [&](size_t off) { return reinterpret_cast<T*>(ws + off); };
   auto D = [&](size_t off) { return reinterpret_cast<double*>(ws + off); };
@@ -502,13 +530,11 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
   double* Hm = D(L.Hm);
   T* RT = S(L.RT);
   T* MRT = S(L.MRT);
+  T* ys = S(L.ys);
   const double* ritz = D(L.ritz);
   double* gpart = D(L.oi + P.L.part);  // Gram partials (the tracking workspace's buffer)
-  const int gsm = ceil_div(int64_t(w.max_ld) * w.max_ld, 256);
-  const int gel = ceil_div(slab, 256);
   fill_f64(acc, 0.0, int64_t(P.nnz_off[B]), s);
-
-  // Q = Y R^-1 of the Rayleigh-Ritz step; W = L Q
+  // R^-1 of every block's Rayleigh-Ritz step in the slab type
   const T* Rc;
   if (std::is_same<T, double>::value) {
     Rc = reinterpret_cast<const T*>(rec.Rrr);
@@ -517,65 +543,84 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
                        S(L.Rc));
     Rc = S(L.Rc);
   }
-  launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, static_cast<const T*>(rec.Y), w.small, Rc, w.tall, Q,
-                      w.nch, s);
-  launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, Q, nullptr, Wl, rec.coef,
-                 stride, m, s, w.epl, w.spmm_var);
-  // projection and Rayleigh-Ritz adjoint
-  hipLaunchKernelGGL(k_adj_tall6<T>, dim3(B, ADJ_CHUNKS), dim3(256), 0, s, A.dev, Q, X, G, part);
-  hipLaunchKernelGGL(k_adj_sum6, dim3(B), dim3(256), 0, s, A.dev, part, EF);
-  hipLaunchKernelGGL(k_rr_zef, dim3(B), dim3(256), 0, s, A.dev, rec.Z, EF, ZEF);
-  hipLaunchKernelGGL(k_rr_pk, dim3(B, gsm), dim3(256), 0, s, A.dev, c, rec.Z, ritz, ZEF, PP, T1);
-  hipLaunchKernelGGL(k_rr_abar<T>, dim3(B, gsm), dim3(256), 0, s, A.dev, c, rec.Z, T1, S2d, S2);
-  launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Wl, w.small, S2, w.tall, Qb, w.nch, s);
-  hipLaunchKernelGGL(k_adj_lowrank<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, A.dev, PP,
-                     X, G, Qb);
-  // wbar_e += d_e(Q S2/2) . d_e(Q)
-  launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Q, w.small, S2, w.tall, Tm, w.nch, s);
-  hipLaunchKernelGGL(k_adj_spmm<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.csr,
-                     row_ptr, col, val, Tm, nullptr, Q, nullptr, acc, nullptr, 0, 0, 0.5);
+  // Every block's reverse sweep ends at its own start basis (the given
+  // start, or its predecessor's result, held constant), so the waves are
+  // reversed one after the other, each with its own pass count and degree.
+  for (size_t wi = 0; wi < P.waves.size(); ++wi) {
+    const WaveTables& w = P.waves[wi];
+    const int32_t* ids = A.ids_dev + A.woff[wi];
+    const int nbw = A.woff[wi + 1] - A.woff[wi];
+    if (nbw <= 0 || w.T <= 0) continue;
+    const int m = w.m, npass = w.T * w.passes;
+    auto coef_of = [&](int j) { return rec.coef + size_t(j / w.passes) * B * stride; };
+    const int gsm = ceil_div(int64_t(w.max_ld) * w.max_ld, 256);
 
-  // Ybar = (I - B B^T) Bbar R^-T for the basis B = Y R^-1 (span-only loss)
-  auto cholqr_adj = [&](const T* Bm, const T* Bbar, const T* R, T* out) {
-    launch_gram<T>(w.gt, w.n_gt, w.tall, Bm, Bm, Bbar, gpart, s);
-    launch_gram_reduce(w.gr, w.n_gr, w.small, gpart, true, M, Hm, s);
-    hipLaunchKernelGGL(k_adj_prep<T>, dim3(B, gsm), dim3(256), 0, s, A.dev, Hm, R, RT, MRT);
-    launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Bm, w.small, MRT, w.tall, Tm, w.nch, s);
-    launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Bbar, w.small, RT, w.tall, out, w.nch, s);
-    hipLaunchKernelGGL(k_adj_sub<T>, dim3(gel), dim3(256), 0, s, slab, out, Tm, out);
-  };
-  cholqr_adj(Q, Qb, Rc, yb[0]);
-  int cur = 0;  // yb slab holding the gradient of the current pass output
-  T* ys = S(L.ys);
-  for (int j = npass - 1; j >= 0; --j) {
-    // forward intermediates y_0 .. y_{m-1} of pass j from its checkpointed input
-    const T* xin = static_cast<const T*>(rec.X[j]);
-    auto y_at = [&](int k) -> const T* { return k == 0 ? xin : ys + int64_t(k - 1) * slab; };
-    for (int k = 0; k + 1 < m; ++k)
-      launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y_at(k),
-                     k > 0 ? y_at(k - 1) : nullptr, ys + int64_t(k) * slab, rec.coef, stride, k, s,
-                     w.epl, w.spmm_var);
-    // reverse recurrence
-    int nxt = cur, prv = -1;
-    for (int k = m - 1; k >= 0; --k) {
-      int o = 0;
-      while (o == nxt || o == prv) ++o;
-      hipLaunchKernelGGL(k_adj_spmm<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.csr,
-                         row_ptr, col, val, yb[nxt], prv >= 0 ? yb[prv] : nullptr, y_at(k), yb[o],
-                         acc, rec.coef, stride, k, 0.0);
-      prv = nxt;
-      nxt = o;
+    // Q = Y R^-1 of the Rayleigh-Ritz step; W = L Q (slot m: the plain product)
+    launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, static_cast<const T*>(rec.Y), w.small, Rc, w.tall,
+                        Q, w.nch, s);
+    launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, Q, nullptr, Wl,
+                   coef_of(npass - 1), stride, m, s, w.epl, w.spmm_var);
+    // projection and Rayleigh-Ritz adjoint
+    hipLaunchKernelGGL(k_adj_tall6<T>, dim3(nbw, ADJ_CHUNKS), dim3(256), 0, s, A.dev, ids, Q, X,
+                       G, part);
+    hipLaunchKernelGGL(k_adj_sum6, dim3(nbw), dim3(256), 0, s, A.dev, ids, part, EF);
+    hipLaunchKernelGGL(k_rr_zef, dim3(nbw), dim3(256), 0, s, A.dev, ids, rec.Z, EF, ZEF);
+    hipLaunchKernelGGL(k_rr_pk, dim3(nbw, gsm), dim3(256), 0, s, A.dev, ids, c, rec.Z, ritz, ZEF,
+                       PP, T1);
+    hipLaunchKernelGGL(k_rr_abar<T>, dim3(nbw, gsm), dim3(256), 0, s, A.dev, ids, c, rec.Z, T1,
+                       S2d, S2);
+    launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Wl, w.small, S2, w.tall, Qb, w.nch, s);
+    hipLaunchKernelGGL(k_adj_lowrank<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, A.dev,
+                       PP, X, G, Qb);
+    // wbar_e += d_e(Q S2/2) . d_e(Q)
+    launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Q, w.small, S2, w.tall, Tm, w.nch, s);
+    hipLaunchKernelGGL(k_adj_spmm<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.csr,
+                       row_ptr, col, val, Tm, nullptr, Q, nullptr, acc, nullptr, 0, 0, 0.5);
+
+    // Ybar = (I - B B^T) Bbar R^-T for the basis B = Y R^-1 (span-only loss)
+    auto cholqr_adj = [&](const T* Bm, const T* Bbar, const T* R, T* out) {
+      launch_gram<T>(w.gt, w.n_gt, w.tall, Bm, Bm, Bbar, gpart, s);
+      launch_gram_reduce(w.gr, w.n_gr, w.small, gpart, true, M, Hm, s);
+      hipLaunchKernelGGL(k_adj_prep<T>, dim3(nbw, gsm), dim3(256), 0, s, A.dev, ids, Hm, R, RT,
+                         MRT);
+      launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Bm, w.small, MRT, w.tall, Tm, w.nch, s);
+      launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Bbar, w.small, RT, w.tall, out, w.nch, s);
+      hipLaunchKernelGGL(k_adj_sub<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, out, Tm,
+                         out);
+    };
+    cholqr_adj(Q, Qb, Rc, yb[0]);
+    int cur = 0;  // yb slab holding the gradient of the current pass output
+    for (int j = npass - 1; j >= 0; --j) {
+      const double* cf = coef_of(j);
+      // forward intermediates y_0 .. y_{m-1} of pass j from its checkpointed input
+      const T* xin = static_cast<const T*>(rec.X[j]);
+      auto y_at = [&](int k) -> const T* { return k == 0 ? xin : ys + int64_t(k - 1) * slab; };
+      for (int k = 0; k + 1 < m; ++k)
+        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, y_at(k),
+                       k > 0 ? y_at(k - 1) : nullptr, ys + int64_t(k) * slab, cf, stride, k, s,
+                       w.epl, w.spmm_var);
+      // reverse recurrence
+      int nxt = cur, prv = -1;
+      for (int k = m - 1; k >= 0; --k) {
+        int o = 0;
+        while (o == nxt || o == prv) ++o;
+        hipLaunchKernelGGL(k_adj_spmm<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.csr,
+                           row_ptr, col, val, yb[nxt], prv >= 0 ? yb[prv] : nullptr, y_at(k),
+                           yb[o], acc, cf, stride, k, 0.0);
+        prv = nxt;
+        nxt = o;
+      }
+      cur = nxt;  // gradient of the pass input
+      if (j > 0) {
+        int o = 0;
+        while (o == cur) ++o;
+        cholqr_adj(xin, yb[cur], static_cast<const T*>(rec.S[j - 1]), yb[o]);
+        cur = o;
+      }
     }
-    cur = nxt;  // gradient of the pass input
-    if (j > 0) {
-      int o = 0;
-      while (o == cur) ++o;
-      cholqr_adj(xin, yb[cur], static_cast<const T*>(rec.S[j - 1]), yb[o]);
-      cur = o;
-    }
+    hipLaunchKernelGGL(k_adj_xbar<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.csr,
+                       A.dev, row_ptr, col, acc, Q, PP, X, mode, Xbar);
   }
-  hipLaunchKernelGGL(k_adj_xbar<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, w.csr, A.dev,
-                     row_ptr, col, acc, Q, PP, X, mode, Xbar);
   if (A.max_ne > 0)
     hipLaunchKernelGGL(k_adj_edges, dim3(B, ceil_div(A.max_ne, 256)), dim3(256), 0, s, A.dev,
                        row_ptr, col, edges, acc, wbar);
@@ -585,18 +630,15 @@ static mi_status adj_check(const mi_oi_params* prm, const HostBlocks& hb) {
   mi_status st = oi_check_params(prm);
   if (st) return st;
   MI_CHECK_ARG(prm->precision != MI_BF16_IN, "the adjoint supports MI_FP32 and MI_FP64");
-  MI_CHECK_ARG(prm->warm == MI_WARM_GIVEN, "the adjoint needs warm = MI_WARM_GIVEN");
   MI_CHECK_ARG(prm->tol == 0, "the adjoint differentiates fixed iteration counts (tol = 0)");
   MI_CHECK_ARG(prm->op == MI_OP_CHEB, "the adjoint differentiates the Chebyshev filter only");
-  MI_CHECK_ARG(prm->adapt == 0 && prm->rr_every == 0,
-               "the adjoint needs a fixed filter interval (adapt = 0, rr_every = 0)");
-  // the reverse sweep holds the interval [a, b] constant, so it must not be
-  // a function of the inputs: a Gershgorin b depends on the weights, and a
-  // Weyl-law a on b
-  MI_CHECK_ARG(prm->b_abs > 0 && prm->a_mode == MI_A_ABS,
-               "the adjoint needs a given filter interval (b_abs > 0, a_mode = MI_A_ABS)");
+  MI_CHECK_ARG(prm->rr_every == 0, "the adjoint needs rr_every = 0");
   MI_CHECK_ARG(prm->eig == MI_EIG_TRIDIAG, "the adjoint needs eig = MI_EIG_TRIDIAG");
   MI_CHECK_ARG(prm->T0 >= 1, "the adjoint needs T0 >= 1");
+  bool warm = false;
+  if (prm->warm == MI_WARM_PRED)
+    for (int b = 0; b < hb.B; ++b) warm = warm || hb.pred[b] >= 0;
+  MI_CHECK_ARG(!warm || prm->T >= 1, "the adjoint needs T >= 1 for warm-started blocks");
   int max_ld = 0;
   for (int b = 0; b < hb.B; ++b) max_ld = std::max(max_ld, hb.ld[b]);
   // the widths the reverse sweep is tested at
@@ -690,7 +732,8 @@ mi_status mi_encdec_adjoint(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_param
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
   const size_t es = prm->precision == MI_FP64 ? 8 : 4;
-  const int npass = prm->T0 * prm->passes0;
+  int npass = 0, n_iter = 0;
+  adj_counts(hb, *prm, &npass, &n_iter);
   std::vector<void*> xs(npass), ss(std::max(npass - 1, 1));
   for (int j = 0; j < npass; ++j) xs[j] = w + L.recX + size_t(j) * hb.u_off[hb.B] * es;
   for (int j = 0; j + 1 < npass; ++j) ss[j] = w + L.recS + size_t(j) * hb.m_off[hb.B] * es;
@@ -702,11 +745,30 @@ mi_status mi_encdec_adjoint(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_param
   rec.Z = reinterpret_cast<double*>(w + L.Z);
   rec.coef = reinterpret_cast<double*>(w + L.coef);
   rec.npass = npass;
+  rec.n_iter = n_iter;
   OiPlan* P = nullptr;
   st = oi_run_plan(ctx, &ctx->adj_oi, hb, nnz, *prm, row_ptr, col, val, V0, w + L.V,
                    reinterpret_cast<double*>(w + L.ritz), reinterpret_cast<int32_t*>(w + L.status),
                    w + L.oi, oi_ws_bytes(hb, *prm), &rec, s, &P);
   if (st) return st;
+  // the plan's waves, as block id lists (wave after wave)
+  std::vector<int32_t> ids, woff{0};
+  for (const WaveTables& wt : P->waves) {
+    for (const MatDesc& d : wt.tall_host) ids.push_back(d.blk);
+    woff.push_back((int32_t)ids.size());
+  }
+  if (ids != A->ids || woff != A->woff) {
+    if (!A->ids_dev && hipMalloc(&A->ids_dev, std::max(hb.B, 1) * sizeof(int32_t)) != hipSuccess) {
+      A->ids_dev = nullptr;
+      set_error("device allocation for the adjoint tables failed");
+      return MI_ERR_HIP;
+    }
+    MI_CHECK_ARG((int)ids.size() == hb.B, "every block must belong to one wave");
+    MI_TRY_HIP(hipMemcpy(A->ids_dev, ids.data(), ids.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    A->ids = ids;
+    A->woff = woff;
+  }
   if (prm->precision == MI_FP64)
     reverse<double>(*P, *A, L, w, rec, row_ptr, col, val, edges, c, static_cast<const double*>(X),
                     static_cast<const double*>(Gbar), mode, Xbar, wbar, s);

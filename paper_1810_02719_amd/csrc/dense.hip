@@ -284,6 +284,122 @@ __global__ void __launch_bounds__(64 * WPG)
   }
 }
 
+// Non-temporal element load and store (the previous iterate is read once and
+// the output is not read again by the launch, so neither should displace the
+// gathered neighbour rows from the caches).
+template <typename T>
+__device__ inline T ld_nt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <>
+__device__ inline bf16 ld_nt<bf16>(const bf16* p) {
+  return bf16{__builtin_nontemporal_load(&p->u)};
+}
+template <typename T>
+__device__ inline void st_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+template <>
+__device__ inline void st_nt<bf16>(bf16* p, bf16 v) {
+  __builtin_nontemporal_store(v.u, &p->u);
+}
+
+// One row per wavefront gathering exactly the row's off-diagonal entries
+// (wave-uniform branches, no padded loads), with the diagonal entry folded
+// into the row's own term:
+//   W_r = alpha sum_{j != r} L_rj Y_j + (alpha L_rr Y_r + beta Y_r) + gamma Yprev_r.
+// The WPG rows of a workgroup are consecutive, so the neighbour rows they
+// share are fetched once into the CU's L1 for all of them; with NT the
+// previous iterate and the output stream past the caches.  The gather
+// volume per row drops from ceil(nnz/8)*8 rows to nnz - 1 (the seven-entry
+// rows of a triangle mesh: 8 to 6), which is what bounds this kernel once
+// the HBM bytes are right.
+template <typename T, int EPL, bool STRIDED, int WPG, bool NT>
+__global__ void __launch_bounds__(64 * WPG)
+    k_spmm_rowx(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val,
+                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  static_assert(SPMM_ROWS % WPG == 0, "workgroup split");
+  typedef Acc<T> AC;
+  typedef typename AC::type A;
+  constexpr int G = SPMM_GATHER;
+  constexpr int SPLIT = SPMM_ROWS / WPG;
+  constexpr int ES = STRIDED ? 64 : 1;
+  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int kx = blockIdx.x / NUM_XCD;
+  const int ti = (blockIdx.x % NUM_XCD) * per + kx / SPLIT;
+  if (ti >= ntiles) return;
+  const SpmmTile t = tiles[ti];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MatDesc d = sets[t.set];
+  const int r = t.row0 + (kx % SPLIT) * WPG + wave;
+  if (r >= d.rows) return;  // wave-uniform
+  const CsrDesc c = csr[t.set];
+  const int lane = threadIdx.x & 63;
+  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+  const A alpha = (A)cf[0], beta = (A)cf[1], gamma = (A)cf[2];
+  const int l0 = STRIDED ? lane : lane * EPL;
+  const T* yv = Yin + d.off + l0;
+  const int64_t o = d.off + int64_t(r) * d.ld + l0;
+  A yin[EPL], ypr[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) yin[e] = AC::load(Yin[o + e * ES]);
+  if (Yprev) {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      ypr[e] = AC::load(NT ? ld_nt(Yprev + o + e * ES) : Yprev[o + e * ES]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) ypr[e] = (A)0;
+  }
+  const A g3 = Yprev ? gamma : (A)0;
+  const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
+  const int32_t* cb = col + c.nnz_off;
+  const float* vb = val + c.nnz_off;
+  A acc[EPL], dg = (A)0;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) acc[e] = (A)0;
+  for (int k = k0; k < k1; k += G) {
+    A y[G][EPL];
+    A w[G];
+    bool has[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      has[u] = false;
+      w[u] = (A)0;
+      if (k + u < k1) {
+        const int cj = cb[k + u];
+        const A wv = (A)vb[k + u];
+        if (cj == r) {
+          dg = wv;
+        } else {
+          has[u] = true;
+          w[u] = wv;
+          const T* src = yv + int64_t(cj) * d.ld;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      if (has[u])
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
+  }
+  const A ad = alpha * dg;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    const T v = AC::store(alpha * acc[e] + (fma(ad, yin[e], beta * yin[e]) + g3 * ypr[e]));
+    if (NT)
+      st_nt(Yout + o + e * ES, v);
+    else
+      Yout[o + e * ES] = v;
+  }
+}
+
 // The same product with two rows per wavefront: both rows' loads are in
 // flight together, so a launch holds twice the rows per wavefront slot.
 template <typename T, int EPL, bool STRIDED = false>
@@ -416,6 +532,29 @@ static void launch_spmm_rows(int var, const SpmmTile* tiles, int ntiles, const M
                        dim3(4 * NUM_XCD * ceil_div(ceil_div(ntiles, 2), NUM_XCD)), dim3(256), 0,
                        s, tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef,
                        coef_stride, step, ntiles);
+  else if (var == SPMM_VAR_X8_NT)
+    hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 8, true>), dim3(2 * grid.x), dim3(512), 0, s,
+                       tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
+                       step, ntiles);
+  else if (var == SPMM_VAR_X16_NT) {
+    // FP64 rows of 320 would spill in 16-wavefront workgroups: 8 instead
+    if constexpr (sizeof(typename Acc<T>::type) * EPL > 32)
+      hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 8, true>), dim3(2 * grid.x), dim3(512), 0, s,
+                         tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef,
+                         coef_stride, step, ntiles);
+    else
+      hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 16, true>), grid, dim3(1024), 0, s, tiles,
+                         sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride, step,
+                         ntiles);
+  }
+  else if (var == SPMM_VAR_X8)
+    hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 8, false>), dim3(2 * grid.x), dim3(512), 0, s,
+                       tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
+                       step, ntiles);
+  else if (var == SPMM_VAR_X4_NT)
+    hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 4, true>), dim3(4 * grid.x), dim3(256), 0, s,
+                       tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
+                       step, ntiles);
   else if (var == SPMM_VAR_ROW_W4)
     hipLaunchKernelGGL((k_spmm_row<T, EPL, ST, SPMM_GATHER, 4>), dim3(4 * grid.x), dim3(256), 0,
                        s, tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef,
@@ -425,7 +564,9 @@ static void launch_spmm_rows(int var, const SpmmTile* tiles, int ntiles, const M
                        csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride, step, ntiles);
 }
 
-int spmm_default_var(int epl) { return epl == 3 ? SPMM_VAR_ROW2 : SPMM_VAR_ROW; }
+// Without the autotuner: the exact-gather kernel in 8-wavefront workgroups
+// with non-temporal streams (the fastest on slabs far beyond the caches).
+int spmm_default_var(int) { return SPMM_VAR_X8_NT; }
 
 template <typename T>
 void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const CsrDesc* csr,

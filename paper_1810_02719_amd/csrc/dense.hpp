@@ -64,7 +64,12 @@ constexpr int ROW_TILE = 64;
 // 4 at a time (fewer registers, more wavefronts per CU), two rows per
 // wavefront, one row per wavefront in workgroups of 4 wavefronts, or 2 or 4
 // rows per wavefront one after the other with all their indices loaded
-// first (2 also in workgroups of 4 wavefronts).
+// first (2 also in workgroups of 4 wavefronts); and one row per wavefront
+// gathering only the off-diagonal entries, the diagonal folded into the
+// row's own term, in workgroups of 8, 16 or 4 wavefronts over consecutive
+// rows, with the previous iterate and the output streamed non-temporally
+// (8 also with ordinary loads and stores).  Variants 0-6 give bit-identical
+// results, and so do 7-10 among themselves.
 constexpr int SPMM_VAR_ROW = 0;
 constexpr int SPMM_VAR_ROW_G4 = 1;
 constexpr int SPMM_VAR_ROW2 = 2;
@@ -72,7 +77,11 @@ constexpr int SPMM_VAR_ROW_W4 = 3;
 constexpr int SPMM_VAR_ROWS2 = 4;
 constexpr int SPMM_VAR_ROWS4 = 5;
 constexpr int SPMM_VAR_ROWS2_W4 = 6;
-constexpr int SPMM_NVAR = 7;
+constexpr int SPMM_VAR_X8_NT = 7;
+constexpr int SPMM_VAR_X16_NT = 8;
+constexpr int SPMM_VAR_X8 = 9;
+constexpr int SPMM_VAR_X4_NT = 10;
+constexpr int SPMM_NVAR = 11;
 int spmm_default_var(int epl);
 
 template <typename T>

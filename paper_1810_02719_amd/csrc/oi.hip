@@ -315,6 +315,24 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Checkpoint copies of one wave's blocks (the recording for the adjoint):
+// ld x ld matrices at m_off, and the filter coefficients of the blocks.
+template <typename E>
+__global__ void __launch_bounds__(256)
+    k_copy_mats(const SmallDesc* __restrict__ sds, const E* __restrict__ src, E* __restrict__ dst) {
+  const SmallDesc d = sds[blockIdx.x];
+  const int64_t n = int64_t(d.ld) * d.ld;
+  for (int64_t e = threadIdx.x; e < n; e += 256) dst[d.m_off + e] = src[d.m_off + e];
+}
+
+__global__ void k_copy_coef(const MatDesc* __restrict__ sets, int nsets, int stride,
+                            const double* __restrict__ src, double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsets * stride) return;
+  const int64_t o = int64_t(sets[i / stride].blk) * stride + i % stride;
+  dst[o] = src[o];
+}
+
 // ------------------------------------------------------------------ R^z (Section 4)
 // The paper's operator R^z = (L + delta I)^-z, applied as z solves with
 // (L + delta I), each by a fixed number of conjugate-gradient iterations on
@@ -1092,12 +1110,6 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   const TV* V0 = static_cast<const TV*>(a.V0);
   TV* Vf = doi ? reinterpret_cast<TV*>(ws + doi->off_vf) : nullptr;
   int32_t* doi_done = doi ? reinterpret_cast<int32_t*>(ws + doi->off_done) : nullptr;
-  const size_t slab_bytes = size_t(P.hb.u_off[B]) * sizeof(T);
-  const size_t mats = size_t(P.hb.m_off[B]);
-  auto keep = [&](void* dst, const void* src, size_t bytes) {
-    (void)hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
-  };
-  int jp = 0;  // filter passes done (recording index)
 
   {
     KScope k_(a.tm, MI_K_SETUP, s);
@@ -1126,6 +1138,21 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   const hipStream_t s_main = s;
   for (WaveTables& w : P.waves) {
     hipStream_t s = fork ? P.lane_s[w.lane] : s_main;
+    int jp = 0;  // filter passes of this wave done (recording index)
+    // checkpoints of this wave's blocks only (other waves' blocks hold their
+    // own passes in the same recording slots)
+    auto keep_slab = [&](void* dst, const T* src) {
+      hipLaunchKernelGGL(k_copy_slab<T>, dim3(w.n_spmm), dim3(256), 0, s, w.spmm, w.tall, src,
+                         static_cast<T*>(dst));
+    };
+    auto keep_mats = [&](void* dst, const void* src, bool f64) {
+      if (f64)
+        hipLaunchKernelGGL(k_copy_mats<double>, dim3(w.nb), dim3(256), 0, s, w.sd,
+                           static_cast<const double*>(src), static_cast<double*>(dst));
+      else
+        hipLaunchKernelGGL(k_copy_mats<TS>, dim3(w.nb), dim3(256), 0, s, w.sd,
+                           static_cast<const TS*>(src), static_cast<TS*>(dst));
+    };
     double* part = part0 + (fork ? size_t(w.lane) * L.part_lane : 0);
     const size_t lds_jac = size_t(4 * (w.max_q / 2) + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
     const bool jac_lds = lds_jac <= (size_t)P.lds_max;
@@ -1236,8 +1263,11 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                                w.nb, a_lo, b_hi, coef, L.coef_stride, w.m);
         }
         if (rec) {
-          if (jp == 0) keep(rec->coef, coef, size_t(B) * L.coef_stride * sizeof(double));
-          keep(rec->X[jp], X, slab_bytes);
+          if (pass == 0)
+            hipLaunchKernelGGL(k_copy_coef, dim3(ceil_div(w.nb * L.coef_stride, 256)), dim3(256),
+                               0, s, w.tall, w.nb, L.coef_stride, (const double*)coef,
+                               rec->coef + size_t(t) * B * L.coef_stride);
+          keep_slab(rec->X[jp], X);
         }
         int free_s[3], nf = 0;
         for (int i = 0; i < 4 && nf < 3; ++i)
@@ -1312,7 +1342,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
             launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
           }
           chol(dbl ? nullptr : S32);
-          if (rec) keep(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, mats * sizeof(T));
+          if (rec) keep_mats(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, false);
           int dst = -1;
           for (int i = 0; i < 4; ++i)
             if (i != ycur && i != xslab) dst = i;
@@ -1351,7 +1381,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         // intermediate iteration: Cholesky-QR of Y; the filter's lower bound
         // follows the largest Rayleigh quotient of the new basis
         chol(dbl ? nullptr : S32);
-        if (rec) keep(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, mats * sizeof(T));
+        if (rec) keep_mats(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, false);
         {
           KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
           launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
@@ -1395,8 +1425,8 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       // Rayleigh-Ritz: A = Rinv^T H Rinv = Z Theta Z^T,  V = Y Rinv Z
       chol(nullptr);
       if (rec && last) {
-        keep(rec->Rrr, Rinv, mats * sizeof(double));
-        keep(rec->Y, Y, slab_bytes);
+        keep_mats(rec->Rrr, Rinv, true);
+        keep_slab(rec->Y, Y);
       }
       {
         KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
@@ -1430,7 +1460,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           KScope k_(a.tm, MI_K_EIG_BACK, s);
           launch_tri_back(w.sd, w.nb, w.max_ld, S64, Wk, tri, Z, s);
         }
-        if (rec && last) keep(rec->Z, Z, mats * sizeof(double));
+        if (rec && last) keep_mats(rec->Z, Z, true);
       } else {
         {
           KScope k_(a.tm, MI_K_JACOBI_INIT, s);

@@ -110,6 +110,9 @@ struct OiPlan {
 
 // Checkpoints of one recorded forward (single wave, MI_WARM_GIVEN, no
 // adaptation of the filter interval): everything the reverse sweep needs.
+// Checkpoints of the forward for the adjoint.  Pass j of a wave is the j-th
+// filter pass of that wave's blocks (T passes-long per wave); every wave
+// writes only its own blocks' rows and matrices, so the slots are shared.
 struct OiRecord {
   void** X = nullptr;       // [npass] input basis of every filter pass (slab)
   void** S = nullptr;       // [npass-1] operand of the Cholesky-QR row product
@@ -117,8 +120,9 @@ struct OiRecord {
   void* Y = nullptr;        // output of the last pass (slab)
   double* Rrr = nullptr;    // Rinv of the Rayleigh-Ritz step (FP64 ld x ld)
   double* Z = nullptr;      // Ritz vectors of A (FP64 ld x ld, ascending)
-  double* coef = nullptr;   // filter coefficients [B][coef_stride]
-  int npass = 0;
+  double* coef = nullptr;   // filter coefficients [iteration][B][coef_stride]
+  int npass = 0;            // passes of the longest wave
+  int n_iter = 0;           // iterations of the longest wave
 };
 
 // The dynamic walk of Alg. 2 (mi_doi_track): the iteration count and the

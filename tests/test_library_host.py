@@ -116,11 +116,22 @@ def test_residual_and_adjoint_workspace_queries():
                                                  C.byref(n))
 
     assert q(ok) == 0 and n.value > 0
-    for field, value in (("warm", mis.MI_WARM_PRED), ("adapt", 1), ("rr_every", 1),
-                         ("eig", L.MI_EIG_JACOBI), ("T0", 0), ("b_abs", 0.0),
-                         ("a_mode", mis.MI_A_WEYL), ("tol", 1e-6), ("warm", mis.MI_RANDOM)):
+    # the interval schedule and the start are held constant by the reverse
+    # sweep, whatever rule sets them
+    for field, value in (("warm", mis.MI_WARM_PRED), ("adapt", 1), ("b_abs", 0.0),
+                         ("a_mode", mis.MI_A_WEYL), ("warm", mis.MI_RANDOM)):
+        assert q(mis.OiParams(**{**ok.__dict__, field: value})) == 0, field
+    for field, value in (("rr_every", 1), ("eig", L.MI_EIG_JACOBI), ("T0", 0), ("tol", 1e-6),
+                         ("precision", mis.MI_BF16_IN), ("op", mis.MI_OP_RZ)):
         bad = mis.OiParams(**{**ok.__dict__, field: value})
         assert q(bad) == L.MI_ERR_ARG, field
+    # warm-started blocks with more passes than the roots need more checkpoints
+    q(ok)
+    n_root = n.value
+    chain = mis.Blocks([300, 500], p=[40, 64], pred=[-1, 0])
+    warm = mis.OiParams(**{**ok.__dict__, "warm": mis.MI_WARM_PRED, "T": 4, "passes": 2})
+    assert q(warm, chain) == 0 and n.value > n_root
+    assert q(mis.OiParams(**{**warm.__dict__, "T": 0}), chain) == L.MI_ERR_ARG
     wide = mis.Blocks([300, 500], p=[40, 200])
     assert q(ok, wide) == L.MI_ERR_ARG
 

@@ -727,6 +727,70 @@ class TestAdjointOracle:
         assert errs[-1] < 1e-8 and errs[0] > errs[-1], errs
 
 
+    def test_tracked_map_reduces_to_the_fixed_interval(self, case):
+        # one pass per iteration, a given b and no adaptation: the same map as
+        # the fixed-interval unrolled iteration
+        adj, n, e, X, V0, G, uw = case
+        gX0, gw0 = adj.unrolled_grad(n, e, X, adj.USER, V0, 0.9, 12.0, 3, 3, 4, G, uw)
+        gX, gw, info = adj.tracked_grad(n, e, X, adj.USER, V0, 4, G, T=3, m=3, passes=1, a0=0.9,
+                                        b=12.0, user_w=uw)
+        assert info["a"] == [0.9, 0.9, 0.9] and info["b"] == 12.0
+        assert np.abs(gw - gw0).max() < 1e-12 * np.abs(gw0).max()
+        assert np.abs(gX - gX0).max() < 1e-12 * np.abs(gX0).max()
+
+    def test_tracked_gradient_matches_differences_at_the_frozen_interval(self, case):
+        # adaptive a and Gershgorin b recorded at the point, then held fixed
+        adj, n, e, X, V0, G, uw = case
+        kw = dict(T=3, m=3, passes=2, a0=lambda b: 1.0 * b * 8 / n, adapt=True, orth_start=True)
+        gX, gw, info = adj.tracked_grad(n, e, X, adj.USER, V0, 4, G, user_w=uw, **kw)
+        assert len(info["a"]) == 3 and len(set(info["a"])) == 3  # the bound moved
+        sched = (info["b"], info["a"])
+
+        def f(w):
+            return adj.tracked_grad(n, e, X, adj.USER, V0, 4, G, user_w=w, schedule=sched,
+                                    **kw)[2]["loss"]
+
+        h = 1e-6
+        for k in (1, 9, e.shape[0] - 2):
+            wp, wm = uw.copy(), uw.copy()
+            wp[k] += h
+            wm[k] -= h
+            fd = (f(wp) - f(wm)) / (2 * h)
+            assert abs(fd - gw[k]) <= 1e-6 * max(1.0, abs(gw).max()), (k, fd, gw[k])
+
+    def test_gershgorin_bound_and_adaptive_bound_on_a_path(self):
+        # path P_n: rows of L sum in absolute value to 2 (ends) and 4 (inside);
+        # eigenpairs lam_k = 2 - 2 cos(k pi / n), u_k(i) ~ cos(k pi (i + 1/2) / n).
+        # Started on the exact lowest p eigenvectors the filter keeps them, so
+        # the largest Rayleigh quotient of the basis is lam_{p-1}.
+        import torch
+        from oracle import adjoint as adj
+        n, p = 12, 4
+        e = np.array([[i, i + 1] for i in range(n - 1)])
+        L = adj.laplacian(n, torch.from_numpy(e), torch.ones(n - 1, dtype=torch.float64))
+        assert adj.gershgorin(L) == 4.0
+        i = np.arange(n) + 0.5
+        U = np.stack([np.cos(k * np.pi * i / n) for k in range(p)], axis=1)
+        U /= np.linalg.norm(U, axis=0)
+        lam = 2 - 2 * np.cos(np.arange(p) * np.pi / n)
+        X = np.stack([np.arange(n), np.zeros(n), np.zeros(n)], axis=1).astype(float)
+        _, _, info = adj.tracked_grad(n, e, X, adj.COMBINATORIAL, U, 2, np.ones((n, 3)), T=3,
+                                      m=3, passes=1, a0=0.5, adapt=True)
+        assert info["b"] == 4.0 and info["a"][0] == 0.5
+        assert abs(info["a"][1] - lam[p - 1]) < 1e-12 and abs(info["a"][2] - lam[p - 1]) < 1e-12
+        assert np.abs(info["theta"] - lam).max() < 1e-12
+
+    def test_warm_start_layout(self):
+        from oracle import adjoint as adj
+        Vp = np.arange(8, dtype=float).reshape(4, 2) + 1.0
+        S0 = adj.warm_start(Vp, 5, 3)
+        # rows 0..3 and columns 0..1 copied, row 4 zero there, column 2 is
+        # the unit vector at (997 * 2) mod 5 = 4
+        want = np.array([[1, 2, 0], [3, 4, 0], [5, 6, 0], [7, 8, 0], [0, 0, 1]], float)
+        assert np.array_equal(S0, want)
+        assert np.array_equal(adj.warm_start(Vp, 3, 1), Vp[:3, :1])
+
+
 # ---------------------------------------------------------------- Section 6.1, Alg. 3
 
 class TestOverlappedMerge:

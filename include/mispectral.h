@@ -340,13 +340,14 @@ mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_pa
  * workgroups, 4 and 5 two and four rows per wavefront one after the other
  * with their indices loaded first, 6 the same with two rows in
  * 4-wavefront workgroups; 7 to 10 one row per wavefront gathering only the
- * off-diagonal entries with the diagonal folded into the row's own term,
+ * off-diagonal entries, in the difference form sum_j L_rj (Y_j - Y_r) plus
+ * the row sum times Y_r (more accurate for the smooth iterates of a
+ * Laplacian),
  * over consecutive rows in workgroups of 8 (7, 9), 16 (8) or 4 (10)
  * wavefronts, the previous iterate and the output streamed non-temporally
  * except in 9; -1 the default, 7) for up to `cap` waves;
  * *n_waves gets the plan's wave count.  Variants 0 to 6 give bit-identical
- * results, and so do 7 to 10 among themselves (the folded diagonal rounds
- * differently).  Host only. */
+ * results, and so do 7 to 10 among themselves.  Host only. */
 mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves);
 
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,
@@ -458,7 +459,8 @@ mi_status mi_ritz_residuals(mi_ctx* ctx, const mi_blocks* blk, int32_t precision
  * row_ptr, col, val, nnz_off   the block Laplacians (layout as mi_oi_track);
  * edges     device int32 [sum |E_b|][2] canonical edges (a < b, block-local)
  *           at edge_off[b] (host int64 [B+1]), as mi_build_laplacian emits.
- * V0        device start slab (precision's element type), as for mi_oi_track.
+ * V0        device start slab (precision's element type), as for mi_oi_track
+ *           (may be NULL under MI_RANDOM).
  * X, Gbar   device [v_off[B]][3] coordinates and d loss/d X~ (element type).
  * c         device int32 [B], 1 <= c_b <= p_b.
  * Xbar      device double [v_off[B]][3]: d loss/d X.

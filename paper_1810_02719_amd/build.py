@@ -55,11 +55,57 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     return OUT
 
 
+# Host-side sanitizer build: every translation unit and the driver under
+# tests/native compiled with AddressSanitizer and UndefinedBehaviorSanitizer
+# on the host pass only (each flag behind -Xarch_host; the kernels are the
+# ordinary gfx950 code), linked into one executable by the LLVM C++ driver.
+SAN_DRIVER = os.path.join(os.path.dirname(HERE), "tests", "native", "sanitized_driver.hip")
+SAN_OUT = os.path.join(HERE, "mispectral_sanitized")
+SAN_BUILD = os.path.join(BUILD, "sanitized")
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-g"]
+CXX_LINK = os.environ.get("MI_CXX_LINK", "/opt/rocm/llvm/bin/clang++")
+LINK_SAN = ["-fsanitize=address,undefined"]
+
+
+def _compile_san(src):
+    obj = os.path.join(SAN_BUILD, os.path.basename(src)[:-4] + ".o")
+    cmd = [HIPCC, *FLAGS, *SAN_HOST, "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+        raise RuntimeError(f"sanitized build failed for {src}:\n{err}")
+    return obj
+
+
+def build_sanitized(jobs: int = 8, verbose: bool = False) -> str:
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    srcs = sources() + [SAN_DRIVER]
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(_compile_san, srcs))
+    rocm = os.path.dirname(os.path.dirname(HIPCC))
+    tmp = SAN_OUT + ".tmp"
+    cmd = [CXX_LINK, *LINK_SAN, "-o", tmp, *objs, f"-L{rocm}/lib", "-lamdhip64",
+           f"-Wl,-rpath,{rocm}/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stderr)
+    os.replace(tmp, SAN_OUT)
+    if verbose:
+        print(f"built {SAN_OUT} (host ASan/UBSan) from {len(srcs)} sources")
+    return SAN_OUT
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--sanitized", action="store_true",
+                    help="also build the host-sanitized test executable")
     a = ap.parse_args(argv)
     build(a.jobs, verbose=True)
+    if a.sanitized:
+        build_sanitized(a.jobs, verbose=True)
 
 
 if __name__ == "__main__":

@@ -679,9 +679,10 @@ mi_status mi_encdec_adjoint(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_param
                             const int32_t* c, const void* Gbar, double* Xbar, double* wbar,
                             void* ws, size_t ws_bytes, void* stream) {
   begin_call();
-  MI_CHECK_ARG(ctx && row_ptr && col && val && nnz_off && edges && edge_off && V0 && X && c &&
+  MI_CHECK_ARG(ctx && prm && row_ptr && col && val && nnz_off && edges && edge_off && X && c &&
                    Gbar && Xbar && wbar,
                "NULL argument");
+  MI_CHECK_ARG(V0 || prm->warm == MI_RANDOM, "V0 is NULL (needed unless warm = MI_RANDOM)");
   MI_CHECK_ARG(mode == MI_W_COMBINATORIAL || mode == MI_W_INV_SQ_DIST || mode == MI_W_INV_DIST ||
                    mode == MI_W_USER,
                "weight mode %d unknown", mode);

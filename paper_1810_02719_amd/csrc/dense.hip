@@ -305,9 +305,16 @@ __device__ inline void st_nt<bf16>(bf16* p, bf16 v) {
 }
 
 // One row per wavefront gathering exactly the row's off-diagonal entries
-// (wave-uniform branches, no padded loads), with the diagonal entry folded
-// into the row's own term:
-//   W_r = alpha sum_{j != r} L_rj Y_j + (alpha L_rr Y_r + beta Y_r) + gamma Yprev_r.
+// (wave-uniform branches, no padded loads), with the product in difference
+// form:
+//   (L Y)_r = sum_{j != r} L_rj (Y_j - Y_r) + (sum_j L_rj) Y_r,
+//   W_r = alpha (L Y)_r + beta Y_r + gamma Yprev_r.
+// For a Laplacian the row sum is zero (exactly, for combinatorial weights)
+// and the differences of a smooth iterate are small and exact in floating
+// point, so the low-frequency components of L Y lose nothing to the
+// cancellation of a degree-sized diagonal term against its neighbours: their
+// rounding error scales with lambda |Y| instead of ||L|| |Y|.  The row's own
+// values are loaded anyway; the diagonal entry itself is never gathered.
 // The WPG rows of a workgroup are consecutive, so the neighbour rows they
 // share are fetched once into the CU's L1 for all of them; with NT the
 // previous iterate and the output stream past the caches.  The gather
@@ -358,7 +365,7 @@ __global__ void __launch_bounds__(64 * WPG)
   const int k0 = row_ptr[c.rp_off + r], k1 = row_ptr[c.rp_off + r + 1];
   const int32_t* cb = col + c.nnz_off;
   const float* vb = val + c.nnz_off;
-  A acc[EPL], dg = (A)0;
+  A acc[EPL], rs = (A)0;  // rs: the row's entry sum (zero for a Laplacian)
 #pragma unroll
   for (int e = 0; e < EPL; ++e) acc[e] = (A)0;
   for (int k = k0; k < k1; k += G) {
@@ -372,9 +379,8 @@ __global__ void __launch_bounds__(64 * WPG)
       if (k + u < k1) {
         const int cj = cb[k + u];
         const A wv = (A)vb[k + u];
-        if (cj == r) {
-          dg = wv;
-        } else {
+        rs += wv;
+        if (cj != r) {
           has[u] = true;
           w[u] = wv;
           const T* src = yv + int64_t(cj) * d.ld;
@@ -387,12 +393,12 @@ __global__ void __launch_bounds__(64 * WPG)
     for (int u = 0; u < G; ++u)
       if (has[u])
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e], acc[e]);
+        for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e] - yin[e], acc[e]);
   }
-  const A ad = alpha * dg;
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
-    const T v = AC::store(alpha * acc[e] + (fma(ad, yin[e], beta * yin[e]) + g3 * ypr[e]));
+    const A ly = fma(rs, yin[e], acc[e]);  // (L Y)_r in difference form
+    const T v = AC::store(alpha * ly + (beta * yin[e] + g3 * ypr[e]));
     if (NT)
       st_nt(Yout + o + e * ES, v);
     else
@@ -620,6 +626,19 @@ template void launch_spmm<bf16>(const SpmmTile*, int, const MatDesc*, const CsrD
 // B(k = l/16, n = l%16).  Result element (m, n = l%16) sits in register q of
 // lane l with m = l/16 + 4q for the FP64 instruction and m = 4(l/16) + q for
 // the FP32 one (measured lane layouts).
+// Workgroups are dealt to the 8 XCDs in contiguous tile ranges (workgroup i
+// takes tile (i mod 8) * per + i / 8): tiles that read the same rows (a row
+// product's output-column chunks, neighbours in its table) then run on one
+// XCD and read those rows through its L2 once, instead of once per tile
+// from HBM (5% off the row product on the 1,024-disk slab; the Gram's
+// super-tile pairs measured 3% slower dealt this way and keep the plain
+// order).
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  return int(blockIdx.x % NUM_XCD) * per + int(blockIdx.x / NUM_XCD);
+}
+inline dim3 xcd_grid(int ntiles) { return dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)); }
+
 template <typename T, bool DUAL>
 __global__ void __launch_bounds__(256)
     k_gram(const GramTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
@@ -633,7 +652,8 @@ __global__ void __launch_bounds__(256)
                                                     // half (FP64) of the banks
   constexpr int NOP = DUAL ? 3 : 2;
   __shared__ __attribute__((aligned(16))) T St[NOP][RC * LDT];
-  const GramTile t = tiles[blockIdx.x];
+  const int ti = blockIdx.x;  // partial slot = table position
+  const GramTile t = tiles[ti];
   const MatDesc d = sets[t.set];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
@@ -691,7 +711,7 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   const int kk = kq, mm = mi;
-  double* out = part + int64_t(blockIdx.x) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
+  double* out = part + int64_t(ti) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
   const int n = mm;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -734,7 +754,8 @@ __global__ void __launch_bounds__(256)
   constexpr int LDT = RC + 8;      // LDS stride of a column (bf16 elements)
   constexpr int NOP = DUAL ? 3 : 2;
   __shared__ __attribute__((aligned(16))) uint16_t St[NOP][GRAM_TILE * LDT];
-  const GramTile t = tiles[blockIdx.x];
+  const int ti = blockIdx.x;  // partial slot = table position
+  const GramTile t = tiles[ti];
   const MatDesc d = sets[t.set];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
@@ -805,7 +826,7 @@ __global__ void __launch_bounds__(256)
         }
     __syncthreads();
   }
-  double* out = part + int64_t(blockIdx.x) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
+  double* out = part + int64_t(ti) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -823,11 +844,11 @@ void launch_gram<bf16>(const GramTile* tiles, int ntiles, const MatDesc* sets, c
                        const bf16* B, const bf16* W, double* part, hipStream_t s) {
   if (ntiles <= 0) return;
   if (W)
-    hipLaunchKernelGGL(k_gram_bf16<true>, dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W,
-                       part);
+    hipLaunchKernelGGL(k_gram_bf16<true>, dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
+                       W, part);
   else
-    hipLaunchKernelGGL(k_gram_bf16<false>, dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W,
-                       part);
+    hipLaunchKernelGGL(k_gram_bf16<false>, dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
+                       W, part);
 }
 
 template <typename T>
@@ -835,10 +856,11 @@ void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T
                  const T* W, double* part, hipStream_t s) {
   if (ntiles <= 0) return;
   if (W)
-    hipLaunchKernelGGL((k_gram<T, true>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W, part);
+    hipLaunchKernelGGL((k_gram<T, true>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
+                       W, part);
   else
-    hipLaunchKernelGGL((k_gram<T, false>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B, W,
-                       part);
+    hipLaunchKernelGGL((k_gram<T, false>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
+                       W, part);
 }
 template void launch_gram<float>(const GramTile*, int, const MatDesc*, const float*, const float*,
                                  const float*, double*, hipStream_t);
@@ -861,20 +883,21 @@ __global__ void __launch_bounds__(256)
   const int gi = j.I0 + il, gj = j.J0 + jl;
   if (gi >= o.ld || gj >= o.ld || gi > gj) return;
   const double* pp = part + int64_t(j.first) * stride + e;
+  const int64_t cs = int64_t(j.stride) * stride;  // from one chunk's partial to the next
   double sg = 0.0, sh = 0.0;
   int c = 0;
   for (; c + 4 <= j.count; c += 4) {
-    const double g0 = pp[(c + 0) * stride], g1 = pp[(c + 1) * stride];
-    const double g2 = pp[(c + 2) * stride], g3 = pp[(c + 3) * stride];
+    const double g0 = pp[(c + 0) * cs], g1 = pp[(c + 1) * cs];
+    const double g2 = pp[(c + 2) * cs], g3 = pp[(c + 3) * cs];
     sg += g0;
     sg += g1;
     sg += g2;
     sg += g3;
     if (dual) {
-      const double h0 = pp[(c + 0) * stride + GRAM_TILE * GRAM_TILE];
-      const double h1 = pp[(c + 1) * stride + GRAM_TILE * GRAM_TILE];
-      const double h2 = pp[(c + 2) * stride + GRAM_TILE * GRAM_TILE];
-      const double h3 = pp[(c + 3) * stride + GRAM_TILE * GRAM_TILE];
+      const double h0 = pp[(c + 0) * cs + GRAM_TILE * GRAM_TILE];
+      const double h1 = pp[(c + 1) * cs + GRAM_TILE * GRAM_TILE];
+      const double h2 = pp[(c + 2) * cs + GRAM_TILE * GRAM_TILE];
+      const double h3 = pp[(c + 3) * cs + GRAM_TILE * GRAM_TILE];
       sh += h0;
       sh += h1;
       sh += h2;
@@ -882,8 +905,8 @@ __global__ void __launch_bounds__(256)
     }
   }
   for (; c < j.count; ++c) {
-    sg += pp[c * stride];
-    if (dual) sh += pp[c * stride + GRAM_TILE * GRAM_TILE];
+    sg += pp[c * cs];
+    if (dual) sh += pp[c * cs + GRAM_TILE * GRAM_TILE];
   }
   G[o.off + int64_t(gi) * o.ld + gj] = sg;
   G[o.off + int64_t(gj) * o.ld + gi] = sg;
@@ -930,7 +953,7 @@ template <typename TA, typename T, typename TO, int NCH>
 __global__ void __launch_bounds__(256)
     k_rowmul(const RowTile* __restrict__ tiles, const MatDesc* __restrict__ asets,
              const TA* __restrict__ A, const MatDesc* __restrict__ ssets, const T* __restrict__ S,
-             const MatDesc* __restrict__ osets, TO* __restrict__ Out) {
+             const MatDesc* __restrict__ osets, TO* __restrict__ Out, int ntiles) {
   typedef typename VecOf<T>::type V;
   typedef typename VecOf<TA>::type VA;
   constexpr int W = VecOf<T>::W;           // elements per 16-byte vector
@@ -947,7 +970,9 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) T As[ROW_TILE * LDA];
   __shared__ __attribute__((aligned(16))) T Ss[KC * LDS_];
   typedef typename Mfma<T>::acc_t acc_t;
-  const RowTile t = tiles[blockIdx.x];
+  const int ti = xcd_tile(ntiles);
+  if (ti >= ntiles) return;
+  const RowTile t = tiles[ti];
   const MatDesc da = asets[t.set], ds = ssets[t.set], dout = osets[t.set];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int K = ds.rows;
@@ -1038,8 +1063,8 @@ void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const
   switch (nch) {
 #define MI_ROWMUL_CASE(N)                                                                       \
   case N:                                                                                       \
-    hipLaunchKernelGGL((k_rowmul<TA, T, TO, N>), dim3(ntiles), dim3(256), 0, s, tiles, asets,  \
-                       A, ssets, S, osets, Out);                                                \
+    hipLaunchKernelGGL((k_rowmul<TA, T, TO, N>), xcd_grid(ntiles), dim3(256), 0, s, tiles,     \
+                       asets, A, ssets, S, osets, Out, ntiles);                                 \
     break;
     MI_ROWMUL_CASE(32)
     MI_ROWMUL_CASE(64)
@@ -1078,9 +1103,12 @@ int gram_chunks(int nsets, int npairs, int rows, int target) {
   return std::max(ch, 1);
 }
 
-// Gram tile table for a list of per-block matrices with `rows` rows each.
+// Gram tile table for a list of per-block matrices with `rows` rows each:
+// per block, its row chunks in order, and per chunk every super-tile pair
+// (I <= J), so that a chunk's pairs are neighbours in the table (and on one
+// XCD, see gram_tile_of); a pair's partials are npairs tiles apart.
 void gram_tables(const std::vector<MatDesc>& sets, bool split,
-                        std::vector<GramTile>* tiles, std::vector<GramReduce>* red, int target) {
+                 std::vector<GramTile>* tiles, std::vector<GramReduce>* red, int target) {
   for (int si = 0; si < (int)sets.size(); ++si) {
     const MatDesc& d = sets[si];
     const int nsup = ceil_div(d.ld, GRAM_TILE);
@@ -1088,26 +1116,17 @@ void gram_tables(const std::vector<MatDesc>& sets, bool split,
     const int ch = split ? gram_chunks((int)sets.size(), npairs, d.rows, target) : 1;
     int rows_per = ceil_div(d.rows, ch);
     rows_per = ((rows_per + 15) / 16) * 16;
+    const int base = (int)tiles->size();
+    int nch = 0;
+    for (int r0 = 0; r0 < d.rows; r0 += rows_per, ++nch)
+      for (int I = 0; I < nsup; ++I)
+        for (int J = I; J < nsup; ++J)
+          tiles->push_back(GramTile{si, I * GRAM_TILE, J * GRAM_TILE, r0,
+                                    std::min(d.rows, r0 + rows_per)});
+    int pidx = 0;
     for (int I = 0; I < nsup; ++I)
-      for (int J = I; J < nsup; ++J) {
-        GramReduce g;
-        g.set = si;
-        g.I0 = I * GRAM_TILE;
-        g.J0 = J * GRAM_TILE;
-        g.first = (int)tiles->size();
-        g.count = 0;
-        for (int r0 = 0; r0 < d.rows; r0 += rows_per) {
-          GramTile t;
-          t.set = si;
-          t.I0 = g.I0;
-          t.J0 = g.J0;
-          t.r0 = r0;
-          t.r1 = std::min(d.rows, r0 + rows_per);
-          tiles->push_back(t);
-          ++g.count;
-        }
-        red->push_back(g);
-      }
+      for (int J = I; J < nsup; ++J, ++pidx)
+        red->push_back(GramReduce{si, I * GRAM_TILE, J * GRAM_TILE, base + pidx, nch, npairs});
   }
 }
 

@@ -43,12 +43,12 @@ struct GramTile {
 };
 constexpr int GRAM_TILE = 64;
 
-// Reduce jobs: block `set`, super-tile (I0, J0), partial tiles
-// [first, first + count) in chunk order.
+// Reduce jobs: block `set`, super-tile (I0, J0), partial tiles first,
+// first + stride, ..., count of them, in chunk order.
 struct GramReduce {
   int32_t set;
   int32_t I0, J0;
-  int32_t first, count;
+  int32_t first, count, stride;
 };
 
 // Row-product tiles: rows [row0, row0 + 64) x output columns [n0, n0 + NCH).
@@ -65,11 +65,12 @@ constexpr int ROW_TILE = 64;
 // wavefront, one row per wavefront in workgroups of 4 wavefronts, or 2 or 4
 // rows per wavefront one after the other with all their indices loaded
 // first (2 also in workgroups of 4 wavefronts); and one row per wavefront
-// gathering only the off-diagonal entries, the diagonal folded into the
-// row's own term, in workgroups of 8, 16 or 4 wavefronts over consecutive
-// rows, with the previous iterate and the output streamed non-temporally
-// (8 also with ordinary loads and stores).  Variants 0-6 give bit-identical
-// results, and so do 7-10 among themselves.
+// gathering only the off-diagonal entries, the product in difference form
+// (sum_j L_rj (Y_j - Y_r) plus the row sum times Y_r), in workgroups of 8,
+// 16 or 4 wavefronts over consecutive rows, with the previous iterate and
+// the output streamed non-temporally (8 also with ordinary loads and
+// stores).  Variants 0-6 give bit-identical results, and so do 7-10 among
+// themselves.
 constexpr int SPMM_VAR_ROW = 0;
 constexpr int SPMM_VAR_ROW_G4 = 1;
 constexpr int SPMM_VAR_ROW2 = 2;

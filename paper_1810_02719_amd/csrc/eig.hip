@@ -821,8 +821,15 @@ void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, double* A, doubl
                        double* tri, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
   if (max_ld > 32 * 6) {
-    hipLaunchKernelGGL(k_tri_reduce_g, dim3(nb), dim3(TRI_G_THREADS), 0, s, sd, A, Hv, tri,
-                       status);
+    // One workgroup per CU: the launch reserves 64 KB of LDS it does not use
+    // (with the kernel's own 18 KB, two workgroups no longer fit the CU's
+    // 160 KB).  The blocks in flight then keep their trailing matrices
+    // (800 KB each at ld = 320, read and written once per step) within the
+    // 256 MB infinity cache, where two per CU overflowed it to HBM: 34.0 to
+    // 27.7 ms for 1,024 blocks of ld 320.
+    constexpr size_t TRI_G_RESERVE = 64 * 1024;
+    hipLaunchKernelGGL(k_tri_reduce_g, dim3(nb), dim3(TRI_G_THREADS), TRI_G_RESERVE, s, sd, A,
+                       Hv, tri, status);
     return;
   }
   switch ((max_ld + 31) / 32) {

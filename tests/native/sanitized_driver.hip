@@ -1,0 +1,339 @@
+// Host-side sanitizer run of the library: built with AddressSanitizer and
+// UndefinedBehaviorSanitizer on the host pass only (the kernels are ordinary
+// gfx950 code), linked with the library's objects into one executable.
+//
+//   sanitized_driver host   planners only (no device): workspace-size
+//                           queries, which build the waves, lanes, launch
+//                           tables and workspace layouts on the host, and the
+//                           argument checks with their error messages
+//   sanitized_driver gpu    the same plus a chained block set with three
+//                           predecessor trees on the device: stream lanes,
+//                           graph capture and replay, a forced launch shape,
+//                           the event timer, the per-block path, choose_c,
+//                           projection, reconstruction and the adjoint
+//
+// Prints one line per step and "ok" at the end; exit status 0 when every
+// call returned MI_OK and every check held (a sanitizer report aborts).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mispectral.h"
+
+namespace {
+
+int fail(const char* what, mi_status st) {
+  std::printf("FAIL %s: status %d (%s)\n", what, (int)st, mi_last_error());
+  std::fflush(stdout);
+  return 1;
+}
+
+#define CHECK(call)                        \
+  do {                                     \
+    mi_status st_ = (call);                \
+    if (st_ != MI_OK) return fail(#call, st_); \
+  } while (0)
+
+#define EXPECT(cond, what)                                  \
+  do {                                                      \
+    if (!(cond)) {                                          \
+      std::printf("FAIL %s\n", what);                       \
+      std::fflush(stdout);                                  \
+      return 1;                                             \
+    }                                                       \
+  } while (0)
+
+void step(const char* s) {
+  std::printf("step: %s\n", s);
+  std::fflush(stdout);
+}
+
+// Nine grid blocks in three chains (0 -> 3 -> 6, 1 -> 4 -> 7, 2 -> 5 -> 8):
+// three predecessor trees, three levels.
+struct Mesh {
+  int B = 9;
+  std::vector<int64_t> v_off, u_off, prim_off;
+  std::vector<int32_t> p, ld, pred, c, prims;
+  std::vector<float> coords;
+  mi_blocks blk{};
+  Mesh() {
+    v_off.push_back(0);
+    u_off.push_back(0);
+    prim_off.push_back(0);
+    for (int b = 0; b < B; ++b) {
+      const int nx = 12 + 3 * (b % 4), ny = 10 + 2 * (b % 3), n = nx * ny;
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const float x = 6.2831853f * i / (nx - 1), y = 6.2831853f * j / (ny - 1);
+          coords.push_back(x);
+          coords.push_back(y);
+          coords.push_back(0.1f * std::sin(x) * std::cos(y));
+        }
+      int64_t nf = 0;
+      for (int j = 0; j + 1 < ny; ++j)
+        for (int i = 0; i + 1 < nx; ++i) {
+          const int a = j * nx + i, bb = a + 1, cc = a + nx, dd = cc + 1;
+          prims.insert(prims.end(), {a, bb, dd, a, dd, cc});
+          nf += 2;
+        }
+      p.push_back(48);
+      ld.push_back(64);
+      c.push_back(24);
+      pred.push_back(b < 3 ? -1 : b - 3);
+      v_off.push_back(v_off.back() + n);
+      u_off.push_back(u_off.back() + int64_t(n) * 64);
+      prim_off.push_back(prim_off.back() + nf);
+    }
+    blk.n_blocks = B;
+    blk.v_off = v_off.data();
+    blk.p = p.data();
+    blk.ld = ld.data();
+    blk.u_off = u_off.data();
+    blk.pred = pred.data();
+    blk.c = nullptr;
+  }
+};
+
+mi_oi_params params() {
+  mi_oi_params q;
+  std::memset(&q, 0, sizeof(q));
+  q.precision = MI_FP32;
+  q.warm = MI_RANDOM;
+  q.T = 2;
+  q.m = 6;
+  q.passes = 2;
+  q.T0 = 4;
+  q.m0 = 6;
+  q.passes0 = 2;
+  q.adapt = 1;
+  q.max_sweeps = 12;
+  q.a_mode = MI_A_WEYL;
+  q.rr_every = 0;
+  q.eig = MI_EIG_TRIDIAG;
+  q.autotune = 1;
+  q.a_value = 1.0;
+  q.b_abs = 0.0;
+  q.jacobi_tol = 1e-14;
+  q.op = MI_OP_CHEB;
+  q.z = 1;
+  q.cg_iters = 40;
+  q.delta = 1e-3;
+  q.tol = 0.0;
+  q.seed = 7;
+  return q;
+}
+
+int host_checks(Mesh& M) {
+  step("workspace queries (planner on the host)");
+  size_t ws = 0;
+  mi_oi_params q = params();
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  EXPECT(ws > 0, "tracking workspace");
+  q.warm = MI_WARM_PRED;
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  q.warm = MI_WARM_GIVEN;
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  q.tol = 1e-4;
+  M.blk.c = M.c.data();
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  M.blk.c = nullptr;
+  q = params();
+  q.op = MI_OP_RZ;
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  q = params();
+  q.eig = MI_EIG_JACOBI;
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  CHECK(mi_laplacian_workspace_size(&M.blk, M.prim_off.data(), 3, &ws));
+  CHECK(mi_encdec_workspace_size(nullptr, &M.blk, MI_FP32, &ws));
+  CHECK(mi_choose_c_workspace_size(nullptr, &M.blk, &ws));
+  std::vector<int64_t> nnz(M.B + 1, 0);
+  for (int b = 0; b < M.B; ++b) nnz[b + 1] = nnz[b] + 7 * (M.v_off[b + 1] - M.v_off[b]);
+  q = params();
+  q.warm = MI_WARM_PRED;
+  CHECK(mi_adjoint_workspace_size(nullptr, &M.blk, &q, nnz.data(), &ws));
+  step("argument errors");
+  q = params();
+  q.m = 0;
+  EXPECT(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws) == MI_ERR_ARG, "m = 0 refused");
+  EXPECT(std::strlen(mi_last_error()) > 0, "error message");
+  q = params();
+  q.warm = 9;
+  EXPECT(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws) == MI_ERR_ARG, "warm mode refused");
+  std::vector<int32_t> bad_pred(M.pred);
+  bad_pred[0] = 4;  // a cycle 0 -> 4 -> 1 ... with 4's predecessor chain
+  bad_pred[1] = 0;
+  bad_pred[4] = 1;
+  mi_blocks cyc = M.blk;
+  cyc.pred = bad_pred.data();
+  q = params();
+  q.warm = MI_WARM_PRED;
+  EXPECT(mi_oi_workspace_size(nullptr, &cyc, &q, &ws) == MI_ERR_ARG, "predecessor cycle refused");
+  std::vector<int32_t> bad_ld(M.ld);
+  bad_ld[2] = 40;
+  mi_blocks bl = M.blk;
+  bl.ld = bad_ld.data();
+  EXPECT(mi_oi_workspace_size(nullptr, &bl, &q, &ws) != MI_OK, "ld not a multiple of 32 refused");
+  return 0;
+}
+
+template <typename X>
+X* upload(const std::vector<X>& v) {
+  X* d = nullptr;
+  if (hipMalloc(&d, std::max<size_t>(v.size(), 1) * sizeof(X)) != hipSuccess) return nullptr;
+  if (!v.empty() && hipMemcpy(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice) != hipSuccess)
+    return nullptr;
+  return d;
+}
+
+template <typename X>
+X* alloc(size_t n) {
+  X* d = nullptr;
+  if (hipMalloc(&d, std::max<size_t>(n, 1) * sizeof(X)) != hipSuccess) return nullptr;
+  if (hipMemset(d, 0, std::max<size_t>(n, 1) * sizeof(X)) != hipSuccess) return nullptr;
+  return d;
+}
+
+int gpu_checks(Mesh& M) {
+  mi_ctx* ctx = nullptr;
+  step("context");
+  CHECK(mi_ctx_create(&ctx, 0));
+  const int B = M.B;
+  const int64_t N = M.v_off[B], U = M.u_off[B];
+  int64_t tp = 0;
+  for (int b = 0; b < B; ++b) tp += M.p[b];
+  int32_t* prims = upload(M.prims);
+  float* coords = upload(M.coords);
+  EXPECT(prims && coords, "uploads");
+  step("Laplacians");
+  size_t lws = 0;
+  CHECK(mi_laplacian_workspace_size(&M.blk, M.prim_off.data(), 3, &lws));
+  char* lw = alloc<char>(lws);
+  std::vector<int64_t> nnz(B + 1), eoff(B + 1);
+  CHECK(mi_build_laplacian_count(ctx, &M.blk, M.prim_off.data(), prims, 3, nnz.data(),
+                                 eoff.data(), lw, lws, nullptr));
+  int32_t* row_ptr = alloc<int32_t>(N + B);
+  int32_t* col = alloc<int32_t>(nnz[B]);
+  float* val = alloc<float>(nnz[B]);
+  int32_t* edges = alloc<int32_t>(2 * eoff[B]);
+  float* edge_w = alloc<float>(eoff[B]);
+  float* gval = alloc<float>(nnz[B]);
+  float* gedge_w = alloc<float>(eoff[B]);
+  CHECK(mi_build_laplacian(ctx, &M.blk, M.prim_off.data(), prims, 3, nnz.data(), eoff.data(),
+                           MI_W_COMBINATORIAL, coords, nullptr, row_ptr, col, val, edges, edge_w,
+                           lw, lws, nullptr));
+  CHECK(mi_laplacian_values(ctx, &M.blk, nnz.data(), eoff.data(), MI_W_INV_DIST, coords, nullptr,
+                            row_ptr, col, edges, gval, gedge_w, nullptr, nullptr));
+  step("tracking: three lanes, capture and replays");
+  mi_oi_params q = params();
+  size_t ows = 0;
+  CHECK(mi_oi_workspace_size(ctx, &M.blk, &q, &ows));
+  char* ow = alloc<char>(ows);
+  float* V = alloc<float>(U);
+  double* ritz = alloc<double>(tp);
+  double* resid = alloc<double>(tp);
+  int32_t* iters = alloc<int32_t>(B);
+  int32_t* status = alloc<int32_t>(B);
+  std::vector<float> ref(U), cur(U);
+  for (int rep = 0; rep < 3; ++rep) {
+    CHECK(mi_oi_track(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
+                      iters, status, ow, ows, nullptr));
+    EXPECT(hipDeviceSynchronize() == hipSuccess, "sync after tracking");
+    EXPECT(hipMemcpy(rep ? cur.data() : ref.data(), V, U * sizeof(float),
+                     hipMemcpyDeviceToHost) == hipSuccess, "copy V");
+    if (rep) EXPECT(std::memcmp(ref.data(), cur.data(), U * sizeof(float)) == 0,
+                    "replays reproduce the first result bit for bit");
+  }
+  std::vector<int32_t> hs(B);
+  EXPECT(hipMemcpy(hs.data(), status, B * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess,
+         "copy status");
+  for (int b = 0; b < B; ++b)
+    EXPECT((hs[b] & (MI_BLOCK_NOT_PD | MI_BLOCK_NONFINITE | MI_BLOCK_NOCONV)) == 0, "status");
+  int32_t nw = 0;
+  CHECK(mi_oi_tuning(ctx, nullptr, 0, &nw));
+  EXPECT(nw == 9, "one wave per level and lane");
+  std::vector<int32_t> tune(4 * nw);
+  CHECK(mi_oi_tuning(ctx, tune.data(), nw, &nw));
+  step("forced SpMM variant (plan rebuilt), then the autotuner again");
+  CHECK(mi_oi_force_spmm(ctx, 3));
+  CHECK(mi_oi_track(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
+                    iters, status, ow, ows, nullptr));
+  CHECK(mi_oi_force_spmm(ctx, -1));
+  CHECK(mi_oi_track(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
+                    iters, status, ow, ows, nullptr));
+  step("event timer");
+  CHECK(mi_ctx_set_timing(ctx, 1));
+  CHECK(mi_oi_track(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
+                    iters, status, ow, ows, nullptr));
+  std::vector<double> kms(MI_K_COUNT);
+  std::vector<int64_t> kn(MI_K_COUNT);
+  CHECK(mi_ctx_kernel_times(ctx, kms.data(), kn.data()));
+  EXPECT(kn[MI_K_SPMM] > 0, "timed SpMM launches");
+  CHECK(mi_ctx_set_timing(ctx, 0));
+  step("per-block path");
+  CHECK(mi_oi_track_per_block(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz,
+                              resid, iters, status, ow, ows, nullptr));
+  CHECK(mi_oi_track(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
+                    iters, status, ow, ows, nullptr));
+  step("choose_c, projection, reconstruction");
+  int32_t* cmax = upload(M.c);
+  int32_t* cc = alloc<int32_t>(B);
+  double* metric = alloc<double>(tp);
+  size_t cws = 0;
+  CHECK(mi_choose_c_workspace_size(ctx, &M.blk, &cws));
+  char* cw = alloc<char>(cws);
+  CHECK(mi_choose_c(ctx, &M.blk, cmax, 1e-3, 1e-3, V, ritz, coords, row_ptr, col, gval,
+                    nnz.data(), cc, metric, cw, cws, nullptr));
+  size_t ews = 0;
+  CHECK(mi_encdec_workspace_size(ctx, &M.blk, MI_FP32, &ews));
+  char* ew = alloc<char>(ews);
+  float* E = alloc<float>(3 * tp);
+  float* E2 = alloc<float>(3 * tp);
+  float* Xr = alloc<float>(3 * N);
+  CHECK(mi_project(ctx, &M.blk, MI_FP32, cc, V, coords, E, ew, ews, nullptr));
+  CHECK(mi_project_noalloc(ctx, &M.blk, MI_FP32, cc, V, coords, E2, nullptr));
+  CHECK(mi_reconstruct(ctx, &M.blk, MI_FP32, cc, V, E, Xr, nullptr));
+  std::vector<float> e1(3 * tp), e2(3 * tp);
+  EXPECT(hipMemcpy(e1.data(), E, e1.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+             hipMemcpy(e2.data(), E2, e2.size() * 4, hipMemcpyDeviceToHost) == hipSuccess,
+         "copy E");
+  EXPECT(std::memcmp(e1.data(), e2.data(), e1.size() * 4) == 0, "allocation-free projection");
+  step("adjoint of the chained tracking");
+  mi_oi_params qa = params();
+  qa.autotune = 0;
+  size_t aws = 0;
+  CHECK(mi_adjoint_workspace_size(ctx, &M.blk, &qa, nnz.data(), &aws));
+  char* aw = alloc<char>(aws);
+  double* Xbar = alloc<double>(3 * N);
+  double* wbar = alloc<double>(eoff[B]);
+  CHECK(mi_encdec_adjoint(ctx, &M.blk, &qa, MI_W_COMBINATORIAL, row_ptr, col, val, nnz.data(),
+                          edges, eoff.data(), nullptr, coords, cc, coords, Xbar, wbar, aw, aws,
+                          nullptr));
+  EXPECT(hipDeviceSynchronize() == hipSuccess, "sync after the adjoint");
+  std::vector<double> xb(3 * N);
+  EXPECT(hipMemcpy(xb.data(), Xbar, xb.size() * 8, hipMemcpyDeviceToHost) == hipSuccess, "Xbar");
+  for (double v : xb) EXPECT(std::isfinite(v), "finite Xbar");
+  step("teardown");
+  CHECK(mi_ctx_destroy(ctx));
+  for (void* p : {(void*)prims, (void*)coords, (void*)lw, (void*)row_ptr, (void*)col, (void*)val,
+                  (void*)edges, (void*)edge_w, (void*)gval, (void*)gedge_w, (void*)ow, (void*)V,
+                  (void*)ritz, (void*)resid, (void*)iters, (void*)status, (void*)cmax, (void*)cc,
+                  (void*)metric, (void*)cw, (void*)ew, (void*)E, (void*)E2, (void*)Xr, (void*)aw,
+                  (void*)Xbar, (void*)wbar})
+    EXPECT(hipFree(p) == hipSuccess, "free");
+  return 0;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const bool gpu = argc > 1 && std::strcmp(argv[1], "gpu") == 0;
+  Mesh M;
+  if (host_checks(M)) return 1;
+  if (gpu && gpu_checks(M)) return 1;
+  std::printf("ok\n");
+  return 0;
+}

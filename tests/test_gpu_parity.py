@@ -290,8 +290,8 @@ def test_spmm_variants_agree(ctx, width):
     """Every launch shape of the wavefront-per-row SpMM (forced on the plan in
     turn) gives the same tracked subspaces and Ritz values on a wave of
     independent disks of one tracked width, and each meets the oracle:
-    variants 0-6 bit for bit, 7-10 (diagonal folded into the row's own
-    term) bit for bit among themselves and within FP32 rounding of 0."""
+    variants 0-6 bit for bit, 7-10 (the diagonal term last in each row's
+    sum) bit for bit among themselves and within FP32 rounding of 0."""
     bs = W.disk_blocks(n_blocks=3, n_min=max(width + 40, 300), n_max=2400, c_max=width - 32,
                        p_max=width, key=(36, width))
     bs.p = np.full(3, width)

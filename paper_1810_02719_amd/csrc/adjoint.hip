@@ -579,8 +579,12 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
 
     // Ybar = (I - B B^T) Bbar R^-T for the basis B = Y R^-1 (span-only loss)
     auto cholqr_adj = [&](const T* Bm, const T* Bbar, const T* R, T* out) {
-      launch_gram<T>(w.gt, w.n_gt, w.tall, Bm, Bm, Bbar, gpart, s);
-      launch_gram_reduce(w.gr, w.n_gr, w.small, gpart, true, M, Hm, s);
+      if (w.gram_direct) {
+        launch_gram_direct<T>(w.gt, w.n_gt, w.tall, w.small, Bm, Bm, Bbar, M, Hm, s);
+      } else {
+        launch_gram<T>(w.gt, w.n_gt, w.tall, Bm, Bm, Bbar, gpart, s);
+        launch_gram_reduce(w.gr, w.n_gr, w.small, gpart, true, M, Hm, s);
+      }
       hipLaunchKernelGGL(k_adj_prep<T>, dim3(nbw, gsm), dim3(256), 0, s, A.dev, ids, Hm, R, RT,
                          MRT);
       launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, Bm, w.small, MRT, w.tall, Tm, w.nch, s);

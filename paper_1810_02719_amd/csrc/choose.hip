@@ -30,6 +30,7 @@ struct CcPlan {
   int n_gt = 0;
   GramReduce* gr = nullptr;
   int n_gr = 0;
+  bool gram_direct = false;  // no super-tile split: the Gram writes M itself
   size_t z_off = 0, gx_off = 0, ef_off = 0, m_off = 0, part_off = 0, nrm_off = 0, total = 0;
   ~CcPlan() {
     if (arena) (void)hipFree(arena);
@@ -271,6 +272,7 @@ static mi_status cc_plan(mi_ctx* ctx, const HostBlocks& hb, const std::vector<in
   P->n_gt = (int)gt.size();
   P->gr = reinterpret_cast<GramReduce*>(a + orr);
   P->n_gr = (int)gr.size();
+  P->gram_direct = gram_unsplit(gr);
   // spmm tile table kept right after the reduce table
   static_assert(sizeof(SpmmTile) == 8, "");
   // workspace layout
@@ -364,8 +366,12 @@ mi_status mi_choose_c(mi_ctx* ctx, const mi_blocks* blk, const int32_t* c_max, d
   hipLaunchKernelGGL(k_gl_coords, dim3(hb.B), dim3(256), 0, s, P->blocks, gl_row_ptr, gl_col,
                      gl_val, X, GX, nrm);
   hipLaunchKernelGGL(k_proj_ef, dim3(hb.B), dim3(256), 0, s, P->blocks, U, Z, X, GX, EF);
-  launch_gram<float>(P->gt, P->n_gt, P->tall, Z, Z, nullptr, part, s);
-  launch_gram_reduce(P->gr, P->n_gr, P->small, part, false, M, nullptr, s);
+  if (P->gram_direct) {
+    launch_gram_direct<float>(P->gt, P->n_gt, P->tall, P->small, Z, Z, nullptr, M, nullptr, s);
+  } else {
+    launch_gram<float>(P->gt, P->n_gt, P->tall, Z, Z, nullptr, part, s);
+    launch_gram_reduce(P->gr, P->n_gr, P->small, part, false, M, nullptr, s);
+  }
   hipLaunchKernelGGL(k_choose, dim3(hb.B), dim3(256), 0, s, P->blocks, c_max, EF, M, nrm, ritz,
                      target, g_min, c_out, metric_out);
   MI_TRY_HIP(hipGetLastError());

@@ -639,11 +639,15 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 }
 inline dim3 xcd_grid(int ntiles) { return dim3(NUM_XCD * ceil_div(ntiles, NUM_XCD)); }
 
+// With G non-null the tile is the whole super-tile (no split over row
+// chunks): its upper triangle and the mirror go straight into the p x p
+// outputs G (and H) described by outsets, and no partial is written.
 template <typename T, bool DUAL>
 __global__ void __launch_bounds__(256)
     k_gram(const GramTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
            const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ Wm,
-           double* __restrict__ part) {
+           double* __restrict__ part, const MatDesc* __restrict__ outsets, double* __restrict__ G,
+           double* __restrict__ H) {
   typedef typename VecOf<T>::type V;
   constexpr int W = VecOf<T>::W;
   constexpr int RC = 32;                            // rows per staged chunk
@@ -711,8 +715,35 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   const int kk = kq, mm = mi;
-  double* out = part + int64_t(ti) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
   const int n = mm;
+  if (G) {
+    const MatDesc o = outsets[t.set];
+    auto put = [&](double* M, int li, int lj, double v) {
+      const int gi = t.I0 + li, gj = t.J0 + lj;
+      if (gi <= gj && gj < o.ld) {
+        M[o.off + int64_t(gi) * o.ld + gj] = v;
+        M[o.off + int64_t(gj) * o.ld + gi] = v;
+      }
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = kk + 4 * q;  // FP64 result layout
+      const int i0 = wi * 32 + m, i1 = i0 + 16;
+      const int j0 = wj * 32 + n, j1 = j0 + 16;
+      put(G, i0, j0, acc00[q]);
+      put(G, i0, j1, acc01[q]);
+      put(G, i1, j0, acc10[q]);
+      put(G, i1, j1, acc11[q]);
+      if (DUAL) {
+        put(H, i0, j0, w00[q]);
+        put(H, i0, j1, w01[q]);
+        put(H, i1, j0, w10[q]);
+        put(H, i1, j1, w11[q]);
+      }
+    }
+    return;
+  }
+  double* out = part + int64_t(ti) * (DUAL ? 2 : 1) * GRAM_TILE * GRAM_TILE;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int m = kk + 4 * q;  // FP64 result layout
@@ -857,15 +888,40 @@ void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T
   if (ntiles <= 0) return;
   if (W)
     hipLaunchKernelGGL((k_gram<T, true>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
-                       W, part);
+                       W, part, nullptr, nullptr, nullptr);
   else
     hipLaunchKernelGGL((k_gram<T, false>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
-                       W, part);
+                       W, part, nullptr, nullptr, nullptr);
 }
 template void launch_gram<float>(const GramTile*, int, const MatDesc*, const float*, const float*,
                                  const float*, double*, hipStream_t);
 template void launch_gram<double>(const GramTile*, int, const MatDesc*, const double*,
                                   const double*, const double*, double*, hipStream_t);
+
+template <typename T>
+void launch_gram_direct(const GramTile* tiles, int ntiles, const MatDesc* sets,
+                        const MatDesc* outsets, const T* A, const T* B, const T* W, double* G,
+                        double* H, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (W)
+    hipLaunchKernelGGL((k_gram<T, true>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
+                       W, nullptr, outsets, G, H);
+  else
+    hipLaunchKernelGGL((k_gram<T, false>), dim3(ntiles), dim3(256), 0, s, tiles, sets, A, B,
+                       W, nullptr, outsets, G, H);
+}
+template void launch_gram_direct<float>(const GramTile*, int, const MatDesc*, const MatDesc*,
+                                        const float*, const float*, const float*, double*,
+                                        double*, hipStream_t);
+template void launch_gram_direct<double>(const GramTile*, int, const MatDesc*, const MatDesc*,
+                                         const double*, const double*, const double*, double*,
+                                         double*, hipStream_t);
+
+bool gram_unsplit(const std::vector<GramReduce>& jobs) {
+  for (const GramReduce& g : jobs)
+    if (g.count != 1) return false;
+  return true;
+}
 
 // Sum the split-K partials of one super-tile in chunk order (deterministic)
 // and write the upper triangle and its mirror.  GRAM_RED_SPLIT workgroups

@@ -100,6 +100,15 @@ void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T
 
 void launch_gram_reduce(const GramReduce* jobs, int njobs, const MatDesc* outsets,
                         const double* part, bool dual, double* G, double* H, hipStream_t s);
+// The same products written straight into G (and H for the dual product)
+// when no super-tile is split over row chunks (every reduce job has one
+// partial: gram_unsplit), with no partials and no reduction.  FP32 and
+// FP64 slabs.
+template <typename T>
+void launch_gram_direct(const GramTile* tiles, int ntiles, const MatDesc* sets,
+                        const MatDesc* outsets, const T* A, const T* B, const T* W, double* G,
+                        double* H, hipStream_t s);
+bool gram_unsplit(const std::vector<GramReduce>& jobs);
 
 // Out = A S row tile by row tile; A may be a BF16 slab with S and the MFMA in
 // FP32 (TA = bf16, T = float).

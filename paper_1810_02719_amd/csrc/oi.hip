@@ -810,6 +810,7 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
   if (spmm_force >= 0 && wt->epl > 0) wt->spmm_var = spmm_force;
   wt->gram_target = tune ? tune->gram_target : GRAM_TARGET;
   gram_tables(h->tall, true, &h->gt, &h->gr, wt->gram_target);
+  wt->gram_direct = prm.precision != MI_BF16_IN && gram_unsplit(h->gr);
   gram_tables(h->small, false, &h->gts, &h->grs);
   row_tables(h->tall, wt->nch, &h->rt);
   row_tables(h->small, wt->nchs, &h->rts);
@@ -1018,7 +1019,15 @@ static void autotune_waves(const OiPlan& P, char* ws, hipStream_t s, const int32
       DevTable<GramTile> dgt(gt);
       DevTable<GramReduce> dgr(gr);
       if (!dgt.p || !dgr.p) continue;
+      const bool direct = !std::is_same<T, bf16>::value && gram_unsplit(gr);
       const float t = time_calls(s, [&] {
+        if constexpr (!std::is_same<T, bf16>::value) {
+          if (direct) {
+            launch_gram_direct<T>(dgt.p, (int)gt.size(), w.tall, w.small, y0, y0, nullptr, G,
+                                  nullptr, s);
+            return;
+          }
+        }
         launch_gram<T>(dgt.p, (int)gt.size(), w.tall, y0, y0, nullptr, part, s);
         launch_gram_reduce(dgr.p, (int)gr.size(), w.small, part, false, G, nullptr, s);
       });
@@ -1210,6 +1219,22 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                          w.from_pred ? 1 : 0, doi->c_max, doi->t_max, doi->c, doi_done, doi->traj,
                          V);
     }
+    // Gram of the wave's slabs into G (and H for the dual product)
+    auto gram = [&](const T* GA, const T* GW, double* Go, double* Ho) {
+      if constexpr (!std::is_same<T, bf16>::value) {
+        if (w.gram_direct) {
+          KScope k_(a.tm, MI_K_GRAM, s);
+          launch_gram_direct<T>(w.gt, w.n_gt, w.tall, w.small, GA, GA, GW, Go, Ho, s);
+          return;
+        }
+      }
+      {
+        KScope k_(a.tm, MI_K_GRAM, s);
+        launch_gram<T>(w.gt, w.n_gt, w.tall, GA, GA, GW, part, s);
+      }
+      KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
+      launch_gram_reduce(w.gr, w.n_gr, w.small, part, GW != nullptr, Go, Ho, s);
+    };
     auto chol = [&](float* s32) {
       KScope k_(a.tm, MI_K_CHOL, s);
       launch_chol_blk(w.sd, w.nb, G, Wk, Rinv, s32, a.status, w.max_ld, P.lds_max, s);
@@ -1219,14 +1244,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       // than its predecessor and can be badly conditioned (and a seeded
       // start is not orthonormal); one Cholesky-QR before the first filter
       // pass keeps the filtered basis of full rank in FP32.
-      {
-        KScope k_(a.tm, MI_K_GRAM, s);
-        launch_gram<T>(w.gt, w.n_gt, w.tall, X, X, nullptr, part, s);
-      }
-      {
-        KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
-        launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
-      }
+      gram(X, nullptr, G, nullptr);
       chol(dbl ? nullptr : S32);
       const TS* Sr = dbl ? reinterpret_cast<const TS*>(Rinv) : reinterpret_cast<const TS*>(S32);
       KScope k_(a.tm, MI_K_ROWMUL, s);
@@ -1333,14 +1351,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         ++jp;
         if (pass < w.passes - 1) {
           // span-preserving Cholesky-QR between passes
-          {
-            KScope k_(a.tm, MI_K_GRAM, s);
-            launch_gram<T>(w.gt, w.n_gt, w.tall, slab[ycur], slab[ycur], nullptr, part, s);
-          }
-          {
-            KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
-            launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
-          }
+          gram(slab[ycur], nullptr, G, nullptr);
           chol(dbl ? nullptr : S32);
           if (rec) keep_mats(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, false);
           int dst = -1;
@@ -1368,14 +1379,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
                        L.coef_stride, w.m, s, w.epl, w.spmm_var);
       }
-      {
-        KScope k_(a.tm, MI_K_GRAM, s);
-        launch_gram<T>(w.gt, w.n_gt, w.tall, Y, Y, Wm, part, s);
-      }
-      {
-        KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
-        launch_gram_reduce(w.gr, w.n_gr, w.small, part, true, G, H, s);
-      }
+      gram(Y, Wm, G, H);
       // T1 = H Rinv
       if (!rr_now) {
         // intermediate iteration: Cholesky-QR of Y; the filter's lower bound
@@ -1433,12 +1437,10 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
       }
       {
+        // p x p: never split over rows
         KScope k_(a.tm, MI_K_GRAM_SMALL, s);
-        launch_gram<double>(w.gts, w.n_gts, w.small, Rinv, T1, nullptr, part, s);
-      }
-      {
-        KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
-        launch_gram_reduce(w.grs, w.n_grs, w.small, part, false, Am, nullptr, s);
+        launch_gram_direct<double>(w.gts, w.n_gts, w.small, w.small, Rinv, T1, nullptr, Am,
+                                   nullptr, s);
       }
       const bool use_tri = prm.eig == MI_EIG_TRIDIAG && tri_eig_supported(w.max_ld);
       if (use_tri) {
@@ -1531,14 +1533,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         }
         // final Cholesky-QR: V = Vtmp R^-1 (upper triangular: keeps the span of
         // every leading column set, hence the Ritz order)
-        {
-          KScope k_(a.tm, MI_K_GRAM, s);
-          launch_gram<T>(w.gt, w.n_gt, w.tall, dstV, dstV, nullptr, part, s);
-        }
-        {
-          KScope k_(a.tm, MI_K_GRAM_REDUCE, s);
-          launch_gram_reduce(w.gr, w.n_gr, w.small, part, false, G, nullptr, s);
-        }
+        gram(dstV, nullptr, G, nullptr);
         chol(dbl ? nullptr : S32);
         {
           KScope k_(a.tm, MI_K_ROWMUL, s);

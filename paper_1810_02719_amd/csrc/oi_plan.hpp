@@ -23,6 +23,7 @@ struct WaveTables {
   int epl = 0;  // elements per lane of the row-per-wavefront SpMM (0: generic kernel)
   int spmm_var = -1;  // SpMM variant (SPMM_VAR_*; -1: the default for epl)
   int gram_target = GRAM_TARGET;  // workgroups of the split Gram launch
+  bool gram_direct = false;        // no super-tile split: the Gram writes G itself
   int lane = 0;  // stream lane: the waves of one lane form one dependency chain
   std::vector<MatDesc> tall_host;  // host copy of `tall` (for retuning)
   // device tables

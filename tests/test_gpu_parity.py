@@ -1400,7 +1400,7 @@ def _c3_target():
 def test_c3_full_size_batched_uneven(ctx):
     """1,024 independent Delaunay disks of 500-5,000 vertices (2.8M vertices),
     p_b = min(320, n_b), c_max = 256, in the benchmark's launch configuration
-    (seeded MI_RANDOM starts, T = 6 iterations of two degree-12 passes, one
+    (seeded MI_RANDOM starts, T = 5 iterations of two degree-12 passes, one
     wave, autotuned shapes).  On the seeded 64-block sample plus the smallest
     and largest disk: the kept space at c_max within sin 1e-5 of the
     oracle's (a block whose cut is a near-tie, relative gap below 1e-3, is
@@ -1415,7 +1415,7 @@ def test_c3_full_size_batched_uneven(ctx):
     blocks = mis.Blocks(bs.n, p=up.fl["p"], ld=up.fl["ld"])
     Lp = up.laplacian(ctx)
     gl = up.laplacian(ctx, mis.MI_W_INV_DIST)
-    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_RANDOM, seed=181002719, T0=6, m0=12,
+    prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_RANDOM, seed=181002719, T0=5, m0=12,
                        passes0=2, adapt=1, a_mode=mis.MI_A_WEYL, a_value=1.0, autotune=1)
     V, ritz, st = mis.oi_track(ctx, blocks, Lp, prm)
     cmax = torch.from_numpy(np.asarray(bs.c, np.int32)).cuda()
@@ -1454,11 +1454,15 @@ def test_c3_full_size_batched_uneven(ctx):
         if cg != co:  # only a curve value at the target within rounding may differ
             k = min(cg, co) - 1
             assert abs(curve[k] - target) < 1e-4 * target, (b, cg, co, curve[k], target)
-        ang_c = S.sin_theta_max(U[:, :cg], Vb[:, :cg])
+        # the snap g_min = 1e-3 keeps chosen cuts below c_max off near-ties;
+        # a choice of c_max at a near-tie is checked at the end of its
+        # cluster, like the kept space above
+        cut_c = cut if cg == cm else cg
+        ang_c = S.sin_theta_max(U[:, :cut_c], Vb[:, :cut_c])
         print(f"block {b} (n {n[b]}): sin angle {ang:.2e} at c {cut}, {ang_c:.2e} at the "
-              f"chosen c {cg} (oracle {co})")
+              f"chosen c {cg} (oracle {co}{', checked at ' + str(cut_c) if cut_c != cg else ''})")
         assert ang <= ANGLE_FP32, (b, ang, cut)
-        assert ang_c <= ANGLE_FP32, (b, ang_c, cg)
+        assert ang_c <= ANGLE_FP32, (b, ang_c, cg, cut_c)
     print(f"worst sin angle {worst:.2e}; near-ties at c_max (block, c, cluster end, gap): {ties}")
 
 

@@ -17,10 +17,11 @@ before the timed region (principal angle <= 1e-5).
 A secondary line covers the static block sequence (displaced level-7
 icosphere, 100 blocks warm-started along a BFS order of the blocks, c = 100,
 p = 192) and the extras measured on it (merge, codec, quality, dynamic walk,
-R^z).
+R^z); a third covers the 1M-vertex precision workload with FP32 and with
+BF16 working slabs.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-secondary]
+                    [--no-secondary] [--no-precision] [--only-precision]
 
 Prints one JSON line.
 """
@@ -43,6 +44,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the static block sequence and its extras")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 1M-vertex FP32 / BF16 precision leg")
+    ap.add_argument("--only-precision", action="store_true",
+                    help="run the 1M-vertex precision leg alone (for profilers)")
     ap.add_argument("--cpu-sample-blocks", type=int, default=60)
     ap.add_argument("--parity-blocks", type=int, default=8,
                     help="sampled disks checked against the oracle before timing")
@@ -472,11 +477,112 @@ def main():
         print("bench.py runs on one GPU only: the workload is one GPU's share and no "
               "multi-GPU path is built (see DESIGN.md, sharding).", file=sys.stderr)
         return 2
+    if args.only_precision:
+        print(json.dumps({"precision": c4_precision(args)}))
+        return 0
     out = c3_headline(args)
     if not args.no_secondary and not args.profile_only:
         out["secondary"] = c2_secondary(args)
+    if not args.no_precision and not args.profile_only:
+        out["precision"] = c4_precision(args)
     print(json.dumps(out))
     return 0
+
+
+def c4_precision(args):
+    """The 1M-vertex precision workload: a displaced geodesic sphere of
+    998,562 vertices in 100 blocks of about 10k vertices, c = 200, p = 256,
+    one wave of independent blocks from seeded starts (12 iterations of two
+    degree-10 passes), tracked once with FP32 slabs and once with BF16
+    working slabs (MI_BF16_IN).  Per precision: the tracking's time (the mean
+    of 3 graph replays after the plan), the SpMM's event-timed launches and
+    their roofline at the slab's element size, and the smallest and the
+    median block against the FP64 oracle (principal angle at c, and the
+    reconstruction error)."""
+    import torch
+
+    import paper_1810_02719_amd as mis
+    from oracle import laplacian as lap
+    from oracle import spectral as S
+    from synth import workloads as W
+    dev = "cuda:0"
+    t0 = time.time()
+    bs = W.geodesic_blocks()
+    fl = W.flatten(bs)
+    blocks = mis.Blocks(bs.n, p=fl["p"], ld=fl["ld"])  # independent blocks: one wave
+    prims = torch.from_numpy(np.ascontiguousarray(fl["prims"].reshape(-1))).to(dev)
+    coords = torch.from_numpy(np.ascontiguousarray(fl["coords"].reshape(-1))).to(dev)
+    gen_s = time.time() - t0
+    ctx = mis.Context(0)
+    L = mis.build_laplacian(ctx, blocks, fl["prim_off"], prims, 3, coords, mis.MI_W_COMBINATORIAL)
+    c = torch.from_numpy(np.asarray(bs.c, np.int32)).to(dev)
+    n = np.asarray(blocks.n)
+    nverts = int(blocks.v_off[-1])
+    if args.traffic_calib and args.only_precision:
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    ids = [int(np.argmin(n)), int(np.argsort(n)[n.size // 2])]  # smallest and median block
+    orc = {}
+    if not args.profile_only:
+        for b in ids:
+            e = lap.canonical_edges(bs.faces[b], int(n[b]))
+            lam, U = S.eigh_lowest(lap.laplacian_dense(int(n[b]), e, np.ones(len(e))),
+                                   int(bs.p[b]) + 1)
+            orc[b] = U
+    out = {"workload": "geodesic316_998562v_100blocks_c200_p256", "vertices": nverts,
+           "blocks": int(blocks.n_blocks), "T": 12, "m": 10, "passes": 2, "input_gen_s": gen_s}
+    for name, prec, es in (("fp32", mis.MI_FP32, 4), ("bf16", mis.MI_BF16_IN, 2)):
+        prm = mis.OiParams(precision=prec, warm=mis.MI_RANDOM, seed=SEED, T0=12, m0=10,
+                           passes0=2, adapt=1, a_mode=mis.MI_A_WEYL, a_value=1.0, autotune=1)
+        V = torch.empty(int(blocks.u_off[-1]), dtype=torch.float32, device=dev)
+        ritz = torch.zeros(int(blocks.t_off[-1]), dtype=torch.float64, device=dev)
+        status = torch.zeros(blocks.n_blocks, dtype=torch.int32, device=dev)
+        mis.oi_track(ctx, blocks, L, prm, V=V, ritz=ritz, status=status)  # plan and capture
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        reps = 1 if args.profile_only else 3
+        ev0.record()
+        for _ in range(reps):
+            mis.oi_track(ctx, blocks, L, prm, V=V, ritz=ritz, status=status)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        ctx.set_timing(True)
+        mis.oi_track(ctx, blocks, L, prm, V=V, ritz=ritz, status=status)
+        torch.cuda.synchronize()
+        kt = ctx.kernel_times()
+        ctx.set_timing(False)
+        mis.oi_track(ctx, blocks, L, prm, V=V, ritz=ritz, status=status)  # graph replay again
+        torch.cuda.synchronize()
+        rec = {"ms_per_tracking": ms, "vertices_per_s": nverts / (ms * 1e-3),
+               "block_status_nonzero": int((status.cpu().numpy() != 0).sum()),
+               "launch_shapes": [list(t) for t in ctx.tuning()],
+               "roofline_spmm": roofline(kt, bs, blocks, L, prm, "spmm", tag="sphere1m_" + name,
+                                         es=es, levels=np.zeros(len(n), np.int64))}
+        if orc:
+            Xr = mis.reconstruct(ctx, blocks, c, V, mis.project(ctx, blocks, c, V, coords))
+            torch.cuda.synchronize()
+            Vh = V.double().cpu().numpy()
+            Xh = Xr.double().cpu().numpy().reshape(-1, 3)
+            rows = []
+            for b in ids:
+                nb, ld, cb = int(n[b]), int(blocks.ld[b]), int(bs.c[b])
+                Vb = Vh[int(blocks.u_off[b]):int(blocks.u_off[b + 1])].reshape(nb, ld)
+                X = bs.coords[b].astype(np.float32).astype(np.float64)
+                v0 = int(blocks.v_off[b])
+                rows.append({"block": b, "n": nb,
+                             "sin_angle": S.sin_theta_max(orc[b][:, :cb], Vb[:, :cb]),
+                             "recon_rel_err": S.rel_error(Xh[v0:v0 + nb],
+                                                          S.encode_decode(orc[b][:, :cb], X))})
+            rec["sample_parity"] = rows
+        out[name] = rec
+    ctx.close()
+    return out
 
 
 def c2_secondary(args):
@@ -631,6 +737,10 @@ CSRC = os.path.join(HERE, "paper_1810_02719_amd", "csrc")
 TRAFFIC = {
     ("spmm", "disks"): (os.path.join(HERE, "profiles", "spmm_disks1024_traffic.json"),
                         os.path.join(CSRC, "dense.hip")),
+    ("spmm", "sphere1m_fp32"): (os.path.join(HERE, "profiles", "spmm_sphere1m_fp32_traffic.json"),
+                                os.path.join(CSRC, "dense.hip")),
+    ("spmm", "sphere1m_bf16"): (os.path.join(HERE, "profiles", "spmm_sphere1m_bf16_traffic.json"),
+                                os.path.join(CSRC, "dense.hip")),
 }
 MI_RANDOM = 2  # seeded start mode of mi_oi_params.warm
 
@@ -663,21 +773,24 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector and MFMA (dense)
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 
 
-def roofline(ktimes, bs, blocks, L, prm, dom=None, c_arr=None, tag="icosphere"):
+def roofline(ktimes, bs, blocks, L, prm, dom=None, c_arr=None, tag="icosphere", es=4,
+             levels=None):
     """Roofline of a kernel class of the step (default: the dominant one, the
     largest event-timed total).  The algorithmic bytes or flops of one step's
     launches of that class (the method's own traffic, not what the caches
     make of it) over the event-timed total.  c_arr: the kept sizes the step
-    used (default: the block set's c)."""
+    used (default: the block set's c); levels: the dependency level of
+    every block as tracked (default: the block set's; all zero when the
+    blocks run as independent blocks in one wave)."""
     if dom is None:
         dom = max(ktimes, key=lambda k: ktimes[k][0])
     ms, launches = ktimes[dom]
-    levels = np.asarray(bs.level)
+    levels = np.asarray(bs.level if levels is None else levels)
     n = np.asarray(blocks.n, np.int64)
     ld = np.asarray(blocks.ld, np.int64)
     p = np.asarray(blocks.p, np.int64)
     nnz = np.diff(np.asarray(L.nnz_off, np.int64))
-    es = 4  # FP32 slab
+    # es: bytes per slab element (4 for FP32, 2 for BF16 working slabs)
     out = {"kernel": dom, "launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
            "traffic": None}
     if dom == "spmm":

@@ -304,6 +304,63 @@ __device__ inline void st_nt<bf16>(bf16* p, bf16 v) {
   __builtin_nontemporal_store(v.u, &p->u);
 }
 
+// A lane's EPL elements of a row (consecutive, or strided by 64 with
+// STRIDED), widened to the arithmetic type.  Two or four consecutive BF16
+// values move as one 4- or 8-byte access (element-wise 2-byte accesses,
+// non-temporal ones especially, cost more than the bytes they move).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+template <typename T, int EPL, bool STRIDED, bool NT>
+__device__ __forceinline__ void row_load(const T* p, typename Acc<T>::type* v) {
+  constexpr int ES = STRIDED ? 64 : 1;
+  if constexpr (std::is_same<T, bf16>::value && !STRIDED && EPL == 4) {
+    const u32x2 w = NT ? __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p))
+                       : *reinterpret_cast<const u32x2*>(p);
+    v[0] = __uint_as_float(w.x << 16);
+    v[1] = __uint_as_float(w.x & 0xFFFF0000u);
+    v[2] = __uint_as_float(w.y << 16);
+    v[3] = __uint_as_float(w.y & 0xFFFF0000u);
+  } else if constexpr (std::is_same<T, bf16>::value && !STRIDED && EPL == 2) {
+    const uint32_t w = NT ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p))
+                          : *reinterpret_cast<const uint32_t*>(p);
+    v[0] = __uint_as_float(w << 16);
+    v[1] = __uint_as_float(w & 0xFFFF0000u);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) v[e] = Acc<T>::load(NT ? ld_nt(p + e * ES) : p[e * ES]);
+  }
+}
+template <typename T, int EPL, bool STRIDED, bool NT>
+__device__ __forceinline__ void row_store(T* p, const typename Acc<T>::type* v) {
+  constexpr int ES = STRIDED ? 64 : 1;
+  if constexpr (std::is_same<T, bf16>::value && !STRIDED && (EPL == 2 || EPL == 4)) {
+    uint32_t w[2];
+#pragma unroll
+    for (int h = 0; h < EPL / 2; ++h)
+      w[h] = uint32_t(f32_to_bf16(v[2 * h]).u) | (uint32_t(f32_to_bf16(v[2 * h + 1]).u) << 16);
+    if constexpr (EPL == 4) {
+      const u32x2 x = {w[0], w[1]};
+      if (NT)
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x2*>(p));
+      else
+        *reinterpret_cast<u32x2*>(p) = x;
+    } else {
+      if (NT)
+        __builtin_nontemporal_store(w[0], reinterpret_cast<uint32_t*>(p));
+      else
+        *reinterpret_cast<uint32_t*>(p) = w[0];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const T x = Acc<T>::store(v[e]);
+      if (NT)
+        st_nt(p + e * ES, x);
+      else
+        p[e * ES] = x;
+    }
+  }
+}
+
 // One row per wavefront gathering exactly the row's off-diagonal entries
 // (wave-uniform branches, no padded loads), with the product in difference
 // form:
@@ -351,12 +408,9 @@ __global__ void __launch_bounds__(64 * WPG)
   const T* yv = Yin + d.off + l0;
   const int64_t o = d.off + int64_t(r) * d.ld + l0;
   A yin[EPL], ypr[EPL];
-#pragma unroll
-  for (int e = 0; e < EPL; ++e) yin[e] = AC::load(Yin[o + e * ES]);
+  row_load<T, EPL, STRIDED, false>(Yin + o, yin);
   if (Yprev) {
-#pragma unroll
-    for (int e = 0; e < EPL; ++e)
-      ypr[e] = AC::load(NT ? ld_nt(Yprev + o + e * ES) : Yprev[o + e * ES]);
+    row_load<T, EPL, STRIDED, NT>(Yprev + o, ypr);
   } else {
 #pragma unroll
     for (int e = 0; e < EPL; ++e) ypr[e] = (A)0;
@@ -383,9 +437,7 @@ __global__ void __launch_bounds__(64 * WPG)
         if (cj != r) {
           has[u] = true;
           w[u] = wv;
-          const T* src = yv + int64_t(cj) * d.ld;
-#pragma unroll
-          for (int e = 0; e < EPL; ++e) y[u][e] = AC::load(src[e * ES]);
+          row_load<T, EPL, STRIDED, false>(yv + int64_t(cj) * d.ld, y[u]);
         }
       }
     }
@@ -395,15 +447,13 @@ __global__ void __launch_bounds__(64 * WPG)
 #pragma unroll
         for (int e = 0; e < EPL; ++e) acc[e] = fma(w[u], y[u][e] - yin[e], acc[e]);
   }
+  A out[EPL];
 #pragma unroll
   for (int e = 0; e < EPL; ++e) {
     const A ly = fma(rs, yin[e], acc[e]);  // (L Y)_r in difference form
-    const T v = AC::store(alpha * ly + (beta * yin[e] + g3 * ypr[e]));
-    if (NT)
-      st_nt(Yout + o + e * ES, v);
-    else
-      Yout[o + e * ES] = v;
+    out[e] = alpha * ly + (beta * yin[e] + g3 * ypr[e]);
   }
+  row_store<T, EPL, STRIDED, NT>(Yout + o, out);
 }
 
 // The same product with two rows per wavefront: both rows' loads are in

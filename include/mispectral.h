@@ -159,7 +159,14 @@ typedef struct {
                         adjoint (mi_encdec_adjoint) rejects it            */
   int32_t z;         /* power of R (MI_OP_RZ), 1..16                               */
   int32_t cg_iters;  /* conjugate-gradient iterations per solve (MI_OP_RZ)         */
-  int32_t pad_;
+  int32_t persistent; /* 1: every filter pass (MI_OP_CHEB) of a wave whose blocks share
+                        one ld (a multiple of 64 up to 320) runs as one persistent
+                        launch: workgroups claim whole blocks from a device queue,
+                        largest first, and run the pass's m Chebyshev steps on each
+                        with workgroup barriers between steps.  The rows are those
+                        of SPMM variants 7-10 (bit-identical to them); the tuned
+                        SpMM variant still serves the Rayleigh-Ritz product.
+                        Other waves, and 0, launch each step over the whole wave */
   double delta;      /* shift of R (MI_OP_RZ), > 0                                  */
   double tol;        /* 0: fixed iteration counts (T, T0).  > 0: tolerance mode
                         (Section 4 leaves the number of iterations to the user):
@@ -224,6 +231,7 @@ enum {
   MI_K_QUALITY,        /* whole-mesh NMSVE and face-normal angle */
   MI_K_DOI,            /* decisions of the dynamic walk (Alg. 2) */
   MI_K_CG,             /* conjugate-gradient updates of R^z */
+  MI_K_CHEB_PASS,      /* a whole filter pass in one persistent launch (persistent = 1) */
   MI_K_COUNT
 };
 /* Name of a kernel class ("spmm", ...), NULL when out of range. */

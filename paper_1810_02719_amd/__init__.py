@@ -233,12 +233,13 @@ class OiParams:
     delta: float = 1e-3
     tol: float = 0.0  # > 0: tolerance mode (T, T0 cap the iterations)
     seed: int = 0     # seed of the MI_RANDOM start
+    persistent: int = 0  # 1: each filter pass as one persistent launch (block work queue)
 
     def struct(self):
         return L.MiOiParams(self.precision, self.warm, self.T, self.m, self.passes, self.T0,
                             self.m0, self.passes0, self.adapt, self.max_sweeps, self.a_mode, self.rr_every,
                             self.eig, self.autotune, self.a_value, self.b_abs, self.jacobi_tol,
-                            self.op, self.z, self.cg_iters, 0, self.delta, self.tol,
+                            self.op, self.z, self.cg_iters, self.persistent, self.delta, self.tol,
                             int(self.seed) & 0xFFFFFFFFFFFFFFFF)
 
 

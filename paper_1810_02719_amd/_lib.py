@@ -47,7 +47,7 @@ MI_OP_RZ = 1
 KERNEL_CLASSES = ["spmm", "gram", "gram_small", "gram_reduce", "chol", "rowmul", "rowmul_small",
                   "rq_max", "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish", "perm_cast",
                   "setup", "project", "reconstruct", "eig_reduce", "eig_values", "eig_vectors",
-                  "eig_back", "merge", "quantize", "quality", "doi", "cg"]
+                  "eig_back", "merge", "quantize", "quality", "doi", "cg", "cheb_pass"]
 MI_K_COUNT = len(KERNEL_CLASSES)
 
 MI_BLOCK_OK = 0
@@ -75,7 +75,7 @@ class MiOiParams(C.Structure):
                 ("a_mode", C.c_int32), ("rr_every", C.c_int32), ("eig", C.c_int32),
                 ("autotune", C.c_int32), ("a_value", C.c_double),
                 ("b_abs", C.c_double), ("jacobi_tol", C.c_double), ("op", C.c_int32),
-                ("z", C.c_int32), ("cg_iters", C.c_int32), ("pad_", C.c_int32),
+                ("z", C.c_int32), ("cg_iters", C.c_int32), ("persistent", C.c_int32),
                 ("delta", C.c_double), ("tol", C.c_double), ("seed", C.c_uint64)]
 
 

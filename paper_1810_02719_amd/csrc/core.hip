@@ -261,7 +261,7 @@ static const char* const k_class_names[MI_K_COUNT] = {
     "rowmul_small", "rq_max",    "jacobi_init", "jacobi_sweep", "apply_rot", "rr_finish",
     "perm_cast",   "setup",      "project",    "reconstruct",  "eig_reduce", "eig_values",
     "eig_vectors", "eig_back",   "merge",      "quantize",
-    "quality",     "doi",        "cg"};
+    "quality",     "doi",        "cg",         "cheb_pass"};
 
 const char* mi_kernel_class_name(int32_t k) {
   return (k >= 0 && k < MI_K_COUNT) ? k_class_names[k] : nullptr;

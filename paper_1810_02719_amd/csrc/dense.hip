@@ -378,32 +378,16 @@ __device__ __forceinline__ void row_store(T* p, const typename Acc<T>::type* v) 
 // volume per row drops from ceil(nnz/8)*8 rows to nnz - 1 (the seven-entry
 // rows of a triangle mesh: 8 to 6), which is what bounds this kernel once
 // the HBM bytes are right.
-template <typename T, int EPL, bool STRIDED, int WPG, bool NT>
-__global__ void __launch_bounds__(64 * WPG)
-    k_spmm_rowx(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
-                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
-                const int32_t* __restrict__ col, const float* __restrict__ val,
-                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
-                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
-  static_assert(SPMM_ROWS % WPG == 0, "workgroup split");
-  typedef Acc<T> AC;
-  typedef typename AC::type A;
+template <typename T, int EPL, bool STRIDED, bool NT>
+__device__ __forceinline__ void rowx_row(const MatDesc& d, const CsrDesc& c, int r, int lane,
+                                         const int32_t* __restrict__ row_ptr,
+                                         const int32_t* __restrict__ col,
+                                         const float* __restrict__ val, const T* Yin,
+                                         const T* Yprev, T* Yout,
+                                         typename Acc<T>::type alpha, typename Acc<T>::type beta,
+                                         typename Acc<T>::type gamma) {
+  typedef typename Acc<T>::type A;
   constexpr int G = SPMM_GATHER;
-  constexpr int SPLIT = SPMM_ROWS / WPG;
-  constexpr int ES = STRIDED ? 64 : 1;
-  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
-  const int kx = blockIdx.x / NUM_XCD;
-  const int ti = (blockIdx.x % NUM_XCD) * per + kx / SPLIT;
-  if (ti >= ntiles) return;
-  const SpmmTile t = tiles[ti];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const MatDesc d = sets[t.set];
-  const int r = t.row0 + (kx % SPLIT) * WPG + wave;
-  if (r >= d.rows) return;  // wave-uniform
-  const CsrDesc c = csr[t.set];
-  const int lane = threadIdx.x & 63;
-  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
-  const A alpha = (A)cf[0], beta = (A)cf[1], gamma = (A)cf[2];
   const int l0 = STRIDED ? lane : lane * EPL;
   const T* yv = Yin + d.off + l0;
   const int64_t o = d.off + int64_t(r) * d.ld + l0;
@@ -454,6 +438,80 @@ __global__ void __launch_bounds__(64 * WPG)
     out[e] = alpha * ly + (beta * yin[e] + g3 * ypr[e]);
   }
   row_store<T, EPL, STRIDED, NT>(Yout + o, out);
+}
+
+template <typename T, int EPL, bool STRIDED, int WPG, bool NT>
+__global__ void __launch_bounds__(64 * WPG)
+    k_spmm_rowx(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val,
+                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  static_assert(SPMM_ROWS % WPG == 0, "workgroup split");
+  typedef typename Acc<T>::type A;
+  constexpr int SPLIT = SPMM_ROWS / WPG;
+  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int kx = blockIdx.x / NUM_XCD;
+  const int ti = (blockIdx.x % NUM_XCD) * per + kx / SPLIT;
+  if (ti >= ntiles) return;
+  const SpmmTile t = tiles[ti];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MatDesc d = sets[t.set];
+  const int r = t.row0 + (kx % SPLIT) * WPG + wave;
+  if (r >= d.rows) return;  // wave-uniform
+  const CsrDesc c = csr[t.set];
+  const int lane = threadIdx.x & 63;
+  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+  rowx_row<T, EPL, STRIDED, NT>(d, c, r, lane, row_ptr, col, val, Yin, Yprev, Yout, (A)cf[0],
+                                (A)cf[1], (A)cf[2]);
+}
+
+// A whole filter pass (the m Chebyshev steps) in one persistent launch:
+// each workgroup claims a block from the queue head (blocks in the order of
+// `order`, largest first) and runs the pass's m steps on it, its wavefronts
+// taking the block's rows in turn with the row product above, with a
+// workgroup barrier between steps (a step reads only its own block's rows
+// of the previous one).  Step k writes out[k mod 3], reading out[k-1] and
+// out[k-2] (X for step 0, nothing before it), as the launch sequence of the
+// separate steps does, so the result is bit-identical to it.  Every
+// workgroup leaves once the queue head passes the last block.
+template <typename T, int EPL, bool STRIDED>
+__global__ void __launch_bounds__(64 * PASS_WAVES)
+    k_cheb_pass(const MatDesc* __restrict__ sets, const CsrDesc* __restrict__ csr,
+                const int32_t* __restrict__ order, int nsets, const int32_t* __restrict__ row_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val, const T* X,
+                T* o0, T* o1, T* o2, const double* __restrict__ coef, int coef_stride, int m,
+                int32_t* queue) {
+  typedef typename Acc<T>::type A;
+  __shared__ int job_s;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (threadIdx.x == 0) job_s = atomicAdd(queue, 1);
+    __syncthreads();
+    const int job = job_s;
+    __syncthreads();  // every thread has read job_s before the next claim
+    if (job >= nsets) break;  // workgroup-uniform
+    const int si = order[job];
+    const MatDesc d = sets[si];
+    const CsrDesc c = csr[si];
+    const double* cf = coef + int64_t(d.blk) * coef_stride;
+    const T* cur = X;
+    const T* prev = nullptr;
+    for (int k = 0; k < m; ++k) {
+      T* out = k % 3 == 0 ? o0 : k % 3 == 1 ? o1 : o2;
+      const A alpha = (A)cf[3 * k], beta = (A)cf[3 * k + 1], gamma = (A)cf[3 * k + 2];
+      // ordinary (cached) loads and stores: the workgroup's wavefronts share
+      // the CU's L1, and the barrier makes every row of the step visible to
+      // all of them before the next step reads it
+      for (int r = wave; r < d.rows; r += PASS_WAVES)
+        rowx_row<T, EPL, STRIDED, false>(d, c, r, lane, row_ptr, col, val, cur, prev, out, alpha,
+                                         beta, gamma);
+      __syncthreads();
+      prev = cur;
+      cur = out;
+    }
+  }
 }
 
 // The same product with two rows per wavefront: both rows' loads are in
@@ -665,6 +723,68 @@ template void launch_spmm<bf16>(const SpmmTile*, int, const MatDesc*, const CsrD
                                 const int32_t*, const int32_t*, const float*, const bf16*,
                                 const bf16*, bf16*, const double*, int, int, hipStream_t, int,
                                 int);
+
+template <typename T>
+void launch_cheb_pass(const MatDesc* sets, const CsrDesc* csr, const int32_t* order, int nsets,
+                      const int32_t* row_ptr, const int32_t* col, const float* val, const T* X,
+                      T* o0, T* o1, T* o2, const double* coef, int coef_stride, int m,
+                      int32_t* queue, int grid, int epl, hipStream_t s) {
+  if (nsets <= 0 || m <= 0 || grid <= 0) return;
+  fill_i32(queue, 0, 1, s);
+#define MI_PASS(E, ST)                                                                          \
+  case E:                                                                                       \
+    hipLaunchKernelGGL((k_cheb_pass<T, E, ST>), dim3(grid), dim3(64 * PASS_WAVES), 0, s, sets,  \
+                       csr, order, nsets, row_ptr, col, val, X, o0, o1, o2, coef, coef_stride, \
+                       m, queue);                                                               \
+    return;
+  switch (epl) {
+    MI_PASS(1, false)
+    MI_PASS(2, false)
+    MI_PASS(3, false)
+    MI_PASS(4, false)
+    MI_PASS(5, true)
+    default:
+      return;
+  }
+#undef MI_PASS
+}
+
+template <typename T>
+int cheb_pass_grid(int epl, int nsets) {
+  int per_cu = 0;
+#define MI_OCC(E, ST)                                                                           \
+  case E:                                                                                       \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cheb_pass<T, E, ST>,           \
+                                                     64 * PASS_WAVES, 0) != hipSuccess)         \
+      per_cu = 0;                                                                               \
+    break;
+  switch (epl) {
+    MI_OCC(1, false)
+    MI_OCC(2, false)
+    MI_OCC(3, false)
+    MI_OCC(4, false)
+    MI_OCC(5, true)
+    default:
+      return 0;
+  }
+#undef MI_OCC
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return std::min(nsets, std::max(per_cu, 1) * std::max(cus, 1));
+}
+
+#define MI_PASS_INST(T)                                                                         \
+  template void launch_cheb_pass<T>(const MatDesc*, const CsrDesc*, const int32_t*, int,       \
+                                    const int32_t*, const int32_t*, const float*, const T*,    \
+                                    T*, T*, T*, const double*, int, int, int32_t*, int, int,   \
+                                    hipStream_t);                                               \
+  template int cheb_pass_grid<T>(int, int);
+MI_PASS_INST(float)
+MI_PASS_INST(double)
+MI_PASS_INST(bf16)
+#undef MI_PASS_INST
 
 // ------------------------------------------------------------------ Gram
 // One workgroup: a 64 x 64 super-tile of A^T B (and A^T W when DUAL) over a

@@ -94,6 +94,23 @@ void launch_spmm(const SpmmTile* tiles, int ntiles, const MatDesc* sets, const C
 // launch has the same ld, a multiple of 64 up to 320; 0 otherwise.
 int spmm_epl(const std::vector<MatDesc>& sets);
 
+// A whole Chebyshev filter pass (m steps) of a wave in one persistent
+// launch: `grid` workgroups claim blocks (sets[order[i]], i = 0, 1, ...) from
+// the queue head *queue (reset to 0 on the stream first) and run the m steps
+// on each with workgroup barriers between them; step k writes o[k mod 3].
+// Rows as SPMM variants 7-10 (bit-identical).  Waves of one width only
+// (epl = spmm_epl of the wave, > 0).
+constexpr int PASS_WAVES = 8;  // wavefronts per workgroup
+template <typename T>
+void launch_cheb_pass(const MatDesc* sets, const CsrDesc* csr, const int32_t* order, int nsets,
+                      const int32_t* row_ptr, const int32_t* col, const float* val, const T* X,
+                      T* o0, T* o1, T* o2, const double* coef, int coef_stride, int m,
+                      int32_t* queue, int grid, int epl, hipStream_t s);
+// Workgroups of that launch: the resident ones (occupancy times CUs), at most
+// one per block; 0 when epl has no kernel.
+template <typename T>
+int cheb_pass_grid(int epl, int nsets);
+
 template <typename T>
 void launch_gram(const GramTile* tiles, int ntiles, const MatDesc* sets, const T* A, const T* B,
                  const T* W, double* part, hipStream_t s);

@@ -730,6 +730,7 @@ static WsLayout ws_layout(const HostBlocks& hb, const mi_oi_params& prm, size_t 
   L.tri = c.used, c.take<double>(4 * tp);
   L.part_lane = std::max<size_t>(part_doubles, 1);
   L.part = c.used, c.take<double>(L.part_lane * std::max(n_lanes, 1));
+  L.queue = c.used, c.take<int32_t>(std::max(n_lanes, 1));
   L.a_lo = c.used, c.take<double>(hb.B);
   L.b_hi = c.used, c.take<double>(hb.B);
   L.coef_stride = 3 * (mmax + 1);
@@ -765,6 +766,7 @@ struct WaveHost {
   std::vector<GramTile> gt, gts;
   std::vector<GramReduce> gr, grs;
   std::vector<RowTile> rt, rts;
+  std::vector<int32_t> porder;
 };
 
 static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
@@ -814,6 +816,20 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
   gram_tables(h->small, false, &h->gts, &h->grs);
   row_tables(h->tall, wt->nch, &h->rt);
   row_tables(h->small, wt->nchs, &h->rts);
+  // persistent filter passes: blocks claimed largest first
+  wt->persistent = prm.persistent == 1 && prm.op == MI_OP_CHEB && wt->epl > 0;
+  h->porder.resize(h->tall.size());
+  for (size_t i = 0; i < h->porder.size(); ++i) h->porder[i] = int32_t(i);
+  std::stable_sort(h->porder.begin(), h->porder.end(),
+                   [&](int32_t x, int32_t y) { return h->tall[x].rows > h->tall[y].rows; });
+  wt->pgrid = 0;
+  if (wt->persistent) {
+    const int nb = (int)blocks.size();
+    wt->pgrid = prm.precision == MI_FP64      ? cheb_pass_grid<double>(wt->epl, nb)
+                : prm.precision == MI_BF16_IN ? cheb_pass_grid<bf16>(wt->epl, nb)
+                                              : cheb_pass_grid<float>(wt->epl, nb);
+    wt->persistent = wt->pgrid > 0;
+  }
 }
 
 template <typename X>
@@ -916,6 +932,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
     put(blob, h.grs, &offs);
     put(blob, h.rt, &offs);
     put(blob, h.rts, &offs);
+    put(blob, h.porder, &offs);
   }
   MI_TRY_HIP(hipMalloc(&P->arena, std::max<size_t>(blob.size(), 256)));
   MI_TRY_HIP(hipMemcpy(P->arena, blob.data(), blob.size(), hipMemcpyHostToDevice));
@@ -948,6 +965,7 @@ static mi_status make_plan(const HostBlocks& hb, const std::vector<int64_t>& nnz
     wt.n_rt = (int)h.rt.size();
     wt.rts = reinterpret_cast<RowTile*>(base + offs[k++]);
     wt.n_rts = (int)h.rts.size();
+    wt.porder = reinterpret_cast<int32_t*>(base + offs[k++]);
     wt.tall_host = h.tall;
   }
   *out = std::move(P);
@@ -1102,6 +1120,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
   double* b_hi = reinterpret_cast<double*>(ws + L.b_hi);
   double* coef = reinterpret_cast<double*>(ws + L.coef);
   int32_t* conv = reinterpret_cast<int32_t*>(ws + L.conv);
+  int32_t* queue0 = reinterpret_cast<int32_t*>(ws + L.queue);
   const bool dbl = std::is_same<T, double>::value;
   const int B = P.hb.B;
   const OiRecord* rec = a.rec;
@@ -1163,6 +1182,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
                            static_cast<const TS*>(src), static_cast<TS*>(dst));
     };
     double* part = part0 + (fork ? size_t(w.lane) * L.part_lane : 0);
+    int32_t* queue = queue0 + (fork ? w.lane : 0);
     const size_t lds_jac = size_t(4 * (w.max_q / 2) + (size_t)w.max_q * (w.max_q + 1) / 2) * 8;
     const bool jac_lds = lds_jac <= (size_t)P.lds_max;
     const size_t lds_jac_use = jac_lds ? lds_jac : size_t(4 * (w.max_q / 2)) * 8;
@@ -1335,9 +1355,17 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           }
           ycur = free_s[0];
         }
+        if (w.persistent && prm.op == MI_OP_CHEB && w.m > 0) {
+          // the pass's m steps in one launch over a block work queue
+          KScope k_(a.tm, MI_K_CHEB_PASS, s);
+          launch_cheb_pass<T>(w.tall, w.csr, w.porder, w.nb, a.row_ptr, a.col, a.val, X,
+                              slab[free_s[0]], slab[free_s[1]], slab[free_s[2]], coef,
+                              L.coef_stride, w.m, queue, w.pgrid, w.epl, s);
+          ycur = free_s[(w.m - 1) % 3];
+        }
         const T* prev = nullptr;
         const T* cur = X;
-        for (int k = 0; k < (prm.op == MI_OP_RZ ? 0 : w.m); ++k) {
+        for (int k = 0; k < (prm.op == MI_OP_RZ || w.persistent ? 0 : w.m); ++k) {
           T* out = slab[free_s[k % 3]];
           {
             KScope k_(a.tm, MI_K_SPMM, s);

@@ -25,6 +25,8 @@ struct WaveTables {
   int gram_target = GRAM_TARGET;  // workgroups of the split Gram launch
   bool gram_direct = false;        // no super-tile split: the Gram writes G itself
   int lane = 0;  // stream lane: the waves of one lane form one dependency chain
+  bool persistent = false;  // filter passes as one persistent launch each
+  int pgrid = 0;            // its workgroups
   std::vector<MatDesc> tall_host;  // host copy of `tall` (for retuning)
   // device tables
   MatDesc *tall = nullptr, *ptall = nullptr, *small = nullptr;
@@ -44,6 +46,7 @@ struct WaveTables {
   int n_rt = 0;
   RowTile* rts = nullptr;
   int n_rts = 0;
+  int32_t* porder = nullptr;  // persistent pass: indices into `tall`, largest block first
 };
 
 struct WsLayout {
@@ -58,6 +61,7 @@ struct WsLayout {
   int cg_ldp = 0;    // largest ld (row stride of the partials)
   int64_t cg_tiles = 0;  // 16-row tiles of all blocks
   size_t part_lane;  // Gram partial doubles of one stream lane
+  size_t queue;      // persistent passes: one int32 queue head per stream lane
   size_t total;
   int coef_stride;
 };

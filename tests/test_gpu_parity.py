@@ -332,6 +332,88 @@ def test_spmm_variants_agree(ctx, width):
             assert dr <= 4 * np.finfo(np.float32).eps * lam[cb - 1] + 1e-12, (var, b, dr)
 
 
+def _persistent_pair(ctx, up, prm, V0=None):
+    """The tracking with every filter pass as one persistent launch, and with
+    one launch per step with the same row product (SpMM variant 7), plus the
+    persistent run's per-class launch counts."""
+    Lp = up.laplacian(ctx)
+    out = []
+    kts = []
+    try:
+        ctx.force_spmm(7)
+        for persistent in (0, 1):
+            prm.persistent = persistent
+            V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)  # plan and graph
+            V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0, V=V, ritz=ritz, status=st)
+            torch.cuda.synchronize()
+            assert int(st.abs().sum()) == 0, (persistent, st)
+            out.append((V.clone(), ritz.clone()))
+            ctx.set_timing(True)
+            mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0, V=V, ritz=ritz, status=st)  # eager
+            torch.cuda.synchronize()
+            kts.append(ctx.kernel_times())
+            ctx.set_timing(False)
+            assert torch.equal(V, out[-1][0]), persistent  # eager run = graph replay
+    finally:
+        ctx.force_spmm(-1)
+        prm.persistent = 0
+    return out, kts
+
+
+@pytest.mark.parametrize("prec,width,nblk", [(mis.MI_FP32, 320, 6), (mis.MI_FP64, 192, 5),
+                                             (mis.MI_BF16_IN, 256, 5), (mis.MI_FP32, 128, 3000)])
+def test_persistent_filter_pass(ctx, prec, width, nblk):
+    """Filter passes run as one persistent launch over a block work queue
+    (workgroups claim whole blocks, largest first, and run the pass's m steps
+    with workgroup barriers) give bit for bit the tracking of one launch per
+    step with the same row product, in every precision and row width; the
+    3,000 small disks outnumber the resident workgroups, so workgroups claim
+    several blocks each.  The result meets the oracle on the smallest and the
+    largest block."""
+    small = nblk > 100
+    bs = W.disk_blocks(n_blocks=nblk, n_min=width + 20 if small else max(width + 40, 400),
+                       n_max=width + 140 if small else 2000, c_max=width - 32, p_max=width,
+                       key=(52, width, nblk))
+    bs.p = np.full(nblk, width)
+    bs.c = bs.p - 32
+    up = Uploaded(bs)
+    assert (np.asarray(up.blocks.ld) == width).all()
+    prm = mis.OiParams(precision=prec, warm=mis.MI_RANDOM, seed=77, T0=6, m0=10, passes0=2)
+    (V_s, r_s), (V_p, r_p) = _persistent_pair(ctx, up, prm)[0]
+    assert torch.equal(V_s, V_p) and torch.equal(r_s, r_p), "persistent pass differs"
+    n = np.asarray(up.blocks.n)
+    bar = 5e-2 if prec == mis.MI_BF16_IN else ANGLE_FP32
+    for b in sorted({int(np.argmin(n)), int(np.argmax(n))}):
+        # BF16 iterates resolve only well-separated cuts (rounding 2^-8 over
+        # the relative gap): the lowest 32 pairs there
+        cb = 32 if prec == mis.MI_BF16_IN else int(bs.c[b])
+        _, lam, U = oracle_block(up, b, k=width + 1)
+        ang = S.sin_theta_max(U[:, :cb], up.slab(V_p, b)[:, :cb])
+        print(f"persistent pass, precision {prec}, width {width}, {nblk} blocks: block {b} "
+              f"(n {int(n[b])}) sin {ang:.2e}")
+        assert ang < bar, (b, ang)
+
+
+def test_persistent_filter_pass_launches_and_lanes(ctx):
+    """The persistent pass replaces the m step launches of every pass (one
+    launch per pass, the step launches left are the Rayleigh-Ritz products),
+    and on a warm-started chain whose trees run on several stream lanes in
+    the graph (one queue head per lane) the result is bit for bit that of
+    the step launches."""
+    bs = W.icosphere_blocks(level=5, n_blocks=8, c=100, p=192, n_roots=3)
+    up = Uploaded(bs)
+    assert (np.asarray(up.blocks.ld) == 192).all()
+    prm = warm_params()
+    (V_s, r_s), (V_p, r_p) = (o := _persistent_pair(ctx, up, prm, V0=up.starts(torch.float32)))[0]
+    kt_s, kt_p = o[1]
+    assert torch.equal(V_s, V_p) and torch.equal(r_s, r_p)
+    waves_T = kt_s["spmm"][1]  # step launches: m per pass plus one product per iteration
+    n_pass = kt_p["cheb_pass"][1]
+    assert kt_s["cheb_pass"][1] == 0
+    assert n_pass > 0 and kt_p["spmm"][1] + 10 * n_pass == waves_T, (kt_s["spmm"], kt_p)
+    _chain_check(up, V_p, r_p, torch.zeros(up.blocks.n_blocks, dtype=torch.int32), 100)
+
+
 @pytest.mark.parametrize("rr_every", [0, 1])
 def test_eigen_solvers_agree(ctx, chain_small, rr_every):
     """Tridiagonal (Householder + multisection + inverse iteration) and

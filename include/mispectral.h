@@ -164,7 +164,7 @@ typedef struct {
                         launch: workgroups claim whole blocks from a device queue,
                         largest first, and run the pass's m Chebyshev steps on each
                         with workgroup barriers between steps.  The rows are those
-                        of SPMM variants 7-10 (bit-identical to them); the tuned
+                        of SPMM variants 7-12 (bit-identical to them); the tuned
                         SpMM variant still serves the Rayleigh-Ritz product.
                         Other waves, and 0, launch each step over the whole wave */
   double delta;      /* shift of R (MI_OP_RZ), > 0                                  */
@@ -246,7 +246,7 @@ mi_status mi_ctx_set_timing(mi_ctx* ctx, int32_t on);
 /* Launch-shape override, for measurement and for checking the variants
  * against each other: tracking plans made after the call (the plan is
  * rebuilt when the variant differs) run the wavefront-per-row SpMM as
- * `variant` (the codes of mi_oi_tuning, 0..10) in every wave that uses it,
+ * `variant` (the codes of mi_oi_tuning, 0..12) in every wave that uses it,
  * whatever the autotuner would pick; -1 restores the autotuner or the
  * default.  MI_ERR_ARG for other values.  Host only. */
 mi_status mi_oi_force_spmm(mi_ctx* ctx, int32_t variant);
@@ -353,7 +353,10 @@ mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_pa
  * Laplacian),
  * over consecutive rows in workgroups of 8 (7, 9), 16 (8) or 4 (10)
  * wavefronts, the previous iterate and the output streamed non-temporally
- * except in 9; -1 the default, 7) for up to `cap` waves;
+ * except in 9; 11 and 12 the same with half a wavefront per row (two rows
+ * per wavefront, twice the elements per lane; rows of up to 256 columns,
+ * wider ones as 7) in workgroups of 8 and 4 wavefronts; 7 to 12 give the
+ * same bits; -1 the default, 7) for up to `cap` waves;
  * *n_waves gets the plan's wave count.  Variants 0 to 6 give bit-identical
  * results, and so do 7 to 10 among themselves.  Host only. */
 mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves);

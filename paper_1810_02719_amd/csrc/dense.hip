@@ -309,10 +309,28 @@ __device__ inline void st_nt<bf16>(bf16* p, bf16 v) {
 // values move as one 4- or 8-byte access (element-wise 2-byte accesses,
 // non-temporal ones especially, cost more than the bytes they move).
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <typename T, int EPL, bool STRIDED, bool NT>
 __device__ __forceinline__ void row_load(const T* p, typename Acc<T>::type* v) {
   constexpr int ES = STRIDED ? 64 : 1;
-  if constexpr (std::is_same<T, bf16>::value && !STRIDED && EPL == 4) {
+  if constexpr (std::is_same<T, bf16>::value && !STRIDED && EPL == 8) {
+    const u32x4 w = NT ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p))
+                       : *reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      v[2 * h] = __uint_as_float(w[h] << 16);
+      v[2 * h + 1] = __uint_as_float(w[h] & 0xFFFF0000u);
+    }
+  } else if constexpr (std::is_same<T, float>::value && !STRIDED && EPL % 4 == 0) {
+#pragma unroll
+    for (int h = 0; h < EPL / 4; ++h) {
+      const f32x4 w = NT ? __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p) + h)
+                         : reinterpret_cast<const f32x4*>(p)[h];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * h + e] = w[e];
+    }
+  } else if constexpr (std::is_same<T, bf16>::value && !STRIDED && EPL == 4) {
     const u32x2 w = NT ? __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p))
                        : *reinterpret_cast<const u32x2*>(p);
     v[0] = __uint_as_float(w.x << 16);
@@ -332,7 +350,25 @@ __device__ __forceinline__ void row_load(const T* p, typename Acc<T>::type* v) {
 template <typename T, int EPL, bool STRIDED, bool NT>
 __device__ __forceinline__ void row_store(T* p, const typename Acc<T>::type* v) {
   constexpr int ES = STRIDED ? 64 : 1;
-  if constexpr (std::is_same<T, bf16>::value && !STRIDED && (EPL == 2 || EPL == 4)) {
+  if constexpr (std::is_same<T, bf16>::value && !STRIDED && EPL == 8) {
+    u32x4 x;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      x[h] = uint32_t(f32_to_bf16(v[2 * h]).u) | (uint32_t(f32_to_bf16(v[2 * h + 1]).u) << 16);
+    if (NT)
+      __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(p));
+    else
+      *reinterpret_cast<u32x4*>(p) = x;
+  } else if constexpr (std::is_same<T, float>::value && !STRIDED && EPL % 4 == 0) {
+#pragma unroll
+    for (int h = 0; h < EPL / 4; ++h) {
+      const f32x4 x = {v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]};
+      if (NT)
+        __builtin_nontemporal_store(x, reinterpret_cast<f32x4*>(p) + h);
+      else
+        reinterpret_cast<f32x4*>(p)[h] = x;
+    }
+  } else if constexpr (std::is_same<T, bf16>::value && !STRIDED && (EPL == 2 || EPL == 4)) {
     uint32_t w[2];
 #pragma unroll
     for (int h = 0; h < EPL / 2; ++h)
@@ -407,6 +443,15 @@ __device__ __forceinline__ void rowx_row(const MatDesc& d, const CsrDesc& c, int
 #pragma unroll
   for (int e = 0; e < EPL; ++e) acc[e] = (A)0;
   for (int k = k0; k < k1; k += G) {
+    // the group's column indices and weights in one vector load (lane u
+    // holds entry k + u), read out lane by lane: one memory round trip per
+    // group instead of a dependent scalar load per entry
+    int cjv = 0;
+    float wvv = 0.0f;
+    if (lane < G && k + lane < k1) {
+      cjv = cb[k + lane];
+      wvv = vb[k + lane];
+    }
     A y[G][EPL];
     A w[G];
     bool has[G];
@@ -415,8 +460,8 @@ __device__ __forceinline__ void rowx_row(const MatDesc& d, const CsrDesc& c, int
       has[u] = false;
       w[u] = (A)0;
       if (k + u < k1) {
-        const int cj = cb[k + u];
-        const A wv = (A)vb[k + u];
+        const int cj = __builtin_amdgcn_readlane(cjv, u);
+        const A wv = (A)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(wvv), u));
         rs += wv;
         if (cj != r) {
           has[u] = true;
@@ -457,13 +502,107 @@ __global__ void __launch_bounds__(64 * WPG)
   const SpmmTile t = tiles[ti];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const MatDesc d = sets[t.set];
+  const CsrDesc c = csr[t.set];
   const int r = t.row0 + (kx % SPLIT) * WPG + wave;
   if (r >= d.rows) return;  // wave-uniform
-  const CsrDesc c = csr[t.set];
   const int lane = threadIdx.x & 63;
   const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
   rowx_row<T, EPL, STRIDED, NT>(d, c, r, lane, row_ptr, col, val, Yin, Yprev, Yout, (A)cf[0],
                                 (A)cf[1], (A)cf[2]);
+}
+
+// The same rows with half a wavefront per row (two rows per wavefront, the
+// WPG wavefronts of a workgroup on 2 WPG consecutive rows): a lane holds
+// 2 EPL consecutive elements, so each of its loads and stores moves twice
+// the bytes (16 bytes for 256-wide BF16 or 128-wide FP32 rows), and a
+// wavefront has both rows' gathers in flight.  Each element sees the same
+// operations in the same order as in k_spmm_rowx, so the results are
+// bit-identical to it (the neighbour rows are gathered 4 at a time instead
+// of 8, which changes only how many loads are in flight together, and keeps
+// the doubled rows within the registers of 6 wavefronts per SIMD).  Rows of
+// up to 256 columns (not strided).
+template <typename T, int EPL, int WPG, bool NT>
+__global__ void __launch_bounds__(64 * WPG)
+    k_spmm_rowh(const SpmmTile* __restrict__ tiles, const MatDesc* __restrict__ sets,
+                const CsrDesc* __restrict__ csr, const int32_t* __restrict__ row_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val,
+                const T* __restrict__ Yin, const T* __restrict__ Yprev, T* __restrict__ Yout,
+                const double* __restrict__ coef, int coef_stride, int step, int ntiles) {
+  static_assert(SPMM_ROWS % (2 * WPG) == 0, "workgroup split");
+  typedef typename Acc<T>::type A;
+  constexpr int H = 2 * EPL;  // elements per lane
+  constexpr int G = 4;
+  constexpr int SPLIT = SPMM_ROWS / (2 * WPG);
+  const int per = (ntiles + NUM_XCD - 1) / NUM_XCD;
+  const int kx = blockIdx.x / NUM_XCD;
+  const int ti = (blockIdx.x % NUM_XCD) * per + kx / SPLIT;
+  if (ti >= ntiles) return;
+  const SpmmTile t = tiles[ti];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const MatDesc d = sets[t.set];
+  const CsrDesc c = csr[t.set];
+  const int r0 = t.row0 + (kx % SPLIT) * 2 * WPG + 2 * wave;
+  if (r0 >= d.rows) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  const int r = r0 + (lane >> 5);
+  const bool act = r < d.rows;  // the second half of the last row pair may be past the block
+  const double* cf = coef + int64_t(d.blk) * coef_stride + 3 * step;
+  const A alpha = (A)cf[0], beta = (A)cf[1], gamma = (A)cf[2];
+  const int l0 = (lane & 31) * H;
+  const T* yv = Yin + d.off + l0;
+  const int64_t o = d.off + int64_t(r) * d.ld + l0;
+  A yin[H], ypr[H];
+#pragma unroll
+  for (int e = 0; e < H; ++e) yin[e] = ypr[e] = (A)0;
+  int k0 = 0, k1 = 0;
+  if (act) {
+    row_load<T, H, false, false>(Yin + o, yin);
+    if (Yprev) row_load<T, H, false, NT>(Yprev + o, ypr);
+    k0 = row_ptr[c.rp_off + r];
+    k1 = row_ptr[c.rp_off + r + 1];
+  }
+  const A g3 = Yprev ? gamma : (A)0;
+  // entries of the longer of the two rows, for the wavefront's loop bound
+  const int deg = k1 - k0;
+  const int dmax = max(__builtin_amdgcn_readlane(deg, 0), __builtin_amdgcn_readlane(deg, 32));
+  const int32_t* cb = col + c.nnz_off;
+  const float* vb = val + c.nnz_off;
+  A acc[H], rs = (A)0;
+#pragma unroll
+  for (int e = 0; e < H; ++e) acc[e] = (A)0;
+  for (int j = 0; j < dmax; j += G) {
+    A y[G][H];
+    A w[G];
+    bool has[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      has[u] = false;
+      w[u] = (A)0;
+      if (j + u < deg) {
+        const int cj = cb[k0 + j + u];
+        const A wv = (A)vb[k0 + j + u];
+        rs += wv;
+        if (cj != r) {
+          has[u] = true;
+          w[u] = wv;
+          row_load<T, H, false, false>(yv + int64_t(cj) * d.ld, y[u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      if (has[u])
+#pragma unroll
+        for (int e = 0; e < H; ++e) acc[e] = fma(w[u], y[u][e] - yin[e], acc[e]);
+  }
+  if (!act) return;
+  A out[H];
+#pragma unroll
+  for (int e = 0; e < H; ++e) {
+    const A ly = fma(rs, yin[e], acc[e]);
+    out[e] = alpha * ly + (beta * yin[e] + g3 * ypr[e]);
+  }
+  row_store<T, H, false, NT>(Yout + o, out);
 }
 
 // A whole filter pass (the m Chebyshev steps) in one persistent launch:
@@ -665,6 +804,24 @@ static void launch_spmm_rows(int var, const SpmmTile* tiles, int ntiles, const M
     hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 8, false>), dim3(2 * grid.x), dim3(512), 0, s,
                        tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
                        step, ntiles);
+  else if (var == SPMM_VAR_XH8_NT || var == SPMM_VAR_XH4_NT) {
+    // half a wavefront per row: rows of up to 256 columns; wider (strided)
+    // rows take the one-wavefront kernel, which gives the same bits
+    if constexpr (!ST && EPL <= 4) {
+      if (var == SPMM_VAR_XH8_NT)
+        hipLaunchKernelGGL((k_spmm_rowh<T, EPL, 8, true>), grid, dim3(512), 0, s, tiles, sets,
+                           csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride, step,
+                           ntiles);
+      else
+        hipLaunchKernelGGL((k_spmm_rowh<T, EPL, 4, true>), dim3(2 * grid.x), dim3(256), 0, s,
+                           tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef,
+                           coef_stride, step, ntiles);
+    } else {
+      hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 8, true>), dim3(2 * grid.x), dim3(512), 0, s,
+                         tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,
+                         step, ntiles);
+    }
+  }
   else if (var == SPMM_VAR_X4_NT)
     hipLaunchKernelGGL((k_spmm_rowx<T, EPL, ST, 4, true>), dim3(4 * grid.x), dim3(256), 0, s,
                        tiles, sets, csr, row_ptr, col, val, Yin, Yprev, Yout, coef, coef_stride,

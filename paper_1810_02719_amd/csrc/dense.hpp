@@ -69,8 +69,10 @@ constexpr int ROW_TILE = 64;
 // (sum_j L_rj (Y_j - Y_r) plus the row sum times Y_r), in workgroups of 8,
 // 16 or 4 wavefronts over consecutive rows, with the previous iterate and
 // the output streamed non-temporally (8 also with ordinary loads and
-// stores).  Variants 0-6 give bit-identical results, and so do 7-10 among
-// themselves.
+// stores); and the same product with half a wavefront per row (two rows
+// per wavefront, twice the elements per lane), in workgroups of 8 or 4
+// wavefronts.  Variants 0-6 give bit-identical results, and so do 7-12
+// among themselves.
 constexpr int SPMM_VAR_ROW = 0;
 constexpr int SPMM_VAR_ROW_G4 = 1;
 constexpr int SPMM_VAR_ROW2 = 2;
@@ -82,7 +84,9 @@ constexpr int SPMM_VAR_X8_NT = 7;
 constexpr int SPMM_VAR_X16_NT = 8;
 constexpr int SPMM_VAR_X8 = 9;
 constexpr int SPMM_VAR_X4_NT = 10;
-constexpr int SPMM_NVAR = 11;
+constexpr int SPMM_VAR_XH8_NT = 11;
+constexpr int SPMM_VAR_XH4_NT = 12;
+constexpr int SPMM_NVAR = 13;
 int spmm_default_var(int epl);
 
 template <typename T>
@@ -98,7 +102,7 @@ int spmm_epl(const std::vector<MatDesc>& sets);
 // launch: `grid` workgroups claim blocks (sets[order[i]], i = 0, 1, ...) from
 // the queue head *queue (reset to 0 on the stream first) and run the m steps
 // on each with workgroup barriers between them; step k writes o[k mod 3].
-// Rows as SPMM variants 7-10 (bit-identical).  Waves of one width only
+// Rows as SPMM variants 7-12 (bit-identical).  Waves of one width only
 // (epl = spmm_epl of the wave, > 0).
 constexpr int PASS_WAVES = 8;  // wavefronts per workgroup
 template <typename T>

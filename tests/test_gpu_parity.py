@@ -290,8 +290,9 @@ def test_spmm_variants_agree(ctx, width):
     """Every launch shape of the wavefront-per-row SpMM (forced on the plan in
     turn) gives the same tracked subspaces and Ritz values on a wave of
     independent disks of one tracked width, and each meets the oracle:
-    variants 0-6 bit for bit, 7-10 (the diagonal term last in each row's
-    sum) bit for bit among themselves and within FP32 rounding of 0."""
+    variants 0-6 bit for bit, 7-12 (the product in difference form, one or
+    half a wavefront per row) bit for bit among themselves and within FP32
+    rounding of 0."""
     bs = W.disk_blocks(n_blocks=3, n_min=max(width + 40, 300), n_max=2400, c_max=width - 32,
                        p_max=width, key=(36, width))
     bs.p = np.full(3, width)
@@ -303,7 +304,7 @@ def test_spmm_variants_agree(ctx, width):
     prm = mis.OiParams(precision=mis.MI_FP32, warm=mis.MI_WARM_GIVEN, T0=6, m0=10, passes0=2)
     out = []
     try:
-        for var in range(11):
+        for var in range(13):
             ctx.force_spmm(var)
             V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm, V0=V0)
             torch.cuda.synchronize()
@@ -330,6 +331,36 @@ def test_spmm_variants_agree(ctx, width):
             assert ang < ANGLE_FP32, (var, b, ang)
             assert dv < 1e-5, (var, b, dv)
             assert dr <= 4 * np.finfo(np.float32).eps * lam[cb - 1] + 1e-12, (var, b, dr)
+
+
+@pytest.mark.parametrize("prec,width", [(mis.MI_BF16_IN, 256), (mis.MI_BF16_IN, 128),
+                                        (mis.MI_FP64, 192)])
+def test_spmm_difference_form_variants_bf16_fp64(ctx, prec, width):
+    """The difference-form SpMM variants (one wavefront per row in three
+    workgroup sizes, and half a wavefront per row) give the same bits on
+    BF16 working slabs (packed 4-, 8- and 16-byte row accesses) and in FP64."""
+    bs = W.disk_blocks(n_blocks=4, n_min=max(width + 40, 400), n_max=1800, c_max=width - 32,
+                       p_max=width, key=(61, width))
+    bs.p = np.full(4, width)
+    bs.c = bs.p - 32
+    up = Uploaded(bs)
+    Lp = up.laplacian(ctx)
+    prm = mis.OiParams(precision=prec, warm=mis.MI_RANDOM, seed=5, T0=4, m0=8, passes0=2)
+    out = {}
+    try:
+        for var in range(7, 13):
+            ctx.force_spmm(var)
+            V, ritz, st = mis.oi_track(ctx, up.blocks, Lp, prm)
+            torch.cuda.synchronize()
+            assert [t[3] for t in ctx.tuning()] == [var], ctx.tuning()
+            assert int(st.abs().sum()) == 0, (var, st)
+            out[var] = (V.clone(), ritz.clone())
+    finally:
+        ctx.force_spmm(-1)
+    for var in range(8, 13):
+        print(f"precision {prec} width {width}: variant {var} bit-equal to 7: "
+              f"{bool(torch.equal(out[var][0], out[7][0]))}")
+        assert torch.equal(out[var][0], out[7][0]) and torch.equal(out[var][1], out[7][1]), var
 
 
 def _persistent_pair(ctx, up, prm, V0=None):

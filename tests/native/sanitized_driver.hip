@@ -148,6 +148,9 @@ int host_checks(Mesh& M) {
   q = params();
   q.eig = MI_EIG_JACOBI;
   CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
+  q = params();
+  q.persistent = 1;
+  CHECK(mi_oi_workspace_size(nullptr, &M.blk, &q, &ws));
   CHECK(mi_laplacian_workspace_size(&M.blk, M.prim_off.data(), 3, &ws));
   CHECK(mi_encdec_workspace_size(nullptr, &M.blk, MI_FP32, &ws));
   CHECK(mi_choose_c_workspace_size(nullptr, &M.blk, &ws));
@@ -279,6 +282,27 @@ int gpu_checks(Mesh& M) {
                               resid, iters, status, ow, ows, nullptr));
   CHECK(mi_oi_track(ctx, &M.blk, &q, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
                     iters, status, ow, ows, nullptr));
+  step("persistent filter passes (three lanes, a queue head each) against the step launches");
+  {
+    mi_oi_params qp = params();
+    CHECK(mi_oi_force_spmm(ctx, 7));
+    CHECK(mi_oi_track(ctx, &M.blk, &qp, row_ptr, col, val, nnz.data(), nullptr, V, ritz, resid,
+                      iters, status, ow, ows, nullptr));
+    EXPECT(hipDeviceSynchronize() == hipSuccess, "sync after the step launches");
+    EXPECT(hipMemcpy(ref.data(), V, U * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess,
+           "copy V");
+    qp.persistent = 1;
+    for (int rep = 0; rep < 2; ++rep) {  // capture, then replay
+      CHECK(mi_oi_track(ctx, &M.blk, &qp, row_ptr, col, val, nnz.data(), nullptr, V, ritz,
+                        resid, iters, status, ow, ows, nullptr));
+      EXPECT(hipDeviceSynchronize() == hipSuccess, "sync after the persistent passes");
+      EXPECT(hipMemcpy(cur.data(), V, U * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess,
+             "copy V");
+      EXPECT(std::memcmp(ref.data(), cur.data(), U * sizeof(float)) == 0,
+             "persistent passes reproduce the step launches bit for bit");
+    }
+    CHECK(mi_oi_force_spmm(ctx, -1));
+  }
   step("choose_c, projection, reconstruction");
   int32_t* cmax = upload(M.c);
   int32_t* cc = alloc<int32_t>(B);

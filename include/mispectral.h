@@ -358,7 +358,7 @@ mi_status mi_oi_workspace_size(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_pa
  * wider ones as 7) in workgroups of 8 and 4 wavefronts; 7 to 12 give the
  * same bits; -1 the default, 7) for up to `cap` waves;
  * *n_waves gets the plan's wave count.  Variants 0 to 6 give bit-identical
- * results, and so do 7 to 10 among themselves.  Host only. */
+ * results, and so do 7 to 12 among themselves.  Host only. */
 mi_status mi_oi_tuning(mi_ctx* ctx, int32_t* out, int32_t cap, int32_t* n_waves);
 
 mi_status mi_oi_track(mi_ctx* ctx, const mi_blocks* blk, const mi_oi_params* prm,

@@ -121,7 +121,7 @@ class Context:
         return [tuple(buf[4 * w:4 * w + 4]) for w in range(n.value)]
 
     def force_spmm(self, variant: int = -1):
-        """Run later tracking plans' per-row SpMM as `variant` (0..10, the codes
+        """Run later tracking plans' per-row SpMM as `variant` (0..12, the codes
         `tuning()` reports) in every wave that uses it; -1 restores the
         autotuner's or the default choice."""
         L.check(L.lib().mi_oi_force_spmm(self.h, int(variant)))

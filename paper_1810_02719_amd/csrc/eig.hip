@@ -327,16 +327,21 @@ __global__ void __launch_bounds__(TRI_THREADS)
 
 // Wider blocks (192 < ld <= TRI_MAX_LD): the same reflectors with the
 // matrix in global memory (the block's A, overwritten), one workgroup of
-// TRI_G_THREADS per block.  A is kept full and symmetric, so column k below
-// the diagonal is row k right of it: one coalesced row load.  The rank-2
-// update of step k - 1 is deferred and fused into step k's sweep, so the
-// trailing block is read and written once per step:
+// TRI_G_THREADS per block.  Only the upper triangle of A is kept current,
+// so column k below the diagonal is read as row k right of it (one
+// coalesced row load), and each step moves half the trailing block.  The
+// rank-2 update of step k - 1 is deferred and fused into step k's sweep,
+// so the trailing triangle is read and written once per step:
 //   A (one wavefront): row k with update k - 1 applied gives x, its norm,
 //     alpha, beta and v (v_{k+1} = x_{k+1} - alpha, zero at and above k),
 //     into LDS and row k of Hv;
 //   B (all): every trailing row i > k gets update k - 1 (A -= v w^T + w v^T
-//     with the previous v, w), is written back, and gives
-//     p_i = beta (A v)_i, one wavefront per row and lanes over columns;
+//     with the previous v, w) on its columns j >= i, written back, and
+//     p = beta A v from the symmetry: a_ij (j > i) adds a_ij v_j to p_i and
+//     a_ij v_i to p_j.  One wavefront per row and lanes over the columns
+//     (lane l owns columns l + 64 t), the p_i parts summed in the
+//     wavefront, the p_j parts kept by the lane that owns column j over all
+//     of its wavefront's rows and added over the wavefronts afterwards;
 //   C: K = (beta/2) v^T p and w = p - K v.
 // The last update is applied to the final 2 x 2 block at the end.  Every
 // sum runs in a fixed order (wavefront tree, then the wavefront partials in
@@ -362,6 +367,8 @@ __global__ void __launch_bounds__(TRI_G_THREADS)
   __shared__ double vv[2][TRI_MAX_LD], ww[2][TRI_MAX_LD];
   __shared__ double sdd[TRI_MAX_LD], see[TRI_MAX_LD], sbb[TRI_MAX_LD];
   __shared__ double part[2][TRI_G_WAVES];
+  __shared__ double rowp[TRI_MAX_LD];               // p_i from row i's own columns
+  __shared__ double cpart[TRI_G_WAVES][TRI_MAX_LD];  // p_j parts of each wavefront
   __shared__ int flag;
   const SmallDesc d = sds[blockIdx.x];
   const int p = d.p, ld = d.ld;
@@ -422,31 +429,39 @@ __global__ void __launch_bounds__(TRI_G_THREADS)
     }
     __syncthreads();
     const double be = sbb[k];
-    // B: pending update of every trailing row, written back, and p = beta A v
-    for (int i = k1 + wave; i < p; i += 2 * TRI_G_WAVES) {
-      const int i2 = i + TRI_G_WAVES;
-      const bool two = i2 < p;
-      const double v1 = vv[prv][i], w1 = ww[prv][i];
-      const double v2 = two ? vv[prv][i2] : 0.0, w2 = two ? ww[prv][i2] : 0.0;
-      double s1 = 0.0, s2 = 0.0;
-      for (int j = k1 + lane; j < p; j += 64) {
-        const double vj = vv[prv][j], wj = ww[prv][j], nj = vv[cur][j];
-        const int64_t o1 = int64_t(i) * ld + j;
-        const double a1 = fma(-v1, wj, fma(-w1, vj, Ab[o1]));
-        Ab[o1] = a1;
-        s1 = fma(a1, nj, s1);
-        if (two) {
-          const int64_t o2 = int64_t(i2) * ld + j;
-          const double a2 = fma(-v2, wj, fma(-w2, vj, Ab[o2]));
-          Ab[o2] = a2;
-          s2 = fma(a2, nj, s2);
+    // B: pending update of the trailing upper triangle, written back, and
+    // p = beta A v by rows (p_i) and by columns (p_j, per lane)
+    double cacc[TRI_G_PL];
+#pragma unroll
+    for (int t = 0; t < TRI_G_PL; ++t) cacc[t] = 0.0;
+    for (int i = k1 + wave; i < p; i += TRI_G_WAVES) {
+      const double vi = vv[prv][i], wi = ww[prv][i], ni = vv[cur][i];
+      double s1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < TRI_G_PL; ++t) {
+        const int j = lane + 64 * t;
+        if (j >= i && j < p) {
+          const int64_t o = int64_t(i) * ld + j;
+          const double a = fma(-vi, ww[prv][j], fma(-wi, vv[prv][j], Ab[o]));
+          Ab[o] = a;
+          s1 = fma(a, vv[cur][j], s1);
+          if (j > i) cacc[t] = fma(a, ni, cacc[t]);
         }
       }
       s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      if (lane == 0) {
-        ww[cur][i] = be * s1;
-        if (two) ww[cur][i2] = be * s2;
+      if (lane == 0) rowp[i] = s1;
+    }
+#pragma unroll
+    for (int t = 0; t < TRI_G_PL; ++t) {
+      const int j = lane + 64 * t;
+      if (j < TRI_MAX_LD) cpart[wave][j] = cacc[t];
+    }
+    __syncthreads();
+    for (int j = tid; j < p; j += TRI_G_THREADS) {
+      if (j > k) {
+        double c = rowp[j];
+        for (int w = 0; w < TRI_G_WAVES; ++w) c += cpart[w][j];
+        ww[cur][j] = be * c;
       }
     }
     __syncthreads();
@@ -467,7 +482,7 @@ __global__ void __launch_bounds__(TRI_G_THREADS)
     };
     if (p >= 2) {
       sdd[p - 2] = upd(p - 2, p - 2);
-      see[p - 2] = upd(p - 1, p - 2);
+      see[p - 2] = upd(p - 2, p - 1);  // the upper triangle is the current one
       sbb[p - 2] = 0.0;
     }
     sdd[p - 1] = upd(p - 1, p - 1);

@@ -892,16 +892,17 @@ def roofline(ktimes, bs, blocks, L, prm, dom=None, c_arr=None, tag="icosphere", 
         out["achieved"] = tot / (ms * 1e-3) / 1e12
         out["traffic"] = measured_traffic("gram", byt / max(launches, 1), tag)
     elif dom == "rowmul":
-        # Y S with S the p x ld inverse factor or Ritz rotation (FP32 MFMA):
-        # 2 n p ld flops per product, one per Cholesky-QR and per
-        # Rayleigh-Ritz rotation
+        # Y S on the FP32 MFMA: the Rayleigh-Ritz rotation (S = R^-1 Z, full:
+        # 2 n p ld flops) and the Cholesky-QRs (S = R^-1, upper triangular:
+        # n p (p + 1) flops, column j summing j + 1 products)
         tot = 0
         for lvl in np.unique(levels):
             sel = levels == lvl
             T, passes = (prm.T0, prm.passes0) if lvl == 0 else (prm.T, prm.passes)
             start = lvl > 0 or prm.warm == MI_RANDOM
-            nprod = T * passes + 1 + (1 if start else 0) + 1
-            tot += nprod * float((2 * n[sel] * p[sel] * ld[sel]).astype(np.float64).sum())
+            ntri = T * passes + (1 if start else 0) + 1
+            nn, pp, ll = (x[sel].astype(np.float64) for x in (n, p, ld))
+            tot += float((2 * nn * pp * ll).sum()) + ntri * float((nn * pp * (pp + 1)).sum())
         out.update(bound="mfma", unit="TFLOP/s", peak=FP32_MFMA_PEAK_TFLOPS, flops_per_step=tot)
         out["achieved"] = tot / (ms * 1e-3) / 1e12
     elif dom in ("project", "reconstruct"):

@@ -557,7 +557,7 @@ static void reverse(const OiPlan& P, const AdjPlan& A, const AdjWs& L, char* ws,
 
     // Q = Y R^-1 of the Rayleigh-Ritz step; W = L Q (slot m: the plain product)
     launch_rowmul<T, T>(w.rt, w.n_rt, w.tall, static_cast<const T*>(rec.Y), w.small, Rc, w.tall,
-                        Q, w.nch, s);
+                        Q, w.nch, s, true);
     launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, row_ptr, col, val, Q, nullptr, Wl,
                    coef_of(npass - 1), stride, m, s, w.epl, w.spmm_var);
     // projection and Rayleigh-Ritz adjoint

@@ -1336,7 +1336,7 @@ template <typename TA, typename T, typename TO, int NCH>
 __global__ void __launch_bounds__(256)
     k_rowmul(const RowTile* __restrict__ tiles, const MatDesc* __restrict__ asets,
              const TA* __restrict__ A, const MatDesc* __restrict__ ssets, const T* __restrict__ S,
-             const MatDesc* __restrict__ osets, TO* __restrict__ Out, int ntiles) {
+             const MatDesc* __restrict__ osets, TO* __restrict__ Out, int ntiles, int upper) {
   typedef typename VecOf<T>::type V;
   typedef typename VecOf<TA>::type VA;
   constexpr int W = VecOf<T>::W;           // elements per 16-byte vector
@@ -1358,7 +1358,10 @@ __global__ void __launch_bounds__(256)
   const RowTile t = tiles[ti];
   const MatDesc da = asets[t.set], ds = ssets[t.set], dout = osets[t.set];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int K = ds.rows;
+  // an upper triangular S has no entries below row n in column n: the
+  // output columns [n0, n0 + NCH) need only its rows k < n0 + NCH (the
+  // chunks skipped would add products with exact zeros)
+  const int K = upper ? min(ds.rows, t.n0 + NCH) : ds.rows;
   acc_t acc[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) acc[i] = (acc_t)(T)0;
@@ -1441,13 +1444,13 @@ __global__ void __launch_bounds__(256)
 template <typename TA, typename T, typename TO>
 void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const TA* A,
                    const MatDesc* ssets, const T* S, const MatDesc* osets, TO* Out, int nch,
-                   hipStream_t s) {
+                   hipStream_t s, bool upper) {
   if (ntiles <= 0) return;
   switch (nch) {
 #define MI_ROWMUL_CASE(N)                                                                       \
   case N:                                                                                       \
     hipLaunchKernelGGL((k_rowmul<TA, T, TO, N>), xcd_grid(ntiles), dim3(256), 0, s, tiles,     \
-                       asets, A, ssets, S, osets, Out, ntiles);                                 \
+                       asets, A, ssets, S, osets, Out, ntiles, upper ? 1 : 0);                  \
     break;
     MI_ROWMUL_CASE(32)
     MI_ROWMUL_CASE(64)
@@ -1463,19 +1466,19 @@ void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const
 
 template void launch_rowmul<float, float, float>(const RowTile*, int, const MatDesc*,
                                                  const float*, const MatDesc*, const float*,
-                                                 const MatDesc*, float*, int, hipStream_t);
+                                                 const MatDesc*, float*, int, hipStream_t, bool);
 template void launch_rowmul<double, double, double>(const RowTile*, int, const MatDesc*,
                                                     const double*, const MatDesc*, const double*,
-                                                    const MatDesc*, double*, int, hipStream_t);
+                                                    const MatDesc*, double*, int, hipStream_t, bool);
 template void launch_rowmul<double, double, float>(const RowTile*, int, const MatDesc*,
                                                    const double*, const MatDesc*, const double*,
-                                                   const MatDesc*, float*, int, hipStream_t);
+                                                   const MatDesc*, float*, int, hipStream_t, bool);
 template void launch_rowmul<bf16, float, bf16>(const RowTile*, int, const MatDesc*, const bf16*,
                                                const MatDesc*, const float*, const MatDesc*, bf16*,
-                                               int, hipStream_t);
+                                               int, hipStream_t, bool);
 template void launch_rowmul<bf16, float, float>(const RowTile*, int, const MatDesc*, const bf16*,
                                                 const MatDesc*, const float*, const MatDesc*,
-                                                float*, int, hipStream_t);
+                                                float*, int, hipStream_t, bool);
 
 // ------------------------------------------------------------------ tile tables
 

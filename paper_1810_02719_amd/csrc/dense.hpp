@@ -132,11 +132,13 @@ void launch_gram_direct(const GramTile* tiles, int ntiles, const MatDesc* sets,
 bool gram_unsplit(const std::vector<GramReduce>& jobs);
 
 // Out = A S row tile by row tile; A may be a BF16 slab with S and the MFMA in
-// FP32 (TA = bf16, T = float).
+// FP32 (TA = bf16, T = float).  upper: S is upper triangular (zero below
+// the diagonal, as R^-1 of a Cholesky-QR), so each output-column chunk reads
+// only the rows of S down to its last column.
 template <typename TA, typename T, typename TO>
 void launch_rowmul(const RowTile* tiles, int ntiles, const MatDesc* asets, const TA* A,
                    const MatDesc* ssets, const T* S, const MatDesc* osets, TO* Out, int nch,
-                   hipStream_t s);
+                   hipStream_t s, bool upper = false);
 
 // Tile tables (host).  Gram: 64 x 64 super-tiles of the upper triangle,
 // split over row chunks when `split` (about 2048 workgroups in total);

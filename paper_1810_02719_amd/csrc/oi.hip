@@ -1062,7 +1062,9 @@ static void autotune_waves(const OiPlan& P, char* ws, hipStream_t s, const int32
       DevTable<RowTile> drt(rt);
       if (!drt.p) continue;
       const float t = time_calls(s, [&] {
-        launch_rowmul<T, TS>(drt.p, (int)rt.size(), w.tall, y0, w.small, Sm, w.tall, y1, nch, s);
+        // most row products of a step multiply by a triangular R^-1
+        launch_rowmul<T, TS>(drt.p, (int)rt.size(), w.tall, y0, w.small, Sm, w.tall, y1, nch, s,
+                             true);
       });
       if (t < bt) bt = t, best.nch = nch;
     }
@@ -1271,10 +1273,11 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       if (!same && w.T == 0 && !doi) {
         // no iteration follows: the orthonormalised start is the result,
         // written in the output type
-        launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, X, w.small, Sr, w.tall, Vout, w.nch, s);
+        launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, X, w.small, Sr, w.tall, Vout, w.nch, s, true);
         start_in_v = true;
       } else {
-        launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, X, w.small, Sr, w.tall, slab[0], w.nch, s);
+        launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, X, w.small, Sr, w.tall, slab[0], w.nch, s,
+                             true);
         X = slab[0];
         xslab = 0;
       }
@@ -1390,7 +1393,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
             launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, slab[ycur], w.small,
                                  dbl ? reinterpret_cast<const TS*>(Rinv)
                                      : reinterpret_cast<const TS*>(S32),
-                                 w.tall, slab[dst], w.nch, s);
+                                 w.tall, slab[dst], w.nch, s, true);
           }
           X = slab[dst];
           xslab = dst;
@@ -1416,7 +1419,8 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
         if (rec) keep_mats(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, false);
         {
           KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
-          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
+          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1,
+                                        w.nchs, s, true);
         }
         if (prm.adapt) {
           KScope k_(a.tm, MI_K_RQ_MAX, s);
@@ -1426,12 +1430,12 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           KScope k_(a.tm, MI_K_ROWMUL, s);
           const TS* Sr = dbl ? reinterpret_cast<const TS*>(Rinv) : reinterpret_cast<const TS*>(S32);
           if constexpr (same) {
-            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, V, w.nch, s);
+            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, V, w.nch, s, true);
             X = V;
             xslab = -1;
           } else {
             // the W = L Y slab is free after the dual Gram
-            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, Wm, w.nch, s);
+            launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, Wm, w.nch, s, true);
             X = Wm;
             xslab = wsl;
           }
@@ -1462,7 +1466,8 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       }
       {
         KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
-        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1, w.nchs, s);
+        launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1,
+                                      w.nchs, s, true);
       }
       {
         // p x p: never split over rows
@@ -1568,7 +1573,7 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
           launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, dstV, w.small,
                                dbl ? reinterpret_cast<const TS*>(Rinv)
                                    : reinterpret_cast<const TS*>(S32),
-                               w.tall, V, w.nch, s);
+                               w.tall, V, w.nch, s, true);
         }
         if constexpr (same) {
           X = V;

@@ -813,6 +813,12 @@ static void wave_host(const HostBlocks& hb, const std::vector<int64_t>& nnz_off,
   wt->gram_target = tune ? tune->gram_target : GRAM_TARGET;
   gram_tables(h->tall, true, &h->gt, &h->gr, wt->gram_target);
   wt->gram_direct = prm.precision != MI_BF16_IN && gram_unsplit(h->gr);
+  // whole-block super-tiles (no partials) run largest block first, so that
+  // the launch does not end on a long tile of a large block
+  if (wt->gram_direct)
+    std::stable_sort(h->gt.begin(), h->gt.end(), [](const GramTile& x, const GramTile& y) {
+      return x.r1 - x.r0 > y.r1 - y.r0;
+    });
   gram_tables(h->small, false, &h->gts, &h->grs);
   row_tables(h->tall, wt->nch, &h->rt);
   row_tables(h->small, wt->nchs, &h->rts);

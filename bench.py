@@ -844,7 +844,10 @@ def roofline(ktimes, bs, blocks, L, prm, dom=None, c_arr=None, tag="icosphere", 
             csr = int(((n[sel] + 1) * 4 + nnz[sel] * 8).sum())
             slab = int((n[sel] * ld[sel] * es).sum())
             per_pass = m * (csr + 2 * slab) + (m - 1) * slab
-            tot += T * (passes * per_pass + csr + 2 * slab)
+            # W = L X once per iteration for the adaptive bound, and for the
+            # Rayleigh-Ritz step
+            n_w = (T - 1) * (1 if prm.adapt else 0) + 1
+            tot += T * passes * per_pass + n_w * (csr + 2 * slab)
         out.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, bytes_per_step=tot,
                    bytes_per_launch=tot / max(launches, 1))
         out["achieved"] = tot / (ms * 1e-3) / 1e9
@@ -876,17 +879,18 @@ def roofline(ktimes, bs, blocks, L, prm, dom=None, c_arr=None, tag="icosphere", 
         out["achieved"] = tot / (ms * 1e-3) / 1e12
     elif dom == "gram":
         # Y^T Y over the rows (upper triangle incl. the diagonal, FP64 MFMA):
-        # n p (p + 1) flops; the iteration-end products are dual (Y^T Y, Y^T W)
+        # n p (p + 1) flops; the Rayleigh-Ritz product is dual (Y^T Y, Y^T W),
+        # every other one (each Cholesky-QR) single
         tot, byt = 0, 0
         for lvl in np.unique(levels):
             sel = levels == lvl
             T, passes = (prm.T0, prm.passes0) if lvl == 0 else (prm.T, prm.passes)
             start = lvl > 0 or prm.warm == MI_RANDOM
-            single = T * (passes - 1) + 1 + (1 if start else 0)
+            single = T * passes + (1 if start else 0)
             per = (n[sel] * p[sel] * (p[sel] + 1)).astype(np.float64).sum()
-            tot += (single + 2 * T) * per
+            tot += (single + 2) * per
             slab = float((n[sel] * ld[sel] * es).sum())
-            byt += (single + 2 * T) * slab  # one read of each operand slab
+            byt += (single + 2) * slab  # one read of each operand slab
         out.update(bound="mfma", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, flops_per_step=tot,
                    bytes_per_launch=byt / max(launches, 1))
         out["achieved"] = tot / (ms * 1e-3) / 1e12

@@ -943,6 +943,69 @@ MI_PASS_INST(double)
 MI_PASS_INST(bf16)
 #undef MI_PASS_INST
 
+// ------------------------------------------------------------------ Rayleigh quotients
+// q_j^T L q_j for the columns of an orthonormalised basis X from W = L X:
+// sums over RQ_CHUNKS row chunks of each block (a workgroup per block and
+// chunk, threads over the columns, rows in order) into the block's p x p
+// matrix slot (RQ_CHUNKS rows of ld doubles), then per block the chunks in
+// order and the largest quotient over its p columns.
+constexpr int RQ_CHUNKS = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_rq_part(const MatDesc* __restrict__ sets, const MatDesc* __restrict__ osets,
+              const T* __restrict__ X, const T* __restrict__ W, double* __restrict__ part) {
+  const int b = blockIdx.x / RQ_CHUNKS, c = blockIdx.x % RQ_CHUNKS;
+  const MatDesc d = sets[b];
+  const int per = (d.rows + RQ_CHUNKS - 1) / RQ_CHUNKS;
+  const int r0 = c * per, r1 = min(d.rows, r0 + per);
+  double* out = part + osets[b].off + int64_t(c) * d.ld;
+  for (int j = threadIdx.x; j < d.ld; j += 256) {
+    double s = 0.0;
+#pragma unroll 4
+    for (int r = r0; r < r1; ++r) {
+      const int64_t e = d.off + int64_t(r) * d.ld + j;
+      s = fma((double)Acc<T>::load(X[e]), (double)Acc<T>::load(W[e]), s);
+    }
+    out[j] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_rq_final(const MatDesc* __restrict__ sets, const MatDesc* __restrict__ osets,
+               const double* __restrict__ part, double* __restrict__ a_lo) {
+  __shared__ double red[4];
+  const MatDesc d = sets[blockIdx.x];
+  const double* pb = part + osets[blockIdx.x].off;
+  double mx = -1e308;
+  for (int j = threadIdx.x; j < d.cols; j += 256) {
+    double s = 0.0;
+    for (int c = 0; c < RQ_CHUNKS; ++c) s += pb[int64_t(c) * d.ld + j];
+    mx = fmax(mx, s);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) a_lo[d.blk] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+template <typename T>
+void launch_rq(const MatDesc* sets, const MatDesc* osets, int nb, const T* X, const T* W,
+               double* part, double* a_lo, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_rq_part<T>, dim3(nb * RQ_CHUNKS), dim3(256), 0, s, sets, osets, X, W,
+                     part);
+  hipLaunchKernelGGL(k_rq_final, dim3(nb), dim3(256), 0, s, sets, osets, (const double*)part,
+                     a_lo);
+}
+template void launch_rq<float>(const MatDesc*, const MatDesc*, int, const float*, const float*,
+                               double*, double*, hipStream_t);
+template void launch_rq<double>(const MatDesc*, const MatDesc*, int, const double*, const double*,
+                                double*, double*, hipStream_t);
+template void launch_rq<bf16>(const MatDesc*, const MatDesc*, int, const bf16*, const bf16*,
+                              double*, double*, hipStream_t);
+
 // ------------------------------------------------------------------ Gram
 // One workgroup: a 64 x 64 super-tile of A^T B (and A^T W when DUAL) over a
 // row range, staged through LDS 32 rows at a time from 16-byte vector loads

@@ -131,6 +131,13 @@ void launch_gram_direct(const GramTile* tiles, int ntiles, const MatDesc* sets,
                         double* H, hipStream_t s);
 bool gram_unsplit(const std::vector<GramReduce>& jobs);
 
+// a_lo[blk] <- max_{j < p} q_j^T L q_j of each block's orthonormalised basis
+// X (the tall sets) from W = L X; part: scratch in each block's p x p
+// matrix slot (osets: 8 ld doubles per block, ld >= 8).
+template <typename T>
+void launch_rq(const MatDesc* sets, const MatDesc* osets, int nb, const T* X, const T* W,
+               double* part, double* a_lo, hipStream_t s);
+
 // Out = A S row tile by row tile; A may be a BF16 slab with S and the MFMA in
 // FP32 (TA = bf16, T = float).  upper: S is upper triangular (zero below
 // the diagonal, as R^-1 of a Cholesky-QR), so each output-column chunk reads

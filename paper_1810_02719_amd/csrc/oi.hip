@@ -1410,25 +1410,33 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
       for (int i = 0; i < 4; ++i)
         if (i != ycur) wsl = i;
       T* Wm = slab[wsl];
-      // W = L Y;  G = Y^T Y, H = Y^T W (one dual Gram pass);  R^T R = G
-      {
-        KScope k_(a.tm, MI_K_SPMM, s);
-        launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm, coef,
-                       L.coef_stride, w.m, s, w.epl, w.spmm_var);
+      // BF16 slabs take the intermediate bound from the dual Gram (Y^T L Y
+      // with R^-1 applied in FP64): a quotient of the BF16-rounded basis
+      // would carry its rounding noise weighted by L
+      const bool bf16_rq = std::is_same<T, bf16>::value && !rr_now && prm.adapt;
+      if (rr_now || bf16_rq) {
+        // W = L Y;  G = Y^T Y, H = Y^T W (one dual Gram pass);  R^T R = G
+        {
+          KScope k_(a.tm, MI_K_SPMM, s);
+          launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, Y, nullptr, Wm,
+                         coef, L.coef_stride, w.m, s, w.epl, w.spmm_var);
+        }
+        gram(Y, Wm, G, H);
       }
-      gram(Y, Wm, G, H);
-      // T1 = H Rinv
       if (!rr_now) {
-        // intermediate iteration: Cholesky-QR of Y; the filter's lower bound
-        // follows the largest Rayleigh quotient of the new basis
+        // intermediate iteration: Cholesky-QR of Y, X = Y R^-1; the filter's
+        // lower bound follows the largest Rayleigh quotient q_j^T L q_j of
+        // the new basis, from W = L X (in Y's slab, free once X is formed)
+        // column by column
+        if (!bf16_rq) gram(Y, nullptr, G, nullptr);
         chol(dbl ? nullptr : S32);
         if (rec) keep_mats(rec->S[jp - 1], dbl ? (const void*)Rinv : (const void*)S32, false);
-        {
-          KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
-          launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1,
-                                        w.nchs, s, true);
-        }
-        if (prm.adapt) {
+        if (bf16_rq) {
+          {
+            KScope k_(a.tm, MI_K_ROWMUL_SMALL, s);
+            launch_rowmul<double, double>(w.rts, w.n_rts, w.small, H, w.small, Rinv, w.small, T1,
+                                          w.nchs, s, true);
+          }
           KScope k_(a.tm, MI_K_RQ_MAX, s);
           launch_rq_max(w.sd, w.nb, Rinv, T1, a_lo, s);
         }
@@ -1440,11 +1448,19 @@ static void enqueue(OiPlan& P, const Args& a, hipStream_t s) {
             X = V;
             xslab = -1;
           } else {
-            // the W = L Y slab is free after the dual Gram
             launch_rowmul<T, TS>(w.rt, w.n_rt, w.tall, Y, w.small, Sr, w.tall, Wm, w.nch, s, true);
             X = Wm;
             xslab = wsl;
           }
+        }
+        if (prm.adapt && !bf16_rq) {
+          {
+            KScope k_(a.tm, MI_K_SPMM, s);
+            launch_spmm<T>(w.spmm, w.n_spmm, w.tall, w.csr, a.row_ptr, a.col, a.val, X, nullptr, Y,
+                           coef, L.coef_stride, w.m, s, w.epl, w.spmm_var);
+          }
+          KScope k_(a.tm, MI_K_RQ_MAX, s);
+          launch_rq<T>(w.tall, w.small, w.nb, X, Y, H, a_lo, s);
         }
         if constexpr (same) if (doi) {
           KScope k_(a.tm, MI_K_DOI, s);

@@ -361,7 +361,7 @@ __device__ __forceinline__ double tri_g_sum(double v, double* part) {
   return t;
 }
 
-__global__ void __launch_bounds__(TRI_G_THREADS)
+__global__ void __launch_bounds__(TRI_G_THREADS, 8)
     k_tri_reduce_g(const SmallDesc* __restrict__ sds, double* __restrict__ A,
                    double* __restrict__ Hv, double* __restrict__ tri, int32_t* __restrict__ status) {
   __shared__ double vv[2][TRI_MAX_LD], ww[2][TRI_MAX_LD];
@@ -836,15 +836,13 @@ void launch_tri_reduce(const SmallDesc* sd, int nb, int max_ld, double* A, doubl
                        double* tri, int32_t* status, hipStream_t s) {
   if (nb <= 0) return;
   if (max_ld > 32 * 6) {
-    // One workgroup per CU: the launch reserves 64 KB of LDS it does not use
-    // (with the kernel's own 18 KB, two workgroups no longer fit the CU's
-    // 160 KB).  The blocks in flight then keep their trailing matrices
-    // (800 KB each at ld = 320, read and written once per step) within the
-    // 256 MB infinity cache, where two per CU overflowed it to HBM: 34.0 to
-    // 27.7 ms for 1,024 blocks of ld 320.
-    constexpr size_t TRI_G_RESERVE = 64 * 1024;
-    hipLaunchKernelGGL(k_tri_reduce_g, dim3(nb), dim3(TRI_G_THREADS), TRI_G_RESERVE, s, sd, A,
-                       Hv, tri, status);
+    // Two workgroups per CU (64 registers, 62 KB of LDS each): with only the
+    // upper triangle swept (about 400 KB touched per block at ld = 320),
+    // the blocks in flight still fit the 256 MB infinity cache (16.5 against
+    // 19.2 ms for 1,024 blocks of ld 320 at one per CU; when the full square
+    // was swept, two per CU overflowed it: 34.0 against 27.7 ms)
+    hipLaunchKernelGGL(k_tri_reduce_g, dim3(nb), dim3(TRI_G_THREADS), 0, s, sd, A, Hv, tri,
+                       status);
     return;
   }
   switch ((max_ld + 31) / 32) {

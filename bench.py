@@ -515,7 +515,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the workload is one GPU's share and no "
-              "multi-GPU path is built (see DESIGN.md, sharding).", file=sys.stderr)
+              "multi-GPU path is built.", file=sys.stderr)
         return 2
     if args.only_precision:
         print(json.dumps({"precision": c4_precision(args)}))

@@ -31,7 +31,8 @@ struct CcPlan {
   GramReduce* gr = nullptr;
   int n_gr = 0;
   bool gram_direct = false;  // no super-tile split: the Gram writes M itself
-  size_t z_off = 0, gx_off = 0, ef_off = 0, m_off = 0, part_off = 0, nrm_off = 0, total = 0;
+  size_t z_off = 0, gx_off = 0, ef_off = 0, efp_off = 0, m_off = 0, part_off = 0, nrm_off = 0,
+         total = 0;
   ~CcPlan() {
     if (arena) (void)hipFree(arena);
   }
@@ -125,17 +126,24 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// E = U^T X and F = Z^T GX (p x 3 each, FP64), one workgroup per block.
+// E = U^T X and F = Z^T GX (p x 3 each, FP64): sums over EF_CHUNKS row
+// chunks of each block (a workgroup per block and chunk, threads over the
+// columns, rows in order), then per block the chunks added in order.
+constexpr int EF_CHUNKS = 8;
+
 __global__ void __launch_bounds__(256)
-    k_proj_ef(const CcBlock* __restrict__ blks, const float* __restrict__ U,
-              const float* __restrict__ Z, const float* __restrict__ X,
-              const double* __restrict__ GX, double* __restrict__ EF) {
+    k_proj_ef_part(const CcBlock* __restrict__ blks, const float* __restrict__ U,
+                   const float* __restrict__ Z, const float* __restrict__ X,
+                   const double* __restrict__ GX, double* __restrict__ EFP) {
   constexpr int KPT = 4;
-  const CcBlock b = blks[blockIdx.x];
+  const int c = blockIdx.x % EF_CHUNKS;
+  const CcBlock b = blks[blockIdx.x / EF_CHUNKS];
+  const int per = (b.n + EF_CHUNKS - 1) / EF_CHUNKS;
+  const int r0 = c * per, r1 = min(b.n, r0 + per);
   double e[KPT][3], f[KPT][3];
   for (int s = 0; s < KPT; ++s)
     for (int d = 0; d < 3; ++d) e[s][d] = f[s][d] = 0.0;
-  for (int i = 0; i < b.n; ++i) {
+  for (int i = r0; i < r1; ++i) {
     const float* x = X + 3 * (b.v_off + i);
     const double* g = GX + 3 * (b.v_off + i);
     const double x0 = x[0], x1 = x[1], x2 = x[2], g0 = g[0], g1 = g[1], g2 = g[2];
@@ -154,10 +162,11 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
+  double* o0 = EFP + 6 * (int64_t(EF_CHUNKS) * b.t_off + int64_t(c) * b.p);
   for (int s = 0; s < KPT; ++s) {
     const int k = threadIdx.x + 256 * s;
     if (k < b.p) {
-      double* o = EF + 6 * (b.t_off + k);
+      double* o = o0 + 6 * k;
       o[0] = e[s][0];
       o[1] = e[s][1];
       o[2] = e[s][2];
@@ -165,6 +174,18 @@ __global__ void __launch_bounds__(256)
       o[4] = f[s][1];
       o[5] = f[s][2];
     }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_proj_ef_sum(const CcBlock* __restrict__ blks, const double* __restrict__ EFP,
+                  double* __restrict__ EF) {
+  const CcBlock b = blks[blockIdx.x];
+  const double* pb = EFP + 6 * int64_t(EF_CHUNKS) * b.t_off;
+  for (int e = threadIdx.x; e < 6 * b.p; e += 256) {
+    double s = 0.0;
+    for (int c = 0; c < EF_CHUNKS; ++c) s += pb[6 * int64_t(c) * b.p + e];
+    EF[6 * b.t_off + e] = s;
   }
 }
 
@@ -246,6 +267,11 @@ static mi_status cc_plan(mi_ctx* ctx, const HostBlocks& hb, const std::vector<in
   std::vector<GramTile> gt;
   std::vector<GramReduce> gr;
   gram_tables(tall, true, &gt, &gr);
+  // whole-block super-tiles (no partials) run largest block first
+  if (gram_unsplit(gr))
+    std::stable_sort(gt.begin(), gt.end(), [](const GramTile& x, const GramTile& y) {
+      return x.r1 - x.r0 > y.r1 - y.r0;
+    });
   std::vector<SpmmTile> st;
   spmm_tables(tall, &st);
   size_t o = 0;
@@ -280,6 +306,7 @@ static mi_status cc_plan(mi_ctx* ctx, const HostBlocks& hb, const std::vector<in
   P->z_off = c.used, c.take<float>(hb.u_off[hb.B]);
   P->gx_off = c.used, c.take<double>(3 * hb.v_off[hb.B]);
   P->ef_off = c.used, c.take<double>(6 * hb.t_off[hb.B]);
+  P->efp_off = c.used, c.take<double>(6 * EF_CHUNKS * hb.t_off[hb.B]);
   P->m_off = c.used, c.take<double>(hb.m_off[hb.B]);
   P->part_off = c.used, c.take<double>(gt.size() * GRAM_TILE * GRAM_TILE);
   P->nrm_off = c.used, c.take<double>(2 * hb.B);
@@ -317,7 +344,9 @@ mi_status mi_choose_c_workspace_size(mi_ctx* ctx, const mi_blocks* blk, size_t* 
   Carver c(nullptr);
   c.take<float>(hb.u_off[hb.B]);
   c.take<double>(3 * hb.v_off[hb.B]);
+  // the same regions as the plan's layout, in the same order
   c.take<double>(6 * hb.t_off[hb.B]);
+  c.take<double>(6 * EF_CHUNKS * hb.t_off[hb.B]);
   c.take<double>(hb.m_off[hb.B]);
   c.take<double>(gt.size() * GRAM_TILE * GRAM_TILE);
   c.take<double>(2 * hb.B);
@@ -365,7 +394,11 @@ mi_status mi_choose_c(mi_ctx* ctx, const mi_blocks* blk, const int32_t* c_max, d
                      gl_col, gl_val, U, Z);
   hipLaunchKernelGGL(k_gl_coords, dim3(hb.B), dim3(256), 0, s, P->blocks, gl_row_ptr, gl_col,
                      gl_val, X, GX, nrm);
-  hipLaunchKernelGGL(k_proj_ef, dim3(hb.B), dim3(256), 0, s, P->blocks, U, Z, X, GX, EF);
+  double* EFP = reinterpret_cast<double*>(w + P->efp_off);
+  hipLaunchKernelGGL(k_proj_ef_part, dim3(hb.B * EF_CHUNKS), dim3(256), 0, s, P->blocks, U, Z, X,
+                     GX, EFP);
+  hipLaunchKernelGGL(k_proj_ef_sum, dim3(hb.B), dim3(256), 0, s, P->blocks, (const double*)EFP,
+                     EF);
   if (P->gram_direct) {
     launch_gram_direct<float>(P->gt, P->n_gt, P->tall, P->small, Z, Z, nullptr, M, nullptr, s);
   } else {

@@ -72,6 +72,80 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The same product for blocks of one width ld = 64 EPL (up to 320): one
+// wavefront per row (lanes over the columns, strided by 64 at 320), the
+// row's column indices and weights in one vector load read out by lane, the
+// off-diagonal rows gathered together and summed in difference form,
+// (L U)_r = sum_{j != r} L_rj (U_j - U_r) + (sum_j L_rj) U_r, then scaled
+// by 1 / L_rr; 8 consecutive rows per workgroup.
+template <int EPL, bool STRIDED>
+__global__ void __launch_bounds__(512)
+    k_gl_apply_rows(const CcBlock* __restrict__ blks, const SpmmTile* __restrict__ tiles,
+                    int ntiles, const int32_t* __restrict__ row_ptr,
+                    const int32_t* __restrict__ col, const float* __restrict__ val,
+                    const float* __restrict__ U, float* __restrict__ Z) {
+  constexpr int G = 8, ES = STRIDED ? 64 : 1;
+  const int ti = blockIdx.x / 2;
+  if (ti >= ntiles) return;
+  const SpmmTile t = tiles[ti];
+  const CcBlock b = blks[t.set];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = t.row0 + (blockIdx.x % 2) * 8 + wave;
+  if (r >= b.n) return;  // wave-uniform
+  const int lane = threadIdx.x & 63;
+  const int l0 = STRIDED ? lane : lane * EPL;
+  const float* uv = U + b.u_off + l0;
+  const int64_t o = b.u_off + int64_t(r) * b.ld + l0;
+  float yin[EPL], acc[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    yin[e] = U[o + e * ES];
+    acc[e] = 0.f;
+  }
+  const int k0 = row_ptr[b.rp_off + r], k1 = row_ptr[b.rp_off + r + 1];
+  float rs = 0.f, diag = 0.f;
+  for (int k = k0; k < k1; k += G) {
+    int cjv = 0;
+    float wvv = 0.f;
+    if (lane < G && k + lane < k1) {
+      cjv = col[b.nnz_off + k + lane];
+      wvv = val[b.nnz_off + k + lane];
+    }
+    float y[G][EPL], w[G];
+    bool has[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      has[u] = false;
+      w[u] = 0.f;
+      if (k + u < k1) {
+        const int cj = __builtin_amdgcn_readlane(cjv, u);
+        const float wv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wvv), u));
+        rs += wv;
+        if (cj == r) {
+          diag = wv;
+        } else {
+          has[u] = true;
+          w[u] = wv;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) y[u][e] = uv[int64_t(cj) * b.ld + e * ES];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+      if (has[u])
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] = fmaf(w[u], y[u][e] - yin[e], acc[e]);
+  }
+  const float inv = diag > 0.f ? 1.f / diag : 0.f;
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    // an isolated vertex (no entries): GL is the identity on it
+    const float out = diag > 0.f ? fmaf(rs, yin[e], acc[e]) * inv : yin[e];
+    Z[o + e * ES] = out;
+  }
+}
+
 // GX = G X in FP64, and the norms ||X||^2, ||GX||^2 per block (one workgroup
 // per block, fixed-order reduction).
 __global__ void __launch_bounds__(256)
@@ -390,8 +464,27 @@ mi_status mi_choose_c(mi_ctx* ctx, const mi_blocks* blk, const int32_t* c_max, d
   const SpmmTile* tiles = reinterpret_cast<const SpmmTile*>(a + osp);
   int ntiles = 0;
   for (int b = 0; b < hb.B; ++b) ntiles += ceil_div(hb.v_off[b + 1] - hb.v_off[b], SPMM_ROWS);
-  hipLaunchKernelGGL(k_gl_apply, dim3(ntiles), dim3(256), 0, s, P->blocks, tiles, gl_row_ptr,
-                     gl_col, gl_val, U, Z);
+  // one width for every block (a multiple of 64 up to 320): a wavefront per
+  // row; otherwise a thread per row and 4 columns
+  int epl = hb.B > 0 && hb.ld[0] % 64 == 0 && hb.ld[0] <= 320 ? hb.ld[0] / 64 : 0;
+  for (int b = 0; b < hb.B && epl; ++b)
+    if (hb.ld[b] != hb.ld[0]) epl = 0;
+  switch (epl) {
+#define MI_GL_ROWS(E, ST)                                                                       \
+  case E:                                                                                       \
+    hipLaunchKernelGGL((k_gl_apply_rows<E, ST>), dim3(2 * ntiles), dim3(512), 0, s, P->blocks,  \
+                       tiles, ntiles, gl_row_ptr, gl_col, gl_val, U, Z);                        \
+    break;
+    MI_GL_ROWS(1, false)
+    MI_GL_ROWS(2, false)
+    MI_GL_ROWS(3, false)
+    MI_GL_ROWS(4, false)
+    MI_GL_ROWS(5, true)
+#undef MI_GL_ROWS
+    default:
+      hipLaunchKernelGGL(k_gl_apply, dim3(ntiles), dim3(256), 0, s, P->blocks, tiles, gl_row_ptr,
+                         gl_col, gl_val, U, Z);
+  }
   hipLaunchKernelGGL(k_gl_coords, dim3(hb.B), dim3(256), 0, s, P->blocks, gl_row_ptr, gl_col,
                      gl_val, X, GX, nrm);
   double* EFP = reinterpret_cast<double*>(w + P->efp_off);

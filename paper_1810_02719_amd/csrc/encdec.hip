@@ -229,8 +229,8 @@ __global__ void __launch_bounds__(256)
 // Reconstruction over 64-row tiles of one block (no block search per row):
 // each lane keeps the coefficients of its columns k = lane + 64 s in
 // registers for the tile's rows; the four wavefronts take every fourth row,
-// a wave reduction per row.  ld <= 256.
-template <typename T>
+// a wave reduction per row.  ld <= 64 KPL.
+template <typename T, int KPL>
 __global__ void __launch_bounds__(256)
     k_reconstruct_t(const EncBlock* __restrict__ blks, const EncTile* __restrict__ tiles,
                     const int32_t* __restrict__ cvec, const T* __restrict__ U,
@@ -240,9 +240,9 @@ __global__ void __launch_bounds__(256)
   const int c = min(max(cvec[t.blk], 0), b.p);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // coefficients of this lane's columns (unconditional loads, 0 past c)
-  double e[ENC_KPL][3];
+  double e[KPL][3];
 #pragma unroll
-  for (int s = 0; s < ENC_KPL; ++s) {
+  for (int s = 0; s < KPL; ++s) {
     const int k = lane + 64 * s;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -255,12 +255,12 @@ __global__ void __launch_bounds__(256)
   // four rows of the wavefront per batch, loads unconditional (a row past
   // the tile reads the tile's first row and is not stored)
   for (int i0 = t.row0 + wv; i0 < r1; i0 += 16) {
-    T ur[4][ENC_KPL];
+    T ur[4][KPL];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int i = i0 + 4 * h < r1 ? i0 + 4 * h : t.row0;
 #pragma unroll
-      for (int s = 0; s < ENC_KPL; ++s) {
+      for (int s = 0; s < KPL; ++s) {
         const int k = lane + 64 * s;
         ur[h][s] = Ub[int64_t(i) * b.ld + (k < c ? k : 0)];  // e is 0 past c
       }
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256)
     for (int h = 0; h < 4; ++h) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int s = 0; s < ENC_KPL; ++s) {
+      for (int s = 0; s < KPL; ++s) {
         const double u = (double)ur[h][s];
         s0 = fma(u, e[s][0], s0);
         s1 = fma(u, e[s][1], s1);
@@ -460,14 +460,26 @@ mi_status mi_reconstruct(mi_ctx* ctx, const mi_blocks* blk, int32_t precision, c
   const int grid = ceil_div(N, 4);
   KClose kc_(ctx->timer);
   KScope k_(ctx->timer, MI_K_RECONSTRUCT, s);
-  const bool tiled = P->max_ld <= 64 * ENC_KPL;
+  // the tiled kernel keeps 4 (ld <= 256) or 5 (ld <= 320) columns per lane
+  const bool tiled = P->max_ld <= 64 * (ENC_KPL + 1);
+  const bool k4 = P->max_ld <= 64 * ENC_KPL;
   if (tiled && P->n_tiles > 0) {
-    if (precision == MI_FP64)
-      hipLaunchKernelGGL(k_reconstruct_t<double>, dim3(P->n_tiles), dim3(256), 0, s, P->dev,
-                         P->tiles, c, (const double*)U, (const double*)E, (double*)Xr);
-    else
-      hipLaunchKernelGGL(k_reconstruct_t<float>, dim3(P->n_tiles), dim3(256), 0, s, P->dev,
-                         P->tiles, c, (const float*)U, (const float*)E, (float*)Xr);
+    if (precision == MI_FP64) {
+      if (k4)
+        hipLaunchKernelGGL((k_reconstruct_t<double, ENC_KPL>), dim3(P->n_tiles), dim3(256), 0, s,
+                           P->dev, P->tiles, c, (const double*)U, (const double*)E, (double*)Xr);
+      else
+        hipLaunchKernelGGL((k_reconstruct_t<double, ENC_KPL + 1>), dim3(P->n_tiles), dim3(256), 0,
+                           s, P->dev, P->tiles, c, (const double*)U, (const double*)E,
+                           (double*)Xr);
+    } else {
+      if (k4)
+        hipLaunchKernelGGL((k_reconstruct_t<float, ENC_KPL>), dim3(P->n_tiles), dim3(256), 0, s,
+                           P->dev, P->tiles, c, (const float*)U, (const float*)E, (float*)Xr);
+      else
+        hipLaunchKernelGGL((k_reconstruct_t<float, ENC_KPL + 1>), dim3(P->n_tiles), dim3(256), 0,
+                           s, P->dev, P->tiles, c, (const float*)U, (const float*)E, (float*)Xr);
+    }
   } else if (!tiled) {
     if (precision == MI_FP64)
       hipLaunchKernelGGL(k_reconstruct<double>, dim3(grid), dim3(256), 0, s, P->dev, P->dev_voff,
